@@ -1,0 +1,86 @@
+"""Tree queries over the oracle's in-order layout (test infrastructure).
+
+The paper names two searches over the built tree: all points inside a
+k-dimensional hyper-rectangle (Appendix, "Source Code for Optimized
+Algorithms") and the m nearest neighbours of a query point kept in a
+priority queue (Appendix, "Nearest Neighbors").  Both walk the implicit tree
+of the in-order layout: the node of ``[s, e]`` is at ``s + (e - s) // 2`` and
+splits on dimension ``depth mod k``.
+
+Every element of a "less than" subtree has a super key below the node's, so
+its coordinate in the split dimension is <= the node's (ties are possible when
+the split coordinates are equal and a later portion decides); symmetrically
+">=" for the "greater than" subtree.  The searches prune with those
+non-strict bounds.  Coordinates are handled exactly: Python ints for int32,
+float64 for float32.
+"""
+from __future__ import annotations
+
+import heapq
+
+import numpy as np
+
+
+def _coords(tuples: np.ndarray):
+    if tuples.dtype == np.int32:
+        return [tuple(int(v) for v in row) for row in tuples]
+    return [tuple(float(v) for v in row) for row in tuples.astype(np.float64)]
+
+
+def region_search(tuples: np.ndarray, perm: np.ndarray, lower, upper):
+    """Rows of all tree nodes with ``lower[d] <= x[d] <= upper[d]`` for every d."""
+    pts = _coords(tuples)
+    k = tuples.shape[1]
+    perm = [int(v) for v in perm]
+    found = []
+
+    def visit(s, e, depth):
+        if e < s:
+            return
+        m = s + (e - s) // 2
+        row = perm[m]
+        x = pts[row]
+        if all(lower[d] <= x[d] <= upper[d] for d in range(k)):
+            found.append(row)
+        p = depth % k
+        if lower[p] <= x[p]:
+            visit(s, m - 1, depth + 1)
+        if upper[p] >= x[p]:
+            visit(m + 1, e, depth + 1)
+
+    visit(0, len(perm) - 1, 0)
+    return sorted(found)
+
+
+def nearest_neighbors(tuples: np.ndarray, perm: np.ndarray, query, m: int):
+    """The m nearest tree nodes to ``query`` as ``[(sq_distance, row), ...]``
+    in increasing distance, found with a bounded max-priority queue."""
+    pts = _coords(tuples)
+    k = tuples.shape[1]
+    perm = [int(v) for v in perm]
+    q = tuple(query)
+    heap = []  # max-heap on distance via negation
+
+    def sqd(x):
+        return sum((x[d] - q[d]) * (x[d] - q[d]) for d in range(k))
+
+    def visit(s, e, depth):
+        if e < s:
+            return
+        mid = s + (e - s) // 2
+        row = perm[mid]
+        x = pts[row]
+        dist = sqd(x)
+        if len(heap) < m:
+            heapq.heappush(heap, (-dist, -row))
+        elif dist < -heap[0][0]:
+            heapq.heapreplace(heap, (-dist, -row))
+        p = depth % k
+        diff = q[p] - x[p]
+        near, far = ((s, mid - 1), (mid + 1, e)) if diff <= 0 else ((mid + 1, e), (s, mid - 1))
+        visit(near[0], near[1], depth + 1)
+        if len(heap) < m or diff * diff <= -heap[0][0]:
+            visit(far[0], far[1], depth + 1)
+
+    visit(0, len(perm) - 1, 0)
+    return sorted((-d, -r) for d, r in heap)
