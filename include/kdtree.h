@@ -1,0 +1,124 @@
+/*
+ * kdtree.h -- C ABI of the MI355X (gfx950) presorting balanced k-d tree builder.
+ *
+ * The method is R. A. Brown, "Building a Balanced k-d Tree in O(kn log n)
+ * Time": presort the tuples k times by the cyclic super keys (Sec. 2.1: x:y:z,
+ * y:z:x, z:x:y, ...; the k = 4 forms in the Appendix, "Deferred Merge Sort and
+ * Partitioning"), remove duplicate tuples in one pass (Sec. 2.1), then split
+ * each subarray at the median of the array sorted in the current dimension and
+ * partition the other k-1 arrays about it, keeping their order (Sec. 2.1;
+ * Appendix, "Optimized Partitioning").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Tuples are n rows of k coordinates, row-major, either int32 (signed
+ *    order) or float32 (IEEE-754 totalOrder: -0.0 < +0.0, NaN ordered by its
+ *    bits).  Two rows are duplicates when they are bit-identical; the row
+ *    with the smallest index survives (Sec. 2.1 keeps one index of each run of
+ *    identical tuples; the sorts are stable).
+ *  - The split dimension at depth L is L mod k; the node of a subarray [s, e]
+ *    is its lower median, position s + (e - s) / 2 (the two-element rule of
+ *    Sec. 3.1 makes the first element the node).
+ *  - Output is the tree's in-order layout: perm[pos] = input row of the node at
+ *    position pos, for pos < n_unique; entries at pos >= n_unique are left
+ *    untouched.  Optional lo[pos] / hi[pos] receive the positions of the
+ *    "less than" / "greater than" children, or -1.  The tree's shape depends
+ *    only on n_unique.
+ *  - All pointers named d_* are device memory owned by the caller; h_* are
+ *    host memory.  The library never frees caller memory and allocates no
+ *    device memory inside a build: it uses the caller's workspace.
+ *  - Calls are asynchronous on `stream` (a hipStream_t; NULL is the default
+ *    stream).  Outputs are valid once the stream has synchronised.  The
+ *    workspace must not be shared by builds that may run concurrently.
+ *  - Arguments are validated on the host before anything is enqueued; on an
+ *    error return nothing has been enqueued.  Limits: 0 <= n <= KD_MAX_N,
+ *    1 <= k <= KD_MAX_K, 4-byte aligned device pointers.
+ *  - Return value: KD_OK (0) or a negative KD_E* code; kd_strerror() names it.
+ */
+#ifndef KDTREE_H_
+#define KDTREE_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KD_MAX_N (((int64_t)1 << 30) - 1) /* rows per build (and per batch) */
+#define KD_MAX_K 8
+
+enum kd_dtype { KD_I32 = 0, KD_F32 = 1 };
+
+enum kd_status {
+  KD_OK = 0,
+  KD_EINVAL = -1,        /* bad argument (null, misaligned, out of range) */
+  KD_ENOMEM = -2,        /* workspace smaller than kdtree_workspace_bytes() */
+  KD_EHIP = -3,          /* a HIP runtime call failed */
+  KD_EUNSUPPORTED = -4   /* k or n beyond the limits above */
+};
+
+/* Tuning knobs; pass NULL for the defaults.  They change speed only, never the
+ * result. */
+typedef struct kd_options {
+  int32_t cutover;     /* largest subarray finished on-chip by one workgroup:
+                          1024, 2048 or 4096; 0 = default */
+  int32_t reserved[7]; /* must be zero */
+} kd_options;
+
+/* Human-readable name of a status code (static string). */
+const char* kd_strerror(int code);
+
+/* Bytes of device workspace a build of n rows in k dimensions needs.  Host
+ * only; writes *h_bytes.  Returns KD_EINVAL / KD_EUNSUPPORTED on bad sizes. */
+int kdtree_workspace_bytes(int64_t n, int32_t k, int32_t dtype, size_t* h_bytes);
+
+/* Whole build (Sec. 2.1): presort by the k cyclic super keys, remove
+ * duplicates, partition level by level.
+ *   d_tuples    n*k int32 or float32, row-major, read only
+ *   d_perm      int32[n]  in-order layout (see above)
+ *   d_lo, d_hi  int32[n]  child positions, or both NULL to skip
+ *   d_n_unique  int64[1]  number of distinct rows
+ *   d_workspace workspace_bytes >= kdtree_workspace_bytes(n, k, dtype)
+ *   opts        NULL or tuning knobs                                      */
+int kdtree_build(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, int32_t* d_perm,
+                 int32_t* d_lo, int32_t* d_hi, int64_t* d_n_unique, void* d_workspace,
+                 size_t workspace_bytes, const kd_options* opts, void* stream);
+
+/* The two halves of kdtree_build, for phase timing.  kdtree_presort() runs the
+ * presort and duplicate removal (Sec. 2.1, first half) into the workspace and
+ * writes d_n_unique; kdtree_partition() must follow on the same stream with
+ * the same workspace and arguments and builds the tree (Sec. 2.1, second
+ * half).  Together they do exactly what kdtree_build does. */
+int kdtree_presort(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, int64_t* d_n_unique,
+                   void* d_workspace, size_t workspace_bytes, const kd_options* opts, void* stream);
+int kdtree_partition(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, int32_t* d_perm,
+                     int32_t* d_lo, int32_t* d_hi, int64_t* d_n_unique, void* d_workspace,
+                     size_t workspace_bytes, const kd_options* opts, void* stream);
+
+/* ---- diagnostics ------------------------------------------------------------
+ * Kernel probe for measurement tools.  kd_probe_start() makes the library
+ * record a HIP event pair around every launch of one kernel class (on the
+ * stream the kernel runs on) for the next `capacity` launches; kd_probe_stop()
+ * waits for those events, writes up to `capacity` durations in milliseconds to
+ * h_ms (host), the number recorded to *h_count, and disables the probe.  The
+ * probe is process-wide state for single-threaded measurement, not for
+ * concurrent builds.  Events are created by the library (host objects, no
+ * device memory). */
+enum kd_kernel_class {
+  KD_K_ONESWEEP = 1, /* one radix scatter pass */
+  KD_K_LEVEL = 2,    /* one global partition level */
+  KD_K_LEAF = 3,     /* the on-chip finish */
+  KD_K_DEDUP = 4,    /* duplicate removal */
+  KD_K_HIST = 5,     /* digit histograms */
+  KD_K_CANON = 6,    /* key canonicalisation */
+  KD_K_RECORDS = 7   /* rank tables and level-0 records */
+};
+int kd_probe_start(int32_t kernel_class, int32_t capacity);
+int kd_probe_stop(float* h_ms, int32_t* h_count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KDTREE_H_ */

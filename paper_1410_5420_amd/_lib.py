@@ -1,0 +1,90 @@
+"""ctypes binding of libkdtree.so (the gfx950 HIP library).
+
+Argument marshalling only: every step of a build runs in the library's
+kernels.  If the library has not been built the import fails loudly; there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkdtree.so")
+
+KD_OK = 0
+KD_I32 = 0
+KD_F32 = 1
+
+
+class KdError(RuntimeError):
+    pass
+
+
+class kd_options(ctypes.Structure):
+    _fields_ = [("cutover", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: the HIP library has not been built "
+            "(run `python -c 'import __graft_entry__ as g; g.build()'`)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+    opt = ctypes.POINTER(kd_options)
+    lib.kd_strerror.argtypes = [ctypes.c_int]
+    lib.kd_strerror.restype = ctypes.c_char_p
+    lib.kdtree_workspace_bytes.argtypes = [i64, i32, i32, ctypes.POINTER(sz)]
+    lib.kdtree_workspace_bytes.restype = ctypes.c_int
+    lib.kdtree_build.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp, vp, sz, opt, vp]
+    lib.kdtree_build.restype = ctypes.c_int
+    lib.kdtree_presort.argtypes = [vp, i64, i32, i32, vp, vp, sz, opt, vp]
+    lib.kdtree_presort.restype = ctypes.c_int
+    lib.kdtree_partition.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp, vp, sz, opt, vp]
+    lib.kdtree_partition.restype = ctypes.c_int
+    lib.kd_probe_start.argtypes = [i32, i32]
+    lib.kd_probe_start.restype = ctypes.c_int
+    lib.kd_probe_stop.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int32)]
+    lib.kd_probe_stop.restype = ctypes.c_int
+    return lib
+
+
+lib = _load()
+
+# Every symbol include/kdtree.h declares (the tests check the library exports them).
+EXPORTED = ["kd_strerror", "kdtree_workspace_bytes", "kdtree_build", "kdtree_presort",
+            "kdtree_partition", "kd_probe_start", "kd_probe_stop"]
+
+KERNEL_CLASSES = {"onesweep": 1, "level": 2, "leaf": 3, "dedup": 4, "hist": 5, "canon": 6,
+                  "records": 7}
+
+
+def probe_start(kernel: str, capacity: int) -> None:
+    check(lib.kd_probe_start(KERNEL_CLASSES[kernel], capacity), "kd_probe_start")
+
+
+def probe_stop(capacity: int):
+    buf = (ctypes.c_float * capacity)()
+    cnt = ctypes.c_int32(0)
+    check(lib.kd_probe_stop(buf, ctypes.byref(cnt)), "kd_probe_stop")
+    return [float(buf[i]) for i in range(cnt.value)]
+
+
+def check(rc: int, what: str) -> None:
+    if rc != KD_OK:
+        raise KdError(f"{what}: {lib.kd_strerror(rc).decode()} ({rc})")
+
+
+def workspace_bytes(n: int, k: int, dtype: int) -> int:
+    out = ctypes.c_size_t(0)
+    check(lib.kdtree_workspace_bytes(n, k, dtype, ctypes.byref(out)), "kdtree_workspace_bytes")
+    return int(out.value)
+
+
+def options(cutover: int | None):
+    if cutover is None:
+        return None
+    o = kd_options()
+    o.cutover = int(cutover)
+    return ctypes.byref(o)

@@ -1,0 +1,128 @@
+// Device-side building blocks shared by the gfx950 kernels of the k-d tree
+// builder: wave64 lane masks, agent-scope flag words for decoupled look-back,
+// block scans and the implicit shape of the balanced tree.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kd {
+
+constexpr int kWave = 64;
+
+// ---- wave helpers -------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanes_below_mask() {
+  const uint32_t l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__device__ __forceinline__ uint32_t popc64(uint64_t m) { return (uint32_t)__popcll(m); }
+
+// Inclusive prefix sum across the 64 lanes of a wave.
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_sum(T v) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    T o = __shfl_up(v, d, kWave);
+    if ((int)lane_id() >= d) v += o;
+  }
+  return v;
+}
+
+// Exclusive block-wide prefix sum of one value per thread (NT threads, a
+// multiple of 64).  `s_tmp` holds NT/64 + 1 words of LDS.  Returns the
+// exclusive prefix; *total receives the block sum.  Contains barriers.
+template <int NT, typename T>
+__device__ __forceinline__ T block_exclusive_sum(T v, T* s_tmp, T* total) {
+  constexpr int kWaves = NT / kWave;
+  const int w = threadIdx.x / kWave;
+  T inc = wave_inclusive_sum(v);
+  if (lane_id() == kWave - 1) s_tmp[w] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T run = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) {
+      T c = s_tmp[i];
+      s_tmp[i] = run;
+      run += c;
+    }
+    s_tmp[kWaves] = run;
+  }
+  __syncthreads();
+  T res = s_tmp[w] + inc - v;
+  *total = s_tmp[kWaves];
+  __syncthreads();
+  return res;
+}
+
+// ---- agent-scope flag words (decoupled look-back) ----------------------------
+// A status word carries its readiness flag and its value together, so one
+// relaxed atomic access at agent scope moves both; no other ordering is
+// needed because only the counts travel between workgroups.
+
+__device__ __forceinline__ uint32_t ld_flag(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_flag(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_flag64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_flag64(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t next_tile(uint32_t* counter) {
+  return __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Upper bound on polls of a predecessor's flag word.  Every wait finishes long
+// before this in a correct run; the bound only guarantees that no wave can
+// spin forever if a flag is never published (the results are then wrong and
+// the tests fail, but the kernel still exits).
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+// 32-bit look-back word: [31:30] status, [29:0] count (counts < 2^30).
+constexpr uint32_t kLbAgg = 1u << 30;
+constexpr uint32_t kLbInc = 2u << 30;
+constexpr uint32_t kLbMask = (1u << 30) - 1;
+
+// ---- implicit shape of the balanced tree --------------------------------------
+// The node of [s, e] sits at its lower median; its children cover [s, m-1] and
+// [m+1, e].  At depth L the largest subarray holds floor(n / 2^L) elements.
+
+__device__ __forceinline__ int64_t median_of(int64_t s, int64_t e) { return s + ((e - s) >> 1); }
+
+// Subarray at depth `depth` that contains position pos, or e < s when pos is
+// the node of a shallower subarray.
+__device__ __forceinline__ void subarray_at(int64_t pos, int64_t nu, int depth, int64_t* s_out,
+                                            int64_t* e_out) {
+  int64_t s = 0, e = nu - 1;
+  for (int l = 0; l < depth; ++l) {
+    int64_t m = median_of(s, e);
+    if (pos < m) {
+      e = m - 1;
+    } else if (pos > m) {
+      s = m + 1;
+    } else {
+      s = 1;
+      e = 0;
+      break;
+    }
+  }
+  *s_out = s;
+  *e_out = e;
+}
+
+// First depth at which every subarray holds at most `cutover` elements.
+__device__ __host__ __forceinline__ int cutover_depth(int64_t nu, int64_t cutover) {
+  int d = 0;
+  while ((nu >> d) > cutover) ++d;
+  return d;
+}
+
+}  // namespace kd

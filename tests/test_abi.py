@@ -1,0 +1,88 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol that
+include/kdtree.h declares, sizes workspaces, and rejects bad arguments on the
+host before any HIP call (so these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kdtree.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1410_5420_amd import _lib
+
+    return _lib
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(kd\w*)\s*\(", text)))
+
+
+def test_header_declarations_are_exported(L):
+    names = declared_functions()
+    assert "kdtree_build" in names and len(names) >= 5
+    for name in names:
+        assert hasattr(L.lib, name), f"{name} declared in kdtree.h but not exported"
+    assert sorted(L.EXPORTED) == names
+
+
+def test_workspace_bytes(L):
+    small = L.workspace_bytes(4096, 3, L.KD_I32)
+    big = L.workspace_bytes(1 << 24, 3, L.KD_I32)
+    assert 0 < small < big
+    assert L.workspace_bytes(0, 3, L.KD_I32) > 0
+    out = ctypes.c_size_t(0)
+    assert L.lib.kdtree_workspace_bytes(-1, 3, 0, ctypes.byref(out)) == -1
+    assert L.lib.kdtree_workspace_bytes(10, 9, 0, ctypes.byref(out)) == -4
+    assert L.lib.kdtree_workspace_bytes(10, 3, 7, ctypes.byref(out)) == -1
+    assert L.lib.kdtree_workspace_bytes(1 << 30, 3, 0, ctypes.byref(out)) == -4
+
+
+FAKE = 0x7F0000000000  # never dereferenced: every call below fails validation first
+
+
+def call_build(L, n=100, k=3, dtype=0, tuples=FAKE, perm=FAKE, lo=None, hi=None, nu=FAKE, ws=FAKE,
+               ws_bytes=None, opts=None):
+    if ws_bytes is None:
+        ws_bytes = L.workspace_bytes(max(n, 0), max(min(k, 8), 1), 0) if 0 <= n < (1 << 30) else 0
+    vp = ctypes.c_void_p
+    return L.lib.kdtree_build(vp(tuples), n, k, dtype, vp(perm), vp(lo), vp(hi), vp(nu), vp(ws),
+                              ws_bytes, opts, None)
+
+
+def test_build_rejects_bad_arguments(L):
+    assert call_build(L, k=0) == -1
+    assert call_build(L, k=9) == -4
+    assert call_build(L, n=-5) == -1
+    assert call_build(L, n=1 << 30) == -4
+    assert call_build(L, dtype=2) == -1
+    assert call_build(L, tuples=0) == -1
+    assert call_build(L, ws=0) == -1
+    assert call_build(L, perm=0) == -1
+    assert call_build(L, nu=0) == -1
+    assert call_build(L, lo=FAKE) == -1          # lo without hi
+    assert call_build(L, tuples=FAKE + 2) == -1  # misaligned
+    assert call_build(L, ws_bytes=16) == -2
+    o = L.kd_options()
+    o.cutover = 3000
+    assert call_build(L, opts=ctypes.byref(o)) == -1
+    o.cutover = 2048
+    o.reserved[3] = 1
+    assert call_build(L, opts=ctypes.byref(o)) == -1
+
+
+def test_strerror(L):
+    for code in (0, -1, -2, -3, -4):
+        assert L.lib.kd_strerror(code)
+    assert L.lib.kd_strerror(-99) == b"unknown status"
+
+
+def test_probe_rejects_bad_class(L):
+    assert L.lib.kd_probe_start(0, 10) == -1
+    assert L.lib.kd_probe_start(2, 0) == -1

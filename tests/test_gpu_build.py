@@ -1,0 +1,152 @@
+"""GPU parity: the HIP build through the C ABI against the CPU oracle.
+
+Every comparison is bit-exact: perm (the in-order layout), n_unique and the
+child positions must equal the oracle's.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import kdgen
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "worked_example.json")
+
+
+@pytest.fixture(scope="module")
+def kd():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1410_5420_amd as kd
+
+    return kd
+
+
+def run_gpu(kd, t: np.ndarray, cutover=None, children=True):
+    print(f"[gpu case] n={t.shape[0]} k={t.shape[1]} dtype={t.dtype} cutover={cutover}", flush=True)
+    dt = torch.from_numpy(np.ascontiguousarray(t)).cuda()
+    res = kd.build(dt, children=children, cutover=cutover)
+    torch.cuda.synchronize()
+    return [r.cpu().numpy() if hasattr(r, "cpu") else r for r in res]
+
+
+def assert_same(kd, t, cutover=None, threads=8):
+    want = oracle.build_tree(t, threads=threads)
+    perm, nu, lo, hi = run_gpu(kd, t, cutover)
+    assert nu == want["n_unique"]
+    assert np.array_equal(perm, want["perm"]), "perm differs"
+    assert np.array_equal(lo, want["lo"]) and np.array_equal(hi, want["hi"]), "children differ"
+
+
+def test_worked_example(kd):
+    g = json.load(open(GOLDEN))
+    rows = dict(g["tuples_stated"])
+    rows.update({k: v for k, v in g["completion_used"].items() if k != "note"})
+    t = np.array([rows[str(i)] for i in range(15)], dtype=np.int32)
+    assert_same(kd, t)
+    perm, nu, lo, hi = run_gpu(kd, t)
+    assert perm[7] == g["tree"]["root"]
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 8])
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 7, 64, 1000, 4095, 4096, 4097, 9000])
+def test_small_many_duplicates(kd, k, n):
+    t = kdgen.uniform_int(n, k, -3, 4, 0.2, 100 + n + k)
+    if n == 0:
+        perm, nu, lo, hi = run_gpu(kd, t)
+        assert nu == 0
+        return
+    assert_same(kd, t)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 6, 8])
+@pytest.mark.parametrize("n", [1023, 5000, 70001])
+def test_wide_values(kd, k, n):
+    t = kdgen.uniform_int(n, k, 0, 1 << 20, 0.02, 7 * n + k)
+    assert_same(kd, t)
+
+
+@pytest.mark.parametrize("cutover", [1024, 2048, 4096])
+@pytest.mark.parametrize("n", [70001, 300000])
+def test_cutover_choices_same_tree(kd, cutover, n):
+    t = kdgen.uniform_int(n, 3, -(2 ** 31), 2 ** 31, 0.01, n + cutover)
+    assert_same(kd, t, cutover=cutover)
+
+
+def test_all_duplicates(kd):
+    t = np.tile(np.array([[5, -7, 9]], dtype=np.int32), (10000, 1))
+    assert_same(kd, t)
+
+
+def test_extreme_ints(kd):
+    lo, hi = np.iinfo(np.int32).min, np.iinfo(np.int32).max
+    g = kdgen.rng(3)
+    t = g.choice(np.array([lo, lo + 1, -1, 0, 1, hi - 1, hi], dtype=np.int32), size=(5000, 3))
+    assert_same(kd, np.ascontiguousarray(t))
+
+
+def test_float_specials(kd):
+    g = kdgen.rng(4)
+    specials = np.array([0x80000000, 0x00000000, 0x7F800000, 0xFF800000, 0x7FC00000, 0xFFC00000,
+                         0x00000001, 0x80000001, 0x3F800000, 0xBF800000], dtype=np.uint32).view(np.float32)
+    t = g.normal(size=(6000, 3)).astype(np.float32)
+    mask = g.random(size=t.shape) < 0.3
+    t[mask] = g.choice(specials, size=int(mask.sum()))
+    assert_same(kd, np.ascontiguousarray(t))
+
+
+@pytest.mark.parametrize("k", [2, 3, 4, 6, 8])
+def test_clustered_reduced(kd, k):
+    t = kdgen.clustered_int(1 << 18, k, 256, float(1 << 12), 1 << 30, 0.10, 1000 + k)
+    assert_same(kd, t)
+
+
+def test_point_cloud_float(kd):
+    t = kdgen.point_cloud(50000, kdgen.rng(12))
+    assert_same(kd, t)
+
+
+def test_c1_workload(kd):
+    assert_same(kd, kdgen.c1_small_uniform())
+
+
+def test_workspace_reuse_shrinking_input(kd):
+    """Two builds through one workspace, the second smaller: look-back state
+    left by the first must not leak into the second."""
+    b = kd.Builder(200000, 3, torch.int32)
+    for n, seed in ((200000, 1), (77777, 2), (5000, 3)):
+        t = kdgen.uniform_int(n, 3, 0, 1 << 16, 0.05, seed)
+        want = oracle.build_tree(t, threads=8, children=False)
+        perm = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+        b.build(torch.from_numpy(t).cuda(), perm)
+        torch.cuda.synchronize()
+        assert int(b.n_unique.item()) == want["n_unique"]
+        assert np.array_equal(perm[: want["n_unique"]].cpu().numpy(), want["perm"])
+
+
+def test_presort_then_partition_equals_build(kd):
+    t = kdgen.uniform_int(123457, 3, 0, 1 << 18, 0.05, 77)
+    want = oracle.build_tree(t, threads=8, children=False)
+    b = kd.Builder(t.shape[0], 3, torch.int32)
+    dt = torch.from_numpy(t).cuda()
+    perm = torch.full((t.shape[0],), -1, dtype=torch.int32, device="cuda")
+    b.presort(dt)
+    b.partition(dt, perm)
+    torch.cuda.synchronize()
+    assert int(b.n_unique.item()) == want["n_unique"]
+    assert np.array_equal(perm[: want["n_unique"]].cpu().numpy(), want["perm"])
+
+
+def test_full_size_c2_bit_exact(kd):
+    """The headline workload (k=3, n=2^24, full-range int32, 0.1% copies) in the
+    configuration the benchmark times, compared over every output."""
+    t = kdgen.c2_full_range()
+    want = oracle.build_tree(t, threads=os.cpu_count() or 8, children=False)
+    perm, nu = run_gpu(kd, t, children=False)
+    assert nu == want["n_unique"]
+    assert np.array_equal(perm, want["perm"])
