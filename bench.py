@@ -30,30 +30,55 @@ METRIC = "tuples/sec k-d build (k=3, n=2^24, bit-exact) plain vs batched/learned
 HBM_PEAK_GBS = 8000.0
 
 
-def byte_model(kernel: str, n: int, nu: int, k: int, R: int):
-    """Algorithmic bytes of every launch of one kernel class in one build.
+def onesweep_bytes(n: int, nu: int, k: int):
+    """(total algorithmic bytes, launches) of all radix scatter passes of one build.
 
-    Returns (bytes per launch, unit description).  Streams count 4 bytes per
-    element word read or written; a gathered word counts 4 bytes.
+    Array 0 is sorted over all n rows, word by word; every pass moves its key
+    word and k payload words (the row id and the other key words), the first
+    one reading the tuple rows themselves.  Each of the k-1 chain sorts runs
+    over the n_unique rows and moves its key word and k payload words (row id,
+    ranks known so far, key words of the later sorts); its last pass drops the
+    key.  Every word read or written counts 4 bytes.
     """
     P = 4  # 8-bit digit passes per 32-bit word
+    words = 0
+    for w in range(k - 1, -1, -1):
+        for ps in range(P):
+            words += n * ((k if (w == k - 1 and ps == 0) else k + 1) + (k + 1))
+    for _ in range(k - 1, 0, -1):
+        for ps in range(P):
+            words += nu * ((k if ps == 0 else k + 1) + (k if ps == P - 1 else k + 1))
+    return 4 * words, 2 * k * P - P
+
+
+def level_bytes(nu: int, k: int, cutover: int):
+    """(total algorithmic bytes, launches) of the global partition levels:
+    every array but the split one is read once and written once; records hold
+    k-1 ranks, plus the row id in array 0's."""
+    R = k - 1
+    levels = 0
+    while (nu >> levels) > cutover:
+        levels += 1
+    total = 0
+    for L in range(levels):
+        p = L % k
+        words = sum(R + (1 if j == 0 else 0) for j in range(k) if j != p)
+        total += nu * words * 4 * 2
+    return total, levels
+
+
+def byte_model(kernel: str, n: int, nu: int, k: int, cutover: int):
+    """Algorithmic bytes of one launch of a kernel class (averaged over the
+    build's launches of that class), and how they arise."""
     if kernel == "level":
-        # k-1 arrays of R rank planes, each read once and written once
-        per_unit = (k - 1) * R * 4 * 2
-        return per_unit * nu, f"{per_unit} B x n_unique elements"
+        total, launches = level_bytes(nu, k, cutover)
+        return total / max(launches, 1), (f"{launches} levels: per level (k-1) arrays x (k-1) ranks "
+                                          f"(+ row id in array 0) x 4 B, read + write, x n_unique")
     if kernel == "onesweep":
-        total = 0
-        for w in range(k):  # array 0: all n rows, LSD over k words
-            first = w == 0
-            total += n * ((4 if first else 8) + 8)  # pass 0: key (+id) in, pair out
-            total += n * 16 * (P - 2)  # middle passes: pair in, pair out
-            total += n * (8 + (8 if w == k - 1 else 4))  # last pass: pair in, id (+key) out
-        for _ in range(k - 1):  # chain: n_unique rows, one word each
-            total += nu * (8 + 8) + nu * 16 * (P - 2) + nu * (8 + 4)
-        launches = k * P + (k - 1) * P
-        return total / launches, "radix pair traffic averaged over the build's passes"
+        total, launches = onesweep_bytes(n, nu, k)
+        return total / launches, f"radix key + payload words of the build's {launches} passes, averaged"
     if kernel == "leaf":
-        per_unit = 4 * k + 4 + 4  # plane-0 ranks of k arrays in, perm out, row id gathered
+        per_unit = 4 * k + 4  # order-0 rank of k-1 arrays + row id in, perm out
         return per_unit * nu, f"{per_unit} B x n_unique elements"
     raise ValueError(kernel)
 
@@ -83,6 +108,8 @@ def main():
     ap.add_argument("--cutover", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--n", type=int, default=1 << 24, help=argparse.SUPPRESS)
+    ap.add_argument("--calibrate", action="store_true",
+                    help="first run one plain 256 MiB device copy (a reference for profiler byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -104,6 +131,12 @@ def main():
     perm = torch.empty(n, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
 
+    if args.calibrate:
+        ref = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        ref.fill_(1)
+        _ = ref.clone()
+        torch.cuda.synchronize()
+        del ref, _
     for _ in range(args.warmup):
         b.build(t, perm)
     torch.cuda.synchronize()
@@ -137,8 +170,7 @@ def main():
         pre_ms.append(ev[0].elapsed_time(ev[1]))
         part_ms.append(ev[1].elapsed_time(ev[2]))
 
-    R = k
-    bytes_per_launch, unit_desc = byte_model(args.probe, n, nu, k, R)
+    bytes_per_launch, unit_desc = byte_model(args.probe, n, nu, k, args.cutover or 1024)
     # no-op launches (levels below the cutover for this n_unique) do not count
     real = [d for d in durations if d > 0.002]
     avg_ms = float(np.mean(real)) if real else float("nan")
@@ -164,7 +196,7 @@ def main():
         "config": {"workload": "k=3, n=2^24 int32 uniform over the full signed range, 0.1% exact "
                                "copies (seeded); one plain build (presort + dedup + partition)",
                    "k": k, "n": n, "n_unique": nu, "tuple_dtype": "int32",
-                   "cutover": args.cutover or 2048,
+                   "cutover": args.cutover or 1024,
                    "presort_ms": round(float(np.median(pre_ms)), 4),
                    "partition_ms": round(float(np.median(part_ms)), 4)},
         "roofline": roofline,

@@ -20,41 +20,37 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// Workspace layout for n rows in k dimensions.  Everything from `hist` to the
-// end is cleared at the start of every build.
+// Workspace layout for n rows in k dimensions.  Every region is fully written
+// before it is read within a build, so nothing needs clearing.
 struct Layout {
-  size_t keys, rka, rkb, rva, rvb, S, rank, rec0, rec1;
-  size_t hist, rlb0, rlb1, dlb0, dlb1, llb0, llb1, counters, nu, end;
+  size_t vbuf, carry, S, rec0, rec1, rec2;
+  size_t rcnt, rgrp, dcnt, seginfo, lcnt, lcarry, nu, end;
 };
 
 Layout plan(int64_t n, int k) {
   Layout L{};
-  const size_t un = (size_t)(n > 0 ? n : 1);
-  const size_t tiles = (un + kSortTile - 1) / kSortTile;
-  const size_t ltiles = (un + kLevelTile - 1) / kLevelTile;
+  const int64_t nn = n > 0 ? n : 1;
+  const size_t un = (size_t)nn;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
     o = align_up(o + bytes);
     return at;
   };
-  L.keys = take(4 * un * k);
-  L.rka = take(4 * un);
-  L.rkb = take(4 * un);
-  L.rva = take(4 * un);
-  L.rvb = take(4 * un);
-  L.S = take(4 * un * k);
-  L.rank = take(4 * un * k);
-  L.rec0 = take(4 * un * k * k);
-  L.rec1 = take(4 * un * k * k);
-  L.hist = take(4 * (size_t)kPassesPerWord * kRadix * 2 * k);
-  L.rlb0 = take(4 * tiles * kRadix);
-  L.rlb1 = take(4 * tiles * kRadix);
-  L.dlb0 = take(4 * tiles);
-  L.dlb1 = take(4 * tiles);
-  L.llb0 = take(8 * ltiles * (k > 1 ? k - 1 : 1));
-  L.llb1 = take(8 * ltiles * (k > 1 ? k - 1 : 1));
-  L.counters = take(4 * 8);
+  L.vbuf = take(4 * un * (k + 1) * 2);  // radix passes: two sets of key + k payload planes
+  L.carry = take(4 * un * k);           // key words handed from one sort to the next
+  L.S = take(4 * un * k);               // the k deduplicated sorted id arrays
+  const size_t rw = 4 * (size_t)record_words(k, nn);
+  L.rec0 = take(k > 1 ? rw : 4);        // level-0 rank records (kept)
+  L.rec1 = take(k > 1 ? rw : 4);        // moved records, odd number of moves
+  L.rec2 = take(k > 1 ? rw : 4);        // moved records, even number of moves
+  L.rcnt = take(4 * (size_t)radix_count_words(nn));
+  L.rgrp = take(4 * (size_t)radix_group_words(nn));
+  L.dcnt = take(4 * (size_t)radix_tiles(nn));
+  const size_t lt = (size_t)level_tiles(nn);
+  L.seginfo = take(lt * level_seginfo_bytes());
+  L.lcnt = take(4 * lt * 8 * (k > 1 ? k - 1 : 1));
+  L.lcarry = take(8 * lt * (k > 1 ? k - 1 : 1));
   L.nu = take(8);
   L.end = o;
   return L;
@@ -74,7 +70,7 @@ int check_common(const void* tuples, int64_t n, int32_t k, int32_t dtype, void* 
   if ((n > 0 && !tuples) || !ws) return KD_EINVAL;
   if (!aligned4(tuples) || !aligned4(ws)) return KD_EINVAL;
   if (ws_bytes < plan(n, k).end) return KD_ENOMEM;
-  *cutover = 2048;
+  *cutover = 1024;
   if (opts) {
     for (int i = 0; i < 7; ++i)
       if (opts->reserved[i] != 0) return KD_EINVAL;
@@ -121,79 +117,109 @@ void probe_end(int cls, hipStream_t st) {
 
 int presort_impl(const void* tuples, int64_t n, int k, int dtype, void* ws, hipStream_t st) {
   const Layout L = plan(n, k);
-  uint32_t* keys = at<uint32_t>(ws, L.keys);
-  uint32_t* kbuf[2] = {at<uint32_t>(ws, L.rka), at<uint32_t>(ws, L.rkb)};
-  uint32_t* vbuf[2] = {at<uint32_t>(ws, L.rva), at<uint32_t>(ws, L.rvb)};
+  uint32_t* vb = at<uint32_t>(ws, L.vbuf);
+  uint32_t* carry = at<uint32_t>(ws, L.carry);
   uint32_t* S = at<uint32_t>(ws, L.S);
-  uint32_t* hist = at<uint32_t>(ws, L.hist);
-  uint32_t* rlb[2] = {at<uint32_t>(ws, L.rlb0), at<uint32_t>(ws, L.rlb1)};
-  uint32_t* counters = at<uint32_t>(ws, L.counters);
+  uint32_t* rec0 = at<uint32_t>(ws, L.rec0);
+  uint32_t* rcnt = at<uint32_t>(ws, L.rcnt);
+  uint32_t* rgrp = at<uint32_t>(ws, L.rgrp);
   int64_t* nu = at<int64_t>(ws, L.nu);
   const size_t un = (size_t)n;
+  // slot q of set `set`: radix pass buffers
+  auto slot = [&](int set, int q) { return vb + ((size_t)set * (k + 1) + q) * un; };
+  const TupleSrc ts{static_cast<const uint32_t*>(tuples), k, dtype == KD_F32 ? 1 : 0};
 
-  KD_TRY(launch_fill_u32(hist, 0u, (int64_t)((L.end - L.hist) / 4), st));
-  if (n == 0) return KD_OK;
-  KD_LAUNCH(KD_K_CANON, launch_canon(tuples, n, k, dtype == KD_F32, keys, st));
+  if (n == 0) {
+    KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(nu), 0u, 2, st));
+    return KD_OK;
+  }
 
-  int pass = 0;
-  auto lookback = [&](int ps) {
-    LookBack lb;
-    lb.cur = rlb[ps & 1];
-    lb.other = rlb[(ps + 1) & 1];
-    lb.counter = counters + (ps & 1);
-    lb.counter_other = counters + ((ps + 1) & 1);
-    return lb;
-  };
-  constexpr int kHist = kPassesPerWord * kRadix;
-  // array 0: LSD over the words of x:y:z:..., least significant word first
+  // Array 0: LSD over the words of x:y:z:..., least significant word first.
+  // Slots: 0 = row id, d = word d (1 <= d < k), k = word 0.  Every pass moves
+  // the sort word as its key and all other slots as payload; the first pass
+  // reads the tuple rows themselves.
+  auto word_slot = [&](int d) { return d == 0 ? k : d; };
   int cur = 0;
   for (int w = k - 1; w >= 0; --w) {
-    uint32_t* h = hist + (size_t)(k - 1 - w) * kHist;
-    const uint32_t* col = keys + (size_t)w * un;
-    const bool first = w == k - 1;
-    // every row takes part, so the digit counts need no particular order
-    KD_LAUNCH(KD_K_HIST, launch_digit_hist(col, nullptr, n, nullptr, 0, h, st));
     for (int ps = 0; ps < kPassesPerWord; ++ps) {
-      const int mode = ps > 0 ? 0 : (first ? 2 : 1);
-      const bool last_of_word = ps == kPassesPerWord - 1;
-      uint32_t* kout = (!last_of_word || w == 0) ? kbuf[cur ^ 1] : nullptr;
-      KD_LAUNCH(KD_K_ONESWEEP, launch_onesweep(mode, kbuf[cur], vbuf[cur], col, kout, vbuf[cur ^ 1], n, nullptr,
-                             ps * kRadixBits, h + ps * kRadix, lookback(pass++), st));
+      const bool from_tuples = (w == k - 1 && ps == 0);
+      Payload pay{};
+      int q = 0;
+      for (int sl = 0; sl <= k; ++sl) {
+        if (sl == word_slot(w)) continue;
+        Plane& pl = pay.p[q++];
+        pl.out = slot(cur ^ 1, sl);
+        if (from_tuples) {
+          pl.kind = sl == 0 ? kPlaneIndex : kPlaneTupleWord;
+          pl.word = sl == k ? 0 : sl;
+        } else {
+          pl.kind = kPlaneArray;
+          pl.in = slot(cur, sl);
+        }
+      }
+      pay.count = q;
+      KD_LAUNCH(KD_K_ONESWEEP,
+                launch_radix_pass(from_tuples ? nullptr : slot(cur, word_slot(w)), ts, w,
+                                  slot(cur ^ 1, word_slot(w)), pay, n, nullptr, ps * kRadixBits,
+                                  rcnt, rgrp, st));
       cur ^= 1;
     }
   }
-  // Sec. 2.1 duplicate removal on the fully sorted order
-  {
-    LookBack lb;
-    lb.cur = at<uint32_t>(ws, L.dlb0);
-    lb.other = at<uint32_t>(ws, L.dlb1);
-    lb.counter = counters + 2;
-    lb.counter_other = counters + 3;
-    KD_LAUNCH(KD_K_DEDUP, launch_dedup(vbuf[cur], kbuf[cur], keys, n, k, S, nu, lb, st));
-  }
-  // chain: the array for super key d is the stable sort by word d of the
-  // array for super key d+1
+  // Sec. 2.1 duplicate removal on the fully sorted order; hands the words
+  // w1..w_{k-1} of the kept rows to the chain
+  KD_LAUNCH(KD_K_DEDUP, launch_dedup(slot(cur, k), slot(cur, 0), n, k, S, carry, (int64_t)un,
+                                     at<uint32_t>(ws, L.dcnt), nu, st));
+  // carry slot d-1 holds word d of the current order
+  auto carried = [&](int d) { return carry + (size_t)(d - 1) * un; };
+  // Chain: the array for super key d is the stable sort by word d of the
+  // array for super key d+1.  Besides the row id, each sort carries the ranks
+  // already known -- the input position is the rank in order d+1 -- straight
+  // into array d's level-0 rank planes (plane c = rank in order d+1+c), and
+  // the key words of the sorts still to come.
   for (int d = k - 1; d >= 1; --d) {
-    uint32_t* h = hist + (size_t)(k + (k - 1 - d)) * kHist;
-    const uint32_t* col = keys + (size_t)d * un;
-    const uint32_t* in = S + (size_t)((d + 1) % k) * un;
-    KD_LAUNCH(KD_K_HIST, launch_digit_hist(col, in, n, nu, 1, h, st));
+    const uint32_t* in_ids = S + (size_t)((d + 1) % k) * un;
+    const uint32_t* in_rec = rec0 + record_offset((d + 1) % k, k, n);
+    uint32_t* out_rec = rec0 + record_offset(d, k, n);
+    const int known = k - d;  // record planes 0 .. k-d-1
     int c = 0;
     for (int ps = 0; ps < kPassesPerWord; ++ps) {
-      const bool last = ps == kPassesPerWord - 1;
-      const int mode = ps == 0 ? 1 : 0;
-      const uint32_t* vin = ps == 0 ? in : vbuf[c];
-      uint32_t* vout = last ? S + (size_t)d * un : vbuf[c ^ 1];
-      uint32_t* kout = last ? nullptr : kbuf[c ^ 1];
-      KD_LAUNCH(KD_K_ONESWEEP, launch_onesweep(mode, kbuf[c], vin, col, kout, vout, n, nu, ps * kRadixBits,
-                             h + ps * kRadix, lookback(pass++), st));
+      const bool first = ps == 0, last = ps == kPassesPerWord - 1;
+      Payload pay{};
+      int q = 0;
+      {  // slot 0: row id
+        Plane& pl = pay.p[q++];
+        pl.kind = kPlaneArray;
+        pl.in = first ? in_ids : slot(c, 0);
+        pl.out = last ? S + (size_t)d * un : slot(c ^ 1, 0);
+      }
+      for (int cc = 0; cc < known; ++cc) {  // slots 1 .. known: rank planes
+        Plane& pl = pay.p[q++];
+        if (first) {
+          pl.kind = cc == 0 ? kPlaneIndex : kPlaneArray;
+          pl.in = cc == 0 ? nullptr : in_rec + (size_t)(cc - 1) * un;
+        } else {
+          pl.kind = kPlaneArray;
+          pl.in = slot(c, 1 + cc);
+        }
+        pl.out = last ? out_rec + (size_t)cc * un : slot(c ^ 1, 1 + cc);
+      }
+      for (int dd = d - 1; dd >= 1; --dd) {  // key words of the later sorts
+        const int sl = known + (d - dd);
+        Plane& pl = pay.p[q++];
+        pl.kind = kPlaneArray;
+        pl.in = first ? carried(dd) : slot(c, sl);
+        pl.out = last ? carried(dd) : slot(c ^ 1, sl);
+      }
+      pay.count = q;
+      const uint32_t* kin = first ? carried(d) : slot(c, k);
+      uint32_t* kout = last ? nullptr : slot(c ^ 1, k);
+      KD_LAUNCH(KD_K_ONESWEEP, launch_radix_pass(kin, ts, 0, kout, pay, n, nu, ps * kRadixBits,
+                                                 rcnt, rgrp, st));
       c ^= 1;
     }
   }
-  if (k > 1) {
-    KD_LAUNCH(KD_K_RECORDS, launch_invert(S, n, k, nu, at<uint32_t>(ws, L.rank), st));
-    KD_LAUNCH(KD_K_RECORDS, launch_records(S, at<uint32_t>(ws, L.rank), n, k, nu, at<uint32_t>(ws, L.rec0), st));
-  }
+  if (k > 1)
+    KD_LAUNCH(KD_K_RECORDS, launch_complete_records(rec0, S + (size_t)1 * un, n, k, nu, st));
   return KD_OK;
 }
 
@@ -202,24 +228,21 @@ int partition_impl(int64_t n, int k, int32_t* perm, int32_t* lo, int32_t* hi, in
   const Layout L = plan(n, k);
   const int64_t* nu = at<int64_t>(ws, L.nu);
   uint32_t* S = at<uint32_t>(ws, L.S);
-  uint32_t* counters = at<uint32_t>(ws, L.counters);
   if (n > 0) {
     if (k == 1) {
       KD_TRY(launch_copy_k1(S, nu, n, perm, st));
     } else {
-      const uint32_t* b0 = at<uint32_t>(ws, L.rec0);
-      const uint32_t* b1 = at<uint32_t>(ws, L.rec1);
-      uint64_t* llb[2] = {at<uint64_t>(ws, L.llb0), at<uint64_t>(ws, L.llb1)};
+      // keep the on-chip finish within the 160 KiB of LDS of a workgroup
+      while (cutover > 1024 && leaf_lds_bytes(cutover, k) + 8192 > 160 * 1024) cutover /= 2;
+      const uint32_t* r0 = at<uint32_t>(ws, L.rec0);
+      uint32_t* r1 = at<uint32_t>(ws, L.rec1);
+      uint32_t* r2 = at<uint32_t>(ws, L.rec2);
       const int levels = cutover_depth(n, cutover);
-      for (int d = 0; d < levels; ++d) {
-        LookBack64 lb;
-        lb.cur = llb[d & 1];
-        lb.other = llb[(d + 1) & 1];
-        lb.counter = counters + 4 + (d & 1);
-        lb.counter_other = counters + 4 + ((d + 1) & 1);
-        KD_LAUNCH(KD_K_LEVEL, launch_level(b0, b1, n, k, d, cutover, nu, S, perm, lb, st));
-      }
-      KD_LAUNCH(KD_K_LEAF, launch_leaf(b0, b1, n, k, cutover, nu, S, perm, levels, st));
+      for (int d = 0; d < levels; ++d)
+        KD_LAUNCH(KD_K_LEVEL, launch_level(r0, r1, r2, n, k, d, cutover, nu, perm,
+                                           at<void>(ws, L.seginfo), at<uint32_t>(ws, L.lcnt),
+                                           at<uint64_t>(ws, L.lcarry), st));
+      KD_LAUNCH(KD_K_LEAF, launch_leaf(r0, r1, r2, n, k, cutover, nu, perm, levels, st));
     }
     if (lo && hi) KD_TRY(launch_children(nu, n, lo, hi, st));
   }

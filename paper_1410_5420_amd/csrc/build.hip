@@ -26,426 +26,739 @@ __device__ __host__ __forceinline__ int moves_before(int depth, int j, int k) {
   return depth - as_split;
 }
 
-// ---- global level -------------------------------------------------------------
+// Record buffers: level-0 records stay untouched in rec0 (they double as the
+// rank-translation tables); moved arrays alternate between b1 and b2.
+struct RecBufs {
+  const uint32_t* rec0;
+  uint32_t* b1;
+  uint32_t* b2;
+};
+__device__ __forceinline__ const uint32_t* buf_after(const RecBufs& B, int moves) {
+  return moves == 0 ? B.rec0 : ((moves & 1) ? B.b1 : B.b2);
+}
 
-constexpr int kLvThreads = 256;
-constexpr int kLvItems = kLevelTile / kLvThreads;  // 16
+// ---- global level -------------------------------------------------------------
+// A level is three launches with no waiting between workgroups:
+//   1. count: tile t of moving array a finds the subarrays that meet it (and
+//      their medians' ranks), then counts, per subarray piece, the elements
+//      that go to the lower half and whether the median itself is there;
+//   2. scan:  one block per array chains those counts from tile to tile
+//      along each subarray (a segmented scan);
+//   3. move:  tile t recomputes its elements' sides, adds the in-tile prefix
+//      to the carried counts and writes every rank plane to its new place.
+
+constexpr int kLvThreads = 512;
+constexpr int kLvItems = kLevelTile / kLvThreads;  // 8
 constexpr int kLvWaves = kLvThreads / kWave;
 constexpr int kLvChunks = kLvItems * kLvWaves;     // 64
 
-// 64-bit look-back word: [63:62] status, [61] segment head seen, [47:32] node
-// count, [31:0] lower count.
-constexpr uint64_t kLb64Agg = 1ull << 62;
-constexpr uint64_t kLb64Inc = 2ull << 62;
-constexpr uint64_t kLb64Head = 1ull << 61;
+// A global level only runs while every subarray holds at least C >= 1024
+// elements, so a tile of 4096 positions meets at most kMaxSeg of them and
+// every one of them contains one of the sample positions t0, t0+512, ...,
+// t0+3584, t1-1 (or the position after it, when the sample is a node).
+constexpr int kMaxSeg = 8;
+constexpr int kSamples = kLevelTile / 512 + 1;
 
-__device__ __forceinline__ uint64_t pack_counts(uint64_t lower, uint64_t node) {
-  return (lower & 0xFFFFFFFFull) | ((node & 0xFFFFull) << 32);
+// Subarrays meeting a tile, shared by the count and move launches.
+struct SegInfo {
+  int32_t s[kMaxSeg];
+  int32_t e[kMaxSeg];
+  uint32_t med[kMaxSeg];  // the median's rank in the split order
+  int32_t nseg;
+  int32_t pad;
+};
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
 }
 
-// A global level only runs while every subarray holds at least C >= 1024
-// elements, so a tile of 4096 positions meets at most kMaxSeg of them.
-constexpr int kMaxSeg = 8;
-
-template <int R>
-__global__ __launch_bounds__(kLvThreads) void k_level(const uint32_t* __restrict__ buf0,
-                                                     const uint32_t* __restrict__ buf1, int64_t n,
-                                                     int k, int depth, int64_t cutover,
-                                                     const int64_t* nu_ptr,
-                                                     const uint32_t* __restrict__ S,
-                                                     int32_t* __restrict__ perm, uint64_t* lb,
-                                                     uint64_t* lb_other, uint32_t* counter,
-                                                     uint32_t* counter_other, int tiles_per_array) {
-  __shared__ uint32_t s_chunk[kLvChunks];
-  __shared__ uint32_t s_pre[kLevelTile];
-  __shared__ int64_t s_seg_s[kMaxSeg], s_seg_e[kMaxSeg];
-  __shared__ uint32_t s_med[kMaxSeg];
-  __shared__ uint32_t s_seg_pre[kMaxSeg];
-  __shared__ int s_nseg;
-  __shared__ uint32_t s_tile;
-  __shared__ uint32_t s_total;
-  __shared__ uint64_t s_carry;
-
-  const int tid = threadIdx.x;
-  const int w = tid / kWave;
-  if (tid == 0) s_tile = next_tile(counter);
-  __syncthreads();
-  const uint32_t tile_g = s_tile;
-  if (tid == 0) {
-    lb_other[tile_g] = 0;
-    if (tile_g == 0) *counter_other = 0;
+// Wave 0 of a block: subarrays meeting [t0, t1) at `depth`, their medians'
+// ranks in order p, and (write_perm) the row id of every median in the tile.
+__device__ void find_subarrays(const RecBufs& B, int64_t n, int k, int depth, int nu, int t0,
+                               int t1, bool write_perm, int32_t* perm, SegInfo* out) {
+  const int lane = lane_id();
+  const int p = depth % k;
+  int s = INT32_MAX, e = -1;
+  if (lane < kSamples) {
+    int pos = t0 + lane * 512;
+    if (pos > t1 - 1) pos = t1 - 1;
+    subarray_at(pos, nu, depth, &s, &e);
+    if (e < s && pos + 1 < t1) subarray_at(pos + 1, nu, depth, &s, &e);
+    if (e < s) {
+      s = INT32_MAX;
+      e = -1;
+    }
   }
-  const int64_t nu = *nu_ptr;
+  const int prev_s = __shfl_up(s, 1, kWave);
+  const bool keep = lane < kSamples && s != INT32_MAX && (lane == 0 || prev_s != s);
+  const uint64_t km = __ballot(keep);
+  if (keep) {
+    const int idx = (int)popc64(km & lanes_below_mask());
+    if (idx < kMaxSeg) {
+      out->s[idx] = s;
+      out->e[idx] = e;
+      // The median's rank in order p: the split array's record holds its rank
+      // in order p+1 (plane 0), and the level-0 records of array p+1 translate
+      // that (their plane k-2 is order p).
+      const int m = s + ((e - s) >> 1);
+      const uint32_t* split = buf_after(B, moves_before(depth, p, k)) + record_offset(p, k, n);
+      const uint32_t r1 = split[m];
+      const int p1 = (p + 1) % k;
+      const uint32_t rp = B.rec0[record_offset(p1, k, n) + (int64_t)(k - 2) * n + r1];
+      out->med[idx] = rp;
+      if (write_perm && m >= t0 && m < t1) {
+        // row ids travel in array 0's records (plane k-1), indexed by the
+        // rank in order 0: that is rp itself when p == 0, otherwise plane
+        // (k - p - 1) of the median's record
+        const uint32_t r0 = p == 0 ? rp : split[(int64_t)((k - p - 1) % k) * n + m];
+        perm[m] = (int32_t)B.rec0[record_offset(0, k, n) + (int64_t)(k - 1) * n + r0];
+      }
+    }
+  }
+  if (lane == 0) out->nseg = min((int)popc64(km), kMaxSeg);
+}
+
+__global__ __launch_bounds__(kLvThreads) void k_level_count(const RecBufs B, int64_t n, int k,
+                                                           int depth, int64_t cutover,
+                                                           const int64_t* nu_ptr,
+                                                           int32_t* __restrict__ perm,
+                                                           SegInfo* __restrict__ seginfo,
+                                                           uint32_t* __restrict__ cnt,
+                                                           int tiles_per_array) {
+  __shared__ SegInfo s_si;
+  __shared__ uint32_t s_cnt[kMaxSeg];
+  const int tid = threadIdx.x;
+  const int nu = (int)*nu_ptr;
   if (depth >= cutover_depth(nu, cutover)) return;
   const int p = depth % k;
-  const int a = (int)(tile_g / (uint32_t)tiles_per_array);
-  const int64_t t = tile_g % (uint32_t)tiles_per_array;
+  const int a = blockIdx.x / tiles_per_array;
+  const int t = blockIdx.x % tiles_per_array;
   const int j = (p + 1 + a) % k;
-  const int64_t t0 = t * kLevelTile;
+  const int t0 = t * kLevelTile;
   if (t0 >= nu) return;
-  const int64_t t1 = (t0 + kLevelTile < nu) ? t0 + kLevelTile : nu;
-
-  const int64_t arr_stride = (int64_t)R * n;
-  const bool odd_j = moves_before(depth, j, k) & 1;
-  const uint32_t* src = (odd_j ? buf1 : buf0) + j * arr_stride;
-  uint32_t* dst = const_cast<uint32_t*>(odd_j ? buf0 : buf1) + j * arr_stride;
-  const uint32_t* split = ((moves_before(depth, p, k) & 1) ? buf1 : buf0) + p * arr_stride;
-
-  if (tid == 0) {
-    int ns = 0;
-    int64_t pos = t0;
-    while (pos < t1 && ns < kMaxSeg) {
-      int64_t s, e;
-      subarray_at(pos, nu, depth, &s, &e);
-      if (e < s) {
-        ++pos;  // node of a shallower level: no element lives here
-        continue;
+  const int t1 = min(t0 + kLevelTile, nu);
+  // the plane holding the rank in order p; its loads go out before the
+  // subarray search
+  const int cp = (p - j - 1 + 2 * k) % k;
+  const uint32_t* plane = buf_after(B, moves_before(depth, j, k)) + record_offset(j, k, n) +
+                          (int64_t)cp * n;
+  uint32_t rp[kLvItems];
+#pragma unroll
+  for (int it = 0; it < kLvItems; ++it) {
+    const int i = t0 + it * kLvThreads + tid;
+    rp[it] = i < t1 ? plane[i] : 0u;
+  }
+  if (tid < kMaxSeg) s_cnt[tid] = 0;
+  if (tid < kWave) find_subarrays(B, n, k, depth, nu, t0, t1, a == 0, perm, &s_si);
+  __syncthreads();
+  const int nseg = s_si.nseg;
+  if (a == 0 && tid < kMaxSeg) {
+    SegInfo* o = seginfo + t;
+    o->s[tid] = s_si.s[tid];
+    o->e[tid] = s_si.e[tid];
+    o->med[tid] = s_si.med[tid];
+    if (tid == 0) o->nseg = nseg;
+  }
+  uint32_t c[kMaxSeg];
+#pragma unroll
+  for (int q = 0; q < kMaxSeg; ++q) c[q] = 0;
+#pragma unroll
+  for (int it = 0; it < kLvItems; ++it) {
+    const int i = t0 + it * kLvThreads + tid;
+    if (i >= t1) continue;
+#pragma unroll
+    for (int q = 0; q < kMaxSeg; ++q) {
+      if (q < nseg && i >= s_si.s[q] && i <= s_si.e[q]) {
+        const uint32_t med = s_si.med[q];
+        c[q] += rp[it] < med ? 1u : (rp[it] == med ? 0x10000u : 0u);
       }
-      s_seg_s[ns] = s;
-      s_seg_e[ns] = e;
-      const int64_t m = median_of(s, e);
-      const uint32_t r = split[(int64_t)p * n + m];  // the median's rank in order p
-      s_med[ns] = r;
-      if (a == 0 && m >= t0 && m < t1) perm[m] = (int32_t)S[(int64_t)p * n + r];
-      ++ns;
-      pos = e + 1;
     }
-    s_nseg = ns;
+  }
+#pragma unroll
+  for (int q = 0; q < kMaxSeg; ++q) {
+    if (q < nseg) {
+      const uint32_t v = wave_sum(c[q]);
+      if (lane_id() == 0 && v) atomicAdd(&s_cnt[q], v);
+    }
   }
   __syncthreads();
-  const int nseg = s_nseg;
+  if (tid < kMaxSeg) cnt[((int64_t)a * tiles_per_array + t) * kMaxSeg + tid] = s_cnt[tid];
+}
 
-  uint32_t v[R][kLvItems];
+// Chains the counts along every subarray: carry[a][t] = counts of tile t's
+// first subarray in all earlier tiles (lower in bits 0-31, node in 32-47).
+__global__ __launch_bounds__(1024) void k_level_scan(int64_t n, int k, int depth, int64_t cutover,
+                                                    const int64_t* nu_ptr,
+                                                    const SegInfo* __restrict__ seginfo,
+                                                    const uint32_t* __restrict__ cnt,
+                                                    uint64_t* __restrict__ carry,
+                                                    int tiles_per_array) {
+  __shared__ uint64_t s_v[1024];
+  __shared__ int s_h[1024];
+  __shared__ uint64_t s_run;
+  const int tid = threadIdx.x;
+  const int64_t nu = *nu_ptr;
+  if (depth >= cutover_depth(nu, cutover)) return;
+  const int a = blockIdx.x;
+  const int tiles = (int)((nu + kLevelTile - 1) / kLevelTile);
+  if (tid == 0) s_run = 0;
+  __syncthreads();
+  for (int base = 0; base < tiles; base += 1024) {
+    const int t = base + tid;
+    // tile t: value = counts of its last subarray inside it; head = that
+    // subarray starts inside it
+    uint64_t v = 0;
+    int h = 1;
+    bool cont = false;
+    if (t < tiles) {
+      const SegInfo& si = seginfo[t];
+      const int t0 = t * kLevelTile;
+      const int ns = si.nseg;
+      if (ns > 0) {
+        const uint32_t c = cnt[((int64_t)a * tiles_per_array + t) * kMaxSeg + (ns - 1)];
+        v = (uint64_t)(c & 0xFFFF) | ((uint64_t)(c >> 16) << 32);
+        h = si.s[ns - 1] >= t0;
+        cont = si.s[0] < t0;
+      }
+    }
+    // inclusive segmented scan over the block (Hillis-Steele in LDS)
+    s_v[tid] = v;
+    s_h[tid] = h;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+      uint64_t vo = 0;
+      int ho = 0;
+      if (tid >= d) {
+        vo = s_v[tid - d];
+        ho = s_h[tid - d];
+      }
+      __syncthreads();
+      if (tid >= d) {
+        if (!h) v += vo;
+        h = h || ho;
+      }
+      s_v[tid] = v;
+      s_h[tid] = h;
+      __syncthreads();
+    }
+    // the carry from the previous block of tiles joins until the first head
+    const uint64_t run = s_run;
+    const uint64_t incl = h ? v : run + v;
+    // exclusive value seen by tile t: inclusive value of tile t-1
+    uint64_t prev = tid > 0 ? (s_h[tid - 1] ? s_v[tid - 1] : run + s_v[tid - 1]) : run;
+    __syncthreads();
+    if (t < tiles) carry[(int64_t)a * tiles_per_array + t] = cont ? prev : 0ull;
+    if (tid == 1023) s_run = incl;
+    __syncthreads();
+  }
+}
+
+template <int W>
+struct Rec {
+  uint32_t v[W];
+};
+
+// Move one tile of one array: W planes (k-1 ranks, + row id for array 0).
+template <int W>
+__device__ __forceinline__ void level_move_tile(const uint32_t* __restrict__ src,
+                                               uint32_t* __restrict__ dst, int64_t n, int cp,
+                                               int t0, int t1, const SegInfo& si, uint64_t carry,
+                                               uint32_t* s_chunk, uint32_t* s_pre) {
+  const int tid = threadIdx.x;
+  const int w = tid / kWave;
+  const int lane = tid % kWave;
+  const int nseg = si.nseg;
+
+  uint32_t v[W][kLvItems];
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    const uint32_t* sp = src + (int64_t)c * n;
+#pragma unroll
+    for (int it = 0; it < kLvItems; ++it) {
+      const int i = t0 + it * kLvThreads + tid;
+      v[c][it] = i < t1 ? sp[i] : 0u;
+    }
+  }
   uint32_t flag[kLvItems];
   int8_t sg[kLvItems];
   uint32_t within[kLvItems];
 #pragma unroll
   for (int it = 0; it < kLvItems; ++it) {
-    const int64_t i = t0 + it * kLvThreads + tid;
+    const int i = t0 + it * kLvThreads + tid;
     sg[it] = -1;
     if (i < t1) {
       for (int q = 0; q < nseg; ++q) {
-        if (i >= s_seg_s[q] && i <= s_seg_e[q]) {
+        if (i >= si.s[q] && i <= si.e[q]) {
           sg[it] = (int8_t)q;
           break;
         }
       }
     }
-    if (sg[it] >= 0) {
-#pragma unroll
-      for (int q = 0; q < R; ++q) v[q][it] = src[(int64_t)q * n + i];
-    }
-  }
-#pragma unroll
-  for (int it = 0; it < kLvItems; ++it) {
     uint32_t f = 0;
     if (sg[it] >= 0) {
       uint32_t rp = 0;
 #pragma unroll
-      for (int q = 0; q < R; ++q)
-        if (q == p) rp = v[q][it];
-      const uint32_t med = s_med[sg[it]];
+      for (int c = 0; c < W; ++c)
+        if (c == cp) rp = v[c][it];
+      const uint32_t med = si.med[sg[it]];
       f = rp < med ? 1u : (rp == med ? 0x10000u : 0u);
     }
     flag[it] = f;
     const uint32_t inc = wave_inclusive_sum(f);
     within[it] = inc - f;
-    if (lane_id() == kWave - 1) s_chunk[it * kLvWaves + w] = inc;
+    if (lane == kWave - 1) s_chunk[it * kLvWaves + w] = inc;
   }
   __syncthreads();
   if (w == 0) {
     const uint32_t c = s_chunk[tid];
-    const uint32_t inc = wave_inclusive_sum(c);
-    s_chunk[tid] = inc - c;
-    if (tid == kWave - 1) s_total = inc;
+    s_chunk[tid] = wave_inclusive_sum(c) - c;
   }
   __syncthreads();
   // exclusive in-tile prefix of every position, packed as lower | node << 16
 #pragma unroll
   for (int it = 0; it < kLvItems; ++it) {
-    const int64_t i = t0 + it * kLvThreads + tid;
+    const int i = t0 + it * kLvThreads + tid;
     if (i < t1) s_pre[i - t0] = s_chunk[it * kLvWaves + w] + within[it];
   }
   __syncthreads();
-
-  if (tid == 0) {
-    const uint32_t tot = s_total;
-    for (int q = 0; q < nseg; ++q) s_seg_pre[q] = s_seg_s[q] >= t0 ? s_pre[s_seg_s[q] - t0] : 0u;
-    // counts of the tile's last subarray inside this tile
-    const bool head = nseg == 0 || s_seg_s[nseg - 1] >= t0;
-    const uint32_t lastv = nseg == 0 ? 0u : tot - s_seg_pre[nseg - 1];
-    const bool need_carry = nseg > 0 && s_seg_s[0] < t0;
-    uint64_t* mine = lb + tile_g;
-    if (head)
-      st_flag64(mine, kLb64Inc | kLb64Head | pack_counts(lastv & 0xFFFF, lastv >> 16));
-    else
-      st_flag64(mine, kLb64Agg | pack_counts(lastv & 0xFFFF, lastv >> 16));
-    uint64_t lower = 0, node = 0;
-    if (need_carry) {
-      // counts of the first subarray in all earlier tiles
-      int64_t tt = (int64_t)tile_g - 1;
-      const int64_t first_tile = (int64_t)a * tiles_per_array;
-      uint32_t spins = 0;
-      while (tt >= first_tile) {
-        const uint64_t x = ld_flag64(lb + tt);
-        const uint64_t status = x >> 62;
-        if (status == 0) {
-          if (++spins > kSpinLimit) break;
-          __builtin_amdgcn_s_sleep(1);
-          continue;
-        }
-        lower += x & 0xFFFFFFFFull;
-        node += (x >> 32) & 0xFFFFull;
-        if (status == 2 || (x & kLb64Head)) break;
-        --tt;
-      }
-      if (!head)
-        st_flag64(mine, kLb64Inc | pack_counts(lower + (lastv & 0xFFFF), node + (lastv >> 16)));
-    }
-    s_carry = pack_counts(lower, node);
-  }
-  __syncthreads();
-  const uint64_t carry = s_carry;
-  const int64_t carry_lower = (int64_t)(carry & 0xFFFFFFFFull);
-  const int64_t carry_node = (int64_t)((carry >> 32) & 0xFFFF);
-
+  const int carry_lower = (int)(carry & 0xFFFFFFFFull);
+  const int carry_node = (int)((carry >> 32) & 0xFFFF);
+  int dest[kLvItems];
 #pragma unroll
   for (int it = 0; it < kLvItems; ++it) {
+    dest[it] = -1;
     if (sg[it] < 0 || flag[it] == 0x10000u) continue;
     const int q = sg[it];
-    const int64_t i = t0 + it * kLvThreads + tid;
+    const int i = t0 + it * kLvThreads + tid;
     const uint32_t pre = s_pre[i - t0];
-    const int64_t s = s_seg_s[q], e = s_seg_e[q];
-    const uint32_t base = s_seg_pre[q];
-    int64_t low = (int64_t)(pre & 0xFFFF) - (base & 0xFFFF);
-    int64_t nd = (int64_t)(pre >> 16) - (base >> 16);
+    const int s = si.s[q], e = si.e[q];
+    const uint32_t base = s >= t0 ? s_pre[s - t0] : 0u;
+    int low = (int)(pre & 0xFFFF) - (int)(base & 0xFFFF);
+    int nd = (int)(pre >> 16) - (int)(base >> 16);
     if (s < t0) {  // only the first subarray can start before the tile
       low += carry_lower;
       nd += carry_node;
     }
-    const int64_t m = median_of(s, e);
-    const int64_t dest = (flag[it] == 1u) ? s + low : m + 1 + (i - s - low - nd);
-    if (dest < s || dest > e || dest == m) continue;  // only reachable if the counts were inconsistent
+    const int m = s + ((e - s) >> 1);
+    const int d = (flag[it] == 1u) ? s + low : m + 1 + (i - s - low - nd);
+    if (d >= s && d <= e && d != m) dest[it] = d;  // otherwise the counts were inconsistent
+  }
 #pragma unroll
-    for (int r = 0; r < R; ++r) dst[(int64_t)r * n + dest] = v[r][it];
+  for (int c = 0; c < W; ++c) {
+    uint32_t* dp = dst + (int64_t)c * n;
+#pragma unroll
+    for (int it = 0; it < kLvItems; ++it)
+      if (dest[it] >= 0) dp[dest[it]] = v[c][it];
   }
 }
 
-hipError_t launch_level(const uint32_t* buf0, const uint32_t* buf1, int64_t n, int k, int depth,
-                        int64_t cutover, const int64_t* nu, const uint32_t* S, int32_t* perm,
-                        const LookBack64& lb, hipStream_t st) {
+template <int R>
+__global__ __launch_bounds__(kLvThreads) void k_level_move(const RecBufs B, int64_t n, int k,
+                                                          int depth, int64_t cutover,
+                                                          const int64_t* nu_ptr,
+                                                          const SegInfo* __restrict__ seginfo,
+                                                          const uint64_t* __restrict__ carry,
+                                                          int tiles_per_array) {
+  __shared__ uint32_t s_chunk[kLvChunks];
+  __shared__ uint32_t s_pre[kLevelTile];
+  __shared__ SegInfo s_si;
+  const int tid = threadIdx.x;
+  const int nu = (int)*nu_ptr;
+  if (depth >= cutover_depth(nu, cutover)) return;
+  const int p = depth % k;
+  const int a = blockIdx.x / tiles_per_array;
+  const int t = blockIdx.x % tiles_per_array;
+  const int j = (p + 1 + a) % k;
+  const int t0 = t * kLevelTile;
+  if (t0 >= nu) return;
+  const int t1 = min(t0 + kLevelTile, nu);
+  if (tid < kMaxSeg) {
+    s_si.s[tid] = seginfo[t].s[tid];
+    s_si.e[tid] = seginfo[t].e[tid];
+    s_si.med[tid] = seginfo[t].med[tid];
+    if (tid == 0) s_si.nseg = seginfo[t].nseg;
+  }
+  __syncthreads();
+  const uint64_t cy = carry[(int64_t)a * tiles_per_array + t];
+  const int mj = moves_before(depth, j, k);
+  const uint32_t* src = buf_after(B, mj) + record_offset(j, k, n);
+  uint32_t* dst = const_cast<uint32_t*>(buf_after(B, mj + 1)) + record_offset(j, k, n);
+  const int cp = (p - j - 1 + 2 * k) % k;
+  if (j == 0)
+    level_move_tile<R + 1>(src, dst, n, cp, t0, t1, s_si, cy, s_chunk, s_pre);
+  else
+    level_move_tile<R>(src, dst, n, cp, t0, t1, s_si, cy, s_chunk, s_pre);
+}
+
+hipError_t launch_level(const uint32_t* rec0, uint32_t* b1, uint32_t* b2, int64_t n, int k,
+                        int depth, int64_t cutover, const int64_t* nu, int32_t* perm,
+                        void* seginfo, uint32_t* cnt, uint64_t* carry, hipStream_t st) {
   if (n <= 0 || k < 2) return hipSuccess;
   const int tiles = (int)((n + kLevelTile - 1) / kLevelTile);
   const unsigned grid = (unsigned)(tiles * (k - 1));
-#define KD_LV(RR)                                                                              \
-  hipLaunchKernelGGL(k_level<RR>, dim3(grid), dim3(kLvThreads), 0, st, buf0, buf1, n, k, depth, \
-                     cutover, nu, S, perm, lb.cur, lb.other, lb.counter, lb.counter_other, tiles)
-  switch (k) {
+  RecBufs B{rec0, b1, b2};
+  SegInfo* si = static_cast<SegInfo*>(seginfo);
+  hipLaunchKernelGGL(k_level_count, dim3(grid), dim3(kLvThreads), 0, st, B, n, k, depth, cutover,
+                     nu, perm, si, cnt, tiles);
+  hipLaunchKernelGGL(k_level_scan, dim3(k - 1), dim3(1024), 0, st, n, k, depth, cutover, nu, si,
+                     cnt, carry, tiles);
+#define KD_LV(RR)                                                                               \
+  hipLaunchKernelGGL(k_level_move<RR>, dim3(grid), dim3(kLvThreads), 0, st, B, n, k, depth,     \
+                     cutover, nu, si, carry, tiles)
+  switch (k - 1) {
+    case 1: KD_LV(1); break;
     case 2: KD_LV(2); break;
     case 3: KD_LV(3); break;
     case 4: KD_LV(4); break;
     case 5: KD_LV(5); break;
     case 6: KD_LV(6); break;
     case 7: KD_LV(7); break;
-    case 8: KD_LV(8); break;
     default: return hipErrorInvalidValue;
   }
 #undef KD_LV
   return hipGetLastError();
 }
 
+size_t level_seginfo_bytes() { return sizeof(SegInfo); }
+
 // ---- on-chip finish (leaf phase) -----------------------------------------------------
 // One workgroup takes one subarray of at most C elements at the cutover depth
-// and runs all remaining levels in LDS.  Elements get local ids (their position
-// in the array sorted by order 0), each array becomes a list of 16-bit local
-// ids, and a level needs only "where does this id sit in the split array":
-// the element goes to the lower half iff that position is below the median.
+// and runs all remaining levels in LDS.  Elements get local ids -- their
+// position in the array sorted by order 0 -- and each array becomes a list of
+// 16-bit local ids.  A level then needs only "where does this id sit in the
+// split array": the element goes to the lower half iff that position is below
+// the median.  The k-1 arrays that move are partitioned together with
+// segmented scans (4 barriers per level).
 
 constexpr int kLfThreads = 256;
+constexpr int kLfWaves = kLfThreads / kWave;
+constexpr uint32_t kHole = 0xFFFFFFFFu;
+constexpr uint32_t kHeadBit = 0x80000000u;
 
+// Inclusive segmented sum across a wave: a lane with `head` starts a new run.
+__device__ __forceinline__ void wave_seg_scan(uint32_t& v, bool& h) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint32_t vo = __shfl_up(v, d, kWave);
+    const int ho = __shfl_up((int)h, d, kWave);
+    if ((int)lane_id() >= d) {
+      if (!h) v += vo;
+      h = h || ho;
+    }
+  }
+}
+
+// Stable LSD radix sort of up to C keys in LDS (8-bit digits): keys and 16-bit
+// values move between (ka, va) and (kb, vb); returns true when the result ended
+// in (kb, vb).  Element e is owned by wave e / (64 * kItems).
 template <int kItems>
-__global__ __launch_bounds__(kLfThreads) void k_leaf(const uint32_t* __restrict__ buf0,
-                                                    const uint32_t* __restrict__ buf1, int64_t n,
-                                                    int k, const int64_t* nu_ptr,
-                                                    const uint32_t* __restrict__ S0,
+__device__ bool lds_radix_sort(uint32_t* ka, uint16_t* va, uint32_t* kb, uint16_t* vb, int N,
+                               int passes, uint32_t (*s_cnt)[kRadix], uint32_t* s_dbase,
+                               uint32_t* s_tmp) {
+  const int tid = threadIdx.x;
+  const int w = tid / kWave;
+  const int lane = tid % kWave;
+  const uint64_t below = lanes_below_mask();
+  bool flipped = false;
+  for (int ps = 0; ps < passes; ++ps) {
+    const int shift = ps * kRadixBits;
+#pragma unroll
+    for (int q = 0; q < kLfWaves; ++q) s_cnt[q][tid] = 0;
+    __syncthreads();
+    uint32_t key[kItems], rank[kItems];
+    uint16_t val[kItems];
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const int e = w * (kWave * kItems) + j * kWave + lane;
+      const bool valid = e < N;
+      key[j] = valid ? ka[e] : 0u;
+      val[j] = valid ? va[e] : (uint16_t)0;
+      const uint32_t d = (key[j] >> shift) & 0xFF;
+      uint64_t m = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < kRadixBits; ++b) {
+        const bool bit = (d >> b) & 1;
+        const uint64_t bb = __ballot(bit);
+        m &= bit ? bb : ~bb;
+      }
+      uint32_t pre = 0;
+      if (valid) pre = s_cnt[w][d];
+      __builtin_amdgcn_wave_barrier();
+      const uint32_t before = popc64(m & below);
+      if (valid && before == 0) s_cnt[w][d] = pre + popc64(m);
+      __builtin_amdgcn_wave_barrier();
+      rank[j] = pre + before;
+    }
+    __syncthreads();
+    uint32_t tot = 0;
+#pragma unroll
+    for (int q = 0; q < kLfWaves; ++q) {
+      const uint32_t c = s_cnt[q][tid];
+      s_cnt[q][tid] = tot;
+      tot += c;
+    }
+    uint32_t all;
+    s_dbase[tid] = block_exclusive_sum<kLfThreads>(tot, s_tmp, &all);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const int e = w * (kWave * kItems) + j * kWave + lane;
+      if (e < N) {
+        const uint32_t d = (key[j] >> shift) & 0xFF;
+        const uint32_t dest = s_dbase[d] + s_cnt[w][d] + rank[j];
+        kb[dest] = key[j];
+        vb[dest] = val[j];
+      }
+    }
+    __syncthreads();
+    uint32_t* tk = ka; ka = kb; kb = tk;
+    uint16_t* tv = va; va = vb; vb = tv;
+    flipped = !flipped;
+  }
+  return flipped;
+}
+
+template <int kItems, int R>
+__global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, int64_t n, int k,
+                                                    const int64_t* nu_ptr,
                                                     int32_t* __restrict__ perm) {
-  extern __shared__ __align__(16) unsigned char s_raw[];
   constexpr int C = kItems * kLfThreads;
-  const int64_t cutover = C;
-  uint32_t* s_r0 = reinterpret_cast<uint32_t*>(s_raw);         // [C] rank in order 0 of each local id
-  uint32_t* s_pre = s_r0 + C;                                  // [C] prefix counts
-  uint16_t* s_segs = reinterpret_cast<uint16_t*>(s_pre + C);   // [C] subarray start per position
-  uint16_t* s_sege = s_segs + C;                               // [C] subarray end per position
-  uint16_t* s_pos = s_sege + C;                                // [C] position in split array per id
-  uint16_t* s_out = s_pos + C;                                 // [C] node id per position
-  uint16_t* s_tmp = s_out + C;                                 // [C]
-  uint16_t* s_arr = s_tmp + C;                                 // [k][C]
-  __shared__ uint32_t s_chunk[kWave + 1];
+  constexpr int kChunks = kItems * kLfWaves;
+  static_assert(kChunks <= kWave, "one wave scans the chunk totals of an array");
+  extern __shared__ __align__(16) unsigned char s_raw[];
+  uint32_t* s_r0 = reinterpret_cast<uint32_t*>(s_raw);       // [C] sorted order-0 ranks
+  uint32_t* s_id = s_r0 + C;                                 // [C] row id of each local id
+  uint16_t* s_pos = reinterpret_cast<uint16_t*>(s_id + C);   // [C] position in the split array
+  uint16_t* s_out = s_pos + C;                               // [C] node id of each position
+  uint16_t* s_lid = s_out + C;                               // [2][k][C] local-id arrays
+  __shared__ uint32_t s_chunk[R][kWave];
+  __shared__ uint32_t s_cnt[kLfWaves][kRadix];
+  __shared__ uint32_t s_dbase[kRadix];
+  __shared__ uint32_t s_tmp[kLfWaves + 1];
 
   const int tid = threadIdx.x;
+  const int w = tid / kWave;
+  const int lane = tid % kWave;
   const int64_t nu = *nu_ptr;
-  const int lc = cutover_depth(nu, cutover);
+  const int lc = cutover_depth(nu, C);
   const int64_t g = blockIdx.x;
-  if (lc < 62 && g >= ((int64_t)1 << lc)) return;
-  int64_t s = 0, e = nu - 1;
+  if (g >= ((int64_t)1 << lc)) return;
+  int64_t s0 = 0, e0 = nu - 1;
   for (int l = 0; l < lc; ++l) {
-    const int64_t m = median_of(s, e);
+    const int64_t m = median_of(s0, e0);
     if ((g >> (lc - 1 - l)) & 1)
-      s = m + 1;
+      s0 = m + 1;
     else
-      e = m - 1;
+      e0 = m - 1;
   }
-  const int N = (int)(e - s + 1);
+  const int N = (int)(e0 - s0 + 1);
   if (N <= 0) return;
 
-  const int R = k;
-  const int64_t arr_stride = (int64_t)R * n;
-  // order-0 ranks of the subarray, ascending (array 0 is sorted by order 0)
+  // Local id of an element = its position in array 0 (sorted by order 0).
+  // Array 1 stores the order-0 rank of each of its elements (plane k-2);
+  // sorting those ranks gives array 0's order, hence every array-1 element's
+  // local id, and the sorted list lets the other arrays find theirs by binary
+  // search.  Array 0's records carry the row ids.
   {
-    const uint32_t* a0 = ((moves_before(lc, 0, k) & 1) ? buf1 : buf0);
-    for (int i = tid; i < N; i += kLfThreads) {
-      s_r0[i] = a0[0 * n + s + i];
-      s_arr[i] = (uint16_t)i;
-      s_segs[i] = 0;
-      s_sege[i] = (uint16_t)(N - 1);
-      s_out[i] = 0xFFFF;
-    }
-  }
-  __syncthreads();
-  for (int j = 1; j < k; ++j) {
-    const uint32_t* aj = ((moves_before(lc, j, k) & 1) ? buf1 : buf0) + j * arr_stride;
-    for (int i = tid; i < N; i += kLfThreads) {
-      const uint32_t x = aj[0 * n + s + i];
-      int lo = 0, hi = N;  // lower_bound
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (s_r0[mid] < x)
-          lo = mid + 1;
-        else
-          hi = mid;
+    const uint32_t* a0 = buf_after(B, moves_before(lc, 0, k)) + record_offset(0, k, n);
+    const uint32_t* a1 = buf_after(B, moves_before(lc, 1, k)) + record_offset(1, k, n);
+    uint32_t* sk = reinterpret_cast<uint32_t*>(s_lid);        // sort scratch (aliases s_lid)
+    uint16_t* sv = reinterpret_cast<uint16_t*>(sk + C);
+    uint16_t* sv2 = sv + C;
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+      const int i = it * kLfThreads + tid;
+      if (i < N) {
+        s_id[i] = a0[(int64_t)R * n + s0 + i];
+        s_r0[i] = a1[(int64_t)(k - 2) * n + s0 + i];
+        sv2[i] = (uint16_t)i;
       }
-      s_arr[j * C + i] = (uint16_t)(lo < N ? lo : N - 1);
+    }
+    __syncthreads();
+    int passes = 1;
+    while (passes < 4 && (((uint64_t)nu - 1) >> (8 * passes)) != 0) ++passes;
+    const bool in_b = lds_radix_sort<kItems>(s_r0, sv2, sk, sv, N, passes, s_cnt, s_dbase, s_tmp);
+    // sorted ranks must end in s_r0; the array-1 positions they came from in regs
+    uint16_t from[kItems];
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+      const int i = it * kLfThreads + tid;
+      if (i < N) {
+        from[it] = in_b ? sv[i] : sv2[i];
+        if (in_b) s_r0[i] = sk[i];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+      const int i = it * kLfThreads + tid;
+      if (i < N) {
+        s_lid[i] = (uint16_t)i;                 // array 0
+        s_lid[1 * C + from[it]] = (uint16_t)i;  // array 1
+      }
+    }
+    for (int j = 2; j < k; ++j) {
+      const uint32_t* aj = buf_after(B, moves_before(lc, j, k)) + record_offset(j, k, n);
+      const int c0 = k - 1 - j;  // plane of order 0 in array j
+#pragma unroll
+      for (int it = 0; it < kItems; ++it) {
+        const int i = it * kLfThreads + tid;
+        if (i < N) {
+          const uint32_t x = aj[(int64_t)c0 * n + s0 + i];
+          int lo = 0, hi = N;  // lower bound of x among the sorted order-0 ranks
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (s_r0[mid] < x)
+              lo = mid + 1;
+            else
+              hi = mid;
+          }
+          s_lid[j * C + i] = (uint16_t)(lo < N ? lo : N - 1);
+        }
+      }
     }
   }
+
+  // Position i = it * kLfThreads + tid is owned by one thread for the whole
+  // phase, so its subarray (s | e << 16, or a hole) lives in registers.
+  uint32_t seg[kItems];
+#pragma unroll
+  for (int it = 0; it < kItems; ++it)
+    seg[it] = (it * kLfThreads + tid) < N ? ((uint32_t)(N - 1) << 16) : kHole;
+  uint32_t curmask = 0;  // bit j: which of the two buffers holds array j
   __syncthreads();
 
-  constexpr int items = kItems;
-  const int w = tid / kWave;
-  constexpr int kWaves = kLfThreads / kWave;
-  for (int depth = lc; (N >> (depth - lc)) > 0; ++depth) {
+  for (int depth = lc, rel = 0; (N >> rel) > 0; ++depth, ++rel) {
     const int p = depth % k;
-    uint16_t* ap = s_arr + p * C;
-    // where each live id sits in the split array; record the medians
-    for (int i = tid; i < N; i += kLfThreads) {
-      const int ss = s_segs[i], ee = s_sege[i];
-      if (ss > ee) continue;
+    const uint16_t* ap = s_lid + ((((curmask >> p) & 1) * k) + p) * C;
+    // phase 1: step down one level (the parent's node becomes a hole), then
+    // record where each id sits in the split array and each subarray's node
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+      const int i = it * kLfThreads + tid;
+      if (seg[it] == kHole) continue;
+      int ss = (int)(seg[it] & 0xFFFF), ee = (int)(seg[it] >> 16);
+      if (rel > 0) {
+        const int pm = ss + ((ee - ss) >> 1);
+        if (i == pm) {
+          seg[it] = kHole;
+          continue;
+        }
+        if (i < pm)
+          ee = pm - 1;
+        else
+          ss = pm + 1;
+        seg[it] = (uint32_t)ss | ((uint32_t)ee << 16);
+      }
       const uint16_t id = ap[i];
       s_pos[id] = (uint16_t)i;
       if (i == ss + ((ee - ss) >> 1)) s_out[i] = id;
     }
     __syncthreads();
-    for (int jj = 1; jj < k; ++jj) {
-      const int j = (p + jj) % k;
-      uint16_t* aj = s_arr + j * C;
-      // flags and chunked prefix (chunk = 64 consecutive positions)
-      uint32_t flag_reg[kItems], within_reg[kItems];
+    // phase 2: flags of the k-1 moving arrays, segmented within-chunk sums.
+    // Packed value: lower count in bits 0-15, node count in bits 16-28.
+    uint32_t fl[R][kItems];
 #pragma unroll
-      for (int it = 0; it < items; ++it) {
-        const int i = it * kLfThreads + tid;
-        uint32_t f = 0;
-        if (i < N) {
-          const int ss = s_segs[i], ee = s_sege[i];
-          if (ss <= ee) {
-            const int m = ss + ((ee - ss) >> 1);
-            const int pp = s_pos[aj[i]];
-            f = pp < m ? 1u : (pp == m ? 0x10000u : 0u);
-          }
-        }
-        const uint32_t inc = wave_inclusive_sum(f);
-        flag_reg[it] = f;
-        within_reg[it] = inc - f;
-        if (lane_id() == kWave - 1) s_chunk[it * kWaves + w] = inc;
-      }
-      __syncthreads();
-      if (w == 0) {
-        const int nchunks = items * kWaves;
-        const uint32_t c = tid < nchunks ? s_chunk[tid] : 0;
-        const uint32_t inc = wave_inclusive_sum(c);
-        if (tid < nchunks) s_chunk[tid] = inc - c;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int it = 0; it < items; ++it) {
-        const int i = it * kLfThreads + tid;
-        if (i < N) s_pre[i] = s_chunk[it * kWaves + w] + within_reg[it];
-      }
-      __syncthreads();
-#pragma unroll
-      for (int it = 0; it < items; ++it) {
-        const int i = it * kLfThreads + tid;
-        if (i >= N) continue;
-        const int ss = s_segs[i], ee = s_sege[i];
-        if (ss > ee) continue;
-        const uint32_t f = flag_reg[it];
-        if (f == 0x10000u) continue;
-        const int m = ss + ((ee - ss) >> 1);
-        const uint32_t pre = s_pre[i], ps = s_pre[ss];
-        const int low = (int)((pre & 0xFFFF) - (ps & 0xFFFF));
-        const int nd = (int)((pre >> 16) - (ps >> 16));
-        const int dest = (f == 1u) ? ss + low : m + 1 + (i - ss - low - nd);
-        if (dest >= ss && dest <= ee) s_tmp[dest] = aj[i];
-      }
-      __syncthreads();
-      // the partitioned list replaces array j (copy back keeps the layout fixed)
-      for (int i = tid; i < N; i += kLfThreads) aj[i] = s_tmp[i];
-      __syncthreads();
-    }
-    // next depth's subarrays
-    for (int i = tid; i < N; i += kLfThreads) {
-      const int ss = s_segs[i], ee = s_sege[i];
-      if (ss > ee) continue;
+    for (int it = 0; it < kItems; ++it) {
+      const int i = it * kLfThreads + tid;
+      const bool live = seg[it] != kHole;
+      const int ss = (int)(seg[it] & 0xFFFF), ee = (int)(seg[it] >> 16);
       const int m = ss + ((ee - ss) >> 1);
-      if (i < m) {
-        s_sege[i] = (uint16_t)(m - 1);
-      } else if (i > m) {
-        s_segs[i] = (uint16_t)(m + 1);
-      } else {
-        s_segs[i] = 1;
-        s_sege[i] = 0;
+      const bool head0 = live && i == ss;
+#pragma unroll
+      for (int a2 = 0; a2 < R; ++a2) {
+        const int j = (p + 1 + a2) % k;
+        uint32_t f = 0;
+        if (live) {
+          const int pp = s_pos[s_lid[((((curmask >> j) & 1) * k) + j) * C + i]];
+          f = pp < m ? 1u : (pp == m ? 0x10000u : 0u);
+        }
+        uint32_t v = f;
+        bool h = head0;
+        wave_seg_scan(v, h);
+        fl[a2][it] = (v - f) | (h ? kHeadBit : 0u) | (f == 1u ? 0x40000000u : 0u) |
+                     (f == 0x10000u ? 0x20000000u : 0u);
+        if (lane == kWave - 1) s_chunk[a2][it * kLfWaves + w] = v | (h ? kHeadBit : 0u);
       }
     }
     __syncthreads();
+    // phase 3: segmented exclusive scan over each array's chunk totals
+    for (int a2 = w; a2 < R; a2 += kLfWaves) {
+      const uint32_t c = lane < kChunks ? s_chunk[a2][lane] : kHeadBit;
+      uint32_t v = c & ~kHeadBit;
+      bool h = (c & kHeadBit) != 0;
+      wave_seg_scan(v, h);
+      const uint32_t prev = __shfl_up(v, 1, kWave);
+      if (lane < kChunks) s_chunk[a2][lane] = lane == 0 ? 0u : prev;
+    }
+    __syncthreads();
+    // phase 4: move every element of the k-1 arrays to its new position
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+      const int i = it * kLfThreads + tid;
+      if (seg[it] == kHole) continue;
+      const int ss = (int)(seg[it] & 0xFFFF), ee = (int)(seg[it] >> 16);
+      const int m = ss + ((ee - ss) >> 1);
+#pragma unroll
+      for (int a2 = 0; a2 < R; ++a2) {
+        const uint32_t x = fl[a2][it];
+        if (x & 0x20000000u) continue;  // the node itself is not copied
+        const int j = (p + 1 + a2) % k;
+        uint32_t pre = x & 0x1FFFFFFFu;
+        if (!(x & kHeadBit)) pre += s_chunk[a2][it * kLfWaves + w];
+        const int low = (int)(pre & 0xFFFF), nd = (int)(pre >> 16);
+        const int dest = (x & 0x40000000u) ? ss + low : m + 1 + (i - ss - low - nd);
+        const int cb = (curmask >> j) & 1;
+        if (dest >= ss && dest <= ee)
+          s_lid[((cb ^ 1) * k + j) * C + dest] = s_lid[(cb * k + j) * C + i];
+      }
+    }
+    curmask ^= ((1u << k) - 1) & ~(1u << p);  // every array but the split one moved
+    __syncthreads();
   }
-  for (int i = tid; i < N; i += kLfThreads) {
-    const int id = s_out[i];
-    if (id >= N) continue;  // every position receives a node; kept as a guard
-    const uint32_t r0 = s_r0[id];
-    if (r0 < (uint64_t)nu) perm[s + i] = (int32_t)S0[r0];
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    const int i = it * kLfThreads + tid;
+    if (i < N) {
+      const int id = s_out[i];
+      if (id < N) perm[s0 + i] = (int32_t)s_id[id];
+    }
   }
 }
 
-hipError_t launch_leaf(const uint32_t* buf0, const uint32_t* buf1, int64_t n, int k,
-                       int64_t cutover, const int64_t* nu, const uint32_t* S, int32_t* perm,
-                       int grid_bound_depth, hipStream_t st) {
+hipError_t launch_leaf(const uint32_t* rec0, uint32_t* b1, uint32_t* b2, int64_t n, int k,
+                       int64_t cutover, const int64_t* nu, int32_t* perm, int grid_bound_depth,
+                       hipStream_t st) {
   if (n <= 0 || k < 2) return hipSuccess;
-  const size_t lds = (size_t)cutover * (4 + 4 + 2 * 5 + 2 * k);
+  const size_t lds = leaf_lds_bytes(cutover, k);
   const unsigned grid = 1u << grid_bound_depth;
-#define KD_LF(IT)                                                                              \
-  do {                                                                                         \
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_leaf<IT>),              \
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);  \
-    if (e != hipSuccess) return e;                                                             \
-    hipLaunchKernelGGL(k_leaf<IT>, dim3(grid), dim3(kLfThreads), lds, st, buf0, buf1, n, k, nu, \
-                       S, perm);                                                               \
-  } while (0)
+  RecBufs B{rec0, b1, b2};
+  const void* fn = nullptr;
+#define KD_LF_R(IT)                                                  \
+  switch (k - 1) {                                                   \
+    case 1: fn = reinterpret_cast<const void*>(k_leaf<IT, 1>); break; \
+    case 2: fn = reinterpret_cast<const void*>(k_leaf<IT, 2>); break; \
+    case 3: fn = reinterpret_cast<const void*>(k_leaf<IT, 3>); break; \
+    case 4: fn = reinterpret_cast<const void*>(k_leaf<IT, 4>); break; \
+    case 5: fn = reinterpret_cast<const void*>(k_leaf<IT, 5>); break; \
+    case 6: fn = reinterpret_cast<const void*>(k_leaf<IT, 6>); break; \
+    case 7: fn = reinterpret_cast<const void*>(k_leaf<IT, 7>); break; \
+    default: return hipErrorInvalidValue;                            \
+  }
   switch (cutover) {
-    case 1024: KD_LF(4); break;
-    case 2048: KD_LF(8); break;
-    case 4096: KD_LF(16); break;
+    case 1024: KD_LF_R(4); break;
+    case 2048: KD_LF_R(8); break;
+    case 4096: KD_LF_R(16); break;
     default: return hipErrorInvalidValue;
   }
-#undef KD_LF
-  return hipGetLastError();
+#undef KD_LF_R
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  void* args[] = {&B, &n, &k, const_cast<int64_t**>(&nu), &perm};
+  return hipLaunchKernel(fn, dim3(grid), dim3(kLfThreads), args, lds, st);
 }
 
 // ---- shape helpers ---------------------------------------------------------------

@@ -1,6 +1,6 @@
 // Device-side building blocks shared by the gfx950 kernels of the k-d tree
-// builder: wave64 lane masks, agent-scope flag words for decoupled look-back,
-// block scans and the implicit shape of the balanced tree.
+// builder: wave64 lane masks and scans, block scans, the implicit shape of the
+// balanced tree and the layout of the rank records.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -59,38 +59,6 @@ __device__ __forceinline__ T block_exclusive_sum(T v, T* s_tmp, T* total) {
   return res;
 }
 
-// ---- agent-scope flag words (decoupled look-back) ----------------------------
-// A status word carries its readiness flag and its value together, so one
-// relaxed atomic access at agent scope moves both; no other ordering is
-// needed because only the counts travel between workgroups.
-
-__device__ __forceinline__ uint32_t ld_flag(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_flag(uint32_t* p, uint32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint64_t ld_flag64(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_flag64(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint32_t next_tile(uint32_t* counter) {
-  return __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Upper bound on polls of a predecessor's flag word.  Every wait finishes long
-// before this in a correct run; the bound only guarantees that no wave can
-// spin forever if a flag is never published (the results are then wrong and
-// the tests fail, but the kernel still exits).
-constexpr uint32_t kSpinLimit = 1u << 22;
-
-// 32-bit look-back word: [31:30] status, [29:0] count (counts < 2^30).
-constexpr uint32_t kLbAgg = 1u << 30;
-constexpr uint32_t kLbInc = 2u << 30;
-constexpr uint32_t kLbMask = (1u << 30) - 1;
-
 // ---- implicit shape of the balanced tree --------------------------------------
 // The node of [s, e] sits at its lower median; its children cover [s, m-1] and
 // [m+1, e].  At depth L the largest subarray holds floor(n / 2^L) elements.
@@ -98,7 +66,7 @@ constexpr uint32_t kLbMask = (1u << 30) - 1;
 __device__ __forceinline__ int64_t median_of(int64_t s, int64_t e) { return s + ((e - s) >> 1); }
 
 // Subarray at depth `depth` that contains position pos, or e < s when pos is
-// the node of a shallower subarray.
+// the node of a shallower subarray (64- and 32-bit forms).
 __device__ __forceinline__ void subarray_at(int64_t pos, int64_t nu, int depth, int64_t* s_out,
                                             int64_t* e_out) {
   int64_t s = 0, e = nu - 1;
@@ -118,11 +86,41 @@ __device__ __forceinline__ void subarray_at(int64_t pos, int64_t nu, int depth, 
   *e_out = e;
 }
 
+__device__ __forceinline__ void subarray_at(int pos, int nu, int depth, int* s_out, int* e_out) {
+  int s = 0, e = nu - 1;
+  for (int l = 0; l < depth; ++l) {
+    const int m = s + ((e - s) >> 1);
+    if (pos < m) {
+      e = m - 1;
+    } else if (pos > m) {
+      s = m + 1;
+    } else {
+      s = 1;
+      e = 0;
+      break;
+    }
+  }
+  *s_out = s;
+  *e_out = e;
+}
+
 // First depth at which every subarray holds at most `cutover` elements.
 __device__ __host__ __forceinline__ int cutover_depth(int64_t nu, int64_t cutover) {
   int d = 0;
   while ((nu >> d) > cutover) ++d;
   return d;
+}
+
+// ---- rank-record layout ------------------------------------------------------------
+// Array j (0 <= j < k) stores one record per position: k-1 ranks (plane c =
+// rank in order (j + 1 + c) mod k), plus the row id for array 0.  Arrays are
+// laid out one after another, array 0 first.
+__device__ __host__ __forceinline__ int record_width(int j, int k) { return k - 1 + (j == 0); }
+__device__ __host__ __forceinline__ int64_t record_offset(int j, int k, int64_t n) {
+  return j == 0 ? 0 : (int64_t)k * n + (int64_t)(j - 1) * (k - 1) * n;
+}
+__device__ __host__ __forceinline__ int64_t record_words(int k, int64_t n) {
+  return (int64_t)k * n + (int64_t)(k - 1) * (k - 1) * n;
 }
 
 }  // namespace kd

@@ -14,67 +14,79 @@ constexpr int kPassesPerWord = 32 / kRadixBits;
 constexpr int kSortTile = 4096;   // elements per onesweep tile
 constexpr int kLevelTile = 4096;  // elements per level-partition tile
 
-// Ping-pong look-back state: the kernel that uses buffer `cur` clears its
-// entries of buffer `other` (left by the previous launch of the same kind).
-struct LookBack {
-  uint32_t* cur;
-  uint32_t* other;
-  uint32_t* counter;
-  uint32_t* counter_other;
-};
-struct LookBack64 {
-  uint64_t* cur;
-  uint64_t* other;
-  uint32_t* counter;
-  uint32_t* counter_other;
-};
-
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t st);
 hipError_t launch_store_i64(int64_t* dst, const int64_t* src, hipStream_t st);
 
-// Order-preserving unsigned keys, one column per dimension (keys[d * n + i]).
-hipError_t launch_canon(const void* tuples, int64_t n, int k, int is_float, uint32_t* keys,
-                        hipStream_t st);
+// Row-major tuples as a source of canonical (order-preserving unsigned) keys.
+struct TupleSrc {
+  const uint32_t* t;
+  int k;
+  int is_float;
+};
 
-// Digit histograms of all four 8-bit digits of one 32-bit word.
-//   gather == 0: key = col[i];  gather == 1: key = col[ids[i]]
-// over i < (n_dev ? *n_dev : n).  hist must be zero beforehand (4*256 words).
-hipError_t launch_digit_hist(const uint32_t* col, const uint32_t* ids, int64_t n,
-                             const int64_t* n_dev, int gather, uint32_t* hist, hipStream_t st);
+// One payload plane of a radix pass.  Element i's value is in[i] (kind
+// kPlaneArray), i itself (kPlaneIndex) or the canonical key word `word` of
+// tuple row i (kPlaneTupleWord); it is written to out[dest].
+enum { kPlaneArray = 0, kPlaneIndex = 1, kPlaneTupleWord = 2 };
+struct Plane {
+  const uint32_t* in;
+  uint32_t* out;
+  int kind;
+  int word;
+};
+constexpr int kMaxPlanes = 8;
+struct Payload {
+  Plane p[kMaxPlanes];
+  int count;
+};
 
-// One stable onesweep scatter pass on 8-bit digit `shift`.
-//   mode 0: key = keys_in[i], val = vals_in[i]
-//   mode 1: key = col[vals_in[i]], val = vals_in[i]
-//   mode 2: key = col[i], val = i
-// keys_out may be null (keys not needed afterwards).
-hipError_t launch_onesweep(int mode, const uint32_t* keys_in, const uint32_t* vals_in,
-                           const uint32_t* col, uint32_t* keys_out, uint32_t* vals_out, int64_t n,
-                           const int64_t* n_dev, int shift, const uint32_t* hist_pass,
-                           const LookBack& lb, hipStream_t st);
+// One stable LSD radix pass on 8-bit digit `shift`: per-tile digit counts, a
+// two-level scan and the scatter (three launches, no waiting between
+// workgroups).  The key of element i is keys_in[i], or (keys_in == nullptr)
+// the canonical word `key_word` of tuple row i.  keys_out may be null.  Every
+// payload plane travels with its key.  Elements: i < (n_dev ? *n_dev : n).
+// cnt: radix_count_words(n) words; group_tot: radix_group_words(n) words.
+hipError_t launch_radix_pass(const uint32_t* keys_in, const TupleSrc& ts, int key_word,
+                             uint32_t* keys_out, const Payload& pay, int64_t n,
+                             const int64_t* n_dev, int shift, uint32_t* cnt, uint32_t* group_tot,
+                             hipStream_t st);
+inline int64_t radix_tiles(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
+inline int64_t radix_count_words(int64_t n) { return radix_tiles(n) * kRadix; }
+inline int64_t radix_group_words(int64_t n) { return (radix_tiles(n) + 63) / 64 * kRadix; }
 
-// Duplicate removal over the fully sorted order: ids[i] sorted, w0[i] its
-// first key word.  Writes the kept ids compacted to out_ids and their count
-// to *nu.
-hipError_t launch_dedup(const uint32_t* ids, const uint32_t* w0, const uint32_t* keys, int64_t n,
-                        int k, uint32_t* out_ids, int64_t* nu, const LookBack& lb, hipStream_t st);
+// Duplicate removal over the fully sorted order.  w0: sorted first key word;
+// planes: n-strided planes [id, w1, ..., w_{k-1}] in the same order.  Writes
+// the kept ids to out_ids, their words w1..w_{k-1} to out_words[(d-1) *
+// out_stride + o] and the count to *nu.  cnt: radix_tiles(n) words.
+hipError_t launch_dedup(const uint32_t* w0, const uint32_t* planes, int64_t n, int k,
+                        uint32_t* out_ids, uint32_t* out_words, int64_t out_stride, uint32_t* cnt,
+                        int64_t* nu, hipStream_t st);
 
-// rank[d][S[d][i]] = i for i < nu, every d.
-hipError_t launch_invert(const uint32_t* S, int64_t n, int k, const int64_t* nu, uint32_t* rank,
-                         hipStream_t st);
-
-// Level-0 rank records: rec[(j * k + q) * n + i] = rank of S[j][i] in order q.
-hipError_t launch_records(const uint32_t* S, const uint32_t* rank, int64_t n, int k,
-                          const int64_t* nu, uint32_t* rec, hipStream_t st);
+// Scatters the record planes the chain of sorts could not fill (see
+// presort.hip).  ids1: row ids in the order of array 1.
+hipError_t launch_complete_records(uint32_t* rec, const uint32_t* ids1, int64_t n, int k,
+                                   const int64_t* nu, hipStream_t st);
 
 // One global partition level (depth) of every array but the split one.
-hipError_t launch_level(const uint32_t* buf0, const uint32_t* buf1, int64_t n, int k, int depth,
-                        int64_t cutover, const int64_t* nu, const uint32_t* S, int32_t* perm,
-                        const LookBack64& lb, hipStream_t st);
+// rec0 holds the level-0 records (never overwritten); b1/b2 the moved ones.
+// Scratch: seginfo level_tiles(n) * level_seginfo_bytes() bytes, cnt
+// (k-1) * level_tiles(n) * 8 words, carry (k-1) * level_tiles(n) words.
+hipError_t launch_level(const uint32_t* rec0, uint32_t* b1, uint32_t* b2, int64_t n, int k,
+                        int depth, int64_t cutover, const int64_t* nu, int32_t* perm,
+                        void* seginfo, uint32_t* cnt, uint64_t* carry, hipStream_t st);
+size_t level_seginfo_bytes();
+inline int64_t level_tiles(int64_t n) { return (n + kLevelTile - 1) / kLevelTile; }
 
-// On-chip finish of every subarray at the cutover depth.
-hipError_t launch_leaf(const uint32_t* buf0, const uint32_t* buf1, int64_t n, int k,
-                       int64_t cutover, const int64_t* nu, const uint32_t* S, int32_t* perm,
-                       int grid_bound_depth, hipStream_t st);
+// LDS bytes the on-chip finish needs for a cutover C in k dimensions.
+inline size_t leaf_lds_bytes(int64_t cutover, int k) {
+  return (size_t)cutover * (4 + 4 + 2 + 2 + 2 * 2 * k);
+}
+
+// On-chip finish of every subarray at the cutover depth (row ids come from
+// array 0's records).
+hipError_t launch_leaf(const uint32_t* rec0, uint32_t* b1, uint32_t* b2, int64_t n, int k,
+                       int64_t cutover, const int64_t* nu, int32_t* perm, int grid_bound_depth,
+                       hipStream_t st);
 
 // k == 1: the in-order layout is the sorted unique order.
 hipError_t launch_copy_k1(const uint32_t* S0, const int64_t* nu, int64_t n, int32_t* perm,

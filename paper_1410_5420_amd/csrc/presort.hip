@@ -2,13 +2,18 @@
 // sorted by the cyclic super keys, and duplicate removal.
 //
 // The paper merge-sorts each index array by its super key.  Here every sort is
-// a stable LSD radix sort over 32-bit key words (8-bit digits, onesweep passes
-// with decoupled look-back).  The first array, sorted by x:y:z:..., is built
+// a stable LSD radix sort over 32-bit key words (8-bit digits; each pass is a
+// per-tile count, a scan and a scatter).  The first array, sorted by x:y:z:..., is built
 // word by word from the least significant word.  Duplicate rows are then
 // adjacent, and one pass keeps the first of each run (Sec. 2.1).  The other
 // arrays follow by a chain: the array for super key d is the stable sort of
 // the array for super key d+1 (mod k) by word d alone, because ties on word d
 // are then already in the order d+1 : d+2 : ... requires.
+//
+// No pass reads anything out of order: every value a pass needs (the row id,
+// the key words of later passes, the ranks known so far) travels with the key
+// as a payload plane and is staged through LDS, so all global traffic is in
+// coalesced runs.
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -44,133 +49,137 @@ hipError_t launch_store_i64(int64_t* dst, const int64_t* src, hipStream_t st) {
 // float32: IEEE totalOrder becomes unsigned order when negative encodings are
 // complemented and non-negative ones get the sign bit set.
 
-__global__ __launch_bounds__(256) void k_canon(const uint32_t* __restrict__ t, int64_t n, int k,
-                                              int is_float, uint32_t* __restrict__ keys) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    for (int d = 0; d < k; ++d) {
-      uint32_t b = t[i * k + d];
-      uint32_t c = is_float ? (b ^ ((b >> 31) ? 0xFFFFFFFFu : 0x80000000u)) : (b ^ 0x80000000u);
-      keys[(int64_t)d * n + i] = c;
+__device__ __forceinline__ uint32_t canon_word(uint32_t b, bool is_float) {
+  return is_float ? (b ^ ((b >> 31) ? 0xFFFFFFFFu : 0x80000000u)) : (b ^ 0x80000000u);
+}
+
+// ---- radix passes: per-tile counts, a two-level scan, then the scatter ----------
+// Every pass is three launches with no waiting between workgroups:
+//   1. count:   tile t (kSortTile elements, fixed by blockIdx) counts its 256
+//               digits into cnt[t][d];
+//   2. scan:    blocks of 16 tiles turn those into exclusive prefixes per digit
+//               (plus per-block totals), one block then scans the block
+//               totals and adds each digit's global start;
+//   3. scatter: tile t ranks its elements stably (wave ballots), adds the
+//               offsets, stages keys and payload planes through LDS in output
+//               order and writes them out in runs.
+
+constexpr int kOsThreads = 512;
+constexpr int kOsItems = kSortTile / kOsThreads;  // 8
+constexpr int kOsWaves = kOsThreads / kWave;
+constexpr int kScanGroup = 64;                      // tiles per first-level scan block
+
+// Positions fit in 31 bits (n <= 2^30 - 1); only tuple rows are addressed in
+// 64-bit, since row * k can exceed that.
+__device__ __forceinline__ uint32_t plane_value(const Plane& pl, const TupleSrc& ts, int i) {
+  if (pl.kind == kPlaneArray) return pl.in[i];
+  if (pl.kind == kPlaneIndex) return (uint32_t)i;
+  return canon_word(ts.t[(int64_t)i * ts.k + pl.word], ts.is_float);
+}
+
+template <bool kFromTuples>
+__global__ __launch_bounds__(kOsThreads) void k_radix_count(const uint32_t* __restrict__ keys_in,
+                                                           const TupleSrc ts, int key_word,
+                                                           int64_t n_host, const int64_t* n_dev,
+                                                           int shift, uint32_t* __restrict__ cnt) {
+  __shared__ uint32_t s_h[kRadix];
+  const int tid = threadIdx.x;
+  if (tid < kRadix) s_h[tid] = 0;
+  __syncthreads();
+  const int n = (int)(n_dev ? *n_dev : n_host);
+  const int base = blockIdx.x * kSortTile;
+#pragma unroll
+  for (int j = 0; j < kOsItems; ++j) {
+    const int i = base + j * kOsThreads + tid;
+    if (i < n) {
+      const uint32_t key =
+          kFromTuples ? canon_word(ts.t[(int64_t)i * ts.k + key_word], ts.is_float) : keys_in[i];
+      atomicAdd(&s_h[(key >> shift) & 0xFF], 1u);
     }
   }
-}
-
-hipError_t launch_canon(const void* tuples, int64_t n, int k, int is_float, uint32_t* keys,
-                        hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_canon, dim3((unsigned)blocks), dim3(256), 0, st,
-                     static_cast<const uint32_t*>(tuples), n, k, is_float, keys);
-  return hipGetLastError();
-}
-
-// ---- digit histograms ---------------------------------------------------------
-
-template <bool kGather>
-__global__ __launch_bounds__(256) void k_digit_hist(const uint32_t* __restrict__ col,
-                                                   const uint32_t* __restrict__ ids, int64_t n_host,
-                                                   const int64_t* n_dev, uint32_t* hist) {
-  __shared__ uint32_t s[4 * kRadix];
-  for (int i = threadIdx.x; i < 4 * kRadix; i += blockDim.x) s[i] = 0;
   __syncthreads();
-  const int64_t n = n_dev ? *n_dev : n_host;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    uint32_t key = kGather ? col[ids[i]] : col[i];
-    atomicAdd(&s[0 * kRadix + (key & 0xFF)], 1u);
-    atomicAdd(&s[1 * kRadix + ((key >> 8) & 0xFF)], 1u);
-    atomicAdd(&s[2 * kRadix + ((key >> 16) & 0xFF)], 1u);
-    atomicAdd(&s[3 * kRadix + (key >> 24)], 1u);
+  if (tid < kRadix) cnt[(int64_t)blockIdx.x * kRadix + tid] = s_h[tid];
+}
+
+// First level: exclusive prefix over the tiles of one group, per digit.
+__global__ __launch_bounds__(kRadix) void k_radix_scan_tiles(uint32_t* __restrict__ cnt,
+                                                            uint32_t* __restrict__ group_tot,
+                                                            int tiles) {
+  const int d = threadIdx.x;
+  const int t0 = blockIdx.x * kScanGroup;
+  const int t1 = min(t0 + kScanGroup, tiles);
+  uint32_t run = 0;
+  for (int t = t0; t < t1; t += 8) {
+    uint32_t c[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) c[q] = (t + q < t1) ? cnt[(int64_t)(t + q) * kRadix + d] : 0u;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (t + q < t1) cnt[(int64_t)(t + q) * kRadix + d] = run;
+      run += c[q];
+    }
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < 4 * kRadix; i += blockDim.x)
-    if (s[i]) atomicAdd(&hist[i], s[i]);
+  group_tot[(int64_t)blockIdx.x * kRadix + d] = run;
 }
 
-hipError_t launch_digit_hist(const uint32_t* col, const uint32_t* ids, int64_t n,
-                             const int64_t* n_dev, int gather, uint32_t* hist, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  int64_t blocks = (n + 4095) / 4096;
-  if (blocks > 2048) blocks = 2048;
-  if (gather)
-    hipLaunchKernelGGL(k_digit_hist<true>, dim3((unsigned)blocks), dim3(256), 0, st, col, ids, n,
-                       n_dev, hist);
-  else
-    hipLaunchKernelGGL(k_digit_hist<false>, dim3((unsigned)blocks), dim3(256), 0, st, col, ids, n,
-                       n_dev, hist);
-  return hipGetLastError();
+// Second level: one block turns group totals into group starts that already
+// include every digit's global start.
+__global__ __launch_bounds__(kRadix) void k_radix_scan_groups(uint32_t* __restrict__ group_tot,
+                                                             int groups) {
+  __shared__ uint32_t s_tmp[kRadix / kWave + 1];
+  const int d = threadIdx.x;
+  uint32_t total = 0;
+  for (int g = 0; g < groups; ++g) total += group_tot[(int64_t)g * kRadix + d];
+  uint32_t all;
+  uint32_t run = block_exclusive_sum<kRadix>(total, s_tmp, &all);
+  for (int g = 0; g < groups; ++g) {
+    const uint32_t c = group_tot[(int64_t)g * kRadix + d];
+    group_tot[(int64_t)g * kRadix + d] = run;
+    run += c;
+  }
 }
 
-// ---- onesweep scatter pass ------------------------------------------------------
-// One workgroup = one tile of kSortTile elements, claimed in order from an
-// atomic counter so that a tile only ever waits on tiles that started before
-// it.  Ranking inside a wave is stable: items are taken in element order and
-// lanes with equal digits are found with 8 ballots.  Each tile publishes its
-// 256 digit counts, looks back for the counts of all earlier tiles, stages its
-// elements in LDS in output order and writes them out in runs.
-
-constexpr int kOsThreads = 256;
-constexpr int kOsItems = kSortTile / kOsThreads;  // 16
-constexpr int kOsWaves = kOsThreads / kWave;
-
-template <int kMode, bool kWriteKeys>
-__global__ __launch_bounds__(kOsThreads) void k_onesweep(
-    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
-    const uint32_t* __restrict__ col, uint32_t* __restrict__ keys_out,
-    uint32_t* __restrict__ vals_out, int64_t n_host, const int64_t* n_dev, int shift,
-    const uint32_t* __restrict__ hist, uint32_t* lb, uint32_t* lb_other, uint32_t* counter,
-    uint32_t* counter_other) {
+template <bool kFromTuples, bool kWriteKeys>
+__global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
+    const uint32_t* __restrict__ keys_in, const TupleSrc ts, int key_word,
+    uint32_t* __restrict__ keys_out, const Payload pay, int64_t n_host, const int64_t* n_dev,
+    int shift, const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ group_start) {
   __shared__ uint32_t s_keys[kSortTile];
-  __shared__ uint32_t s_vals[kSortTile];
+  __shared__ uint32_t s_stage[kSortTile];
   __shared__ uint32_t s_wcnt[kOsWaves][kRadix];
   __shared__ uint32_t s_tile_excl[kRadix];
   __shared__ uint32_t s_gbase[kRadix];
   __shared__ uint32_t s_tmp[kOsWaves + 1];
-  __shared__ uint32_t s_tile;
 
   const int tid = threadIdx.x;
   const int w = tid / kWave;
   const int lane = tid % kWave;
-  if (tid == 0) s_tile = next_tile(counter);
-#pragma unroll
-  for (int q = 0; q < kOsWaves; ++q) s_wcnt[q][tid] = 0;
-  __syncthreads();
-  const uint32_t tile = s_tile;
-  lb_other[(int64_t)tile * kRadix + tid] = 0;
-  if (tile == 0 && tid == 0) *counter_other = 0;
-
-  const int64_t n = n_dev ? *n_dev : n_host;
-  const int64_t base = (int64_t)tile * kSortTile;
+  const int n = (int)(n_dev ? *n_dev : n_host);
+  const int tile = blockIdx.x;
+  const int base = tile * kSortTile;
   if (base >= n) return;
+  for (int q = tid; q < kOsWaves * kRadix; q += kOsThreads) (&s_wcnt[0][0])[q] = 0;
+  // global start of this tile's run of digit tid
+  if (tid < kRadix)
+    s_gbase[tid] = cnt[(int64_t)tile * kRadix + tid] +
+                   group_start[(int64_t)(tile / kScanGroup) * kRadix + tid];
 
-  uint32_t key[kOsItems], val[kOsItems], rank[kOsItems];
-  const int64_t wbase = base + (int64_t)w * (kWave * kOsItems) + lane;
+  uint32_t key[kOsItems], rank[kOsItems];
+  const int wbase = base + w * (kWave * kOsItems) + lane;
 #pragma unroll
   for (int j = 0; j < kOsItems; ++j) {
-    const int64_t i = wbase + j * kWave;
-    if (i < n) {
-      if (kMode == 0) {
-        key[j] = keys_in[i];
-        val[j] = vals_in[i];
-      } else if (kMode == 1) {
-        val[j] = vals_in[i];
-        key[j] = col[val[j]];
-      } else {
-        val[j] = (uint32_t)i;
-        key[j] = col[i];
-      }
-    } else {
-      key[j] = 0;
-      val[j] = 0xFFFFFFFFu;  // marks an empty slot
-    }
+    const int i = wbase + j * kWave;
+    key[j] = 0;
+    if (i < n)
+      key[j] = kFromTuples ? canon_word(ts.t[(int64_t)i * ts.k + key_word], ts.is_float)
+                           : keys_in[i];
   }
+  __syncthreads();
 
   const uint64_t below = lanes_below_mask();
 #pragma unroll
   for (int j = 0; j < kOsItems; ++j) {
-    const int64_t i = wbase + j * kWave;
+    const int i = wbase + j * kWave;
     const bool valid = i < n;
     const uint32_t d = (key[j] >> shift) & 0xFF;
     uint64_t m = __ballot(valid);
@@ -190,199 +199,231 @@ __global__ __launch_bounds__(kOsThreads) void k_onesweep(
   }
   __syncthreads();
 
-  // thread tid owns digit tid: wave bases and the tile count
+  // threads below 256 own one digit each: wave bases and the tile count
   uint32_t tile_cnt = 0;
+  if (tid < kRadix) {
 #pragma unroll
-  for (int q = 0; q < kOsWaves; ++q) {
-    const uint32_t c = s_wcnt[q][tid];
-    s_wcnt[q][tid] = tile_cnt;
-    tile_cnt += c;
-  }
-
-  // decoupled look-back on digit tid
-  uint32_t* mine = lb + (int64_t)tile * kRadix + tid;
-  uint32_t excl = 0;
-  if (tile == 0) {
-    st_flag(mine, kLbInc | tile_cnt);
-  } else {
-    st_flag(mine, kLbAgg | tile_cnt);
-    int64_t t = (int64_t)tile - 1;
-    uint32_t spins = 0;
-    while (t >= 0) {
-      const uint32_t v = ld_flag(lb + t * kRadix + tid);
-      const uint32_t status = v >> 30;
-      if (status == 0) {
-        if (++spins > kSpinLimit) break;
-        __builtin_amdgcn_s_sleep(1);
-        continue;
-      }
-      excl += v & kLbMask;
-      if (status == 2) break;
-      --t;
+    for (int q = 0; q < kOsWaves; ++q) {
+      const uint32_t c = s_wcnt[q][tid];
+      s_wcnt[q][tid] = tile_cnt;
+      tile_cnt += c;
     }
-    st_flag(mine, kLbInc | (excl + tile_cnt));
   }
-
   uint32_t total;
-  const uint32_t hexcl = block_exclusive_sum<kOsThreads>(hist[tid], s_tmp, &total);
-  s_gbase[tid] = hexcl + excl;
   const uint32_t texcl = block_exclusive_sum<kOsThreads>(tile_cnt, s_tmp, &total);
-  s_tile_excl[tid] = texcl;
+  if (tid < kRadix) s_tile_excl[tid] = texcl;
   __syncthreads();
 
+  // local (tile-sorted) slot of every item
 #pragma unroll
   for (int j = 0; j < kOsItems; ++j) {
-    const int64_t i = wbase + j * kWave;
+    const int i = wbase + j * kWave;
     if (i < n) {
       const uint32_t d = (key[j] >> shift) & 0xFF;
-      const uint32_t lpos = s_tile_excl[d] + s_wcnt[w][d] + rank[j];
-      s_keys[lpos] = key[j];
-      s_vals[lpos] = val[j];
+      rank[j] = s_tile_excl[d] + s_wcnt[w][d] + rank[j];
+      s_keys[rank[j]] = key[j];
     }
   }
   __syncthreads();
 
-  const int tile_n = (int)((n - base) < kSortTile ? (n - base) : kSortTile);
-  for (int i = tid; i < tile_n; i += kOsThreads) {
-    const uint32_t kk = s_keys[i];
-    const uint32_t d = (kk >> shift) & 0xFF;
-    const int64_t g = (int64_t)s_gbase[d] + (i - (int64_t)s_tile_excl[d]);
-    if (g < 0 || g >= n) continue;  // only reachable if the counts were inconsistent
-    if (kWriteKeys) keys_out[g] = kk;
-    vals_out[g] = s_vals[i];
+  // global destination of every tile-sorted slot this thread writes out
+  const int tile_n = min(n - base, kSortTile);
+  int dest[kOsItems];
+#pragma unroll
+  for (int j = 0; j < kOsItems; ++j) {
+    const int i = tid + j * kOsThreads;
+    dest[j] = -1;
+    if (i < tile_n) {
+      const uint32_t kk = s_keys[i];
+      const uint32_t d = (kk >> shift) & 0xFF;
+      const int g = (int)s_gbase[d] + (i - (int)s_tile_excl[d]);
+      if (g >= 0 && g < n) dest[j] = g;  // out of range only if the counts were inconsistent
+      if (kWriteKeys && dest[j] >= 0) keys_out[g] = kk;
+    }
+  }
+
+  // payload planes: the next plane's values are loaded before the current
+  // one is written out
+  uint32_t nxt[kOsItems];
+  if (pay.count > 0) {
+#pragma unroll
+    for (int j = 0; j < kOsItems; ++j) {
+      const int i = wbase + j * kWave;
+      nxt[j] = i < n ? plane_value(pay.p[0], ts, i) : 0u;
+    }
+  }
+  for (int q = 0; q < pay.count; ++q) {
+#pragma unroll
+    for (int j = 0; j < kOsItems; ++j) {
+      const int i = wbase + j * kWave;
+      if (i < n) s_stage[rank[j]] = nxt[j];
+    }
+    if (q + 1 < pay.count) {
+      const Plane pn = pay.p[q + 1];
+#pragma unroll
+      for (int j = 0; j < kOsItems; ++j) {
+        const int i = wbase + j * kWave;
+        nxt[j] = i < n ? plane_value(pn, ts, i) : 0u;
+      }
+    }
+    __syncthreads();
+    uint32_t* out = pay.p[q].out;
+#pragma unroll
+    for (int j = 0; j < kOsItems; ++j) {
+      if (dest[j] >= 0) out[dest[j]] = s_stage[tid + j * kOsThreads];
+    }
+    __syncthreads();
   }
 }
 
-hipError_t launch_onesweep(int mode, const uint32_t* keys_in, const uint32_t* vals_in,
-                           const uint32_t* col, uint32_t* keys_out, uint32_t* vals_out, int64_t n,
-                           const int64_t* n_dev, int shift, const uint32_t* hist_pass,
-                           const LookBack& lb, hipStream_t st) {
+hipError_t launch_radix_pass(const uint32_t* keys_in, const TupleSrc& ts, int key_word,
+                             uint32_t* keys_out, const Payload& pay, int64_t n,
+                             const int64_t* n_dev, int shift, uint32_t* cnt, uint32_t* group_tot,
+                             hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  const unsigned tiles = (unsigned)((n + kSortTile - 1) / kSortTile);
-#define KD_OS(MODE, WK)                                                                       \
-  hipLaunchKernelGGL((k_onesweep<MODE, WK>), dim3(tiles), dim3(kOsThreads), 0, st, keys_in,   \
-                     vals_in, col, keys_out, vals_out, n, n_dev, shift, hist_pass, lb.cur,    \
-                     lb.other, lb.counter, lb.counter_other)
+  const int tiles = (int)((n + kSortTile - 1) / kSortTile);
+  const int groups = (tiles + kScanGroup - 1) / kScanGroup;
+  const bool ft = keys_in == nullptr;
+  if (ft)
+    hipLaunchKernelGGL(k_radix_count<true>, dim3(tiles), dim3(kOsThreads), 0, st, keys_in, ts,
+                       key_word, n, n_dev, shift, cnt);
+  else
+    hipLaunchKernelGGL(k_radix_count<false>, dim3(tiles), dim3(kOsThreads), 0, st, keys_in, ts,
+                       key_word, n, n_dev, shift, cnt);
+  hipLaunchKernelGGL(k_radix_scan_tiles, dim3(groups), dim3(kRadix), 0, st, cnt, group_tot, tiles);
+  hipLaunchKernelGGL(k_radix_scan_groups, dim3(1), dim3(kRadix), 0, st, group_tot, groups);
+#define KD_RS(FT, WK)                                                                           \
+  hipLaunchKernelGGL((k_radix_scatter<FT, WK>), dim3(tiles), dim3(kOsThreads), 0, st, keys_in, \
+                     ts, key_word, keys_out, pay, n, n_dev, shift, cnt, group_tot)
   const bool wk = keys_out != nullptr;
-  if (mode == 0) {
-    if (wk) KD_OS(0, true); else KD_OS(0, false);
-  } else if (mode == 1) {
-    if (wk) KD_OS(1, true); else KD_OS(1, false);
+  if (ft) {
+    if (wk) KD_RS(true, true); else KD_RS(true, false);
   } else {
-    if (wk) KD_OS(2, true); else KD_OS(2, false);
+    if (wk) KD_RS(false, true); else KD_RS(false, false);
   }
-#undef KD_OS
+#undef KD_RS
   return hipGetLastError();
 }
 
 // ---- duplicate removal --------------------------------------------------------
 // Sec. 2.1: after the sort by x:y:z:..., identical rows are contiguous; keep
-// the first of each run (the smallest row, the sort being stable).  The first
-// key word arrives sorted alongside, so the other words are fetched only when
-// it ties with the predecessor.  Kept ids are compacted with a single-word
-// decoupled look-back per tile.
+// the first of each run (the smallest row, the sort being stable).  The sorted
+// key words arrive as coalesced planes: w0 (the last sort key) and the
+// payload planes [id, w1, ..., w_{k-1}].  Three launches: per-tile counts of
+// kept rows, one scan block (which also writes the number of distinct rows),
+// then the compaction, which writes the kept ids and, for the chain of sorts,
+// their words w1..w_{k-1}.
 
-constexpr int kDdThreads = 256;
+constexpr int kDdThreads = 512;
 constexpr int kDdItems = kSortTile / kDdThreads;
+constexpr int kDdWaves = kDdThreads / kWave;
 
-__global__ __launch_bounds__(kDdThreads) void k_dedup(const uint32_t* __restrict__ ids,
-                                                     const uint32_t* __restrict__ w0,
-                                                     const uint32_t* __restrict__ keys, int64_t n,
-                                                     int k, uint32_t* __restrict__ out_ids,
-                                                     int64_t* nu, uint32_t* lb, uint32_t* lb_other,
-                                                     uint32_t* counter, uint32_t* counter_other) {
-  __shared__ uint32_t s_chunk[kDdItems * (kDdThreads / kWave)];
-  __shared__ uint32_t s_tile;
-  __shared__ uint32_t s_base;
-  const int tid = threadIdx.x;
-  const int w = tid / kWave;
-  if (tid == 0) s_tile = next_tile(counter);
-  __syncthreads();
-  const uint32_t tile = s_tile;
-  if (tid == 0) {
-    lb_other[tile] = 0;
-    if (tile == 0) *counter_other = 0;
+__device__ __forceinline__ bool keep_row(const uint32_t* __restrict__ w0,
+                                         const uint32_t* __restrict__ planes, int64_t n, int k,
+                                         int64_t i) {
+  if (i == 0) return true;
+  if (w0[i] != w0[i - 1]) return true;
+  for (int d = 1; d < k; ++d) {
+    const uint32_t* wd = planes + (int64_t)d * n;
+    if (wd[i] != wd[i - 1]) return true;
   }
-  const int64_t base = (int64_t)tile * kSortTile;
-  if (base >= n) return;
+  return false;
+}
 
-  uint32_t keep[kDdItems], id[kDdItems], within[kDdItems];
+__global__ __launch_bounds__(kDdThreads) void k_dedup_count(const uint32_t* __restrict__ w0,
+                                                           const uint32_t* __restrict__ planes,
+                                                           int64_t n, int k,
+                                                           uint32_t* __restrict__ cnt) {
+  __shared__ uint32_t s_part[kDdWaves];
+  const int tid = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  uint32_t c = 0;
 #pragma unroll
   for (int j = 0; j < kDdItems; ++j) {
     const int64_t i = base + j * kDdThreads + tid;
-    keep[j] = 0;
-    if (i < n) {
-      id[j] = ids[i];
-      keep[j] = 1;
-      if (i > 0) {
-        const uint32_t a = w0[i], b = w0[i - 1];
-        if (a == b) {
-          const uint32_t prev = ids[i - 1];
-          bool same = true;
-          for (int d = 1; d < k; ++d) {
-            if (keys[(int64_t)d * n + id[j]] != keys[(int64_t)d * n + prev]) {
-              same = false;
-              break;
-            }
-          }
-          keep[j] = same ? 0 : 1;
-        }
-      }
-    }
-    const uint32_t inc = wave_inclusive_sum(keep[j]);
-    within[j] = inc - keep[j];
-    if (lane_id() == kWave - 1) s_chunk[j * (kDdThreads / kWave) + w] = inc;
+    if (i < n && keep_row(w0, planes, n, k, i)) ++c;
   }
+  c = wave_inclusive_sum(c);
+  if (lane_id() == kWave - 1) s_part[tid / kWave] = c;
   __syncthreads();
-  // chunks are in element order (item-major, then wave): scan them in one wave
-  constexpr int kChunks = kDdItems * (kDdThreads / kWave);
-  static_assert(kChunks == kWave, "one wave scans the chunk totals");
-  if (w == 0) {
-    const uint32_t c = s_chunk[tid];
-    const uint32_t inc = wave_inclusive_sum(c);
-    s_chunk[tid] = inc - c;
-    if (tid == kWave - 1) {
-      const uint32_t tile_total = inc;
-      uint32_t excl = 0;
-      if (tile == 0) {
-        st_flag(lb + tile, kLbInc | tile_total);
-      } else {
-        st_flag(lb + tile, kLbAgg | tile_total);
-        int64_t t = (int64_t)tile - 1;
-        uint32_t spins = 0;
-        while (t >= 0) {
-          const uint32_t v = ld_flag(lb + t);
-          const uint32_t status = v >> 30;
-          if (status == 0) {
-            if (++spins > kSpinLimit) break;
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-          }
-          excl += v & kLbMask;
-          if (status == 2) break;
-          --t;
-        }
-        st_flag(lb + tile, kLbInc | (excl + tile_total));
-      }
-      s_base = excl;
-      if (base + kSortTile >= n) *nu = (int64_t)(excl + tile_total);
-    }
-  }
-  __syncthreads();
-  const uint32_t gb = s_base;
-#pragma unroll
-  for (int j = 0; j < kDdItems; ++j) {
-    const int64_t o = (int64_t)gb + s_chunk[j * (kDdThreads / kWave) + w] + within[j];
-    if (keep[j] && o < n) out_ids[o] = id[j];
+  if (tid == 0) {
+    uint32_t t = 0;
+    for (int q = 0; q < kDdWaves; ++q) t += s_part[q];
+    cnt[blockIdx.x] = t;
   }
 }
 
-hipError_t launch_dedup(const uint32_t* ids, const uint32_t* w0, const uint32_t* keys, int64_t n,
-                        int k, uint32_t* out_ids, int64_t* nu, const LookBack& lb, hipStream_t st) {
+// One block: exclusive scan of the per-tile counts; writes the total to *nu.
+__global__ __launch_bounds__(1024) void k_scan_counts(uint32_t* __restrict__ cnt, int tiles,
+                                                     int64_t* nu) {
+  __shared__ uint32_t s_tmp[1024 / kWave + 1];
+  __shared__ uint32_t s_carry;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_carry = 0;
+  __syncthreads();
+  for (int t0 = 0; t0 < tiles; t0 += 1024) {
+    const int t = t0 + tid;
+    const uint32_t c = t < tiles ? cnt[t] : 0u;
+    uint32_t all;
+    const uint32_t ex = block_exclusive_sum<1024>(c, s_tmp, &all);
+    const uint32_t carry = s_carry;
+    if (t < tiles) cnt[t] = carry + ex;
+    __syncthreads();
+    if (tid == 0) s_carry = carry + all;
+    __syncthreads();
+  }
+  if (tid == 0) *nu = (int64_t)s_carry;
+}
+
+__global__ __launch_bounds__(kDdThreads) void k_dedup_write(const uint32_t* __restrict__ w0,
+                                                           const uint32_t* __restrict__ planes,
+                                                           int64_t n, int k,
+                                                           const uint32_t* __restrict__ cnt,
+                                                           uint32_t* __restrict__ out_ids,
+                                                           uint32_t* __restrict__ out_words,
+                                                           int64_t out_stride) {
+  __shared__ uint32_t s_chunk[kDdItems * kDdWaves];
+  const int tid = threadIdx.x;
+  const int wv = tid / kWave;
+  const int lane = tid % kWave;
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  if (base >= n) return;
+  uint32_t keep[kDdItems], within[kDdItems];
+#pragma unroll
+  for (int j = 0; j < kDdItems; ++j) {
+    const int64_t i = base + j * kDdThreads + tid;
+    keep[j] = (i < n && keep_row(w0, planes, n, k, i)) ? 1u : 0u;
+    const uint32_t inc = wave_inclusive_sum(keep[j]);
+    within[j] = inc - keep[j];
+    if (lane == kWave - 1) s_chunk[j * kDdWaves + wv] = inc;
+  }
+  __syncthreads();
+  static_assert(kDdItems * kDdWaves == kWave, "one wave scans the chunk totals");
+  if (wv == 0) {
+    const uint32_t c = s_chunk[lane];
+    s_chunk[lane] = wave_inclusive_sum(c) - c;
+  }
+  __syncthreads();
+  const uint32_t gb = cnt[blockIdx.x];
+#pragma unroll
+  for (int j = 0; j < kDdItems; ++j) {
+    const int64_t i = base + j * kDdThreads + tid;
+    const int64_t o = (int64_t)gb + s_chunk[j * kDdWaves + wv] + within[j];
+    if (!keep[j] || o >= n) continue;
+    out_ids[o] = planes[i];
+    for (int d = 1; d < k; ++d) out_words[(d - 1) * out_stride + o] = planes[(int64_t)d * n + i];
+  }
+}
+
+hipError_t launch_dedup(const uint32_t* w0, const uint32_t* planes, int64_t n, int k,
+                        uint32_t* out_ids, uint32_t* out_words, int64_t out_stride, uint32_t* cnt,
+                        int64_t* nu, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  const unsigned tiles = (unsigned)((n + kSortTile - 1) / kSortTile);
-  hipLaunchKernelGGL(k_dedup, dim3(tiles), dim3(kDdThreads), 0, st, ids, w0, keys, n, k, out_ids,
-                     nu, lb.cur, lb.other, lb.counter, lb.counter_other);
+  const int tiles = (int)((n + kSortTile - 1) / kSortTile);
+  hipLaunchKernelGGL(k_dedup_count, dim3(tiles), dim3(kDdThreads), 0, st, w0, planes, n, k, cnt);
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, cnt, tiles, nu);
+  hipLaunchKernelGGL(k_dedup_write, dim3(tiles), dim3(kDdThreads), 0, st, w0, planes, n, k, cnt,
+                     out_ids, out_words, out_stride);
   return hipGetLastError();
 }
 
@@ -390,48 +431,44 @@ hipError_t launch_dedup(const uint32_t* ids, const uint32_t* w0, const uint32_t*
 // The tree phase compares ranks instead of tuples: the rank of a row in order
 // q is its position in the deduplicated array sorted by super key q, and
 // comparing two rows' super keys q is the same as comparing those ranks.
+//
+// Array j's record holds the k-1 ranks of the other orders, plane c being the
+// rank in order (j + 1 + c) mod k; array 0's records carry the row id as one
+// more plane.  Planes are stored as separate columns (plane c of array j at
+// record_offset(j) + c * n).  The chain of sorts fills most planes: the sort producing array
+// d carries the ranks already known (its input position is the rank in order
+// d+1).  Array 1 comes out complete; this kernel reads it and scatters the
+// planes still missing: all of array 0's and, for d >= 2, the ranks in orders
+// 1 .. d-1 of array d.
 
-__global__ __launch_bounds__(256) void k_invert(const uint32_t* __restrict__ S, int64_t n, int k,
-                                               const int64_t* nu_ptr, uint32_t* __restrict__ rank) {
+__global__ __launch_bounds__(256) void k_complete_records(uint32_t* __restrict__ rec,
+                                                         const uint32_t* __restrict__ ids1,
+                                                         int64_t n, int k, const int64_t* nu_ptr) {
   const int64_t nu = *nu_ptr;
-  const int d = blockIdx.y;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nu;
-       i += (int64_t)gridDim.x * blockDim.x)
-    rank[(int64_t)d * n + S[(int64_t)d * n + i]] = (uint32_t)i;
-}
-
-hipError_t launch_invert(const uint32_t* S, int64_t n, int k, const int64_t* nu, uint32_t* rank,
-                         hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_invert, dim3((unsigned)blocks, (unsigned)k), dim3(256), 0, st, S, n, k, nu,
-                     rank);
-  return hipGetLastError();
-}
-
-__global__ __launch_bounds__(256) void k_records(const uint32_t* __restrict__ S,
-                                                const uint32_t* __restrict__ rank, int64_t n, int k,
-                                                const int64_t* nu_ptr, uint32_t* __restrict__ rec) {
-  const int64_t nu = *nu_ptr;
-  const int j = blockIdx.y;
+  const int R = k - 1;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nu;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t id = S[(int64_t)j * n + i];
-    for (int q = 0; q < k; ++q) {
-      const uint32_t r = (q == j) ? (uint32_t)i : rank[(int64_t)q * n + id];
-      rec[((int64_t)j * k + q) * n + i] = r;
+    uint32_t rv[kMaxK];
+    rv[1 % k] = (uint32_t)i;
+    const uint32_t* a1 = rec + record_offset(1, k, n);
+    for (int c = 0; c < R; ++c) rv[(2 + c) % k] = a1[c * n + i];
+    uint32_t* a0 = rec + record_offset(0, k, n);
+    for (int c = 0; c < R; ++c) a0[c * n + rv[0]] = rv[(1 + c) % k];
+    a0[R * n + rv[0]] = ids1[i];
+    for (int j = 2; j < k; ++j) {
+      uint32_t* aj = rec + record_offset(j, k, n);
+      for (int c = k - j; c <= k - 2; ++c) aj[c * n + rv[j]] = rv[(j + 1 + c) % k];
     }
   }
 }
 
-hipError_t launch_records(const uint32_t* S, const uint32_t* rank, int64_t n, int k,
-                          const int64_t* nu, uint32_t* rec, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
+hipError_t launch_complete_records(uint32_t* rec, const uint32_t* ids1, int64_t n, int k,
+                                   const int64_t* nu, hipStream_t st) {
+  if (n <= 0 || k < 2) return hipSuccess;
   int64_t blocks = (n + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_records, dim3((unsigned)blocks, (unsigned)k), dim3(256), 0, st, S, rank, n,
-                     k, nu, rec);
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_complete_records, dim3((unsigned)blocks), dim3(256), 0, st, rec, ids1, n, k,
+                     nu);
   return hipGetLastError();
 }
 
