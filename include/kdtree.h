@@ -47,6 +47,7 @@ extern "C" {
 
 #define KD_MAX_N (((int64_t)1 << 30) - 1) /* rows per build (and per batch) */
 #define KD_MAX_K 8
+#define KD_MAX_TREES (1 << 20) /* trees per batched build */
 
 enum kd_dtype { KD_I32 = 0, KD_F32 = 1 };
 
@@ -95,6 +96,29 @@ int kdtree_presort(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, in
 int kdtree_partition(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, int32_t* d_perm,
                      int32_t* d_lo, int32_t* d_hi, int64_t* d_n_unique, void* d_workspace,
                      size_t workspace_bytes, const kd_options* opts, void* stream);
+
+/* Batched build: num_trees independent trees in one sequence of launches
+ * (the rows of tree b are rows offsets[b] .. offsets[b+1]-1 of d_tuples, and
+ * each tree is exactly the tree kdtree_build would produce from those rows
+ * alone).  The on-chip finish, where every tree of at most the cutover size is
+ * built entirely, is one persistent launch whose workgroups take (tree,
+ * subarray) items from a work counter.
+ *   d_offsets   int64[num_trees + 1] device, non-decreasing, offsets[0] = 0
+ *   h_offsets   the same values in host memory (used to size launches)
+ *   d_perm      int32[offsets[B]]: tree b's in-order layout in positions
+ *               offsets[b] .. offsets[b] + n_unique[b] - 1, as row indices
+ *               local to the tree (0 .. n_b - 1); later positions untouched
+ *   d_n_unique  int64[num_trees]
+ *   d_workspace >= kdtree_workspace_bytes_batched(offsets[B], B, k, dtype)
+ * Limits: 1 <= num_trees <= KD_MAX_TREES, offsets[B] <= KD_MAX_N.  Returns
+ * KD_EINVAL for decreasing or non-zero-based offsets.  The tuples of all trees
+ * must share k and dtype. */
+int kdtree_workspace_bytes_batched(int64_t total_rows, int32_t num_trees, int32_t k, int32_t dtype,
+                                   size_t* h_bytes);
+int kdtree_build_batched(const void* d_tuples, const int64_t* d_offsets, const int64_t* h_offsets,
+                         int32_t num_trees, int32_t k, int32_t dtype, int32_t* d_perm,
+                         int64_t* d_n_unique, void* d_workspace, size_t workspace_bytes,
+                         const kd_options* opts, void* stream);
 
 /* ---- diagnostics ------------------------------------------------------------
  * Kernel probe for measurement tools.  kd_probe_start() makes the library

@@ -17,7 +17,7 @@ import torch
 from . import _lib
 from ._lib import KD_F32, KD_I32, KdError  # noqa: F401
 
-__all__ = ["Builder", "build", "KdError"]
+__all__ = ["Builder", "BatchedBuilder", "build", "build_batched", "KdError"]
 
 
 def _dtype_code(t: torch.Tensor) -> int:
@@ -81,6 +81,53 @@ class Builder:
                                        self.workspace.numel(), _lib.options(self.cutover),
                                        _stream(stream))
         _lib.check(rc, "kdtree_partition")
+
+
+class BatchedBuilder:
+    """Builds many independent trees with one sequence of launches.
+
+    ``offsets`` (host sequence or int64 tensor of B+1 values) splits the rows of
+    ``tuples`` into trees; the workspace is sized for exactly that split."""
+
+    def __init__(self, offsets, k: int, dtype=torch.int32, device="cuda", cutover: int | None = None):
+        import numpy as np
+
+        off = np.asarray(offsets.cpu() if isinstance(offsets, torch.Tensor) else offsets, dtype=np.int64)
+        self.h_offsets = np.ascontiguousarray(off)
+        self.trees = int(off.shape[0] - 1)
+        self.total = int(off[-1])
+        self.k = int(k)
+        self.code = _dtype_code(torch.empty(0, dtype=dtype))
+        self.device = torch.device(device)
+        self.cutover = cutover
+        self.d_offsets = torch.from_numpy(self.h_offsets).to(self.device)
+        nbytes = _lib.workspace_bytes_batched(self.total, self.trees, self.k, self.code)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.n_unique = torch.zeros(self.trees, dtype=torch.int64, device=self.device)
+
+    def build(self, tuples: torch.Tensor, perm: torch.Tensor, stream=None):
+        if tuples.dim() != 2 or tuples.shape[0] != self.total or tuples.shape[1] != self.k:
+            raise ValueError(f"tuples must be ({self.total}, {self.k})")
+        if not tuples.is_cuda or not tuples.is_contiguous() or _dtype_code(tuples) != self.code:
+            raise ValueError("tuples must be a contiguous device tensor of the builder's dtype")
+        rc = _lib.lib.kdtree_build_batched(
+            _ptr(tuples), _ptr(self.d_offsets), self.h_offsets.ctypes.data_as(ctypes.c_void_p),
+            self.trees, self.k, self.code, _ptr(perm), _ptr(self.n_unique), _ptr(self.workspace),
+            self.workspace.numel(), _lib.options(self.cutover), _stream(stream))
+        _lib.check(rc, "kdtree_build_batched")
+
+
+def build_batched(tuples: torch.Tensor, offsets, cutover: int | None = None, stream=None):
+    """Build one tree per row range ``offsets[b] .. offsets[b+1]-1``.
+
+    Returns ``(perm, n_unique)``: perm (int32, length offsets[-1]) holds tree
+    b's in-order layout at positions offsets[b] .. offsets[b]+n_unique[b]-1,
+    as row indices local to the tree.
+    """
+    b = BatchedBuilder(offsets, tuples.shape[1], tuples.dtype, tuples.device, cutover)
+    perm = torch.full((max(b.total, 1),), -1, dtype=torch.int32, device=tuples.device)
+    b.build(tuples.contiguous(), perm, stream)
+    return perm[: b.total], b.n_unique
 
 
 def build(tuples: torch.Tensor, children: bool = False, cutover: int | None = None, stream=None):

@@ -43,6 +43,10 @@ def _load():
     lib.kdtree_presort.restype = ctypes.c_int
     lib.kdtree_partition.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp, vp, sz, opt, vp]
     lib.kdtree_partition.restype = ctypes.c_int
+    lib.kdtree_workspace_bytes_batched.argtypes = [i64, i32, i32, i32, ctypes.POINTER(sz)]
+    lib.kdtree_workspace_bytes_batched.restype = ctypes.c_int
+    lib.kdtree_build_batched.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp, sz, opt, vp]
+    lib.kdtree_build_batched.restype = ctypes.c_int
     lib.kd_probe_start.argtypes = [i32, i32]
     lib.kd_probe_start.restype = ctypes.c_int
     lib.kd_probe_stop.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int32)]
@@ -54,7 +58,8 @@ lib = _load()
 
 # Every symbol include/kdtree.h declares (the tests check the library exports them).
 EXPORTED = ["kd_strerror", "kdtree_workspace_bytes", "kdtree_build", "kdtree_presort",
-            "kdtree_partition", "kd_probe_start", "kd_probe_stop"]
+            "kdtree_partition", "kdtree_workspace_bytes_batched", "kdtree_build_batched",
+            "kd_probe_start", "kd_probe_stop"]
 
 KERNEL_CLASSES = {"onesweep": 1, "level": 2, "leaf": 3, "dedup": 4, "hist": 5, "canon": 6,
                   "records": 7}
@@ -79,6 +84,13 @@ def check(rc: int, what: str) -> None:
 def workspace_bytes(n: int, k: int, dtype: int) -> int:
     out = ctypes.c_size_t(0)
     check(lib.kdtree_workspace_bytes(n, k, dtype, ctypes.byref(out)), "kdtree_workspace_bytes")
+    return int(out.value)
+
+
+def workspace_bytes_batched(total: int, trees: int, k: int, dtype: int) -> int:
+    out = ctypes.c_size_t(0)
+    check(lib.kdtree_workspace_bytes_batched(total, trees, k, dtype, ctypes.byref(out)),
+          "kdtree_workspace_bytes_batched")
     return int(out.value)
 
 

@@ -3,9 +3,12 @@
 // A build is a fixed sequence of kernel launches on the caller's stream with
 // no host synchronisation: the number of distinct rows stays on the device,
 // and every launch sized by n (a bound on it) lets surplus workgroups exit.
-// The whole sequence can therefore be captured into a HIP graph.
+// The whole sequence can therefore be captured into a HIP graph.  A single
+// build is a forest of one tree; the batched entry point builds many trees
+// with the same sequence of launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -20,14 +23,21 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// Workspace layout for n rows in k dimensions.  Every region is fully written
-// before it is read within a build, so nothing needs clearing.
+int tree_digit_passes(int B) {
+  int bits = 0;
+  while (B > 1 && ((int64_t)(B - 1) >> bits) != 0) ++bits;
+  return (bits + kRadixBits - 1) / kRadixBits;
+}
+
+// Workspace layout for N rows in k dimensions and B trees.  Every region is
+// fully written before it is read within a build, so nothing needs clearing.
 struct Layout {
   size_t vbuf, carry, S, rec0, rec1, rec2;
-  size_t rcnt, rgrp, dcnt, seginfo, lcnt, lcarry, nu, end;
+  size_t rcnt, rgrp, dcnt, seginfo, lcnt, lcarry;
+  size_t uoff, wgbase, lmax, queue, offs, end;
 };
 
-Layout plan(int64_t n, int k) {
+Layout plan(int64_t n, int k, int B) {
   Layout L{};
   const int64_t nn = n > 0 ? n : 1;
   const size_t un = (size_t)nn;
@@ -37,8 +47,8 @@ Layout plan(int64_t n, int k) {
     o = align_up(o + bytes);
     return at;
   };
-  L.vbuf = take(4 * un * (k + 1) * 2);  // radix passes: two sets of key + k payload planes
-  L.carry = take(4 * un * k);           // key words handed from one sort to the next
+  L.vbuf = take(4 * un * (k + 2) * 2);  // radix passes: two sets of k+2 quantity slots
+  L.carry = take(4 * un * (k + 1));     // key words (and tree ids) handed between sorts
   L.S = take(4 * un * k);               // the k deduplicated sorted id arrays
   const size_t rw = 4 * (size_t)record_words(k, nn);
   L.rec0 = take(k > 1 ? rw : 4);        // level-0 rank records (kept)
@@ -51,7 +61,11 @@ Layout plan(int64_t n, int k) {
   L.seginfo = take(lt * level_seginfo_bytes());
   L.lcnt = take(4 * lt * 8 * (k > 1 ? k - 1 : 1));
   L.lcarry = take(8 * lt * (k > 1 ? k - 1 : 1));
-  L.nu = take(8);
+  L.uoff = take(4 * ((size_t)B + 1));
+  L.wgbase = take(4 * ((size_t)B + 1));
+  L.lmax = take(4);
+  L.queue = take(4);
+  L.offs = take(16);
   L.end = o;
   return L;
 }
@@ -63,13 +77,7 @@ T* at(void* base, size_t off) {
 
 bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
 
-int check_common(const void* tuples, int64_t n, int32_t k, int32_t dtype, void* ws,
-                 size_t ws_bytes, const kd_options* opts, int64_t* cutover) {
-  if (n < 0 || k < 1 || (dtype != KD_I32 && dtype != KD_F32)) return KD_EINVAL;
-  if (n > KD_MAX_N || k > KD_MAX_K) return KD_EUNSUPPORTED;
-  if ((n > 0 && !tuples) || !ws) return KD_EINVAL;
-  if (!aligned4(tuples) || !aligned4(ws)) return KD_EINVAL;
-  if (ws_bytes < plan(n, k).end) return KD_ENOMEM;
+int check_opts(const kd_options* opts, int64_t* cutover) {
   *cutover = 1024;
   if (opts) {
     for (int i = 0; i < 7; ++i)
@@ -107,146 +115,280 @@ void probe_end(int cls, hipStream_t st) {
 }
 
 // launch `expr` (a hipError_t expression) bracketed by the probe for class `cls`
-#define KD_LAUNCH(cls, expr)      \
-  do {                            \
-    probe_begin((cls), st);       \
-    hipError_t e__ = (expr);      \
-    probe_end((cls), st);         \
-    if (e__ != hipSuccess) return KD_EHIP; \
+#define KD_LAUNCH(cls, expr)                   \
+  do {                                         \
+    probe_begin((cls), st);                    \
+    hipError_t e__ = (expr);                   \
+    probe_end((cls), st);                      \
+    if (e__ != hipSuccess) return KD_EHIP;     \
   } while (0)
 
-int presort_impl(const void* tuples, int64_t n, int k, int dtype, void* ws, hipStream_t st) {
-  const Layout L = plan(n, k);
+// ---- stable multi-pass sorts ----------------------------------------------------
+// A sort moves a set of quantities (row id, key words, tree id, ranks) through
+// a list of radix passes, each keyed on one quantity's digit.  Between passes
+// quantity i lives in slot i of one of two buffer sets; after its last use a
+// quantity is dropped, and the last pass writes the survivors to their
+// destinations.
+struct Quant {
+  int kind;             // kPlaneArray / kPlaneIndex / kPlaneTupleWord
+  const uint32_t* in;   // current location (kPlaneArray)
+  int word;             // tuple word (kPlaneTupleWord)
+  uint32_t* dst;        // destination after the sort, or null when not needed
+};
+
+struct Pass {
+  int key;    // quantity index
+  int shift;  // digit
+};
+
+int run_sort(std::vector<Quant>& q, const std::vector<Pass>& passes, const TupleSrc& ts, int64_t n,
+             const int32_t* n_dev, uint32_t* vb, int slots, uint32_t* rcnt, uint32_t* rgrp,
+             hipStream_t st) {
+  const size_t un = (size_t)n;
+  auto slot = [&](int set, int i) { return vb + ((size_t)set * slots + i) * un; };
+  const int np = (int)passes.size();
+  auto needed_after = [&](int i, int p) {
+    for (int p2 = p + 1; p2 < np; ++p2)
+      if (passes[p2].key == i) return true;
+    return q[i].dst != nullptr;
+  };
+  int set = 0;
+  for (int p = 0; p < np; ++p) {
+    const bool last = p == np - 1;
+    const int kq = passes[p].key;
+    const uint32_t* kin = q[kq].kind == kPlaneArray ? q[kq].in : nullptr;
+    uint32_t* kout = nullptr;
+    if (needed_after(kq, p)) kout = last ? q[kq].dst : slot(set ^ 1, kq);
+    Payload pay{};
+    int c = 0;
+    std::vector<int> moved;
+    for (int i = 0; i < (int)q.size(); ++i) {
+      if (i == kq || q[i].kind < 0 || !needed_after(i, p)) continue;
+      Plane& pl = pay.p[c++];
+      pl.kind = q[i].kind;
+      pl.in = q[i].in;
+      pl.word = q[i].word;
+      pl.out = last ? q[i].dst : slot(set ^ 1, i);
+      moved.push_back(i);
+    }
+    pay.count = c;
+    KD_LAUNCH(KD_K_ONESWEEP, launch_radix_pass(kin, ts, q[kq].word, kout, pay, n, n_dev,
+                                               passes[p].shift, rcnt, rgrp, st));
+    for (int i = 0; i < (int)q.size(); ++i) {
+      if (q[i].kind < 0) continue;
+      const bool written = i == kq ? kout != nullptr
+                                   : std::find(moved.begin(), moved.end(), i) != moved.end();
+      if (written) {
+        q[i].kind = kPlaneArray;
+        q[i].in = i == kq ? kout : (last ? q[i].dst : slot(set ^ 1, i));
+      } else {
+        q[i].kind = -1;  // dropped
+      }
+    }
+    set ^= 1;
+  }
+  return KD_OK;
+}
+
+// ---- the build ---------------------------------------------------------------------
+
+struct Job {
+  const void* tuples;
+  int64_t n;      // rows over all trees
+  int B;          // trees
+  const int64_t* d_off;
+  const int64_t* h_off;
+  int k;
+  int dtype;
+  int32_t* perm;
+  int32_t* lo;
+  int32_t* hi;
+  int64_t* n_unique;  // [B]
+  void* ws;
+  int64_t cutover;
+};
+
+ForestArgs forest_args(const Job& J, const Layout& L) {
+  ForestArgs fa;
+  fa.B = J.B;
+  fa.off = J.d_off;
+  fa.uoff = at<int32_t>(J.ws, L.uoff);
+  fa.lmax = at<int32_t>(J.ws, L.lmax);
+  fa.wgbase = at<int32_t>(J.ws, L.wgbase);
+  fa.queue = at<int32_t>(J.ws, L.queue);
+  return fa;
+}
+
+int presort_impl(const Job& J, hipStream_t st) {
+  const int64_t n = J.n;
+  const int k = J.k;
+  const int B = J.B;
+  const Layout L = plan(n, k, B);
+  void* ws = J.ws;
   uint32_t* vb = at<uint32_t>(ws, L.vbuf);
   uint32_t* carry = at<uint32_t>(ws, L.carry);
   uint32_t* S = at<uint32_t>(ws, L.S);
   uint32_t* rec0 = at<uint32_t>(ws, L.rec0);
   uint32_t* rcnt = at<uint32_t>(ws, L.rcnt);
   uint32_t* rgrp = at<uint32_t>(ws, L.rgrp);
-  int64_t* nu = at<int64_t>(ws, L.nu);
+  int32_t* uoff = at<int32_t>(ws, L.uoff);
   const size_t un = (size_t)n;
-  // slot q of set `set`: radix pass buffers
-  auto slot = [&](int set, int q) { return vb + ((size_t)set * (k + 1) + q) * un; };
-  const TupleSrc ts{static_cast<const uint32_t*>(tuples), k, dtype == KD_F32 ? 1 : 0};
+  const int slots = k + 2;
+  const int tp = tree_digit_passes(B);
+  const TupleSrc ts{static_cast<const uint32_t*>(J.tuples), k, J.dtype == KD_F32 ? 1 : 0};
 
-  if (n == 0) {
-    KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(nu), 0u, 2, st));
-    return KD_OK;
+  KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(uoff), 0x7FFFFFFFu, B, st));
+  KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(uoff + B), 0u, 1, st));
+  if (n > 0) {
+    // Array 0: LSD over the words of x:y:z:..., least significant word first,
+    // then (several trees) the tree id, which groups the rows by tree.
+    // Quantities: 0 = row id, d = word d (1 <= d < k), k = word 0, k+1 = tree.
+    uint32_t* tree_in = carry + (size_t)(k - 1) * un;
+    if (B > 1) KD_TRY(launch_tree_ids(J.d_off, B, tree_in, st));
+    std::vector<Quant> q(k + 2);
+    const int fs = (k * kPassesPerWord + tp) & 1;  // buffer set holding the sorted result
+    auto final_slot = [&](int i) { return vb + ((size_t)fs * slots + i) * un; };
+    q[0] = Quant{kPlaneIndex, nullptr, 0, final_slot(0)};
+    for (int d = 1; d < k; ++d) q[d] = Quant{kPlaneTupleWord, nullptr, d, final_slot(d)};
+    q[k] = Quant{kPlaneTupleWord, nullptr, 0, final_slot(k)};
+    q[k + 1] = B > 1 ? Quant{kPlaneArray, tree_in, 0, final_slot(k + 1)}
+                     : Quant{-1, nullptr, 0, nullptr};
+    std::vector<Pass> passes;
+    for (int w = k - 1; w >= 0; --w)
+      for (int ps = 0; ps < kPassesPerWord; ++ps) passes.push_back({w == 0 ? k : w, ps * kRadixBits});
+    for (int ps = 0; ps < tp; ++ps) passes.push_back({k + 1, ps * kRadixBits});
+    int rc = run_sort(q, passes, ts, n, nullptr, vb, slots, rcnt, rgrp, st);
+    if (rc != KD_OK) return rc;
+    // Sec. 2.1 duplicate removal on the fully sorted order; hands the words
+    // w1..w_{k-1} (and tree ids) of the kept rows to the chain
+    KD_LAUNCH(KD_K_DEDUP, launch_dedup(final_slot(k), final_slot(0), B > 1 ? final_slot(k + 1) : nullptr,
+                                       n, k, S, carry, (int64_t)un, B > 1 ? tree_in : nullptr,
+                                       at<uint32_t>(ws, L.dcnt), uoff, B, st));
   }
-
-  // Array 0: LSD over the words of x:y:z:..., least significant word first.
-  // Slots: 0 = row id, d = word d (1 <= d < k), k = word 0.  Every pass moves
-  // the sort word as its key and all other slots as payload; the first pass
-  // reads the tuple rows themselves.
-  auto word_slot = [&](int d) { return d == 0 ? k : d; };
-  int cur = 0;
-  for (int w = k - 1; w >= 0; --w) {
-    for (int ps = 0; ps < kPassesPerWord; ++ps) {
-      const bool from_tuples = (w == k - 1 && ps == 0);
-      Payload pay{};
-      int q = 0;
-      for (int sl = 0; sl <= k; ++sl) {
-        if (sl == word_slot(w)) continue;
-        Plane& pl = pay.p[q++];
-        pl.out = slot(cur ^ 1, sl);
-        if (from_tuples) {
-          pl.kind = sl == 0 ? kPlaneIndex : kPlaneTupleWord;
-          pl.word = sl == k ? 0 : sl;
-        } else {
-          pl.kind = kPlaneArray;
-          pl.in = slot(cur, sl);
-        }
-      }
-      pay.count = q;
-      KD_LAUNCH(KD_K_ONESWEEP,
-                launch_radix_pass(from_tuples ? nullptr : slot(cur, word_slot(w)), ts, w,
-                                  slot(cur ^ 1, word_slot(w)), pay, n, nullptr, ps * kRadixBits,
-                                  rcnt, rgrp, st));
-      cur ^= 1;
-    }
-  }
-  // Sec. 2.1 duplicate removal on the fully sorted order; hands the words
-  // w1..w_{k-1} of the kept rows to the chain
-  KD_LAUNCH(KD_K_DEDUP, launch_dedup(slot(cur, k), slot(cur, 0), n, k, S, carry, (int64_t)un,
-                                     at<uint32_t>(ws, L.dcnt), nu, st));
-  // carry slot d-1 holds word d of the current order
+  KD_TRY(launch_forest_finish(uoff, B, J.cutover, J.n_unique, at<int32_t>(ws, L.lmax),
+                              at<int32_t>(ws, L.wgbase), at<int32_t>(ws, L.queue), st));
+  if (n == 0) return KD_OK;
+  const int32_t* total = uoff + B;
+  // Chain: the array for super key d is the stable sort by word d (then tree)
+  // of the array for super key d+1.  Besides the row id, each sort carries the
+  // ranks already known -- the input position is the rank in order d+1 --
+  // straight into array d's level-0 rank planes (plane c = rank in order
+  // d+1+c), the key words of the sorts still to come, and the tree ids.
   auto carried = [&](int d) { return carry + (size_t)(d - 1) * un; };
-  // Chain: the array for super key d is the stable sort by word d of the
-  // array for super key d+1.  Besides the row id, each sort carries the ranks
-  // already known -- the input position is the rank in order d+1 -- straight
-  // into array d's level-0 rank planes (plane c = rank in order d+1+c), and
-  // the key words of the sorts still to come.
+  uint32_t* tree_c = carry + (size_t)(k - 1) * un;
   for (int d = k - 1; d >= 1; --d) {
-    const uint32_t* in_ids = S + (size_t)((d + 1) % k) * un;
     const uint32_t* in_rec = rec0 + record_offset((d + 1) % k, k, n);
     uint32_t* out_rec = rec0 + record_offset(d, k, n);
     const int known = k - d;  // record planes 0 .. k-d-1
-    int c = 0;
-    for (int ps = 0; ps < kPassesPerWord; ++ps) {
-      const bool first = ps == 0, last = ps == kPassesPerWord - 1;
-      Payload pay{};
-      int q = 0;
-      {  // slot 0: row id
-        Plane& pl = pay.p[q++];
-        pl.kind = kPlaneArray;
-        pl.in = first ? in_ids : slot(c, 0);
-        pl.out = last ? S + (size_t)d * un : slot(c ^ 1, 0);
-      }
-      for (int cc = 0; cc < known; ++cc) {  // slots 1 .. known: rank planes
-        Plane& pl = pay.p[q++];
-        if (first) {
-          pl.kind = cc == 0 ? kPlaneIndex : kPlaneArray;
-          pl.in = cc == 0 ? nullptr : in_rec + (size_t)(cc - 1) * un;
-        } else {
-          pl.kind = kPlaneArray;
-          pl.in = slot(c, 1 + cc);
-        }
-        pl.out = last ? out_rec + (size_t)cc * un : slot(c ^ 1, 1 + cc);
-      }
-      for (int dd = d - 1; dd >= 1; --dd) {  // key words of the later sorts
-        const int sl = known + (d - dd);
-        Plane& pl = pay.p[q++];
-        pl.kind = kPlaneArray;
-        pl.in = first ? carried(dd) : slot(c, sl);
-        pl.out = last ? carried(dd) : slot(c ^ 1, sl);
-      }
-      pay.count = q;
-      const uint32_t* kin = first ? carried(d) : slot(c, k);
-      uint32_t* kout = last ? nullptr : slot(c ^ 1, k);
-      KD_LAUNCH(KD_K_ONESWEEP, launch_radix_pass(kin, ts, 0, kout, pay, n, nu, ps * kRadixBits,
-                                                 rcnt, rgrp, st));
-      c ^= 1;
+    std::vector<Quant> q;
+    q.push_back(Quant{kPlaneArray, S + (size_t)((d + 1) % k) * un, 0, S + (size_t)d * un});
+    for (int cc = 0; cc < known; ++cc)
+      q.push_back(cc == 0 ? Quant{kPlaneIndex, nullptr, 0, out_rec}
+                          : Quant{kPlaneArray, in_rec + (size_t)(cc - 1) * un, 0,
+                                  out_rec + (size_t)cc * un});
+    for (int dd = d - 1; dd >= 1; --dd) q.push_back(Quant{kPlaneArray, carried(dd), 0, carried(dd)});
+    const int keyq = (int)q.size();
+    q.push_back(Quant{kPlaneArray, carried(d), 0, nullptr});
+    int treeq = -1;
+    if (B > 1) {
+      treeq = (int)q.size();
+      q.push_back(Quant{kPlaneArray, tree_c, 0, tree_c});
     }
+    std::vector<Pass> passes;
+    for (int ps = 0; ps < kPassesPerWord; ++ps) passes.push_back({keyq, ps * kRadixBits});
+    for (int ps = 0; ps < tp; ++ps) passes.push_back({treeq, ps * kRadixBits});
+    int rc = run_sort(q, passes, ts, n, total, vb, slots, rcnt, rgrp, st);
+    if (rc != KD_OK) return rc;
   }
-  if (k > 1)
-    KD_LAUNCH(KD_K_RECORDS, launch_complete_records(rec0, S + (size_t)1 * un, n, k, nu, st));
+  if (k > 1) KD_LAUNCH(KD_K_RECORDS, launch_complete_records(rec0, S + un, n, k, total, st));
   return KD_OK;
 }
 
-int partition_impl(int64_t n, int k, int32_t* perm, int32_t* lo, int32_t* hi, int64_t* n_unique,
-                   void* ws, int64_t cutover, hipStream_t st) {
-  const Layout L = plan(n, k);
-  const int64_t* nu = at<int64_t>(ws, L.nu);
+int partition_impl(const Job& J, hipStream_t st) {
+  const int64_t n = J.n;
+  const int k = J.k;
+  const Layout L = plan(n, k, J.B);
+  void* ws = J.ws;
+  const ForestArgs fa = forest_args(J, L);
   uint32_t* S = at<uint32_t>(ws, L.S);
   if (n > 0) {
     if (k == 1) {
-      KD_TRY(launch_copy_k1(S, nu, n, perm, st));
+      KD_TRY(launch_copy_k1(S, fa, n, J.perm, st));
     } else {
-      // keep the on-chip finish within the 160 KiB of LDS of a workgroup
-      while (cutover > 1024 && leaf_lds_bytes(cutover, k) + 8192 > 160 * 1024) cutover /= 2;
+      int64_t cutover = J.cutover;
       const uint32_t* r0 = at<uint32_t>(ws, L.rec0);
       uint32_t* r1 = at<uint32_t>(ws, L.rec1);
       uint32_t* r2 = at<uint32_t>(ws, L.rec2);
-      const int levels = cutover_depth(n, cutover);
+      // host bounds from the row counts: deepest global level, finish items
+      int levels = 0;
+      int64_t items = 0;
+      for (int b = 0; b < J.B; ++b) {
+        const int64_t nb = J.h_off[b + 1] - J.h_off[b];
+        const int lc = cutover_depth(nb, cutover);
+        levels = lc > levels ? lc : levels;
+        items += nb > 0 ? ((int64_t)1 << lc) : 0;
+      }
       for (int d = 0; d < levels; ++d)
-        KD_LAUNCH(KD_K_LEVEL, launch_level(r0, r1, r2, n, k, d, cutover, nu, perm,
+        KD_LAUNCH(KD_K_LEVEL, launch_level(r0, r1, r2, n, k, d, cutover, fa, J.perm,
                                            at<void>(ws, L.seginfo), at<uint32_t>(ws, L.lcnt),
                                            at<uint64_t>(ws, L.lcarry), st));
-      KD_LAUNCH(KD_K_LEAF, launch_leaf(r0, r1, r2, n, k, cutover, nu, perm, levels, st));
+      // the finish takes its items from a counter; partition may run again
+      // after one presort, so the counter is cleared here
+      KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(fa.queue), 0u, 1, st));
+      KD_LAUNCH(KD_K_LEAF, launch_leaf(r0, r1, r2, n, k, cutover, fa, J.perm, items, st));
     }
-    if (lo && hi) KD_TRY(launch_children(nu, n, lo, hi, st));
+    if (J.lo && J.hi) KD_TRY(launch_children(fa.uoff, n, J.lo, J.hi, st));
   }
-  KD_TRY(launch_store_i64(n_unique, nu, st));
+  return KD_OK;
+}
+
+// Validation shared by every entry point; `cutover` may be lowered so that the
+// on-chip finish fits the 160 KiB of LDS of a workgroup.
+int check_job(Job& J, size_t ws_bytes, const kd_options* opts) {
+  if (J.n < 0 || J.k < 1 || J.B < 1 || (J.dtype != KD_I32 && J.dtype != KD_F32)) return KD_EINVAL;
+  if (J.n > KD_MAX_N || J.k > KD_MAX_K) return KD_EUNSUPPORTED;
+  if ((J.n > 0 && !J.tuples) || !J.ws || !J.n_unique) return KD_EINVAL;
+  if (!aligned4(J.tuples) || !aligned4(J.ws)) return KD_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(J.n_unique) & 7u) != 0) return KD_EINVAL;
+  if (ws_bytes < plan(J.n, J.k, J.B).end) return KD_ENOMEM;
+  int rc = check_opts(opts, &J.cutover);
+  if (rc != KD_OK) return rc;
+  while (J.cutover > 1024 && leaf_lds_bytes(J.cutover, J.k) + 8192 > 160 * 1024) J.cutover /= 2;
+  return KD_OK;
+}
+
+int check_outputs(const Job& J) {
+  if ((J.n > 0 && !J.perm) || !aligned4(J.perm)) return KD_EINVAL;
+  if ((J.lo == nullptr) != (J.hi == nullptr)) return KD_EINVAL;
+  if (!aligned4(J.lo) || !aligned4(J.hi)) return KD_EINVAL;
+  return KD_OK;
+}
+
+// single tree: offsets {0, n} live in the workspace
+int single_job(Job& J, const void* tuples, int64_t n, int32_t k, int32_t dtype, int64_t* nu,
+               void* ws, size_t ws_bytes, const kd_options* opts, int64_t* h_off, hipStream_t st,
+               bool upload) {
+  J = Job{};
+  J.tuples = tuples;
+  J.n = n;
+  J.B = 1;
+  J.k = k;
+  J.dtype = dtype;
+  J.n_unique = nu;
+  J.ws = ws;
+  h_off[0] = 0;
+  h_off[1] = n;
+  J.h_off = h_off;
+  int rc = check_job(J, ws_bytes, opts);
+  if (rc != KD_OK) return rc;
+  int64_t* d_off = at<int64_t>(ws, plan(n, k, 1).offs);
+  J.d_off = d_off;
+  if (upload) {
+    const uint32_t words[4] = {0u, 0u, (uint32_t)(n & 0xFFFFFFFF), (uint32_t)(n >> 32)};
+    KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(d_off), words[0], 2, st));
+    KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(d_off) + 2, words[2], 1, st));
+    KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(d_off) + 3, words[3], 1, st));
+  }
   return KD_OK;
 }
 
@@ -269,54 +411,108 @@ const char* kd_strerror(int code) {
 int kdtree_workspace_bytes(int64_t n, int32_t k, int32_t dtype, size_t* h_bytes) {
   if (!h_bytes || n < 0 || k < 1 || (dtype != KD_I32 && dtype != KD_F32)) return KD_EINVAL;
   if (n > KD_MAX_N || k > KD_MAX_K) return KD_EUNSUPPORTED;
-  *h_bytes = kd::plan(n, k).end;
+  *h_bytes = kd::plan(n, k, 1).end;
+  return KD_OK;
+}
+
+int kdtree_workspace_bytes_batched(int64_t total_rows, int32_t num_trees, int32_t k, int32_t dtype,
+                                   size_t* h_bytes) {
+  if (!h_bytes || total_rows < 0 || num_trees < 1 || k < 1 ||
+      (dtype != KD_I32 && dtype != KD_F32))
+    return KD_EINVAL;
+  if (total_rows > KD_MAX_N || k > KD_MAX_K || num_trees > KD_MAX_TREES) return KD_EUNSUPPORTED;
+  *h_bytes = kd::plan(total_rows, k, num_trees).end;
   return KD_OK;
 }
 
 int kdtree_presort(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, int64_t* d_n_unique,
                    void* d_workspace, size_t workspace_bytes, const kd_options* opts,
                    void* stream) {
-  int64_t cutover;
-  int rc = kd::check_common(d_tuples, n, k, dtype, d_workspace, workspace_bytes, opts, &cutover);
-  if (rc != KD_OK) return rc;
-  if (!d_n_unique || (reinterpret_cast<uintptr_t>(d_n_unique) & 7u)) return KD_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  rc = kd::presort_impl(d_tuples, n, k, dtype, d_workspace, st);
+  kd::Job J;
+  int64_t h_off[2];
+  int rc = kd::single_job(J, d_tuples, n, k, dtype, d_n_unique, d_workspace, workspace_bytes, opts,
+                          h_off, st, true);
   if (rc != KD_OK) return rc;
-  if (kd::launch_store_i64(d_n_unique, kd::at<int64_t>(d_workspace, kd::plan(n, k).nu), st) !=
-      hipSuccess)
-    return KD_EHIP;
-  return KD_OK;
+  return kd::presort_impl(J, st);
 }
 
 int kdtree_partition(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, int32_t* d_perm,
                      int32_t* d_lo, int32_t* d_hi, int64_t* d_n_unique, void* d_workspace,
                      size_t workspace_bytes, const kd_options* opts, void* stream) {
-  int64_t cutover;
-  int rc = kd::check_common(d_tuples, n, k, dtype, d_workspace, workspace_bytes, opts, &cutover);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  kd::Job J;
+  int64_t h_off[2];
+  int rc = kd::single_job(J, d_tuples, n, k, dtype, d_n_unique, d_workspace, workspace_bytes, opts,
+                          h_off, st, false);
   if (rc != KD_OK) return rc;
-  if (!d_n_unique || (reinterpret_cast<uintptr_t>(d_n_unique) & 7u)) return KD_EINVAL;
-  if ((n > 0 && !d_perm) || !kd::aligned4(d_perm)) return KD_EINVAL;
-  if ((d_lo == nullptr) != (d_hi == nullptr)) return KD_EINVAL;
-  if (!kd::aligned4(d_lo) || !kd::aligned4(d_hi)) return KD_EINVAL;
-  return kd::partition_impl(n, k, d_perm, d_lo, d_hi, d_n_unique, d_workspace, cutover,
-                            static_cast<hipStream_t>(stream));
+  J.perm = d_perm;
+  J.lo = d_lo;
+  J.hi = d_hi;
+  rc = kd::check_outputs(J);
+  if (rc != KD_OK) return rc;
+  return kd::partition_impl(J, st);
 }
 
 int kdtree_build(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, int32_t* d_perm,
                  int32_t* d_lo, int32_t* d_hi, int64_t* d_n_unique, void* d_workspace,
                  size_t workspace_bytes, const kd_options* opts, void* stream) {
-  int64_t cutover;
-  int rc = kd::check_common(d_tuples, n, k, dtype, d_workspace, workspace_bytes, opts, &cutover);
-  if (rc != KD_OK) return rc;
-  if (!d_n_unique || (reinterpret_cast<uintptr_t>(d_n_unique) & 7u)) return KD_EINVAL;
-  if ((n > 0 && !d_perm) || !kd::aligned4(d_perm)) return KD_EINVAL;
-  if ((d_lo == nullptr) != (d_hi == nullptr)) return KD_EINVAL;
-  if (!kd::aligned4(d_lo) || !kd::aligned4(d_hi)) return KD_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  rc = kd::presort_impl(d_tuples, n, k, dtype, d_workspace, st);
+  kd::Job J;
+  int64_t h_off[2];
+  // validate everything before the first launch
+  {
+    kd::Job V;
+    int64_t h2[2];
+    int rc = kd::single_job(V, d_tuples, n, k, dtype, d_n_unique, d_workspace, workspace_bytes,
+                            opts, h2, st, false);
+    if (rc != KD_OK) return rc;
+    V.perm = d_perm;
+    V.lo = d_lo;
+    V.hi = d_hi;
+    rc = kd::check_outputs(V);
+    if (rc != KD_OK) return rc;
+  }
+  int rc = kd::single_job(J, d_tuples, n, k, dtype, d_n_unique, d_workspace, workspace_bytes, opts,
+                          h_off, st, true);
   if (rc != KD_OK) return rc;
-  return kd::partition_impl(n, k, d_perm, d_lo, d_hi, d_n_unique, d_workspace, cutover, st);
+  J.perm = d_perm;
+  J.lo = d_lo;
+  J.hi = d_hi;
+  rc = kd::presort_impl(J, st);
+  if (rc != KD_OK) return rc;
+  return kd::partition_impl(J, st);
+}
+
+int kdtree_build_batched(const void* d_tuples, const int64_t* d_offsets, const int64_t* h_offsets,
+                         int32_t num_trees, int32_t k, int32_t dtype, int32_t* d_perm,
+                         int64_t* d_n_unique, void* d_workspace, size_t workspace_bytes,
+                         const kd_options* opts, void* stream) {
+  if (num_trees < 1 || !d_offsets || !h_offsets) return KD_EINVAL;
+  if (num_trees > KD_MAX_TREES) return KD_EUNSUPPORTED;
+  if ((reinterpret_cast<uintptr_t>(d_offsets) & 7u) != 0) return KD_EINVAL;
+  if (h_offsets[0] != 0) return KD_EINVAL;
+  for (int b = 0; b < num_trees; ++b)
+    if (h_offsets[b + 1] < h_offsets[b]) return KD_EINVAL;
+  kd::Job J{};
+  J.tuples = d_tuples;
+  J.n = h_offsets[num_trees];
+  J.B = num_trees;
+  J.d_off = d_offsets;
+  J.h_off = h_offsets;
+  J.k = k;
+  J.dtype = dtype;
+  J.perm = d_perm;
+  J.n_unique = d_n_unique;
+  J.ws = d_workspace;
+  int rc = kd::check_job(J, workspace_bytes, opts);
+  if (rc != KD_OK) return rc;
+  rc = kd::check_outputs(J);
+  if (rc != KD_OK) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  rc = kd::presort_impl(J, st);
+  if (rc != KD_OK) return rc;
+  return kd::partition_impl(J, st);
 }
 
 int kd_probe_start(int32_t kernel_class, int32_t capacity) {

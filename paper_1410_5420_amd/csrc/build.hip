@@ -37,6 +37,54 @@ __device__ __forceinline__ const uint32_t* buf_after(const RecBufs& B, int moves
   return moves == 0 ? B.rec0 : ((moves & 1) ? B.b1 : B.b2);
 }
 
+// ---- forests ------------------------------------------------------------------
+// Several independent trees are built at once as a forest.  In the sorted
+// orders the distinct rows of tree b occupy positions uoff[b] .. uoff[b+1]-1
+// (ranks are global positions, consistent within each tree); in the input and
+// in perm, tree b owns rows off[b] .. off[b+1]-1.  A single build is a forest
+// of one tree.
+struct Forest {
+  int B;
+  const int64_t* off;
+  const int32_t* uoff;
+  const int32_t* lmax;    // deepest global level any tree needs
+  const int32_t* wgbase;  // on-chip finish items of tree b: wgbase[b] .. wgbase[b+1]-1
+  int32_t* queue;         // work counter of the on-chip finish (zero before it runs)
+};
+
+// Largest b < B with v[b] <= x (v non-decreasing, v[0] <= x).
+__device__ __forceinline__ int upper_index(const int32_t* v, int B, int x) {
+  int lo = 0, hi = B - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (v[mid] <= x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Subarray of the forest at `depth` that contains position pos, or e < s when
+// pos is the node of a shallower level or its tree is finished on-chip from
+// a shallower depth.  *tree receives the tree.
+__device__ __forceinline__ void forest_subarray(const Forest& F, int64_t cutover, int pos,
+                                                int depth, int* s_out, int* e_out, int* tree) {
+  const int b = F.B == 1 ? 0 : upper_index(F.uoff, F.B, pos);
+  const int base = F.uoff[b];
+  const int nb = F.uoff[b + 1] - base;
+  *tree = b;
+  if (depth >= cutover_depth(nb, cutover)) {
+    *s_out = 1;
+    *e_out = 0;
+    return;
+  }
+  int s, e;
+  subarray_at(pos - base, nb, depth, &s, &e);
+  *s_out = s + base;
+  *e_out = e + base;
+}
+
 // ---- global level -------------------------------------------------------------
 // A level is three launches with no waiting between workgroups:
 //   1. count: tile t of moving array a finds the subarrays that meet it (and
@@ -77,16 +125,17 @@ __device__ __forceinline__ T wave_sum(T v) {
 
 // Wave 0 of a block: subarrays meeting [t0, t1) at `depth`, their medians'
 // ranks in order p, and (write_perm) the row id of every median in the tile.
-__device__ void find_subarrays(const RecBufs& B, int64_t n, int k, int depth, int nu, int t0,
-                               int t1, bool write_perm, int32_t* perm, SegInfo* out) {
+__device__ void find_subarrays(const RecBufs& B, const Forest& F, int64_t n, int k, int depth,
+                               int64_t cutover, int t0, int t1, bool write_perm, int32_t* perm,
+                               SegInfo* out) {
   const int lane = lane_id();
   const int p = depth % k;
-  int s = INT32_MAX, e = -1;
+  int s = INT32_MAX, e = -1, tr = 0;
   if (lane < kSamples) {
     int pos = t0 + lane * 512;
     if (pos > t1 - 1) pos = t1 - 1;
-    subarray_at(pos, nu, depth, &s, &e);
-    if (e < s && pos + 1 < t1) subarray_at(pos + 1, nu, depth, &s, &e);
+    forest_subarray(F, cutover, pos, depth, &s, &e, &tr);
+    if (e < s && pos + 1 < t1) forest_subarray(F, cutover, pos + 1, depth, &s, &e, &tr);
     if (e < s) {
       s = INT32_MAX;
       e = -1;
@@ -114,16 +163,18 @@ __device__ void find_subarrays(const RecBufs& B, int64_t n, int k, int depth, in
         // rank in order 0: that is rp itself when p == 0, otherwise plane
         // (k - p - 1) of the median's record
         const uint32_t r0 = p == 0 ? rp : split[(int64_t)((k - p - 1) % k) * n + m];
-        perm[m] = (int32_t)B.rec0[record_offset(0, k, n) + (int64_t)(k - 1) * n + r0];
+        const int64_t row = B.rec0[record_offset(0, k, n) + (int64_t)(k - 1) * n + r0];
+        const int64_t ob = F.off[tr];
+        perm[ob + (m - F.uoff[tr])] = (int32_t)(row - ob);
       }
     }
   }
   if (lane == 0) out->nseg = min((int)popc64(km), kMaxSeg);
 }
 
-__global__ __launch_bounds__(kLvThreads) void k_level_count(const RecBufs B, int64_t n, int k,
-                                                           int depth, int64_t cutover,
-                                                           const int64_t* nu_ptr,
+__global__ __launch_bounds__(kLvThreads) void k_level_count(const RecBufs B, const Forest F,
+                                                           int64_t n, int k, int depth,
+                                                           int64_t cutover,
                                                            int32_t* __restrict__ perm,
                                                            SegInfo* __restrict__ seginfo,
                                                            uint32_t* __restrict__ cnt,
@@ -131,8 +182,8 @@ __global__ __launch_bounds__(kLvThreads) void k_level_count(const RecBufs B, int
   __shared__ SegInfo s_si;
   __shared__ uint32_t s_cnt[kMaxSeg];
   const int tid = threadIdx.x;
-  const int nu = (int)*nu_ptr;
-  if (depth >= cutover_depth(nu, cutover)) return;
+  const int nu = F.uoff[F.B];
+  if (depth >= *F.lmax) return;
   const int p = depth % k;
   const int a = blockIdx.x / tiles_per_array;
   const int t = blockIdx.x % tiles_per_array;
@@ -152,7 +203,7 @@ __global__ __launch_bounds__(kLvThreads) void k_level_count(const RecBufs B, int
     rp[it] = i < t1 ? plane[i] : 0u;
   }
   if (tid < kMaxSeg) s_cnt[tid] = 0;
-  if (tid < kWave) find_subarrays(B, n, k, depth, nu, t0, t1, a == 0, perm, &s_si);
+  if (tid < kWave) find_subarrays(B, F, n, k, depth, cutover, t0, t1, a == 0, perm, &s_si);
   __syncthreads();
   const int nseg = s_si.nseg;
   if (a == 0 && tid < kMaxSeg) {
@@ -190,8 +241,7 @@ __global__ __launch_bounds__(kLvThreads) void k_level_count(const RecBufs B, int
 
 // Chains the counts along every subarray: carry[a][t] = counts of tile t's
 // first subarray in all earlier tiles (lower in bits 0-31, node in 32-47).
-__global__ __launch_bounds__(1024) void k_level_scan(int64_t n, int k, int depth, int64_t cutover,
-                                                    const int64_t* nu_ptr,
+__global__ __launch_bounds__(1024) void k_level_scan(const Forest F, int depth,
                                                     const SegInfo* __restrict__ seginfo,
                                                     const uint32_t* __restrict__ cnt,
                                                     uint64_t* __restrict__ carry,
@@ -200,8 +250,8 @@ __global__ __launch_bounds__(1024) void k_level_scan(int64_t n, int k, int depth
   __shared__ int s_h[1024];
   __shared__ uint64_t s_run;
   const int tid = threadIdx.x;
-  const int64_t nu = *nu_ptr;
-  if (depth >= cutover_depth(nu, cutover)) return;
+  const int nu = F.uoff[F.B];
+  if (depth >= *F.lmax) return;
   const int a = blockIdx.x;
   const int tiles = (int)((nu + kLevelTile - 1) / kLevelTile);
   if (tid == 0) s_run = 0;
@@ -356,9 +406,8 @@ __device__ __forceinline__ void level_move_tile(const uint32_t* __restrict__ src
 }
 
 template <int R>
-__global__ __launch_bounds__(kLvThreads) void k_level_move(const RecBufs B, int64_t n, int k,
-                                                          int depth, int64_t cutover,
-                                                          const int64_t* nu_ptr,
+__global__ __launch_bounds__(kLvThreads) void k_level_move(const RecBufs B, const Forest F,
+                                                          int64_t n, int k, int depth,
                                                           const SegInfo* __restrict__ seginfo,
                                                           const uint64_t* __restrict__ carry,
                                                           int tiles_per_array) {
@@ -366,8 +415,8 @@ __global__ __launch_bounds__(kLvThreads) void k_level_move(const RecBufs B, int6
   __shared__ uint32_t s_pre[kLevelTile];
   __shared__ SegInfo s_si;
   const int tid = threadIdx.x;
-  const int nu = (int)*nu_ptr;
-  if (depth >= cutover_depth(nu, cutover)) return;
+  const int nu = F.uoff[F.B];
+  if (depth >= *F.lmax) return;
   const int p = depth % k;
   const int a = blockIdx.x / tiles_per_array;
   const int t = blockIdx.x % tiles_per_array;
@@ -394,20 +443,21 @@ __global__ __launch_bounds__(kLvThreads) void k_level_move(const RecBufs B, int6
 }
 
 hipError_t launch_level(const uint32_t* rec0, uint32_t* b1, uint32_t* b2, int64_t n, int k,
-                        int depth, int64_t cutover, const int64_t* nu, int32_t* perm,
+                        int depth, int64_t cutover, const ForestArgs& fa, int32_t* perm,
                         void* seginfo, uint32_t* cnt, uint64_t* carry, hipStream_t st) {
   if (n <= 0 || k < 2) return hipSuccess;
   const int tiles = (int)((n + kLevelTile - 1) / kLevelTile);
   const unsigned grid = (unsigned)(tiles * (k - 1));
   RecBufs B{rec0, b1, b2};
+  Forest F{fa.B, fa.off, fa.uoff, fa.lmax, fa.wgbase, fa.queue};
   SegInfo* si = static_cast<SegInfo*>(seginfo);
-  hipLaunchKernelGGL(k_level_count, dim3(grid), dim3(kLvThreads), 0, st, B, n, k, depth, cutover,
-                     nu, perm, si, cnt, tiles);
-  hipLaunchKernelGGL(k_level_scan, dim3(k - 1), dim3(1024), 0, st, n, k, depth, cutover, nu, si,
-                     cnt, carry, tiles);
+  hipLaunchKernelGGL(k_level_count, dim3(grid), dim3(kLvThreads), 0, st, B, F, n, k, depth,
+                     cutover, perm, si, cnt, tiles);
+  hipLaunchKernelGGL(k_level_scan, dim3(k - 1), dim3(1024), 0, st, F, depth, si, cnt, carry,
+                     tiles);
 #define KD_LV(RR)                                                                               \
-  hipLaunchKernelGGL(k_level_move<RR>, dim3(grid), dim3(kLvThreads), 0, st, B, n, k, depth,     \
-                     cutover, nu, si, carry, tiles)
+  hipLaunchKernelGGL(k_level_move<RR>, dim3(grid), dim3(kLvThreads), 0, st, B, F, n, k, depth,  \
+                     si, carry, tiles)
   switch (k - 1) {
     case 1: KD_LV(1); break;
     case 2: KD_LV(2); break;
@@ -522,9 +572,8 @@ __device__ bool lds_radix_sort(uint32_t* ka, uint16_t* va, uint32_t* kb, uint16_
 }
 
 template <int kItems, int R>
-__global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, int64_t n, int k,
-                                                    const int64_t* nu_ptr,
-                                                    int32_t* __restrict__ perm) {
+__global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Forest F, int64_t n,
+                                                    int k, int32_t* __restrict__ perm) {
   constexpr int C = kItems * kLfThreads;
   constexpr int kChunks = kItems * kLfWaves;
   static_assert(kChunks <= kWave, "one wave scans the chunk totals of an array");
@@ -538,24 +587,36 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, int64_t n,
   __shared__ uint32_t s_cnt[kLfWaves][kRadix];
   __shared__ uint32_t s_dbase[kRadix];
   __shared__ uint32_t s_tmp[kLfWaves + 1];
+  __shared__ int s_item;
 
   const int tid = threadIdx.x;
   const int w = tid / kWave;
   const int lane = tid % kWave;
-  const int64_t nu = *nu_ptr;
-  const int lc = cutover_depth(nu, C);
-  const int64_t g = blockIdx.x;
-  if (g >= ((int64_t)1 << lc)) return;
-  int64_t s0 = 0, e0 = nu - 1;
+  const int items_total = F.wgbase[F.B];
+  // Persistent: every workgroup takes (tree, subarray) items from a counter
+  // until none are left; items never wait on each other.
+  for (;;) {
+  if (tid == 0) s_item = atomicAdd(F.queue, 1);
+  __syncthreads();
+  const int item = s_item;
+  __syncthreads();
+  if (item >= items_total) break;
+  const int tree = F.B == 1 ? 0 : upper_index(F.wgbase, F.B, item);
+  const int g = item - F.wgbase[tree];
+  const int tbase = F.uoff[tree];
+  const int nb = F.uoff[tree + 1] - tbase;
+  const int lc = cutover_depth(nb, C);
+  int s0 = 0, e0 = nb - 1;
   for (int l = 0; l < lc; ++l) {
-    const int64_t m = median_of(s0, e0);
+    const int m = s0 + ((e0 - s0) >> 1);
     if ((g >> (lc - 1 - l)) & 1)
       s0 = m + 1;
     else
       e0 = m - 1;
   }
-  const int N = (int)(e0 - s0 + 1);
-  if (N <= 0) return;
+  const int N = e0 - s0 + 1;
+  if (N <= 0) continue;
+  s0 += tbase;
 
   // Local id of an element = its position in array 0 (sorted by order 0).
   // Array 1 stores the order-0 rank of each of its elements (plane k-2);
@@ -579,7 +640,8 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, int64_t n,
     }
     __syncthreads();
     int passes = 1;
-    while (passes < 4 && (((uint64_t)nu - 1) >> (8 * passes)) != 0) ++passes;
+    const uint32_t total = (uint32_t)F.uoff[F.B];
+    while (passes < 4 && ((uint64_t)(total - 1) >> (8 * passes)) != 0) ++passes;
     const bool in_b = lds_radix_sort<kItems>(s_r0, sv2, sk, sv, N, passes, s_cnt, s_dbase, s_tmp);
     // sorted ranks must end in s_r0; the array-1 positions they came from in regs
     uint16_t from[kItems];
@@ -719,23 +781,29 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, int64_t n,
     curmask ^= ((1u << k) - 1) & ~(1u << p);  // every array but the split one moved
     __syncthreads();
   }
+  {
+    const int64_t ob = F.off[tree];
+    int32_t* out = perm + ob + (s0 - tbase);
 #pragma unroll
-  for (int it = 0; it < kItems; ++it) {
-    const int i = it * kLfThreads + tid;
-    if (i < N) {
-      const int id = s_out[i];
-      if (id < N) perm[s0 + i] = (int32_t)s_id[id];
+    for (int it = 0; it < kItems; ++it) {
+      const int i = it * kLfThreads + tid;
+      if (i < N) {
+        const int id = s_out[i];
+        if (id < N) out[i] = (int32_t)((int64_t)s_id[id] - ob);
+      }
     }
+  }
+  __syncthreads();  // LDS is reused by the next item
   }
 }
 
 hipError_t launch_leaf(const uint32_t* rec0, uint32_t* b1, uint32_t* b2, int64_t n, int k,
-                       int64_t cutover, const int64_t* nu, int32_t* perm, int grid_bound_depth,
+                       int64_t cutover, const ForestArgs& fa, int32_t* perm, int64_t items_bound,
                        hipStream_t st) {
   if (n <= 0 || k < 2) return hipSuccess;
   const size_t lds = leaf_lds_bytes(cutover, k);
-  const unsigned grid = 1u << grid_bound_depth;
   RecBufs B{rec0, b1, b2};
+  Forest F{fa.B, fa.off, fa.uoff, fa.lmax, fa.wgbase, fa.queue};
   const void* fn = nullptr;
 #define KD_LF_R(IT)                                                  \
   switch (k - 1) {                                                   \
@@ -757,32 +825,41 @@ hipError_t launch_leaf(const uint32_t* rec0, uint32_t* b1, uint32_t* b2, int64_t
 #undef KD_LF_R
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  void* args[] = {&B, &n, &k, const_cast<int64_t**>(&nu), &perm};
-  return hipLaunchKernel(fn, dim3(grid), dim3(kLfThreads), args, lds, st);
+  // persistent grid: enough workgroups to fill the chip, never more than items
+  int64_t grid = 256 * 8;
+  if (items_bound < grid) grid = items_bound;
+  if (grid < 1) grid = 1;
+  void* args[] = {&B, &F, &n, &k, &perm};
+  return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kLfThreads), args, lds, st);
 }
 
 // ---- shape helpers ---------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_copy_k1(const uint32_t* __restrict__ S0,
-                                                const int64_t* nu_ptr, int32_t* __restrict__ perm) {
-  const int64_t nu = *nu_ptr;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nu;
-       i += (int64_t)gridDim.x * blockDim.x)
-    perm[i] = (int32_t)S0[i];
+// k == 1: every tree's in-order layout is its sorted distinct rows.
+__global__ __launch_bounds__(256) void k_copy_k1(const uint32_t* __restrict__ S0, const Forest F,
+                                                int32_t* __restrict__ perm) {
+  const int total = F.uoff[F.B];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    const int b = F.B == 1 ? 0 : upper_index(F.uoff, F.B, i);
+    const int64_t ob = F.off[b];
+    perm[ob + (i - F.uoff[b])] = (int32_t)((int64_t)S0[i] - ob);
+  }
 }
 
-hipError_t launch_copy_k1(const uint32_t* S0, const int64_t* nu, int64_t n, int32_t* perm,
+hipError_t launch_copy_k1(const uint32_t* S0, const ForestArgs& fa, int64_t n, int32_t* perm,
                           hipStream_t st) {
   if (n <= 0) return hipSuccess;
   int64_t blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_copy_k1, dim3((unsigned)blocks), dim3(256), 0, st, S0, nu, perm);
+  Forest F{fa.B, fa.off, fa.uoff, fa.lmax, fa.wgbase, fa.queue};
+  hipLaunchKernelGGL(k_copy_k1, dim3((unsigned)blocks), dim3(256), 0, st, S0, F, perm);
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_children(const int64_t* nu_ptr, int32_t* __restrict__ lo,
-                                                 int32_t* __restrict__ hi) {
-  const int64_t nu = *nu_ptr;
+// Child positions of a single tree's in-order layout.
+__global__ __launch_bounds__(256) void k_children(const int32_t* __restrict__ uoff,
+                                                 int32_t* __restrict__ lo, int32_t* __restrict__ hi) {
+  const int64_t nu = uoff[1];
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nu;
        i += (int64_t)gridDim.x * blockDim.x) {
     int64_t s = 0, e = nu - 1;
@@ -801,11 +878,12 @@ __global__ __launch_bounds__(256) void k_children(const int64_t* nu_ptr, int32_t
   }
 }
 
-hipError_t launch_children(const int64_t* nu, int64_t n, int32_t* lo, int32_t* hi, hipStream_t st) {
+hipError_t launch_children(const int32_t* uoff, int64_t n, int32_t* lo, int32_t* hi,
+                           hipStream_t st) {
   if (n <= 0) return hipSuccess;
   int64_t blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_children, dim3((unsigned)blocks), dim3(256), 0, st, nu, lo, hi);
+  hipLaunchKernelGGL(k_children, dim3((unsigned)blocks), dim3(256), 0, st, uoff, lo, hi);
   return hipGetLastError();
 }
 

@@ -14,6 +14,18 @@ constexpr int kPassesPerWord = 32 / kRadixBits;
 constexpr int kSortTile = 4096;   // elements per onesweep tile
 constexpr int kLevelTile = 4096;  // elements per level-partition tile
 
+// Device view of a forest of independent trees (a single build is one tree):
+// rows of tree b are off[b] .. off[b+1]-1; after duplicate removal its distinct
+// rows occupy positions uoff[b] .. uoff[b+1]-1 of every sorted order.
+struct ForestArgs {
+  int B;
+  const int64_t* off;
+  const int32_t* uoff;
+  const int32_t* lmax;
+  const int32_t* wgbase;
+  int32_t* queue;
+};
+
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t st);
 hipError_t launch_store_i64(int64_t* dst, const int64_t* src, hipStream_t st);
 
@@ -34,7 +46,7 @@ struct Plane {
   int kind;
   int word;
 };
-constexpr int kMaxPlanes = 8;
+constexpr int kMaxPlanes = 10;
 struct Payload {
   Plane p[kMaxPlanes];
   int count;
@@ -48,7 +60,7 @@ struct Payload {
 // cnt: radix_count_words(n) words; group_tot: radix_group_words(n) words.
 hipError_t launch_radix_pass(const uint32_t* keys_in, const TupleSrc& ts, int key_word,
                              uint32_t* keys_out, const Payload& pay, int64_t n,
-                             const int64_t* n_dev, int shift, uint32_t* cnt, uint32_t* group_tot,
+                             const int32_t* n_dev, int shift, uint32_t* cnt, uint32_t* group_tot,
                              hipStream_t st);
 inline int64_t radix_tiles(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
 inline int64_t radix_count_words(int64_t n) { return radix_tiles(n) * kRadix; }
@@ -58,21 +70,32 @@ inline int64_t radix_group_words(int64_t n) { return (radix_tiles(n) + 63) / 64 
 // planes: n-strided planes [id, w1, ..., w_{k-1}] in the same order.  Writes
 // the kept ids to out_ids, their words w1..w_{k-1} to out_words[(d-1) *
 // out_stride + o] and the count to *nu.  cnt: radix_tiles(n) words.
-hipError_t launch_dedup(const uint32_t* w0, const uint32_t* planes, int64_t n, int k,
-                        uint32_t* out_ids, uint32_t* out_words, int64_t out_stride, uint32_t* cnt,
-                        int64_t* nu, hipStream_t st);
+hipError_t launch_dedup(const uint32_t* w0, const uint32_t* planes, const uint32_t* tree, int64_t n,
+                        int k, uint32_t* out_ids, uint32_t* out_words, int64_t out_stride,
+                        uint32_t* out_tree, uint32_t* cnt, int32_t* uoff, int num_trees,
+                        hipStream_t st);
+
+// tree[r] = b for the rows of every tree b.
+hipError_t launch_tree_ids(const int64_t* off, int num_trees, uint32_t* tree, hipStream_t st);
+
+// After duplicate removal (uoff[b] = first distinct position of tree b, or
+// INT32_MAX when the tree has none; uoff[B] = total): fixes empty trees,
+// writes n_unique[b] (may be null), the deepest global level *lmax, the
+// on-chip finish item prefix wgbase[0..B], and clears the work counter.
+hipError_t launch_forest_finish(int32_t* uoff, int num_trees, int64_t cutover, int64_t* n_unique,
+                                int32_t* lmax, int32_t* wgbase, int32_t* queue, hipStream_t st);
 
 // Scatters the record planes the chain of sorts could not fill (see
 // presort.hip).  ids1: row ids in the order of array 1.
 hipError_t launch_complete_records(uint32_t* rec, const uint32_t* ids1, int64_t n, int k,
-                                   const int64_t* nu, hipStream_t st);
+                                   const int32_t* nu, hipStream_t st);
 
 // One global partition level (depth) of every array but the split one.
 // rec0 holds the level-0 records (never overwritten); b1/b2 the moved ones.
 // Scratch: seginfo level_tiles(n) * level_seginfo_bytes() bytes, cnt
 // (k-1) * level_tiles(n) * 8 words, carry (k-1) * level_tiles(n) words.
 hipError_t launch_level(const uint32_t* rec0, uint32_t* b1, uint32_t* b2, int64_t n, int k,
-                        int depth, int64_t cutover, const int64_t* nu, int32_t* perm,
+                        int depth, int64_t cutover, const ForestArgs& fa, int32_t* perm,
                         void* seginfo, uint32_t* cnt, uint64_t* carry, hipStream_t st);
 size_t level_seginfo_bytes();
 inline int64_t level_tiles(int64_t n) { return (n + kLevelTile - 1) / kLevelTile; }
@@ -85,14 +108,15 @@ inline size_t leaf_lds_bytes(int64_t cutover, int k) {
 // On-chip finish of every subarray at the cutover depth (row ids come from
 // array 0's records).
 hipError_t launch_leaf(const uint32_t* rec0, uint32_t* b1, uint32_t* b2, int64_t n, int k,
-                       int64_t cutover, const int64_t* nu, int32_t* perm, int grid_bound_depth,
+                       int64_t cutover, const ForestArgs& fa, int32_t* perm, int64_t items_bound,
                        hipStream_t st);
 
 // k == 1: the in-order layout is the sorted unique order.
-hipError_t launch_copy_k1(const uint32_t* S0, const int64_t* nu, int64_t n, int32_t* perm,
+hipError_t launch_copy_k1(const uint32_t* S0, const ForestArgs& fa, int64_t n, int32_t* perm,
                           hipStream_t st);
 
-// Child positions from the implicit shape.
-hipError_t launch_children(const int64_t* nu, int64_t n, int32_t* lo, int32_t* hi, hipStream_t st);
+// Child positions from the implicit shape of a single tree (uoff[1] rows).
+hipError_t launch_children(const int32_t* uoff, int64_t n, int32_t* lo, int32_t* hi,
+                           hipStream_t st);
 
 }  // namespace kd

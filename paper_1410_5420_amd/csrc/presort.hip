@@ -80,7 +80,7 @@ __device__ __forceinline__ uint32_t plane_value(const Plane& pl, const TupleSrc&
 template <bool kFromTuples>
 __global__ __launch_bounds__(kOsThreads) void k_radix_count(const uint32_t* __restrict__ keys_in,
                                                            const TupleSrc ts, int key_word,
-                                                           int64_t n_host, const int64_t* n_dev,
+                                                           int64_t n_host, const int32_t* n_dev,
                                                            int shift, uint32_t* __restrict__ cnt) {
   __shared__ uint32_t s_h[kRadix];
   const int tid = threadIdx.x;
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(kRadix) void k_radix_scan_groups(uint32_t* __restri
 template <bool kFromTuples, bool kWriteKeys>
 __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const TupleSrc ts, int key_word,
-    uint32_t* __restrict__ keys_out, const Payload pay, int64_t n_host, const int64_t* n_dev,
+    uint32_t* __restrict__ keys_out, const Payload pay, int64_t n_host, const int32_t* n_dev,
     int shift, const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ group_start) {
   __shared__ uint32_t s_keys[kSortTile];
   __shared__ uint32_t s_stage[kSortTile];
@@ -278,7 +278,7 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
 
 hipError_t launch_radix_pass(const uint32_t* keys_in, const TupleSrc& ts, int key_word,
                              uint32_t* keys_out, const Payload& pay, int64_t n,
-                             const int64_t* n_dev, int shift, uint32_t* cnt, uint32_t* group_tot,
+                             const int32_t* n_dev, int shift, uint32_t* cnt, uint32_t* group_tot,
                              hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const int tiles = (int)((n + kSortTile - 1) / kSortTile);
@@ -309,19 +309,22 @@ hipError_t launch_radix_pass(const uint32_t* keys_in, const TupleSrc& ts, int ke
 // Sec. 2.1: after the sort by x:y:z:..., identical rows are contiguous; keep
 // the first of each run (the smallest row, the sort being stable).  The sorted
 // key words arrive as coalesced planes: w0 (the last sort key) and the
-// payload planes [id, w1, ..., w_{k-1}].  Three launches: per-tile counts of
-// kept rows, one scan block (which also writes the number of distinct rows),
-// then the compaction, which writes the kept ids and, for the chain of sorts,
-// their words w1..w_{k-1}.
+// payload planes [id, w1, ..., w_{k-1}], plus the tree id of every row when
+// several trees are built at once (rows are then grouped by tree, and rows of
+// different trees are never duplicates).  Three launches: per-tile counts of
+// kept rows, one scan block, then the compaction, which writes the kept ids,
+// their words w1..w_{k-1} (and tree ids) for the chain of sorts, and the
+// start of every tree in the compacted order.
 
 constexpr int kDdThreads = 512;
 constexpr int kDdItems = kSortTile / kDdThreads;
 constexpr int kDdWaves = kDdThreads / kWave;
 
 __device__ __forceinline__ bool keep_row(const uint32_t* __restrict__ w0,
-                                         const uint32_t* __restrict__ planes, int64_t n, int k,
-                                         int64_t i) {
+                                         const uint32_t* __restrict__ planes,
+                                         const uint32_t* __restrict__ tree, int n, int k, int i) {
   if (i == 0) return true;
+  if (tree && tree[i] != tree[i - 1]) return true;
   if (w0[i] != w0[i - 1]) return true;
   for (int d = 1; d < k; ++d) {
     const uint32_t* wd = planes + (int64_t)d * n;
@@ -332,16 +335,17 @@ __device__ __forceinline__ bool keep_row(const uint32_t* __restrict__ w0,
 
 __global__ __launch_bounds__(kDdThreads) void k_dedup_count(const uint32_t* __restrict__ w0,
                                                            const uint32_t* __restrict__ planes,
-                                                           int64_t n, int k,
+                                                           const uint32_t* __restrict__ tree,
+                                                           int n, int k,
                                                            uint32_t* __restrict__ cnt) {
   __shared__ uint32_t s_part[kDdWaves];
   const int tid = threadIdx.x;
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  const int base = blockIdx.x * kSortTile;
   uint32_t c = 0;
 #pragma unroll
   for (int j = 0; j < kDdItems; ++j) {
-    const int64_t i = base + j * kDdThreads + tid;
-    if (i < n && keep_row(w0, planes, n, k, i)) ++c;
+    const int i = base + j * kDdThreads + tid;
+    if (i < n && keep_row(w0, planes, tree, n, k, i)) ++c;
   }
   c = wave_inclusive_sum(c);
   if (lane_id() == kWave - 1) s_part[tid / kWave] = c;
@@ -353,9 +357,10 @@ __global__ __launch_bounds__(kDdThreads) void k_dedup_count(const uint32_t* __re
   }
 }
 
-// One block: exclusive scan of the per-tile counts; writes the total to *nu.
+// One block: exclusive scan of the per-tile counts; the total goes to
+// uoff[B] (the number of distinct rows over all trees).
 __global__ __launch_bounds__(1024) void k_scan_counts(uint32_t* __restrict__ cnt, int tiles,
-                                                     int64_t* nu) {
+                                                     int32_t* total) {
   __shared__ uint32_t s_tmp[1024 / kWave + 1];
   __shared__ uint32_t s_carry;
   const int tid = threadIdx.x;
@@ -372,27 +377,25 @@ __global__ __launch_bounds__(1024) void k_scan_counts(uint32_t* __restrict__ cnt
     if (tid == 0) s_carry = carry + all;
     __syncthreads();
   }
-  if (tid == 0) *nu = (int64_t)s_carry;
+  if (tid == 0) *total = (int32_t)s_carry;
 }
 
-__global__ __launch_bounds__(kDdThreads) void k_dedup_write(const uint32_t* __restrict__ w0,
-                                                           const uint32_t* __restrict__ planes,
-                                                           int64_t n, int k,
-                                                           const uint32_t* __restrict__ cnt,
-                                                           uint32_t* __restrict__ out_ids,
-                                                           uint32_t* __restrict__ out_words,
-                                                           int64_t out_stride) {
+__global__ __launch_bounds__(kDdThreads) void k_dedup_write(
+    const uint32_t* __restrict__ w0, const uint32_t* __restrict__ planes,
+    const uint32_t* __restrict__ tree, int n, int k, const uint32_t* __restrict__ cnt,
+    uint32_t* __restrict__ out_ids, uint32_t* __restrict__ out_words, int64_t out_stride,
+    uint32_t* __restrict__ out_tree, int32_t* __restrict__ uoff) {
   __shared__ uint32_t s_chunk[kDdItems * kDdWaves];
   const int tid = threadIdx.x;
   const int wv = tid / kWave;
   const int lane = tid % kWave;
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  const int base = blockIdx.x * kSortTile;
   if (base >= n) return;
   uint32_t keep[kDdItems], within[kDdItems];
 #pragma unroll
   for (int j = 0; j < kDdItems; ++j) {
-    const int64_t i = base + j * kDdThreads + tid;
-    keep[j] = (i < n && keep_row(w0, planes, n, k, i)) ? 1u : 0u;
+    const int i = base + j * kDdThreads + tid;
+    keep[j] = (i < n && keep_row(w0, planes, tree, n, k, i)) ? 1u : 0u;
     const uint32_t inc = wave_inclusive_sum(keep[j]);
     within[j] = inc - keep[j];
     if (lane == kWave - 1) s_chunk[j * kDdWaves + wv] = inc;
@@ -407,23 +410,130 @@ __global__ __launch_bounds__(kDdThreads) void k_dedup_write(const uint32_t* __re
   const uint32_t gb = cnt[blockIdx.x];
 #pragma unroll
   for (int j = 0; j < kDdItems; ++j) {
-    const int64_t i = base + j * kDdThreads + tid;
-    const int64_t o = (int64_t)gb + s_chunk[j * kDdWaves + wv] + within[j];
+    const int i = base + j * kDdThreads + tid;
+    const int o = (int)(gb + s_chunk[j * kDdWaves + wv] + within[j]);
     if (!keep[j] || o >= n) continue;
     out_ids[o] = planes[i];
     for (int d = 1; d < k; ++d) out_words[(d - 1) * out_stride + o] = planes[(int64_t)d * n + i];
+    if (tree) {
+      const uint32_t b = tree[i];
+      out_tree[o] = b;
+      if (i == 0 || tree[i - 1] != b) uoff[b] = o;  // first distinct row of tree b
+    } else if (i == 0) {
+      uoff[0] = 0;
+    }
   }
 }
 
-hipError_t launch_dedup(const uint32_t* w0, const uint32_t* planes, int64_t n, int k,
-                        uint32_t* out_ids, uint32_t* out_words, int64_t out_stride, uint32_t* cnt,
-                        int64_t* nu, hipStream_t st) {
+hipError_t launch_dedup(const uint32_t* w0, const uint32_t* planes, const uint32_t* tree, int64_t n,
+                        int k, uint32_t* out_ids, uint32_t* out_words, int64_t out_stride,
+                        uint32_t* out_tree, uint32_t* cnt, int32_t* uoff, int num_trees,
+                        hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const int tiles = (int)((n + kSortTile - 1) / kSortTile);
-  hipLaunchKernelGGL(k_dedup_count, dim3(tiles), dim3(kDdThreads), 0, st, w0, planes, n, k, cnt);
-  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, cnt, tiles, nu);
-  hipLaunchKernelGGL(k_dedup_write, dim3(tiles), dim3(kDdThreads), 0, st, w0, planes, n, k, cnt,
-                     out_ids, out_words, out_stride);
+  hipLaunchKernelGGL(k_dedup_count, dim3(tiles), dim3(kDdThreads), 0, st, w0, planes, tree, (int)n,
+                     k, cnt);
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, cnt, tiles, uoff + num_trees);
+  hipLaunchKernelGGL(k_dedup_write, dim3(tiles), dim3(kDdThreads), 0, st, w0, planes, tree, (int)n,
+                     k, cnt, out_ids, out_words, out_stride, out_tree, uoff);
+  return hipGetLastError();
+}
+
+// ---- forest bookkeeping ----------------------------------------------------------
+
+// tree[r] = b for every row r of tree b (rows of tree b: off[b] .. off[b+1]-1).
+__global__ __launch_bounds__(256) void k_tree_ids(const int64_t* __restrict__ off,
+                                                 uint32_t* __restrict__ tree) {
+  const int b = blockIdx.x;
+  const int64_t s = off[b], e = off[b + 1];
+  for (int64_t r = s + threadIdx.x; r < e; r += blockDim.x) tree[r] = (uint32_t)b;
+}
+
+hipError_t launch_tree_ids(const int64_t* off, int num_trees, uint32_t* tree, hipStream_t st) {
+  if (num_trees <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tree_ids, dim3(num_trees), dim3(256), 0, st, off, tree);
+  return hipGetLastError();
+}
+
+// After duplicate removal: trees with no rows start where the next tree
+// starts; per-tree distinct counts go to n_unique[b]; lmax = deepest global
+// level any tree needs; wgbase[b] = exclusive prefix of the on-chip finish
+// items (2^(cutover depth)) of the trees, wgbase[B] their total.
+__global__ __launch_bounds__(1024) void k_forest_finish(int32_t* __restrict__ uoff, int B,
+                                                       int64_t cutover, int64_t* n_unique,
+                                                       int32_t* lmax, int32_t* wgbase,
+                                                       int32_t* queue) {
+  __shared__ int32_t s_rmin[1024];
+  __shared__ uint32_t s_tmp[1024 / kWave + 1];
+  __shared__ int32_t s_lmax[1024 / kWave];
+  __shared__ uint32_t s_carry;
+  const int tid = threadIdx.x;
+  // Empty trees (still marked INT32_MAX) start where the next tree starts:
+  // every start becomes the minimum over itself and all later trees (starts of
+  // non-empty trees increase with the tree index).  Thread t owns a range of
+  // `per` trees: local suffix minima, then one thread chains the ranges.
+  const int per = (B + 1023) / 1024;
+  const int r0 = tid * per, r1 = min(B, r0 + per);
+  int32_t m = INT32_MAX;
+  for (int b = r1 - 1; b >= r0; --b) m = min(m, uoff[b]);
+  s_rmin[tid] = m;
+  __syncthreads();
+  if (tid == 0) {
+    int32_t run = uoff[B];
+    for (int q = 1023; q >= 0; --q) {
+      const int32_t here = min(s_rmin[q], run);
+      s_rmin[q] = run;  // minimum over all trees after range q
+      run = here;
+    }
+  }
+  __syncthreads();
+  {
+    int32_t run = s_rmin[tid];
+    for (int b = r1 - 1; b >= r0; --b) {
+      run = min(run, uoff[b]);
+      uoff[b] = run;
+    }
+  }
+  __syncthreads();
+  int32_t lm = 0;
+  if (tid == 0) s_carry = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < B; c0 += 1024) {
+    const int b = c0 + tid;
+    uint32_t items = 0;
+    if (b < B) {
+      const int32_t nb = uoff[b + 1] - uoff[b];
+      if (n_unique) n_unique[b] = nb;
+      const int lc = cutover_depth(nb, cutover);
+      lm = max(lm, lc);
+      items = nb > 0 ? (1u << lc) : 0u;
+    }
+    uint32_t all;
+    const uint32_t ex = block_exclusive_sum<1024>(items, s_tmp, &all);
+    const uint32_t carry = s_carry;
+    if (b < B) wgbase[b] = (int32_t)(carry + ex);
+    __syncthreads();
+    if (tid == 0) s_carry = carry + all;
+    __syncthreads();
+  }
+  // block max of the deepest level
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) lm = max(lm, __shfl_xor(lm, d, kWave));
+  if (lane_id() == 0) s_lmax[tid / kWave] = lm;
+  __syncthreads();
+  if (tid == 0) {
+    int32_t m = 0;
+    for (int q = 0; q < 1024 / kWave; ++q) m = max(m, s_lmax[q]);
+    *lmax = m;
+    wgbase[B] = (int32_t)s_carry;
+    *queue = 0;
+  }
+}
+
+hipError_t launch_forest_finish(int32_t* uoff, int num_trees, int64_t cutover, int64_t* n_unique,
+                                int32_t* lmax, int32_t* wgbase, int32_t* queue, hipStream_t st) {
+  hipLaunchKernelGGL(k_forest_finish, dim3(1), dim3(1024), 0, st, uoff, num_trees, cutover,
+                     n_unique, lmax, wgbase, queue);
   return hipGetLastError();
 }
 
@@ -443,8 +553,8 @@ hipError_t launch_dedup(const uint32_t* w0, const uint32_t* planes, int64_t n, i
 
 __global__ __launch_bounds__(256) void k_complete_records(uint32_t* __restrict__ rec,
                                                          const uint32_t* __restrict__ ids1,
-                                                         int64_t n, int k, const int64_t* nu_ptr) {
-  const int64_t nu = *nu_ptr;
+                                                         int64_t n, int k, const int32_t* total) {
+  const int64_t nu = *total;
   const int R = k - 1;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nu;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -463,7 +573,7 @@ __global__ __launch_bounds__(256) void k_complete_records(uint32_t* __restrict__
 }
 
 hipError_t launch_complete_records(uint32_t* rec, const uint32_t* ids1, int64_t n, int k,
-                                   const int64_t* nu, hipStream_t st) {
+                                   const int32_t* nu, hipStream_t st) {
   if (n <= 0 || k < 2) return hipSuccess;
   int64_t blocks = (n + 255) / 256;
   if (blocks > 8192) blocks = 8192;

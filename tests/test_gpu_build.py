@@ -150,3 +150,56 @@ def test_full_size_c2_bit_exact(kd):
     perm, nu = run_gpu(kd, t, children=False)
     assert nu == want["n_unique"]
     assert np.array_equal(perm, want["perm"])
+
+
+# ---- batched form ---------------------------------------------------------------
+
+def assert_batched_same(kd, t, offsets, cutover=None):
+    print(f"[gpu case] batched trees={len(offsets) - 1} rows={offsets[-1]} k={t.shape[1]} "
+          f"dtype={t.dtype} cutover={cutover}", flush=True)
+    perm, nu = kd.build_batched(torch.from_numpy(np.ascontiguousarray(t)).cuda(), offsets,
+                                cutover=cutover)
+    torch.cuda.synchronize()
+    perm = perm.cpu().numpy()
+    nu = nu.cpu().numpy()
+    for b in range(len(offsets) - 1):
+        s, e = int(offsets[b]), int(offsets[b + 1])
+        want = oracle.build_tree(t[s:e], children=False) if e > s else {"n_unique": 0, "perm": []}
+        assert nu[b] == want["n_unique"], f"tree {b}: n_unique"
+        assert np.array_equal(perm[s:s + nu[b]], want["perm"]), f"tree {b}: perm"
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_batched_mixed_sizes(kd, k):
+    g = kdgen.rng(50 + k)
+    sizes = [0, 1, 2, 3, 5, 64, 1000, 1023, 1024, 1025, 3000, 0, 5000, 17, 20000]
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    t = g.integers(-20, 20, size=(int(offsets[-1]), k)).astype(np.int32)
+    assert_batched_same(kd, t, offsets)
+
+
+@pytest.mark.parametrize("cutover", [1024, 2048, 4096])
+def test_batched_point_clouds(kd, cutover):
+    t, offsets = kdgen.c4_batched(trees=96, lo=64, hi=65536, seed=77)
+    assert_batched_same(kd, t, offsets, cutover=cutover)
+
+
+def test_batched_single_tree_equals_plain(kd):
+    t = kdgen.uniform_int(50000, 3, 0, 1000, 0.05, 8)
+    assert_batched_same(kd, t, np.array([0, 50000], dtype=np.int64))
+
+
+def test_batched_c4_workload_sampled(kd):
+    """The batched workload (4096 point-cloud trees, log-uniform 64..65536 rows,
+    float32) in the benchmark's configuration; every 64th tree is compared."""
+    t, offsets = kdgen.c4_batched()
+    print(f"[gpu case] c4 batched rows={offsets[-1]}", flush=True)
+    perm, nu = kd.build_batched(torch.from_numpy(t).cuda(), offsets)
+    torch.cuda.synchronize()
+    perm = perm.cpu().numpy()
+    nu = nu.cpu().numpy()
+    for b in range(0, len(offsets) - 1, 64):
+        s, e = int(offsets[b]), int(offsets[b + 1])
+        want = oracle.build_tree(t[s:e], children=False)
+        assert nu[b] == want["n_unique"]
+        assert np.array_equal(perm[s:s + nu[b]], want["perm"])
