@@ -418,8 +418,10 @@ __global__ __launch_bounds__(kLvThreads) void k_level_move(const RecBufs B, cons
   const int nu = F.uoff[F.B];
   if (depth >= *F.lmax) return;
   const int p = depth % k;
-  const int a = blockIdx.x / tiles_per_array;
-  const int t = blockIdx.x % tiles_per_array;
+  const int bt = xcd_tile(blockIdx.x, gridDim.x);
+  const int a = bt / tiles_per_array;
+  const int t = bt % tiles_per_array;
+  if (a >= k - 1) return;
   const int j = (p + 1 + a) % k;
   const int t0 = t * kLevelTile;
   if (t0 >= nu) return;
@@ -456,7 +458,8 @@ hipError_t launch_level(const uint32_t* rec0, uint32_t* b1, uint32_t* b2, int64_
   hipLaunchKernelGGL(k_level_scan, dim3(k - 1), dim3(1024), 0, st, F, depth, si, cnt, carry,
                      tiles);
 #define KD_LV(RR)                                                                               \
-  hipLaunchKernelGGL(k_level_move<RR>, dim3(grid), dim3(kLvThreads), 0, st, B, F, n, k, depth,  \
+  hipLaunchKernelGGL(k_level_move<RR>, dim3(xcd_grid(grid)), dim3(kLvThreads), 0, st, B, F, n, \
+                     k, depth,                                                                   \
                      si, carry, tiles)
   switch (k - 1) {
     case 1: KD_LV(1); break;

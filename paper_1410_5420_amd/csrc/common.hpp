@@ -59,6 +59,20 @@ __device__ __forceinline__ T block_exclusive_sum(T v, T* s_tmp, T* total) {
   return res;
 }
 
+// ---- XCD-aware tile order ------------------------------------------------------
+// Workgroups are handed to the 8 XCDs round-robin (workgroup b runs on XCD
+// b mod 8), and each XCD has its own L2.  For a launch of `grid` workgroups
+// (a multiple of 8) this bijection gives XCD x the contiguous tile range
+// [x * grid/8, (x+1) * grid/8), walked in dispatch order, so partial cache
+// lines written by neighbouring tiles meet in the same L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile(int b, int grid) {
+  return (b % kXcds) * (grid / kXcds) + b / kXcds;
+}
+__host__ __device__ __forceinline__ int xcd_grid(int tiles) {
+  return (tiles + kXcds - 1) / kXcds * kXcds;
+}
+
 // ---- implicit shape of the balanced tree --------------------------------------
 // The node of [s, e] sits at its lower median; its children cover [s, m-1] and
 // [m+1, e].  At depth L the largest subarray holds floor(n / 2^L) elements.

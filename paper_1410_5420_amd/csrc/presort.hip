@@ -123,19 +123,55 @@ __global__ __launch_bounds__(kRadix) void k_radix_scan_tiles(uint32_t* __restric
 }
 
 // Second level: one block turns group totals into group starts that already
-// include every digit's global start.
-__global__ __launch_bounds__(kRadix) void k_radix_scan_groups(uint32_t* __restrict__ group_tot,
-                                                             int groups) {
-  __shared__ uint32_t s_tmp[kRadix / kWave + 1];
-  const int d = threadIdx.x;
-  uint32_t total = 0;
-  for (int g = 0; g < groups; ++g) total += group_tot[(int64_t)g * kRadix + d];
+// include every digit's global start.  Four threads per digit each take a
+// quarter of the groups, with their loads batched.
+constexpr int kSgSub = 4;
+constexpr int kSgBatch = 16;
+__global__ __launch_bounds__(kRadix * kSgSub) void k_radix_scan_groups(
+    uint32_t* __restrict__ group_tot, int groups) {
+  __shared__ uint32_t s_part[kSgSub][kRadix];
+  __shared__ uint32_t s_tmp[kRadix * kSgSub / kWave + 1];
+  const int d = threadIdx.x % kRadix;
+  const int sub = threadIdx.x / kRadix;
+  const int per = (groups + kSgSub - 1) / kSgSub;
+  const int g0 = sub * per, g1 = min(groups, g0 + per);
+  uint32_t sum = 0;
+  for (int g = g0; g < g1; g += kSgBatch) {
+    uint32_t c[kSgBatch];
+#pragma unroll
+    for (int q = 0; q < kSgBatch; ++q)
+      c[q] = g + q < g1 ? group_tot[(int64_t)(g + q) * kRadix + d] : 0u;
+#pragma unroll
+    for (int q = 0; q < kSgBatch; ++q) sum += c[q];
+  }
+  s_part[sub][d] = sum;
+  __syncthreads();
+  uint32_t digit_total = 0;
+  if (sub == 0)
+    for (int q = 0; q < kSgSub; ++q) digit_total += s_part[q][d];
   uint32_t all;
-  uint32_t run = block_exclusive_sum<kRadix>(total, s_tmp, &all);
-  for (int g = 0; g < groups; ++g) {
-    const uint32_t c = group_tot[(int64_t)g * kRadix + d];
-    group_tot[(int64_t)g * kRadix + d] = run;
-    run += c;
+  const uint32_t digit_start = block_exclusive_sum<kRadix * kSgSub>(digit_total, s_tmp, &all);
+  __syncthreads();
+  if (sub == 0) {
+    uint32_t run = digit_start;
+    for (int q = 0; q < kSgSub; ++q) {
+      const uint32_t c = s_part[q][d];
+      s_part[q][d] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  uint32_t run = s_part[sub][d];
+  for (int g = g0; g < g1; g += kSgBatch) {
+    uint32_t c[kSgBatch];
+#pragma unroll
+    for (int q = 0; q < kSgBatch; ++q)
+      c[q] = g + q < g1 ? group_tot[(int64_t)(g + q) * kRadix + d] : 0u;
+#pragma unroll
+    for (int q = 0; q < kSgBatch; ++q) {
+      if (g + q < g1) group_tot[(int64_t)(g + q) * kRadix + d] = run;
+      run += c[q];
+    }
   }
 }
 
@@ -155,7 +191,7 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
   const int w = tid / kWave;
   const int lane = tid % kWave;
   const int n = (int)(n_dev ? *n_dev : n_host);
-  const int tile = blockIdx.x;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int base = tile * kSortTile;
   if (base >= n) return;
   for (int q = tid; q < kOsWaves * kRadix; q += kOsThreads) (&s_wcnt[0][0])[q] = 0;
@@ -291,9 +327,9 @@ hipError_t launch_radix_pass(const uint32_t* keys_in, const TupleSrc& ts, int ke
     hipLaunchKernelGGL(k_radix_count<false>, dim3(tiles), dim3(kOsThreads), 0, st, keys_in, ts,
                        key_word, n, n_dev, shift, cnt);
   hipLaunchKernelGGL(k_radix_scan_tiles, dim3(groups), dim3(kRadix), 0, st, cnt, group_tot, tiles);
-  hipLaunchKernelGGL(k_radix_scan_groups, dim3(1), dim3(kRadix), 0, st, group_tot, groups);
+  hipLaunchKernelGGL(k_radix_scan_groups, dim3(1), dim3(kRadix * kSgSub), 0, st, group_tot, groups);
 #define KD_RS(FT, WK)                                                                           \
-  hipLaunchKernelGGL((k_radix_scatter<FT, WK>), dim3(tiles), dim3(kOsThreads), 0, st, keys_in, \
+  hipLaunchKernelGGL((k_radix_scatter<FT, WK>), dim3(xcd_grid(tiles)), dim3(kOsThreads), 0, st, keys_in, \
                      ts, key_word, keys_out, pay, n, n_dev, shift, cnt, group_tot)
   const bool wk = keys_out != nullptr;
   if (ft) {
