@@ -120,6 +120,84 @@ int kdtree_build_batched(const void* d_tuples, const int64_t* d_offsets, const i
                          int64_t* d_n_unique, void* d_workspace, size_t workspace_bytes,
                          const kd_options* opts, void* stream);
 
+/* ---- learned presort ---------------------------------------------------------
+ * Not in the paper: a faster route to the same presorted arrays (Sec. 2.1).
+ * Each sort sends a key straight to one of 2^b buckets through a learned
+ * model of the key's cumulative distribution, orders the buckets with one or
+ * two stable radix passes on the bucket number, and finishes each bucket in
+ * LDS.  Because the model is monotone the result equals the radix presort bit
+ * for bit; a bucket larger than the on-chip capacity, or an output that fails
+ * the strict-order certificate, makes that sort fall back to the radix sort
+ * on the device (no host synchronisation).  The tree is therefore always
+ * exactly the tree kdtree_build produces.
+ *
+ * Model: per dimension, a piecewise-linear CDF over KD_CDF_SEGMENTS equal
+ * segments of the sample's finite value range, whose segment masses are the
+ * softmax of trainable logits.  kd_cdf_train() fits them on the GPU: it takes
+ * a strided sample of n_samples rows (row floor(s * n / n_samples)), presorts
+ * each dimension's sample with the radix passes, reads the mass of every
+ * segment off the sample's ranks, and runs `steps` Adam steps (beta1 0.9,
+ * beta2 0.999, eps 1e-8, step size lr) from all-zero logits on the
+ * cross-entropy between the model's masses and the sample's.  A model buffer
+ * holds k consecutive records of KD_CDF_MODEL_BYTES bytes:
+ *   float lo, hi, scale; uint32 kmin, kmax; int32 is_float, segments;
+ *   float loss; float c[KD_CDF_SEGMENTS + 1]; float theta[KD_CDF_SEGMENTS];
+ *   padding.
+ * c[i] is the cumulative distribution at the start of segment i (c[0] = 0,
+ * c[K] = 1, non-decreasing); kmin / kmax are the order-preserving keys of lo
+ * and hi.  A model trained on one data set may be reused for others of the
+ * same dtype: a poor model costs speed (fallbacks), never correctness.      */
+#define KD_CDF_SEGMENTS 1024
+#define KD_CDF_MODEL_BYTES 8448
+#define KD_CDF_MAX_SAMPLES (1 << 20)
+#define KD_CDF_MAX_STEPS 100000
+
+/* Bytes of a model buffer for k dimensions (host only). */
+int kd_cdf_model_bytes(int32_t k, size_t* h_bytes);
+/* Workspace bytes of kd_cdf_train (host only). */
+int kd_cdf_train_workspace_bytes(int32_t k, int32_t n_samples, size_t* h_bytes);
+/* Train one model per dimension on d_tuples (n >= 1 rows).  Asynchronous on
+ * `stream`; writes d_models (kd_cdf_model_bytes(k) bytes, 4-byte aligned).
+ * 1 <= n_samples <= KD_CDF_MAX_SAMPLES, 0 <= steps <= KD_CDF_MAX_STEPS,
+ * lr > 0. */
+int kd_cdf_train(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, int32_t n_samples,
+                 int32_t steps, float lr, void* d_models, void* d_workspace,
+                 size_t workspace_bytes, void* stream);
+/* The training objective for given logits, for checking: d_values holds m
+ * coordinates of `dtype` sorted ascending in the order above; lo_bits /
+ * hi_bits are the raw bits of the range ends.  Writes the cross-entropy to
+ * *d_loss and its gradient with respect to the K logits d_theta to d_grad
+ * (K floats).  d_scratch: m words.  1 <= m <= KD_CDF_MAX_SAMPLES. */
+int kd_cdf_loss_grad(const void* d_values, int32_t m, int32_t dtype, uint32_t lo_bits,
+                     uint32_t hi_bits, const float* d_theta, float* d_loss, float* d_grad,
+                     void* d_scratch, void* stream);
+/* Evaluate one dimension's model (d_model points at its record) on m raw
+ * coordinates of the model's dtype: d_F[i] = F(value i), d_bucket[i] its
+ * bucket among 2^nb_bits (1 <= nb_bits <= 16). */
+int kd_cdf_eval(const void* d_model, const void* d_values, int32_t m, int32_t nb_bits, float* d_F,
+                int32_t* d_bucket, void* stream);
+
+/* Workspace bytes of a learned build (host only). */
+int kdtree_workspace_bytes_learned(int64_t n, int32_t k, int32_t dtype, size_t* h_bytes);
+/* Build with the learned presort: arguments as kdtree_build, plus
+ *   d_models     k model records (kd_cdf_train)
+ *   d_fell_back  int32[k] device, or NULL: entry d receives 0 when the sort
+ *                for super key d used the learned path, else a non-zero
+ *                reason (1: a bucket exceeded the on-chip capacity, 2: the
+ *                certificate failed, 4: inconsistent bucket bounds)
+ *   d_workspace  >= kdtree_workspace_bytes_learned(n, k, dtype)
+ * The output equals kdtree_build's. */
+int kdtree_build_learned(const void* d_tuples, int64_t n, int32_t k, int32_t dtype,
+                         const void* d_models, int32_t* d_perm, int32_t* d_lo, int32_t* d_hi,
+                         int64_t* d_n_unique, int32_t* d_fell_back, void* d_workspace,
+                         size_t workspace_bytes, const kd_options* opts, void* stream);
+/* Presort half of kdtree_build_learned (for phase timing); follow it with
+ * kdtree_partition on the same workspace. */
+int kdtree_presort_learned(const void* d_tuples, int64_t n, int32_t k, int32_t dtype,
+                           const void* d_models, int64_t* d_n_unique, int32_t* d_fell_back,
+                           void* d_workspace, size_t workspace_bytes, const kd_options* opts,
+                           void* stream);
+
 /* ---- diagnostics ------------------------------------------------------------
  * Kernel probe for measurement tools.  kd_probe_start() makes the library
  * record a HIP event pair around every launch of one kernel class (on the
@@ -136,7 +214,8 @@ enum kd_kernel_class {
   KD_K_DEDUP = 4,    /* duplicate removal */
   KD_K_HIST = 5,     /* digit histograms */
   KD_K_CANON = 6,    /* key canonicalisation */
-  KD_K_RECORDS = 7   /* rank tables and level-0 records */
+  KD_K_RECORDS = 7,  /* rank tables and level-0 records */
+  KD_K_BUCKET = 8    /* learned presort: per-bucket finish */
 };
 int kd_probe_start(int32_t kernel_class, int32_t capacity);
 int kd_probe_stop(float* h_ms, int32_t* h_count);

@@ -110,8 +110,13 @@ def gaussian_mixture_f32(n: int, k: int, components: int, seed: int, log_sigma: 
     for s in range(0, n, chunk):
         e = min(n, s + chunk)
         w = which[s:e]
-        z = g.normal(size=(e - s, k)) * scales[w]
-        out[s:e] = (np.einsum("nij,nj->ni", rots[w], z) + means[w]).astype(np.float32)
+        z = g.standard_normal(size=(e - s, k), dtype=np.float32) * scales.astype(np.float32)[w]
+        r32 = rots.astype(np.float32)
+        for i in range(k):
+            acc = means.astype(np.float32)[w, i]
+            for j in range(k):
+                acc += r32[:, i, j][w] * z[:, j]
+            out[s:e, i] = acc
     return out
 
 

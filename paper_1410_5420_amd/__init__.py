@@ -17,7 +17,8 @@ import torch
 from . import _lib
 from ._lib import KD_F32, KD_I32, KdError  # noqa: F401
 
-__all__ = ["Builder", "BatchedBuilder", "build", "build_batched", "KdError"]
+__all__ = ["Builder", "BatchedBuilder", "LearnedBuilder", "build", "build_batched", "build_learned",
+           "train_cdf", "cdf_loss_grad", "cdf_eval", "KdError"]
 
 
 def _dtype_code(t: torch.Tensor) -> int:
@@ -148,3 +149,122 @@ def build(tuples: torch.Tensor, children: bool = False, cutover: int | None = No
     if children:
         return perm[:nu], nu, lo[:nu], hi[:nu]
     return perm[:nu], nu
+
+
+# ---- learned presort ------------------------------------------------------------
+
+def train_cdf(tuples: torch.Tensor, n_samples: int = 1 << 16, steps: int = 300, lr: float = 0.1,
+              stream=None) -> torch.Tensor:
+    """Train one CDF model per dimension on the GPU (kd_cdf_train).
+
+    Returns the model buffer (uint8 device tensor of k * 8448 bytes)."""
+    if tuples.dim() != 2 or not tuples.is_cuda or not tuples.is_contiguous():
+        raise ValueError("tuples must be a contiguous (n, k) device tensor")
+    n, k = tuples.shape
+    code = _dtype_code(tuples)
+    models = torch.zeros(_lib.cdf_model_bytes(k), dtype=torch.uint8, device=tuples.device)
+    ws = torch.empty(_lib.cdf_train_workspace_bytes(k, n_samples), dtype=torch.uint8,
+                     device=tuples.device)
+    rc = _lib.lib.kd_cdf_train(_ptr(tuples), n, k, code, n_samples, steps, float(lr), _ptr(models),
+                               _ptr(ws), ws.numel(), _stream(stream))
+    _lib.check(rc, "kd_cdf_train")
+    return models
+
+
+def model_record(models: torch.Tensor, d: int) -> dict:
+    """Fields of dimension d's model record (copies to the host)."""
+    import numpy as np
+
+    raw = models.view(-1)[d * _lib.CDF_MODEL_BYTES:(d + 1) * _lib.CDF_MODEL_BYTES].cpu().numpy()
+    f = raw.view(np.float32)
+    u = raw.view(np.uint32)
+    i = raw.view(np.int32)
+    K = _lib.CDF_SEGMENTS
+    return {"lo": float(f[0]), "hi": float(f[1]), "scale": float(f[2]), "kmin": int(u[3]),
+            "kmax": int(u[4]), "is_float": int(i[5]), "segments": int(i[6]), "loss": float(f[7]),
+            "c": f[8:8 + K + 1].copy(), "theta": f[8 + K + 1:8 + 2 * K + 1].copy()}
+
+
+def cdf_loss_grad(values_sorted: torch.Tensor, lo_bits: int, hi_bits: int, theta: torch.Tensor,
+                  stream=None):
+    """Training objective and its gradient for logits ``theta`` (kd_cdf_loss_grad)."""
+    m = values_sorted.numel()
+    code = _dtype_code(values_sorted)
+    dev = values_sorted.device
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    grad = torch.zeros(_lib.CDF_SEGMENTS, dtype=torch.float32, device=dev)
+    scratch = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+    rc = _lib.lib.kd_cdf_loss_grad(_ptr(values_sorted.contiguous()), m, code, lo_bits & 0xFFFFFFFF,
+                                   hi_bits & 0xFFFFFFFF, _ptr(theta.contiguous()), _ptr(loss),
+                                   _ptr(grad), _ptr(scratch), _stream(stream))
+    _lib.check(rc, "kd_cdf_loss_grad")
+    return loss, grad
+
+
+def cdf_eval(models: torch.Tensor, d: int, values: torch.Tensor, nb_bits: int, stream=None):
+    """(F, bucket) of ``values`` under dimension d's model (kd_cdf_eval)."""
+    m = values.numel()
+    F = torch.zeros(max(m, 1), dtype=torch.float32, device=values.device)
+    bucket = torch.zeros(max(m, 1), dtype=torch.int32, device=values.device)
+    rec = ctypes.c_void_p(models.data_ptr() + d * _lib.CDF_MODEL_BYTES)
+    rc = _lib.lib.kd_cdf_eval(rec, _ptr(values.contiguous()), m, nb_bits, _ptr(F), _ptr(bucket),
+                              _stream(stream))
+    _lib.check(rc, "kd_cdf_eval")
+    return F[:m], bucket[:m]
+
+
+class LearnedBuilder(Builder):
+    """Builder whose presort goes through learned CDF buckets (same output as
+    :class:`Builder`).  ``fell_back`` (int32[k] device) reports, per sort,
+    whether it had to fall back to the radix passes."""
+
+    def __init__(self, n: int, k: int, dtype=torch.int32, device="cuda", cutover: int | None = None):
+        self.n, self.k = int(n), int(k)
+        self.code = _dtype_code(torch.empty(0, dtype=dtype))
+        self.device = torch.device(device)
+        self.cutover = cutover
+        nbytes = _lib.workspace_bytes_learned(self.n, self.k, self.code)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.n_unique = torch.zeros(1, dtype=torch.int64, device=self.device)
+        self.fell_back = torch.zeros(self.k, dtype=torch.int32, device=self.device)
+
+    def build(self, tuples: torch.Tensor, perm: torch.Tensor, lo=None, hi=None, stream=None,
+              models: torch.Tensor | None = None):
+        self._check_input(tuples)
+        if models is None:
+            raise ValueError("a learned build needs the models from train_cdf()")
+        rc = _lib.lib.kdtree_build_learned(_ptr(tuples), tuples.shape[0], self.k, self.code, _ptr(models),
+                                           _ptr(perm), _ptr(lo), _ptr(hi), _ptr(self.n_unique),
+                                           _ptr(self.fell_back), _ptr(self.workspace),
+                                           self.workspace.numel(), _lib.options(self.cutover),
+                                           _stream(stream))
+        _lib.check(rc, "kdtree_build_learned")
+
+    def presort(self, tuples: torch.Tensor, stream=None, models: torch.Tensor | None = None):
+        self._check_input(tuples)
+        if models is None:
+            raise ValueError("a learned presort needs the models from train_cdf()")
+        rc = _lib.lib.kdtree_presort_learned(_ptr(tuples), tuples.shape[0], self.k, self.code,
+                                             _ptr(models), _ptr(self.n_unique), _ptr(self.fell_back),
+                                             _ptr(self.workspace), self.workspace.numel(),
+                                             _lib.options(self.cutover), _stream(stream))
+        _lib.check(rc, "kdtree_presort_learned")
+
+
+def build_learned(tuples: torch.Tensor, models: torch.Tensor, children: bool = False,
+                  cutover: int | None = None, stream=None):
+    """Like :func:`build`, through the learned presort.  Returns ``(perm,
+    n_unique, fell_back)`` or ``(perm, n_unique, fell_back, lo, hi)``."""
+    n, k = tuples.shape
+    b = LearnedBuilder(max(n, 1), k, tuples.dtype, tuples.device, cutover)
+    perm = torch.full((max(n, 1),), -1, dtype=torch.int32, device=tuples.device)
+    lo = hi = None
+    if children:
+        lo = torch.full_like(perm, -2)
+        hi = torch.full_like(perm, -2)
+    b.build(tuples.contiguous(), perm, lo, hi, stream, models=models)
+    nu = int(b.n_unique.item())
+    fb = b.fell_back.cpu()
+    if children:
+        return perm[:nu], nu, fb, lo[:nu], hi[:nu]
+    return perm[:nu], nu, fb

@@ -10,11 +10,13 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libkdtree.so")
-SOURCES = ["presort.hip", "build.hip", "api.cpp"]
+SOURCES = ["presort.hip", "build.hip", "learned.hip", "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
+    # contraction stays on except where a function switches it off by pragma
+    "-ffp-contract=fast-honor-pragmas",
     # keep the compiler away from packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),

@@ -47,6 +47,23 @@ def _load():
     lib.kdtree_workspace_bytes_batched.restype = ctypes.c_int
     lib.kdtree_build_batched.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp, sz, opt, vp]
     lib.kdtree_build_batched.restype = ctypes.c_int
+    u32, fp = ctypes.c_uint32, ctypes.c_float
+    lib.kd_cdf_model_bytes.argtypes = [i32, ctypes.POINTER(sz)]
+    lib.kd_cdf_model_bytes.restype = ctypes.c_int
+    lib.kd_cdf_train_workspace_bytes.argtypes = [i32, i32, ctypes.POINTER(sz)]
+    lib.kd_cdf_train_workspace_bytes.restype = ctypes.c_int
+    lib.kd_cdf_train.argtypes = [vp, i64, i32, i32, i32, i32, fp, vp, vp, sz, vp]
+    lib.kd_cdf_train.restype = ctypes.c_int
+    lib.kd_cdf_loss_grad.argtypes = [vp, i32, i32, u32, u32, vp, vp, vp, vp, vp]
+    lib.kd_cdf_loss_grad.restype = ctypes.c_int
+    lib.kd_cdf_eval.argtypes = [vp, vp, i32, i32, vp, vp, vp]
+    lib.kd_cdf_eval.restype = ctypes.c_int
+    lib.kdtree_workspace_bytes_learned.argtypes = [i64, i32, i32, ctypes.POINTER(sz)]
+    lib.kdtree_workspace_bytes_learned.restype = ctypes.c_int
+    lib.kdtree_build_learned.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp, vp, vp, vp, sz, opt, vp]
+    lib.kdtree_build_learned.restype = ctypes.c_int
+    lib.kdtree_presort_learned.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp, sz, opt, vp]
+    lib.kdtree_presort_learned.restype = ctypes.c_int
     lib.kd_probe_start.argtypes = [i32, i32]
     lib.kd_probe_start.restype = ctypes.c_int
     lib.kd_probe_stop.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int32)]
@@ -59,10 +76,15 @@ lib = _load()
 # Every symbol include/kdtree.h declares (the tests check the library exports them).
 EXPORTED = ["kd_strerror", "kdtree_workspace_bytes", "kdtree_build", "kdtree_presort",
             "kdtree_partition", "kdtree_workspace_bytes_batched", "kdtree_build_batched",
-            "kd_probe_start", "kd_probe_stop"]
+            "kd_cdf_model_bytes", "kd_cdf_train_workspace_bytes", "kd_cdf_train",
+            "kd_cdf_loss_grad", "kd_cdf_eval", "kdtree_workspace_bytes_learned",
+            "kdtree_build_learned", "kdtree_presort_learned", "kd_probe_start", "kd_probe_stop"]
 
 KERNEL_CLASSES = {"onesweep": 1, "level": 2, "leaf": 3, "dedup": 4, "hist": 5, "canon": 6,
-                  "records": 7}
+                  "records": 7, "bucket": 8}
+
+CDF_SEGMENTS = 1024
+CDF_MODEL_BYTES = 8448
 
 
 def probe_start(kernel: str, capacity: int) -> None:
@@ -100,3 +122,21 @@ def options(cutover: int | None):
     o = kd_options()
     o.cutover = int(cutover)
     return ctypes.byref(o)
+
+
+def _size(fn, *args) -> int:
+    out = ctypes.c_size_t(0)
+    check(getattr(lib, fn)(*args, ctypes.byref(out)), fn)
+    return int(out.value)
+
+
+def workspace_bytes_learned(n: int, k: int, dtype: int) -> int:
+    return _size("kdtree_workspace_bytes_learned", n, k, dtype)
+
+
+def cdf_model_bytes(k: int) -> int:
+    return _size("kd_cdf_model_bytes", k)
+
+
+def cdf_train_workspace_bytes(k: int, n_samples: int) -> int:
+    return _size("kd_cdf_train_workspace_bytes", k, n_samples)

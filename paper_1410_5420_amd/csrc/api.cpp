@@ -9,7 +9,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
+#include <utility>
 #include <vector>
 
 #include "../../include/kdtree.h"
@@ -31,13 +33,26 @@ int tree_digit_passes(int B) {
 
 // Workspace layout for N rows in k dimensions and B trees.  Every region is
 // fully written before it is read within a build, so nothing needs clearing.
+// The learned presort appends its own regions, so the regions shared with the
+// plain build sit at the same offsets in both layouts.
 struct Layout {
   size_t vbuf, carry, S, rec0, rec1, rec2;
   size_t rcnt, rgrp, dcnt, seginfo, lcnt, lcarry;
-  size_t uoff, wgbase, lmax, queue, offs, end;
+  size_t uoff, wgbase, lmax, queue, offs;
+  size_t starts, flags, lkey, carry2;  // learned presort only
+  size_t end;
 };
 
-Layout plan(int64_t n, int k, int B) {
+constexpr int kMaxBucketBits = 16;
+
+// Buckets of the learned presort: about 1024 keys each, at most 2^16.
+int bucket_bits(int64_t n) {
+  int b = 1;
+  while (b < kMaxBucketBits && ((int64_t)1024 << b) < n) ++b;
+  return b;
+}
+
+Layout plan(int64_t n, int k, int B, bool learned = false) {
   Layout L{};
   const int64_t nn = n > 0 ? n : 1;
   const size_t un = (size_t)nn;
@@ -66,6 +81,12 @@ Layout plan(int64_t n, int k, int B) {
   L.lmax = take(4);
   L.queue = take(4);
   L.offs = take(16);
+  if (learned) {
+    L.starts = take(4 * (((size_t)1 << kMaxBucketBits) + 1));
+    L.flags = take(4 * kMaxK);
+    L.lkey = take(4 * un);
+    L.carry2 = take(4 * un * (k + 1));
+  }
   L.end = o;
   return L;
 }
@@ -143,7 +164,9 @@ struct Pass {
 
 int run_sort(std::vector<Quant>& q, const std::vector<Pass>& passes, const TupleSrc& ts, int64_t n,
              const int32_t* n_dev, uint32_t* vb, int slots, uint32_t* rcnt, uint32_t* rgrp,
-             hipStream_t st) {
+             hipStream_t st, const int32_t* gate = nullptr) {
+  RadixExtra ex;
+  ex.gate = gate;
   const size_t un = (size_t)n;
   auto slot = [&](int set, int i) { return vb + ((size_t)set * slots + i) * un; };
   const int np = (int)passes.size();
@@ -173,7 +196,7 @@ int run_sort(std::vector<Quant>& q, const std::vector<Pass>& passes, const Tuple
     }
     pay.count = c;
     KD_LAUNCH(KD_K_ONESWEEP, launch_radix_pass(kin, ts, q[kq].word, kout, pay, n, n_dev,
-                                               passes[p].shift, rcnt, rgrp, st));
+                                               passes[p].shift, rcnt, rgrp, st, ex));
     for (int i = 0; i < (int)q.size(); ++i) {
       if (q[i].kind < 0) continue;
       const bool written = i == kq ? kout != nullptr
@@ -187,6 +210,71 @@ int run_sort(std::vector<Quant>& q, const std::vector<Pass>& passes, const Tuple
     }
     set ^= 1;
   }
+  return KD_OK;
+}
+
+// Learned sort of the quantities q (every one with a destination) by the
+// key words sortq (least significant first), bucketed on quantity keyq under
+// `model`.  Sets *flag when a bucket overflows LDS or the certificate (words
+// certq most significant first, then tieq, strictly increasing) fails; the
+// caller then runs the radix sort gated on the flag.
+struct LearnedSort {
+  const CdfModel* model;
+  int nb_bits;
+  int keyq;
+  std::vector<int> sortq, certq;
+  int tieq;
+  int32_t* starts;
+  int32_t* flag;
+};
+
+int learned_sort(std::vector<Quant> q, const LearnedSort& ls, const TupleSrc& ts, int64_t n,
+                 const int32_t* n_dev, uint32_t* vb, int slots, uint32_t* rcnt, uint32_t* rgrp,
+                 hipStream_t st) {
+  const size_t un = (size_t)n;
+  auto slot = [&](int set, int i) { return vb + ((size_t)set * slots + i) * un; };
+  KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(ls.flag), 0u, 1, st));
+  RadixExtra ex;
+  ex.model = ls.model;
+  ex.nb_bits = ls.nb_bits;
+  // bucket passes: stable, keyed by the bucket's 8-bit digits, moving everything
+  const int bpasses = ls.nb_bits > kRadixBits ? 2 : 1;
+  int set = 0;
+  for (int p = 0; p < bpasses; ++p) {
+    const Quant& kqq = q[ls.keyq];
+    const uint32_t* kin = kqq.kind == kPlaneArray ? kqq.in : nullptr;
+    Payload pay{};
+    for (int i = 0; i < (int)q.size(); ++i) {
+      if (i == ls.keyq) continue;
+      Plane& pl = pay.p[pay.count++];
+      pl.kind = q[i].kind;
+      pl.in = q[i].in;
+      pl.word = q[i].word;
+      pl.out = slot(set ^ 1, i);
+    }
+    KD_LAUNCH(KD_K_ONESWEEP, launch_radix_pass(kin, ts, kqq.word, slot(set ^ 1, ls.keyq), pay, n,
+                                               n_dev, p * kRadixBits, rcnt, rgrp, st, ex));
+    for (int i = 0; i < (int)q.size(); ++i) {
+      q[i].kind = kPlaneArray;
+      q[i].in = slot(set ^ 1, i);
+    }
+    set ^= 1;
+  }
+  KD_TRY(launch_bucket_bounds(q[ls.keyq].in, n, n_dev, ls.model, ls.nb_bits, ls.starts, ls.flag, st));
+  LocalSort lso{};
+  lso.nq = (int)q.size();
+  for (int i = 0; i < lso.nq; ++i) {
+    lso.in[i] = q[i].in;
+    lso.out[i] = q[i].dst;
+  }
+  lso.nkeys = (int)ls.sortq.size();
+  for (int w = 0; w < lso.nkeys; ++w) lso.keyq[w] = ls.sortq[w];
+  KD_LAUNCH(KD_K_BUCKET, launch_bucket_sort(ls.starts, ls.nb_bits, n, n_dev, ls.flag, lso, st));
+  CertArgs ca{};
+  ca.nw = (int)ls.certq.size();
+  for (int w = 0; w < ca.nw; ++w) ca.w[w] = q[ls.certq[w]].dst;
+  ca.tie = q[ls.tieq].dst;
+  KD_TRY(launch_certify(ca, n, n_dev, ls.flag, st));
   return KD_OK;
 }
 
@@ -206,6 +294,8 @@ struct Job {
   int64_t* n_unique;  // [B]
   void* ws;
   int64_t cutover;
+  const CdfModel* models = nullptr;  // learned presort: one model per dimension
+  int32_t* fell_back = nullptr;      // learned presort: per-sort fallback flags (device)
 };
 
 ForestArgs forest_args(const Job& J, const Layout& L) {
@@ -223,7 +313,8 @@ int presort_impl(const Job& J, hipStream_t st) {
   const int64_t n = J.n;
   const int k = J.k;
   const int B = J.B;
-  const Layout L = plan(n, k, B);
+  const bool learned = J.models != nullptr;
+  const Layout L = plan(n, k, B, learned);
   void* ws = J.ws;
   uint32_t* vb = at<uint32_t>(ws, L.vbuf);
   uint32_t* carry = at<uint32_t>(ws, L.carry);
@@ -237,6 +328,7 @@ int presort_impl(const Job& J, hipStream_t st) {
   const int tp = tree_digit_passes(B);
   const TupleSrc ts{static_cast<const uint32_t*>(J.tuples), k, J.dtype == KD_F32 ? 1 : 0};
 
+  if (learned) KD_TRY(launch_fill_u32(at<uint32_t>(ws, L.flags), 0u, k, st));
   KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(uoff), 0x7FFFFFFFu, B, st));
   KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(uoff + B), 0u, 1, st));
   if (n > 0) {
@@ -257,7 +349,26 @@ int presort_impl(const Job& J, hipStream_t st) {
     for (int w = k - 1; w >= 0; --w)
       for (int ps = 0; ps < kPassesPerWord; ++ps) passes.push_back({w == 0 ? k : w, ps * kRadixBits});
     for (int ps = 0; ps < tp; ++ps) passes.push_back({k + 1, ps * kRadixBits});
-    int rc = run_sort(q, passes, ts, n, nullptr, vb, slots, rcnt, rgrp, st);
+    const int32_t* gate = nullptr;
+    if (learned) {
+      // bucket on word 0; finish by words k-1 .. 1, then word 0; ties by row
+      LearnedSort ls;
+      ls.model = J.models;
+      ls.nb_bits = bucket_bits(n);
+      ls.keyq = k;
+      for (int d = k - 1; d >= 1; --d) ls.sortq.push_back(d);
+      ls.sortq.push_back(k);
+      ls.certq.push_back(k);
+      for (int d = 1; d < k; ++d) ls.certq.push_back(d);
+      ls.tieq = 0;
+      ls.starts = at<int32_t>(ws, L.starts);
+      ls.flag = at<int32_t>(ws, L.flags);
+      std::vector<Quant> ql(q.begin(), q.begin() + k + 1);
+      int rc = learned_sort(ql, ls, ts, n, nullptr, vb, slots, rcnt, rgrp, st);
+      if (rc != KD_OK) return rc;
+      gate = ls.flag;
+    }
+    int rc = run_sort(q, passes, ts, n, nullptr, vb, slots, rcnt, rgrp, st, gate);
     if (rc != KD_OK) return rc;
     // Sec. 2.1 duplicate removal on the fully sorted order; hands the words
     // w1..w_{k-1} (and tree ids) of the kept rows to the chain
@@ -274,9 +385,15 @@ int presort_impl(const Job& J, hipStream_t st) {
   // ranks already known -- the input position is the rank in order d+1 --
   // straight into array d's level-0 rank planes (plane c = rank in order
   // d+1+c), the key words of the sorts still to come, and the tree ids.
-  auto carried = [&](int d) { return carry + (size_t)(d - 1) * un; };
+  // The plain build rewrites the carried key words in place.  The learned
+  // sort must leave its inputs intact for a fallback, so it alternates
+  // between two carry buffers.
+  uint32_t* cin = carry;
+  uint32_t* cout = learned ? at<uint32_t>(ws, L.carry2) : carry;
   uint32_t* tree_c = carry + (size_t)(k - 1) * un;
   for (int d = k - 1; d >= 1; --d) {
+    auto carried_in = [&](int dd) { return cin + (size_t)(dd - 1) * un; };
+    auto carried_out = [&](int dd) { return cout + (size_t)(dd - 1) * un; };
     const uint32_t* in_rec = rec0 + record_offset((d + 1) % k, k, n);
     uint32_t* out_rec = rec0 + record_offset(d, k, n);
     const int known = k - d;  // record planes 0 .. k-d-1
@@ -286,9 +403,10 @@ int presort_impl(const Job& J, hipStream_t st) {
       q.push_back(cc == 0 ? Quant{kPlaneIndex, nullptr, 0, out_rec}
                           : Quant{kPlaneArray, in_rec + (size_t)(cc - 1) * un, 0,
                                   out_rec + (size_t)cc * un});
-    for (int dd = d - 1; dd >= 1; --dd) q.push_back(Quant{kPlaneArray, carried(dd), 0, carried(dd)});
+    for (int dd = d - 1; dd >= 1; --dd)
+      q.push_back(Quant{kPlaneArray, carried_in(dd), 0, carried_out(dd)});
     const int keyq = (int)q.size();
-    q.push_back(Quant{kPlaneArray, carried(d), 0, nullptr});
+    q.push_back(Quant{kPlaneArray, carried_in(d), 0, nullptr});
     int treeq = -1;
     if (B > 1) {
       treeq = (int)q.size();
@@ -297,8 +415,28 @@ int presort_impl(const Job& J, hipStream_t st) {
     std::vector<Pass> passes;
     for (int ps = 0; ps < kPassesPerWord; ++ps) passes.push_back({keyq, ps * kRadixBits});
     for (int ps = 0; ps < tp; ++ps) passes.push_back({treeq, ps * kRadixBits});
-    int rc = run_sort(q, passes, ts, n, total, vb, slots, rcnt, rgrp, st);
+    const int32_t* gate = nullptr;
+    if (learned) {
+      // bucket on word d and finish by it; ties keep the order of array d+1,
+      // whose position is the quantity-1 rank plane
+      LearnedSort ls;
+      ls.model = J.models + d;
+      ls.nb_bits = bucket_bits(n);
+      ls.keyq = keyq;
+      ls.sortq.push_back(keyq);
+      ls.certq.push_back(keyq);
+      ls.tieq = 1;
+      ls.starts = at<int32_t>(ws, L.starts);
+      ls.flag = at<int32_t>(ws, L.flags) + d;
+      std::vector<Quant> ql = q;
+      ql[keyq].dst = at<uint32_t>(ws, L.lkey);
+      int rc = learned_sort(ql, ls, ts, n, total, vb, slots, rcnt, rgrp, st);
+      if (rc != KD_OK) return rc;
+      gate = ls.flag;
+    }
+    int rc = run_sort(q, passes, ts, n, total, vb, slots, rcnt, rgrp, st, gate);
     if (rc != KD_OK) return rc;
+    if (learned) std::swap(cin, cout);
   }
   if (k > 1) KD_LAUNCH(KD_K_RECORDS, launch_complete_records(rec0, S + un, n, k, total, st));
   return KD_OK;
@@ -350,7 +488,7 @@ int check_job(Job& J, size_t ws_bytes, const kd_options* opts) {
   if ((J.n > 0 && !J.tuples) || !J.ws || !J.n_unique) return KD_EINVAL;
   if (!aligned4(J.tuples) || !aligned4(J.ws)) return KD_EINVAL;
   if ((reinterpret_cast<uintptr_t>(J.n_unique) & 7u) != 0) return KD_EINVAL;
-  if (ws_bytes < plan(J.n, J.k, J.B).end) return KD_ENOMEM;
+  if (ws_bytes < plan(J.n, J.k, J.B, J.models != nullptr).end) return KD_ENOMEM;
   int rc = check_opts(opts, &J.cutover);
   if (rc != KD_OK) return rc;
   while (J.cutover > 1024 && leaf_lds_bytes(J.cutover, J.k) + 8192 > 160 * 1024) J.cutover /= 2;
@@ -367,8 +505,10 @@ int check_outputs(const Job& J) {
 // single tree: offsets {0, n} live in the workspace
 int single_job(Job& J, const void* tuples, int64_t n, int32_t k, int32_t dtype, int64_t* nu,
                void* ws, size_t ws_bytes, const kd_options* opts, int64_t* h_off, hipStream_t st,
-               bool upload) {
+               bool upload, const void* models = nullptr) {
   J = Job{};
+  J.models = static_cast<const CdfModel*>(models);
+  if (models && (reinterpret_cast<uintptr_t>(models) & 3u) != 0) return KD_EINVAL;
   J.tuples = tuples;
   J.n = n;
   J.B = 1;
@@ -390,6 +530,36 @@ int single_job(Job& J, const void* tuples, int64_t n, int32_t k, int32_t dtype, 
     KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(d_off) + 3, words[3], 1, st));
   }
   return KD_OK;
+}
+
+int presort_learned(const Job& J, hipStream_t st) {
+  int rc = presort_impl(J, st);
+  if (rc != KD_OK) return rc;
+  if (J.fell_back) {
+    const Layout L = plan(J.n, J.k, 1, true);
+    KD_TRY(launch_copy_i32(at<int32_t>(J.ws, L.flags), J.k, J.fell_back, st));
+  }
+  return KD_OK;
+}
+
+// ---- model training (host side) -----------------------------------------------------
+struct TrainLayout {
+  size_t a, b, cnt, grp, end;
+};
+TrainLayout train_plan(int k, int S) {
+  TrainLayout T{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at2 = o;
+    o = align_up(o + bytes);
+    return at2;
+  };
+  T.a = take(4 * (size_t)k * S);
+  T.b = take(4 * (size_t)k * S);
+  T.cnt = take(4 * (size_t)radix_count_words(S));
+  T.grp = take(4 * (size_t)radix_group_words(S));
+  T.end = o;
+  return T;
 }
 
 }  // namespace
@@ -515,8 +685,147 @@ int kdtree_build_batched(const void* d_tuples, const int64_t* d_offsets, const i
   return kd::partition_impl(J, st);
 }
 
+int kdtree_workspace_bytes_learned(int64_t n, int32_t k, int32_t dtype, size_t* h_bytes) {
+  if (!h_bytes || n < 0 || k < 1 || (dtype != KD_I32 && dtype != KD_F32)) return KD_EINVAL;
+  if (n > KD_MAX_N || k > KD_MAX_K) return KD_EUNSUPPORTED;
+  *h_bytes = kd::plan(n, k, 1, true).end;
+  return KD_OK;
+}
+
+int kd_cdf_model_bytes(int32_t k, size_t* h_bytes) {
+  if (!h_bytes || k < 1) return KD_EINVAL;
+  if (k > KD_MAX_K) return KD_EUNSUPPORTED;
+  *h_bytes = (size_t)k * sizeof(kd::CdfModel);
+  return KD_OK;
+}
+
+int kd_cdf_train_workspace_bytes(int32_t k, int32_t n_samples, size_t* h_bytes) {
+  if (!h_bytes || k < 1 || n_samples < 1) return KD_EINVAL;
+  if (k > KD_MAX_K || n_samples > KD_CDF_MAX_SAMPLES) return KD_EUNSUPPORTED;
+  *h_bytes = kd::train_plan(k, n_samples).end;
+  return KD_OK;
+}
+
+int kd_cdf_train(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, int32_t n_samples,
+                 int32_t steps, float lr, void* d_models, void* d_workspace, size_t workspace_bytes,
+                 void* stream) {
+  if (n < 1 || k < 1 || n_samples < 1 || steps < 0 || (dtype != KD_I32 && dtype != KD_F32))
+    return KD_EINVAL;
+  if (!(lr > 0.f) || !std::isfinite(lr)) return KD_EINVAL;
+  if (n > KD_MAX_N || k > KD_MAX_K || n_samples > KD_CDF_MAX_SAMPLES || steps > KD_CDF_MAX_STEPS)
+    return KD_EUNSUPPORTED;
+  if (!d_tuples || !d_models || !d_workspace) return KD_EINVAL;
+  if (!kd::aligned4(d_tuples) || !kd::aligned4(d_models) || !kd::aligned4(d_workspace))
+    return KD_EINVAL;
+  const kd::TrainLayout T = kd::train_plan(k, n_samples);
+  if (workspace_bytes < T.end) return KD_ENOMEM;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  uint32_t* a = kd::at<uint32_t>(d_workspace, T.a);
+  uint32_t* b = kd::at<uint32_t>(d_workspace, T.b);
+  uint32_t* cnt = kd::at<uint32_t>(d_workspace, T.cnt);
+  uint32_t* grp = kd::at<uint32_t>(d_workspace, T.grp);
+  const int is_float = dtype == KD_F32 ? 1 : 0;
+  KD_TRY(kd::launch_cdf_sample(static_cast<const uint32_t*>(d_tuples), n, k, is_float, n_samples, a,
+                               st));
+  // the sample of each dimension is presorted by the radix passes (4 passes,
+  // so the result is back in a)
+  const kd::TupleSrc ts{nullptr, k, is_float};
+  const kd::Payload none{};
+  for (int d = 0; d < k; ++d) {
+    uint32_t* x = a + (size_t)d * n_samples;
+    uint32_t* y = b + (size_t)d * n_samples;
+    for (int ps = 0; ps < kd::kPassesPerWord; ++ps) {
+      KD_TRY(kd::launch_radix_pass(x, ts, 0, y, none, n_samples, nullptr, ps * kd::kRadixBits, cnt,
+                                   grp, st));
+      std::swap(x, y);
+    }
+  }
+  KD_TRY(kd::launch_cdf_fit(a, n_samples, k, is_float, steps, lr,
+                            static_cast<kd::CdfModel*>(d_models), st));
+  return KD_OK;
+}
+
+int kd_cdf_loss_grad(const void* d_values, int32_t m, int32_t dtype, uint32_t lo_bits,
+                     uint32_t hi_bits, const float* d_theta, float* d_loss, float* d_grad,
+                     void* d_scratch, void* stream) {
+  if (m < 1 || (dtype != KD_I32 && dtype != KD_F32)) return KD_EINVAL;
+  if (m > KD_CDF_MAX_SAMPLES) return KD_EUNSUPPORTED;
+  if (!d_values || !d_theta || !d_loss || !d_grad || !d_scratch) return KD_EINVAL;
+  if (!kd::aligned4(d_values) || !kd::aligned4(d_theta) || !kd::aligned4(d_loss) ||
+      !kd::aligned4(d_grad) || !kd::aligned4(d_scratch))
+    return KD_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  KD_TRY(kd::launch_cdf_loss_grad(static_cast<const uint32_t*>(d_values), m, dtype == KD_F32 ? 1 : 0,
+                                  lo_bits, hi_bits, d_theta, static_cast<uint32_t*>(d_scratch),
+                                  d_loss, d_grad, st));
+  return KD_OK;
+}
+
+int kd_cdf_eval(const void* d_model, const void* d_values, int32_t m, int32_t nb_bits, float* d_F,
+                int32_t* d_bucket, void* stream) {
+  if (m < 0 || nb_bits < 1 || nb_bits > 16) return KD_EINVAL;
+  if (m == 0) return KD_OK;
+  if (!d_model || !d_values || !d_F || !d_bucket) return KD_EINVAL;
+  if (!kd::aligned4(d_model) || !kd::aligned4(d_values) || !kd::aligned4(d_F) ||
+      !kd::aligned4(d_bucket))
+    return KD_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  KD_TRY(kd::launch_cdf_eval(static_cast<const kd::CdfModel*>(d_model),
+                             static_cast<const uint32_t*>(d_values), m, nb_bits, d_F, d_bucket, st));
+  return KD_OK;
+}
+
+int kdtree_presort_learned(const void* d_tuples, int64_t n, int32_t k, int32_t dtype,
+                           const void* d_models, int64_t* d_n_unique, int32_t* d_fell_back,
+                           void* d_workspace, size_t workspace_bytes, const kd_options* opts,
+                           void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (!d_models) return KD_EINVAL;
+  if (!kd::aligned4(d_fell_back)) return KD_EINVAL;
+  kd::Job J;
+  int64_t h_off[2];
+  int rc = kd::single_job(J, d_tuples, n, k, dtype, d_n_unique, d_workspace, workspace_bytes, opts,
+                          h_off, st, true, d_models);
+  if (rc != KD_OK) return rc;
+  J.fell_back = d_fell_back;
+  return kd::presort_learned(J, st);
+}
+
+int kdtree_build_learned(const void* d_tuples, int64_t n, int32_t k, int32_t dtype,
+                         const void* d_models, int32_t* d_perm, int32_t* d_lo, int32_t* d_hi,
+                         int64_t* d_n_unique, int32_t* d_fell_back, void* d_workspace,
+                         size_t workspace_bytes, const kd_options* opts, void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (!d_models) return KD_EINVAL;
+  if (!kd::aligned4(d_fell_back)) return KD_EINVAL;
+  {
+    kd::Job V;
+    int64_t h2[2];
+    int rc = kd::single_job(V, d_tuples, n, k, dtype, d_n_unique, d_workspace, workspace_bytes,
+                            opts, h2, st, false, d_models);
+    if (rc != KD_OK) return rc;
+    V.perm = d_perm;
+    V.lo = d_lo;
+    V.hi = d_hi;
+    rc = kd::check_outputs(V);
+    if (rc != KD_OK) return rc;
+  }
+  kd::Job J;
+  int64_t h_off[2];
+  int rc = kd::single_job(J, d_tuples, n, k, dtype, d_n_unique, d_workspace, workspace_bytes, opts,
+                          h_off, st, true, d_models);
+  if (rc != KD_OK) return rc;
+  J.perm = d_perm;
+  J.lo = d_lo;
+  J.hi = d_hi;
+  J.fell_back = d_fell_back;
+  rc = kd::presort_learned(J, st);
+  if (rc != KD_OK) return rc;
+  return kd::partition_impl(J, st);
+}
+
 int kd_probe_start(int32_t kernel_class, int32_t capacity) {
-  if (kernel_class < KD_K_ONESWEEP || kernel_class > KD_K_RECORDS || capacity < 1 ||
+  if (kernel_class < KD_K_ONESWEEP || kernel_class > KD_K_BUCKET || capacity < 1 ||
       capacity > (1 << 20))
     return KD_EINVAL;
   kd::Probe& p = kd::g_probe;

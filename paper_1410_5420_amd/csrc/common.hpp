@@ -125,6 +125,80 @@ __device__ __host__ __forceinline__ int cutover_depth(int64_t nu, int64_t cutove
   return d;
 }
 
+// ---- learned CDF model ------------------------------------------------------
+// A monotone piecewise-linear estimate F of the cumulative distribution of one
+// coordinate, used by the learned presort to send a key straight to its
+// bucket.  K segments split the value range [lo, hi] evenly; c[i] is F at the
+// start of segment i (c[0] = 0, c[K] = 1, non-decreasing).  Keys are
+// canonical (order-preserving) 32-bit words; at or below kmin F is 0, at or
+// above kmax it is 1.  The model changes only where keys land, never the
+// sorted result.
+constexpr int kCdfSegments = 1024;
+struct CdfModel {
+  float lo, hi;      // value range of the training sample (finite values)
+  float scale;       // K / (hi - lo), or 0 for a degenerate range
+  uint32_t kmin;     // canonical key of lo
+  uint32_t kmax;     // canonical key of hi
+  int32_t is_float;  // coordinate type the model was trained on
+  int32_t segments;  // K
+  float loss;        // training loss at the last step
+  float c[kCdfSegments + 1];
+  float theta[kCdfSegments];  // trained parameters (segment-mass logits)
+  float pad[55];
+};
+static_assert(sizeof(CdfModel) == 8448, "model size is part of the ABI");
+
+// Order-preserving 32-bit key of a coordinate: int32 with the sign bit
+// flipped (signed order); float32 under IEEE totalOrder (negative encodings
+// complemented, non-negative ones with the sign bit set).
+__device__ __forceinline__ uint32_t canon_word(uint32_t b, bool is_float) {
+  return is_float ? (b ^ ((b >> 31) ? 0xFFFFFFFFu : 0x80000000u)) : (b ^ 0x80000000u);
+}
+
+// Coordinate value of a canonical key (monotone non-decreasing in the key).
+__device__ __forceinline__ float cdf_key_value(uint32_t key, int is_float) {
+  if (!is_float) return (float)(int32_t)(key ^ 0x80000000u);
+  const uint32_t bits = (key & 0x80000000u) ? (key ^ 0x80000000u) : ~key;
+  return __uint_as_float(bits);
+}
+
+// Segment index and fraction of a key strictly inside (kmin, kmax).
+// Every operation is a separately rounded single-precision step: contraction
+// into fused multiply-adds is switched off here (the library is built with
+// -ffp-contract=fast-honor-pragmas), so every kernel that evaluates the model
+// gets the same bits.
+__device__ __forceinline__ int cdf_segment(float v, float lo, float scale, float* frac) {
+#pragma clang fp contract(off)
+  const float t = (v - lo) * scale;
+  int i = t < (float)kCdfSegments ? (int)t : kCdfSegments - 1;
+  if (i < 0) i = 0;
+  float f = t - (float)i;
+  f = f < 0.f ? 0.f : (f > 1.f ? 1.f : f);
+  *frac = f;
+  return i;
+}
+
+// F(key).  Monotone: inside a segment F grows with the fraction, and F never
+// exceeds the next segment's start c[i+1].
+__device__ __forceinline__ float cdf_eval(const float* c, float lo, float scale, uint32_t kmin,
+                                          uint32_t kmax, int is_float, uint32_t key) {
+#pragma clang fp contract(off)
+  if (key <= kmin) return 0.f;
+  if (key >= kmax) return 1.f;
+  float f;
+  const int i = cdf_segment(cdf_key_value(key, is_float), lo, scale, &f);
+  const float a = c[i], b = c[i + 1];
+  return fminf(a + f * (b - a), b);
+}
+
+// Bucket of a key among 2^nb_bits buckets.
+__device__ __forceinline__ uint32_t cdf_bucket(float F, int nb_bits) {
+#pragma clang fp contract(off)
+  const uint32_t nb = 1u << nb_bits;
+  const uint32_t b = (uint32_t)(F * (float)nb);
+  return b < nb ? b : nb - 1;
+}
+
 // ---- rank-record layout ------------------------------------------------------------
 // Array j (0 <= j < k) stores one record per position: k-1 ranks (plane c =
 // rank in order (j + 1 + c) mod k), plus the row id for array 0.  Arrays are

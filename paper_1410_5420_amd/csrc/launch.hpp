@@ -52,8 +52,20 @@ struct Payload {
   int count;
 };
 
+struct CdfModel;
+
+// Options of a radix pass.  model: rank by the key's bucket under a learned
+// CDF model (2^nb_bits buckets) instead of the key itself.  gate: when set,
+// every kernel of the pass does nothing unless *gate != 0 (a sort that only
+// runs when an earlier attempt failed).
+struct RadixExtra {
+  const CdfModel* model = nullptr;
+  int nb_bits = 0;
+  const int32_t* gate = nullptr;
+};
+
 // One stable LSD radix pass on 8-bit digit `shift`: per-tile digit counts, a
-// two-level scan and the scatter (three launches, no waiting between
+// two-level scan and the scatter (four launches, no waiting between
 // workgroups).  The key of element i is keys_in[i], or (keys_in == nullptr)
 // the canonical word `key_word` of tuple row i.  keys_out may be null.  Every
 // payload plane travels with its key.  Elements: i < (n_dev ? *n_dev : n).
@@ -61,7 +73,7 @@ struct Payload {
 hipError_t launch_radix_pass(const uint32_t* keys_in, const TupleSrc& ts, int key_word,
                              uint32_t* keys_out, const Payload& pay, int64_t n,
                              const int32_t* n_dev, int shift, uint32_t* cnt, uint32_t* group_tot,
-                             hipStream_t st);
+                             hipStream_t st, const RadixExtra& ex = RadixExtra());
 inline int64_t radix_tiles(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
 inline int64_t radix_count_words(int64_t n) { return radix_tiles(n) * kRadix; }
 inline int64_t radix_group_words(int64_t n) { return (radix_tiles(n) + 63) / 64 * kRadix; }
@@ -114,6 +126,53 @@ hipError_t launch_leaf(const uint32_t* rec0, uint32_t* b1, uint32_t* b2, int64_t
 // k == 1: the in-order layout is the sorted unique order.
 hipError_t launch_copy_k1(const uint32_t* S0, const ForestArgs& fa, int64_t n, int32_t* perm,
                           hipStream_t st);
+
+// ---- learned presort (learned.hip) ----------------------------------------------
+
+// Sample of S canonical keys per dimension (rows floor(s * n / S)); out [k][S].
+hipError_t launch_cdf_sample(const uint32_t* t, int64_t n, int k, int is_float, int S, uint32_t* out,
+                             hipStream_t st);
+// Train k models (one workgroup each) on the sorted samples [k][S].
+hipError_t launch_cdf_fit(const uint32_t* sorted, int S, int k, int is_float, int steps, float lr,
+                          CdfModel* models, hipStream_t st);
+// Loss and gradient of the training objective on a sorted raw sample.
+// keys: M words of scratch.
+hipError_t launch_cdf_loss_grad(const uint32_t* raw, int M, int is_float, uint32_t lo_bits,
+                                uint32_t hi_bits, const float* theta, uint32_t* keys, float* loss,
+                                float* grad, hipStream_t st);
+hipError_t launch_cdf_eval(const CdfModel* model, const uint32_t* raw, int M, int nb_bits, float* F,
+                           int32_t* bucket, hipStream_t st);
+
+// Bucket starts (2^nb_bits + 1 entries) of keys ordered by bucket.
+hipError_t launch_bucket_bounds(const uint32_t* keys, int64_t n, const int32_t* n_dev,
+                                const CdfModel* model, int nb_bits, int32_t* starts, int32_t* flag,
+                                hipStream_t st);
+
+// Planes of one bucket sort: nq planes moved from in[q] to out[q] (out may
+// equal in); the sort words are planes keyq[0..nkeys-1], least significant
+// first.
+struct LocalSort {
+  int nq;
+  const uint32_t* in[kMaxPlanes];
+  uint32_t* out[kMaxPlanes];
+  int nkeys;
+  int keyq[kMaxK];
+};
+hipError_t launch_bucket_sort(const int32_t* starts, int nb_bits, int64_t n, const int32_t* n_dev,
+                              int32_t* flag, const LocalSort& ls, hipStream_t st);
+size_t bucket_sort_lds_bytes();
+int bucket_sort_capacity();
+
+// Strict order check of a sorted output: words w[0..nw-1] (most significant
+// first), then tie.
+struct CertArgs {
+  int nw;
+  const uint32_t* w[kMaxK];
+  const uint32_t* tie;
+};
+hipError_t launch_certify(const CertArgs& ca, int64_t n, const int32_t* n_dev, int32_t* flag,
+                          hipStream_t st);
+hipError_t launch_copy_i32(const int32_t* src, int count, int32_t* dst, hipStream_t st);
 
 // Child positions from the implicit shape of a single tree (uoff[1] rows).
 hipError_t launch_children(const int32_t* uoff, int64_t n, int32_t* lo, int32_t* hi,

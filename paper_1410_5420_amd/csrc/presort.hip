@@ -45,19 +45,14 @@ hipError_t launch_store_i64(int64_t* dst, const int64_t* src, hipStream_t st) {
 }
 
 // ---- key canonicalisation ----------------------------------------------------
-// int32: flipping the sign bit turns signed order into unsigned order.
-// float32: IEEE totalOrder becomes unsigned order when negative encodings are
-// complemented and non-negative ones get the sign bit set.
-
-__device__ __forceinline__ uint32_t canon_word(uint32_t b, bool is_float) {
-  return is_float ? (b ^ ((b >> 31) ? 0xFFFFFFFFu : 0x80000000u)) : (b ^ 0x80000000u);
-}
+// canon_word (common.hpp) turns int32 signed order and float32 IEEE totalOrder
+// into unsigned order; it is applied as the tuples are read.
 
 // ---- radix passes: per-tile counts, a two-level scan, then the scatter ----------
 // Every pass is three launches with no waiting between workgroups:
 //   1. count:   tile t (kSortTile elements, fixed by blockIdx) counts its 256
 //               digits into cnt[t][d];
-//   2. scan:    blocks of 16 tiles turn those into exclusive prefixes per digit
+//   2. scan:    blocks of 64 tiles turn those into exclusive prefixes per digit
 //               (plus per-block totals), one block then scans the block
 //               totals and adds each digit's global start;
 //   3. scatter: tile t ranks its elements stably (wave ballots), adds the
@@ -77,14 +72,48 @@ __device__ __forceinline__ uint32_t plane_value(const Plane& pl, const TupleSrc&
   return canon_word(ts.t[(int64_t)i * ts.k + pl.word], ts.is_float);
 }
 
-template <bool kFromTuples>
+// Learned digit source: the key's bucket under a CDF model (table in LDS).
+struct ModelView {
+  const float* c;
+  float lo, scale;
+  uint32_t kmin, kmax;
+  int is_float, nb_bits;
+};
+
+__device__ __forceinline__ ModelView load_model(const RadixExtra& ex, float* s_c) {
+  for (int q = threadIdx.x; q <= kCdfSegments; q += blockDim.x) s_c[q] = ex.model->c[q];
+  ModelView m;
+  m.c = s_c;
+  m.lo = ex.model->lo;
+  m.scale = ex.model->scale;
+  m.kmin = ex.model->kmin;
+  m.kmax = ex.model->kmax;
+  m.is_float = ex.model->is_float;
+  m.nb_bits = ex.nb_bits;
+  return m;
+}
+
+__device__ __forceinline__ uint32_t model_bucket(const ModelView& m, uint32_t key) {
+  return cdf_bucket(cdf_eval(m.c, m.lo, m.scale, m.kmin, m.kmax, m.is_float, key), m.nb_bits);
+}
+
+__device__ __forceinline__ bool gated_off(const RadixExtra& ex) {
+  return ex.gate != nullptr && *ex.gate == 0;
+}
+
+template <bool kFromTuples, bool kModel>
 __global__ __launch_bounds__(kOsThreads) void k_radix_count(const uint32_t* __restrict__ keys_in,
                                                            const TupleSrc ts, int key_word,
                                                            int64_t n_host, const int32_t* n_dev,
-                                                           int shift, uint32_t* __restrict__ cnt) {
+                                                           int shift, uint32_t* __restrict__ cnt,
+                                                           const RadixExtra ex) {
   __shared__ uint32_t s_h[kRadix];
+  __shared__ float s_c[kModel ? kCdfSegments + 1 : 1];
+  if (gated_off(ex)) return;
   const int tid = threadIdx.x;
   if (tid < kRadix) s_h[tid] = 0;
+  ModelView mv{};
+  if (kModel) mv = load_model(ex, s_c);
   __syncthreads();
   const int n = (int)(n_dev ? *n_dev : n_host);
   const int base = blockIdx.x * kSortTile;
@@ -92,8 +121,9 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_count(const uint32_t* __re
   for (int j = 0; j < kOsItems; ++j) {
     const int i = base + j * kOsThreads + tid;
     if (i < n) {
-      const uint32_t key =
+      uint32_t key =
           kFromTuples ? canon_word(ts.t[(int64_t)i * ts.k + key_word], ts.is_float) : keys_in[i];
+      if (kModel) key = model_bucket(mv, key);
       atomicAdd(&s_h[(key >> shift) & 0xFF], 1u);
     }
   }
@@ -104,7 +134,8 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_count(const uint32_t* __re
 // First level: exclusive prefix over the tiles of one group, per digit.
 __global__ __launch_bounds__(kRadix) void k_radix_scan_tiles(uint32_t* __restrict__ cnt,
                                                             uint32_t* __restrict__ group_tot,
-                                                            int tiles) {
+                                                            int tiles, const RadixExtra ex) {
+  if (gated_off(ex)) return;
   const int d = threadIdx.x;
   const int t0 = blockIdx.x * kScanGroup;
   const int t1 = min(t0 + kScanGroup, tiles);
@@ -128,9 +159,10 @@ __global__ __launch_bounds__(kRadix) void k_radix_scan_tiles(uint32_t* __restric
 constexpr int kSgSub = 4;
 constexpr int kSgBatch = 16;
 __global__ __launch_bounds__(kRadix * kSgSub) void k_radix_scan_groups(
-    uint32_t* __restrict__ group_tot, int groups) {
+    uint32_t* __restrict__ group_tot, int groups, const RadixExtra ex) {
   __shared__ uint32_t s_part[kSgSub][kRadix];
   __shared__ uint32_t s_tmp[kRadix * kSgSub / kWave + 1];
+  if (gated_off(ex)) return;
   const int d = threadIdx.x % kRadix;
   const int sub = threadIdx.x / kRadix;
   const int per = (groups + kSgSub - 1) / kSgSub;
@@ -175,17 +207,20 @@ __global__ __launch_bounds__(kRadix * kSgSub) void k_radix_scan_groups(
   }
 }
 
-template <bool kFromTuples, bool kWriteKeys>
+template <bool kFromTuples, bool kWriteKeys, bool kModel>
 __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const TupleSrc ts, int key_word,
     uint32_t* __restrict__ keys_out, const Payload pay, int64_t n_host, const int32_t* n_dev,
-    int shift, const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ group_start) {
+    int shift, const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ group_start,
+    const RadixExtra ex) {
   __shared__ uint32_t s_keys[kSortTile];
   __shared__ uint32_t s_stage[kSortTile];
   __shared__ uint32_t s_wcnt[kOsWaves][kRadix];
   __shared__ uint32_t s_tile_excl[kRadix];
   __shared__ uint32_t s_gbase[kRadix];
   __shared__ uint32_t s_tmp[kOsWaves + 1];
+  __shared__ float s_c[kModel ? kCdfSegments + 1 : 1];
+  if (gated_off(ex)) return;
 
   const int tid = threadIdx.x;
   const int w = tid / kWave;
@@ -195,6 +230,8 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
   const int base = tile * kSortTile;
   if (base >= n) return;
   for (int q = tid; q < kOsWaves * kRadix; q += kOsThreads) (&s_wcnt[0][0])[q] = 0;
+  ModelView mv{};
+  if (kModel) mv = load_model(ex, s_c);
   // global start of this tile's run of digit tid
   if (tid < kRadix)
     s_gbase[tid] = cnt[(int64_t)tile * kRadix + tid] +
@@ -211,6 +248,11 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
                            : keys_in[i];
   }
   __syncthreads();
+  // learned digits: rank by bucket (the raw key travels as a payload plane)
+  if (kModel) {
+#pragma unroll
+    for (int j = 0; j < kOsItems; ++j) key[j] = model_bucket(mv, key[j]);
+  }
 
   const uint64_t below = lanes_below_mask();
 #pragma unroll
@@ -313,29 +355,48 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
 }
 
 hipError_t launch_radix_pass(const uint32_t* keys_in, const TupleSrc& ts, int key_word,
-                             uint32_t* keys_out, const Payload& pay, int64_t n,
+                             uint32_t* keys_out, const Payload& pay_in, int64_t n,
                              const int32_t* n_dev, int shift, uint32_t* cnt, uint32_t* group_tot,
-                             hipStream_t st) {
+                             hipStream_t st, const RadixExtra& ex) {
   if (n <= 0) return hipSuccess;
   const int tiles = (int)((n + kSortTile - 1) / kSortTile);
   const int groups = (tiles + kScanGroup - 1) / kScanGroup;
   const bool ft = keys_in == nullptr;
-  if (ft)
-    hipLaunchKernelGGL(k_radix_count<true>, dim3(tiles), dim3(kOsThreads), 0, st, keys_in, ts,
-                       key_word, n, n_dev, shift, cnt);
-  else
-    hipLaunchKernelGGL(k_radix_count<false>, dim3(tiles), dim3(kOsThreads), 0, st, keys_in, ts,
-                       key_word, n, n_dev, shift, cnt);
-  hipLaunchKernelGGL(k_radix_scan_tiles, dim3(groups), dim3(kRadix), 0, st, cnt, group_tot, tiles);
-  hipLaunchKernelGGL(k_radix_scan_groups, dim3(1), dim3(kRadix * kSgSub), 0, st, group_tot, groups);
-#define KD_RS(FT, WK)                                                                           \
-  hipLaunchKernelGGL((k_radix_scatter<FT, WK>), dim3(xcd_grid(tiles)), dim3(kOsThreads), 0, st, keys_in, \
-                     ts, key_word, keys_out, pay, n, n_dev, shift, cnt, group_tot)
-  const bool wk = keys_out != nullptr;
+  const bool md = ex.model != nullptr;
+  Payload pay = pay_in;
+  if (md && keys_out) {
+    // the kernel ranks by bucket; the raw key is moved like any payload plane
+    if (pay.count >= kMaxPlanes) return hipErrorInvalidValue;
+    Plane& pl = pay.p[pay.count++];
+    pl.in = keys_in;
+    pl.out = keys_out;
+    pl.kind = ft ? kPlaneTupleWord : kPlaneArray;
+    pl.word = key_word;
+    keys_out = nullptr;
+  }
+#define KD_RC(FT, MD)                                                                   \
+  hipLaunchKernelGGL((k_radix_count<FT, MD>), dim3(tiles), dim3(kOsThreads), 0, st, keys_in, \
+                     ts, key_word, n, n_dev, shift, cnt, ex)
   if (ft) {
-    if (wk) KD_RS(true, true); else KD_RS(true, false);
+    if (md) KD_RC(true, true); else KD_RC(true, false);
   } else {
-    if (wk) KD_RS(false, true); else KD_RS(false, false);
+    if (md) KD_RC(false, true); else KD_RC(false, false);
+  }
+#undef KD_RC
+  hipLaunchKernelGGL(k_radix_scan_tiles, dim3(groups), dim3(kRadix), 0, st, cnt, group_tot, tiles,
+                     ex);
+  hipLaunchKernelGGL(k_radix_scan_groups, dim3(1), dim3(kRadix * kSgSub), 0, st, group_tot, groups,
+                     ex);
+#define KD_RS(FT, WK, MD)                                                                   \
+  hipLaunchKernelGGL((k_radix_scatter<FT, WK, MD>), dim3(xcd_grid(tiles)), dim3(kOsThreads), 0, \
+                     st, keys_in, ts, key_word, keys_out, pay, n, n_dev, shift, cnt, group_tot, ex)
+  const bool wk = keys_out != nullptr;
+  if (md) {
+    if (ft) KD_RS(true, false, true); else KD_RS(false, false, true);
+  } else if (ft) {
+    if (wk) KD_RS(true, true, false); else KD_RS(true, false, false);
+  } else {
+    if (wk) KD_RS(false, true, false); else KD_RS(false, false, false);
   }
 #undef KD_RS
   return hipGetLastError();

@@ -1,0 +1,118 @@
+"""Pins of the learned-CDF oracle (oracle/learned.py) against facts that do
+not come from it: finite differences of its own loss, the closed-form
+minimiser of the cross-entropy, the linear map of the untrained model, a
+library histogram, and monotonicity."""
+import numpy as np
+import pytest
+
+import kdgen
+from oracle import learned as L
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def test_gradient_matches_central_differences():
+    g = rng(1)
+    theta = g.normal(0, 2, size=L.K)
+    p = g.dirichlet(np.full(L.K, 0.3))
+    _, grad = L.loss_grad(theta, p)
+    h = 1e-5
+    idx = g.choice(L.K, size=64, replace=False)
+    for i in idx:
+        e = np.zeros(L.K)
+        e[i] = h
+        fd = (L.loss(theta + e, p) - L.loss(theta - e, p)) / (2 * h)
+        assert abs(fd - grad[i]) <= 1e-7 + 1e-5 * abs(grad[i]), i
+
+
+def test_minimiser_is_log_mass():
+    """The cross-entropy is minimised by q = p, i.e. theta = log p, where it
+    equals the entropy of p."""
+    g = rng(2)
+    p = g.dirichlet(np.ones(L.K))
+    theta = np.log(p)
+    val, grad = L.loss_grad(theta, p)
+    assert np.max(np.abs(grad)) < 1e-12
+    assert val == pytest.approx(-np.sum(p * np.log(p)), rel=1e-12)
+
+
+def test_adam_reaches_the_minimum():
+    g = rng(3)
+    p = g.dirichlet(np.full(L.K, 2.0))
+    th = L.train_adam(p, steps=300, lr=0.1)
+    kl = L.loss(th, p) + np.sum(p * np.log(p))
+    assert kl < 1e-3
+
+
+def test_untrained_model_is_the_linear_map():
+    g = rng(4)
+    vals = np.sort(g.integers(-(1 << 20), 1 << 20, size=5000).astype(np.int32))
+    keys = L.canonical(vals, False)
+    dm = L.Domain.of_sample(keys, False)
+    F = L.forward(L.levels(np.zeros(L.K)), dm, keys)
+    lin = (vals.astype(np.float64) - dm.lo) / (float(dm.hi) - float(dm.lo))
+    assert np.max(np.abs(F - lin)) < 1e-5
+
+
+def test_masses_equal_library_histogram():
+    """Integer values with (hi - lo) = 8 K: every segment is exactly 8 values
+    wide, so the masses are np.histogram's."""
+    g = rng(5)
+    vals = np.sort(g.integers(0, 8 * L.K + 1, size=20000)).astype(np.int32)
+    vals[0], vals[-1] = 0, 8 * L.K
+    keys = L.canonical(vals, False)
+    dm = L.Domain.of_sample(keys, False)
+    h, _ = np.histogram(vals, bins=L.K, range=(0, 8 * L.K))
+    assert np.array_equal(np.rint(L.masses(dm, keys) * len(vals)).astype(np.int64), h)
+
+
+def test_canonical_keys_follow_total_order():
+    vals = np.array([-np.inf, -3.5, -1e-30, -0.0, 0.0, 1e-45, 2.0, np.inf], dtype=np.float32)
+    keys = L.canonical(vals, True)
+    assert np.all(np.diff(keys.astype(np.int64)) > 0)
+    assert np.array_equal(L.key_value(keys, True).view(np.uint32), vals.view(np.uint32))
+    ints = np.array([-(2 ** 31), -1, 0, 1, 2 ** 31 - 1], dtype=np.int32)
+    ik = L.canonical(ints, False)
+    assert np.all(np.diff(ik.astype(np.int64)) > 0)
+    assert np.array_equal(L.key_value(ik, False), ints.astype(np.float32))
+
+
+@pytest.mark.parametrize("is_float", [False, True])
+def test_forward_and_buckets_are_monotone(is_float):
+    g = rng(6)
+    if is_float:
+        vals = kdgen.gaussian_mixture_f32(20000, 1, 8, 7)[:, 0]
+        vals[:20] = np.array([np.inf, -np.inf, np.nan, -0.0, 0.0] * 4, dtype=np.float32)
+    else:
+        vals = g.integers(-(2 ** 31), 2 ** 31, size=20000).astype(np.int32)
+    keys = np.sort(L.canonical(vals, is_float))
+    dm = L.Domain.of_sample(keys[::7], is_float)
+    c32 = L.levels(g.normal(0, 3, size=L.K)).astype(np.float32)
+    F = L.forward_f32(c32, dm, keys)
+    assert np.all(np.diff(F.astype(np.float64)) >= 0)
+    assert F.min() >= 0 and F.max() <= 1
+    b = L.bucket(F, 12)
+    assert np.all(np.diff(b) >= 0) and b.min() >= 0 and b.max() < 4096
+
+
+def test_trained_model_balances_mixture_buckets():
+    """What training buys on the heavy-tailed mixture: with the untrained
+    (linear) map the fullest of 2^10 buckets holds far more than its share;
+    after training it holds a few shares at most."""
+    x = kdgen.gaussian_mixture_f32(1 << 20, 3, 64, kdgen.SEED_BASE + 5)
+    sample = L.strided_sample(x, 1 << 16)
+    nb = 10
+    for d in range(3):
+        sk = np.sort(L.canonical(sample[:, d], True))
+        dm = L.Domain.of_sample(sk, True)
+        keys = L.canonical(x[:, d], True)
+        untrained = np.bincount(L.bucket(L.forward_f32(L.levels(np.zeros(L.K)).astype(np.float32),
+                                                       dm, keys), nb), minlength=1 << nb)
+        th = L.train_adam(L.masses(dm, sk), steps=300, lr=0.1)
+        trained = np.bincount(L.bucket(L.forward_f32(L.levels(th).astype(np.float32), dm, keys), nb),
+                              minlength=1 << nb)
+        mean = len(keys) / (1 << nb)
+        assert trained.max() < 4 * mean, d
+        assert untrained.max() > 2 * trained.max(), d
