@@ -1,23 +1,33 @@
 """Benchmark: balanced k-d tree build throughput on one MI355X.
 
-Workload (the headline configuration): k = 3, n = 2^24 int32 tuples uniform
-over the full signed range with 0.1% exact copies, one tree.  A step is one
-whole build -- presort by the three cyclic super keys, duplicate removal and
-the level-by-level partition -- with the tuples already resident in HBM and a
-preallocated workspace.  value = n / (time per step), in tuples/s.
+Headline workload: k = 3, n = 2^24 int32 tuples uniform over the full signed
+range with 0.1% exact copies, one tree.  A step is one whole build -- presort
+by the three cyclic super keys, duplicate removal and the level-by-level
+partition -- with the tuples already resident in HBM and a preallocated
+workspace.  value = n / (time per step), in tuples/s.
 
-Beside it: presort and partition phase times (measured on their own), the
-roofline of the dominant kernel (algorithmic bytes per launch over its average
-launch time, from HIP events the library records around that kernel on its own
-stream during the timed steps), and the CPU oracle timed on the host.
+Beside it (all on the same GPU, all bit-exact against the plain build):
+  * presort and partition phase times, and per-kernel-class time per step
+    (HIP events the library records around its own launches);
+  * the roofline of the dominant kernel class: algorithmic bytes per launch
+    over its average launch time, with HBM traffic from profiler counters
+    when they were taken for the current kernel sources;
+  * the learned-presort form on the headline input and on the 2^26 float32
+    Gaussian mixture, against the plain build on the same inputs;
+  * the batched form on 4096 point-cloud trees, against a host loop of plain
+    builds and as a replayed HIP graph;
+  * the CPU oracle timed on the host.
 
 Prints exactly one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -30,16 +40,20 @@ METRIC = "tuples/sec k-d build (k=3, n=2^24, bit-exact) plain vs batched/learned
 HBM_PEAK_GBS = 8000.0
 
 
-def onesweep_bytes(n: int, nu: int, k: int):
-    """(total algorithmic bytes, launches) of all radix scatter passes of one build.
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
-    Array 0 is sorted over all n rows, word by word; every pass moves its key
-    word and k payload words (the row id and the other key words), the first
-    one reading the tuple rows themselves.  Each of the k-1 chain sorts runs
-    over the n_unique rows and moves its key word and k payload words (row id,
-    ranks known so far, key words of the later sorts); its last pass drops the
-    key.  Every word read or written counts 4 bytes.
-    """
+
+# ---- algorithmic byte model ----------------------------------------------------------
+
+def onesweep_bytes(n: int, nu: int, k: int):
+    """(total algorithmic bytes, launches) of all radix scatter passes of one
+    plain build.  Array 0 is sorted over all n rows, word by word; every pass
+    moves its key word and k payload words (the row id and the other key
+    words), the first one reading the tuple rows themselves.  Each of the k-1
+    chain sorts runs over the n_unique rows and moves its key word and k
+    payload words (row id, ranks known so far, key words of the later sorts);
+    its last pass drops the key.  Every word read or written counts 4 bytes."""
     P = 4  # 8-bit digit passes per 32-bit word
     words = 0
     for w in range(k - 1, -1, -1):
@@ -53,8 +67,8 @@ def onesweep_bytes(n: int, nu: int, k: int):
 
 def level_bytes(nu: int, k: int, cutover: int):
     """(total algorithmic bytes, launches) of the global partition levels:
-    every array but the split one is read once and written once; records hold
-    k-1 ranks, plus the row id in array 0's."""
+    every array but the split one is read once and written once; records
+    hold k-1 ranks, plus the row id in array 0's."""
     R = k - 1
     levels = 0
     while (nu >> levels) > cutover:
@@ -83,6 +97,33 @@ def byte_model(kernel: str, n: int, nu: int, k: int, cutover: int):
     raise ValueError(kernel)
 
 
+# ---- profiler traffic ------------------------------------------------------------------
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1410_5420_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(os.path.basename(p).encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from a committed counter summary, if it was taken
+    for the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_sha = re.search(r"source digest:\s*`?([0-9a-f]+)", text)
+    m_val = re.search(r"traffic bytes per launch:\s*([0-9]+)", text)
+    if not m_sha or not m_val or m_sha.group(1) != source_digest():
+        return None
+    return int(m_val.group(1))
+
+
+# ---- CPU baseline -------------------------------------------------------------------
+
 def cpu_baseline(t: np.ndarray):
     import oracle
 
@@ -93,10 +134,23 @@ def cpu_baseline(t: np.ndarray):
     t0 = time.perf_counter()
     r = oracle.build_tree(t, threads=q, children=False)
     dt = time.perf_counter() - t0
-    return {"value": t.shape[0] / dt, "unit": "tuples/s", "cores": q, "kind": "oracle",
+    return {"value": round(t.shape[0] / dt, 1), "unit": "tuples/s", "cores": q, "kind": "oracle",
             "sample": f"one whole build of the same {t.shape[0]}-row input "
                       f"({dt:.1f} s; presort {r['times'][0]:.1f} s, partition {r['times'][1]:.1f} s), "
                       f"paper's parent/child threads, q={q}"}
+
+
+# ---- timing helpers ----------------------------------------------------------------
+
+def time_steps(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
 
 
 def main():
@@ -104,9 +158,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--probe", default="level", choices=["level", "onesweep", "leaf"])
     ap.add_argument("--cutover", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-forms", action="store_true", help="skip the learned and batched forms")
     ap.add_argument("--n", type=int, default=1 << 24, help=argparse.SUPPRESS)
     ap.add_argument("--calibrate", action="store_true",
                     help="first run one plain 256 MiB device copy (a reference for profiler byte counters)")
@@ -123,12 +177,13 @@ def main():
     from paper_1410_5420_amd import _lib
 
     n, k = args.n, 3
-    print(f"[bench] generating n={n} k={k}", file=sys.stderr, flush=True)
+    cutover = args.cutover or 1024
+    log(f"generating n={n} k={k}")
     t_host = kdgen.c2_full_range(n)
     dev = torch.device("cuda:0")
     t = torch.from_numpy(t_host).to(dev)
     b = kd.Builder(n, k, torch.int32, dev, cutover=args.cutover)
-    perm = torch.empty(n, dtype=torch.int32, device=dev)
+    perm = torch.full((n,), -1, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
 
     if args.calibrate:
@@ -141,21 +196,36 @@ def main():
         b.build(t, perm)
     torch.cuda.synchronize()
     nu = int(b.n_unique.item())
-    print(f"[bench] warmup done, n_unique={nu}", file=sys.stderr, flush=True)
+    log(f"warmup done, n_unique={nu}")
 
-    # timed region: K whole builds; the probe records the dominant kernel's launches
-    launches_per_step = {"level": 64, "onesweep": 4 * (2 * k - 1), "leaf": 1}[args.probe]
-    cap = launches_per_step * args.steps
-    _lib.probe_start(args.probe, cap)
+    # timed region: K whole builds; the library's probe times the level launches
+    cap = 64 * args.steps
+    _lib.probe_start("level", cap)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         b.build(t, perm)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    durations = _lib.probe_stop(cap)
+    durations = {"level": _lib.probe_stop(cap)}
     ms_per_step = elapsed * 1e3 / args.steps
-    print(f"[bench] {args.steps} steps, {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
+    log(f"{args.steps} steps, {ms_per_step:.3f} ms/step")
+
+    # the other kernel classes, each over its own (untimed) builds
+    for cls in ("onesweep", "leaf", "records", "dedup"):
+        reps = max(3, args.steps // 4)
+        c2 = 64 * reps
+        _lib.probe_start(cls, c2)
+        for _ in range(reps):
+            b.build(t, perm)
+        torch.cuda.synchronize()
+        durations[cls] = _lib.probe_stop(c2)
+        durations[cls + "_reps"] = reps
+    steps_of = {"level": args.steps}
+    class_ms = {}
+    for cls in ("level", "onesweep", "leaf", "records", "dedup"):
+        reps = steps_of.get(cls, durations.get(cls + "_reps", 1))
+        class_ms[cls] = round(float(np.sum(durations[cls])) / reps, 4)
 
     # phase split, measured separately with events on the same stream
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
@@ -170,15 +240,20 @@ def main():
         pre_ms.append(ev[0].elapsed_time(ev[1]))
         part_ms.append(ev[1].elapsed_time(ev[2]))
 
-    bytes_per_launch, unit_desc = byte_model(args.probe, n, nu, k, args.cutover or 1024)
-    # no-op launches (levels below the cutover for this n_unique) do not count
-    real = [d for d in durations if d > 0.002]
-    avg_ms = float(np.mean(real)) if real else float("nan")
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": args.probe, "avg_launch_ms": round(avg_ms, 4), "launches": len(real),
+    def roofline_of(cls):
+        bytes_per_launch, unit_desc = byte_model(cls, n, nu, k, cutover)
+        real = [d for d in durations[cls] if d > 0.002]  # no-op launches (levels past the cutover) excluded
+        avg_ms = float(np.mean(real)) if real else float("nan")
+        achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+        traffic = recorded_traffic(cls, "c2")
+        return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": cls,
+                "avg_launch_ms": round(avg_ms, 4), "launches": len(real),
                 "bytes_per_launch": int(bytes_per_launch), "byte_model": unit_desc}
+
+    dominant = max(("level", "onesweep"), key=lambda c: class_ms[c])
+    roofline = roofline_of(dominant)
+    secondary = roofline_of("onesweep" if dominant == "level" else "level")
 
     out = {
         "metric": METRIC,
@@ -195,16 +270,140 @@ def main():
         "data": "synthetic",
         "config": {"workload": "k=3, n=2^24 int32 uniform over the full signed range, 0.1% exact "
                                "copies (seeded); one plain build (presort + dedup + partition)",
-                   "k": k, "n": n, "n_unique": nu, "tuple_dtype": "int32",
-                   "cutover": args.cutover or 1024,
+                   "k": k, "n": n, "n_unique": nu, "tuple_dtype": "int32", "cutover": cutover,
                    "presort_ms": round(float(np.median(pre_ms)), 4),
-                   "partition_ms": round(float(np.median(part_ms)), 4)},
+                   "partition_ms": round(float(np.median(part_ms)), 4),
+                   "kernel_class_ms_per_step": class_ms},
         "roofline": roofline,
+        "roofline_secondary": secondary,
     }
+
+    if not args.no_forms:
+        plain_perm = perm.clone()
+        out["forms"] = {"learned_c2": learned_form(torch, kd, t, plain_perm, nu, args, "c2 (same input)")}
+        del b, t, perm, plain_perm
+        torch.cuda.empty_cache()
+        out["forms"]["learned_c5"] = learned_c5(torch, kd, kdgen, args)
+        torch.cuda.empty_cache()
+        out["forms"]["batched_c4"] = batched_c4(torch, kd, kdgen, args)
+        torch.cuda.empty_cache()
+
     if not args.no_cpu:
-        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(t_host)
     print(json.dumps(out), flush=True)
+
+
+def learned_form(torch, kd, t, plain_perm, nu, args, label):
+    """Learned build on an input already built plainly: training time, build
+    time, fallbacks, equality with the plain perm."""
+    n, k = t.shape
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    models = kd.train_cdf(t)
+    torch.cuda.synchronize()
+    train_ms = (time.perf_counter() - t0) * 1e3
+    lb = kd.LearnedBuilder(n, k, t.dtype)
+    perm = torch.full((n,), -1, dtype=torch.int32, device=t.device)
+    ms = time_steps(torch, lambda: lb.build(t, perm, models=models), max(3, args.steps // 2), 2)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    pre = []
+    for _ in range(3):
+        ev[0].record()
+        lb.presort(t, models=models)
+        ev[1].record()
+        torch.cuda.synchronize()
+        pre.append(ev[0].elapsed_time(ev[1]))
+    lb.build(t, perm, models=models)
+    torch.cuda.synchronize()
+    same = int(lb.n_unique.item()) == nu and torch.equal(perm[:nu], plain_perm[:nu])
+    res = {"workload": label, "n": n, "train_ms": round(train_ms, 3), "ms_per_build": round(ms, 4),
+           "tuples_per_s": round(n / (ms * 1e-3), 1), "presort_ms": round(float(np.median(pre)), 4),
+           "fell_back": lb.fell_back.cpu().numpy().tolist(), "bit_exact_vs_plain": bool(same)}
+    log(f"learned {label}: {ms:.3f} ms/build, presort {res['presort_ms']} ms, fell_back {res['fell_back']}")
+    return res
+
+
+def learned_c5(torch, kd, kdgen, args):
+    log("generating the 2^26 float32 mixture")
+    x = kdgen.c5_mixture()
+    t = torch.from_numpy(x).cuda()
+    del x
+    n, k = t.shape
+    b = kd.Builder(n, k, torch.float32)
+    perm = torch.full((n,), -1, dtype=torch.int32, device=t.device)
+    reps = max(3, args.steps // 4)
+    plain_ms = time_steps(torch, lambda: b.build(t, perm), reps, 2)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    pre = []
+    for _ in range(3):
+        ev[0].record()
+        b.presort(t)
+        ev[1].record()
+        torch.cuda.synchronize()
+        pre.append(ev[0].elapsed_time(ev[1]))
+    nu = int(b.n_unique.item())
+    del b
+    torch.cuda.empty_cache()
+    res = learned_form(torch, kd, t, perm, nu, args, "k=3, n=2^26 float32 mixture of 64 anisotropic Gaussians")
+    res["plain_ms_per_build"] = round(plain_ms, 4)
+    res["plain_presort_ms"] = round(float(np.median(pre)), 4)
+    res["speedup_vs_plain"] = round(plain_ms / res["ms_per_build"], 3)
+    log(f"c5 plain {plain_ms:.3f} ms, learned {res['ms_per_build']} ms")
+    return res
+
+
+def batched_c4(torch, kd, kdgen, args):
+    log("generating 4096 point-cloud trees")
+    x, offsets = kdgen.c4_batched()
+    t = torch.from_numpy(x).cuda()
+    total = int(offsets[-1])
+    B = len(offsets) - 1
+    bb = kd.BatchedBuilder(offsets, 3, torch.float32)
+    perm_b = torch.full((total,), -1, dtype=torch.int32, device=t.device)
+    reps = max(3, args.steps // 4)
+    batched_ms = time_steps(torch, lambda: bb.build(t, perm_b), reps, 2)
+
+    # the same build captured once into a HIP graph and replayed
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        bb.build(t, perm_b)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        bb.build(t, perm_b)
+    graph_ms = time_steps(torch, g.replay, reps, 1)
+    nub = bb.n_unique.clone()
+
+    # a host loop of plain builds, one per tree, on the same stream
+    maxn = int(np.max(np.diff(offsets)))
+    pb = kd.Builder(maxn, 3, torch.float32)
+    perm_l = torch.full((total,), -1, dtype=torch.int32, device=t.device)
+    views = [(t[int(offsets[i]):int(offsets[i + 1])], perm_l[int(offsets[i]):int(offsets[i + 1])])
+             for i in range(B)]
+
+    def loop():
+        for tv, pv in views:
+            pb.build(tv, pv)
+
+    loop_ms = time_steps(torch, loop, 1, 1)
+    torch.cuda.synchronize()
+    # bit-exact: every tree of the batch equals its plain build (positions
+    # past n_unique stay -1 on both sides)
+    perm_b.fill_(-1)
+    bb.build(t, perm_b)
+    torch.cuda.synchronize()
+    same = torch.equal(perm_b, perm_l) and torch.equal(bb.n_unique, nub)
+    res = {"workload": f"{B} float32 point-cloud trees, n_i log-uniform in [64, 65536], k=3",
+           "trees": B, "rows": total, "ms_per_build": round(batched_ms, 4),
+           "tuples_per_s": round(total / (batched_ms * 1e-3), 1),
+           "graph_replay_ms": round(graph_ms, 4),
+           "host_loop_of_plain_builds_ms": round(loop_ms, 3),
+           "speedup_vs_loop": round(loop_ms / batched_ms, 2), "bit_exact_vs_loop": bool(same)}
+    log(f"batched: {batched_ms:.3f} ms (graph {graph_ms:.3f}), loop {loop_ms:.1f} ms, same={same}")
+    return res
 
 
 if __name__ == "__main__":

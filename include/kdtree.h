@@ -132,13 +132,15 @@ int kdtree_build_batched(const void* d_tuples, const int64_t* d_offsets, const i
  * exactly the tree kdtree_build produces.
  *
  * Model: per dimension, a piecewise-linear CDF over KD_CDF_SEGMENTS equal
- * segments of the sample's finite value range, whose segment masses are the
- * softmax of trainable logits.  kd_cdf_train() fits them on the GPU: it takes
- * a strided sample of n_samples rows (row floor(s * n / n_samples)), presorts
- * each dimension's sample with the radix passes, reads the mass of every
- * segment off the sample's ranks, and runs `steps` Adam steps (beta1 0.9,
- * beta2 0.999, eps 1e-8, step size lr) from all-zero logits on the
- * cross-entropy between the model's masses and the sample's.  A model buffer
+ * segments of the column's finite value range, whose segment masses are the
+ * softmax of trainable logits.  kd_cdf_train() fits them on the GPU: it
+ * takes the finite range of every column, a strided sample of n_samples rows
+ * (row floor(s * n / n_samples)), presorts each dimension's sample with the
+ * radix passes, reads the mass of every segment off the sample's ranks, and
+ * runs `steps` Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, step size lr)
+ * from all-zero logits on the cross-entropy between the model's masses and
+ * the sample's.  The exported levels floor every segment's mass at
+ * 1/(4 n_samples) and renormalise.  A model buffer
  * holds k consecutive records of KD_CDF_MODEL_BYTES bytes:
  *   float lo, hi, scale; uint32 kmin, kmax; int32 is_float, segments;
  *   float loss; float c[KD_CDF_SEGMENTS + 1]; float theta[KD_CDF_SEGMENTS];
@@ -147,8 +149,8 @@ int kdtree_build_batched(const void* d_tuples, const int64_t* d_offsets, const i
  * c[K] = 1, non-decreasing); kmin / kmax are the order-preserving keys of lo
  * and hi.  A model trained on one data set may be reused for others of the
  * same dtype: a poor model costs speed (fallbacks), never correctness.      */
-#define KD_CDF_SEGMENTS 1024
-#define KD_CDF_MODEL_BYTES 8448
+#define KD_CDF_SEGMENTS 4096
+#define KD_CDF_MODEL_BYTES 33024
 #define KD_CDF_MAX_SAMPLES (1 << 20)
 #define KD_CDF_MAX_STEPS 100000
 

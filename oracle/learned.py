@@ -7,9 +7,11 @@ The model is not in the paper.  It only guesses where a key lands in the
 sorted order; the presort it serves must return exactly what the radix presort
 returns, so the model changes speed, never results.
 
-Definition.  K segments split the finite value range [lo, hi] of a sample
-evenly.  Logits theta[0..K-1] give segment masses q = softmax(theta) and the
-cumulative levels c_0 = 0, c_i = q_0 + ... + q_{i-1}, c_K = 1.  For a key
+Definition.  K segments split a finite value range [lo, hi] evenly (the
+trained model uses the column's finite range).  Logits theta[0..K-1] give segment masses q = softmax(theta); the
+exported model floors every mass at 1/(4S) for a sample of S keys and
+renormalises (q' = (q + 1/(4S)) / (1 + K/(4S))), and its cumulative levels
+are c_0 = 0, c_i = q'_0 + ... + q'_{i-1}, c_K = 1.  For a key
 strictly between the keys of lo and hi, with value v:
 
     t = (v - lo) * scale,   scale = K / (hi - lo)
@@ -35,7 +37,7 @@ from __future__ import annotations
 
 import numpy as np
 
-K = 1024
+K = 4096
 
 
 # ---- keys ----------------------------------------------------------------------
@@ -88,6 +90,15 @@ class Domain:
         if len(fin) == 0:
             return Domain(0x80000000, 0x80000000, is_float)
         return Domain(int(sorted_keys[fin[0]]), int(sorted_keys[fin[-1]]), is_float)
+
+    @staticmethod
+    def of_column(keys: np.ndarray, is_float: bool) -> "Domain":
+        """The finite range of a whole column (the trained model's domain)."""
+        keys = np.asarray(keys, dtype=np.uint32)
+        fk = keys[finite(keys, is_float)]
+        if len(fk) == 0:
+            return Domain(0x80000000, 0x80000000, is_float)
+        return Domain(int(fk.min()), int(fk.max()), is_float)
 
 
 def segments_f32(dm: Domain, keys: np.ndarray):
@@ -154,9 +165,15 @@ def train_adam(p: np.ndarray, steps: int, lr: float, b1=0.9, b2=0.999, eps=1e-8)
     return th
 
 
-def levels(theta: np.ndarray) -> np.ndarray:
-    """c_0 .. c_K (fp64): running sums of the segment masses, c_K = 1."""
+def levels(theta: np.ndarray, S: int = 0) -> np.ndarray:
+    """c_0 .. c_K (fp64): running sums of the segment masses, c_K = 1.  With
+    a sample size S, every mass first gets a floor of 1/(4S) and the masses
+    are renormalised (the exported model; segments the sample missed still
+    cover some range)."""
     q = softmax(theta)
+    if S > 0:
+        fl = 0.25 / S
+        q = (q + fl) / (1.0 + len(q) * fl)
     c = np.concatenate([[0.0], np.cumsum(q)])
     c[-1] = 1.0
     return np.minimum(c, 1.0)

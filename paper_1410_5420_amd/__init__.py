@@ -153,11 +153,11 @@ def build(tuples: torch.Tensor, children: bool = False, cutover: int | None = No
 
 # ---- learned presort ------------------------------------------------------------
 
-def train_cdf(tuples: torch.Tensor, n_samples: int = 1 << 16, steps: int = 300, lr: float = 0.1,
+def train_cdf(tuples: torch.Tensor, n_samples: int = 1 << 18, steps: int = 300, lr: float = 0.1,
               stream=None) -> torch.Tensor:
     """Train one CDF model per dimension on the GPU (kd_cdf_train).
 
-    Returns the model buffer (uint8 device tensor of k * 8448 bytes)."""
+    Returns the model buffer (uint8 device tensor of k * 33024 bytes)."""
     if tuples.dim() != 2 or not tuples.is_cuda or not tuples.is_contiguous():
         raise ValueError("tuples must be a contiguous (n, k) device tensor")
     n, k = tuples.shape

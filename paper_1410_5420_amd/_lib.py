@@ -83,8 +83,8 @@ EXPORTED = ["kd_strerror", "kdtree_workspace_bytes", "kdtree_build", "kdtree_pre
 KERNEL_CLASSES = {"onesweep": 1, "level": 2, "leaf": 3, "dedup": 4, "hist": 5, "canon": 6,
                   "records": 7, "bucket": 8}
 
-CDF_SEGMENTS = 1024
-CDF_MODEL_BYTES = 8448
+CDF_SEGMENTS = 4096
+CDF_MODEL_BYTES = 33024
 
 
 def probe_start(kernel: str, capacity: int) -> None:

@@ -269,6 +269,8 @@ int learned_sort(std::vector<Quant> q, const LearnedSort& ls, const TupleSrc& ts
   }
   lso.nkeys = (int)ls.sortq.size();
   for (int w = 0; w < lso.nkeys; ++w) lso.keyq[w] = ls.sortq[w];
+  lso.model = ls.model;
+  lso.nb_bits = ls.nb_bits;
   KD_LAUNCH(KD_K_BUCKET, launch_bucket_sort(ls.starts, ls.nb_bits, n, n_dev, ls.flag, lso, st));
   CertArgs ca{};
   ca.nw = (int)ls.certq.size();
@@ -544,7 +546,7 @@ int presort_learned(const Job& J, hipStream_t st) {
 
 // ---- model training (host side) -----------------------------------------------------
 struct TrainLayout {
-  size_t a, b, cnt, grp, end;
+  size_t a, b, cnt, grp, range, end;
 };
 TrainLayout train_plan(int k, int S) {
   TrainLayout T{};
@@ -558,6 +560,7 @@ TrainLayout train_plan(int k, int S) {
   T.b = take(4 * (size_t)k * S);
   T.cnt = take(4 * (size_t)radix_count_words(S));
   T.grp = take(4 * (size_t)radix_group_words(S));
+  T.range = take(4 * 2 * (size_t)k);
   T.end = o;
   return T;
 }
@@ -740,7 +743,9 @@ int kd_cdf_train(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, int3
       std::swap(x, y);
     }
   }
-  KD_TRY(kd::launch_cdf_fit(a, n_samples, k, is_float, steps, lr,
+  uint32_t* range = kd::at<uint32_t>(d_workspace, T.range);
+  KD_TRY(kd::launch_col_range(static_cast<const uint32_t*>(d_tuples), n, k, is_float, range, st));
+  KD_TRY(kd::launch_cdf_fit(a, n_samples, k, is_float, range, steps, lr,
                             static_cast<kd::CdfModel*>(d_models), st));
   return KD_OK;
 }

@@ -133,7 +133,7 @@ __device__ __host__ __forceinline__ int cutover_depth(int64_t nu, int64_t cutove
 // canonical (order-preserving) 32-bit words; at or below kmin F is 0, at or
 // above kmax it is 1.  The model changes only where keys land, never the
 // sorted result.
-constexpr int kCdfSegments = 1024;
+constexpr int kCdfSegments = 4096;
 struct CdfModel {
   float lo, hi;      // value range of the training sample (finite values)
   float scale;       // K / (hi - lo), or 0 for a degenerate range
@@ -146,7 +146,7 @@ struct CdfModel {
   float theta[kCdfSegments];  // trained parameters (segment-mass logits)
   float pad[55];
 };
-static_assert(sizeof(CdfModel) == 8448, "model size is part of the ABI");
+static_assert(sizeof(CdfModel) == 33024, "model size is part of the ABI");
 
 // Order-preserving 32-bit key of a coordinate: int32 with the sign bit
 // flipped (signed order); float32 under IEEE totalOrder (negative encodings

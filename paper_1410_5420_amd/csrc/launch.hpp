@@ -132,9 +132,14 @@ hipError_t launch_copy_k1(const uint32_t* S0, const ForestArgs& fa, int64_t n, i
 // Sample of S canonical keys per dimension (rows floor(s * n / S)); out [k][S].
 hipError_t launch_cdf_sample(const uint32_t* t, int64_t n, int k, int is_float, int S, uint32_t* out,
                              hipStream_t st);
-// Train k models (one workgroup each) on the sorted samples [k][S].
-hipError_t launch_cdf_fit(const uint32_t* sorted, int S, int k, int is_float, int steps, float lr,
-                          CdfModel* models, hipStream_t st);
+// Finite range of every column: range[2d], range[2d+1] = smallest, largest
+// canonical key of dimension d among its finite values.
+hipError_t launch_col_range(const uint32_t* t, int64_t n, int k, int is_float, uint32_t* range,
+                            hipStream_t st);
+// Train k models (one workgroup each) on the sorted samples [k][S] over the
+// column ranges.
+hipError_t launch_cdf_fit(const uint32_t* sorted, int S, int k, int is_float, const uint32_t* range,
+                          int steps, float lr, CdfModel* models, hipStream_t st);
 // Loss and gradient of the training objective on a sorted raw sample.
 // keys: M words of scratch.
 hipError_t launch_cdf_loss_grad(const uint32_t* raw, int M, int is_float, uint32_t lo_bits,
@@ -157,6 +162,8 @@ struct LocalSort {
   uint32_t* out[kMaxPlanes];
   int nkeys;
   int keyq[kMaxK];
+  const CdfModel* model;  // the model the buckets were cut with
+  int nb_bits;            // 2^nb_bits buckets
 };
 hipError_t launch_bucket_sort(const int32_t* starts, int nb_bits, int64_t n, const int32_t* n_dev,
                               int32_t* flag, const LocalSort& ls, hipStream_t st);

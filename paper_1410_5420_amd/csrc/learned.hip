@@ -12,7 +12,7 @@
 // raises a flag, and the radix sort then runs in its place (gated on the
 // flag, so nothing waits on the host).
 //
-// The model (common.hpp) is a piecewise-linear CDF over K = 1024 equal value
+// The model (common.hpp) is a piecewise-linear CDF over K = 4096 equal value
 // segments.  Its parameters are logits theta of the segment masses q =
 // softmax(theta); it is trained by Adam on the cross-entropy between q and
 // the masses that the ranks of a presorted sample of the keys give (the mass
@@ -25,7 +25,8 @@
 namespace kd {
 
 constexpr int kFitThreads = 1024;
-static_assert(kFitThreads == kCdfSegments, "thread j owns segment j");
+constexpr int kSegPer = kCdfSegments / kFitThreads;  // segments owned by one thread
+static_assert(kSegPer * kFitThreads == kCdfSegments, "thread j owns segments j*kSegPer ..");
 
 // ---- block reductions (1024 threads, fixed order, deterministic) --------------
 
@@ -87,38 +88,56 @@ __device__ __forceinline__ int sample_segment(const Domain& dm, uint32_t key, in
   return cdf_segment(cdf_key_value(key, is_float), dm.lo, dm.scale, &f);
 }
 
-// Segment masses from the ranks of the sorted sample: thread j finds the rank
-// of the first sample in segment >= j; p_j = (start_{j+1} - start_j) / S.
-__device__ float segment_mass(const uint32_t* keys, int S, const Domain& dm, int is_float,
-                              int32_t* s_start) {
-  const int j = threadIdx.x;
-  int lo = 0, hi = S;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (sample_segment(dm, keys[mid], is_float) < j)
-      lo = mid + 1;
-    else
-      hi = mid;
+// Segment masses from the ranks of the sorted sample: the rank of the first
+// sample in segment >= j is found by binary search (thread j owns segments
+// j*kSegPer ..); p_j = (start_{j+1} - start_j) / S.
+__device__ void segment_mass(const uint32_t* keys, int S, const Domain& dm, int is_float,
+                             int32_t* s_start, float (&p)[kSegPer]) {
+#pragma unroll
+  for (int r = 0; r < kSegPer; ++r) {
+    const int j = threadIdx.x * kSegPer + r;
+    int lo = 0, hi = S;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (sample_segment(dm, keys[mid], is_float) < j)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    s_start[j] = lo;
   }
-  s_start[j] = lo;
-  if (j == 0) s_start[kCdfSegments] = S;
+  if (threadIdx.x == 0) s_start[kCdfSegments] = S;
   __syncthreads();
-  const float p = S > 0 ? (float)(s_start[j + 1] - s_start[j]) / (float)S : 0.f;
+#pragma unroll
+  for (int r = 0; r < kSegPer; ++r) {
+    const int j = threadIdx.x * kSegPer + r;
+    p[r] = S > 0 ? (float)(s_start[j + 1] - s_start[j]) / (float)S : 0.f;
+  }
   __syncthreads();
-  return p;
 }
 
-// q_j = softmax(theta)_j over the block (thread j holds theta_j).
-__device__ float softmax_mass(float th, float* s_tmp) {
-  const float mx = block_reduce(th, s_tmp, OpMax());
-  const float e = expf(th - mx);
-  const float sum = block_reduce(e, s_tmp, OpAdd());
-  return e / sum;
+// q = softmax(theta) over the block's kCdfSegments logits.
+__device__ void softmax_mass(const float (&th)[kSegPer], float* s_tmp, float (&q)[kSegPer]) {
+  float mx = th[0];
+#pragma unroll
+  for (int r = 1; r < kSegPer; ++r) mx = fmaxf(mx, th[r]);
+  mx = block_reduce(mx, s_tmp, OpMax());
+  float e[kSegPer], sum = 0.f;
+#pragma unroll
+  for (int r = 0; r < kSegPer; ++r) {
+    e[r] = expf(th[r] - mx);
+    sum += e[r];
+  }
+  sum = block_reduce(sum, s_tmp, OpAdd());
+#pragma unroll
+  for (int r = 0; r < kSegPer; ++r) q[r] = e[r] / sum;
 }
 
 // Cross-entropy -sum_j p_j log q_j.
-__device__ float cross_entropy(float p, float q, float* s_tmp) {
-  const float term = p > 0.f ? -p * logf(fmaxf(q, 1e-30f)) : 0.f;
+__device__ float cross_entropy(const float (&p)[kSegPer], const float (&q)[kSegPer], float* s_tmp) {
+  float term = 0.f;
+#pragma unroll
+  for (int r = 0; r < kSegPer; ++r) term += p[r] > 0.f ? -p[r] * logf(fmaxf(q[r], 1e-30f)) : 0.f;
   return block_reduce(term, s_tmp, OpAdd());
 }
 
@@ -138,16 +157,59 @@ __global__ void k_cdf_sample(const uint32_t* __restrict__ t, int64_t n, int k, i
   }
 }
 
+// Finite range of every column: range[2d] = smallest, range[2d + 1] =
+// largest canonical key among the finite values of dimension d (ranges
+// start as [0xFFFFFFFF, 0], which also marks a column with none).
+__global__ void k_col_range(const uint32_t* __restrict__ t, int64_t n, int k, int is_float,
+                            uint32_t* __restrict__ range) {
+  uint32_t mn[kMaxK], mx[kMaxK];
+#pragma unroll
+  for (int d = 0; d < kMaxK; ++d) {
+    mn[d] = 0xFFFFFFFFu;
+    mx[d] = 0u;
+  }
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
+       r += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int d = 0; d < kMaxK; ++d) {
+      if (d < k) {
+        const uint32_t key = canon_word(t[r * k + d], is_float != 0);
+        if (finite_key(key, is_float)) {
+          mn[d] = min(mn[d], key);
+          mx[d] = max(mx[d], key);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < kMaxK; ++d) {
+    if (d >= k) continue;
+    uint32_t a = mn[d], b = mx[d];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      a = min(a, (uint32_t)__shfl_xor((int)a, o, kWave));
+      b = max(b, (uint32_t)__shfl_xor((int)b, o, kWave));
+    }
+    if (lane_id() == 0) {
+      atomicMin(&range[2 * d], a);
+      atomicMax(&range[2 * d + 1], b);
+    }
+  }
+}
+
 struct AdamCfg {
   int steps;
   float lr, b1, b2, eps;
 };
 
-// One block per dimension: domain from the sorted sample, masses from its
-// ranks, Adam from theta = 0 (the untrained model is the linear map of
-// [lo, hi]), then the cumulative levels c.
+// One block per dimension: domain from the column's finite range, masses
+// from the sorted sample's ranks, Adam from theta = 0 (the untrained model is
+// the linear map of [lo, hi]), then the cumulative levels c (with a small
+// mass floor).
 __global__ __launch_bounds__(kFitThreads) void k_cdf_fit(const uint32_t* __restrict__ sorted,
-                                                         int S, int is_float, AdamCfg cfg,
+                                                         int S, int is_float,
+                                                         const uint32_t* __restrict__ range,
+                                                         AdamCfg cfg,
                                                          CdfModel* __restrict__ models) {
   __shared__ float s_tmp[kFitThreads / kWave];
   __shared__ int32_t s_itmp[kFitThreads / kWave];
@@ -158,47 +220,51 @@ __global__ __launch_bounds__(kFitThreads) void k_cdf_fit(const uint32_t* __restr
   const uint32_t* keys = sorted + (int64_t)d * S;
   CdfModel* m = models + d;
 
-  // finite range of the sample (NaN and infinities sit at the two ends)
-  int first = S, last = -1;
-  for (int i = j; i < S; i += kFitThreads) {
-    if (finite_key(keys[i], is_float)) {
-      first = min(first, i);
-      last = max(last, i);
-    }
-  }
-  first = block_reduce(first, s_itmp, OpMin());
-  last = block_reduce(last, s_itmp, OpMax());
-  uint32_t kmin = 0x80000000u, kmax = 0x80000000u;
-  if (last >= 0) {
-    kmin = keys[first];
-    kmax = keys[last];
-  }
+  // the domain is the column's finite range (so the tails beyond the
+  // sample's extremes stay inside it)
+  (void)s_itmp;
+  uint32_t kmin = range[2 * d], kmax = range[2 * d + 1];
+  if (kmin > kmax) kmin = kmax = 0x80000000u;  // no finite value
   const Domain dm = make_domain(kmin, kmax, is_float);
-  const float p = segment_mass(keys, S, dm, is_float, s_start);
+  float p[kSegPer];
+  segment_mass(keys, S, dm, is_float, s_start, p);
 
-  float th = 0.f, m1 = 0.f, m2 = 0.f, b1t = 1.f, b2t = 1.f;
+  float th[kSegPer], m1[kSegPer], m2[kSegPer], q[kSegPer];
+#pragma unroll
+  for (int r = 0; r < kSegPer; ++r) th[r] = m1[r] = m2[r] = 0.f;
+  float b1t = 1.f, b2t = 1.f;
   for (int step = 0; step < cfg.steps; ++step) {
-    const float q = softmax_mass(th, s_tmp);
-    const float g = q - p;
-    m1 = cfg.b1 * m1 + (1.f - cfg.b1) * g;
-    m2 = cfg.b2 * m2 + (1.f - cfg.b2) * g * g;
+    softmax_mass(th, s_tmp, q);
     b1t *= cfg.b1;
     b2t *= cfg.b2;
-    const float mh = m1 / (1.f - b1t);
-    const float vh = m2 / (1.f - b2t);
-    th -= cfg.lr * mh / (sqrtf(vh) + cfg.eps);
+#pragma unroll
+    for (int r = 0; r < kSegPer; ++r) {
+      const float g = q[r] - p[r];
+      m1[r] = cfg.b1 * m1[r] + (1.f - cfg.b1) * g;
+      m2[r] = cfg.b2 * m2[r] + (1.f - cfg.b2) * g * g;
+      const float mh = m1[r] / (1.f - b1t);
+      const float vh = m2[r] / (1.f - b2t);
+      th[r] -= cfg.lr * mh / (sqrtf(vh) + cfg.eps);
+    }
   }
-  const float q = softmax_mass(th, s_tmp);
+  softmax_mass(th, s_tmp, q);
   const float loss = cross_entropy(p, q, s_tmp);
-  s_q[j] = q;
-  m->theta[j] = th;
+#pragma unroll
+  for (int r = 0; r < kSegPer; ++r) {
+    s_q[j * kSegPer + r] = q[r];
+    m->theta[j * kSegPer + r] = th[r];
+  }
   __syncthreads();
   if (j == 0) {
-    // sequential cumulative sum: non-decreasing by construction
+    // Levels: every segment keeps a mass of at least 1/(4S) (regions the
+    // sample missed still spread over a slice of buckets), renormalised; a
+    // sequential cumulative sum is non-decreasing by construction.
+    const float floor_mass = S > 0 ? 0.25f / (float)S : 0.f;
+    const float norm = 1.f / (1.f + (float)kCdfSegments * floor_mass);
     float run = 0.f;
     for (int i = 0; i < kCdfSegments; ++i) {
       m->c[i] = fminf(run, 1.f);
-      run += s_q[i];
+      run += (s_q[i] + floor_mass) * norm;
     }
     m->c[kCdfSegments] = 1.f;
     m->lo = dm.lo;
@@ -227,10 +293,14 @@ __global__ __launch_bounds__(kFitThreads) void k_cdf_loss_grad(const uint32_t* _
   __syncthreads();
   const Domain dm = make_domain(canon_word(lo_bits, is_float != 0), canon_word(hi_bits, is_float != 0),
                                 is_float);
-  const float p = segment_mass(keys, M, dm, is_float, s_start);
-  const float q = softmax_mass(theta[threadIdx.x], s_tmp);
+  float p[kSegPer], th[kSegPer], q[kSegPer];
+  segment_mass(keys, M, dm, is_float, s_start, p);
+#pragma unroll
+  for (int r = 0; r < kSegPer; ++r) th[r] = theta[threadIdx.x * kSegPer + r];
+  softmax_mass(th, s_tmp, q);
   const float L = cross_entropy(p, q, s_tmp);
-  grad[threadIdx.x] = q - p;
+#pragma unroll
+  for (int r = 0; r < kSegPer; ++r) grad[threadIdx.x * kSegPer + r] = q[r] - p[r];
   if (threadIdx.x == 0) *loss = L;
 }
 
@@ -260,10 +330,26 @@ hipError_t launch_cdf_sample(const uint32_t* t, int64_t n, int k, int is_float, 
   return hipGetLastError();
 }
 
-hipError_t launch_cdf_fit(const uint32_t* sorted, int S, int k, int is_float, int steps, float lr,
-                          CdfModel* models, hipStream_t st) {
+hipError_t launch_col_range(const uint32_t* t, int64_t n, int k, int is_float, uint32_t* range,
+                            hipStream_t st) {
+  hipError_t e = launch_fill_u32(range, 0u, 2 * k, st);  // maxima start at 0
+  if (e != hipSuccess) return e;
+  for (int d = 0; d < k; ++d) {
+    e = launch_fill_u32(range + 2 * d, 0xFFFFFFFFu, 1, st);  // minima at the top
+    if (e != hipSuccess) return e;
+  }
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_col_range, dim3((unsigned)blocks), dim3(256), 0, st, t, n, k, is_float, range);
+  return hipGetLastError();
+}
+
+hipError_t launch_cdf_fit(const uint32_t* sorted, int S, int k, int is_float, const uint32_t* range,
+                          int steps, float lr, CdfModel* models, hipStream_t st) {
   AdamCfg cfg{steps, lr, 0.9f, 0.999f, 1e-8f};
-  hipLaunchKernelGGL(k_cdf_fit, dim3(k), dim3(kFitThreads), 0, st, sorted, S, is_float, cfg, models);
+  hipLaunchKernelGGL(k_cdf_fit, dim3(k), dim3(kFitThreads), 0, st, sorted, S, is_float, range, cfg,
+                     models);
   return hipGetLastError();
 }
 
@@ -334,93 +420,20 @@ hipError_t launch_bucket_bounds(const uint32_t* keys, int64_t n, const int32_t* 
 
 constexpr int kBsThreads = 512;
 constexpr int kBsWaves = kBsThreads / kWave;
-constexpr int kBsCap = 8192;
-constexpr int kBsMaxItems = kBsCap / kBsThreads;  // 16
+constexpr int kBsCap = 4096;      // most keys a workgroup sorts at once (two workgroups per CU)
+constexpr int kBsItems = kBsCap / kBsThreads;
+constexpr int kBsMaxBins = kBsCap / 2;  // CDF interpolation bins per unit (plus up to half as many tail bins)
+constexpr int kBsDenseBin = 64;   // larger bins are ranked by the whole workgroup
+constexpr int kBsMaxDense = kBsCap; // largest bin a workgroup ranks
+constexpr int kBsMaxBig = 64;     // most such bins per unit
+constexpr int kBsPrefetch = 3;    // output planes loaded into registers while the unit sorts
+constexpr int kBsLdsTies = 2;     // tie-break words held in LDS (later ones are read from memory)
 
-size_t bucket_sort_lds_bytes() { return (size_t)kBsCap * (4 + 4 + 4 + 2 + 2); }
+// primary word, two tie-break words (all three reused as output staging),
+// and the sorted order
+size_t bucket_sort_lds_bytes() { return (size_t)kBsCap * (4 * (1 + kBsLdsTies) + 2); }
 int bucket_sort_capacity() { return kBsCap; }
-
-// Stable LSD radix sort of N <= kBsCap (key, 16-bit value) pairs in LDS over
-// `passes` 8-bit digits.  Wave w owns elements [w * items * 64, (w+1) *
-// items * 64), items = ceil(N / kBsThreads).  Returns true when the result is
-// in (kb, vb).
-__device__ bool bucket_lds_sort(uint32_t* ka, uint16_t* va, uint32_t* kb, uint16_t* vb, int N,
-                                int passes, uint32_t (*s_cnt)[kRadix], uint32_t* s_dbase,
-                                uint32_t* s_tmp) {
-  const int tid = threadIdx.x;
-  const int w = tid / kWave;
-  const int lane = tid % kWave;
-  const uint64_t below = lanes_below_mask();
-  const int items = (N + kBsThreads - 1) / kBsThreads;
-  const int per_wave = items * kWave;
-  bool flipped = false;
-  for (int ps = 0; ps < passes; ++ps) {
-    const int shift = ps * kRadixBits;
-    for (int q = tid; q < kBsWaves * kRadix; q += kBsThreads) (&s_cnt[0][0])[q] = 0;
-    __syncthreads();
-    uint32_t key[kBsMaxItems], rank[kBsMaxItems];
-    uint16_t val[kBsMaxItems];
-#pragma unroll
-    for (int j = 0; j < kBsMaxItems; ++j) {
-      if (j < items) {
-        const int e = w * per_wave + j * kWave + lane;
-        const bool valid = e < N;
-        key[j] = valid ? ka[e] : 0u;
-        val[j] = valid ? va[e] : (uint16_t)0;
-        const uint32_t d = (key[j] >> shift) & 0xFF;
-        uint64_t m = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < kRadixBits; ++b) {
-          const bool bit = (d >> b) & 1;
-          const uint64_t bb = __ballot(bit);
-          m &= bit ? bb : ~bb;
-        }
-        uint32_t pre = 0;
-        if (valid) pre = s_cnt[w][d];
-        __builtin_amdgcn_wave_barrier();
-        const uint32_t before = popc64(m & below);
-        if (valid && before == 0) s_cnt[w][d] = pre + popc64(m);
-        __builtin_amdgcn_wave_barrier();
-        rank[j] = pre + before;
-      }
-    }
-    __syncthreads();
-    uint32_t tot = 0;
-    if (tid < kRadix) {
-#pragma unroll
-      for (int q = 0; q < kBsWaves; ++q) {
-        const uint32_t c = s_cnt[q][tid];
-        s_cnt[q][tid] = tot;
-        tot += c;
-      }
-    }
-    uint32_t all;
-    const uint32_t ex = block_exclusive_sum<kBsThreads>(tot, s_tmp, &all);
-    if (tid < kRadix) s_dbase[tid] = ex;
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kBsMaxItems; ++j) {
-      if (j < items) {
-        const int e = w * per_wave + j * kWave + lane;
-        if (e < N) {
-          const uint32_t d = (key[j] >> shift) & 0xFF;
-          const uint32_t dest = s_dbase[d] + s_cnt[w][d] + rank[j];
-          kb[dest] = key[j];
-          vb[dest] = val[j];
-        }
-      }
-    }
-    __syncthreads();
-    uint32_t* tk = ka;
-    ka = kb;
-    kb = tk;
-    uint16_t* tv = va;
-    va = vb;
-    vb = tv;
-    flipped = !flipped;
-  }
-  return flipped;
-}
+int bucket_sort_target() { return kBsCap / 2; }
 
 template <typename T, typename Op>
 __device__ __forceinline__ T bs_reduce(T v, T* s_red, Op op) {
@@ -444,26 +457,345 @@ __device__ __forceinline__ T pick(const T (&arr)[N], int i) {
   return r;
 }
 
-// One workgroup per bucket: the bucket's elements (in stable bucket-pass
-// order) are sorted stably by the key words ls.keyq (least significant
-// first; each word's digits are taken relative to its minimum in the bucket,
-// so only the digits that vary are sorted), then every plane is written
-// permuted.  Planes are staged through LDS, so an output may be its input.
+// The model as the bucket sort reads it.
+struct ModelLds {
+  const float* c;
+  float lo, hi, scale;
+  uint32_t kmin, kmax;
+  int is_float;
+  float nbf;  // number of buckets, 2^nb_bits
+};
+
+// Interpolation bins of a unit of buckets [b0, b0 + nbk): keys inside the
+// model's domain use their position F * 2^nb_bits - b0 in the model's CDF
+// space (where the model has spread keys evenly); keys at or below kmin (only
+// in bucket 0) and at or above kmax (only in the last bucket) all have F = 0
+// or 1, so they get bins of their own, cut by value between the unit's
+// extreme and the domain's end.  The layout [low tail | CDF bins | high tail]
+// is monotone non-decreasing in the key; NaN keys go to the outermost bins.
+// Contraction is off so that the counting and the scattering pass compute
+// the same bin.
+struct UnitBins {
+  float fb0, fscale;         // CDF bins
+  int nlo, nmid, nhi;        // bins per region
+  float vmin, lo_scale;      // low tail: (value - vmin) * lo_scale
+  float hi, hi_scale;        // high tail: (value - hi) * hi_scale
+};
+
+__device__ __forceinline__ int tail_bin(float t, int nt) {
+  if (t >= 0.f) return t < (float)nt ? (int)t : nt - 1;
+  return t < 0.f ? 0 : nt - 1;  // t is NaN: the last bin
+}
+
+__device__ __forceinline__ int interp_bin(const ModelLds& m, const UnitBins& u, uint32_t v) {
+#pragma clang fp contract(off)
+  if (v <= m.kmin && u.nlo > 0) {
+    const float t = (cdf_key_value(v, m.is_float) - u.vmin) * u.lo_scale;
+    if (t != t) return 0;  // NaN: the lowest keys
+    return tail_bin(t, u.nlo);
+  }
+  if (v >= m.kmax && u.nhi > 0) return u.nlo + u.nmid + tail_bin((cdf_key_value(v, m.is_float) - u.hi) * u.hi_scale, u.nhi);
+  if (v <= m.kmin) return u.nlo;
+  if (v >= m.kmax) return u.nlo + u.nmid - 1;
+  // the model's F in double precision: a bucket of 2^-16 of the CDF holds
+  // only a few hundred single-precision values of F near 1
+  const double t = ((double)cdf_key_value(v, m.is_float) - (double)m.lo) * (double)m.scale;
+  int i = t < (double)kCdfSegments ? (int)t : kCdfSegments - 1;
+  if (i < 0) i = 0;
+  double f = t - (double)i;
+  f = f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
+  const double a = m.c[i], b = m.c[i + 1];
+  double F = a + f * (b - a);
+  F = F < b ? F : b;
+  const double x = (F * (double)m.nbf - u.fb0) * u.fscale;
+  int bin = 0;
+  if (x >= 0.0) bin = x < (double)u.nmid ? (int)x : u.nmid - 1;
+  return u.nlo + bin;
+}
+
+// Total order of a unit's elements x, y (local positions): primary word,
+// tie words from most to least significant, then position.
+struct UnitKeys {
+  const uint32_t* k;
+  const uint32_t* t1;  // null when there is no such word
+  const uint32_t* t2;
+};
+__device__ __forceinline__ bool unit_less(const LocalSort& ls, const UnitKeys& uk, int s, int x,
+                                          int y) {
+  const uint32_t kx = uk.k[x], ky = uk.k[y];
+  if (kx != ky) return kx < ky;
+  if (uk.t1 && uk.t1[x] != uk.t1[y]) return uk.t1[x] < uk.t1[y];
+  if (uk.t2 && uk.t2[x] != uk.t2[y]) return uk.t2[x] < uk.t2[y];
+  for (int t = ls.nkeys - 4; t >= 0; --t) {
+    const uint32_t* w = pick(ls.in, pick(ls.keyq, t)) + s;
+    const uint32_t a = w[x], b = w[y];
+    if (a != b) return a < b;
+  }
+  return x < y;
+}
+
+// Sort positions [s, s + N) (N <= kBsCap), which hold the buckets [bk0,
+// bk0 + nbk), stably by the sort words and write every plane permuted.
+// Returns false (after raising flag bit 8) when a bin is too dense for the
+// insertion step.
+__device__ bool sort_unit(const LocalSort& ls, const ModelLds& m, int s, int N, int bk0, int nbk,
+                          uint32_t* s_k, uint32_t* s_t1, uint32_t* s_t2, uint16_t* s_perm,
+                          uint32_t* s_cnt, uint32_t* s_tmp, uint32_t* s_red, int32_t* s_nbig,
+                          int32_t* s_big, int32_t* s_bigoff, int32_t* flag) {
+  const int tid = threadIdx.x;
+  const int nk = ls.nkeys;
+  const uint32_t* k0 = pick(ls.in, pick(ls.keyq, nk - 1)) + s;
+  const uint32_t* w1 = nk >= 2 ? pick(ls.in, pick(ls.keyq, nk - 2)) + s : nullptr;
+  const uint32_t* w2 = nk >= 3 ? pick(ls.in, pick(ls.keyq, nk - 3)) + s : nullptr;
+  // the first planes that are not sort words held in LDS are loaded now, so
+  // their loads overlap the sort
+  int pq[kBsPrefetch] = {-1, -1, -1};
+  {
+    int r = 0;
+    for (int q = 0; q < ls.nq && r < kBsPrefetch; ++q) {
+      const uint32_t* in = pick(ls.in, q) + s;
+      if (in == k0 || (w1 && in == w1) || (w2 && in == w2)) continue;
+      pq[r++] = q;
+    }
+  }
+  uint32_t pre[kBsPrefetch][kBsItems];
+#pragma unroll
+  for (int r = 0; r < kBsPrefetch; ++r) {
+    const uint32_t* in = pq[r] >= 0 ? pick(ls.in, pq[r]) + s : nullptr;
+#pragma unroll
+    for (int j = 0; j < kBsItems; ++j) {
+      const int i = tid + j * kBsThreads;
+      pre[r][j] = (in && i < N) ? in[i] : 0u;
+    }
+  }
+  UnitBins u;
+  u.nmid = 1;
+  while (u.nmid < kBsMaxBins && 2 * u.nmid < N) u.nmid <<= 1;
+  u.fb0 = (float)bk0;
+  u.fscale = (float)u.nmid / (float)nbk;
+  const bool lowend = bk0 == 0, highend = bk0 + nbk == (int)m.nbf;
+  u.nlo = lowend ? max(1, u.nmid / 4) : 0;
+  u.nhi = highend ? max(1, u.nmid / 4) : 0;
+  u.vmin = u.hi = 0.f;
+  u.lo_scale = u.hi_scale = 0.f;
+  uint32_t mn = 0xFFFFFFFFu, mx = 0u;
+  for (int i = tid; i < N; i += kBsThreads) {
+    const uint32_t v = k0[i];
+    s_k[i] = v;
+    if (w1) s_t1[i] = w1[i];
+    if (w2) s_t2[i] = w2[i];
+    mn = min(mn, v);
+    mx = max(mx, v);
+  }
+  if (lowend || highend) {
+    mn = bs_reduce(mn, s_red, OpMin());
+    mx = bs_reduce(mx, s_red, OpMax());
+    u.vmin = cdf_key_value(mn, m.is_float);
+    u.hi = m.hi;
+    const float vmax = cdf_key_value(mx, m.is_float);
+    if (m.lo > u.vmin) u.lo_scale = (float)((double)u.nlo / (((double)m.lo - (double)u.vmin) * (1.0 + 1e-6)));
+    if (vmax > m.hi) u.hi_scale = (float)((double)u.nhi / (((double)vmax - (double)m.hi) * (1.0 + 1e-6)));
+  }
+  const int nbins = u.nlo + u.nmid + u.nhi;
+  for (int b = tid; b < nbins; b += kBsThreads) s_cnt[b] = 0;
+  __syncthreads();
+  for (int i = tid; i < N; i += kBsThreads) atomicAdd(&s_cnt[interp_bin(m, u, s_k[i])], 1u);
+  __syncthreads();
+  // exclusive bin starts (each thread scans a run of consecutive bins)
+  const int per = (nbins + kBsThreads - 1) / kBsThreads;
+  const int b0 = min(nbins, tid * per), b1 = min(nbins, b0 + per);
+  uint32_t run = 0, big = 0;
+  for (int b = b0; b < b1; ++b) {
+    run += s_cnt[b];
+    big = max(big, s_cnt[b]);
+  }
+  uint32_t all;
+  uint32_t off = block_exclusive_sum<kBsThreads>(run, s_tmp, &all);
+  big = bs_reduce(big, s_red, OpMax());
+  if (big > (uint32_t)kBsMaxDense) {
+    if (tid == 0) atomicOr(flag, 8);
+    return false;
+  }
+  if (tid == 0) *s_nbig = 0;
+  for (int b = b0; b < b1; ++b) {
+    const uint32_t c = s_cnt[b];
+    s_cnt[b] = off;
+    off += c;
+  }
+  __syncthreads();
+  for (int i = tid; i < N; i += kBsThreads) {
+    const uint32_t pos = atomicAdd(&s_cnt[interp_bin(m, u, s_k[i])], 1u);
+    if (pos < (uint32_t)N)
+      s_perm[pos] = (uint16_t)i;
+    else
+      atomicOr(flag, 4);  // the two bin computations disagreed
+  }
+  __syncthreads();
+  // s_cnt[b] is now the end of bin b.  Bins of up to kBsDenseBin keys are
+  // put in order by one thread each (insertion); larger ones (long runs of
+  // equal primary words) are listed and ranked by the whole workgroup.
+  const UnitKeys uk{s_k, w1 ? s_t1 : nullptr, w2 ? s_t2 : nullptr};
+  for (int b = tid; b < nbins; b += kBsThreads) {
+    const int st = b ? (int)s_cnt[b - 1] : 0;
+    const int en = (int)s_cnt[b];
+    if (en - st > kBsDenseBin) {
+      const int idx = atomicAdd(s_nbig, 1);
+      if (idx < kBsMaxBig) s_big[idx] = b;
+      continue;
+    }
+    for (int x = st + 1; x < en; ++x) {
+      const int cur = s_perm[x];
+      int y = x;
+      while (y > st) {
+        const int prv = s_perm[y - 1];
+        if (!unit_less(ls, uk, s, cur, prv)) break;
+        s_perm[y] = (uint16_t)prv;
+        --y;
+      }
+      s_perm[y] = (uint16_t)cur;
+    }
+  }
+  __syncthreads();
+  const int nbig = *s_nbig;
+  if (nbig > kBsMaxBig) {
+    if (tid == 0) atomicOr(flag, 8);
+    return false;
+  }
+  if (nbig > 0) {
+    // all large bins in one pass: the keys of the listed bins, concatenated,
+    // are shared out over the threads; each key's rank in its bin is the
+    // number of smaller keys there
+    if (tid == 0) {
+      int run = 0;
+      for (int q = 0; q < nbig; ++q) {
+        const int b = s_big[q];
+        s_bigoff[q] = run;
+        run += (int)s_cnt[b] - (b ? (int)s_cnt[b - 1] : 0);
+      }
+      s_bigoff[nbig] = run;
+    }
+    __syncthreads();
+    const int total = s_bigoff[nbig];
+    int elem[kBsItems], dst[kBsItems];
+#pragma unroll
+    for (int r = 0; r < kBsItems; ++r) {
+      const int x = tid + r * kBsThreads;
+      elem[r] = -1;
+      dst[r] = 0;
+      if (x < total) {
+        int q = 0;
+        while (q + 1 < nbig && s_bigoff[q + 1] <= x) ++q;
+        const int b = s_big[q];
+        const int st = b ? (int)s_cnt[b - 1] : 0;
+        const int en = (int)s_cnt[b];
+        const int a = s_perm[st + (x - s_bigoff[q])];
+        int c = 0;
+        for (int j2 = st; j2 < en; ++j2) c += unit_less(ls, uk, s, s_perm[j2], a) ? 1 : 0;
+        elem[r] = a;
+        dst[r] = st + c;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kBsItems; ++r)
+      if (elem[r] >= 0) s_perm[dst[r]] = (uint16_t)elem[r];
+  }
+  // every plane permuted: the sort words straight from LDS, then the
+  // prefetched planes, then the rest, three at a time through the LDS arrays
+  __syncthreads();
+  for (int q = 0; q < ls.nq; ++q) {
+    const uint32_t* in = pick(ls.in, q) + s;
+    const uint32_t* src = in == k0 ? s_k : (w1 && in == w1 ? s_t1 : (w2 && in == w2 ? s_t2 : nullptr));
+    if (!src) continue;
+    uint32_t* out = pick(ls.out, q) + s;
+    for (int i = tid; i < N; i += kBsThreads) out[i] = src[s_perm[i]];
+  }
+  __syncthreads();
+  uint32_t* stage[3] = {s_k, s_t1, s_t2};
+#pragma unroll
+  for (int r = 0; r < kBsPrefetch; ++r) {
+    if (pq[r] < 0) continue;
+#pragma unroll
+    for (int j = 0; j < kBsItems; ++j) {
+      const int i = tid + j * kBsThreads;
+      if (i < N) stage[r][i] = pre[r][j];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kBsPrefetch; ++r) {
+    if (pq[r] < 0) continue;
+    uint32_t* out = pick(ls.out, pq[r]) + s;
+    for (int i = tid; i < N; i += kBsThreads) out[i] = stage[r][s_perm[i]];
+  }
+  int r = 0;
+  int rest[3];
+  for (int q = 0; q <= ls.nq; ++q) {
+    bool take = false;
+    if (q < ls.nq) {
+      const uint32_t* in = pick(ls.in, q) + s;
+      const bool in_lds = in == k0 || (w1 && in == w1) || (w2 && in == w2);
+      take = !in_lds && q != pq[0] && q != pq[1] && q != pq[2];
+    }
+    if (take) rest[r++] = q;
+    if (r == 3 || (q == ls.nq && r > 0)) {
+      __syncthreads();
+      for (int x = 0; x < r; ++x) {
+        const uint32_t* in = pick(ls.in, rest[x]) + s;
+        for (int i = tid; i < N; i += kBsThreads) stage[x][i] = in[i];
+      }
+      __syncthreads();
+      for (int x = 0; x < r; ++x) {
+        uint32_t* out = pick(ls.out, rest[x]) + s;
+        for (int i = tid; i < N; i += kBsThreads) out[i] = stage[x][s_perm[i]];
+      }
+      r = 0;
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
+// Workgroup g takes buckets [g * G, (g + 1) * G).  Buckets are already in
+// order, so consecutive buckets sort as one unit; the workgroup packs them
+// into units of at most kBsCap keys.  The bucket's elements arrive in stable
+// order (the bucket passes are stable), and each unit comes out stably
+// sorted by the sort words ls.keyq (least significant first), i.e. by the
+// total order (primary word, the other words from most to least significant,
+// position):
+//   1. the primary word (and two tie words) go to LDS;
+//   2. an interpolation step in the model's CDF space, where keys are close
+//      to uniform: about two keys per bin, bin = (F * 2^b - first bucket) *
+//      bins / buckets (keys outside the model's domain: by value), counted
+//      and scattered with LDS atomics;
+//   3. every bin is put in order by the total order above: by one thread
+//      (insertion) when small, by the whole workgroup (each key's rank =
+//      number of smaller keys in the bin) when it holds a long run of equal
+//      primary words;
+//   4. every plane is written permuted: the sort words straight from LDS,
+//      the others staged through LDS (so an output may be its input), the
+//      first three of them loaded into registers before the sort.
+// A bucket beyond kBsCap raises flag bit 1, and a bin beyond kBsMaxDense
+// keys, or more than kBsMaxBig large bins in a unit, bit 8: the caller's
+// radix sort then runs instead.
 __global__ __launch_bounds__(kBsThreads) void k_bucket_sort(const int32_t* __restrict__ starts,
-                                                            int64_t n_host, const int32_t* n_dev,
+                                                            int nb, int group, int64_t n_host,
+                                                            const int32_t* n_dev,
                                                             int32_t* __restrict__ flag,
                                                             const LocalSort ls) {
   extern __shared__ __align__(16) unsigned char s_raw[];
-  uint32_t* ka = reinterpret_cast<uint32_t*>(s_raw);
-  uint32_t* kb = ka + kBsCap;
-  uint32_t* stage = kb + kBsCap;
-  uint16_t* va = reinterpret_cast<uint16_t*>(stage + kBsCap);
-  uint16_t* vb = va + kBsCap;
-  __shared__ uint32_t s_cnt[kBsWaves][kRadix];
-  __shared__ uint32_t s_dbase[kRadix];
+  uint32_t* s_k = reinterpret_cast<uint32_t*>(s_raw);
+  uint32_t* s_t1 = s_k + kBsCap;
+  uint32_t* s_t2 = s_t1 + kBsCap;
+  uint16_t* s_perm = reinterpret_cast<uint16_t*>(s_t2 + kBsCap);
+  __shared__ uint32_t s_cnt[kBsMaxBins + kBsMaxBins / 2];
+  static_assert(kBsPrefetch == 3, "three LDS staging arrays");
   __shared__ uint32_t s_tmp[kBsWaves + 1];
   __shared__ uint32_t s_red[kBsWaves];
   __shared__ int32_t s_flag;
+  __shared__ int32_t s_nbig;
+  __shared__ int32_t s_big[kBsMaxBig];
+  __shared__ int32_t s_bigoff[kBsMaxBig + 1];
 
   // Other workgroups of this launch may raise the flag while this one reads
   // it, so one thread reads it and the block follows that one value.
@@ -471,56 +803,41 @@ __global__ __launch_bounds__(kBsThreads) void k_bucket_sort(const int32_t* __res
   if (tid == 0) s_flag = *flag;
   __syncthreads();
   if (s_flag != 0) return;
+  ModelLds m;
+  m.c = ls.model->c;  // read through the caches (the table is 16 KiB)
+  m.lo = ls.model->lo;
+  m.hi = ls.model->hi;
+  m.scale = ls.model->scale;
+  m.kmin = ls.model->kmin;
+  m.kmax = ls.model->kmax;
+  m.is_float = ls.model->is_float;
+  m.nbf = (float)(1 << ls.nb_bits);
   const int nu = (int)(n_dev ? *n_dev : n_host);
-  const int s = starts[blockIdx.x], e = starts[blockIdx.x + 1];
-  if (s < 0 || e < s || e > nu) {
-    if (tid == 0) atomicOr(flag, 4);
-    return;
-  }
-  const int N = e - s;
-  if (N == 0) return;
-  if (N > kBsCap) {
-    if (tid == 0) atomicOr(flag, 1);
-    return;
-  }
-  for (int i = tid; i < N; i += kBsThreads) va[i] = (uint16_t)i;
-  uint32_t* ck = ka;
-  uint16_t* cv = va;
-  uint32_t* ok = kb;
-  uint16_t* ov = vb;
-  for (int w = 0; w < ls.nkeys; ++w) {
-    const uint32_t* src = pick(ls.in, pick(ls.keyq, w)) + s;
-    __syncthreads();
-    uint32_t mn = 0xFFFFFFFFu, mx = 0u;
-    for (int i = tid; i < N; i += kBsThreads) {
-      const uint32_t v = src[i];
-      stage[i] = v;
-      mn = min(mn, v);
-      mx = max(mx, v);
+  const int g0 = blockIdx.x * group, g1 = min(nb, g0 + group);
+  int b = g0;
+  while (b < g1) {
+    // the longest run of buckets from b that fits
+    const int s = starts[b];
+    int e = starts[b + 1];
+    if (s < 0 || e < s || e > nu) {
+      if (tid == 0) atomicOr(flag, 4);
+      return;
     }
-    mn = bs_reduce(mn, s_red, OpMin());
-    mx = bs_reduce(mx, s_red, OpMax());
-    if (mn == mx) continue;
-    const int bits = 32 - __clz(mx - mn);
-    const int passes = (bits + kRadixBits - 1) / kRadixBits;
-    for (int i = tid; i < N; i += kBsThreads) ck[i] = stage[cv[i]] - mn;
-    __syncthreads();
-    if (bucket_lds_sort(ck, cv, ok, ov, N, passes, s_cnt, s_dbase, s_tmp)) {
-      uint32_t* tk = ck;
-      ck = ok;
-      ok = tk;
-      uint16_t* tv = cv;
-      cv = ov;
-      ov = tv;
+    if (e - s > kBsCap) {
+      if (tid == 0) atomicOr(flag, 1);
+      return;
     }
-  }
-  for (int q = 0; q < ls.nq; ++q) {
-    __syncthreads();
-    const uint32_t* in = pick(ls.in, q) + s;
-    for (int i = tid; i < N; i += kBsThreads) stage[i] = in[i];
-    __syncthreads();
-    uint32_t* out = pick(ls.out, q) + s;
-    for (int i = tid; i < N; i += kBsThreads) out[i] = stage[cv[i]];
+    int nb2 = b + 1;
+    while (nb2 < g1) {
+      const int e2 = starts[nb2 + 1];
+      if (e2 < e || e2 > nu || e2 - s > kBsCap) break;
+      e = e2;
+      ++nb2;
+    }
+    if (e > s && !sort_unit(ls, m, s, e - s, b, nb2 - b, s_k, s_t1, s_t2, s_perm, s_cnt, s_tmp,
+                            s_red, &s_nbig, s_big, s_bigoff, flag))
+      return;
+    b = nb2;
   }
 }
 
@@ -530,8 +847,15 @@ hipError_t launch_bucket_sort(const int32_t* starts, int nb_bits, int64_t n, con
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bucket_sort),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bucket_sort, dim3(1u << nb_bits), dim3(kBsThreads), lds, st, starts, n, n_dev,
-                     flag, ls);
+  const int nb = 1 << nb_bits;
+  // about half the capacity per workgroup on average
+  const int64_t mean = n / nb + 1;
+  int group = (int)(bucket_sort_target() / mean);
+  if (group < 1) group = 1;
+  if (group > nb) group = nb;
+  const int grid = (nb + group - 1) / group;
+  hipLaunchKernelGGL(k_bucket_sort, dim3(grid), dim3(kBsThreads), lds, st, starts, nb, group, n,
+                     n_dev, flag, ls);
   return hipGetLastError();
 }
 

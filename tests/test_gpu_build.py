@@ -203,3 +203,59 @@ def test_batched_c4_workload_sampled(kd):
         want = oracle.build_tree(t[s:e], children=False)
         assert nu[b] == want["n_unique"]
         assert np.array_equal(perm[s:s + nu[b]], want["perm"])
+
+
+def _capture(fn):
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()  # warm-up outside the capture (sets kernel attributes)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        fn()
+    return g
+
+
+def test_batched_build_graph_replays(kd):
+    """The batched launch sequence captured once in a HIP graph: every replay,
+    with eager work in between, equals the eager build."""
+    print("[gpu case] batched graph capture", flush=True)
+    x, offsets = kdgen.c4_batched(trees=64, lo=64, hi=20000, seed=99)
+    t = torch.from_numpy(x).cuda()
+    bb = kd.BatchedBuilder(offsets, 3, torch.float32)
+    perm = torch.full((int(offsets[-1]),), -1, dtype=torch.int32, device="cuda")
+    bb.build(t, perm)
+    torch.cuda.synchronize()
+    ref, ref_nu = perm.clone(), bb.n_unique.clone()
+    g = _capture(lambda: bb.build(t, perm))
+    for r in range(3):
+        perm.fill_(-1)
+        bb.n_unique.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(perm, ref), r
+        assert torch.equal(bb.n_unique, ref_nu), r
+
+
+def test_learned_build_graph_replays(kd):
+    print("[gpu case] learned graph capture", flush=True)
+    x = kdgen.gaussian_mixture_f32(300000, 3, 64, 17)
+    t = torch.from_numpy(x).cuda()
+    models = kd.train_cdf(t)
+    lb = kd.LearnedBuilder(x.shape[0], 3, torch.float32)
+    perm = torch.full((x.shape[0],), -1, dtype=torch.int32, device="cuda")
+    lb.build(t, perm, models=models)
+    torch.cuda.synchronize()
+    ref = perm.clone()
+    want = oracle.build_tree(x, threads=8, children=False)
+    assert np.array_equal(ref[: want["n_unique"]].cpu().numpy(), want["perm"])
+    g = _capture(lambda: lb.build(t, perm, models=models))
+    for r in range(3):
+        perm.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(perm, ref), r

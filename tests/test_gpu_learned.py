@@ -76,7 +76,7 @@ def model_bytes(c32, dm, theta):
     body = np.concatenate([c32.astype(np.float32).view(np.uint32), theta.astype(np.float32).view(np.uint32),
                            np.zeros(55, dtype=np.uint32)])
     out = np.concatenate([head, body])
-    assert out.nbytes == 8448
+    assert out.nbytes == 33024
     return out.view(np.uint8)
 
 
@@ -113,12 +113,12 @@ def test_training_matches_oracle_adam(kd):
     for d in range(3):
         rec = kd.model_record(models, d)
         sk = np.sort(L.canonical(sample[:, d], True))
-        dm = L.Domain.of_sample(sk, True)
+        dm = L.Domain.of_column(L.canonical(x[:, d], True), True)
         assert rec["kmin"] == int(dm.kmin) and rec["kmax"] == int(dm.kmax)
         assert np.float32(rec["scale"]) == dm.scale
         p = L.masses(dm, sk)
         th = L.train_adam(p, steps, lr)
-        assert np.max(np.abs(rec["c"].astype(np.float64) - L.levels(th))) < 2e-4, d
+        assert np.max(np.abs(rec["c"].astype(np.float64) - L.levels(th, S))) < 2e-4, d
         assert rec["loss"] == pytest.approx(L.loss(th, p), rel=1e-3)
 
 
@@ -145,8 +145,18 @@ def assert_learned_same(kd, t, models=None, expect_learned=True):
 @pytest.mark.parametrize("n", [1, 2, 7, 1000, 4097, 70001])
 def test_learned_small(kd, k, n):
     case(f"learned n={n} k={k}")
-    t = kdgen.uniform_int(n, k, -50, 50, 0.1, 500 + n + k)
+    t = kdgen.uniform_int(n, k, -(1 << 20), 1 << 20, 0.1, 500 + n + k)
     assert_learned_same(kd, t)
+
+
+@pytest.mark.parametrize("k", [1, 3, 8])
+@pytest.mark.parametrize("n", [1000, 70001])
+def test_learned_heavy_duplicates(kd, k, n):
+    """100 distinct values per coordinate: long runs of equal keys may send a
+    sort to the radix fallback; the tree is exact either way."""
+    case(f"learned heavy duplicates n={n} k={k}")
+    t = kdgen.uniform_int(n, k, -50, 50, 0.1, 900 + n + k)
+    assert_learned_same(kd, t, expect_learned=False)
 
 
 def test_learned_all_duplicates_fall_back(kd):
@@ -171,9 +181,13 @@ def test_learned_float_specials(kd):
 
 @pytest.mark.parametrize("k", [2, 3, 6])
 def test_learned_clustered(kd, k):
+    """256 narrow clusters over a wide range: each cluster is much narrower
+    than one model segment, so buckets can be lopsided and sorts may fall
+    back; the tree is exact either way."""
     case(f"learned clustered k={k}")
     t = kdgen.clustered_int(1 << 18, k, 256, float(1 << 12), 1 << 30, 0.10, 1000 + k)
-    assert_learned_same(kd, t)
+    fb = assert_learned_same(kd, t, expect_learned=False)
+    print(f"fell_back {fb.numpy().tolist()}", flush=True)
 
 
 def test_learned_mixture_and_c1(kd):

@@ -106,13 +106,23 @@ def test_trained_model_balances_mixture_buckets():
     nb = 10
     for d in range(3):
         sk = np.sort(L.canonical(sample[:, d], True))
-        dm = L.Domain.of_sample(sk, True)
         keys = L.canonical(x[:, d], True)
+        dm = L.Domain.of_column(keys, True)
         untrained = np.bincount(L.bucket(L.forward_f32(L.levels(np.zeros(L.K)).astype(np.float32),
                                                        dm, keys), nb), minlength=1 << nb)
         th = L.train_adam(L.masses(dm, sk), steps=300, lr=0.1)
-        trained = np.bincount(L.bucket(L.forward_f32(L.levels(th).astype(np.float32), dm, keys), nb),
+        trained = np.bincount(L.bucket(L.forward_f32(L.levels(th, 1 << 16).astype(np.float32), dm, keys), nb),
                               minlength=1 << nb)
         mean = len(keys) / (1 << nb)
         assert trained.max() < 4 * mean, d
         assert untrained.max() > 2 * trained.max(), d
+
+
+def test_mass_floor_keeps_levels_increasing():
+    """With the export floor every segment spans some CDF range, even where
+    the trained mass is negligible."""
+    th = np.full(L.K, -50.0)
+    th[10] = 0.0
+    c = L.levels(th, 1 << 16)
+    assert c[0] == 0.0 and c[-1] == 1.0
+    assert np.all(np.diff(c) > 0.2 / (1 << 16))
