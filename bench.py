@@ -161,6 +161,7 @@ def main():
     ap.add_argument("--cutover", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip the learned and batched forms")
+    ap.add_argument("--no-tune", action="store_true", help="use the default knobs instead of autotuning")
     ap.add_argument("--n", type=int, default=1 << 24, help=argparse.SUPPRESS)
     ap.add_argument("--calibrate", action="store_true",
                     help="first run one plain 256 MiB device copy (a reference for profiler byte counters)")
@@ -177,12 +178,23 @@ def main():
     from paper_1410_5420_amd import _lib
 
     n, k = args.n, 3
-    cutover = args.cutover or 1024
     log(f"generating n={n} k={k}")
     t_host = kdgen.c2_full_range(n)
     dev = torch.device("cuda:0")
     t = torch.from_numpy(t_host).to(dev)
-    b = kd.Builder(n, k, torch.int32, dev, cutover=args.cutover)
+    tuned = None
+    if args.cutover:
+        knobs = {"cutover": args.cutover, "leaf_blocks": None}
+    elif args.no_tune:
+        knobs = {"cutover": None, "leaf_blocks": None}
+    else:
+        from paper_1410_5420_amd import autotune
+
+        log("autotuning the knobs on this input")
+        tuned = autotune.tune(t, "plain", reps=3, record=False)
+        knobs = dict(tuned["config"])
+    cutover = knobs["cutover"] or 1024
+    b = kd.Builder(n, k, torch.int32, dev, **knobs)
     perm = torch.full((n,), -1, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
 
@@ -271,6 +283,8 @@ def main():
         "config": {"workload": "k=3, n=2^24 int32 uniform over the full signed range, 0.1% exact "
                                "copies (seeded); one plain build (presort + dedup + partition)",
                    "k": k, "n": n, "n_unique": nu, "tuple_dtype": "int32", "cutover": cutover,
+                   "leaf_blocks": knobs["leaf_blocks"] or 2048,
+                   "autotuned": tuned is not None,
                    "presort_ms": round(float(np.median(pre_ms)), 4),
                    "partition_ms": round(float(np.median(part_ms)), 4),
                    "kernel_class_ms_per_step": class_ms},
@@ -280,7 +294,8 @@ def main():
 
     if not args.no_forms:
         plain_perm = perm.clone()
-        out["forms"] = {"learned_c2": learned_form(torch, kd, t, plain_perm, nu, args, "c2 (same input)")}
+        out["forms"] = {"learned_c2": learned_form(torch, kd, t, plain_perm, nu, args, "c2 (same input)",
+                                                   knobs)}
         del b, t, perm, plain_perm
         torch.cuda.empty_cache()
         out["forms"]["learned_c5"] = learned_c5(torch, kd, kdgen, args)
@@ -294,7 +309,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def learned_form(torch, kd, t, plain_perm, nu, args, label):
+def learned_form(torch, kd, t, plain_perm, nu, args, label, knobs=None):
     """Learned build on an input already built plainly: training time, build
     time, fallbacks, equality with the plain perm."""
     n, k = t.shape
@@ -303,7 +318,7 @@ def learned_form(torch, kd, t, plain_perm, nu, args, label):
     models = kd.train_cdf(t)
     torch.cuda.synchronize()
     train_ms = (time.perf_counter() - t0) * 1e3
-    lb = kd.LearnedBuilder(n, k, t.dtype)
+    lb = kd.LearnedBuilder(n, k, t.dtype, **(knobs or {}))
     perm = torch.full((n,), -1, dtype=torch.int32, device=t.device)
     ms = time_steps(torch, lambda: lb.build(t, perm, models=models), max(3, args.steps // 2), 2)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
@@ -359,7 +374,13 @@ def batched_c4(torch, kd, kdgen, args):
     t = torch.from_numpy(x).cuda()
     total = int(offsets[-1])
     B = len(offsets) - 1
-    bb = kd.BatchedBuilder(offsets, 3, torch.float32)
+    knobs = {}
+    if not args.no_tune:
+        from paper_1410_5420_amd import autotune
+
+        knobs = autotune.tune(t, "batched", offsets=offsets, reps=3, record=False)["config"]
+        log(f"batched knobs {knobs}")
+    bb = kd.BatchedBuilder(offsets, 3, torch.float32, **knobs)
     perm_b = torch.full((total,), -1, dtype=torch.int32, device=t.device)
     reps = max(3, args.steps // 4)
     batched_ms = time_steps(torch, lambda: bb.build(t, perm_b), reps, 2)
@@ -397,7 +418,7 @@ def batched_c4(torch, kd, kdgen, args):
     torch.cuda.synchronize()
     same = torch.equal(perm_b, perm_l) and torch.equal(bb.n_unique, nub)
     res = {"workload": f"{B} float32 point-cloud trees, n_i log-uniform in [64, 65536], k=3",
-           "trees": B, "rows": total, "ms_per_build": round(batched_ms, 4),
+           "trees": B, "rows": total, "knobs": knobs, "ms_per_build": round(batched_ms, 4),
            "tuples_per_s": round(total / (batched_ms * 1e-3), 1),
            "graph_replay_ms": round(graph_ms, 4),
            "host_loop_of_plain_builds_ms": round(loop_ms, 3),

@@ -63,8 +63,10 @@ enum kd_status {
  * result. */
 typedef struct kd_options {
   int32_t cutover;     /* largest subarray finished on-chip by one workgroup:
-                          1024, 2048 or 4096; 0 = default */
-  int32_t reserved[7]; /* must be zero */
+                          1024, 2048 or 4096; 0 = default (1024) */
+  int32_t leaf_blocks; /* workgroups of the persistent on-chip finish:
+                          0 = default (2048), else 256 .. 16384 */
+  int32_t reserved[6]; /* must be zero */
 } kd_options;
 
 /* Human-readable name of a status code (static string). */

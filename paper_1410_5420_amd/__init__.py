@@ -42,14 +42,19 @@ class Builder:
     """Holds a device workspace for builds of up to ``n`` rows in ``k``
     dimensions, so repeated builds allocate nothing."""
 
-    def __init__(self, n: int, k: int, dtype=torch.int32, device="cuda", cutover: int | None = None):
+    def __init__(self, n: int, k: int, dtype=torch.int32, device="cuda", cutover: int | None = None,
+                 leaf_blocks: int | None = None):
         self.n, self.k = int(n), int(k)
         self.code = _dtype_code(torch.empty(0, dtype=dtype))
         self.device = torch.device(device)
         self.cutover = cutover
+        self.leaf_blocks = leaf_blocks
         nbytes = _lib.workspace_bytes(self.n, self.k, self.code)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.n_unique = torch.zeros(1, dtype=torch.int64, device=self.device)
+
+    def _opts(self):
+        return _lib.options(self.cutover, getattr(self, "leaf_blocks", None))
 
     def _check_input(self, tuples: torch.Tensor):
         if tuples.dim() != 2 or tuples.shape[1] != self.k or tuples.shape[0] > self.n:
@@ -65,21 +70,21 @@ class Builder:
         n = tuples.shape[0]
         rc = _lib.lib.kdtree_build(_ptr(tuples), n, self.k, self.code, _ptr(perm), _ptr(lo), _ptr(hi),
                                    _ptr(self.n_unique), _ptr(self.workspace), self.workspace.numel(),
-                                   _lib.options(self.cutover), _stream(stream))
+                                   self._opts(), _stream(stream))
         _lib.check(rc, "kdtree_build")
 
     def presort(self, tuples: torch.Tensor, stream=None):
         self._check_input(tuples)
         rc = _lib.lib.kdtree_presort(_ptr(tuples), tuples.shape[0], self.k, self.code, _ptr(self.n_unique),
                                      _ptr(self.workspace), self.workspace.numel(),
-                                     _lib.options(self.cutover), _stream(stream))
+                                     self._opts(), _stream(stream))
         _lib.check(rc, "kdtree_presort")
 
     def partition(self, tuples: torch.Tensor, perm: torch.Tensor, lo=None, hi=None, stream=None):
         self._check_input(tuples)
         rc = _lib.lib.kdtree_partition(_ptr(tuples), tuples.shape[0], self.k, self.code, _ptr(perm),
                                        _ptr(lo), _ptr(hi), _ptr(self.n_unique), _ptr(self.workspace),
-                                       self.workspace.numel(), _lib.options(self.cutover),
+                                       self.workspace.numel(), self._opts(),
                                        _stream(stream))
         _lib.check(rc, "kdtree_partition")
 
@@ -90,9 +95,11 @@ class BatchedBuilder:
     ``offsets`` (host sequence or int64 tensor of B+1 values) splits the rows of
     ``tuples`` into trees; the workspace is sized for exactly that split."""
 
-    def __init__(self, offsets, k: int, dtype=torch.int32, device="cuda", cutover: int | None = None):
+    def __init__(self, offsets, k: int, dtype=torch.int32, device="cuda", cutover: int | None = None,
+                 leaf_blocks: int | None = None):
         import numpy as np
 
+        self.leaf_blocks = leaf_blocks
         off = np.asarray(offsets.cpu() if isinstance(offsets, torch.Tensor) else offsets, dtype=np.int64)
         self.h_offsets = np.ascontiguousarray(off)
         self.trees = int(off.shape[0] - 1)
@@ -114,7 +121,7 @@ class BatchedBuilder:
         rc = _lib.lib.kdtree_build_batched(
             _ptr(tuples), _ptr(self.d_offsets), self.h_offsets.ctypes.data_as(ctypes.c_void_p),
             self.trees, self.k, self.code, _ptr(perm), _ptr(self.n_unique), _ptr(self.workspace),
-            self.workspace.numel(), _lib.options(self.cutover), _stream(stream))
+            self.workspace.numel(), _lib.options(self.cutover, self.leaf_blocks), _stream(stream))
         _lib.check(rc, "kdtree_build_batched")
 
 
@@ -218,11 +225,13 @@ class LearnedBuilder(Builder):
     :class:`Builder`).  ``fell_back`` (int32[k] device) reports, per sort,
     whether it had to fall back to the radix passes."""
 
-    def __init__(self, n: int, k: int, dtype=torch.int32, device="cuda", cutover: int | None = None):
+    def __init__(self, n: int, k: int, dtype=torch.int32, device="cuda", cutover: int | None = None,
+                 leaf_blocks: int | None = None):
         self.n, self.k = int(n), int(k)
         self.code = _dtype_code(torch.empty(0, dtype=dtype))
         self.device = torch.device(device)
         self.cutover = cutover
+        self.leaf_blocks = leaf_blocks
         nbytes = _lib.workspace_bytes_learned(self.n, self.k, self.code)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.n_unique = torch.zeros(1, dtype=torch.int64, device=self.device)
@@ -236,7 +245,7 @@ class LearnedBuilder(Builder):
         rc = _lib.lib.kdtree_build_learned(_ptr(tuples), tuples.shape[0], self.k, self.code, _ptr(models),
                                            _ptr(perm), _ptr(lo), _ptr(hi), _ptr(self.n_unique),
                                            _ptr(self.fell_back), _ptr(self.workspace),
-                                           self.workspace.numel(), _lib.options(self.cutover),
+                                           self.workspace.numel(), self._opts(),
                                            _stream(stream))
         _lib.check(rc, "kdtree_build_learned")
 
@@ -247,7 +256,7 @@ class LearnedBuilder(Builder):
         rc = _lib.lib.kdtree_presort_learned(_ptr(tuples), tuples.shape[0], self.k, self.code,
                                              _ptr(models), _ptr(self.n_unique), _ptr(self.fell_back),
                                              _ptr(self.workspace), self.workspace.numel(),
-                                             _lib.options(self.cutover), _stream(stream))
+                                             self._opts(), _stream(stream))
         _lib.check(rc, "kdtree_presort_learned")
 
 

@@ -22,7 +22,8 @@ class KdError(RuntimeError):
 
 
 class kd_options(ctypes.Structure):
-    _fields_ = [("cutover", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+    _fields_ = [("cutover", ctypes.c_int32), ("leaf_blocks", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 def _load():
@@ -116,11 +117,12 @@ def workspace_bytes_batched(total: int, trees: int, k: int, dtype: int) -> int:
     return int(out.value)
 
 
-def options(cutover: int | None):
-    if cutover is None:
+def options(cutover: int | None, leaf_blocks: int | None = None):
+    if cutover is None and leaf_blocks is None:
         return None
     o = kd_options()
-    o.cutover = int(cutover)
+    o.cutover = int(cutover or 0)
+    o.leaf_blocks = int(leaf_blocks or 0)
     return ctypes.byref(o)
 
 

@@ -1,0 +1,120 @@
+"""Autotuner of the build's speed knobs.
+
+The knobs -- the cutover C below which a subarray is finished on-chip, and
+the number of workgroups of the persistent on-chip finish -- change speed
+only.  tune() times every candidate configuration on the caller's input, and
+checks that each one returns exactly the output of the default
+configuration (a difference would be a bug, and raises); the fastest is
+cached per (form, k, dtype, log2 n) in a JSON file, from which
+best_options() reads it back.  Timing uses HIP events on the build's stream.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+DEFAULTS = {"cutover": 1024, "leaf_blocks": 2048}
+CANDIDATES = [{"cutover": c, "leaf_blocks": b} for c in (1024, 2048, 4096) for b in (1024, 2048, 4096)]
+
+
+def cache_path() -> str:
+    return os.environ.get("KD_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "paper_1410_5420_amd",
+                                       "tune.json"))
+
+
+def cache_key(form: str, n: int, k: int, dtype: str) -> str:
+    """Inputs of similar size share an entry: n is bucketed by log2."""
+    return f"{form}|k={k}|{dtype}|log2n={int(round(math.log2(max(n, 1))))}"
+
+
+def load(path: str | None = None) -> dict:
+    path = path or cache_path()
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def save(entries: dict, path: str | None = None) -> None:
+    path = path or cache_path()
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(entries, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def best_options(form: str, n: int, k: int, dtype: str, path: str | None = None) -> dict:
+    """The cached best configuration, or the defaults."""
+    e = load(path).get(cache_key(form, n, k, dtype))
+    return dict(e["config"]) if e else dict(DEFAULTS)
+
+
+def select(results: list) -> dict:
+    """The fastest of [{"config": ..., "ms": ...}], ties to the earlier one."""
+    if not results:
+        raise ValueError("no candidate was timed")
+    return min(results, key=lambda r: r["ms"])
+
+
+def tune(tuples, form: str = "plain", offsets=None, models=None, candidates=None, reps: int = 5,
+         warmup: int = 1, path: str | None = None, record: bool = True) -> dict:
+    """Time the candidate configurations on ``tuples`` (a device tensor) and
+    cache the fastest.  form: "plain", "learned" (needs ``models``) or
+    "batched" (needs ``offsets``).  Returns {"config", "ms", "results"}."""
+    import torch
+
+    from . import BatchedBuilder, Builder, LearnedBuilder
+
+    n, k = tuples.shape
+    dev = tuples.device
+    candidates = candidates or CANDIDATES
+    dtype = str(tuples.dtype).replace("torch.", "")
+
+    def make(cfg):
+        if form == "plain":
+            b = Builder(max(n, 1), k, tuples.dtype, dev, **cfg)
+            return b, lambda perm: b.build(tuples, perm)
+        if form == "learned":
+            b = LearnedBuilder(max(n, 1), k, tuples.dtype, dev, **cfg)
+            return b, lambda perm: b.build(tuples, perm, models=models)
+        if form == "batched":
+            b = BatchedBuilder(offsets, k, tuples.dtype, dev, **cfg)
+            return b, lambda perm: b.build(tuples, perm)
+        raise ValueError(form)
+
+    ref_builder, run = make(dict(DEFAULTS))
+    ref = torch.full((max(n, 1),), -1, dtype=torch.int32, device=dev)
+    run(ref)
+    torch.cuda.synchronize()
+    ref_nu = ref_builder.n_unique.clone()
+    del ref_builder
+
+    results = []
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for cfg in candidates:
+        b, run = make(dict(cfg))
+        perm = torch.full_like(ref, -1)
+        for _ in range(warmup):
+            run(perm)
+        torch.cuda.synchronize()
+        if not (torch.equal(perm, ref) and torch.equal(b.n_unique, ref_nu)):
+            raise RuntimeError(f"configuration {cfg} changed the output: the knobs must not")
+        times = []
+        for _ in range(reps):
+            ev0.record()
+            run(perm)
+            ev1.record()
+            torch.cuda.synchronize()
+            times.append(ev0.elapsed_time(ev1))
+        times.sort()
+        results.append({"config": dict(cfg), "ms": times[len(times) // 2]})
+        del b
+    best = select(results)
+    if record:
+        entries = load(path)
+        entries[cache_key(form, n, k, dtype)] = {"config": best["config"], "ms": best["ms"]}
+        save(entries, path)
+    return {"config": best["config"], "ms": best["ms"], "results": results}

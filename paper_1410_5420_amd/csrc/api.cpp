@@ -98,15 +98,20 @@ T* at(void* base, size_t off) {
 
 bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
 
-int check_opts(const kd_options* opts, int64_t* cutover) {
+int check_opts(const kd_options* opts, int64_t* cutover, int* leaf_blocks) {
   *cutover = 1024;
+  *leaf_blocks = 2048;
   if (opts) {
-    for (int i = 0; i < 7; ++i)
+    for (int i = 0; i < 6; ++i)
       if (opts->reserved[i] != 0) return KD_EINVAL;
     if (opts->cutover != 0) {
       if (opts->cutover != 1024 && opts->cutover != 2048 && opts->cutover != 4096)
         return KD_EINVAL;
       *cutover = opts->cutover;
+    }
+    if (opts->leaf_blocks != 0) {
+      if (opts->leaf_blocks < 256 || opts->leaf_blocks > 16384) return KD_EINVAL;
+      *leaf_blocks = opts->leaf_blocks;
     }
   }
   return KD_OK;
@@ -296,6 +301,7 @@ struct Job {
   int64_t* n_unique;  // [B]
   void* ws;
   int64_t cutover;
+  int leaf_blocks = 2048;
   const CdfModel* models = nullptr;  // learned presort: one model per dimension
   int32_t* fell_back = nullptr;      // learned presort: per-sort fallback flags (device)
 };
@@ -475,7 +481,8 @@ int partition_impl(const Job& J, hipStream_t st) {
       // the finish takes its items from a counter; partition may run again
       // after one presort, so the counter is cleared here
       KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(fa.queue), 0u, 1, st));
-      KD_LAUNCH(KD_K_LEAF, launch_leaf(r0, r1, r2, n, k, cutover, fa, J.perm, items, st));
+      KD_LAUNCH(KD_K_LEAF, launch_leaf(r0, r1, r2, n, k, cutover, fa, J.perm, items, J.leaf_blocks,
+                                       st));
     }
     if (J.lo && J.hi) KD_TRY(launch_children(fa.uoff, n, J.lo, J.hi, st));
   }
@@ -491,7 +498,7 @@ int check_job(Job& J, size_t ws_bytes, const kd_options* opts) {
   if (!aligned4(J.tuples) || !aligned4(J.ws)) return KD_EINVAL;
   if ((reinterpret_cast<uintptr_t>(J.n_unique) & 7u) != 0) return KD_EINVAL;
   if (ws_bytes < plan(J.n, J.k, J.B, J.models != nullptr).end) return KD_ENOMEM;
-  int rc = check_opts(opts, &J.cutover);
+  int rc = check_opts(opts, &J.cutover, &J.leaf_blocks);
   if (rc != KD_OK) return rc;
   while (J.cutover > 1024 && leaf_lds_bytes(J.cutover, J.k) + 8192 > 160 * 1024) J.cutover /= 2;
   return KD_OK;

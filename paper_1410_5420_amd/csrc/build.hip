@@ -802,7 +802,7 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
 
 hipError_t launch_leaf(const uint32_t* rec0, uint32_t* b1, uint32_t* b2, int64_t n, int k,
                        int64_t cutover, const ForestArgs& fa, int32_t* perm, int64_t items_bound,
-                       hipStream_t st) {
+                       int blocks, hipStream_t st) {
   if (n <= 0 || k < 2) return hipSuccess;
   const size_t lds = leaf_lds_bytes(cutover, k);
   RecBufs B{rec0, b1, b2};
@@ -829,7 +829,7 @@ hipError_t launch_leaf(const uint32_t* rec0, uint32_t* b1, uint32_t* b2, int64_t
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   // persistent grid: enough workgroups to fill the chip, never more than items
-  int64_t grid = 256 * 8;
+  int64_t grid = blocks;
   if (items_bound < grid) grid = items_bound;
   if (grid < 1) grid = 1;
   void* args[] = {&B, &F, &n, &k, &perm};

@@ -118,10 +118,11 @@ inline size_t leaf_lds_bytes(int64_t cutover, int k) {
 }
 
 // On-chip finish of every subarray at the cutover depth (row ids come from
-// array 0's records).
+// array 0's records): a persistent grid of `blocks` workgroups (at most one
+// per item).
 hipError_t launch_leaf(const uint32_t* rec0, uint32_t* b1, uint32_t* b2, int64_t n, int k,
                        int64_t cutover, const ForestArgs& fa, int32_t* perm, int64_t items_bound,
-                       hipStream_t st);
+                       int blocks, hipStream_t st);
 
 // k == 1: the in-order layout is the sorted unique order.
 hipError_t launch_copy_k1(const uint32_t* S0, const ForestArgs& fa, int64_t n, int32_t* perm,

@@ -73,8 +73,43 @@ def test_build_rejects_bad_arguments(L):
     o.cutover = 3000
     assert call_build(L, opts=ctypes.byref(o)) == -1
     o.cutover = 2048
-    o.reserved[3] = 1
+    o.leaf_blocks = 100  # below the accepted range
     assert call_build(L, opts=ctypes.byref(o)) == -1
+    o.leaf_blocks = 20000  # above it
+    assert call_build(L, opts=ctypes.byref(o)) == -1
+    o.leaf_blocks = 0
+    o.reserved[3] = 1  # reserved words must be zero
+    assert call_build(L, opts=ctypes.byref(o)) == -1
+
+
+def test_learned_and_training_reject_bad_arguments(L):
+    vp = ctypes.c_void_p
+    out = ctypes.c_size_t(0)
+    assert L.lib.kd_cdf_model_bytes(0, ctypes.byref(out)) == -1
+    assert L.lib.kd_cdf_model_bytes(9, ctypes.byref(out)) == -4
+    assert L.lib.kd_cdf_model_bytes(3, ctypes.byref(out)) == 0 and out.value == 3 * L.CDF_MODEL_BYTES
+    assert L.lib.kd_cdf_train_workspace_bytes(3, 0, ctypes.byref(out)) == -1
+    assert L.lib.kd_cdf_train_workspace_bytes(3, (1 << 20) + 1, ctypes.byref(out)) == -4
+    ws = 1 << 30
+    # n < 1, bad steps, non-positive learning rate, null model: rejected before any launch
+    assert L.lib.kd_cdf_train(vp(FAKE), 0, 3, 0, 1024, 10, 0.1, vp(FAKE), vp(FAKE), ws, None) == -1
+    assert L.lib.kd_cdf_train(vp(FAKE), 100, 3, 0, 1024, -1, 0.1, vp(FAKE), vp(FAKE), ws, None) == -1
+    assert L.lib.kd_cdf_train(vp(FAKE), 100, 3, 0, 1024, 10, 0.0, vp(FAKE), vp(FAKE), ws, None) == -1
+    assert L.lib.kd_cdf_train(vp(FAKE), 100, 3, 0, 1024, 10, 0.1, None, vp(FAKE), ws, None) == -1
+    assert L.lib.kd_cdf_train(vp(FAKE), 100, 3, 0, 1024, 10, 0.1, vp(FAKE), vp(FAKE), 8, None) == -2
+    assert L.lib.kd_cdf_eval(vp(FAKE), vp(FAKE), 10, 17, vp(FAKE), vp(FAKE), None) == -1
+    assert L.lib.kd_cdf_loss_grad(vp(FAKE), 0, 0, 0, 1, vp(FAKE), vp(FAKE), vp(FAKE), vp(FAKE), None) == -1
+    assert L.lib.kdtree_workspace_bytes_learned(-1, 3, 0, ctypes.byref(out)) == -1
+    assert L.lib.kdtree_workspace_bytes_learned(100, 3, 0, ctypes.byref(out)) == 0
+    learned_ws = out.value
+    assert L.lib.kdtree_workspace_bytes(100, 3, 0, ctypes.byref(out)) == 0
+    assert learned_ws > out.value
+    nu = FAKE
+    # no models; too small a workspace
+    assert L.lib.kdtree_build_learned(vp(FAKE), 100, 3, 0, None, vp(FAKE), None, None, vp(nu), None,
+                                      vp(FAKE), learned_ws, None, None) == -1
+    assert L.lib.kdtree_build_learned(vp(FAKE), 100, 3, 0, vp(FAKE), vp(FAKE), None, None, vp(nu),
+                                      None, vp(FAKE), out.value, None, None) == -2
 
 
 def test_strerror(L):

@@ -1,0 +1,46 @@
+"""Host logic of the autotuner: cache keys, persistence, selection."""
+import pytest
+
+pytest.importorskip("torch")
+
+
+@pytest.fixture()
+def at(tmp_path, monkeypatch):
+    monkeypatch.setenv("KD_TUNE_CACHE", str(tmp_path / "tune.json"))
+    from paper_1410_5420_amd import autotune
+
+    return autotune
+
+
+def test_defaults_without_cache(at):
+    assert at.best_options("plain", 1 << 20, 3, "int32") == at.DEFAULTS
+
+
+def test_key_buckets_sizes_by_log2(at):
+    assert at.cache_key("plain", 1 << 20, 3, "int32") == at.cache_key("plain", (1 << 20) + 5, 3, "int32")
+    assert at.cache_key("plain", 1 << 20, 3, "int32") != at.cache_key("plain", 1 << 22, 3, "int32")
+    assert at.cache_key("plain", 1 << 20, 3, "int32") != at.cache_key("learned", 1 << 20, 3, "int32")
+
+
+def test_select_fastest_and_persist(at):
+    res = [{"config": {"cutover": 1024, "leaf_blocks": 2048}, "ms": 3.0},
+           {"config": {"cutover": 2048, "leaf_blocks": 1024}, "ms": 2.5},
+           {"config": {"cutover": 4096, "leaf_blocks": 1024}, "ms": 2.5}]
+    best = at.select(res)
+    assert best["config"] == {"cutover": 2048, "leaf_blocks": 1024}
+    entries = at.load()
+    entries[at.cache_key("plain", 1 << 24, 3, "int32")] = {"config": best["config"], "ms": best["ms"]}
+    at.save(entries)
+    assert at.best_options("plain", 1 << 24, 3, "int32") == {"cutover": 2048, "leaf_blocks": 1024}
+    assert at.best_options("plain", 1 << 10, 3, "int32") == at.DEFAULTS
+
+
+def test_select_needs_results(at):
+    with pytest.raises(ValueError):
+        at.select([])
+
+
+def test_candidates_are_valid_options(at):
+    for c in at.CANDIDATES:
+        assert c["cutover"] in (1024, 2048, 4096)
+        assert 256 <= c["leaf_blocks"] <= 16384

@@ -259,3 +259,22 @@ def test_learned_build_graph_replays(kd):
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(perm, ref), r
+
+
+def test_autotune_keeps_output_and_caches(kd, tmp_path, monkeypatch):
+    """The tuner times candidate knob settings, checks each returns the
+    default configuration's output, and caches the fastest."""
+    print("[gpu case] autotune", flush=True)
+    monkeypatch.setenv("KD_TUNE_CACHE", str(tmp_path / "tune.json"))
+    from paper_1410_5420_amd import autotune
+
+    t = torch.from_numpy(kdgen.uniform_int(300000, 3, 0, 1 << 20, 0.02, 5)).cuda()
+    cands = [{"cutover": 1024, "leaf_blocks": 2048}, {"cutover": 2048, "leaf_blocks": 1024},
+             {"cutover": 4096, "leaf_blocks": 4096}]
+    r = autotune.tune(t, "plain", candidates=cands, reps=2)
+    assert r["config"] in cands and len(r["results"]) == 3
+    assert autotune.best_options("plain", 300000, 3, "int32") == r["config"]
+    x, offsets = kdgen.c4_batched(trees=32, lo=64, hi=20000, seed=5)
+    rb = autotune.tune(torch.from_numpy(x).cuda(), "batched", offsets=offsets, candidates=cands, reps=2)
+    assert rb["config"] in cands
+    assert autotune.best_options("batched", int(offsets[-1]), 3, "float32") == rb["config"]
