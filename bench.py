@@ -184,9 +184,9 @@ def main():
     t = torch.from_numpy(t_host).to(dev)
     tuned = None
     if args.cutover:
-        knobs = {"cutover": args.cutover, "leaf_blocks": None}
+        knobs = {"cutover": args.cutover, "leaf_blocks": None, "records": None}
     elif args.no_tune:
-        knobs = {"cutover": None, "leaf_blocks": None}
+        knobs = {"cutover": None, "leaf_blocks": None, "records": None}
     else:
         from paper_1410_5420_amd import autotune
 
@@ -284,6 +284,7 @@ def main():
                                "copies (seeded); one plain build (presort + dedup + partition)",
                    "k": k, "n": n, "n_unique": nu, "tuple_dtype": "int32", "cutover": cutover,
                    "leaf_blocks": knobs["leaf_blocks"] or 2048,
+                   "records": knobs["records"] or 0,
                    "autotuned": tuned is not None,
                    "presort_ms": round(float(np.median(pre_ms)), 4),
                    "partition_ms": round(float(np.median(part_ms)), 4),

@@ -66,7 +66,10 @@ typedef struct kd_options {
                           1024, 2048 or 4096; 0 = default (1024) */
   int32_t leaf_blocks; /* workgroups of the persistent on-chip finish:
                           0 = default (2048), else 256 .. 16384 */
-  int32_t reserved[6]; /* must be zero */
+  int32_t records;     /* how the level-0 rank records are completed: 0 = by
+                          size, 1 = one direct scatter, 2 = a radix pass on
+                          the destination's top digit, then placement */
+  int32_t reserved[5]; /* must be zero */
 } kd_options;
 
 /* Human-readable name of a status code (static string). */

@@ -43,18 +43,20 @@ class Builder:
     dimensions, so repeated builds allocate nothing."""
 
     def __init__(self, n: int, k: int, dtype=torch.int32, device="cuda", cutover: int | None = None,
-                 leaf_blocks: int | None = None):
+                 leaf_blocks: int | None = None, records: int | None = None):
         self.n, self.k = int(n), int(k)
         self.code = _dtype_code(torch.empty(0, dtype=dtype))
         self.device = torch.device(device)
         self.cutover = cutover
         self.leaf_blocks = leaf_blocks
+        self.records = records
         nbytes = _lib.workspace_bytes(self.n, self.k, self.code)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.n_unique = torch.zeros(1, dtype=torch.int64, device=self.device)
 
     def _opts(self):
-        return _lib.options(self.cutover, getattr(self, "leaf_blocks", None))
+        return _lib.options(self.cutover, getattr(self, "leaf_blocks", None),
+                            getattr(self, "records", None))
 
     def _check_input(self, tuples: torch.Tensor):
         if tuples.dim() != 2 or tuples.shape[1] != self.k or tuples.shape[0] > self.n:
@@ -96,10 +98,11 @@ class BatchedBuilder:
     ``tuples`` into trees; the workspace is sized for exactly that split."""
 
     def __init__(self, offsets, k: int, dtype=torch.int32, device="cuda", cutover: int | None = None,
-                 leaf_blocks: int | None = None):
+                 leaf_blocks: int | None = None, records: int | None = None):
         import numpy as np
 
         self.leaf_blocks = leaf_blocks
+        self.records = records
         off = np.asarray(offsets.cpu() if isinstance(offsets, torch.Tensor) else offsets, dtype=np.int64)
         self.h_offsets = np.ascontiguousarray(off)
         self.trees = int(off.shape[0] - 1)
@@ -121,7 +124,8 @@ class BatchedBuilder:
         rc = _lib.lib.kdtree_build_batched(
             _ptr(tuples), _ptr(self.d_offsets), self.h_offsets.ctypes.data_as(ctypes.c_void_p),
             self.trees, self.k, self.code, _ptr(perm), _ptr(self.n_unique), _ptr(self.workspace),
-            self.workspace.numel(), _lib.options(self.cutover, self.leaf_blocks), _stream(stream))
+            self.workspace.numel(), _lib.options(self.cutover, self.leaf_blocks, self.records),
+            _stream(stream))
         _lib.check(rc, "kdtree_build_batched")
 
 
@@ -138,14 +142,15 @@ def build_batched(tuples: torch.Tensor, offsets, cutover: int | None = None, str
     return perm[: b.total], b.n_unique
 
 
-def build(tuples: torch.Tensor, children: bool = False, cutover: int | None = None, stream=None):
+def build(tuples: torch.Tensor, children: bool = False, cutover: int | None = None, stream=None,
+          records: int | None = None):
     """Build the tree of ``tuples`` ((n, k) int32/float32 device tensor).
 
     Returns ``(perm, n_unique)`` or ``(perm, n_unique, lo, hi)`` with device
     tensors trimmed to ``n_unique`` (this synchronises to read the count).
     """
     n, k = tuples.shape
-    b = Builder(max(n, 1), k, tuples.dtype, tuples.device, cutover)
+    b = Builder(max(n, 1), k, tuples.dtype, tuples.device, cutover, records=records)
     perm = torch.full((max(n, 1),), -1, dtype=torch.int32, device=tuples.device)
     lo = hi = None
     if children:
@@ -226,12 +231,13 @@ class LearnedBuilder(Builder):
     whether it had to fall back to the radix passes."""
 
     def __init__(self, n: int, k: int, dtype=torch.int32, device="cuda", cutover: int | None = None,
-                 leaf_blocks: int | None = None):
+                 leaf_blocks: int | None = None, records: int | None = None):
         self.n, self.k = int(n), int(k)
         self.code = _dtype_code(torch.empty(0, dtype=dtype))
         self.device = torch.device(device)
         self.cutover = cutover
         self.leaf_blocks = leaf_blocks
+        self.records = records
         nbytes = _lib.workspace_bytes_learned(self.n, self.k, self.code)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.n_unique = torch.zeros(1, dtype=torch.int64, device=self.device)

@@ -1,8 +1,8 @@
 """Autotuner of the build's speed knobs.
 
-The knobs -- the cutover C below which a subarray is finished on-chip, and
-the number of workgroups of the persistent on-chip finish -- change speed
-only.  tune() times every candidate configuration on the caller's input, and
+The knobs -- the cutover C below which a subarray is finished on-chip, the
+number of workgroups of the persistent on-chip finish, and how the level-0
+rank records are completed -- change speed only.  tune() times every candidate configuration on the caller's input, and
 checks that each one returns exactly the output of the default
 configuration (a difference would be a bug, and raises); the fastest is
 cached per (form, k, dtype, log2 n) in a JSON file, from which
@@ -14,8 +14,9 @@ import json
 import math
 import os
 
-DEFAULTS = {"cutover": 1024, "leaf_blocks": 2048}
-CANDIDATES = [{"cutover": c, "leaf_blocks": b} for c in (1024, 2048, 4096) for b in (1024, 2048, 4096)]
+DEFAULTS = {"cutover": 1024, "leaf_blocks": 2048, "records": 0}
+CANDIDATES = [{"cutover": c, "leaf_blocks": b, "records": r} for c in (1024, 2048, 4096)
+              for b in (1024, 2048, 4096) for r in (1, 2)]
 
 
 def cache_path() -> str:

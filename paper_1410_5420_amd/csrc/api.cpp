@@ -98,12 +98,15 @@ T* at(void* base, size_t off) {
 
 bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
 
-int check_opts(const kd_options* opts, int64_t* cutover, int* leaf_blocks) {
+int check_opts(const kd_options* opts, int64_t* cutover, int* leaf_blocks, int* records) {
   *cutover = 1024;
   *leaf_blocks = 2048;
+  *records = 0;
   if (opts) {
-    for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < 5; ++i)
       if (opts->reserved[i] != 0) return KD_EINVAL;
+    if (opts->records < 0 || opts->records > 2) return KD_EINVAL;
+    *records = opts->records;
     if (opts->cutover != 0) {
       if (opts->cutover != 1024 && opts->cutover != 2048 && opts->cutover != 4096)
         return KD_EINVAL;
@@ -302,6 +305,7 @@ struct Job {
   void* ws;
   int64_t cutover;
   int leaf_blocks = 2048;
+  int records = 0;  // 0: by size, 1: direct scatter, 2: radix pass + placement
   const CdfModel* models = nullptr;  // learned presort: one model per dimension
   int32_t* fell_back = nullptr;      // learned presort: per-sort fallback flags (device)
 };
@@ -316,6 +320,11 @@ ForestArgs forest_args(const Job& J, const Layout& L) {
   fa.queue = at<int32_t>(J.ws, L.queue);
   return fa;
 }
+
+// Up to this many rows the level-0 records are completed by one direct
+// scatter (measured faster while the scattered planes fit the 256 MiB
+// memory-side cache); above it by a top-digit radix pass plus placement.
+constexpr int64_t kDirectRecordsRows = (int64_t)1 << 24;
 
 int presort_impl(const Job& J, hipStream_t st) {
   const int64_t n = J.n;
@@ -446,7 +455,55 @@ int presort_impl(const Job& J, hipStream_t st) {
     if (rc != KD_OK) return rc;
     if (learned) std::swap(cin, cout);
   }
-  if (k > 1) KD_LAUNCH(KD_K_RECORDS, launch_complete_records(rec0, S + un, n, k, total, st));
+  const bool direct = J.records == 1 || (J.records == 0 && n <= kDirectRecordsRows);
+  if (k > 1 && direct) {
+    // small enough for the scattered planes to stay in the memory-side
+    // cache: one direct scatter
+    KD_LAUNCH(KD_K_RECORDS, launch_complete_records(rec0, S + un, n, k, total, st));
+  } else if (k > 1) {
+    // The record planes the chain could not fill (array 0's, and the ranks
+    // in orders 1 .. j-1 of array j >= 2) are scattered from array 1: the
+    // element at position i of array 1 has rank rv[1] = i in order 1 and
+    // rv[m] = plane (m - 2) mod k of its record in the other orders.  For
+    // each target array t the scatter key is rv[t]; it is done as one radix
+    // pass on the key's top digit (which groups every element with its
+    // destination window) and a placement pass.
+    const uint32_t* a1 = rec0 + record_offset(1, k, n);
+    int bits = 1;
+    while (((int64_t)1 << bits) < n) ++bits;
+    const int top = bits > kRadixBits ? bits - kRadixBits : 0;
+    auto rv_plane = [&](int m) -> Quant {
+      if (m == 1) return Quant{kPlaneIndex, nullptr, 0, nullptr};
+      return Quant{kPlaneArray, a1 + (size_t)((m - 2 + k) % k) * un, 0, nullptr};
+    };
+    for (int tgt = 0; tgt < k; ++tgt) {
+      if (tgt == 1) continue;
+      uint32_t* at_rec = rec0 + record_offset(tgt, k, n);
+      std::vector<std::pair<Quant, uint32_t*>> vals;  // source, destination plane
+      if (tgt == 0) {
+        for (int c = 0; c <= k - 2; ++c) vals.push_back({rv_plane((1 + c) % k), at_rec + (size_t)c * un});
+        vals.push_back({Quant{kPlaneArray, S + un, 0, nullptr}, at_rec + (size_t)(k - 1) * un});
+      } else {
+        for (int c = k - tgt; c <= k - 2; ++c)
+          vals.push_back({rv_plane((tgt + 1 + c) % k), at_rec + (size_t)c * un});
+      }
+      const Quant key = rv_plane(tgt);
+      Payload pay{};
+      PlaceArgs pa{};
+      pa.nv = (int)vals.size();
+      for (int v = 0; v < pa.nv; ++v) {
+        Plane& pl = pay.p[pay.count++];
+        pl.kind = vals[v].first.kind;
+        pl.in = vals[v].first.in;
+        pl.word = 0;
+        pl.out = vb + (size_t)(v + 1) * un;
+        pa.val[v] = pl.out;
+        pa.dst[v] = vals[v].second;
+      }
+      KD_LAUNCH(KD_K_RECORDS, launch_radix_pass(key.in, ts, 0, vb, pay, n, total, top, rcnt, rgrp, st));
+      KD_LAUNCH(KD_K_RECORDS, launch_place(vb, pa, n, total, st));
+    }
+  }
   return KD_OK;
 }
 
@@ -498,7 +555,7 @@ int check_job(Job& J, size_t ws_bytes, const kd_options* opts) {
   if (!aligned4(J.tuples) || !aligned4(J.ws)) return KD_EINVAL;
   if ((reinterpret_cast<uintptr_t>(J.n_unique) & 7u) != 0) return KD_EINVAL;
   if (ws_bytes < plan(J.n, J.k, J.B, J.models != nullptr).end) return KD_ENOMEM;
-  int rc = check_opts(opts, &J.cutover, &J.leaf_blocks);
+  int rc = check_opts(opts, &J.cutover, &J.leaf_blocks, &J.records);
   if (rc != KD_OK) return rc;
   while (J.cutover > 1024 && leaf_lds_bytes(J.cutover, J.k) + 8192 > 160 * 1024) J.cutover /= 2;
   return KD_OK;

@@ -97,6 +97,16 @@ hipError_t launch_tree_ids(const int64_t* off, int num_trees, uint32_t* tree, hi
 hipError_t launch_forest_finish(int32_t* uoff, int num_trees, int64_t cutover, int64_t* n_unique,
                                 int32_t* lmax, int32_t* wgbase, int32_t* queue, hipStream_t st);
 
+// dst[v][key[p]] = val[v][p] for p < *total, where key is a permutation of
+// 0 .. *total - 1 grouped by its top digit (after one radix pass on it).
+struct PlaceArgs {
+  int nv;
+  const uint32_t* val[kMaxK];
+  uint32_t* dst[kMaxK];
+};
+hipError_t launch_place(const uint32_t* key, const PlaceArgs& pa, int64_t n, const int32_t* total,
+                        hipStream_t st);
+
 // Scatters the record planes the chain of sorts could not fill (see
 // presort.hip).  ids1: row ids in the order of array 1.
 hipError_t launch_complete_records(uint32_t* rec, const uint32_t* ids1, int64_t n, int k,

@@ -669,6 +669,35 @@ __global__ __launch_bounds__(256) void k_complete_records(uint32_t* __restrict__
   }
 }
 
+// Placement: after a radix pass on the top digit of the destination key,
+// the elements of tile t all have destinations inside the range of positions
+// the tile itself covers (the keys are a permutation of 0 .. nu-1), so
+// dst[v][key[p]] = val[v][p] writes stay inside a window; with the XCD-aware
+// tile order each window is written through one L2.
+__global__ __launch_bounds__(256) void k_place(const uint32_t* __restrict__ key, const PlaceArgs pa,
+                                              const int32_t* total) {
+  const int nu = *total;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int base = tile * kSortTile;
+  if (base >= nu) return;
+  const int end = min(nu, base + kSortTile);
+  for (int p = base + (int)threadIdx.x; p < end; p += 256) {
+    const uint32_t kk = key[p];
+    if (kk >= (uint32_t)nu) continue;  // not a permutation: leave it (cannot happen)
+#pragma unroll
+    for (int v = 0; v < kMaxK; ++v)
+      if (v < pa.nv) pa.dst[v][kk] = pa.val[v][p];
+  }
+}
+
+hipError_t launch_place(const uint32_t* key, const PlaceArgs& pa, int64_t n, const int32_t* total,
+                        hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int tiles = (int)((n + kSortTile - 1) / kSortTile);
+  hipLaunchKernelGGL(k_place, dim3(xcd_grid(tiles)), dim3(256), 0, st, key, pa, total);
+  return hipGetLastError();
+}
+
 hipError_t launch_complete_records(uint32_t* rec, const uint32_t* ids1, int64_t n, int k,
                                    const int32_t* nu, hipStream_t st) {
   if (n <= 0 || k < 2) return hipSuccess;

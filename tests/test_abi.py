@@ -78,6 +78,9 @@ def test_build_rejects_bad_arguments(L):
     o.leaf_blocks = 20000  # above it
     assert call_build(L, opts=ctypes.byref(o)) == -1
     o.leaf_blocks = 0
+    o.records = 3  # 0, 1 or 2
+    assert call_build(L, opts=ctypes.byref(o)) == -1
+    o.records = 0
     o.reserved[3] = 1  # reserved words must be zero
     assert call_build(L, opts=ctypes.byref(o)) == -1
 

@@ -44,3 +44,4 @@ def test_candidates_are_valid_options(at):
     for c in at.CANDIDATES:
         assert c["cutover"] in (1024, 2048, 4096)
         assert 256 <= c["leaf_blocks"] <= 16384
+        assert c["records"] in (0, 1, 2)

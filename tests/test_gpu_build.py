@@ -78,6 +78,20 @@ def test_cutover_choices_same_tree(kd, cutover, n):
     assert_same(kd, t, cutover=cutover)
 
 
+@pytest.mark.parametrize("records", [1, 2])
+@pytest.mark.parametrize("k", [2, 3, 5])
+def test_record_completion_paths(kd, records, k):
+    """Both ways of completing the level-0 records give the oracle's tree."""
+    t = kdgen.uniform_int(300001, k, -(2 ** 31), 2 ** 31, 0.01, 40 + k)
+    want = oracle.build_tree(t, threads=8)
+    print(f"[gpu case] records={records} k={k}", flush=True)
+    perm, nu, lo, hi = kd.build(torch.from_numpy(t).cuda(), children=True, records=records)
+    torch.cuda.synchronize()
+    assert nu == want["n_unique"]
+    assert np.array_equal(perm.cpu().numpy(), want["perm"])
+    assert np.array_equal(lo.cpu().numpy(), want["lo"])
+
+
 def test_all_duplicates(kd):
     t = np.tile(np.array([[5, -7, 9]], dtype=np.int32), (10000, 1))
     assert_same(kd, t)
@@ -269,8 +283,9 @@ def test_autotune_keeps_output_and_caches(kd, tmp_path, monkeypatch):
     from paper_1410_5420_amd import autotune
 
     t = torch.from_numpy(kdgen.uniform_int(300000, 3, 0, 1 << 20, 0.02, 5)).cuda()
-    cands = [{"cutover": 1024, "leaf_blocks": 2048}, {"cutover": 2048, "leaf_blocks": 1024},
-             {"cutover": 4096, "leaf_blocks": 4096}]
+    cands = [{"cutover": 1024, "leaf_blocks": 2048, "records": 1},
+             {"cutover": 2048, "leaf_blocks": 1024, "records": 2},
+             {"cutover": 4096, "leaf_blocks": 4096, "records": 0}]
     r = autotune.tune(t, "plain", candidates=cands, reps=2)
     assert r["config"] in cands and len(r["results"]) == 3
     assert autotune.best_options("plain", 300000, 3, "int32") == r["config"]
