@@ -322,9 +322,10 @@ ForestArgs forest_args(const Job& J, const Layout& L) {
 }
 
 // Up to this many rows the level-0 records are completed by one direct
-// scatter (measured faster while the scattered planes fit the 256 MiB
-// memory-side cache); above it by a top-digit radix pass plus placement.
-constexpr int64_t kDirectRecordsRows = (int64_t)1 << 24;
+// scatter; above it by radix passes plus a placement through LDS (measured
+// faster from 2^24 rows on: 0.79 against 1.27 ms at 2^24, 2.6 against 9 ms
+// at 2^26).
+constexpr int64_t kDirectRecordsRows = (int64_t)1 << 16;
 
 int presort_impl(const Job& J, hipStream_t st) {
   const int64_t n = J.n;
@@ -457,25 +458,23 @@ int presort_impl(const Job& J, hipStream_t st) {
   }
   const bool direct = J.records == 1 || (J.records == 0 && n <= kDirectRecordsRows);
   if (k > 1 && direct) {
-    // small enough for the scattered planes to stay in the memory-side
-    // cache: one direct scatter
+    // small: one direct scatter
     KD_LAUNCH(KD_K_RECORDS, launch_complete_records(rec0, S + un, n, k, total, st));
   } else if (k > 1) {
     // The record planes the chain could not fill (array 0's, and the ranks
     // in orders 1 .. j-1 of array j >= 2) are scattered from array 1: the
     // element at position i of array 1 has rank rv[1] = i in order 1 and
     // rv[m] = plane (m - 2) mod k of its record in the other orders.  For
-    // each target array t the scatter key is rv[t]; it is done as one radix
-    // pass on the key's top digit (which groups every element with its
-    // destination window) and a placement pass.
+    // each target array t the scatter key is rv[t]; radix passes on its
+    // digits above the low 12 bring every element to the 4096-position
+    // block holding its destination, and a placement pass writes each
+    // block out through LDS.
     const uint32_t* a1 = rec0 + record_offset(1, k, n);
-    int bits = 1;
-    while (((int64_t)1 << bits) < n) ++bits;
-    const int top = bits > kRadixBits ? bits - kRadixBits : 0;
     auto rv_plane = [&](int m) -> Quant {
       if (m == 1) return Quant{kPlaneIndex, nullptr, 0, nullptr};
       return Quant{kPlaneArray, a1 + (size_t)((m - 2 + k) % k) * un, 0, nullptr};
     };
+    const int passes = place_passes(n);
     for (int tgt = 0; tgt < k; ++tgt) {
       if (tgt == 1) continue;
       uint32_t* at_rec = rec0 + record_offset(tgt, k, n);
@@ -487,21 +486,31 @@ int presort_impl(const Job& J, hipStream_t st) {
         for (int c = k - tgt; c <= k - 2; ++c)
           vals.push_back({rv_plane((tgt + 1 + c) % k), at_rec + (size_t)c * un});
       }
-      const Quant key = rv_plane(tgt);
-      Payload pay{};
+      const int nv = (int)vals.size();
+      auto slot = [&](int set, int i) { return vb + ((size_t)set * (k + 2) + i) * un; };
+      const uint32_t* kin = rv_plane(tgt).in;
+      int set = 0;
+      for (int p = 0; p < passes; ++p) {
+        Payload pay{};
+        for (int v = 0; v < nv; ++v) {
+          Plane& pl = pay.p[pay.count++];
+          pl.kind = p == 0 ? vals[v].first.kind : kPlaneArray;
+          pl.in = p == 0 ? vals[v].first.in : slot(set, v + 1);
+          pl.word = 0;
+          pl.out = slot(set ^ 1, v + 1);
+        }
+        KD_LAUNCH(KD_K_RECORDS, launch_radix_pass(kin, ts, 0, slot(set ^ 1, 0), pay, n, total,
+                                                  place_shift(p), rcnt, rgrp, st));
+        set ^= 1;
+        kin = slot(set, 0);
+      }
       PlaceArgs pa{};
-      pa.nv = (int)vals.size();
-      for (int v = 0; v < pa.nv; ++v) {
-        Plane& pl = pay.p[pay.count++];
-        pl.kind = vals[v].first.kind;
-        pl.in = vals[v].first.in;
-        pl.word = 0;
-        pl.out = vb + (size_t)(v + 1) * un;
-        pa.val[v] = pl.out;
+      pa.nv = nv;
+      for (int v = 0; v < nv; ++v) {
+        pa.val[v] = slot(set, v + 1);
         pa.dst[v] = vals[v].second;
       }
-      KD_LAUNCH(KD_K_RECORDS, launch_radix_pass(key.in, ts, 0, vb, pay, n, total, top, rcnt, rgrp, st));
-      KD_LAUNCH(KD_K_RECORDS, launch_place(vb, pa, n, total, st));
+      KD_LAUNCH(KD_K_RECORDS, launch_place(slot(set, 0), pa, n, total, st));
     }
   }
   return KD_OK;

@@ -98,7 +98,8 @@ hipError_t launch_forest_finish(int32_t* uoff, int num_trees, int64_t cutover, i
                                 int32_t* lmax, int32_t* wgbase, int32_t* queue, hipStream_t st);
 
 // dst[v][key[p]] = val[v][p] for p < *total, where key is a permutation of
-// 0 .. *total - 1 grouped by its top digit (after one radix pass on it).
+// 0 .. *total - 1 already grouped by key >> 12: place_passes(n) radix passes
+// on digits place_shift(0), place_shift(1), ... do that.
 struct PlaceArgs {
   int nv;
   const uint32_t* val[kMaxK];
@@ -106,6 +107,8 @@ struct PlaceArgs {
 };
 hipError_t launch_place(const uint32_t* key, const PlaceArgs& pa, int64_t n, const int32_t* total,
                         hipStream_t st);
+int place_passes(int64_t n);
+int place_shift(int pass);
 
 // Scatters the record planes the chain of sorts could not fill (see
 // presort.hip).  ids1: row ids in the order of array 1.

@@ -609,10 +609,13 @@ __device__ bool sort_unit(const LocalSort& ls, const ModelLds& m, int s, int N, 
     run += s_cnt[b];
     big = max(big, s_cnt[b]);
   }
+  // one scan carries both the bin counts (low 16 bits: at most kBsCap) and,
+  // in the high bits, the number of bins beyond kBsMaxDense keys
+  static_assert(kBsCap < (1 << 16), "counts fit 16 bits");
   uint32_t all;
-  uint32_t off = block_exclusive_sum<kBsThreads>(run, s_tmp, &all);
-  big = bs_reduce(big, s_red, OpMax());
-  if (big > (uint32_t)kBsMaxDense) {
+  uint32_t off = block_exclusive_sum<kBsThreads>(run | (big > (uint32_t)kBsMaxDense ? 0x10000u : 0u),
+                                                 s_tmp, &all) & 0xFFFFu;
+  if (all >> 16) {
     if (tid == 0) atomicOr(flag, 8);
     return false;
   }
@@ -850,7 +853,7 @@ hipError_t launch_bucket_sort(const int32_t* starts, int nb_bits, int64_t n, con
   const int nb = 1 << nb_bits;
   // about half the capacity per workgroup on average
   const int64_t mean = n / nb + 1;
-  int group = (int)(bucket_sort_target() / mean);
+  int group = (int)((bucket_sort_target() + mean / 2) / mean);
   if (group < 1) group = 1;
   if (group > nb) group = nb;
   const int grid = (nb + group - 1) / group;

@@ -80,10 +80,11 @@ struct ModelView {
   int is_float, nb_bits;
 };
 
-__device__ __forceinline__ ModelView load_model(const RadixExtra& ex, float* s_c) {
-  for (int q = threadIdx.x; q <= kCdfSegments; q += blockDim.x) s_c[q] = ex.model->c[q];
+// The level table (16 KiB) is read through the caches: every workgroup of a
+// pass reads the same table, and an LDS copy would cost occupancy.
+__device__ __forceinline__ ModelView load_model(const RadixExtra& ex) {
   ModelView m;
-  m.c = s_c;
+  m.c = ex.model->c;
   m.lo = ex.model->lo;
   m.scale = ex.model->scale;
   m.kmin = ex.model->kmin;
@@ -108,12 +109,11 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_count(const uint32_t* __re
                                                            int shift, uint32_t* __restrict__ cnt,
                                                            const RadixExtra ex) {
   __shared__ uint32_t s_h[kRadix];
-  __shared__ float s_c[kModel ? kCdfSegments + 1 : 1];
   if (gated_off(ex)) return;
   const int tid = threadIdx.x;
   if (tid < kRadix) s_h[tid] = 0;
   ModelView mv{};
-  if (kModel) mv = load_model(ex, s_c);
+  if (kModel) mv = load_model(ex);
   __syncthreads();
   const int n = (int)(n_dev ? *n_dev : n_host);
   const int base = blockIdx.x * kSortTile;
@@ -219,7 +219,6 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
   __shared__ uint32_t s_tile_excl[kRadix];
   __shared__ uint32_t s_gbase[kRadix];
   __shared__ uint32_t s_tmp[kOsWaves + 1];
-  __shared__ float s_c[kModel ? kCdfSegments + 1 : 1];
   if (gated_off(ex)) return;
 
   const int tid = threadIdx.x;
@@ -231,7 +230,7 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
   if (base >= n) return;
   for (int q = tid; q < kOsWaves * kRadix; q += kOsThreads) (&s_wcnt[0][0])[q] = 0;
   ModelView mv{};
-  if (kModel) mv = load_model(ex, s_c);
+  if (kModel) mv = load_model(ex);
   // global start of this tile's run of digit tid
   if (tid < kRadix)
     s_gbase[tid] = cnt[(int64_t)tile * kRadix + tid] +
@@ -669,32 +668,54 @@ __global__ __launch_bounds__(256) void k_complete_records(uint32_t* __restrict__
   }
 }
 
-// Placement: after a radix pass on the top digit of the destination key,
-// the elements of tile t all have destinations inside the range of positions
-// the tile itself covers (the keys are a permutation of 0 .. nu-1), so
-// dst[v][key[p]] = val[v][p] writes stay inside a window; with the XCD-aware
-// tile order each window is written through one L2.
-__global__ __launch_bounds__(256) void k_place(const uint32_t* __restrict__ key, const PlaceArgs pa,
+// Placement: once the elements are grouped by key >> kPlaceBits (radix
+// passes on those digits), the elements at positions [b * 4096, (b+1) * 4096)
+// are exactly those whose keys -- a permutation of 0 .. nu-1 -- lie in that
+// same range.  Workgroup b therefore gathers its values in LDS at key - base
+// and writes the block out in order: every global write is coalesced.
+constexpr int kPlaceBits = 12;
+constexpr int kPlaceTile = 1 << kPlaceBits;
+
+__global__ __launch_bounds__(512) void k_place(const uint32_t* __restrict__ key, const PlaceArgs pa,
                                               const int32_t* total) {
+  extern __shared__ uint32_t s_val[];  // [nv][kPlaceTile]
   const int nu = *total;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int base = tile * kSortTile;
+  const int base = blockIdx.x * kPlaceTile;
   if (base >= nu) return;
-  const int end = min(nu, base + kSortTile);
-  for (int p = base + (int)threadIdx.x; p < end; p += 256) {
-    const uint32_t kk = key[p];
-    if (kk >= (uint32_t)nu) continue;  // not a permutation: leave it (cannot happen)
+  const int cnt = min(nu - base, kPlaceTile);
+  for (int p = (int)threadIdx.x; p < cnt; p += 512) {
+    const uint32_t slot = key[base + p] - (uint32_t)base;
+    if (slot >= (uint32_t)cnt) continue;  // not a permutation (cannot happen)
 #pragma unroll
     for (int v = 0; v < kMaxK; ++v)
-      if (v < pa.nv) pa.dst[v][kk] = pa.val[v][p];
+      if (v < pa.nv) s_val[v * kPlaceTile + slot] = pa.val[v][base + p];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int v = 0; v < kMaxK; ++v) {
+    if (v >= pa.nv) continue;
+    uint32_t* d = pa.dst[v] + base;
+    for (int p = (int)threadIdx.x; p < cnt; p += 512) d[p] = s_val[v * kPlaceTile + p];
   }
 }
+
+int place_passes(int64_t n) {
+  int bits = 1;
+  while (((int64_t)1 << bits) < n) ++bits;
+  const int rest = bits - kPlaceBits;
+  return rest <= 0 ? 1 : (rest + kRadixBits - 1) / kRadixBits;
+}
+int place_shift(int pass) { return kPlaceBits + pass * kRadixBits; }
 
 hipError_t launch_place(const uint32_t* key, const PlaceArgs& pa, int64_t n, const int32_t* total,
                         hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  const int tiles = (int)((n + kSortTile - 1) / kSortTile);
-  hipLaunchKernelGGL(k_place, dim3(xcd_grid(tiles)), dim3(256), 0, st, key, pa, total);
+  const size_t lds = (size_t)pa.nv * kPlaceTile * 4;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_place),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const int blocks = (int)((n + kPlaceTile - 1) / kPlaceTile);
+  hipLaunchKernelGGL(k_place, dim3(blocks), dim3(512), lds, st, key, pa, total);
   return hipGetLastError();
 }
 
