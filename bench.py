@@ -319,7 +319,14 @@ def learned_form(torch, kd, t, plain_perm, nu, args, label, knobs=None):
     models = kd.train_cdf(t)
     torch.cuda.synchronize()
     train_ms = (time.perf_counter() - t0) * 1e3
-    lb = kd.LearnedBuilder(n, k, t.dtype, **(knobs or {}))
+    knobs = dict(knobs or {})
+    if not args.no_tune:
+        from paper_1410_5420_amd import autotune
+
+        cands = [dict(knobs, learned_sorts=m) for m in autotune.LEARNED_SORTS]
+        knobs = autotune.tune(t, "learned", models=models, candidates=cands, reps=3,
+                              record=False)["config"]
+    lb = kd.LearnedBuilder(n, k, t.dtype, **knobs)
     perm = torch.full((n,), -1, dtype=torch.int32, device=t.device)
     ms = time_steps(torch, lambda: lb.build(t, perm, models=models), max(3, args.steps // 2), 2)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
@@ -333,7 +340,8 @@ def learned_form(torch, kd, t, plain_perm, nu, args, label, knobs=None):
     lb.build(t, perm, models=models)
     torch.cuda.synchronize()
     same = int(lb.n_unique.item()) == nu and torch.equal(perm[:nu], plain_perm[:nu])
-    res = {"workload": label, "n": n, "train_ms": round(train_ms, 3), "ms_per_build": round(ms, 4),
+    res = {"workload": label, "n": n, "knobs": knobs, "train_ms": round(train_ms, 3),
+           "ms_per_build": round(ms, 4),
            "tuples_per_s": round(n / (ms * 1e-3), 1), "presort_ms": round(float(np.median(pre)), 4),
            "fell_back": lb.fell_back.cpu().numpy().tolist(), "bit_exact_vs_plain": bool(same)}
     log(f"learned {label}: {ms:.3f} ms/build, presort {res['presort_ms']} ms, fell_back {res['fell_back']}")
@@ -346,7 +354,13 @@ def learned_c5(torch, kd, kdgen, args):
     t = torch.from_numpy(x).cuda()
     del x
     n, k = t.shape
-    b = kd.Builder(n, k, torch.float32)
+    knobs = {}
+    if not args.no_tune:
+        from paper_1410_5420_amd import autotune
+
+        knobs = autotune.tune(t, "plain", reps=2, record=False)["config"]
+        log(f"c5 plain knobs {knobs}")
+    b = kd.Builder(n, k, torch.float32, **knobs)
     perm = torch.full((n,), -1, dtype=torch.int32, device=t.device)
     reps = max(3, args.steps // 4)
     plain_ms = time_steps(torch, lambda: b.build(t, perm), reps, 2)
@@ -361,7 +375,9 @@ def learned_c5(torch, kd, kdgen, args):
     nu = int(b.n_unique.item())
     del b
     torch.cuda.empty_cache()
-    res = learned_form(torch, kd, t, perm, nu, args, "k=3, n=2^26 float32 mixture of 64 anisotropic Gaussians")
+    res = learned_form(torch, kd, t, perm, nu, args, "k=3, n=2^26 float32 mixture of 64 anisotropic Gaussians",
+                       knobs)
+    res["plain_knobs"] = knobs
     res["plain_ms_per_build"] = round(plain_ms, 4)
     res["plain_presort_ms"] = round(float(np.median(pre)), 4)
     res["speedup_vs_plain"] = round(plain_ms / res["ms_per_build"], 3)

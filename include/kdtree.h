@@ -67,9 +67,12 @@ typedef struct kd_options {
   int32_t leaf_blocks; /* workgroups of the persistent on-chip finish:
                           0 = default (2048), else 256 .. 16384 */
   int32_t records;     /* how the level-0 rank records are completed: 0 = by
-                          size, 1 = one direct scatter, 2 = a radix pass on
-                          the destination's top digit, then placement */
-  int32_t reserved[5]; /* must be zero */
+                          size, 1 = one direct scatter, 2 = radix passes on
+                          the destination's high digits, then placement */
+  int32_t learned_sorts; /* learned builds only: bit d set = the sort for
+                          super key d goes through the learned buckets, the
+                          others through the radix passes; 0 = all */
+  int32_t reserved[4]; /* must be zero */
 } kd_options;
 
 /* Human-readable name of a status code (static string). */

@@ -56,7 +56,7 @@ class Builder:
 
     def _opts(self):
         return _lib.options(self.cutover, getattr(self, "leaf_blocks", None),
-                            getattr(self, "records", None))
+                            getattr(self, "records", None), getattr(self, "learned_sorts", None))
 
     def _check_input(self, tuples: torch.Tensor):
         if tuples.dim() != 2 or tuples.shape[1] != self.k or tuples.shape[0] > self.n:
@@ -228,16 +228,20 @@ def cdf_eval(models: torch.Tensor, d: int, values: torch.Tensor, nb_bits: int, s
 class LearnedBuilder(Builder):
     """Builder whose presort goes through learned CDF buckets (same output as
     :class:`Builder`).  ``fell_back`` (int32[k] device) reports, per sort,
-    whether it had to fall back to the radix passes."""
+    whether it had to fall back to the radix passes.  ``learned_sorts``
+    (bit d: the sort for super key d uses the learned buckets; default all)
+    is a speed knob."""
 
     def __init__(self, n: int, k: int, dtype=torch.int32, device="cuda", cutover: int | None = None,
-                 leaf_blocks: int | None = None, records: int | None = None):
+                 leaf_blocks: int | None = None, records: int | None = None,
+                 learned_sorts: int | None = None):
         self.n, self.k = int(n), int(k)
         self.code = _dtype_code(torch.empty(0, dtype=dtype))
         self.device = torch.device(device)
         self.cutover = cutover
         self.leaf_blocks = leaf_blocks
         self.records = records
+        self.learned_sorts = learned_sorts
         nbytes = _lib.workspace_bytes_learned(self.n, self.k, self.code)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.n_unique = torch.zeros(1, dtype=torch.int64, device=self.device)

@@ -1,8 +1,9 @@
 """Autotuner of the build's speed knobs.
 
 The knobs -- the cutover C below which a subarray is finished on-chip, the
-number of workgroups of the persistent on-chip finish, and how the level-0
-rank records are completed -- change speed only.  tune() times every candidate configuration on the caller's input, and
+number of workgroups of the persistent on-chip finish, how the level-0 rank
+records are completed, and (learned form) which sorts use the learned
+buckets -- change speed only.  tune() times every candidate configuration on the caller's input, and
 checks that each one returns exactly the output of the default
 configuration (a difference would be a bug, and raises); the fastest is
 cached per (form, k, dtype, log2 n) in a JSON file, from which
@@ -17,6 +18,16 @@ import os
 DEFAULTS = {"cutover": 1024, "leaf_blocks": 2048, "records": 0}
 CANDIDATES = [{"cutover": c, "leaf_blocks": b, "records": r} for c in (1024, 2048, 4096)
               for b in (1024, 2048, 4096) for r in (1, 2)]
+# the learned form also chooses which sorts go through the learned buckets:
+# all of them, or only the first (the multi-word sort, where the buckets save
+# the most passes)
+LEARNED_SORTS = (0, 1)
+
+
+def candidates_for(form: str) -> list:
+    if form != "learned":
+        return list(CANDIDATES)
+    return [dict(c, learned_sorts=m) for c in CANDIDATES for m in LEARNED_SORTS]
 
 
 def cache_path() -> str:
@@ -71,7 +82,7 @@ def tune(tuples, form: str = "plain", offsets=None, models=None, candidates=None
 
     n, k = tuples.shape
     dev = tuples.device
-    candidates = candidates or CANDIDATES
+    candidates = candidates or candidates_for(form)
     dtype = str(tuples.dtype).replace("torch.", "")
 
     def make(cfg):

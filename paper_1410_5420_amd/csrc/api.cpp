@@ -98,13 +98,17 @@ T* at(void* base, size_t off) {
 
 bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
 
-int check_opts(const kd_options* opts, int64_t* cutover, int* leaf_blocks, int* records) {
+int check_opts(const kd_options* opts, int64_t* cutover, int* leaf_blocks, int* records,
+               int* learned_sorts) {
   *cutover = 1024;
   *leaf_blocks = 2048;
   *records = 0;
+  *learned_sorts = 0;
   if (opts) {
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < 4; ++i)
       if (opts->reserved[i] != 0) return KD_EINVAL;
+    if (opts->learned_sorts < 0 || opts->learned_sorts > 0xFF) return KD_EINVAL;
+    *learned_sorts = opts->learned_sorts;
     if (opts->records < 0 || opts->records > 2) return KD_EINVAL;
     *records = opts->records;
     if (opts->cutover != 0) {
@@ -306,6 +310,7 @@ struct Job {
   int64_t cutover;
   int leaf_blocks = 2048;
   int records = 0;  // 0: by size, 1: direct scatter, 2: radix pass + placement
+  int learned_sorts = 0;  // learned presort: bit d = sort d uses the buckets; 0 = all
   const CdfModel* models = nullptr;  // learned presort: one model per dimension
   int32_t* fell_back = nullptr;      // learned presort: per-sort fallback flags (device)
 };
@@ -326,6 +331,10 @@ ForestArgs forest_args(const Job& J, const Layout& L) {
 // faster from 2^24 rows on: 0.79 against 1.27 ms at 2^24, 2.6 against 9 ms
 // at 2^26).
 constexpr int64_t kDirectRecordsRows = (int64_t)1 << 16;
+
+bool learned_sort_on(const Job& J, int d) {
+  return J.learned_sorts == 0 || ((J.learned_sorts >> d) & 1) != 0;
+}
 
 int presort_impl(const Job& J, hipStream_t st) {
   const int64_t n = J.n;
@@ -368,7 +377,7 @@ int presort_impl(const Job& J, hipStream_t st) {
       for (int ps = 0; ps < kPassesPerWord; ++ps) passes.push_back({w == 0 ? k : w, ps * kRadixBits});
     for (int ps = 0; ps < tp; ++ps) passes.push_back({k + 1, ps * kRadixBits});
     const int32_t* gate = nullptr;
-    if (learned) {
+    if (learned && learned_sort_on(J, 0)) {
       // bucket on word 0; finish by words k-1 .. 1, then word 0; ties by row
       LearnedSort ls;
       ls.model = J.models;
@@ -434,7 +443,7 @@ int presort_impl(const Job& J, hipStream_t st) {
     for (int ps = 0; ps < kPassesPerWord; ++ps) passes.push_back({keyq, ps * kRadixBits});
     for (int ps = 0; ps < tp; ++ps) passes.push_back({treeq, ps * kRadixBits});
     const int32_t* gate = nullptr;
-    if (learned) {
+    if (learned && learned_sort_on(J, d)) {
       // bucket on word d and finish by it; ties keep the order of array d+1,
       // whose position is the quantity-1 rank plane
       LearnedSort ls;
@@ -564,7 +573,7 @@ int check_job(Job& J, size_t ws_bytes, const kd_options* opts) {
   if (!aligned4(J.tuples) || !aligned4(J.ws)) return KD_EINVAL;
   if ((reinterpret_cast<uintptr_t>(J.n_unique) & 7u) != 0) return KD_EINVAL;
   if (ws_bytes < plan(J.n, J.k, J.B, J.models != nullptr).end) return KD_ENOMEM;
-  int rc = check_opts(opts, &J.cutover, &J.leaf_blocks, &J.records);
+  int rc = check_opts(opts, &J.cutover, &J.leaf_blocks, &J.records, &J.learned_sorts);
   if (rc != KD_OK) return rc;
   while (J.cutover > 1024 && leaf_lds_bytes(J.cutover, J.k) + 8192 > 160 * 1024) J.cutover /= 2;
   return KD_OK;

@@ -423,9 +423,9 @@ constexpr int kBsWaves = kBsThreads / kWave;
 constexpr int kBsCap = 4096;      // most keys a workgroup sorts at once (two workgroups per CU)
 constexpr int kBsItems = kBsCap / kBsThreads;
 constexpr int kBsMaxBins = kBsCap / 2;  // CDF interpolation bins per unit (plus up to half as many tail bins)
-constexpr int kBsDenseBin = 64;   // larger bins are ranked by the whole workgroup
+constexpr int kBsDenseBin = 16;   // larger bins are ranked by the whole workgroup
 constexpr int kBsMaxDense = kBsCap; // largest bin a workgroup ranks
-constexpr int kBsMaxBig = 64;     // most such bins per unit
+constexpr int kBsMaxBig = 512;    // most such bins per unit
 constexpr int kBsPrefetch = 3;    // output planes loaded into registers while the unit sorts
 constexpr int kBsLdsTies = 2;     // tie-break words held in LDS (later ones are read from memory)
 
@@ -473,8 +473,6 @@ struct ModelLds {
 // or 1, so they get bins of their own, cut by value between the unit's
 // extreme and the domain's end.  The layout [low tail | CDF bins | high tail]
 // is monotone non-decreasing in the key; NaN keys go to the outermost bins.
-// Contraction is off so that the counting and the scattering pass compute
-// the same bin.
 struct UnitBins {
   float fb0, fscale;         // CDF bins
   int nlo, nmid, nhi;        // bins per region
@@ -578,14 +576,25 @@ __device__ bool sort_unit(const LocalSort& ls, const ModelLds& m, int s, int N, 
   u.nhi = highend ? max(1, u.nmid / 4) : 0;
   u.vmin = u.hi = 0.f;
   u.lo_scale = u.hi_scale = 0.f;
+  // every thread owns positions tid + j * kBsThreads: their primary words
+  // (and, later, bins) stay in registers
+  uint32_t kv[kBsItems];
   uint32_t mn = 0xFFFFFFFFu, mx = 0u;
-  for (int i = tid; i < N; i += kBsThreads) {
-    const uint32_t v = k0[i];
-    s_k[i] = v;
-    if (w1) s_t1[i] = w1[i];
-    if (w2) s_t2[i] = w2[i];
-    mn = min(mn, v);
-    mx = max(mx, v);
+#pragma unroll
+  for (int j = 0; j < kBsItems; ++j) {
+    const int i = tid + j * kBsThreads;
+    kv[j] = i < N ? k0[i] : 0u;
+  }
+#pragma unroll
+  for (int j = 0; j < kBsItems; ++j) {
+    const int i = tid + j * kBsThreads;
+    if (i < N) {
+      s_k[i] = kv[j];
+      if (w1) s_t1[i] = w1[i];
+      if (w2) s_t2[i] = w2[i];
+      mn = min(mn, kv[j]);
+      mx = max(mx, kv[j]);
+    }
   }
   if (lowend || highend) {
     mn = bs_reduce(mn, s_red, OpMin());
@@ -598,8 +607,14 @@ __device__ bool sort_unit(const LocalSort& ls, const ModelLds& m, int s, int N, 
   }
   const int nbins = u.nlo + u.nmid + u.nhi;
   for (int b = tid; b < nbins; b += kBsThreads) s_cnt[b] = 0;
+  int bin[kBsItems];
+#pragma unroll
+  for (int j = 0; j < kBsItems; ++j)
+    bin[j] = tid + j * kBsThreads < N ? interp_bin(m, u, kv[j]) : 0;
   __syncthreads();
-  for (int i = tid; i < N; i += kBsThreads) atomicAdd(&s_cnt[interp_bin(m, u, s_k[i])], 1u);
+#pragma unroll
+  for (int j = 0; j < kBsItems; ++j)
+    if (tid + j * kBsThreads < N) atomicAdd(&s_cnt[bin[j]], 1u);
   __syncthreads();
   // exclusive bin starts (each thread scans a run of consecutive bins)
   const int per = (nbins + kBsThreads - 1) / kBsThreads;
@@ -626,12 +641,15 @@ __device__ bool sort_unit(const LocalSort& ls, const ModelLds& m, int s, int N, 
     off += c;
   }
   __syncthreads();
-  for (int i = tid; i < N; i += kBsThreads) {
-    const uint32_t pos = atomicAdd(&s_cnt[interp_bin(m, u, s_k[i])], 1u);
+#pragma unroll
+  for (int j = 0; j < kBsItems; ++j) {
+    const int i = tid + j * kBsThreads;
+    if (i >= N) continue;
+    const uint32_t pos = atomicAdd(&s_cnt[bin[j]], 1u);
     if (pos < (uint32_t)N)
       s_perm[pos] = (uint16_t)i;
     else
-      atomicOr(flag, 4);  // the two bin computations disagreed
+      atomicOr(flag, 4);  // inconsistent counts (cannot happen)
   }
   __syncthreads();
   // s_cnt[b] is now the end of bin b.  Bins of up to kBsDenseBin keys are
@@ -668,15 +686,16 @@ __device__ bool sort_unit(const LocalSort& ls, const ModelLds& m, int s, int N, 
     // all large bins in one pass: the keys of the listed bins, concatenated,
     // are shared out over the threads; each key's rank in its bin is the
     // number of smaller keys there
-    if (tid == 0) {
-      int run = 0;
-      for (int q = 0; q < nbig; ++q) {
-        const int b = s_big[q];
-        s_bigoff[q] = run;
-        run += (int)s_cnt[b] - (b ? (int)s_cnt[b - 1] : 0);
-      }
-      s_bigoff[nbig] = run;
+    static_assert(kBsMaxBig <= kBsThreads, "one thread per listed bin");
+    uint32_t sz = 0;
+    if (tid < nbig) {
+      const int b = s_big[tid];
+      sz = s_cnt[b] - (b ? s_cnt[b - 1] : 0u);
     }
+    uint32_t all_big;
+    const uint32_t boff = block_exclusive_sum<kBsThreads>(sz, s_tmp, &all_big);
+    if (tid < nbig) s_bigoff[tid] = (int32_t)boff;
+    if (tid == 0) s_bigoff[nbig] = (int32_t)all_big;
     __syncthreads();
     const int total = s_bigoff[nbig];
     int elem[kBsItems], dst[kBsItems];
@@ -686,8 +705,14 @@ __device__ bool sort_unit(const LocalSort& ls, const ModelLds& m, int s, int N, 
       elem[r] = -1;
       dst[r] = 0;
       if (x < total) {
-        int q = 0;
-        while (q + 1 < nbig && s_bigoff[q + 1] <= x) ++q;
+        int q = 0, hi = nbig - 1;  // last q with s_bigoff[q] <= x
+        while (q < hi) {
+          const int mid = (q + hi + 1) >> 1;
+          if (s_bigoff[mid] <= x)
+            q = mid;
+          else
+            hi = mid - 1;
+        }
         const int b = s_big[q];
         const int st = b ? (int)s_cnt[b - 1] : 0;
         const int en = (int)s_cnt[b];
