@@ -86,10 +86,12 @@ __device__ __forceinline__ void forest_subarray(const Forest& F, int64_t cutover
 }
 
 // ---- global level -------------------------------------------------------------
-// A level is three launches with no waiting between workgroups:
-//   1. count: tile t of moving array a finds the subarrays that meet it (and
-//      their medians' ranks), then counts, per subarray piece, the elements
-//      that go to the lower half and whether the median itself is there;
+// A level is four launches with no waiting between workgroups:
+//   0. seg:   one wave per tile finds the subarrays that meet it and their
+//      medians' ranks (and records the medians' row ids);
+//   1. count: tile t of moving array a counts, per subarray piece, the
+//      elements that go to the lower half and whether the median itself is
+//      there;
 //   2. scan:  one block per array chains those counts from tile to tile
 //      along each subarray (a segmented scan);
 //   3. move:  tile t recomputes its elements' sides, adds the in-tile prefix
@@ -172,11 +174,29 @@ __device__ void find_subarrays(const RecBufs& B, const Forest& F, int64_t n, int
   if (lane == 0) out->nseg = min((int)popc64(km), kMaxSeg);
 }
 
+// Subarrays meeting every tile (one wave per tile), their medians' ranks,
+// and the row ids of the medians inside the tile.
+constexpr int kSegThreads = 256;
+__global__ __launch_bounds__(kSegThreads) void k_level_seg(const RecBufs B, const Forest F, int64_t n,
+                                                          int k, int depth, int64_t cutover,
+                                                          int32_t* __restrict__ perm,
+                                                          SegInfo* __restrict__ seginfo, int tiles) {
+  const int nu = F.uoff[F.B];
+  if (depth >= *F.lmax) return;
+  const int t = blockIdx.x * (kSegThreads / kWave) + threadIdx.x / kWave;
+  if (t >= tiles) return;
+  const int t0 = t * kLevelTile;
+  if (t0 >= nu) return;
+  const int t1 = min(t0 + kLevelTile, nu);
+  find_subarrays(B, F, n, k, depth, cutover, t0, t1, true, perm, seginfo + t);
+}
+
+// Per tile of every moving array: how many elements of each subarray piece
+// go to the lower half, and whether the median itself is there (packed as
+// lower | node << 16).
 __global__ __launch_bounds__(kLvThreads) void k_level_count(const RecBufs B, const Forest F,
                                                            int64_t n, int k, int depth,
-                                                           int64_t cutover,
-                                                           int32_t* __restrict__ perm,
-                                                           SegInfo* __restrict__ seginfo,
+                                                           const SegInfo* __restrict__ seginfo,
                                                            uint32_t* __restrict__ cnt,
                                                            int tiles_per_array) {
   __shared__ SegInfo s_si;
@@ -191,8 +211,7 @@ __global__ __launch_bounds__(kLvThreads) void k_level_count(const RecBufs B, con
   const int t0 = t * kLevelTile;
   if (t0 >= nu) return;
   const int t1 = min(t0 + kLevelTile, nu);
-  // the plane holding the rank in order p; its loads go out before the
-  // subarray search
+  // the plane holding the rank in order p
   const int cp = (p - j - 1 + 2 * k) % k;
   const uint32_t* plane = buf_after(B, moves_before(depth, j, k)) + record_offset(j, k, n) +
                           (int64_t)cp * n;
@@ -202,17 +221,15 @@ __global__ __launch_bounds__(kLvThreads) void k_level_count(const RecBufs B, con
     const int i = t0 + it * kLvThreads + tid;
     rp[it] = i < t1 ? plane[i] : 0u;
   }
-  if (tid < kMaxSeg) s_cnt[tid] = 0;
-  if (tid < kWave) find_subarrays(B, F, n, k, depth, cutover, t0, t1, a == 0, perm, &s_si);
+  if (tid < kMaxSeg) {
+    s_cnt[tid] = 0;
+    s_si.s[tid] = seginfo[t].s[tid];
+    s_si.e[tid] = seginfo[t].e[tid];
+    s_si.med[tid] = seginfo[t].med[tid];
+    if (tid == 0) s_si.nseg = seginfo[t].nseg;
+  }
   __syncthreads();
   const int nseg = s_si.nseg;
-  if (a == 0 && tid < kMaxSeg) {
-    SegInfo* o = seginfo + t;
-    o->s[tid] = s_si.s[tid];
-    o->e[tid] = s_si.e[tid];
-    o->med[tid] = s_si.med[tid];
-    if (tid == 0) o->nseg = nseg;
-  }
   uint32_t c[kMaxSeg];
 #pragma unroll
   for (int q = 0; q < kMaxSeg; ++q) c[q] = 0;
@@ -241,68 +258,106 @@ __global__ __launch_bounds__(kLvThreads) void k_level_count(const RecBufs B, con
 
 // Chains the counts along every subarray: carry[a][t] = counts of tile t's
 // first subarray in all earlier tiles (lower in bits 0-31, node in 32-47).
+// Tile t contributes (v, h): v = the counts of its last subarray, h = that
+// subarray starts inside the tile; the chained value is the segmented
+// inclusive scan I_t = h ? v : I_{t-1} + v, and carry[t] = I_{t-1} when the
+// tile's first subarray started before it.  One block per moving array:
+// every thread scans a run of consecutive tiles, and the runs are joined by
+// a segmented scan over the block.
+__device__ __forceinline__ void seg_combine(uint64_t& v, int& h, uint64_t v_prev, int h_prev) {
+  if (!h) v += v_prev;
+  h = h || h_prev;
+}
+
 __global__ __launch_bounds__(1024) void k_level_scan(const Forest F, int depth,
                                                     const SegInfo* __restrict__ seginfo,
                                                     const uint32_t* __restrict__ cnt,
                                                     uint64_t* __restrict__ carry,
                                                     int tiles_per_array) {
-  __shared__ uint64_t s_v[1024];
-  __shared__ int s_h[1024];
-  __shared__ uint64_t s_run;
+  constexpr int kThreads = 1024, kWaves = kThreads / kWave;
+  __shared__ uint64_t s_v[kWaves];
+  __shared__ int s_h[kWaves];
   const int tid = threadIdx.x;
   const int nu = F.uoff[F.B];
   if (depth >= *F.lmax) return;
   const int a = blockIdx.x;
   const int tiles = (int)((nu + kLevelTile - 1) / kLevelTile);
-  if (tid == 0) s_run = 0;
+  const int per = (tiles + kThreads - 1) / kThreads;
+  const int c0 = min(tiles, tid * per), c1 = min(tiles, c0 + per);
+  auto tile_value = [&](int t, uint64_t* v, int* h, bool* cont) {
+    const SegInfo& si = seginfo[t];
+    const int ns = si.nseg;
+    *v = 0;
+    *h = 1;
+    *cont = false;
+    if (ns > 0) {
+      const uint32_t c = cnt[((int64_t)a * tiles_per_array + t) * kMaxSeg + (ns - 1)];
+      *v = (uint64_t)(c & 0xFFFF) | ((uint64_t)(c >> 16) << 32);
+      *h = si.s[ns - 1] >= t * kLevelTile;
+      *cont = si.s[0] < t * kLevelTile;
+    }
+  };
+  // aggregate of this thread's run
+  uint64_t av = 0;
+  int ah = 0;
+  for (int t = c0; t < c1; ++t) {
+    uint64_t v;
+    int h;
+    bool cont;
+    tile_value(t, &v, &h, &cont);
+    seg_combine(v, h, av, ah);
+    av = v;
+    ah = h;
+  }
+  // inclusive segmented scan of the run aggregates over the block
+  uint64_t iv = av;
+  int ih = ah;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint64_t ov = __shfl_up(iv, d, kWave);
+    const int oh = __shfl_up(ih, d, kWave);
+    if ((int)lane_id() >= d) seg_combine(iv, ih, ov, oh);
+  }
+  const int w = tid / kWave;
+  if (lane_id() == kWave - 1) {
+    s_v[w] = iv;
+    s_h[w] = ih;
+  }
   __syncthreads();
-  for (int base = 0; base < tiles; base += 1024) {
-    const int t = base + tid;
-    // tile t: value = counts of its last subarray inside it; head = that
-    // subarray starts inside it
-    uint64_t v = 0;
-    int h = 1;
-    bool cont = false;
-    if (t < tiles) {
-      const SegInfo& si = seginfo[t];
-      const int t0 = t * kLevelTile;
-      const int ns = si.nseg;
-      if (ns > 0) {
-        const uint32_t c = cnt[((int64_t)a * tiles_per_array + t) * kMaxSeg + (ns - 1)];
-        v = (uint64_t)(c & 0xFFFF) | ((uint64_t)(c >> 16) << 32);
-        h = si.s[ns - 1] >= t0;
-        cont = si.s[0] < t0;
-      }
+  if (tid == 0) {
+    uint64_t rv = 0;
+    int rh = 0;
+    for (int q = 0; q < kWaves; ++q) {  // exclusive prefix of the wave totals
+      const uint64_t qv = s_v[q];
+      const int qh = s_h[q];
+      s_v[q] = rv;
+      s_h[q] = rh;
+      uint64_t nv = qv;
+      int nh = qh;
+      seg_combine(nv, nh, rv, rh);
+      rv = nv;
+      rh = nh;
     }
-    // inclusive segmented scan over the block (Hillis-Steele in LDS)
-    s_v[tid] = v;
-    s_h[tid] = h;
-    __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-      uint64_t vo = 0;
-      int ho = 0;
-      if (tid >= d) {
-        vo = s_v[tid - d];
-        ho = s_h[tid - d];
-      }
-      __syncthreads();
-      if (tid >= d) {
-        if (!h) v += vo;
-        h = h || ho;
-      }
-      s_v[tid] = v;
-      s_h[tid] = h;
-      __syncthreads();
-    }
-    // the carry from the previous block of tiles joins until the first head
-    const uint64_t run = s_run;
-    const uint64_t incl = h ? v : run + v;
-    // exclusive value seen by tile t: inclusive value of tile t-1
-    uint64_t prev = tid > 0 ? (s_h[tid - 1] ? s_v[tid - 1] : run + s_v[tid - 1]) : run;
-    __syncthreads();
-    if (t < tiles) carry[(int64_t)a * tiles_per_array + t] = cont ? prev : 0ull;
-    if (tid == 1023) s_run = incl;
-    __syncthreads();
+  }
+  __syncthreads();
+  // exclusive value before this thread's run: the wave prefix joined with
+  // the lanes below
+  uint64_t ev = __shfl_up(iv, 1, kWave);
+  int eh = __shfl_up(ih, 1, kWave);
+  if (lane_id() == 0) {
+    ev = 0;
+    eh = 0;
+  }
+  seg_combine(ev, eh, s_v[w], s_h[w]);
+  // walk the run again, writing every tile's carry
+  uint64_t run = ev;
+  for (int t = c0; t < c1; ++t) {
+    uint64_t v;
+    int h;
+    bool cont;
+    tile_value(t, &v, &h, &cont);
+    carry[(int64_t)a * tiles_per_array + t] = cont ? run : 0ull;
+    run = h ? v : run + v;
   }
 }
 
@@ -453,8 +508,11 @@ hipError_t launch_level(const uint32_t* rec0, uint32_t* b1, uint32_t* b2, int64_
   RecBufs B{rec0, b1, b2};
   Forest F{fa.B, fa.off, fa.uoff, fa.lmax, fa.wgbase, fa.queue};
   SegInfo* si = static_cast<SegInfo*>(seginfo);
-  hipLaunchKernelGGL(k_level_count, dim3(grid), dim3(kLvThreads), 0, st, B, F, n, k, depth,
-                     cutover, perm, si, cnt, tiles);
+  const int seg_blocks = (tiles + kSegThreads / kWave - 1) / (kSegThreads / kWave);
+  hipLaunchKernelGGL(k_level_seg, dim3(seg_blocks), dim3(kSegThreads), 0, st, B, F, n, k, depth,
+                     cutover, perm, si, tiles);
+  hipLaunchKernelGGL(k_level_count, dim3(grid), dim3(kLvThreads), 0, st, B, F, n, k, depth, si, cnt,
+                     tiles);
   hipLaunchKernelGGL(k_level_scan, dim3(k - 1), dim3(1024), 0, st, F, depth, si, cnt, carry,
                      tiles);
 #define KD_LV(RR)                                                                               \
