@@ -225,7 +225,8 @@ enum kd_kernel_class {
   KD_K_HIST = 5,     /* digit histograms */
   KD_K_CANON = 6,    /* key canonicalisation */
   KD_K_RECORDS = 7,  /* rank tables and level-0 records */
-  KD_K_BUCKET = 8    /* learned presort: per-bucket finish */
+  KD_K_BUCKET = 8,   /* learned presort: per-bucket finish */
+  KD_K_TIES = 9      /* array 0: ordering the runs of equal first words */
 };
 int kd_probe_start(int32_t kernel_class, int32_t capacity);
 int kd_probe_stop(float* h_ms, int32_t* h_count);

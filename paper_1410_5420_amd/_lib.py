@@ -83,7 +83,7 @@ EXPORTED = ["kd_strerror", "kdtree_workspace_bytes", "kdtree_build", "kdtree_pre
             "kdtree_build_learned", "kdtree_presort_learned", "kd_probe_start", "kd_probe_stop"]
 
 KERNEL_CLASSES = {"onesweep": 1, "level": 2, "leaf": 3, "dedup": 4, "hist": 5, "canon": 6,
-                  "records": 7, "bucket": 8}
+                  "records": 7, "bucket": 8, "ties": 9}
 
 CDF_SEGMENTS = 4096
 CDF_MODEL_BYTES = 33024

@@ -38,7 +38,7 @@ int tree_digit_passes(int B) {
 struct Layout {
   size_t vbuf, carry, S, rec0, rec1, rec2;
   size_t rcnt, rgrp, dcnt, seginfo, lcnt, lcarry;
-  size_t uoff, wgbase, lmax, queue, offs;
+  size_t uoff, wgbase, lmax, queue, offs, ties;
   size_t starts, flags, lkey, carry2;  // learned presort only
   size_t end;
 };
@@ -81,6 +81,7 @@ Layout plan(int64_t n, int k, int B, bool learned = false) {
   L.lmax = take(4);
   L.queue = take(4);
   L.offs = take(16);
+  L.ties = take(4 * ((size_t)kMaxTieRuns + 2));  // run list, count, flag
   if (learned) {
     L.starts = take(4 * (((size_t)1 << kMaxBucketBits) + 1));
     L.flags = take(4 * kMaxK);
@@ -377,7 +378,23 @@ int presort_impl(const Job& J, hipStream_t st) {
       for (int ps = 0; ps < kPassesPerWord; ++ps) passes.push_back({w == 0 ? k : w, ps * kRadixBits});
     for (int ps = 0; ps < tp; ++ps) passes.push_back({k + 1, ps * kRadixBits});
     const int32_t* gate = nullptr;
-    if (learned && learned_sort_on(J, 0)) {
+    if (k > 1 && !(learned && learned_sort_on(J, 0))) {
+      // word 0 first (then tree), then the runs of equal word 0 by the other
+      // words and row; the complete sort above runs only if a run is too
+      // long for the tie step
+      std::vector<Pass> first;
+      for (int ps = 0; ps < kPassesPerWord; ++ps) first.push_back({k, ps * kRadixBits});
+      for (int ps = 0; ps < tp; ++ps) first.push_back({k + 1, ps * kRadixBits});
+      std::vector<Quant> qf = q;
+      int rc = run_sort(qf, first, ts, n, nullptr, vb, slots, rcnt, rgrp, st);
+      if (rc != KD_OK) return rc;
+      int32_t* tl = at<int32_t>(ws, L.ties);
+      int32_t* tcount = tl + kMaxTieRuns;
+      KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(tcount), 0u, 2, st));  // count, flag
+      TieArgs ta{final_slot(k), B > 1 ? final_slot(k + 1) : nullptr, final_slot(0), k};
+      KD_LAUNCH(KD_K_TIES, launch_ties(ta, n, tl, tcount, tcount + 1, st));
+      gate = tcount + 1;
+    } else if (learned && learned_sort_on(J, 0)) {
       // bucket on word 0; finish by words k-1 .. 1, then word 0; ties by row
       LearnedSort ls;
       ls.model = J.models;
@@ -912,7 +929,7 @@ int kdtree_build_learned(const void* d_tuples, int64_t n, int32_t k, int32_t dty
 }
 
 int kd_probe_start(int32_t kernel_class, int32_t capacity) {
-  if (kernel_class < KD_K_ONESWEEP || kernel_class > KD_K_BUCKET || capacity < 1 ||
+  if (kernel_class < KD_K_ONESWEEP || kernel_class > KD_K_TIES || capacity < 1 ||
       capacity > (1 << 20))
     return KD_EINVAL;
   kd::Probe& p = kd::g_probe;

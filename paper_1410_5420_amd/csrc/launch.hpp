@@ -87,6 +87,21 @@ hipError_t launch_dedup(const uint32_t* w0, const uint32_t* planes, const uint32
                         uint32_t* out_tree, uint32_t* cnt, int32_t* uoff, int num_trees,
                         hipStream_t st);
 
+// Word-0-first order of array 0 (after a radix sort by word 0 and tree):
+// w0 and tree (null for one tree) are the sorted key planes, planes the
+// n-strided planes [row id, w1, ..., w_{k-1}].  list: kMaxTieRuns words;
+// count and flag must be zero on entry; a non-zero flag asks for the full
+// radix sort instead.
+constexpr int kMaxTieRuns = 1 << 16;
+struct TieArgs {
+  const uint32_t* w0;
+  const uint32_t* tree;
+  uint32_t* planes;
+  int k;
+};
+hipError_t launch_ties(const TieArgs& ta, int64_t n, int32_t* list, int32_t* count, int32_t* flag,
+                       hipStream_t st);
+
 // tree[r] = b for the rows of every tree b.
 hipError_t launch_tree_ids(const int64_t* off, int num_trees, uint32_t* tree, hipStream_t st);
 

@@ -401,6 +401,146 @@ hipError_t launch_radix_pass(const uint32_t* keys_in, const TupleSrc& ts, int ke
   return hipGetLastError();
 }
 
+// ---- word-0-first order of array 0 ------------------------------------------
+// Appendix, "Optimized Super Key Comparison": compare word 0 first and look at
+// the other words only on a tie.  Array 0 is radix-sorted by word 0 (then
+// tree) alone, which leaves it in (tree, word 0, row) order; then every run of
+// equal (tree, word 0) -- rare for most inputs -- is put in (word 1, ...,
+// word k-1, row) order.  Runs of up to kSmallRun are sorted by one thread;
+// longer ones are listed and ranked by a workgroup each, unless they are
+// already in order (runs of identical rows).  A listed run longer than
+// kBigRun, or a full list, raises the flag, and the complete radix sort then
+// runs instead (gated on the flag).
+
+constexpr int kSmallRun = 32;
+constexpr int kBigRun = 4096;
+
+__device__ __forceinline__ bool same_w0(const TieArgs& ta, int i, int j) {
+  if (ta.tree && ta.tree[i] != ta.tree[j]) return false;
+  return ta.w0[i] == ta.w0[j];
+}
+
+// (words 1 .. k-1, then row id) of position x before position y?
+__device__ __forceinline__ bool tie_less(const TieArgs& ta, int64_t n, int x, int y) {
+  for (int d = 1; d < ta.k; ++d) {
+    const uint32_t* w = ta.planes + (int64_t)d * n;
+    const uint32_t a = w[x], b = w[y];
+    if (a != b) return a < b;
+  }
+  return ta.planes[x] < ta.planes[y];
+}
+
+__global__ __launch_bounds__(256) void k_ties_small(const TieArgs ta, int64_t n_host,
+                                                   int32_t* __restrict__ list,
+                                                   int32_t* __restrict__ count,
+                                                   int32_t* __restrict__ flag) {
+  const int n = (int)n_host;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    if (i > 0 && same_w0(ta, i, i - 1)) continue;  // not the start of a run
+    if (i + 1 >= n || !same_w0(ta, i, i + 1)) continue;  // a run of one
+    int e = i + 2;
+    while (e < n && e - i <= kSmallRun && same_w0(ta, i, e)) ++e;
+    if (e < n && same_w0(ta, i, e)) {  // longer than kSmallRun: for the workgroups
+      const int idx = atomicAdd(count, 1);
+      if (idx < kMaxTieRuns)
+        list[idx] = i;
+      else
+        atomicOr(flag, 1);
+      continue;
+    }
+    // insertion sort of positions i .. e-1, moving the k planes together
+    for (int x = i + 1; x < e; ++x) {
+      int y = x;
+      while (y > i && tie_less(ta, n, y, y - 1)) {
+        for (int d = 0; d < ta.k; ++d) {
+          uint32_t* w = ta.planes + (int64_t)d * n;
+          const uint32_t t = w[y];
+          w[y] = w[y - 1];
+          w[y - 1] = t;
+        }
+        --y;
+      }
+    }
+  }
+}
+
+// One workgroup per listed run: its length, whether it is already in order,
+// every element's rank (the number of smaller elements in the run), then the
+// planes permuted in place (every plane is read whole before it is written).
+constexpr int kTieThreads = 256;
+constexpr int kTieItems = kBigRun / kTieThreads;
+
+__global__ __launch_bounds__(kTieThreads) void k_ties_big(const TieArgs ta, int64_t n_host,
+                                                         const int32_t* __restrict__ list,
+                                                         const int32_t* __restrict__ count,
+                                                         int32_t* __restrict__ flag) {
+  __shared__ int s_len, s_unsorted;
+  const int n = (int)n_host;
+  const int tid = threadIdx.x;
+  const int runs = min(*count, kMaxTieRuns);
+  for (int r = blockIdx.x; r < runs; r += gridDim.x) {
+    const int s = list[r];
+    if (tid == 0) {
+      s_len = kBigRun + 1;
+      s_unsorted = 0;
+    }
+    __syncthreads();
+    // run length (at most kBigRun is looked at): the first position that differs
+    for (int j = tid + 1; j <= kBigRun; j += kTieThreads)
+      if (s + j >= n || !same_w0(ta, s, s + j)) atomicMin(&s_len, j);
+    __syncthreads();
+    const int L = s_len;
+    if (L > kBigRun) {  // longer than a workgroup sorts: the full sort runs instead
+      if (tid == 0) atomicOr(flag, 2);
+      __syncthreads();
+      continue;
+    }
+    for (int j = tid + 1; j < L; j += kTieThreads)
+      if (tie_less(ta, n, s + j, s + j - 1)) s_unsorted = 1;
+    __syncthreads();
+    if (s_unsorted) {
+      int rank[kTieItems];
+#pragma unroll
+      for (int q = 0; q < kTieItems; ++q) {
+        const int j = tid + q * kTieThreads;
+        rank[q] = 0;
+        if (j < L) {
+          int c = 0;
+          for (int b = 0; b < L; ++b) c += tie_less(ta, n, s + b, s + j) ? 1 : 0;
+          rank[q] = c;
+        }
+      }
+      for (int d = 0; d < ta.k; ++d) {
+        uint32_t* w = ta.planes + (int64_t)d * n + s;
+        uint32_t v[kTieItems];
+#pragma unroll
+        for (int q = 0; q < kTieItems; ++q) {
+          const int j = tid + q * kTieThreads;
+          v[q] = j < L ? w[j] : 0u;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kTieItems; ++q) {
+          const int j = tid + q * kTieThreads;
+          if (j < L) w[rank[q]] = v[q];
+        }
+        __syncthreads();
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_ties(const TieArgs& ta, int64_t n, int32_t* list, int32_t* count, int32_t* flag,
+                       hipStream_t st) {
+  if (n <= 1) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_ties_small, dim3((unsigned)blocks), dim3(256), 0, st, ta, n, list, count, flag);
+  hipLaunchKernelGGL(k_ties_big, dim3(1024), dim3(kTieThreads), 0, st, ta, n, list, count, flag);
+  return hipGetLastError();
+}
+
 // ---- duplicate removal --------------------------------------------------------
 // Sec. 2.1: after the sort by x:y:z:..., identical rows are contiguous; keep
 // the first of each run (the smallest row, the sort being stable).  The sorted
