@@ -92,7 +92,7 @@ hipError_t launch_dedup(const uint32_t* w0, const uint32_t* planes, const uint32
 // n-strided planes [row id, w1, ..., w_{k-1}].  list: kMaxTieRuns words;
 // count and flag must be zero on entry; a non-zero flag asks for the full
 // radix sort instead.
-constexpr int kMaxTieRuns = 1 << 16;
+constexpr int kMaxTieRuns = 1 << 20;
 struct TieArgs {
   const uint32_t* w0;
   const uint32_t* tree;

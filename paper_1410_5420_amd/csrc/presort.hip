@@ -406,14 +406,16 @@ hipError_t launch_radix_pass(const uint32_t* keys_in, const TupleSrc& ts, int ke
 // the other words only on a tie.  Array 0 is radix-sorted by word 0 (then
 // tree) alone, which leaves it in (tree, word 0, row) order; then every run of
 // equal (tree, word 0) -- rare for most inputs -- is put in (word 1, ...,
-// word k-1, row) order.  Runs of up to kSmallRun are sorted by one thread;
-// longer ones are listed and ranked by a workgroup each, unless they are
-// already in order (runs of identical rows).  A listed run longer than
+// word k-1, row) order.  Runs of up to kSmallRun are ranked in LDS by the
+// workgroup of their tile; longer ones are listed and ranked by a workgroup each,
+// unless they are already in order (runs of identical rows).  A listed run longer than
 // kBigRun, or a full list, raises the flag, and the complete radix sort then
 // runs instead (gated on the flag).
 
-constexpr int kSmallRun = 32;
+constexpr int kSmallRun = 64;
 constexpr int kBigRun = 4096;
+constexpr int kTieTile = 1024;               // positions per workgroup
+constexpr int kTieSpan = kTieTile + kSmallRun;  // plus the longest run crossing its end
 
 __device__ __forceinline__ bool same_w0(const TieArgs& ta, int i, int j) {
   if (ta.tree && ta.tree[i] != ta.tree[j]) return false;
@@ -430,37 +432,227 @@ __device__ __forceinline__ bool tie_less(const TieArgs& ta, int64_t n, int x, in
   return ta.planes[x] < ta.planes[y];
 }
 
-__global__ __launch_bounds__(256) void k_ties_small(const TieArgs ta, int64_t n_host,
-                                                   int32_t* __restrict__ list,
-                                                   int32_t* __restrict__ count,
-                                                   int32_t* __restrict__ flag) {
-  const int n = (int)n_host;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    if (i > 0 && same_w0(ta, i, i - 1)) continue;  // not the start of a run
-    if (i + 1 >= n || !same_w0(ta, i, i + 1)) continue;  // a run of one
-    int e = i + 2;
-    while (e < n && e - i <= kSmallRun && same_w0(ta, i, e)) ++e;
-    if (e < n && same_w0(ta, i, e)) {  // longer than kSmallRun: for the workgroups
-      const int idx = atomicAdd(count, 1);
-      if (idx < kMaxTieRuns)
-        list[idx] = i;
-      else
-        atomicOr(flag, 1);
-      continue;
-    }
-    // insertion sort of positions i .. e-1, moving the k planes together
-    for (int x = i + 1; x < e; ++x) {
-      int y = x;
-      while (y > i && tie_less(ta, n, y, y - 1)) {
-        for (int d = 0; d < ta.k; ++d) {
-          uint32_t* w = ta.planes + (int64_t)d * n;
-          const uint32_t t = w[y];
-          w[y] = w[y - 1];
-          w[y - 1] = t;
-        }
-        --y;
+constexpr int kTileThreads = 256;
+constexpr int kTileItems = (kTieSpan + kTileThreads - 1) / kTileThreads;  // positions per thread
+constexpr int kTileGrid = 1024;  // resident workgroups walking the tiles
+
+// Exclusive max over the threads of a kTileThreads workgroup (-1 for thread
+// 0); s_tmp holds kTileThreads/64 words.  Contains barriers.
+__device__ __forceinline__ int block_exclusive_max(int v, int* s_tmp) {
+  const int lane = (int)lane_id(), w = threadIdx.x / kWave;
+  int inc = v;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int o = __shfl_up(inc, d, kWave);
+    if (lane >= d) inc = max(inc, o);
+  }
+  const int below = __shfl_up(inc, 1, kWave);
+  if (lane == kWave - 1) s_tmp[w] = inc;
+  __syncthreads();
+  int res = lane > 0 ? below : -1;
+  for (int i = 0; i < w; ++i) res = max(res, s_tmp[i]);
+  __syncthreads();
+  return res;
+}
+
+// Staged values of one tile: thread t holds local positions t - 1 + m * kTileThreads
+// (position -1 is the one before the tile).
+constexpr int kTileLoads = (kTieSpan + 1 + kTileThreads - 1) / kTileThreads;
+struct TileRegs {
+  uint32_t w0[kTileLoads], tr[kTileLoads], a[kTileLoads], b[kTileLoads], id[kTileLoads];
+};
+
+__device__ __forceinline__ int tile_span(int t0, int n) {
+  return min(n, min(n, t0 + kTieTile) + kSmallRun) - t0;
+}
+
+__device__ __forceinline__ void tile_load(const TieArgs& ta, int n, int t0, TileRegs& r) {
+  const int span = tile_span(t0, n);
+  const uint32_t* w1 = ta.k > 1 ? ta.planes + (int64_t)n : nullptr;
+  const uint32_t* w2 = ta.k > 2 ? ta.planes + 2 * (int64_t)n : nullptr;
+#pragma unroll
+  for (int m = 0; m < kTileLoads; ++m) {
+    const int x = (int)threadIdx.x - 1 + m * kTileThreads;
+    const int i = t0 + x;
+    r.w0[m] = 0;
+    r.tr[m] = 0xFFFFFFFFu;  // no predecessor: never equal (tree ids are small)
+    r.a[m] = r.b[m] = r.id[m] = 0;
+    if (x < span && i >= 0) {
+      r.w0[m] = ta.w0[i];
+      r.tr[m] = ta.tree ? ta.tree[i] : 0u;
+      if (x >= 0) {
+        if (w1) r.a[m] = w1[i];
+        if (w2) r.b[m] = w2[i];
+        r.id[m] = ta.planes[i];
       }
     }
+  }
+}
+
+// Runs that start in a tile of kTieTile positions and hold at most kSmallRun
+// elements are ordered in LDS.  The place of an element in its run is the
+// number of the run's elements that precede it; the element-by-element
+// comparisons this takes (the sum of the squared run lengths) are dealt out
+// evenly to the threads, whatever the mix of run lengths.  Words 1 and 2 and
+// the row id are staged; later words are read on ties of those.  The planes
+// are then rewritten at the positions that moved.  Longer runs are listed for
+// k_ties_big.  Each workgroup walks tiles with a grid stride and loads the
+// next tile's planes into registers while it orders the current one.  Other
+// workgroups rewrite only positions of runs that start in their own tiles, so
+// values staged here for positions of such runs may be stale but are never
+// used; word 0 and the tree ids are not written at all.
+__global__ __launch_bounds__(kTileThreads) void k_ties_tile(const TieArgs ta, int64_t n_host,
+                                                           int32_t* __restrict__ list,
+                                                           int32_t* __restrict__ count,
+                                                           int32_t* __restrict__ flag) {
+  __shared__ uint32_t s_w0[kTieSpan + 1], s_tr[kTieSpan + 1];  // later: pair offsets, ranks
+  __shared__ uint32_t s_a[kTieSpan], s_b[kTieSpan], s_id[kTieSpan];
+  __shared__ int16_t s_start[kTieSpan];
+  __shared__ uint16_t s_end[kTieSpan], s_perm[kTieSpan];
+  __shared__ int s_tmp[kTileThreads / kWave + 1];
+  const int n = (int)n_host;
+  const int tid = threadIdx.x;
+  const int tiles = (n + kTieTile - 1) / kTieTile;
+  TileRegs r;
+  if ((int)blockIdx.x < tiles) tile_load(ta, n, blockIdx.x * kTieTile, r);
+  for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int t0 = tile * kTieTile;
+    const int own = min(n, t0 + kTieTile) - t0;  // runs starting at local [0, own) are this tile's
+    const int t2 = min(n, t0 + own + kSmallRun);
+    const int span = t2 - t0;                     // staged local positions [0, span)
+    // s_w0[x + 1] holds local position x, s_w0[0] the position before the tile
+#pragma unroll
+    for (int m = 0; m < kTileLoads; ++m) {
+      const int x = tid - 1 + m * kTileThreads;
+      if (x < span) {
+        s_w0[x + 1] = r.w0[m];
+        s_tr[x + 1] = r.tr[m];
+        if (x >= 0) {
+          s_a[x] = r.a[m];
+          s_b[x] = r.b[m];
+          s_id[x] = r.id[m];
+          s_perm[x] = (uint16_t)x;
+        }
+      }
+    }
+    __syncthreads();
+    if (tile + (int)gridDim.x < tiles) tile_load(ta, n, (tile + gridDim.x) * kTieTile, r);
+    auto same = [&](int x, int y) {  // local positions, -1 = the one before
+      return s_w0[x + 1] == s_w0[y + 1] && s_tr[x + 1] == s_tr[y + 1];
+    };
+    // run starts: thread t holds positions [t * kTileItems, (t + 1) * kTileItems);
+    // a position continuing the run before the tile gets start -1
+    const int p0 = tid * kTileItems;
+    int last = -1;
+    for (int q = 0; q < kTileItems; ++q) {
+      const int x = p0 + q;
+      if (x < span && !same(x - 1, x)) last = x;
+    }
+    int st = block_exclusive_max(last, s_tmp);
+    for (int q = 0; q < kTileItems; ++q) {
+      const int x = p0 + q;
+      if (x >= span) break;
+      if (!same(x - 1, x)) st = x;
+      s_start[x] = (int16_t)st;
+      if (st >= 0 && (x + 1 == span || !same(x, x + 1))) s_end[st] = (uint16_t)(x + 1);
+    }
+    __syncthreads();
+    // comparisons per element: its run's length, for runs of 2 .. kSmallRun
+    // that start in the tile and end inside the staged span
+    int len[kTileItems];
+    int mine = 0;
+    for (int q = 0; q < kTileItems; ++q) {
+      const int x = p0 + q;
+      len[q] = 0;
+      if (x >= span) continue;
+      const int s = s_start[x];
+      if (s < 0 || s >= own) continue;
+      const int e = s_end[s];
+      if (e - s < 2) continue;
+      const bool longer = (e - s > kSmallRun) || (e == span && t2 < n && same_w0(ta, t0 + s, t2));
+      if (longer) {
+        if (x == s) {
+          const int idx = atomicAdd(count, 1);
+          if (idx < kMaxTieRuns)
+            list[idx] = t0 + s;
+          else
+            atomicOr(flag, 1);
+        }
+        continue;
+      }
+      len[q] = e - s;
+      mine += len[q];
+    }
+    int total;
+    int off = block_exclusive_sum<kTileThreads>(mine, s_tmp, &total);
+    int* s_off = reinterpret_cast<int*>(s_w0);   // s_off[x]: first comparison of x; s_off[span] = total
+    int* s_rank = reinterpret_cast<int*>(s_tr);  // elements of the run before x
+    for (int q = 0; q < kTileItems; ++q) {
+      const int x = p0 + q;
+      if (x >= span) break;
+      s_off[x] = off;
+      s_rank[x] = 0;
+      off += len[q];
+    }
+    if (tid == 0) s_off[span] = total;
+    __syncthreads();
+    auto less = [&](int x, int y) {  // local positions
+      if (s_a[x] != s_a[y]) return s_a[x] < s_a[y];
+      if (s_b[x] != s_b[y]) return s_b[x] < s_b[y];
+      for (int d = 3; d < ta.k; ++d) {
+        const uint32_t* w = ta.planes + (int64_t)d * n;
+        const uint32_t a = w[t0 + x], b = w[t0 + y];
+        if (a != b) return a < b;
+      }
+      return s_id[x] < s_id[y];
+    };
+    if (total > 0) {
+      const int chunk = (total + kTileThreads - 1) / kTileThreads;
+      const int c0 = min(total, tid * chunk), c1 = min(total, c0 + chunk);
+      if (c0 < c1) {
+        int lo = 0, hi = span - 1;  // the last x with s_off[x] <= c0 (it has len > 0)
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_off[mid] <= c0)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        int x = lo, ox = s_off[x], ex = s_off[x + 1], sx = s_start[x], c = 0;
+        for (int w = c0; w < c1; ++w) {
+          while (w >= ex) {  // next element with comparisons
+            if (c) atomicAdd(&s_rank[x], c);
+            c = 0;
+            ++x;
+            ox = s_off[x];
+            ex = s_off[x + 1];
+            sx = s_start[x];
+          }
+          c += less(sx + (w - ox), x) ? 1 : 0;
+        }
+        if (c) atomicAdd(&s_rank[x], c);
+      }
+      __syncthreads();
+      for (int q = 0; q < kTileItems; ++q) {
+        const int x = p0 + q;
+        if (len[q]) s_perm[s_start[x] + s_rank[x]] = (uint16_t)x;
+      }
+      __syncthreads();
+      // rewrite the planes where an element moved; planes 0..2 come from LDS,
+      // later ones are staged through s_w0 (free once the places are known)
+      for (int d = 0; d < ta.k; ++d) {
+        uint32_t* w = ta.planes + (int64_t)d * n + t0;
+        const uint32_t* src = d == 0 ? s_id : d == 1 ? s_a : d == 2 ? s_b : s_w0;
+        if (d >= 3) {
+          for (int x = tid; x < span; x += kTileThreads) s_w0[x] = w[x];
+          __syncthreads();
+        }
+        for (int x = tid; x < span; x += kTileThreads)
+          if (s_perm[x] != x) w[x] = src[s_perm[x]];
+        if (d >= 3) __syncthreads();
+      }
+    }
+    __syncthreads();  // LDS is refilled for the next tile
   }
 }
 
@@ -534,9 +726,9 @@ __global__ __launch_bounds__(kTieThreads) void k_ties_big(const TieArgs ta, int6
 hipError_t launch_ties(const TieArgs& ta, int64_t n, int32_t* list, int32_t* count, int32_t* flag,
                        hipStream_t st) {
   if (n <= 1) return hipSuccess;
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_ties_small, dim3((unsigned)blocks), dim3(256), 0, st, ta, n, list, count, flag);
+  const int64_t tiles = (n + kTieTile - 1) / kTieTile;
+  const int64_t blocks = tiles < kTileGrid ? tiles : kTileGrid;
+  hipLaunchKernelGGL(k_ties_tile, dim3((unsigned)blocks), dim3(kTileThreads), 0, st, ta, n, list, count, flag);
   hipLaunchKernelGGL(k_ties_big, dim3(1024), dim3(kTieThreads), 0, st, ta, n, list, count, flag);
   return hipGetLastError();
 }

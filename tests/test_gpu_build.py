@@ -92,6 +92,33 @@ def test_record_completion_paths(kd, records, k):
     assert np.array_equal(lo.cpu().numpy(), want["lo"])
 
 
+def word0_runs(lengths, k, seed, spread):
+    """Rows whose first coordinate repeats in runs of the given lengths (in
+    shuffled order); the other coordinates are drawn from [-spread, spread]."""
+    g = kdgen.rng(seed)
+    x0 = np.repeat(g.permutation(len(lengths)).astype(np.int32) * 3 - 1000, lengths)
+    t = g.integers(-spread, spread + 1, size=(len(x0), k)).astype(np.int32)
+    t[:, 0] = x0
+    return np.ascontiguousarray(t[g.permutation(len(x0))])
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5])
+@pytest.mark.parametrize("spread", [3, 1 << 20])
+def test_first_coordinate_runs(kd, k, spread):
+    """Array 0 is ordered by its first word, then equal first words are put in
+    order by the remaining words: runs of every length class (one, a few, the
+    LDS limit of 64 and just past it, long runs ranked by a workgroup), placed
+    across tile boundaries."""
+    g = kdgen.rng(40 + k)
+    lengths = g.choice([1, 2, 3, 5, 17, 63, 64, 65, 66, 100, 1000, 4096], size=400)
+    assert_same(kd, word0_runs(lengths, k, 50 + k, spread))
+
+
+def test_first_coordinate_run_too_long(kd):
+    """A run past the workgroup limit sends array 0 to the complete sort."""
+    assert_same(kd, word0_runs([3, 5000, 70, 2, 9000, 1], 3, 61, 1 << 20))
+
+
 def test_all_duplicates(kd):
     t = np.tile(np.array([[5, -7, 9]], dtype=np.int32), (10000, 1))
     assert_same(kd, t)
