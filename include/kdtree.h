@@ -72,7 +72,10 @@ typedef struct kd_options {
   int32_t learned_sorts; /* learned builds only: bit d set = the sort for
                           super key d goes through the learned buckets, the
                           others through the radix passes; 0 = all */
-  int32_t reserved[4]; /* must be zero */
+  int32_t level;       /* global partition levels: 0 = default (1), 1 = count,
+                          chain and move launches, 2 = one move launch per
+                          level whose tiles chain their counts by look-back */
+  int32_t reserved[3]; /* must be zero */
 } kd_options;
 
 /* Human-readable name of a status code (static string). */

@@ -43,20 +43,22 @@ class Builder:
     dimensions, so repeated builds allocate nothing."""
 
     def __init__(self, n: int, k: int, dtype=torch.int32, device="cuda", cutover: int | None = None,
-                 leaf_blocks: int | None = None, records: int | None = None):
+                 leaf_blocks: int | None = None, records: int | None = None, level: int | None = None):
         self.n, self.k = int(n), int(k)
         self.code = _dtype_code(torch.empty(0, dtype=dtype))
         self.device = torch.device(device)
         self.cutover = cutover
         self.leaf_blocks = leaf_blocks
         self.records = records
+        self.level = level
         nbytes = _lib.workspace_bytes(self.n, self.k, self.code)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.n_unique = torch.zeros(1, dtype=torch.int64, device=self.device)
 
     def _opts(self):
         return _lib.options(self.cutover, getattr(self, "leaf_blocks", None),
-                            getattr(self, "records", None), getattr(self, "learned_sorts", None))
+                            getattr(self, "records", None), getattr(self, "learned_sorts", None),
+                            getattr(self, "level", None))
 
     def _check_input(self, tuples: torch.Tensor):
         if tuples.dim() != 2 or tuples.shape[1] != self.k or tuples.shape[0] > self.n:
@@ -98,11 +100,12 @@ class BatchedBuilder:
     ``tuples`` into trees; the workspace is sized for exactly that split."""
 
     def __init__(self, offsets, k: int, dtype=torch.int32, device="cuda", cutover: int | None = None,
-                 leaf_blocks: int | None = None, records: int | None = None):
+                 leaf_blocks: int | None = None, records: int | None = None, level: int | None = None):
         import numpy as np
 
         self.leaf_blocks = leaf_blocks
         self.records = records
+        self.level = level
         off = np.asarray(offsets.cpu() if isinstance(offsets, torch.Tensor) else offsets, dtype=np.int64)
         self.h_offsets = np.ascontiguousarray(off)
         self.trees = int(off.shape[0] - 1)
@@ -124,33 +127,35 @@ class BatchedBuilder:
         rc = _lib.lib.kdtree_build_batched(
             _ptr(tuples), _ptr(self.d_offsets), self.h_offsets.ctypes.data_as(ctypes.c_void_p),
             self.trees, self.k, self.code, _ptr(perm), _ptr(self.n_unique), _ptr(self.workspace),
-            self.workspace.numel(), _lib.options(self.cutover, self.leaf_blocks, self.records),
+            self.workspace.numel(), _lib.options(self.cutover, self.leaf_blocks, self.records,
+                                                 level=self.level),
             _stream(stream))
         _lib.check(rc, "kdtree_build_batched")
 
 
-def build_batched(tuples: torch.Tensor, offsets, cutover: int | None = None, stream=None):
+def build_batched(tuples: torch.Tensor, offsets, cutover: int | None = None, stream=None,
+                  level: int | None = None):
     """Build one tree per row range ``offsets[b] .. offsets[b+1]-1``.
 
     Returns ``(perm, n_unique)``: perm (int32, length offsets[-1]) holds tree
     b's in-order layout at positions offsets[b] .. offsets[b]+n_unique[b]-1,
     as row indices local to the tree.
     """
-    b = BatchedBuilder(offsets, tuples.shape[1], tuples.dtype, tuples.device, cutover)
+    b = BatchedBuilder(offsets, tuples.shape[1], tuples.dtype, tuples.device, cutover, level=level)
     perm = torch.full((max(b.total, 1),), -1, dtype=torch.int32, device=tuples.device)
     b.build(tuples.contiguous(), perm, stream)
     return perm[: b.total], b.n_unique
 
 
 def build(tuples: torch.Tensor, children: bool = False, cutover: int | None = None, stream=None,
-          records: int | None = None):
+          records: int | None = None, level: int | None = None):
     """Build the tree of ``tuples`` ((n, k) int32/float32 device tensor).
 
     Returns ``(perm, n_unique)`` or ``(perm, n_unique, lo, hi)`` with device
     tensors trimmed to ``n_unique`` (this synchronises to read the count).
     """
     n, k = tuples.shape
-    b = Builder(max(n, 1), k, tuples.dtype, tuples.device, cutover, records=records)
+    b = Builder(max(n, 1), k, tuples.dtype, tuples.device, cutover, records=records, level=level)
     perm = torch.full((max(n, 1),), -1, dtype=torch.int32, device=tuples.device)
     lo = hi = None
     if children:
@@ -234,7 +239,7 @@ class LearnedBuilder(Builder):
 
     def __init__(self, n: int, k: int, dtype=torch.int32, device="cuda", cutover: int | None = None,
                  leaf_blocks: int | None = None, records: int | None = None,
-                 learned_sorts: int | None = None):
+                 learned_sorts: int | None = None, level: int | None = None):
         self.n, self.k = int(n), int(k)
         self.code = _dtype_code(torch.empty(0, dtype=dtype))
         self.device = torch.device(device)
@@ -242,6 +247,7 @@ class LearnedBuilder(Builder):
         self.leaf_blocks = leaf_blocks
         self.records = records
         self.learned_sorts = learned_sorts
+        self.level = level
         nbytes = _lib.workspace_bytes_learned(self.n, self.k, self.code)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.n_unique = torch.zeros(1, dtype=torch.int64, device=self.device)

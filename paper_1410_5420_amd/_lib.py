@@ -24,7 +24,7 @@ class KdError(RuntimeError):
 class kd_options(ctypes.Structure):
     _fields_ = [("cutover", ctypes.c_int32), ("leaf_blocks", ctypes.c_int32),
                 ("records", ctypes.c_int32), ("learned_sorts", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("level", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 def _load():
@@ -119,14 +119,16 @@ def workspace_bytes_batched(total: int, trees: int, k: int, dtype: int) -> int:
 
 
 def options(cutover: int | None, leaf_blocks: int | None = None, records: int | None = None,
-            learned_sorts: int | None = None):
-    if cutover is None and leaf_blocks is None and records is None and learned_sorts is None:
+            learned_sorts: int | None = None, level: int | None = None):
+    if cutover is None and leaf_blocks is None and records is None and learned_sorts is None \
+            and level is None:
         return None
     o = kd_options()
     o.cutover = int(cutover or 0)
     o.leaf_blocks = int(leaf_blocks or 0)
     o.records = int(records or 0)
     o.learned_sorts = int(learned_sorts or 0)
+    o.level = int(level or 0)
     return ctypes.byref(o)
 
 

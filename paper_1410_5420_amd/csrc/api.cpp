@@ -37,7 +37,7 @@ int tree_digit_passes(int B) {
 // plain build sit at the same offsets in both layouts.
 struct Layout {
   size_t vbuf, carry, S, rec0, rec1, rec2;
-  size_t rcnt, rgrp, dcnt, seginfo, lcnt, lcarry;
+  size_t rcnt, rgrp, dcnt, seginfo, lcnt, lcarry, lstat, ltick;
   size_t uoff, wgbase, lmax, queue, offs, ties;
   size_t starts, flags, lkey, carry2;  // learned presort only
   size_t end;
@@ -76,6 +76,8 @@ Layout plan(int64_t n, int k, int B, bool learned = false) {
   L.seginfo = take(lt * level_seginfo_bytes());
   L.lcnt = take(4 * lt * 8 * (k > 1 ? k - 1 : 1));
   L.lcarry = take(8 * lt * (k > 1 ? k - 1 : 1));
+  L.lstat = take(8 * lt * (k > 1 ? k - 1 : 1));
+  L.ltick = take(4 * kMaxLevels);
   L.uoff = take(4 * ((size_t)B + 1));
   L.wgbase = take(4 * ((size_t)B + 1));
   L.lmax = take(4);
@@ -100,14 +102,17 @@ T* at(void* base, size_t off) {
 bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
 
 int check_opts(const kd_options* opts, int64_t* cutover, int* leaf_blocks, int* records,
-               int* learned_sorts) {
+               int* learned_sorts, int* level) {
   *cutover = 1024;
   *leaf_blocks = 2048;
   *records = 0;
   *learned_sorts = 0;
+  *level = 0;
   if (opts) {
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 3; ++i)
       if (opts->reserved[i] != 0) return KD_EINVAL;
+    if (opts->level < 0 || opts->level > 2) return KD_EINVAL;
+    *level = opts->level;
     if (opts->learned_sorts < 0 || opts->learned_sorts > 0xFF) return KD_EINVAL;
     *learned_sorts = opts->learned_sorts;
     if (opts->records < 0 || opts->records > 2) return KD_EINVAL;
@@ -312,6 +317,7 @@ struct Job {
   int leaf_blocks = 2048;
   int records = 0;  // 0: by size, 1: direct scatter, 2: radix pass + placement
   int learned_sorts = 0;  // learned presort: bit d = sort d uses the buckets; 0 = all
+  int level = 0;          // 0/1: seg + chain + move launches per level, 2: look-back launch
   const CdfModel* models = nullptr;  // learned presort: one model per dimension
   int32_t* fell_back = nullptr;      // learned presort: per-sort fallback flags (device)
 };
@@ -566,10 +572,19 @@ int partition_impl(const Job& J, hipStream_t st) {
         levels = lc > levels ? lc : levels;
         items += nb > 0 ? ((int64_t)1 << lc) : 0;
       }
+      // look-back levels: status words and tile counters start from zero
+      const bool lookback = J.level == 2;
+      uint64_t* lstat = lookback ? at<uint64_t>(ws, L.lstat) : nullptr;
+      int32_t* ltick = at<int32_t>(ws, L.ltick);
+      if (lookback && levels > 0) {
+        KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(lstat), 0u,
+                               2 * level_tiles(n) * (k - 1), st));
+        KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(ltick), 0u, kMaxLevels, st));
+      }
       for (int d = 0; d < levels; ++d)
         KD_LAUNCH(KD_K_LEVEL, launch_level(r0, r1, r2, n, k, d, cutover, fa, J.perm,
                                            at<void>(ws, L.seginfo), at<uint32_t>(ws, L.lcnt),
-                                           at<uint64_t>(ws, L.lcarry), st));
+                                           at<uint64_t>(ws, L.lcarry), lstat, ltick, st));
       // the finish takes its items from a counter; partition may run again
       // after one presort, so the counter is cleared here
       KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(fa.queue), 0u, 1, st));
@@ -590,7 +605,7 @@ int check_job(Job& J, size_t ws_bytes, const kd_options* opts) {
   if (!aligned4(J.tuples) || !aligned4(J.ws)) return KD_EINVAL;
   if ((reinterpret_cast<uintptr_t>(J.n_unique) & 7u) != 0) return KD_EINVAL;
   if (ws_bytes < plan(J.n, J.k, J.B, J.models != nullptr).end) return KD_ENOMEM;
-  int rc = check_opts(opts, &J.cutover, &J.leaf_blocks, &J.records, &J.learned_sorts);
+  int rc = check_opts(opts, &J.cutover, &J.leaf_blocks, &J.records, &J.learned_sorts, &J.level);
   if (rc != KD_OK) return rc;
   while (J.cutover > 1024 && leaf_lds_bytes(J.cutover, J.k) + 8192 > 160 * 1024) J.cutover /= 2;
   return KD_OK;

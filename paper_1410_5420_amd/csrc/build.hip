@@ -86,16 +86,17 @@ __device__ __forceinline__ void forest_subarray(const Forest& F, int64_t cutover
 }
 
 // ---- global level -------------------------------------------------------------
-// A level is four launches with no waiting between workgroups:
-//   0. seg:   one wave per tile finds the subarrays that meet it and their
-//      medians' ranks (and records the medians' row ids);
-//   1. count: tile t of moving array a counts, per subarray piece, the
-//      elements that go to the lower half and whether the median itself is
-//      there;
+// A level is three launches with no waiting between workgroups:
+//   1. seg:   one workgroup per tile finds the subarrays that meet it and
+//      their medians' ranks (and records the medians' row ids), and counts,
+//      in every moving array, the elements of the tile's last subarray piece
+//      that go to the lower half and whether the median itself is there;
 //   2. scan:  one block per array chains those counts from tile to tile
 //      along each subarray (a segmented scan);
 //   3. move:  tile t recomputes its elements' sides, adds the in-tile prefix
 //      to the carried counts and writes every rank plane to its new place.
+// (A look-back form that chains the counts inside the move launch follows
+// the move kernel.)
 
 constexpr int kLvThreads = 512;
 constexpr int kLvItems = kLevelTile / kLvThreads;  // 8
@@ -174,86 +175,82 @@ __device__ void find_subarrays(const RecBufs& B, const Forest& F, int64_t n, int
   if (lane == 0) out->nseg = min((int)popc64(km), kMaxSeg);
 }
 
-// Subarrays meeting every tile (one wave per tile), their medians' ranks,
-// and the row ids of the medians inside the tile.
+// Subarrays meeting every tile, their medians' ranks, and the row ids of the
+// medians inside the tile (wave 0 of a workgroup per tile); then, for every
+// moving array, the counts of the tile's last subarray piece (lower | node <<
+// 32), whether that subarray starts inside the tile (bit 48) and whether the
+// tile's first subarray started before it (bit 49).  The rank planes are
+// loaded before the subarrays are known, so the loads overlap that search.
 constexpr int kSegThreads = 256;
+constexpr int kSegItems = kLevelTile / kSegThreads;
+template <int R>  // moving arrays counted (k - 1, or 0 when only the subarrays are wanted)
 __global__ __launch_bounds__(kSegThreads) void k_level_seg(const RecBufs B, const Forest F, int64_t n,
                                                           int k, int depth, int64_t cutover,
                                                           int32_t* __restrict__ perm,
-                                                          SegInfo* __restrict__ seginfo, int tiles) {
-  const int nu = F.uoff[F.B];
-  if (depth >= *F.lmax) return;
-  const int t = blockIdx.x * (kSegThreads / kWave) + threadIdx.x / kWave;
-  if (t >= tiles) return;
-  const int t0 = t * kLevelTile;
-  if (t0 >= nu) return;
-  const int t1 = min(t0 + kLevelTile, nu);
-  find_subarrays(B, F, n, k, depth, cutover, t0, t1, true, perm, seginfo + t);
-}
-
-// Per tile of every moving array: how many elements of each subarray piece
-// go to the lower half, and whether the median itself is there (packed as
-// lower | node << 16).
-__global__ __launch_bounds__(kLvThreads) void k_level_count(const RecBufs B, const Forest F,
-                                                           int64_t n, int k, int depth,
-                                                           const SegInfo* __restrict__ seginfo,
-                                                           uint32_t* __restrict__ cnt,
-                                                           int tiles_per_array) {
+                                                          SegInfo* __restrict__ seginfo,
+                                                          uint64_t* __restrict__ tval, int tiles) {
   __shared__ SegInfo s_si;
-  __shared__ uint32_t s_cnt[kMaxSeg];
+  __shared__ uint32_t s_c[kMaxK];
   const int tid = threadIdx.x;
   const int nu = F.uoff[F.B];
   if (depth >= *F.lmax) return;
-  const int p = depth % k;
-  const int a = blockIdx.x / tiles_per_array;
-  const int t = blockIdx.x % tiles_per_array;
-  const int j = (p + 1 + a) % k;
+  const int t = blockIdx.x;
   const int t0 = t * kLevelTile;
-  if (t0 >= nu) return;
+  if (t >= tiles || t0 >= nu) return;
   const int t1 = min(t0 + kLevelTile, nu);
-  // the plane holding the rank in order p
-  const int cp = (p - j - 1 + 2 * k) % k;
-  const uint32_t* plane = buf_after(B, moves_before(depth, j, k)) + record_offset(j, k, n) +
-                          (int64_t)cp * n;
-  uint32_t rp[kLvItems];
+  const int p = depth % k;
+  constexpr int arrays = R;
+  uint32_t rp[R > 0 ? R : 1][kSegItems];
 #pragma unroll
-  for (int it = 0; it < kLvItems; ++it) {
-    const int i = t0 + it * kLvThreads + tid;
-    rp[it] = i < t1 ? plane[i] : 0u;
+  for (int a = 0; a < R; ++a) {
+    const int j = (p + 1 + a) % k;
+    const int cp = (p - j - 1 + 2 * k) % k;  // the plane holding the rank in order p
+    const uint32_t* plane = buf_after(B, moves_before(depth, j, k)) + record_offset(j, k, n) +
+                            (int64_t)cp * n;
+#pragma unroll
+    for (int it = 0; it < kSegItems; ++it) {
+      const int i = t0 + it * kSegThreads + tid;
+      rp[a][it] = i < t1 ? plane[i] : 0u;
+    }
   }
+  if (tid < kWave) find_subarrays(B, F, n, k, depth, cutover, t0, t1, true, perm, &s_si);
+  if (tid < kMaxK) s_c[tid] = 0;
+  __syncthreads();
   if (tid < kMaxSeg) {
-    s_cnt[tid] = 0;
-    s_si.s[tid] = seginfo[t].s[tid];
-    s_si.e[tid] = seginfo[t].e[tid];
-    s_si.med[tid] = seginfo[t].med[tid];
-    if (tid == 0) s_si.nseg = seginfo[t].nseg;
+    seginfo[t].s[tid] = s_si.s[tid];
+    seginfo[t].e[tid] = s_si.e[tid];
+    seginfo[t].med[tid] = s_si.med[tid];
+    if (tid == 0) seginfo[t].nseg = s_si.nseg;
+  }
+  if (R == 0) return;
+  const int ns = s_si.nseg;
+  int from = t1, to = t1;
+  uint32_t med = 0;
+  if (ns > 0) {
+    from = max(s_si.s[ns - 1], t0);
+    to = min(s_si.e[ns - 1] + 1, t1);
+    med = s_si.med[ns - 1];
+  }
+#pragma unroll
+  for (int a = 0; a < R; ++a) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int it = 0; it < kSegItems; ++it) {
+      const int i = t0 + it * kSegThreads + tid;
+      if (i >= from && i < to) c += rp[a][it] < med ? 1u : (rp[a][it] == med ? 0x10000u : 0u);
+    }
+    c = wave_sum(c);
+    if (lane_id() == 0 && c) atomicAdd(&s_c[a], c);
   }
   __syncthreads();
-  const int nseg = s_si.nseg;
-  uint32_t c[kMaxSeg];
-#pragma unroll
-  for (int q = 0; q < kMaxSeg; ++q) c[q] = 0;
-#pragma unroll
-  for (int it = 0; it < kLvItems; ++it) {
-    const int i = t0 + it * kLvThreads + tid;
-    if (i >= t1) continue;
-#pragma unroll
-    for (int q = 0; q < kMaxSeg; ++q) {
-      if (q < nseg && i >= s_si.s[q] && i <= s_si.e[q]) {
-        const uint32_t med = s_si.med[q];
-        c[q] += rp[it] < med ? 1u : (rp[it] == med ? 0x10000u : 0u);
-      }
-    }
+  if (tid < arrays) {
+    const uint32_t c = s_c[tid];
+    uint64_t v = (uint64_t)(c & 0xFFFF) | ((uint64_t)(c >> 16) << 32);
+    const bool head = ns == 0 || s_si.s[ns - 1] >= t0;
+    const bool cont = ns > 0 && s_si.s[0] < t0;
+    v |= ((uint64_t)head << 48) | ((uint64_t)cont << 49);
+    tval[(int64_t)tid * tiles + t] = v;
   }
-#pragma unroll
-  for (int q = 0; q < kMaxSeg; ++q) {
-    if (q < nseg) {
-      const uint32_t v = wave_sum(c[q]);
-      if (lane_id() == 0 && v) atomicAdd(&s_cnt[q], v);
-    }
-  }
-  __syncthreads();
-  if (tid < kMaxSeg) cnt[((int64_t)a * tiles_per_array + t) * kMaxSeg + tid] = s_cnt[tid];
 }
 
 // Chains the counts along every subarray: carry[a][t] = counts of tile t's
@@ -270,8 +267,7 @@ __device__ __forceinline__ void seg_combine(uint64_t& v, int& h, uint64_t v_prev
 }
 
 __global__ __launch_bounds__(1024) void k_level_scan(const Forest F, int depth,
-                                                    const SegInfo* __restrict__ seginfo,
-                                                    const uint32_t* __restrict__ cnt,
+                                                    const uint64_t* __restrict__ tval,
                                                     uint64_t* __restrict__ carry,
                                                     int tiles_per_array) {
   constexpr int kThreads = 1024, kWaves = kThreads / kWave;
@@ -285,17 +281,10 @@ __global__ __launch_bounds__(1024) void k_level_scan(const Forest F, int depth,
   const int per = (tiles + kThreads - 1) / kThreads;
   const int c0 = min(tiles, tid * per), c1 = min(tiles, c0 + per);
   auto tile_value = [&](int t, uint64_t* v, int* h, bool* cont) {
-    const SegInfo& si = seginfo[t];
-    const int ns = si.nseg;
-    *v = 0;
-    *h = 1;
-    *cont = false;
-    if (ns > 0) {
-      const uint32_t c = cnt[((int64_t)a * tiles_per_array + t) * kMaxSeg + (ns - 1)];
-      *v = (uint64_t)(c & 0xFFFF) | ((uint64_t)(c >> 16) << 32);
-      *h = si.s[ns - 1] >= t * kLevelTile;
-      *cont = si.s[0] < t * kLevelTile;
-    }
+    const uint64_t x = tval[(int64_t)a * tiles_per_array + t];
+    *v = x & ((1ull << 48) - 1);
+    *h = (int)((x >> 48) & 1);
+    *cont = ((x >> 49) & 1) != 0;
   };
   // aggregate of this thread's run
   uint64_t av = 0;
@@ -366,12 +355,78 @@ struct Rec {
   uint32_t v[W];
 };
 
+// ---- single-pass level: decoupled look-back --------------------------------------
+// The count and chain steps can instead run inside the move launch: tiles are
+// taken in launch order from a counter, every tile publishes the counts of its
+// last subarray (and whether that subarray starts inside it) as soon as it has
+// them, and a tile whose first subarray started earlier sums its
+// predecessors' published values backwards until it meets a subarray start or
+// a predecessor that already published its inclusive value.  A tile only ever
+// waits for tiles that took their numbers before it and publish before they
+// wait themselves, so the waits always end.
+// Status word of (tile, array): bits 0-31 lower count, 32-47 median count,
+// bit 48 head (the last subarray starts inside the tile), bits 56-62 the
+// level's epoch (depth + 1), bit 63 inclusive (the value runs from the
+// subarray's start).
+constexpr uint64_t kStValue = (1ull << 48) - 1;
+constexpr int kStHead = 48, kStEpoch = 56, kStIncl = 63;
+constexpr int kLookbackSpin = 1 << 24;  // polls before giving up (never reached when consistent)
+
+struct LookBack {
+  uint64_t* status;
+  int stride;  // moving arrays per tile
+  int a, t;
+  uint32_t epoch;
+};
+
+__device__ __forceinline__ void status_store(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t status_load(uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wave 0: publish this tile's value, then (cont) gather the carry of its
+// first subarray; returns it in every lane.
+__device__ uint64_t level_lookback(const LookBack& lb, uint64_t agg, bool head, bool cont) {
+  const int lane = lane_id();
+  uint64_t* me = lb.status + (int64_t)lb.t * lb.stride + lb.a;
+  const uint64_t tag = ((uint64_t)lb.epoch << kStEpoch) | ((uint64_t)head << kStHead);
+  if (lane == 0) status_store(me, tag | agg | (head ? 1ull << kStIncl : 0ull));
+  uint64_t carry = 0;
+  if (cont) {
+    int pos = lb.t - 1;
+    for (int spin = 0; spin < kLookbackSpin; ++spin) {
+      const int q = pos - lane;  // lane l looks at tile pos - l
+      uint64_t sv = 0;
+      bool ready = true, stop = true;
+      if (q >= 0) {
+        sv = status_load(lb.status + (int64_t)q * lb.stride + lb.a);
+        ready = (uint32_t)((sv >> kStEpoch) & 0x7F) == lb.epoch;
+        stop = ready && (((sv >> kStIncl) & 1) || ((sv >> kStHead) & 1));
+      }
+      const uint64_t nr = __ballot(!ready), sp = __ballot(stop);
+      const int fnr = nr ? __ffsll((unsigned long long)nr) - 1 : kWave;
+      const int fsp = sp ? __ffsll((unsigned long long)sp) - 1 : kWave;
+      // consume the ready lanes below the first unready one, up to the first stop
+      const int take = fsp < fnr ? fsp + 1 : fnr;
+      carry += wave_sum(lane < take ? (sv & kStValue) : 0ull);
+      if (fsp < fnr) break;
+      pos -= take;
+    }
+    if (!head && lane == 0) status_store(me, tag | ((carry + agg) & kStValue) | (1ull << kStIncl));
+  }
+  return carry;
+}
+
 // Move one tile of one array: W planes (k-1 ranks, + row id for array 0).
-template <int W>
+// kFused: the carry comes from the look-back instead of `carry`.
+template <int W, bool kFused>
 __device__ __forceinline__ void level_move_tile(const uint32_t* __restrict__ src,
                                                uint32_t* __restrict__ dst, int64_t n, int cp,
                                                int t0, int t1, const SegInfo& si, uint64_t carry,
-                                               uint32_t* s_chunk, uint32_t* s_pre) {
+                                               uint32_t* s_chunk, uint32_t* s_pre,
+                                               const LookBack& lb, uint64_t* s_carry) {
   const int tid = threadIdx.x;
   const int w = tid / kWave;
   const int lane = tid % kWave;
@@ -417,9 +472,12 @@ __device__ __forceinline__ void level_move_tile(const uint32_t* __restrict__ src
     if (lane == kWave - 1) s_chunk[it * kLvWaves + w] = inc;
   }
   __syncthreads();
+  uint32_t tile_total = 0;  // wave 0: the tile's packed total
   if (w == 0) {
     const uint32_t c = s_chunk[tid];
-    s_chunk[tid] = wave_inclusive_sum(c) - c;
+    const uint32_t inc = wave_inclusive_sum(c);
+    s_chunk[tid] = inc - c;
+    tile_total = __shfl(inc, kWave - 1, kWave);
   }
   __syncthreads();
   // exclusive in-tile prefix of every position, packed as lower | node << 16
@@ -429,6 +487,24 @@ __device__ __forceinline__ void level_move_tile(const uint32_t* __restrict__ src
     if (i < t1) s_pre[i - t0] = s_chunk[it * kLvWaves + w] + within[it];
   }
   __syncthreads();
+  if constexpr (kFused) {
+    if (w == 0) {
+      // value for the next tiles: the counts of the last subarray in this tile
+      uint64_t agg = 0;
+      bool head = true, cont = false;
+      if (nseg > 0) {
+        const int sl = si.s[nseg - 1];
+        head = sl >= t0;
+        cont = si.s[0] < t0;
+        const uint32_t part = tile_total - (head ? s_pre[sl - t0] : 0u);
+        agg = (uint64_t)(part & 0xFFFF) | ((uint64_t)(part >> 16) << 32);
+      }
+      const uint64_t c = level_lookback(lb, agg, head, cont);
+      if (tid == 0) *s_carry = c;
+    }
+    __syncthreads();
+    carry = *s_carry;
+  }
   const int carry_lower = (int)(carry & 0xFFFFFFFFull);
   const int carry_node = (int)((carry >> 32) & 0xFFFF);
   int dest[kLvItems];
@@ -493,28 +569,102 @@ __global__ __launch_bounds__(kLvThreads) void k_level_move(const RecBufs B, cons
   const uint32_t* src = buf_after(B, mj) + record_offset(j, k, n);
   uint32_t* dst = const_cast<uint32_t*>(buf_after(B, mj + 1)) + record_offset(j, k, n);
   const int cp = (p - j - 1 + 2 * k) % k;
+  const LookBack lb{};
   if (j == 0)
-    level_move_tile<R + 1>(src, dst, n, cp, t0, t1, s_si, cy, s_chunk, s_pre);
+    level_move_tile<R + 1, false>(src, dst, n, cp, t0, t1, s_si, cy, s_chunk, s_pre, lb, nullptr);
   else
-    level_move_tile<R>(src, dst, n, cp, t0, t1, s_si, cy, s_chunk, s_pre);
+    level_move_tile<R, false>(src, dst, n, cp, t0, t1, s_si, cy, s_chunk, s_pre, lb, nullptr);
+}
+
+// Count, chain and move in one launch (look-back).  Tile numbers come from
+// tickets[depth], cleared before the first level; tile t of array a is
+// ticket t * (k - 1) + a, so the arrays advance together.
+template <int R>
+__global__ __launch_bounds__(kLvThreads) void k_level_fused(const RecBufs B, const Forest F,
+                                                           int64_t n, int k, int depth,
+                                                           const SegInfo* __restrict__ seginfo,
+                                                           uint64_t* __restrict__ status,
+                                                           int32_t* __restrict__ tickets) {
+  __shared__ uint32_t s_chunk[kLvChunks];
+  __shared__ uint32_t s_pre[kLevelTile];
+  __shared__ SegInfo s_si;
+  __shared__ int s_ticket;
+  __shared__ uint64_t s_carry;
+  const int tid = threadIdx.x;
+  const int nu = F.uoff[F.B];
+  if (depth >= *F.lmax) return;  // the same for every workgroup of the launch
+  if (tid == 0) s_ticket = atomicAdd(tickets + depth, 1);
+  __syncthreads();
+  const int a = s_ticket % (k - 1);
+  const int t = s_ticket / (k - 1);
+  const int p = depth % k;
+  const int j = (p + 1 + a) % k;
+  const int t0 = t * kLevelTile;
+  if (t0 >= nu) return;
+  const int t1 = min(t0 + kLevelTile, nu);
+  if (tid < kMaxSeg) {
+    s_si.s[tid] = seginfo[t].s[tid];
+    s_si.e[tid] = seginfo[t].e[tid];
+    s_si.med[tid] = seginfo[t].med[tid];
+    if (tid == 0) s_si.nseg = seginfo[t].nseg;
+  }
+  __syncthreads();
+  const int mj = moves_before(depth, j, k);
+  const uint32_t* src = buf_after(B, mj) + record_offset(j, k, n);
+  uint32_t* dst = const_cast<uint32_t*>(buf_after(B, mj + 1)) + record_offset(j, k, n);
+  const int cp = (p - j - 1 + 2 * k) % k;
+  const LookBack lb{status, k - 1, a, t, (uint32_t)depth + 1};
+  if (j == 0)
+    level_move_tile<R + 1, true>(src, dst, n, cp, t0, t1, s_si, 0, s_chunk, s_pre, lb, &s_carry);
+  else
+    level_move_tile<R, true>(src, dst, n, cp, t0, t1, s_si, 0, s_chunk, s_pre, lb, &s_carry);
 }
 
 hipError_t launch_level(const uint32_t* rec0, uint32_t* b1, uint32_t* b2, int64_t n, int k,
                         int depth, int64_t cutover, const ForestArgs& fa, int32_t* perm,
-                        void* seginfo, uint32_t* cnt, uint64_t* carry, hipStream_t st) {
+                        void* seginfo, uint32_t* cnt, uint64_t* carry, uint64_t* status,
+                        int32_t* tickets, hipStream_t st) {
   if (n <= 0 || k < 2) return hipSuccess;
   const int tiles = (int)((n + kLevelTile - 1) / kLevelTile);
   const unsigned grid = (unsigned)(tiles * (k - 1));
   RecBufs B{rec0, b1, b2};
   Forest F{fa.B, fa.off, fa.uoff, fa.lmax, fa.wgbase, fa.queue};
   SegInfo* si = static_cast<SegInfo*>(seginfo);
-  const int seg_blocks = (tiles + kSegThreads / kWave - 1) / (kSegThreads / kWave);
-  hipLaunchKernelGGL(k_level_seg, dim3(seg_blocks), dim3(kSegThreads), 0, st, B, F, n, k, depth,
-                     cutover, perm, si, tiles);
-  hipLaunchKernelGGL(k_level_count, dim3(grid), dim3(kLvThreads), 0, st, B, F, n, k, depth, si, cnt,
-                     tiles);
-  hipLaunchKernelGGL(k_level_scan, dim3(k - 1), dim3(1024), 0, st, F, depth, si, cnt, carry,
-                     tiles);
+  uint64_t* tval = status ? nullptr : reinterpret_cast<uint64_t*>(cnt);
+#define KD_SEG(RR)                                                                                  \
+  hipLaunchKernelGGL(k_level_seg<RR>, dim3(tiles), dim3(kSegThreads), 0, st, B, F, n, k, depth, cutover, \
+                     perm, si, tval, tiles)
+  switch (status ? 0 : k - 1) {
+    case 0: KD_SEG(0); break;
+    case 1: KD_SEG(1); break;
+    case 2: KD_SEG(2); break;
+    case 3: KD_SEG(3); break;
+    case 4: KD_SEG(4); break;
+    case 5: KD_SEG(5); break;
+    case 6: KD_SEG(6); break;
+    case 7: KD_SEG(7); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef KD_SEG
+  if (status) {
+    if (depth >= kMaxLevels) return hipErrorInvalidValue;
+#define KD_LF(RR)                                                                                \
+  hipLaunchKernelGGL(k_level_fused<RR>, dim3(grid), dim3(kLvThreads), 0, st, B, F, n, k, depth, si, \
+                     status, tickets)
+    switch (k - 1) {
+      case 1: KD_LF(1); break;
+      case 2: KD_LF(2); break;
+      case 3: KD_LF(3); break;
+      case 4: KD_LF(4); break;
+      case 5: KD_LF(5); break;
+      case 6: KD_LF(6); break;
+      case 7: KD_LF(7); break;
+      default: return hipErrorInvalidValue;
+    }
+#undef KD_LF
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_level_scan, dim3(k - 1), dim3(1024), 0, st, F, depth, tval, carry, tiles);
 #define KD_LV(RR)                                                                               \
   hipLaunchKernelGGL(k_level_move<RR>, dim3(xcd_grid(grid)), dim3(kLvThreads), 0, st, B, F, n, \
                      k, depth,                                                                   \

@@ -132,11 +132,17 @@ hipError_t launch_complete_records(uint32_t* rec, const uint32_t* ids1, int64_t 
 
 // One global partition level (depth) of every array but the split one.
 // rec0 holds the level-0 records (never overwritten); b1/b2 the moved ones.
-// Scratch: seginfo level_tiles(n) * level_seginfo_bytes() bytes, cnt
-// (k-1) * level_tiles(n) * 8 words, carry (k-1) * level_tiles(n) words.
+// Scratch: seginfo level_tiles(n) * level_seginfo_bytes() bytes.  With
+// `status` null the level runs as count, chain and move launches (cnt
+// (k-1) * level_tiles(n) 64-bit words of tile counts, carry (k-1) *
+// level_tiles(n) 64-bit words); otherwise the counts are chained by
+// look-back inside the move launch (status (k-1) * level_tiles(n) 64-bit
+// words and tickets kMaxLevels words, both zeroed before depth 0).
+constexpr int kMaxLevels = 64;
 hipError_t launch_level(const uint32_t* rec0, uint32_t* b1, uint32_t* b2, int64_t n, int k,
                         int depth, int64_t cutover, const ForestArgs& fa, int32_t* perm,
-                        void* seginfo, uint32_t* cnt, uint64_t* carry, hipStream_t st);
+                        void* seginfo, uint32_t* cnt, uint64_t* carry, uint64_t* status,
+                        int32_t* tickets, hipStream_t st);
 size_t level_seginfo_bytes();
 inline int64_t level_tiles(int64_t n) { return (n + kLevelTile - 1) / kLevelTile; }
 

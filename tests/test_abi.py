@@ -81,7 +81,10 @@ def test_build_rejects_bad_arguments(L):
     o.records = 3  # 0, 1 or 2
     assert call_build(L, opts=ctypes.byref(o)) == -1
     o.records = 0
-    o.reserved[3] = 1  # reserved words must be zero
+    o.level = 3  # 0, 1 or 2
+    assert call_build(L, opts=ctypes.byref(o)) == -1
+    o.level = 0
+    o.reserved[2] = 1  # reserved words must be zero
     assert call_build(L, opts=ctypes.byref(o)) == -1
 
 

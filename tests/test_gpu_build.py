@@ -27,17 +27,17 @@ def kd():
     return kd
 
 
-def run_gpu(kd, t: np.ndarray, cutover=None, children=True):
-    print(f"[gpu case] n={t.shape[0]} k={t.shape[1]} dtype={t.dtype} cutover={cutover}", flush=True)
+def run_gpu(kd, t: np.ndarray, cutover=None, children=True, **knobs):
+    print(f"[gpu case] n={t.shape[0]} k={t.shape[1]} dtype={t.dtype} cutover={cutover} {knobs}", flush=True)
     dt = torch.from_numpy(np.ascontiguousarray(t)).cuda()
-    res = kd.build(dt, children=children, cutover=cutover)
+    res = kd.build(dt, children=children, cutover=cutover, **knobs)
     torch.cuda.synchronize()
     return [r.cpu().numpy() if hasattr(r, "cpu") else r for r in res]
 
 
-def assert_same(kd, t, cutover=None, threads=8):
+def assert_same(kd, t, cutover=None, threads=8, **knobs):
     want = oracle.build_tree(t, threads=threads)
-    perm, nu, lo, hi = run_gpu(kd, t, cutover)
+    perm, nu, lo, hi = run_gpu(kd, t, cutover, **knobs)
     assert nu == want["n_unique"]
     assert np.array_equal(perm, want["perm"]), "perm differs"
     assert np.array_equal(lo, want["lo"]) and np.array_equal(hi, want["hi"]), "children differ"
@@ -76,6 +76,16 @@ def test_wide_values(kd, k, n):
 def test_cutover_choices_same_tree(kd, cutover, n):
     t = kdgen.uniform_int(n, 3, -(2 ** 31), 2 ** 31, 0.01, n + cutover)
     assert_same(kd, t, cutover=cutover)
+
+
+@pytest.mark.parametrize("level", [1, 2])
+@pytest.mark.parametrize("k", [2, 3, 4, 8])
+@pytest.mark.parametrize("n", [4097, 70001, 600000])
+def test_level_launch_forms(kd, level, k, n):
+    """The global levels as count, chain and move launches (1) or as one
+    look-back launch (2): the same tree."""
+    t = kdgen.uniform_int(n, k, -(1 << 20), 1 << 20, 0.05, 300 + n + k)
+    assert_same(kd, t, cutover=1024, level=level)
 
 
 @pytest.mark.parametrize("records", [1, 2])
@@ -195,11 +205,11 @@ def test_full_size_c2_bit_exact(kd):
 
 # ---- batched form ---------------------------------------------------------------
 
-def assert_batched_same(kd, t, offsets, cutover=None):
+def assert_batched_same(kd, t, offsets, cutover=None, level=None):
     print(f"[gpu case] batched trees={len(offsets) - 1} rows={offsets[-1]} k={t.shape[1]} "
-          f"dtype={t.dtype} cutover={cutover}", flush=True)
+          f"dtype={t.dtype} cutover={cutover} level={level}", flush=True)
     perm, nu = kd.build_batched(torch.from_numpy(np.ascontiguousarray(t)).cuda(), offsets,
-                                cutover=cutover)
+                                cutover=cutover, level=level)
     torch.cuda.synchronize()
     perm = perm.cpu().numpy()
     nu = nu.cpu().numpy()
@@ -217,6 +227,17 @@ def test_batched_mixed_sizes(kd, k):
     offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
     t = g.integers(-20, 20, size=(int(offsets[-1]), k)).astype(np.int32)
     assert_batched_same(kd, t, offsets)
+
+
+@pytest.mark.parametrize("level", [1, 2])
+def test_batched_level_forms(kd, level):
+    """Forests whose trees reach different depths: global levels in both
+    launch forms."""
+    g = kdgen.rng(90 + level)
+    sizes = [70000, 3, 1024, 1025, 250000, 0, 9000, 4097, 130000, 17]
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    t = g.integers(-5000, 5000, size=(int(offsets[-1]), 3)).astype(np.int32)
+    assert_batched_same(kd, t, offsets, cutover=1024, level=level)
 
 
 @pytest.mark.parametrize("cutover", [1024, 2048, 4096])
