@@ -421,16 +421,18 @@ __device__ uint64_t level_lookback(const LookBack& lb, uint64_t agg, bool head, 
 
 // Move one tile of one array: W planes (k-1 ranks, + row id for array 0).
 // kFused: the carry comes from the look-back instead of `carry`.
+// The tile's subarrays (gsi, global) are copied to si (LDS) while the planes
+// are in flight.
 template <int W, bool kFused>
 __device__ __forceinline__ void level_move_tile(const uint32_t* __restrict__ src,
                                                uint32_t* __restrict__ dst, int64_t n, int cp,
-                                               int t0, int t1, const SegInfo& si, uint64_t carry,
-                                               uint32_t* s_chunk, uint32_t* s_pre,
-                                               const LookBack& lb, uint64_t* s_carry) {
+                                               int t0, int t1, const SegInfo* __restrict__ gsi,
+                                               SegInfo& si, uint64_t carry, uint32_t* s_chunk,
+                                               uint32_t* s_pre, const LookBack& lb,
+                                               uint64_t* s_carry) {
   const int tid = threadIdx.x;
   const int w = tid / kWave;
   const int lane = tid % kWave;
-  const int nseg = si.nseg;
 
   uint32_t v[W][kLvItems];
 #pragma unroll
@@ -442,6 +444,14 @@ __device__ __forceinline__ void level_move_tile(const uint32_t* __restrict__ src
       v[c][it] = i < t1 ? sp[i] : 0u;
     }
   }
+  if (tid < kMaxSeg) {
+    si.s[tid] = gsi->s[tid];
+    si.e[tid] = gsi->e[tid];
+    si.med[tid] = gsi->med[tid];
+    if (tid == 0) si.nseg = gsi->nseg;
+  }
+  __syncthreads();
+  const int nseg = si.nseg;
   uint32_t flag[kLvItems];
   int8_t sg[kLvItems];
   uint32_t within[kLvItems];
@@ -545,7 +555,6 @@ __global__ __launch_bounds__(kLvThreads) void k_level_move(const RecBufs B, cons
   __shared__ uint32_t s_chunk[kLvChunks];
   __shared__ uint32_t s_pre[kLevelTile];
   __shared__ SegInfo s_si;
-  const int tid = threadIdx.x;
   const int nu = F.uoff[F.B];
   if (depth >= *F.lmax) return;
   const int p = depth % k;
@@ -557,13 +566,6 @@ __global__ __launch_bounds__(kLvThreads) void k_level_move(const RecBufs B, cons
   const int t0 = t * kLevelTile;
   if (t0 >= nu) return;
   const int t1 = min(t0 + kLevelTile, nu);
-  if (tid < kMaxSeg) {
-    s_si.s[tid] = seginfo[t].s[tid];
-    s_si.e[tid] = seginfo[t].e[tid];
-    s_si.med[tid] = seginfo[t].med[tid];
-    if (tid == 0) s_si.nseg = seginfo[t].nseg;
-  }
-  __syncthreads();
   const uint64_t cy = carry[(int64_t)a * tiles_per_array + t];
   const int mj = moves_before(depth, j, k);
   const uint32_t* src = buf_after(B, mj) + record_offset(j, k, n);
@@ -571,9 +573,11 @@ __global__ __launch_bounds__(kLvThreads) void k_level_move(const RecBufs B, cons
   const int cp = (p - j - 1 + 2 * k) % k;
   const LookBack lb{};
   if (j == 0)
-    level_move_tile<R + 1, false>(src, dst, n, cp, t0, t1, s_si, cy, s_chunk, s_pre, lb, nullptr);
+    level_move_tile<R + 1, false>(src, dst, n, cp, t0, t1, seginfo + t, s_si, cy, s_chunk, s_pre, lb,
+                                  nullptr);
   else
-    level_move_tile<R, false>(src, dst, n, cp, t0, t1, s_si, cy, s_chunk, s_pre, lb, nullptr);
+    level_move_tile<R, false>(src, dst, n, cp, t0, t1, seginfo + t, s_si, cy, s_chunk, s_pre, lb,
+                              nullptr);
 }
 
 // Count, chain and move in one launch (look-back).  Tile numbers come from
@@ -602,22 +606,17 @@ __global__ __launch_bounds__(kLvThreads) void k_level_fused(const RecBufs B, con
   const int t0 = t * kLevelTile;
   if (t0 >= nu) return;
   const int t1 = min(t0 + kLevelTile, nu);
-  if (tid < kMaxSeg) {
-    s_si.s[tid] = seginfo[t].s[tid];
-    s_si.e[tid] = seginfo[t].e[tid];
-    s_si.med[tid] = seginfo[t].med[tid];
-    if (tid == 0) s_si.nseg = seginfo[t].nseg;
-  }
-  __syncthreads();
   const int mj = moves_before(depth, j, k);
   const uint32_t* src = buf_after(B, mj) + record_offset(j, k, n);
   uint32_t* dst = const_cast<uint32_t*>(buf_after(B, mj + 1)) + record_offset(j, k, n);
   const int cp = (p - j - 1 + 2 * k) % k;
   const LookBack lb{status, k - 1, a, t, (uint32_t)depth + 1};
   if (j == 0)
-    level_move_tile<R + 1, true>(src, dst, n, cp, t0, t1, s_si, 0, s_chunk, s_pre, lb, &s_carry);
+    level_move_tile<R + 1, true>(src, dst, n, cp, t0, t1, seginfo + t, s_si, 0, s_chunk, s_pre, lb,
+                                 &s_carry);
   else
-    level_move_tile<R, true>(src, dst, n, cp, t0, t1, s_si, 0, s_chunk, s_pre, lb, &s_carry);
+    level_move_tile<R, true>(src, dst, n, cp, t0, t1, seginfo + t, s_si, 0, s_chunk, s_pre, lb,
+                             &s_carry);
 }
 
 hipError_t launch_level(const uint32_t* rec0, uint32_t* b1, uint32_t* b2, int64_t n, int k,
