@@ -930,34 +930,44 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
       if (i == ss + ((ee - ss) >> 1)) s_out[i] = id;
     }
     __syncthreads();
-    // phase 2: flags of the k-1 moving arrays, segmented within-chunk sums.
-    // Packed value: lower count in bits 0-15, node count in bits 16-28.
-    uint32_t fl[R][kItems];
+    // phase 2: side of every element of the k-1 moving arrays, counted as
+    // lower (bits 0-15) | upper << 16 by a plain scan over each wave chunk;
+    // an element whose subarray starts in the same chunk takes its count
+    // relative to that start right away, the others add the chunk's carry in
+    // phase 4.  Each chunk's last subarray piece goes to s_chunk (with
+    // kHeadBit when the piece starts inside the chunk).
+    // per element and array: count of the same side before it (bits 0-28),
+    // side << 29 (1 lower, 2 upper, 0 node), head in this chunk << 31
+    uint32_t pref[R][kItems];
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
       const int i = it * kLfThreads + tid;
       const bool live = seg[it] != kHole;
       const int ss = (int)(seg[it] & 0xFFFF), ee = (int)(seg[it] >> 16);
       const int m = ss + ((ee - ss) >> 1);
-      const bool head0 = live && i == ss;
+      const int cbase = it * kLfThreads + w * kWave;
+      const bool hin = live && ss >= cbase;
+      const int hlane = hin ? ss - cbase : 0;
 #pragma unroll
       for (int a2 = 0; a2 < R; ++a2) {
         const int j = (p + 1 + a2) % k;
-        uint32_t f = 0;
+        uint32_t id = 0, side = 0;
         if (live) {
-          const int pp = s_pos[s_lid[((((curmask >> j) & 1) * k) + j) * C + i]];
-          f = pp < m ? 1u : (pp == m ? 0x10000u : 0u);
+          id = s_lid[((((curmask >> j) & 1) * k) + j) * C + i];
+          const int pp = s_pos[id];
+          side = pp < m ? 1u : (pp > m ? 2u : 0u);
         }
-        uint32_t v = f;
-        bool h = head0;
-        wave_seg_scan(v, h);
-        fl[a2][it] = (v - f) | (h ? kHeadBit : 0u) | (f == 1u ? 0x40000000u : 0u) |
-                     (f == 0x10000u ? 0x20000000u : 0u);
-        if (lane == kWave - 1) s_chunk[a2][it * kLfWaves + w] = v | (h ? kHeadBit : 0u);
+        const uint32_t f = side == 1u ? 1u : (side == 2u ? 0x10000u : 0u);
+        const uint32_t inc = wave_scan_dpp(f);
+        const uint32_t exc = inc - f;
+        const uint32_t hexc = __shfl(exc, hlane, kWave);
+        pref[a2][it] = (hin ? exc - hexc : exc) | (side << 29) | (hin ? 1u << 31 : 0u);
+        if (lane == kWave - 1)
+          s_chunk[a2][it * kLfWaves + w] = !live ? kHeadBit : (hin ? (inc - hexc) | kHeadBit : inc);
       }
     }
     __syncthreads();
-    // phase 3: segmented exclusive scan over each array's chunk totals
+    // phase 3: segmented exclusive scan over each array's chunk pieces
     for (int a2 = w; a2 < R; a2 += kLfWaves) {
       const uint32_t c = lane < kChunks ? s_chunk[a2][lane] : kHeadBit;
       uint32_t v = c & ~kHeadBit;
@@ -970,22 +980,21 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
     // phase 4: move every element of the k-1 arrays to its new position
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
-      const int i = it * kLfThreads + tid;
       if (seg[it] == kHole) continue;
       const int ss = (int)(seg[it] & 0xFFFF), ee = (int)(seg[it] >> 16);
       const int m = ss + ((ee - ss) >> 1);
 #pragma unroll
       for (int a2 = 0; a2 < R; ++a2) {
-        const uint32_t x = fl[a2][it];
-        if (x & 0x20000000u) continue;  // the node itself is not copied
+        const uint32_t x = pref[a2][it];
+        const uint32_t side = (x >> 29) & 3u;
+        if (side == 0u) continue;  // the node itself is not copied
         const int j = (p + 1 + a2) % k;
         uint32_t pre = x & 0x1FFFFFFFu;
-        if (!(x & kHeadBit)) pre += s_chunk[a2][it * kLfWaves + w];
-        const int low = (int)(pre & 0xFFFF), nd = (int)(pre >> 16);
-        const int dest = (x & 0x40000000u) ? ss + low : m + 1 + (i - ss - low - nd);
+        if (!(x >> 31)) pre += s_chunk[a2][it * kLfWaves + w];
+        const int dest = side == 1u ? ss + (int)(pre & 0xFFFF) : m + 1 + (int)(pre >> 16);
         const int cb = (curmask >> j) & 1;
         if (dest >= ss && dest <= ee)
-          s_lid[((cb ^ 1) * k + j) * C + dest] = s_lid[(cb * k + j) * C + i];
+          s_lid[((cb ^ 1) * k + j) * C + dest] = s_lid[(cb * k + j) * C + it * kLfThreads + tid];
       }
     }
     curmask ^= ((1u << k) - 1) & ~(1u << p);  // every array but the split one moved

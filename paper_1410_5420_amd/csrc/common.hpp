@@ -32,6 +32,20 @@ __device__ __forceinline__ T wave_inclusive_sum(T v) {
   return v;
 }
 
+// Inclusive prefix sum across the 64 lanes of a wave through DPP lane moves:
+// shifts by 1, 2, 4 and 8 within each row of 16 lanes, then the last lane of
+// row r added to row r+1 and the last lane of row 1 to rows 2 and 3.  All 64
+// lanes must be active.
+__device__ __forceinline__ uint32_t wave_scan_dpp(uint32_t v) {
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x111, 0xF, 0xF, false);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x112, 0xF, 0xF, false);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x114, 0xF, 0xF, false);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x118, 0xF, 0xF, false);  // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x143, 0xC, 0xF, false);  // row_bcast:31
+  return v;
+}
+
 // Exclusive block-wide prefix sum of one value per thread (NT threads, a
 // multiple of 64).  `s_tmp` holds NT/64 + 1 words of LDS.  Returns the
 // exclusive prefix; *total receives the block sum.  Contains barriers.
