@@ -47,22 +47,33 @@ def log(msg):
 # ---- algorithmic byte model ----------------------------------------------------------
 
 def onesweep_bytes(n: int, nu: int, k: int):
-    """(total algorithmic bytes, launches) of all radix scatter passes of one
-    plain build.  Array 0 is sorted over all n rows, word by word; every pass
-    moves its key word and k payload words (the row id and the other key
-    words), the first one reading the tuple rows themselves.  Each of the k-1
+    """(total algorithmic bytes, launches) of all radix passes of one plain
+    build (each pass counts as one launch of the class).  Array 0 is sorted
+    over all n rows by its first word alone (k > 1): every pass moves that
+    key word and k payload words (the row id, made by the first pass, and the
+    other key words), the first one reading the tuple rows themselves.  The
+    complete word-by-word sort of array 0 is also enqueued, gated on the tie
+    step's flag: its k * 4 passes move nothing unless a run of equal first
+    words is too long, and count as launches of no bytes.  Each of the k-1
     chain sorts runs over the n_unique rows and moves its key word and k
     payload words (row id, ranks known so far, key words of the later sorts);
     its last pass drops the key.  Every word read or written counts 4 bytes."""
     P = 4  # 8-bit digit passes per 32-bit word
     words = 0
-    for w in range(k - 1, -1, -1):
+    launches = 0
+    if k > 1:
         for ps in range(P):
-            words += n * ((k if (w == k - 1 and ps == 0) else k + 1) + (k + 1))
+            words += n * ((k if ps == 0 else k + 1) + (k + 1))
+        launches += P + k * P
+    else:
+        for ps in range(P):
+            words += n * ((1 if ps == 0 else 2) + 2)
+        launches += P
     for _ in range(k - 1, 0, -1):
         for ps in range(P):
             words += nu * ((k if ps == 0 else k + 1) + (k if ps == P - 1 else k + 1))
-    return 4 * words, 2 * k * P - P
+        launches += P
+    return 4 * words, launches
 
 
 def level_bytes(nu: int, k: int, cutover: int):
