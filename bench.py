@@ -78,17 +78,15 @@ def onesweep_bytes(n: int, nu: int, k: int):
 
 def level_bytes(nu: int, k: int, cutover: int):
     """(total algorithmic bytes, launches) of the global partition levels:
-    every array but the split one is read once and written once; records
-    hold k-1 ranks, plus the row id in array 0's."""
+    every array but the split one is read once and written once; a moving
+    record holds k-1 ranks (row ids stay in the level-0 records)."""
     R = k - 1
     levels = 0
     while (nu >> levels) > cutover:
         levels += 1
     total = 0
     for L in range(levels):
-        p = L % k
-        words = sum(R + (1 if j == 0 else 0) for j in range(k) if j != p)
-        total += nu * words * 4 * 2
+        total += nu * R * R * 4 * 2
     return total, levels
 
 
@@ -98,7 +96,7 @@ def byte_model(kernel: str, n: int, nu: int, k: int, cutover: int):
     if kernel == "level":
         total, launches = level_bytes(nu, k, cutover)
         return total / max(launches, 1), (f"{launches} levels: per level (k-1) arrays x (k-1) ranks "
-                                          f"(+ row id in array 0) x 4 B, read + write, x n_unique")
+                                          f"x 4 B, read + write, x n_unique")
     if kernel == "onesweep":
         total, launches = onesweep_bytes(n, nu, k)
         return total / launches, f"radix key + payload words of the build's {launches} passes, averaged"

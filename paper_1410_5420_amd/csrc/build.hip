@@ -162,7 +162,7 @@ __device__ void find_subarrays(const RecBufs& B, const Forest& F, int64_t n, int
       const uint32_t rp = B.rec0[record_offset(p1, k, n) + (int64_t)(k - 2) * n + r1];
       out->med[idx] = rp;
       if (write_perm && m >= t0 && m < t1) {
-        // row ids travel in array 0's records (plane k-1), indexed by the
+        // row ids sit in array 0's level-0 records (plane k-1), indexed by the
         // rank in order 0: that is rp itself when p == 0, otherwise plane
         // (k - p - 1) of the median's record
         const uint32_t r0 = p == 0 ? rp : split[(int64_t)((k - p - 1) % k) * n + m];
@@ -419,7 +419,8 @@ __device__ uint64_t level_lookback(const LookBack& lb, uint64_t agg, bool head, 
   return carry;
 }
 
-// Move one tile of one array: W planes (k-1 ranks, + row id for array 0).
+// Move one tile of one array: its W = k-1 rank planes (array 0's row ids stay
+// in the level-0 records, indexed by the order-0 rank).
 // kFused: the carry comes from the look-back instead of `carry`.
 // The tile's subarrays (gsi, global) are copied to si (LDS) while the planes
 // are in flight.
@@ -572,12 +573,8 @@ __global__ __launch_bounds__(kLvThreads) void k_level_move(const RecBufs B, cons
   uint32_t* dst = const_cast<uint32_t*>(buf_after(B, mj + 1)) + record_offset(j, k, n);
   const int cp = (p - j - 1 + 2 * k) % k;
   const LookBack lb{};
-  if (j == 0)
-    level_move_tile<R + 1, false>(src, dst, n, cp, t0, t1, seginfo + t, s_si, cy, s_chunk, s_pre, lb,
-                                  nullptr);
-  else
-    level_move_tile<R, false>(src, dst, n, cp, t0, t1, seginfo + t, s_si, cy, s_chunk, s_pre, lb,
-                              nullptr);
+  level_move_tile<R, false>(src, dst, n, cp, t0, t1, seginfo + t, s_si, cy, s_chunk, s_pre, lb,
+                            nullptr);
 }
 
 // Count, chain and move in one launch (look-back).  Tile numbers come from
@@ -611,12 +608,8 @@ __global__ __launch_bounds__(kLvThreads) void k_level_fused(const RecBufs B, con
   uint32_t* dst = const_cast<uint32_t*>(buf_after(B, mj + 1)) + record_offset(j, k, n);
   const int cp = (p - j - 1 + 2 * k) % k;
   const LookBack lb{status, k - 1, a, t, (uint32_t)depth + 1};
-  if (j == 0)
-    level_move_tile<R + 1, true>(src, dst, n, cp, t0, t1, seginfo + t, s_si, 0, s_chunk, s_pre, lb,
-                                 &s_carry);
-  else
-    level_move_tile<R, true>(src, dst, n, cp, t0, t1, seginfo + t, s_si, 0, s_chunk, s_pre, lb,
-                             &s_carry);
+  level_move_tile<R, true>(src, dst, n, cp, t0, t1, seginfo + t, s_si, 0, s_chunk, s_pre, lb,
+                           &s_carry);
 }
 
 hipError_t launch_level(const uint32_t* rec0, uint32_t* b1, uint32_t* b2, int64_t n, int k,
@@ -789,8 +782,7 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
   static_assert(kChunks <= kWave, "one wave scans the chunk totals of an array");
   extern __shared__ __align__(16) unsigned char s_raw[];
   uint32_t* s_r0 = reinterpret_cast<uint32_t*>(s_raw);       // [C] sorted order-0 ranks
-  uint32_t* s_id = s_r0 + C;                                 // [C] row id of each local id
-  uint16_t* s_pos = reinterpret_cast<uint16_t*>(s_id + C);   // [C] position in the split array
+  uint16_t* s_pos = reinterpret_cast<uint16_t*>(s_r0 + C);   // [C] position in the split array
   uint16_t* s_out = s_pos + C;                               // [C] node id of each position
   uint16_t* s_lid = s_out + C;                               // [2][k][C] local-id arrays
   __shared__ uint32_t s_chunk[R][kWave];
@@ -832,9 +824,9 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
   // Array 1 stores the order-0 rank of each of its elements (plane k-2);
   // sorting those ranks gives array 0's order, hence every array-1 element's
   // local id, and the sorted list lets the other arrays find theirs by binary
-  // search.  Array 0's records carry the row ids.
+  // search.  The row ids are read at the end from array 0's level-0 records,
+  // at the order-0 ranks.
   {
-    const uint32_t* a0 = buf_after(B, moves_before(lc, 0, k)) + record_offset(0, k, n);
     const uint32_t* a1 = buf_after(B, moves_before(lc, 1, k)) + record_offset(1, k, n);
     uint32_t* sk = reinterpret_cast<uint32_t*>(s_lid);        // sort scratch (aliases s_lid)
     uint16_t* sv = reinterpret_cast<uint16_t*>(sk + C);
@@ -843,7 +835,6 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
     for (int it = 0; it < kItems; ++it) {
       const int i = it * kLfThreads + tid;
       if (i < N) {
-        s_id[i] = a0[(int64_t)R * n + s0 + i];
         s_r0[i] = a1[(int64_t)(k - 2) * n + s0 + i];
         sv2[i] = (uint16_t)i;
       }
@@ -1003,12 +994,14 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
   {
     const int64_t ob = F.off[tree];
     int32_t* out = perm + ob + (s0 - tbase);
+    const uint32_t* rows = B.rec0 + record_offset(0, k, n) + (int64_t)(k - 1) * n;
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
       const int i = it * kLfThreads + tid;
       if (i < N) {
         const int id = s_out[i];
-        if (id < N) out[i] = (int32_t)((int64_t)s_id[id] - ob);
+        // the row id of order-0 rank r sits in the level-0 records of array 0
+        if (id < N) out[i] = (int32_t)((int64_t)rows[s_r0[id]] - ob);
       }
     }
   }
