@@ -63,6 +63,7 @@ constexpr int kOsThreads = 512;
 constexpr int kOsItems = kSortTile / kOsThreads;  // 8
 constexpr int kOsWaves = kOsThreads / kWave;
 constexpr int kScanGroup = 64;                      // tiles per first-level scan block
+constexpr int kGatedGrid = 256;                     // workgroups of a gated pass (a multiple of 8)
 
 // Positions fit in 31 bits (n <= 2^30 - 1); only tuple rows are addressed in
 // 64-bit, since row * k can exceed that.
@@ -102,6 +103,8 @@ __device__ __forceinline__ bool gated_off(const RadixExtra& ex) {
   return ex.gate != nullptr && *ex.gate == 0;
 }
 
+// Workgroup b counts tiles b, b + grid, ... (one tile each in an ordinary
+// pass), loading the next tile's keys while it counts the current one.
 template <bool kFromTuples, bool kModel>
 __global__ __launch_bounds__(kOsThreads) void k_radix_count(const uint32_t* __restrict__ keys_in,
                                                            const TupleSrc ts, int key_word,
@@ -111,24 +114,41 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_count(const uint32_t* __re
   __shared__ uint32_t s_h[kRadix];
   if (gated_off(ex)) return;
   const int tid = threadIdx.x;
-  if (tid < kRadix) s_h[tid] = 0;
   ModelView mv{};
   if (kModel) mv = load_model(ex);
-  __syncthreads();
   const int n = (int)(n_dev ? *n_dev : n_host);
-  const int base = blockIdx.x * kSortTile;
+  // every tile of the launch bound gets its row (zeros beyond the device count)
+  const int tiles = (int)((n_host + kSortTile - 1) / kSortTile);
+  uint32_t key[kOsItems];
+  auto load = [&](int tile) {
+    const int base = tile * kSortTile;
 #pragma unroll
-  for (int j = 0; j < kOsItems; ++j) {
-    const int i = base + j * kOsThreads + tid;
-    if (i < n) {
-      uint32_t key =
-          kFromTuples ? canon_word(ts.t[(int64_t)i * ts.k + key_word], ts.is_float) : keys_in[i];
-      if (kModel) key = model_bucket(mv, key);
-      atomicAdd(&s_h[(key >> shift) & 0xFF], 1u);
+    for (int j = 0; j < kOsItems; ++j) {
+      const int i = base + j * kOsThreads + tid;
+      key[j] = 0u;
+      if (i < n)
+        key[j] = kFromTuples ? canon_word(ts.t[(int64_t)i * ts.k + key_word], ts.is_float) : keys_in[i];
     }
+  };
+  int tile = blockIdx.x;
+  if (tile < tiles) load(tile);
+  for (; tile < tiles; tile += gridDim.x) {
+    if (tid < kRadix) s_h[tid] = 0;
+    __syncthreads();
+    const int base = tile * kSortTile;
+#pragma unroll
+    for (int j = 0; j < kOsItems; ++j) {
+      const int i = base + j * kOsThreads + tid;
+      if (i < n) {
+        const uint32_t kk = kModel ? model_bucket(mv, key[j]) : key[j];
+        atomicAdd(&s_h[(kk >> shift) & 0xFF], 1u);
+      }
+    }
+    if (tile + (int)gridDim.x < tiles) load(tile + gridDim.x);
+    __syncthreads();
+    if (tid < kRadix) cnt[(int64_t)tile * kRadix + tid] = s_h[tid];
+    __syncthreads();
   }
-  __syncthreads();
-  if (tid < kRadix) cnt[(int64_t)blockIdx.x * kRadix + tid] = s_h[tid];
 }
 
 // First level: exclusive prefix over the tiles of one group, per digit.
@@ -207,12 +227,16 @@ __global__ __launch_bounds__(kRadix * kSgSub) void k_radix_scan_groups(
   }
 }
 
+// XCD-aware: the padded tiles are split into 8 contiguous ranges, one per
+// XCD, and workgroup b (on XCD b mod 8) walks its XCD's range with a stride of
+// grid / 8 (one tile each in an ordinary pass), loading the next tile's keys
+// while it writes the current tile's planes.
 template <bool kFromTuples, bool kWriteKeys, bool kModel>
 __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const TupleSrc ts, int key_word,
     uint32_t* __restrict__ keys_out, const Payload pay, int64_t n_host, const int32_t* n_dev,
     int shift, const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ group_start,
-    const RadixExtra ex) {
+    int tiles_pad, const RadixExtra ex) {
   __shared__ uint32_t s_keys[kSortTile];
   __shared__ uint32_t s_stage[kSortTile];
   __shared__ uint32_t s_wcnt[kOsWaves][kRadix];
@@ -225,27 +249,34 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
   const int w = tid / kWave;
   const int lane = tid % kWave;
   const int n = (int)(n_dev ? *n_dev : n_host);
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int base = tile * kSortTile;
-  if (base >= n) return;
-  for (int q = tid; q < kOsWaves * kRadix; q += kOsThreads) (&s_wcnt[0][0])[q] = 0;
   ModelView mv{};
   if (kModel) mv = load_model(ex);
+  const int range = tiles_pad / kXcds;
+  const int xcd = blockIdx.x % kXcds, step = gridDim.x / kXcds;
+  uint32_t key[kOsItems], rank[kOsItems];
+  auto load_keys = [&](int tile) {
+    const int wb = tile * kSortTile + w * (kWave * kOsItems) + lane;
+#pragma unroll
+    for (int j = 0; j < kOsItems; ++j) {
+      const int i = wb + j * kWave;
+      key[j] = 0;
+      if (i < n)
+        key[j] = kFromTuples ? canon_word(ts.t[(int64_t)i * ts.k + key_word], ts.is_float)
+                             : keys_in[i];
+    }
+  };
+  int lt = blockIdx.x / kXcds;
+  if (lt < range && (xcd * range + lt) * kSortTile < n) load_keys(xcd * range + lt);
+  for (; lt < range; lt += step) {
+  const int tile = xcd * range + lt;
+  const int base = tile * kSortTile;
+  if (base >= n) break;  // the XCD's later tiles lie further on
+  for (int q = tid; q < kOsWaves * kRadix; q += kOsThreads) (&s_wcnt[0][0])[q] = 0;
   // global start of this tile's run of digit tid
   if (tid < kRadix)
     s_gbase[tid] = cnt[(int64_t)tile * kRadix + tid] +
                    group_start[(int64_t)(tile / kScanGroup) * kRadix + tid];
-
-  uint32_t key[kOsItems], rank[kOsItems];
   const int wbase = base + w * (kWave * kOsItems) + lane;
-#pragma unroll
-  for (int j = 0; j < kOsItems; ++j) {
-    const int i = wbase + j * kWave;
-    key[j] = 0;
-    if (i < n)
-      key[j] = kFromTuples ? canon_word(ts.t[(int64_t)i * ts.k + key_word], ts.is_float)
-                           : keys_in[i];
-  }
   __syncthreads();
   // learned digits: rank by bucket (the raw key travels as a payload plane)
   if (kModel) {
@@ -318,6 +349,8 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
       if (kWriteKeys && dest[j] >= 0) keys_out[g] = kk;
     }
   }
+  // the next tile's keys load while this tile's planes are written
+  if (lt + step < range && (xcd * range + lt + step) * kSortTile < n) load_keys(xcd * range + lt + step);
 
   // payload planes: the next plane's values are loaded before the current
   // one is written out
@@ -351,6 +384,8 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
     }
     __syncthreads();
   }
+  __syncthreads();  // LDS is reused by the next tile
+  }
 }
 
 hipError_t launch_radix_pass(const uint32_t* keys_in, const TupleSrc& ts, int key_word,
@@ -373,8 +408,14 @@ hipError_t launch_radix_pass(const uint32_t* keys_in, const TupleSrc& ts, int ke
     pl.word = key_word;
     keys_out = nullptr;
   }
+  // one tile per workgroup; a gated pass (which usually does nothing) is
+  // launched with a small persistent grid so that skipping it costs little
+  const bool gated = ex.gate != nullptr;
+  const int cgrid = gated && tiles > kGatedGrid ? kGatedGrid : tiles;
+  const int tiles_pad = xcd_grid(tiles);
+  const int sgrid = gated && tiles_pad > kGatedGrid ? kGatedGrid : tiles_pad;
 #define KD_RC(FT, MD)                                                                   \
-  hipLaunchKernelGGL((k_radix_count<FT, MD>), dim3(tiles), dim3(kOsThreads), 0, st, keys_in, \
+  hipLaunchKernelGGL((k_radix_count<FT, MD>), dim3(cgrid), dim3(kOsThreads), 0, st, keys_in, \
                      ts, key_word, n, n_dev, shift, cnt, ex)
   if (ft) {
     if (md) KD_RC(true, true); else KD_RC(true, false);
@@ -387,8 +428,8 @@ hipError_t launch_radix_pass(const uint32_t* keys_in, const TupleSrc& ts, int ke
   hipLaunchKernelGGL(k_radix_scan_groups, dim3(1), dim3(kRadix * kSgSub), 0, st, group_tot, groups,
                      ex);
 #define KD_RS(FT, WK, MD)                                                                   \
-  hipLaunchKernelGGL((k_radix_scatter<FT, WK, MD>), dim3(xcd_grid(tiles)), dim3(kOsThreads), 0, \
-                     st, keys_in, ts, key_word, keys_out, pay, n, n_dev, shift, cnt, group_tot, ex)
+  hipLaunchKernelGGL((k_radix_scatter<FT, WK, MD>), dim3(sgrid), dim3(kOsThreads), 0, st, keys_in, \
+                     ts, key_word, keys_out, pay, n, n_dev, shift, cnt, group_tot, tiles_pad, ex)
   const bool wk = keys_out != nullptr;
   if (md) {
     if (ft) KD_RS(true, false, true); else KD_RS(false, false, true);
