@@ -423,17 +423,15 @@ constexpr int kBsWaves = kBsThreads / kWave;
 constexpr int kBsCap = 4096;      // most keys a workgroup sorts at once (two workgroups per CU)
 constexpr int kBsItems = kBsCap / kBsThreads;
 constexpr int kBsMaxBins = kBsCap / 2;  // CDF interpolation bins per unit (plus up to half as many tail bins)
-constexpr int kBsDenseBin = 16;   // larger bins are ranked by the whole workgroup
-constexpr int kBsMaxDense = kBsCap; // largest bin a workgroup ranks
-constexpr int kBsMaxBig = 512;    // most such bins per unit
+constexpr int kBsWorkPerKey = 64;  // most element comparisons per key of a unit (sum of squared bin sizes)
 constexpr int kBsPrefetch = 3;    // output planes loaded into registers while the unit sorts
-constexpr int kBsLdsTies = 2;     // tie-break words held in LDS (later ones are read from memory)
+constexpr int kBsLdsTies = 1;     // tie-break words held in LDS (later ones are read from memory)
 
-// primary word, two tie-break words (all three reused as output staging),
-// and the sorted order
-size_t bucket_sort_lds_bytes() { return (size_t)kBsCap * (4 * (1 + kBsLdsTies) + 2); }
+// primary word and one tie-break word (both reused as output staging), the
+// bin order, the sorted order and every slot's bin
+size_t bucket_sort_lds_bytes() { return (size_t)kBsCap * (4 * (1 + kBsLdsTies) + 3 * 2); }
 int bucket_sort_capacity() { return kBsCap; }
-int bucket_sort_target() { return kBsCap / 2; }
+int bucket_sort_target() { return kBsCap * 3 / 4; }
 
 template <typename T, typename Op>
 __device__ __forceinline__ T bs_reduce(T v, T* s_red, Op op) {
@@ -511,40 +509,21 @@ __device__ __forceinline__ int interp_bin(const ModelLds& m, const UnitBins& u, 
   return u.nlo + bin;
 }
 
-// Total order of a unit's elements x, y (local positions): primary word,
-// tie words from most to least significant, then position.
-struct UnitKeys {
-  const uint32_t* k;
-  const uint32_t* t1;  // null when there is no such word
-  const uint32_t* t2;
-};
-__device__ __forceinline__ bool unit_less(const LocalSort& ls, const UnitKeys& uk, int s, int x,
-                                          int y) {
-  const uint32_t kx = uk.k[x], ky = uk.k[y];
-  if (kx != ky) return kx < ky;
-  if (uk.t1 && uk.t1[x] != uk.t1[y]) return uk.t1[x] < uk.t1[y];
-  if (uk.t2 && uk.t2[x] != uk.t2[y]) return uk.t2[x] < uk.t2[y];
-  for (int t = ls.nkeys - 4; t >= 0; --t) {
-    const uint32_t* w = pick(ls.in, pick(ls.keyq, t)) + s;
-    const uint32_t a = w[x], b = w[y];
-    if (a != b) return a < b;
-  }
-  return x < y;
-}
-
 // Sort positions [s, s + N) (N <= kBsCap), which hold the buckets [bk0,
 // bk0 + nbk), stably by the sort words and write every plane permuted.
-// Returns false (after raising flag bit 8) when a bin is too dense for the
-// insertion step.
+// Elements are placed in bin order first ("slots"), with the primary and
+// first tie word copied into slot order so that ranking reads them in
+// sequence; s_perm[slot] is the element (its input position, the final tie).
+// Returns false (after raising flag bit 8) when the bins are too uneven for
+// the ranking step.
 __device__ bool sort_unit(const LocalSort& ls, const ModelLds& m, int s, int N, int bk0, int nbk,
-                          uint32_t* s_k, uint32_t* s_t1, uint32_t* s_t2, uint16_t* s_perm,
-                          uint32_t* s_cnt, uint32_t* s_tmp, uint32_t* s_red, int32_t* s_nbig,
-                          int32_t* s_big, int32_t* s_bigoff, int32_t* flag) {
+                          uint32_t* s_k, uint32_t* s_t1, uint16_t* s_perm, uint16_t* s_ord,
+                          uint16_t* s_bin, uint32_t* s_cnt, uint32_t* s_tmp, uint32_t* s_red,
+                          int32_t* flag) {
   const int tid = threadIdx.x;
   const int nk = ls.nkeys;
   const uint32_t* k0 = pick(ls.in, pick(ls.keyq, nk - 1)) + s;
   const uint32_t* w1 = nk >= 2 ? pick(ls.in, pick(ls.keyq, nk - 2)) + s : nullptr;
-  const uint32_t* w2 = nk >= 3 ? pick(ls.in, pick(ls.keyq, nk - 3)) + s : nullptr;
   // the first planes that are not sort words held in LDS are loaded now, so
   // their loads overlap the sort
   int pq[kBsPrefetch] = {-1, -1, -1};
@@ -552,7 +531,7 @@ __device__ bool sort_unit(const LocalSort& ls, const ModelLds& m, int s, int N, 
     int r = 0;
     for (int q = 0; q < ls.nq && r < kBsPrefetch; ++q) {
       const uint32_t* in = pick(ls.in, q) + s;
-      if (in == k0 || (w1 && in == w1) || (w2 && in == w2)) continue;
+      if (in == k0 || (w1 && in == w1)) continue;
       pq[r++] = q;
     }
   }
@@ -576,22 +555,19 @@ __device__ bool sort_unit(const LocalSort& ls, const ModelLds& m, int s, int N, 
   u.nhi = highend ? max(1, u.nmid / 4) : 0;
   u.vmin = u.hi = 0.f;
   u.lo_scale = u.hi_scale = 0.f;
-  // every thread owns positions tid + j * kBsThreads: their primary words
-  // (and, later, bins) stay in registers
-  uint32_t kv[kBsItems];
+  // every thread owns elements tid + j * kBsThreads: their primary and first
+  // tie words, bins and slots stay in registers
+  uint32_t kv[kBsItems], tv[kBsItems];
   uint32_t mn = 0xFFFFFFFFu, mx = 0u;
 #pragma unroll
   for (int j = 0; j < kBsItems; ++j) {
     const int i = tid + j * kBsThreads;
     kv[j] = i < N ? k0[i] : 0u;
+    tv[j] = (w1 && i < N) ? w1[i] : 0u;
   }
 #pragma unroll
   for (int j = 0; j < kBsItems; ++j) {
-    const int i = tid + j * kBsThreads;
-    if (i < N) {
-      s_k[i] = kv[j];
-      if (w1) s_t1[i] = w1[i];
-      if (w2) s_t2[i] = w2[i];
+    if (tid + j * kBsThreads < N) {
       mn = min(mn, kv[j]);
       mx = max(mx, kv[j]);
     }
@@ -616,171 +592,142 @@ __device__ bool sort_unit(const LocalSort& ls, const ModelLds& m, int s, int N, 
   for (int j = 0; j < kBsItems; ++j)
     if (tid + j * kBsThreads < N) atomicAdd(&s_cnt[bin[j]], 1u);
   __syncthreads();
-  // exclusive bin starts (each thread scans a run of consecutive bins)
+  // exclusive bin starts (each thread scans a run of consecutive bins), and
+  // the ranking work: the sum of the squared bin sizes
   const int per = (nbins + kBsThreads - 1) / kBsThreads;
   const int b0 = min(nbins, tid * per), b1 = min(nbins, b0 + per);
-  uint32_t run = 0, big = 0;
+  uint32_t run = 0, work = 0;
   for (int b = b0; b < b1; ++b) {
-    run += s_cnt[b];
-    big = max(big, s_cnt[b]);
+    const uint32_t c = s_cnt[b];
+    run += c;
+    work += c > 1 ? c * c : 0u;
   }
-  // one scan carries both the bin counts (low 16 bits: at most kBsCap) and,
-  // in the high bits, the number of bins beyond kBsMaxDense keys
-  static_assert(kBsCap < (1 << 16), "counts fit 16 bits");
-  uint32_t all;
-  uint32_t off = block_exclusive_sum<kBsThreads>(run | (big > (uint32_t)kBsMaxDense ? 0x10000u : 0u),
-                                                 s_tmp, &all) & 0xFFFFu;
-  if (all >> 16) {
+  uint32_t all, all_work;
+  uint32_t off = block_exclusive_sum<kBsThreads>(run, s_tmp, &all);
+  block_exclusive_sum<kBsThreads>(work, s_tmp, &all_work);
+  if (all_work > (uint32_t)kBsWorkPerKey * (uint32_t)N) {
     if (tid == 0) atomicOr(flag, 8);
     return false;
   }
-  if (tid == 0) *s_nbig = 0;
   for (int b = b0; b < b1; ++b) {
     const uint32_t c = s_cnt[b];
     s_cnt[b] = off;
     off += c;
   }
   __syncthreads();
+  int slot[kBsItems];
 #pragma unroll
   for (int j = 0; j < kBsItems; ++j) {
     const int i = tid + j * kBsThreads;
+    slot[j] = -1;
     if (i >= N) continue;
     const uint32_t pos = atomicAdd(&s_cnt[bin[j]], 1u);
-    if (pos < (uint32_t)N)
+    if (pos < (uint32_t)N) {
+      slot[j] = (int)pos;
       s_perm[pos] = (uint16_t)i;
-    else
+      s_bin[pos] = (uint16_t)bin[j];
+      s_k[pos] = kv[j];
+      s_t1[pos] = tv[j];
+    } else {
       atomicOr(flag, 4);  // inconsistent counts (cannot happen)
+    }
   }
   __syncthreads();
-  // s_cnt[b] is now the end of bin b.  Bins of up to kBsDenseBin keys are
-  // put in order by one thread each (insertion); larger ones (long runs of
-  // equal primary words) are listed and ranked by the whole workgroup.
-  const UnitKeys uk{s_k, w1 ? s_t1 : nullptr, w2 ? s_t2 : nullptr};
-  for (int b = tid; b < nbins; b += kBsThreads) {
+  // s_cnt[b] is now the end of bin b.  Every slot ranks its element among its
+  // bin's (slots of a bin are neighbours, so a wave's slots mostly share the
+  // same few bins and loop about as long as each other): the element goes to
+  // bin start + the number of the bin's elements before it in the total order
+  // (primary word, tie words, input position).
+#pragma unroll
+  for (int j = 0; j < kBsItems; ++j) {
+    const int p = tid + j * kBsThreads;
+    if (p >= N) continue;
+    const int b = s_bin[p];
     const int st = b ? (int)s_cnt[b - 1] : 0;
     const int en = (int)s_cnt[b];
-    if (en - st > kBsDenseBin) {
-      const int idx = atomicAdd(s_nbig, 1);
-      if (idx < kBsMaxBig) s_big[idx] = b;
-      continue;
-    }
-    for (int x = st + 1; x < en; ++x) {
-      const int cur = s_perm[x];
-      int y = x;
-      while (y > st) {
-        const int prv = s_perm[y - 1];
-        if (!unit_less(ls, uk, s, cur, prv)) break;
-        s_perm[y] = (uint16_t)prv;
-        --y;
-      }
-      s_perm[y] = (uint16_t)cur;
-    }
-  }
-  __syncthreads();
-  const int nbig = *s_nbig;
-  if (nbig > kBsMaxBig) {
-    if (tid == 0) atomicOr(flag, 8);
-    return false;
-  }
-  if (nbig > 0) {
-    // all large bins in one pass: the keys of the listed bins, concatenated,
-    // are shared out over the threads; each key's rank in its bin is the
-    // number of smaller keys there
-    static_assert(kBsMaxBig <= kBsThreads, "one thread per listed bin");
-    uint32_t sz = 0;
-    if (tid < nbig) {
-      const int b = s_big[tid];
-      sz = s_cnt[b] - (b ? s_cnt[b - 1] : 0u);
-    }
-    uint32_t all_big;
-    const uint32_t boff = block_exclusive_sum<kBsThreads>(sz, s_tmp, &all_big);
-    if (tid < nbig) s_bigoff[tid] = (int32_t)boff;
-    if (tid == 0) s_bigoff[nbig] = (int32_t)all_big;
-    __syncthreads();
-    const int total = s_bigoff[nbig];
-    int elem[kBsItems], dst[kBsItems];
-#pragma unroll
-    for (int r = 0; r < kBsItems; ++r) {
-      const int x = tid + r * kBsThreads;
-      elem[r] = -1;
-      dst[r] = 0;
-      if (x < total) {
-        int q = 0, hi = nbig - 1;  // last q with s_bigoff[q] <= x
-        while (q < hi) {
-          const int mid = (q + hi + 1) >> 1;
-          if (s_bigoff[mid] <= x)
-            q = mid;
-          else
-            hi = mid - 1;
+    int r = 0;
+    if (en - st > 1) {
+      const uint32_t kx = s_k[p], tx = s_t1[p];
+      const int x = s_perm[p];
+      for (int q = st; q < en; ++q) {
+        const uint32_t ky = s_k[q], ty = s_t1[q];
+        bool lt = ky < kx || (ky == kx && ty < tx);
+        if (ky == kx && ty == tx && q != p) {
+          const int y = s_perm[q];
+          int c = 0;
+          for (int t = nk - 3; t >= 0 && c == 0; --t) {
+            const uint32_t* w = pick(ls.in, pick(ls.keyq, t)) + s;
+            const uint32_t a = w[y], bb = w[x];
+            c = a < bb ? -1 : (a > bb ? 1 : 0);
+          }
+          lt = c < 0 || (c == 0 && y < x);
         }
-        const int b = s_big[q];
-        const int st = b ? (int)s_cnt[b - 1] : 0;
-        const int en = (int)s_cnt[b];
-        const int a = s_perm[st + (x - s_bigoff[q])];
-        int c = 0;
-        for (int j2 = st; j2 < en; ++j2) c += unit_less(ls, uk, s, s_perm[j2], a) ? 1 : 0;
-        elem[r] = a;
-        dst[r] = st + c;
+        r += lt ? 1 : 0;
       }
     }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kBsItems; ++r)
-      if (elem[r] >= 0) s_perm[dst[r]] = (uint16_t)elem[r];
+    s_ord[st + r] = (uint16_t)p;
   }
   // every plane permuted: the sort words straight from LDS, then the
-  // prefetched planes, then the rest, three at a time through the LDS arrays
+  // prefetched planes, then the rest, two at a time through the LDS arrays
+  // (staged in slot order)
   __syncthreads();
   for (int q = 0; q < ls.nq; ++q) {
     const uint32_t* in = pick(ls.in, q) + s;
-    const uint32_t* src = in == k0 ? s_k : (w1 && in == w1 ? s_t1 : (w2 && in == w2 ? s_t2 : nullptr));
+    const uint32_t* src = in == k0 ? s_k : (w1 && in == w1 ? s_t1 : nullptr);
     if (!src) continue;
     uint32_t* out = pick(ls.out, q) + s;
-    for (int i = tid; i < N; i += kBsThreads) out[i] = src[s_perm[i]];
+    for (int i = tid; i < N; i += kBsThreads) out[i] = src[s_ord[i]];
   }
   __syncthreads();
-  uint32_t* stage[3] = {s_k, s_t1, s_t2};
+  uint32_t* stage[2] = {s_k, s_t1};
 #pragma unroll
-  for (int r = 0; r < kBsPrefetch; ++r) {
-    if (pq[r] < 0) continue;
+  for (int r0 = 0; r0 < kBsPrefetch; r0 += 2) {
 #pragma unroll
-    for (int j = 0; j < kBsItems; ++j) {
-      const int i = tid + j * kBsThreads;
-      if (i < N) stage[r][i] = pre[r][j];
+    for (int h = 0; h < 2; ++h) {
+      const int r = r0 + h;
+      if (r >= kBsPrefetch || pq[r] < 0) continue;
+#pragma unroll
+      for (int j = 0; j < kBsItems; ++j)
+        if (slot[j] >= 0) stage[h][slot[j]] = pre[r][j];
     }
-  }
-  __syncthreads();
+    __syncthreads();
 #pragma unroll
-  for (int r = 0; r < kBsPrefetch; ++r) {
-    if (pq[r] < 0) continue;
-    uint32_t* out = pick(ls.out, pq[r]) + s;
-    for (int i = tid; i < N; i += kBsThreads) out[i] = stage[r][s_perm[i]];
+    for (int h = 0; h < 2; ++h) {
+      const int r = r0 + h;
+      if (r >= kBsPrefetch || pq[r] < 0) continue;
+      uint32_t* out = pick(ls.out, pq[r]) + s;
+      for (int i = tid; i < N; i += kBsThreads) out[i] = stage[h][s_ord[i]];
+    }
+    __syncthreads();
   }
   int r = 0;
-  int rest[3];
+  int rest[2];
   for (int q = 0; q <= ls.nq; ++q) {
     bool take = false;
     if (q < ls.nq) {
       const uint32_t* in = pick(ls.in, q) + s;
-      const bool in_lds = in == k0 || (w1 && in == w1) || (w2 && in == w2);
+      const bool in_lds = in == k0 || (w1 && in == w1);
       take = !in_lds && q != pq[0] && q != pq[1] && q != pq[2];
     }
     if (take) rest[r++] = q;
-    if (r == 3 || (q == ls.nq && r > 0)) {
-      __syncthreads();
+    if (r == 2 || (q == ls.nq && r > 0)) {
       for (int x = 0; x < r; ++x) {
         const uint32_t* in = pick(ls.in, rest[x]) + s;
-        for (int i = tid; i < N; i += kBsThreads) stage[x][i] = in[i];
+#pragma unroll
+        for (int j = 0; j < kBsItems; ++j) {
+          const int i = tid + j * kBsThreads;
+          if (slot[j] >= 0) stage[x][slot[j]] = in[i];
+        }
       }
       __syncthreads();
       for (int x = 0; x < r; ++x) {
         uint32_t* out = pick(ls.out, rest[x]) + s;
-        for (int i = tid; i < N; i += kBsThreads) out[i] = stage[x][s_perm[i]];
+        for (int i = tid; i < N; i += kBsThreads) out[i] = stage[x][s_ord[i]];
       }
+      __syncthreads();
       r = 0;
     }
   }
-  __syncthreads();
   return true;
 }
 
@@ -814,16 +761,14 @@ __global__ __launch_bounds__(kBsThreads) void k_bucket_sort(const int32_t* __res
   extern __shared__ __align__(16) unsigned char s_raw[];
   uint32_t* s_k = reinterpret_cast<uint32_t*>(s_raw);
   uint32_t* s_t1 = s_k + kBsCap;
-  uint32_t* s_t2 = s_t1 + kBsCap;
-  uint16_t* s_perm = reinterpret_cast<uint16_t*>(s_t2 + kBsCap);
+  uint16_t* s_perm = reinterpret_cast<uint16_t*>(s_t1 + kBsCap);
+  uint16_t* s_ord = s_perm + kBsCap;
+  uint16_t* s_bin = s_ord + kBsCap;
   __shared__ uint32_t s_cnt[kBsMaxBins + kBsMaxBins / 2];
-  static_assert(kBsPrefetch == 3, "three LDS staging arrays");
+  static_assert(kBsMaxBins + kBsMaxBins / 2 <= 65536, "bins fit 16 bits");
   __shared__ uint32_t s_tmp[kBsWaves + 1];
   __shared__ uint32_t s_red[kBsWaves];
   __shared__ int32_t s_flag;
-  __shared__ int32_t s_nbig;
-  __shared__ int32_t s_big[kBsMaxBig];
-  __shared__ int32_t s_bigoff[kBsMaxBig + 1];
 
   // Other workgroups of this launch may raise the flag while this one reads
   // it, so one thread reads it and the block follows that one value.
@@ -862,8 +807,8 @@ __global__ __launch_bounds__(kBsThreads) void k_bucket_sort(const int32_t* __res
       e = e2;
       ++nb2;
     }
-    if (e > s && !sort_unit(ls, m, s, e - s, b, nb2 - b, s_k, s_t1, s_t2, s_perm, s_cnt, s_tmp,
-                            s_red, &s_nbig, s_big, s_bigoff, flag))
+    if (e > s && !sort_unit(ls, m, s, e - s, b, nb2 - b, s_k, s_t1, s_perm, s_ord, s_bin, s_cnt,
+                            s_tmp, s_red, flag))
       return;
     b = nb2;
   }

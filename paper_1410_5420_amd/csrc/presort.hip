@@ -81,11 +81,14 @@ struct ModelView {
   int is_float, nb_bits;
 };
 
-// The level table (16 KiB) is read through the caches: every workgroup of a
-// pass reads the same table, and an LDS copy would cost occupancy.
-__device__ __forceinline__ ModelView load_model(const RadixExtra& ex) {
+// The level table (16 KiB) is copied to LDS (s_c, kCdfSegments + 1 floats):
+// the keys of a tile look up segments all over it, which LDS serves far
+// faster than the caches.  The copy is complete after the caller's next
+// barrier.
+__device__ __forceinline__ ModelView load_model(const RadixExtra& ex, float* s_c) {
   ModelView m;
-  m.c = ex.model->c;
+  for (int i = threadIdx.x; i <= kCdfSegments; i += blockDim.x) s_c[i] = ex.model->c[i];
+  m.c = s_c;
   m.lo = ex.model->lo;
   m.scale = ex.model->scale;
   m.kmin = ex.model->kmin;
@@ -112,10 +115,11 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_count(const uint32_t* __re
                                                            int shift, uint32_t* __restrict__ cnt,
                                                            const RadixExtra ex) {
   __shared__ uint32_t s_h[kRadix];
+  __shared__ float s_c[kModel ? kCdfSegments + 1 : 1];
   if (gated_off(ex)) return;
   const int tid = threadIdx.x;
   ModelView mv{};
-  if (kModel) mv = load_model(ex);
+  if constexpr (kModel) mv = load_model(ex, s_c);
   const int n = (int)(n_dev ? *n_dev : n_host);
   // every tile of the launch bound gets its row (zeros beyond the device count)
   const int tiles = (int)((n_host + kSortTile - 1) / kSortTile);
@@ -231,14 +235,17 @@ __global__ __launch_bounds__(kRadix * kSgSub) void k_radix_scan_groups(
 // XCD, and workgroup b (on XCD b mod 8) walks its XCD's range with a stride of
 // grid / 8 (one tile each in an ordinary pass), loading the next tile's keys
 // while it writes the current tile's planes.
-template <bool kFromTuples, bool kWriteKeys, bool kModel>
+template <bool kFromTuples, bool kWriteKeys, bool kModel, bool kLoop>
 __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const TupleSrc ts, int key_word,
     uint32_t* __restrict__ keys_out, const Payload pay, int64_t n_host, const int32_t* n_dev,
     int shift, const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ group_start,
     int tiles_pad, const RadixExtra ex) {
-  __shared__ uint32_t s_keys[kSortTile];
-  __shared__ uint32_t s_stage[kSortTile];
+  // keys and staging; before the keys are placed, the model table lives here
+  __shared__ uint32_t s_buf[2 * kSortTile];
+  static_assert(2 * kSortTile >= kCdfSegments + 1, "model table fits the tile buffers");
+  uint32_t* s_keys = s_buf;
+  uint32_t* s_stage = s_buf + kSortTile;
   __shared__ uint32_t s_wcnt[kOsWaves][kRadix];
   __shared__ uint32_t s_tile_excl[kRadix];
   __shared__ uint32_t s_gbase[kRadix];
@@ -250,7 +257,6 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
   const int lane = tid % kWave;
   const int n = (int)(n_dev ? *n_dev : n_host);
   ModelView mv{};
-  if (kModel) mv = load_model(ex);
   const int range = tiles_pad / kXcds;
   const int xcd = blockIdx.x % kXcds, step = gridDim.x / kXcds;
   uint32_t key[kOsItems], rank[kOsItems];
@@ -272,6 +278,7 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
   const int base = tile * kSortTile;
   if (base >= n) break;  // the XCD's later tiles lie further on
   for (int q = tid; q < kOsWaves * kRadix; q += kOsThreads) (&s_wcnt[0][0])[q] = 0;
+  if constexpr (kModel) mv = load_model(ex, reinterpret_cast<float*>(s_buf));
   // global start of this tile's run of digit tid
   if (tid < kRadix)
     s_gbase[tid] = cnt[(int64_t)tile * kRadix + tid] +
@@ -350,7 +357,8 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
     }
   }
   // the next tile's keys load while this tile's planes are written
-  if (lt + step < range && (xcd * range + lt + step) * kSortTile < n) load_keys(xcd * range + lt + step);
+  if constexpr (kLoop)
+    if (lt + step < range && (xcd * range + lt + step) * kSortTile < n) load_keys(xcd * range + lt + step);
 
   // payload planes: the next plane's values are loaded before the current
   // one is written out
@@ -384,6 +392,7 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
     }
     __syncthreads();
   }
+  if constexpr (!kLoop) break;  // one tile per workgroup
   __syncthreads();  // LDS is reused by the next tile
   }
 }
@@ -427,9 +436,17 @@ hipError_t launch_radix_pass(const uint32_t* keys_in, const TupleSrc& ts, int ke
                      ex);
   hipLaunchKernelGGL(k_radix_scan_groups, dim3(1), dim3(kRadix * kSgSub), 0, st, group_tot, groups,
                      ex);
-#define KD_RS(FT, WK, MD)                                                                   \
-  hipLaunchKernelGGL((k_radix_scatter<FT, WK, MD>), dim3(sgrid), dim3(kOsThreads), 0, st, keys_in, \
-                     ts, key_word, keys_out, pay, n, n_dev, shift, cnt, group_tot, tiles_pad, ex)
+#define KD_RS(FT, WK, MD)                                                                       \
+  do {                                                                                          \
+    if (gated)                                                                                  \
+      hipLaunchKernelGGL((k_radix_scatter<FT, WK, MD, true>), dim3(sgrid), dim3(kOsThreads), 0, st, \
+                         keys_in, ts, key_word, keys_out, pay, n, n_dev, shift, cnt, group_tot,      \
+                         tiles_pad, ex);                                                        \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_radix_scatter<FT, WK, MD, false>), dim3(sgrid), dim3(kOsThreads), 0,    \
+                         st, keys_in, ts, key_word, keys_out, pay, n, n_dev, shift, cnt, group_tot,  \
+                         tiles_pad, ex);                                                        \
+  } while (0)
   const bool wk = keys_out != nullptr;
   if (md) {
     if (ft) KD_RS(true, false, true); else KD_RS(false, false, true);
