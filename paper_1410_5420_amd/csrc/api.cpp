@@ -491,7 +491,7 @@ int presort_impl(const Job& J, hipStream_t st) {
   const bool direct = J.records == 1 || (J.records == 0 && n <= kDirectRecordsRows);
   if (k > 1 && direct) {
     // small: one direct scatter
-    KD_LAUNCH(KD_K_RECORDS, launch_complete_records(rec0, S + un, n, k, total, st));
+    KD_LAUNCH(KD_K_RECORDS, launch_complete_records(rec0, n, k, total, st));
   } else if (k > 1) {
     // The record planes the chain could not fill (array 0's, and the ranks
     // in orders 1 .. j-1 of array j >= 2) are scattered from array 1: the
@@ -513,7 +513,6 @@ int presort_impl(const Job& J, hipStream_t st) {
       std::vector<std::pair<Quant, uint32_t*>> vals;  // source, destination plane
       if (tgt == 0) {
         for (int c = 0; c <= k - 2; ++c) vals.push_back({rv_plane((1 + c) % k), at_rec + (size_t)c * un});
-        vals.push_back({Quant{kPlaneArray, S + un, 0, nullptr}, at_rec + (size_t)(k - 1) * un});
       } else {
         for (int c = k - tgt; c <= k - 2; ++c)
           vals.push_back({rv_plane((tgt + 1 + c) % k), at_rec + (size_t)c * un});
@@ -582,13 +581,13 @@ int partition_impl(const Job& J, hipStream_t st) {
         KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(ltick), 0u, kMaxLevels, st));
       }
       for (int d = 0; d < levels; ++d)
-        KD_LAUNCH(KD_K_LEVEL, launch_level(r0, r1, r2, n, k, d, cutover, fa, J.perm,
+        KD_LAUNCH(KD_K_LEVEL, launch_level(r0, S, r1, r2, n, k, d, cutover, fa, J.perm,
                                            at<void>(ws, L.seginfo), at<uint32_t>(ws, L.lcnt),
                                            at<uint64_t>(ws, L.lcarry), lstat, ltick, st));
       // the finish takes its items from a counter; partition may run again
       // after one presort, so the counter is cleared here
       KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(fa.queue), 0u, 1, st));
-      KD_LAUNCH(KD_K_LEAF, launch_leaf(r0, r1, r2, n, k, cutover, fa, J.perm, items, J.leaf_blocks,
+      KD_LAUNCH(KD_K_LEAF, launch_leaf(r0, S, r1, r2, n, k, cutover, fa, J.perm, items, J.leaf_blocks,
                                        st));
     }
     if (J.lo && J.hi) KD_TRY(launch_children(fa.uoff, n, J.lo, J.hi, st));

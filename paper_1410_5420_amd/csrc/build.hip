@@ -27,9 +27,11 @@ __device__ __host__ __forceinline__ int moves_before(int depth, int j, int k) {
 }
 
 // Record buffers: level-0 records stay untouched in rec0 (they double as the
-// rank-translation tables); moved arrays alternate between b1 and b2.
+// rank-translation tables); moved arrays alternate between b1 and b2.  rows:
+// the row id of every order-0 rank (the deduplicated order-0 id array).
 struct RecBufs {
   const uint32_t* rec0;
+  const uint32_t* rows;
   uint32_t* b1;
   uint32_t* b2;
 };
@@ -162,11 +164,10 @@ __device__ void find_subarrays(const RecBufs& B, const Forest& F, int64_t n, int
       const uint32_t rp = B.rec0[record_offset(p1, k, n) + (int64_t)(k - 2) * n + r1];
       out->med[idx] = rp;
       if (write_perm && m >= t0 && m < t1) {
-        // row ids sit in array 0's level-0 records (plane k-1), indexed by the
-        // rank in order 0: that is rp itself when p == 0, otherwise plane
-        // (k - p - 1) of the median's record
+        // the row id is found at the median's rank in order 0: that is rp
+        // itself when p == 0, otherwise plane (k - p - 1) of its record
         const uint32_t r0 = p == 0 ? rp : split[(int64_t)((k - p - 1) % k) * n + m];
-        const int64_t row = B.rec0[record_offset(0, k, n) + (int64_t)(k - 1) * n + r0];
+        const int64_t row = B.rows[r0];
         const int64_t ob = F.off[tr];
         perm[ob + (m - F.uoff[tr])] = (int32_t)(row - ob);
       }
@@ -419,8 +420,7 @@ __device__ uint64_t level_lookback(const LookBack& lb, uint64_t agg, bool head, 
   return carry;
 }
 
-// Move one tile of one array: its W = k-1 rank planes (array 0's row ids stay
-// in the level-0 records, indexed by the order-0 rank).
+// Move one tile of one array: its W = k-1 rank planes.
 // kFused: the carry comes from the look-back instead of `carry`.
 // The tile's subarrays (gsi, global) are copied to si (LDS) while the planes
 // are in flight.
@@ -612,14 +612,15 @@ __global__ __launch_bounds__(kLvThreads) void k_level_fused(const RecBufs B, con
                            &s_carry);
 }
 
-hipError_t launch_level(const uint32_t* rec0, uint32_t* b1, uint32_t* b2, int64_t n, int k,
+hipError_t launch_level(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1, uint32_t* b2,
+                        int64_t n, int k,
                         int depth, int64_t cutover, const ForestArgs& fa, int32_t* perm,
                         void* seginfo, uint32_t* cnt, uint64_t* carry, uint64_t* status,
                         int32_t* tickets, hipStream_t st) {
   if (n <= 0 || k < 2) return hipSuccess;
   const int tiles = (int)((n + kLevelTile - 1) / kLevelTile);
   const unsigned grid = (unsigned)(tiles * (k - 1));
-  RecBufs B{rec0, b1, b2};
+  RecBufs B{rec0, rows, b1, b2};
   Forest F{fa.B, fa.off, fa.uoff, fa.lmax, fa.wgbase, fa.queue};
   SegInfo* si = static_cast<SegInfo*>(seginfo);
   uint64_t* tval = status ? nullptr : reinterpret_cast<uint64_t*>(cnt);
@@ -824,8 +825,7 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
   // Array 1 stores the order-0 rank of each of its elements (plane k-2);
   // sorting those ranks gives array 0's order, hence every array-1 element's
   // local id, and the sorted list lets the other arrays find theirs by binary
-  // search.  The row ids are read at the end from array 0's level-0 records,
-  // at the order-0 ranks.
+  // search.  The row ids are read at the end at the order-0 ranks.
   {
     const uint32_t* a1 = buf_after(B, moves_before(lc, 1, k)) + record_offset(1, k, n);
     uint32_t* sk = reinterpret_cast<uint32_t*>(s_lid);        // sort scratch (aliases s_lid)
@@ -994,13 +994,13 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
   {
     const int64_t ob = F.off[tree];
     int32_t* out = perm + ob + (s0 - tbase);
-    const uint32_t* rows = B.rec0 + record_offset(0, k, n) + (int64_t)(k - 1) * n;
+    const uint32_t* rows = B.rows;
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
       const int i = it * kLfThreads + tid;
       if (i < N) {
         const int id = s_out[i];
-        // the row id of order-0 rank r sits in the level-0 records of array 0
+        // the row id of order-0 rank r is rows[r]
         if (id < N) out[i] = (int32_t)((int64_t)rows[s_r0[id]] - ob);
       }
     }
@@ -1009,12 +1009,13 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
   }
 }
 
-hipError_t launch_leaf(const uint32_t* rec0, uint32_t* b1, uint32_t* b2, int64_t n, int k,
+hipError_t launch_leaf(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1, uint32_t* b2,
+                       int64_t n, int k,
                        int64_t cutover, const ForestArgs& fa, int32_t* perm, int64_t items_bound,
                        int blocks, hipStream_t st) {
   if (n <= 0 || k < 2) return hipSuccess;
   const size_t lds = leaf_lds_bytes(cutover, k);
-  RecBufs B{rec0, b1, b2};
+  RecBufs B{rec0, rows, b1, b2};
   Forest F{fa.B, fa.off, fa.uoff, fa.lmax, fa.wgbase, fa.queue};
   const void* fn = nullptr;
 #define KD_LF_R(IT)                                                  \

@@ -215,14 +215,15 @@ __device__ __forceinline__ uint32_t cdf_bucket(float F, int nb_bits) {
 
 // ---- rank-record layout ------------------------------------------------------------
 // Array j (0 <= j < k) stores one record per position: k-1 ranks (plane c =
-// rank in order (j + 1 + c) mod k), plus the row id for array 0.  Arrays are
-// laid out one after another, array 0 first.
-__device__ __host__ __forceinline__ int record_width(int j, int k) { return k - 1 + (j == 0); }
+// rank in order (j + 1 + c) mod k).  Arrays are laid out one after another,
+// array 0 first.  (Row ids are read from the order-0 sorted id array, at the
+// order-0 rank.)
+__device__ __host__ __forceinline__ int record_width(int, int k) { return k - 1; }
 __device__ __host__ __forceinline__ int64_t record_offset(int j, int k, int64_t n) {
-  return j == 0 ? 0 : (int64_t)k * n + (int64_t)(j - 1) * (k - 1) * n;
+  return (int64_t)j * (k - 1) * n;
 }
 __device__ __host__ __forceinline__ int64_t record_words(int k, int64_t n) {
-  return (int64_t)k * n + (int64_t)(k - 1) * (k - 1) * n;
+  return (int64_t)k * (k - 1) * n;
 }
 
 }  // namespace kd

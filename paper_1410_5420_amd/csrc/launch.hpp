@@ -126,9 +126,9 @@ int place_passes(int64_t n);
 int place_shift(int pass);
 
 // Scatters the record planes the chain of sorts could not fill (see
-// presort.hip).  ids1: row ids in the order of array 1.
-hipError_t launch_complete_records(uint32_t* rec, const uint32_t* ids1, int64_t n, int k,
-                                   const int32_t* nu, hipStream_t st);
+// presort.hip).
+hipError_t launch_complete_records(uint32_t* rec, int64_t n, int k, const int32_t* nu,
+                                   hipStream_t st);
 
 // One global partition level (depth) of every array but the split one.
 // rec0 holds the level-0 records (never overwritten); b1/b2 the moved ones.
@@ -139,7 +139,8 @@ hipError_t launch_complete_records(uint32_t* rec, const uint32_t* ids1, int64_t 
 // look-back inside the move launch (status (k-1) * level_tiles(n) 64-bit
 // words and tickets kMaxLevels words, both zeroed before depth 0).
 constexpr int kMaxLevels = 64;
-hipError_t launch_level(const uint32_t* rec0, uint32_t* b1, uint32_t* b2, int64_t n, int k,
+hipError_t launch_level(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1, uint32_t* b2,
+                        int64_t n, int k,
                         int depth, int64_t cutover, const ForestArgs& fa, int32_t* perm,
                         void* seginfo, uint32_t* cnt, uint64_t* carry, uint64_t* status,
                         int32_t* tickets, hipStream_t st);
@@ -154,7 +155,8 @@ inline size_t leaf_lds_bytes(int64_t cutover, int k) {
 // On-chip finish of every subarray at the cutover depth (row ids come from
 // array 0's records): a persistent grid of `blocks` workgroups (at most one
 // per item).
-hipError_t launch_leaf(const uint32_t* rec0, uint32_t* b1, uint32_t* b2, int64_t n, int k,
+hipError_t launch_leaf(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1, uint32_t* b2,
+                       int64_t n, int k,
                        int64_t cutover, const ForestArgs& fa, int32_t* perm, int64_t items_bound,
                        int blocks, hipStream_t st);
 

@@ -1029,17 +1029,16 @@ hipError_t launch_forest_finish(int32_t* uoff, int num_trees, int64_t cutover, i
 // comparing two rows' super keys q is the same as comparing those ranks.
 //
 // Array j's record holds the k-1 ranks of the other orders, plane c being the
-// rank in order (j + 1 + c) mod k; array 0's records carry the row id as one
-// more plane.  Planes are stored as separate columns (plane c of array j at
+// rank in order (j + 1 + c) mod k (row ids are read from the order-0 sorted id
+// array at the order-0 rank).  Planes are stored as separate columns (plane c of array j at
 // record_offset(j) + c * n).  The chain of sorts fills most planes: the sort producing array
 // d carries the ranks already known (its input position is the rank in order
 // d+1).  Array 1 comes out complete; this kernel reads it and scatters the
 // planes still missing: all of array 0's and, for d >= 2, the ranks in orders
 // 1 .. d-1 of array d.
 
-__global__ __launch_bounds__(256) void k_complete_records(uint32_t* __restrict__ rec,
-                                                         const uint32_t* __restrict__ ids1,
-                                                         int64_t n, int k, const int32_t* total) {
+__global__ __launch_bounds__(256) void k_complete_records(uint32_t* __restrict__ rec, int64_t n,
+                                                         int k, const int32_t* total) {
   const int64_t nu = *total;
   const int R = k - 1;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nu;
@@ -1050,7 +1049,6 @@ __global__ __launch_bounds__(256) void k_complete_records(uint32_t* __restrict__
     for (int c = 0; c < R; ++c) rv[(2 + c) % k] = a1[c * n + i];
     uint32_t* a0 = rec + record_offset(0, k, n);
     for (int c = 0; c < R; ++c) a0[c * n + rv[0]] = rv[(1 + c) % k];
-    a0[R * n + rv[0]] = ids1[i];
     for (int j = 2; j < k; ++j) {
       uint32_t* aj = rec + record_offset(j, k, n);
       for (int c = k - j; c <= k - 2; ++c) aj[c * n + rv[j]] = rv[(j + 1 + c) % k];
@@ -1109,13 +1107,12 @@ hipError_t launch_place(const uint32_t* key, const PlaceArgs& pa, int64_t n, con
   return hipGetLastError();
 }
 
-hipError_t launch_complete_records(uint32_t* rec, const uint32_t* ids1, int64_t n, int k,
-                                   const int32_t* nu, hipStream_t st) {
+hipError_t launch_complete_records(uint32_t* rec, int64_t n, int k, const int32_t* nu,
+                                   hipStream_t st) {
   if (n <= 0 || k < 2) return hipSuccess;
   int64_t blocks = (n + 255) / 256;
   if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_complete_records, dim3((unsigned)blocks), dim3(256), 0, st, rec, ids1, n, k,
-                     nu);
+  hipLaunchKernelGGL(k_complete_records, dim3((unsigned)blocks), dim3(256), 0, st, rec, n, k, nu);
   return hipGetLastError();
 }
 
