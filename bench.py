@@ -55,9 +55,10 @@ def onesweep_bytes(n: int, nu: int, k: int):
     complete word-by-word sort of array 0 is also enqueued, gated on the tie
     step's flag: its k * 4 passes move nothing unless a run of equal first
     words is too long, and count as launches of no bytes.  Each of the k-1
-    chain sorts runs over the n_unique rows and moves its key word and k
-    payload words (row id, ranks known so far, key words of the later sorts);
-    its last pass drops the key.  Every word read or written counts 4 bytes."""
+    chain sorts runs over the n_unique rows and moves its key word and k-1
+    payload words (the ranks known so far, the first made by its first pass
+    as the input position, and the key words of the later sorts); its last
+    pass drops the key.  Every word read or written counts 4 bytes."""
     P = 4  # 8-bit digit passes per 32-bit word
     words = 0
     launches = 0
@@ -71,7 +72,7 @@ def onesweep_bytes(n: int, nu: int, k: int):
         launches += P
     for _ in range(k - 1, 0, -1):
         for ps in range(P):
-            words += nu * ((k if ps == 0 else k + 1) + (k if ps == P - 1 else k + 1))
+            words += nu * ((k - 1 if ps == 0 else k) + (k - 1 if ps == P - 1 else k))
         launches += P
     return 4 * words, launches
 

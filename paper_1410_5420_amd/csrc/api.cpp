@@ -64,7 +64,7 @@ Layout plan(int64_t n, int k, int B, bool learned = false) {
   };
   L.vbuf = take(4 * un * (k + 2) * 2);  // radix passes: two sets of k+2 quantity slots
   L.carry = take(4 * un * (k + 1));     // key words (and tree ids) handed between sorts
-  L.S = take(4 * un * k);               // the k deduplicated sorted id arrays
+  L.S = take(4 * un);                   // row ids in order 0 (the deduplicated order-0 array)
   const size_t rw = 4 * (size_t)record_words(k, nn);
   L.rec0 = take(k > 1 ? rw : 4);        // level-0 rank records (kept)
   L.rec1 = take(k > 1 ? rw : 4);        // moved records, odd number of moves
@@ -431,8 +431,8 @@ int presort_impl(const Job& J, hipStream_t st) {
   if (n == 0) return KD_OK;
   const int32_t* total = uoff + B;
   // Chain: the array for super key d is the stable sort by word d (then tree)
-  // of the array for super key d+1.  Besides the row id, each sort carries the
-  // ranks already known -- the input position is the rank in order d+1 --
+  // of the array for super key d+1.  Each sort carries the ranks already
+  // known -- the input position is the rank in order d+1 --
   // straight into array d's level-0 rank planes (plane c = rank in order
   // d+1+c), the key words of the sorts still to come, and the tree ids.
   // The plain build rewrites the carried key words in place.  The learned
@@ -447,8 +447,7 @@ int presort_impl(const Job& J, hipStream_t st) {
     const uint32_t* in_rec = rec0 + record_offset((d + 1) % k, k, n);
     uint32_t* out_rec = rec0 + record_offset(d, k, n);
     const int known = k - d;  // record planes 0 .. k-d-1
-    std::vector<Quant> q;
-    q.push_back(Quant{kPlaneArray, S + (size_t)((d + 1) % k) * un, 0, S + (size_t)d * un});
+    std::vector<Quant> q;  // (row ids are needed in order 0 only: none travel here)
     for (int cc = 0; cc < known; ++cc)
       q.push_back(cc == 0 ? Quant{kPlaneIndex, nullptr, 0, out_rec}
                           : Quant{kPlaneArray, in_rec + (size_t)(cc - 1) * un, 0,
@@ -475,7 +474,7 @@ int presort_impl(const Job& J, hipStream_t st) {
       ls.keyq = keyq;
       ls.sortq.push_back(keyq);
       ls.certq.push_back(keyq);
-      ls.tieq = 1;
+      ls.tieq = 0;
       ls.starts = at<int32_t>(ws, L.starts);
       ls.flag = at<int32_t>(ws, L.flags) + d;
       std::vector<Quant> ql = q;
