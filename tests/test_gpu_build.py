@@ -203,6 +203,24 @@ def test_full_size_c2_bit_exact(kd):
     assert np.array_equal(perm, want["perm"])
 
 
+@pytest.mark.parametrize("k", [2, 3, 4, 6, 8])
+def test_c3_full_size(kd, k):
+    """The dimension sweep at its full size (n=2^22, 256 Gaussian clusters, 10%
+    copies), every output compared, children included."""
+    assert_same(kd, kdgen.c3_clustered(k), threads=os.cpu_count() or 8)
+
+
+def test_c5_full_size_plain(kd):
+    """The learned form's workload (k=3, n=2^26 float32 mixture of 64
+    anisotropic Gaussians) through the plain build, every output compared; the
+    learned build is compared with this one in the learned tests."""
+    t = kdgen.c5_mixture()
+    want = oracle.build_tree(t, threads=os.cpu_count() or 8, children=False)
+    perm, nu = run_gpu(kd, t, children=False)
+    assert nu == want["n_unique"]
+    assert np.array_equal(perm, want["perm"])
+
+
 # ---- batched form ---------------------------------------------------------------
 
 def assert_batched_same(kd, t, offsets, cutover=None, level=None):
