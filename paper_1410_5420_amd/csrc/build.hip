@@ -783,8 +783,8 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
   static_assert(kChunks <= kWave, "one wave scans the chunk totals of an array");
   extern __shared__ __align__(16) unsigned char s_raw[];
   uint32_t* s_r0 = reinterpret_cast<uint32_t*>(s_raw);       // [C] sorted order-0 ranks
-  uint16_t* s_pos = reinterpret_cast<uint16_t*>(s_r0 + C);   // [C] position in the split array
-  uint16_t* s_out = s_pos + C;                               // [C] node id of each position
+  uint8_t* s_side = reinterpret_cast<uint8_t*>(s_r0 + C);    // [C] side of each local id this level
+  uint16_t* s_out = reinterpret_cast<uint16_t*>(s_side + 2 * C);  // [C] node id of each position
   uint16_t* s_lid = s_out + C;                               // [2][k][C] local-id arrays
   __shared__ uint32_t s_chunk[R][kWave];
   __shared__ uint32_t s_cnt[kLfWaves][kRadix];
@@ -898,7 +898,8 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
     const int p = depth % k;
     const uint16_t* ap = s_lid + ((((curmask >> p) & 1) * k) + p) * C;
     // phase 1: step down one level (the parent's node becomes a hole), then
-    // record where each id sits in the split array and each subarray's node
+    // record the side of each id (from its place in the split array) and
+    // each subarray's node
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
       const int i = it * kLfThreads + tid;
@@ -917,8 +918,9 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
         seg[it] = (uint32_t)ss | ((uint32_t)ee << 16);
       }
       const uint16_t id = ap[i];
-      s_pos[id] = (uint16_t)i;
-      if (i == ss + ((ee - ss) >> 1)) s_out[i] = id;
+      const int m = ss + ((ee - ss) >> 1);
+      s_side[id] = i < m ? 1 : (i > m ? 2 : 0);  // lower, upper, node
+      if (i == m) s_out[i] = id;
     }
     __syncthreads();
     // phase 2: side of every element of the k-1 moving arrays, counted as
@@ -934,21 +936,16 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
     for (int it = 0; it < kItems; ++it) {
       const int i = it * kLfThreads + tid;
       const bool live = seg[it] != kHole;
-      const int ss = (int)(seg[it] & 0xFFFF), ee = (int)(seg[it] >> 16);
-      const int m = ss + ((ee - ss) >> 1);
+      const int ss = (int)(seg[it] & 0xFFFF);
       const int cbase = it * kLfThreads + w * kWave;
       const bool hin = live && ss >= cbase;
       const int hlane = hin ? ss - cbase : 0;
 #pragma unroll
       for (int a2 = 0; a2 < R; ++a2) {
         const int j = (p + 1 + a2) % k;
-        uint32_t id = 0, side = 0;
-        if (live) {
-          id = s_lid[((((curmask >> j) & 1) * k) + j) * C + i];
-          const int pp = s_pos[id];
-          side = pp < m ? 1u : (pp > m ? 2u : 0u);
-        }
-        const uint32_t f = side == 1u ? 1u : (side == 2u ? 0x10000u : 0u);
+        uint32_t side = 0;
+        if (live) side = s_side[s_lid[((((curmask >> j) & 1) * k) + j) * C + i]];
+        const uint32_t f = (side & 1u) | ((side & 2u) << 15);
         const uint32_t inc = wave_scan_dpp(f);
         const uint32_t exc = inc - f;
         const uint32_t hexc = __shfl(exc, hlane, kWave);

@@ -149,7 +149,7 @@ inline int64_t level_tiles(int64_t n) { return (n + kLevelTile - 1) / kLevelTile
 
 // LDS bytes the on-chip finish needs for a cutover C in k dimensions.
 inline size_t leaf_lds_bytes(int64_t cutover, int k) {
-  return (size_t)cutover * (4 + 2 + 2 + 2 * 2 * k);
+  return (size_t)cutover * (4 + 2 + 2 + 2 * 2 * k);  // s_r0, s_side (padded to 2), s_out, s_lid
 }
 
 // On-chip finish of every subarray at the cutover depth (row ids come from
