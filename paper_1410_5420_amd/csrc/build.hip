@@ -777,7 +777,8 @@ __device__ bool lds_radix_sort(uint32_t* ka, uint16_t* va, uint32_t* kb, uint16_
 
 template <int kItems, int R>
 __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Forest F, int64_t n,
-                                                    int k, int32_t* __restrict__ perm) {
+                                                    int /* k: R + 1 */, int32_t* __restrict__ perm) {
+  constexpr int k = R + 1;  // known at compile time: index arithmetic mod k folds
   constexpr int C = kItems * kLfThreads;
   constexpr int kChunks = kItems * kLfWaves;
   static_assert(kChunks <= kWave, "one wave scans the chunk totals of an array");
