@@ -21,17 +21,6 @@ __device__ __forceinline__ uint64_t lanes_below_mask() {
 
 __device__ __forceinline__ uint32_t popc64(uint64_t m) { return (uint32_t)__popcll(m); }
 
-// Inclusive prefix sum across the 64 lanes of a wave.
-template <typename T>
-__device__ __forceinline__ T wave_inclusive_sum(T v) {
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    T o = __shfl_up(v, d, kWave);
-    if ((int)lane_id() >= d) v += o;
-  }
-  return v;
-}
-
 // Inclusive prefix sum across the 64 lanes of a wave through DPP lane moves:
 // shifts by 1, 2, 4 and 8 within each row of 16 lanes, then the last lane of
 // row r added to row r+1 and the last lane of row 1 to rows 2 and 3.  All 64
@@ -44,6 +33,22 @@ __device__ __forceinline__ uint32_t wave_scan_dpp(uint32_t v) {
   v += __builtin_amdgcn_update_dpp(0u, v, 0x142, 0xA, 0xF, false);  // row_bcast:15
   v += __builtin_amdgcn_update_dpp(0u, v, 0x143, 0xC, 0xF, false);  // row_bcast:31
   return v;
+}
+
+// Inclusive prefix sum across the 64 lanes of a wave (all lanes active):
+// DPP lane moves for 32-bit values, shuffles otherwise.
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_sum(T v) {
+  if constexpr (sizeof(T) == 4) {
+    return (T)wave_scan_dpp((uint32_t)v);
+  } else {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      T o = __shfl_up(v, d, kWave);
+      if ((int)lane_id() >= d) v += o;
+    }
+    return v;
+  }
 }
 
 // Exclusive block-wide prefix sum of one value per thread (NT threads, a
