@@ -121,11 +121,16 @@ struct SegInfo {
   int32_t pad;
 };
 
+// Sum over a wave (all lanes active), the same in every lane.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
+  if constexpr (sizeof(T) == 4) {
+    return (T)__builtin_amdgcn_readlane((int)wave_scan_dpp((uint32_t)v), kWave - 1);
+  } else {
 #pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
-  return v;
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+  }
 }
 
 // Wave 0 of a block: subarrays meeting [t0, t1) at `depth`, their medians'
@@ -692,17 +697,17 @@ constexpr int kLfWaves = kLfThreads / kWave;
 constexpr uint32_t kHole = 0xFFFFFFFFu;
 constexpr uint32_t kHeadBit = 0x80000000u;
 
-// Inclusive segmented sum across a wave: a lane with `head` starts a new run.
+// Inclusive segmented sum across a wave (all lanes active): a lane with
+// `head` starts a new run.  On return v is the sum from the latest head at or
+// before the lane (from lane 0 when there is none) and h tells whether there
+// is such a head.  An unsegmented DPP sum S and a DPP max-scan of the head
+// lanes give it: v = S[lane] - S[latest head - 1].
 __device__ __forceinline__ void wave_seg_scan(uint32_t& v, bool& h) {
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const uint32_t vo = __shfl_up(v, d, kWave);
-    const int ho = __shfl_up((int)h, d, kWave);
-    if ((int)lane_id() >= d) {
-      if (!h) v += vo;
-      h = h || ho;
-    }
-  }
+  const uint32_t sum = wave_scan_dpp(v);
+  const uint32_t hl = wave_max_dpp(h ? lane_id() + 1u : 0u);  // latest head lane + 1, 0 if none
+  const uint32_t before = __shfl(sum, hl > 1u ? (int)hl - 2 : 0, kWave);
+  v = sum - (hl > 1u ? before : 0u);
+  h = hl != 0u;
 }
 
 // Stable LSD radix sort of up to C keys in LDS (8-bit digits): keys and 16-bit

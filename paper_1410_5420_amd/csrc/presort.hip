@@ -498,12 +498,7 @@ constexpr int kTileGrid = 1024;  // resident workgroups walking the tiles
 // 0); s_tmp holds kTileThreads/64 words.  Contains barriers.
 __device__ __forceinline__ int block_exclusive_max(int v, int* s_tmp) {
   const int lane = (int)lane_id(), w = threadIdx.x / kWave;
-  int inc = v;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const int o = __shfl_up(inc, d, kWave);
-    if (lane >= d) inc = max(inc, o);
-  }
+  const int inc = (int)wave_max_dpp((uint32_t)(v + 1)) - 1;  // values >= -1
   const int below = __shfl_up(inc, 1, kWave);
   if (lane == kWave - 1) s_tmp[w] = inc;
   __syncthreads();
