@@ -903,6 +903,12 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
   for (int depth = lc, rel = 0; (N >> rel) > 0; ++depth, ++rel) {
     const int p = depth % k;
     const uint16_t* ap = s_lid + ((((curmask >> p) & 1) * k) + p) * C;
+    // The largest subarray at this level holds N >> rel elements.  Once that
+    // is at most 3, every child holds at most one element, and the split
+    // array, which this level does not move, already has each child's
+    // element in the child's position: every remaining node is the split
+    // array's element in place.
+    const bool last = (N >> rel) <= 3;
     // phase 1: step down one level (the parent's node becomes a hole), then
     // record the side of each id (from its place in the split array) and
     // each subarray's node
@@ -924,11 +930,16 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
         seg[it] = (uint32_t)ss | ((uint32_t)ee << 16);
       }
       const uint16_t id = ap[i];
+      if (last) {
+        s_out[i] = id;
+        continue;
+      }
       const int m = ss + ((ee - ss) >> 1);
       s_side[id] = i < m ? 1 : (i > m ? 2 : 0);  // lower, upper, node
       if (i == m) s_out[i] = id;
     }
     __syncthreads();
+    if (last) break;
     // phase 2: side of every element of the k-1 moving arrays, counted as
     // lower (bits 0-15) | upper << 16 by a plain scan over each wave chunk;
     // an element whose subarray starts in the same chunk takes its count

@@ -743,16 +743,16 @@ __device__ bool sort_unit(const LocalSort& ls, const ModelLds& m, int s, int N, 
 //      to uniform: about two keys per bin, bin = (F * 2^b - first bucket) *
 //      bins / buckets (keys outside the model's domain: by value), counted
 //      and scattered with LDS atomics;
-//   3. every bin is put in order by the total order above: by one thread
-//      (insertion) when small, by the whole workgroup (each key's rank =
-//      number of smaller keys in the bin) when it holds a long run of equal
-//      primary words;
+//   3. the keys are copied into bin order (slots); every slot's key is
+//      ranked by counting the keys of its bin that precede it in the total
+//      order above (primary and first tie word from LDS, later tie words
+//      from memory only on a full tie);
 //   4. every plane is written permuted: the sort words straight from LDS,
 //      the others staged through LDS (so an output may be its input), the
 //      first three of them loaded into registers before the sort.
-// A bucket beyond kBsCap raises flag bit 1, and a bin beyond kBsMaxDense
-// keys, or more than kBsMaxBig large bins in a unit, bit 8: the caller's
-// radix sort then runs instead.
+// A bucket beyond kBsCap raises flag bit 1, and bins so uneven that the
+// ranking would exceed kBsWorkPerKey comparisons per key (the sum of the
+// squared bin sizes) bit 8: the caller's radix sort then runs instead.
 __global__ __launch_bounds__(kBsThreads) void k_bucket_sort(const int32_t* __restrict__ starts,
                                                             int nb, int group, int64_t n_host,
                                                             const int32_t* n_dev,
