@@ -172,6 +172,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip the learned and batched forms")
     ap.add_argument("--no-tune", action="store_true", help="use the default knobs instead of autotuning")
+    ap.add_argument("--no-queries", action="store_true", help="skip the tree searches on the C2 tree")
     ap.add_argument("--n", type=int, default=1 << 24, help=argparse.SUPPRESS)
     ap.add_argument("--calibrate", action="store_true",
                     help="first run one plain 256 MiB device copy (a reference for profiler byte counters)")
@@ -303,6 +304,9 @@ def main():
         "roofline_secondary": secondary,
     }
 
+    if not args.no_queries:
+        out["queries"] = queries_c2(torch, kd, _lib, kdgen, t, t_host, perm, b.n_unique, nu, args)
+
     if not args.no_forms:
         plain_perm = perm.clone()
         out["forms"] = {"learned_c2": learned_form(torch, kd, t, plain_perm, nu, args, "c2 (same input)",
@@ -318,6 +322,76 @@ def main():
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(t_host)
     print(json.dumps(out), flush=True)
+
+
+def queries_c2(torch, kd, _lib, kdgen, t, t_host, perm, n_nodes, nu, args):
+    """Batched searches over the C2 tree just built: 2^20 nearest-neighbour
+    queries (m = 8) and 2^20 box counts, each kernel timed over its launches
+    with the library's probe (HIP events on the launch stream).  Bytes: every
+    visited node reads its row id (4 B) and its coordinates (4k B); the
+    visits are counted by the kernels.  The CPU oracle runs a sample of the
+    same queries."""
+    n, k = t.shape
+    nq = 1 << 20
+    pts, lo, hi = kdgen.c2_queries(t_host, nq)
+    dp, dlo, dhi = (torch.from_numpy(a).to(t.device) for a in (pts, lo, hi))
+    reps = 5
+    res = {"workload": "C2 tree (k=3, 2^24 int32 rows); 2^20 points within 1000 of a random row "
+                       "(m = 8 nearest) and 2^20 boxes of half-width 2^26 around random rows"}
+    visits = torch.zeros(1, dtype=torch.int64, device=t.device)
+    runs = {"nearest_m8": lambda v: kd.nearest(t, perm, n_nodes, dp, 8, visits=v),
+            "box_count": lambda v: kd.region_count(t, perm, n_nodes, dlo, dhi, visits=v)}
+    outs = {}
+    for name, fn in runs.items():
+        fn(None)
+        visits.zero_()
+        outs[name] = fn(visits)
+        torch.cuda.synchronize()
+        per_query = int(visits.item()) / nq
+        _lib.probe_start("query", reps)
+        for _ in range(reps):
+            fn(None)
+        torch.cuda.synchronize()
+        ms = float(np.mean(_lib.probe_stop(reps)))
+        gbs = per_query * nq * (4 + 4 * k) / (ms * 1e-3) / 1e9
+        res[name] = {"ms_per_batch": round(ms, 4), "queries_per_s": round(nq / (ms * 1e-3), 1),
+                     "visits_per_query": round(per_query, 2), "node_bytes_gbs": round(gbs, 1),
+                     "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+        log(f"queries {name}: {ms:.3f} ms per 2^20, {per_query:.1f} visits per query")
+    res["box_mean_count"] = round(float(outs["box_count"].float().mean().item()), 2)
+    # spot check against the oracle on a few queries
+    from oracle import queries as oq
+
+    p = perm[:nu].cpu().numpy()
+    nn_rows = outs["nearest_m8"].cpu().numpy()
+    counts = outs["box_count"].cpu().numpy()
+    ok = True
+    for q in range(4):
+        od = [d for d, _ in oq.nearest_neighbors(t_host, p, [int(v) for v in pts[q]], 8)]
+        x = t_host[nn_rows[q]].astype(object)
+        gd = [sum((int(a) - int(b)) ** 2 for a, b in zip(r, pts[q])) for r in x]
+        ok = ok and od == gd
+        ok = ok and len(oq.region_search(t_host, p, lo[q].tolist(), hi[q].tolist())) == counts[q]
+    res["spot_check_vs_oracle"] = bool(ok)
+    if not args.no_cpu:
+        # the oracle as it stands, on a sample of the same queries
+        t0 = time.perf_counter()
+        s_nn = 2000
+        for q in range(s_nn):
+            oq.nearest_neighbors(t_host, p, [int(v) for v in pts[q]], 8)
+        nn_s = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        s_box = 200
+        for q in range(s_box):
+            oq.region_search(t_host, p, lo[q].tolist(), hi[q].tolist())
+        box_s = time.perf_counter() - t0
+        res["cpu_baseline"] = {"kind": "oracle", "cores": 1,
+                               "nearest_m8_queries_per_s": round(s_nn / nn_s, 1),
+                               "box_count_queries_per_s": round(s_box / box_s, 1),
+                               "sample": f"the first {s_nn} points and {s_box} boxes of the same "
+                                         f"batches ({nn_s + box_s:.1f} s, one Python thread)"}
+        log(f"queries cpu oracle: {s_nn / nn_s:.0f} nn/s, {s_box / box_s:.0f} boxes/s")
+    return res
 
 
 def learned_form(torch, kd, t, plain_perm, nu, args, label, knobs=None):

@@ -211,6 +211,58 @@ int kdtree_presort_learned(const void* d_tuples, int64_t n, int32_t k, int32_t d
                            void* d_workspace, size_t workspace_bytes, const kd_options* opts,
                            void* stream);
 
+/* ---- searches over a built tree ---------------------------------------------
+ * The two searches the paper runs on its tree, batched over many queries on
+ * the device (one query per thread): all nodes inside a k-dimensional
+ * hyper-rectangle (Appendix, "Source Code for Optimized Algorithms": region
+ * search) and the m nearest nodes of a point (Appendix, "Nearest Neighbors").
+ * Both walk the implicit tree of the in-order layout (the node of [s, e] is
+ * position s + (e - s) / 2 and splits on dimension depth mod k) and prune
+ * with non-strict bounds: a "less than" subtree's coordinates in the split
+ * dimension are <= the node's, a "greater than" subtree's are >= (equal
+ * values occur when a later portion of the super key decides), so the
+ * results are exactly those of a linear scan over the tree's nodes.
+ * Coordinates compare as values of dtype (float32: IEEE comparisons, so
+ * -0.0 == +0.0 and a NaN coordinate is never inside a box; distances that
+ * involve NaN order unpredictably).
+ *   d_tuples    n*k of dtype, row-major: the rows the tree was built from
+ *   d_perm      int32 in-order layout from kdtree_build (positions
+ *               0 .. n_nodes - 1 are read; every entry must be a row < n,
+ *               an entry that is not is skipped with its subtree)
+ *   d_n_nodes   int64[1] device: the tree's node count (kdtree_build's
+ *               d_n_unique), clamped to 0 .. n
+ *   d_visits    uint64[1] device, or NULL: the number of nodes the queries
+ *               visited is added to it (for measurement)
+ * Queries are nq rows of k values of dtype, row-major; 0 <= nq <=
+ * KD_MAX_QUERIES.  Asynchronous on `stream`; validation as for the builds. */
+#define KD_MAX_QUERIES ((int64_t)1 << 28)
+#define KD_MAX_NEIGHBORS 64
+
+/* Box queries, counts: d_counts[q] = number of nodes x with
+ * d_lower[q][d] <= x[d] <= d_upper[q][d] for every d (int32[nq]). */
+int kd_region_count(const void* d_tuples, int64_t n, int32_t k, int32_t dtype,
+                    const int32_t* d_perm, const int64_t* d_n_nodes, const void* d_lower,
+                    const void* d_upper, int64_t nq, int32_t* d_counts, uint64_t* d_visits,
+                    void* stream);
+/* Box queries, rows: the rows of query q's nodes are written to
+ * d_rows[d_offsets[q]], d_rows[d_offsets[q] + 1], ... in increasing tree
+ * position (int64 d_offsets[nq], e.g. the exclusive scan of kd_region_count's
+ * counts); no write goes at or past rows_capacity. */
+int kd_region_rows(const void* d_tuples, int64_t n, int32_t k, int32_t dtype,
+                   const int32_t* d_perm, const int64_t* d_n_nodes, const void* d_lower,
+                   const void* d_upper, int64_t nq, const int64_t* d_offsets, int32_t* d_rows,
+                   int64_t rows_capacity, uint64_t* d_visits, void* stream);
+/* m nearest nodes (1 <= m <= KD_MAX_NEIGHBORS) of each query point by squared
+ * Euclidean distance: exact integers for int32 coordinates, for float32 the
+ * float64 sum over d = 0 .. k-1 of (x[d] - q[d])^2, each difference, square
+ * and sum rounded once.  d_rows[q * m + i] (int32[nq * m]) receives the rows
+ * of the m nodes smallest in (distance, row), in that order, and -1 past the
+ * node count; ties in distance go to the smaller row, so the result does not
+ * depend on the walk. */
+int kd_nearest(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, const int32_t* d_perm,
+               const int64_t* d_n_nodes, const void* d_points, int64_t nq, int32_t m,
+               int32_t* d_rows, uint64_t* d_visits, void* stream);
+
 /* ---- diagnostics ------------------------------------------------------------
  * Kernel probe for measurement tools.  kd_probe_start() makes the library
  * record a HIP event pair around every launch of one kernel class (on the
@@ -229,7 +281,8 @@ enum kd_kernel_class {
   KD_K_CANON = 6,    /* key canonicalisation */
   KD_K_RECORDS = 7,  /* rank tables and level-0 records */
   KD_K_BUCKET = 8,   /* learned presort: per-bucket finish */
-  KD_K_TIES = 9      /* array 0: ordering the runs of equal first words */
+  KD_K_TIES = 9,     /* array 0: ordering the runs of equal first words */
+  KD_K_QUERY = 10    /* one batch of tree searches */
 };
 int kd_probe_start(int32_t kernel_class, int32_t capacity);
 int kd_probe_stop(float* h_ms, int32_t* h_count);

@@ -156,3 +156,19 @@ def c5_mixture(n: int = 1 << 26) -> np.ndarray:
     """k=3, n=2^26, float32 mixture of 64 anisotropic Gaussians with lognormal
     scales (mu 0, sigma 1.5)."""
     return gaussian_mixture_f32(n, 3, 64, SEED_BASE + 5)
+
+
+def c2_queries(t: np.ndarray, nq: int = 1 << 20, seed: int = SEED_BASE + 6):
+    """Queries over the C2 tree: ``nq`` points, each a random tuple moved by
+    up to 1000 in every coordinate (nearest-neighbour queries), and ``nq``
+    boxes of half-width 2^26 around random tuples (about 500 of the 2^24
+    rows inside each).  Returns ``(points, lower, upper)``, int32 (nq, k)."""
+    g = rng(seed)
+    n, k = t.shape
+    base = t[g.integers(0, n, size=nq)].astype(np.int64)
+    pts = np.clip(base + g.integers(-1000, 1001, size=base.shape), -2**31, 2**31 - 1)
+    centre = t[g.integers(0, n, size=nq)].astype(np.int64)
+    half = 1 << 26
+    lower = np.clip(centre - half, -2**31, 2**31 - 1)
+    upper = np.clip(centre + half, -2**31, 2**31 - 1)
+    return pts.astype(np.int32), lower.astype(np.int32), upper.astype(np.int32)

@@ -21,24 +21,37 @@ import heapq
 import numpy as np
 
 
-def _coords(tuples: np.ndarray):
-    if tuples.dtype == np.int32:
-        return [tuple(int(v) for v in row) for row in tuples]
-    return [tuple(float(v) for v in row) for row in tuples.astype(np.float64)]
+class _coords:
+    """Exact coordinates of a row, converted when first read (Python ints for
+    int32, float64 for float32), so a search costs what it visits."""
+
+    def __init__(self, tuples: np.ndarray):
+        self.t = tuples
+        self.cache = {}
+
+    def __getitem__(self, row: int):
+        x = self.cache.get(row)
+        if x is None:
+            r = self.t[row]
+            if self.t.dtype == np.int32:
+                x = tuple(int(v) for v in r)
+            else:
+                x = tuple(float(v) for v in r.astype(np.float64))
+            self.cache[row] = x
+        return x
 
 
 def region_search(tuples: np.ndarray, perm: np.ndarray, lower, upper):
     """Rows of all tree nodes with ``lower[d] <= x[d] <= upper[d]`` for every d."""
     pts = _coords(tuples)
     k = tuples.shape[1]
-    perm = [int(v) for v in perm]
     found = []
 
     def visit(s, e, depth):
         if e < s:
             return
         m = s + (e - s) // 2
-        row = perm[m]
+        row = int(perm[m])
         x = pts[row]
         if all(lower[d] <= x[d] <= upper[d] for d in range(k)):
             found.append(row)
@@ -57,7 +70,6 @@ def nearest_neighbors(tuples: np.ndarray, perm: np.ndarray, query, m: int):
     in increasing distance, found with a bounded max-priority queue."""
     pts = _coords(tuples)
     k = tuples.shape[1]
-    perm = [int(v) for v in perm]
     q = tuple(query)
     heap = []  # max-heap on distance via negation
 
@@ -68,7 +80,7 @@ def nearest_neighbors(tuples: np.ndarray, perm: np.ndarray, query, m: int):
         if e < s:
             return
         mid = s + (e - s) // 2
-        row = perm[mid]
+        row = int(perm[mid])
         x = pts[row]
         dist = sqd(x)
         if len(heap) < m:

@@ -941,8 +941,86 @@ int kdtree_build_learned(const void* d_tuples, int64_t n, int32_t k, int32_t dty
   return kd::partition_impl(J, st);
 }
 
+#define KD_QLAUNCH(expr)                              \
+  do {                                                \
+    kd::probe_begin(KD_K_QUERY, st);                  \
+    hipError_t e__ = (expr);                          \
+    kd::probe_end(KD_K_QUERY, st);                    \
+    if (e__ != hipSuccess) return KD_EHIP;            \
+  } while (0)
+
+namespace {
+// Shared checks of the tree searches; on success *is_float is set.
+int check_query(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, const int32_t* d_perm,
+                const int64_t* d_n_nodes, int64_t nq, uint64_t* d_visits, int* is_float) {
+  if (n < 0 || k < 1 || nq < 0 || (dtype != KD_I32 && dtype != KD_F32)) return KD_EINVAL;
+  if (n > KD_MAX_N || k > KD_MAX_K || nq > KD_MAX_QUERIES) return KD_EUNSUPPORTED;
+  if (!d_tuples || !d_perm || !d_n_nodes) return KD_EINVAL;
+  if (!kd::aligned4(d_tuples) || !kd::aligned4(d_perm) ||
+      (reinterpret_cast<uintptr_t>(d_n_nodes) & 7u) || (reinterpret_cast<uintptr_t>(d_visits) & 7u))
+    return KD_EINVAL;
+  *is_float = dtype == KD_F32;
+  return KD_OK;
+}
+}  // namespace
+
+int kd_region_count(const void* d_tuples, int64_t n, int32_t k, int32_t dtype,
+                    const int32_t* d_perm, const int64_t* d_n_nodes, const void* d_lower,
+                    const void* d_upper, int64_t nq, int32_t* d_counts, uint64_t* d_visits,
+                    void* stream) {
+  int fl = 0;
+  int rc = check_query(d_tuples, n, k, dtype, d_perm, d_n_nodes, nq, d_visits, &fl);
+  if (rc != KD_OK) return rc;
+  if (nq == 0) return KD_OK;
+  if (!d_lower || !d_upper || !d_counts) return KD_EINVAL;
+  if (!kd::aligned4(d_lower) || !kd::aligned4(d_upper) || !kd::aligned4(d_counts)) return KD_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  KD_QLAUNCH( kd::launch_region(d_tuples, n, k, fl, d_perm, d_n_nodes, d_lower, d_upper,
+                                          nq, d_counts, nullptr, nullptr, 0,
+                                          reinterpret_cast<unsigned long long*>(d_visits), st));
+  return KD_OK;
+}
+
+int kd_region_rows(const void* d_tuples, int64_t n, int32_t k, int32_t dtype,
+                   const int32_t* d_perm, const int64_t* d_n_nodes, const void* d_lower,
+                   const void* d_upper, int64_t nq, const int64_t* d_offsets, int32_t* d_rows,
+                   int64_t rows_capacity, uint64_t* d_visits, void* stream) {
+  int fl = 0;
+  int rc = check_query(d_tuples, n, k, dtype, d_perm, d_n_nodes, nq, d_visits, &fl);
+  if (rc != KD_OK) return rc;
+  if (rows_capacity < 0) return KD_EINVAL;
+  if (nq == 0) return KD_OK;
+  if (!d_lower || !d_upper || !d_offsets || (!d_rows && rows_capacity > 0)) return KD_EINVAL;
+  if (!kd::aligned4(d_lower) || !kd::aligned4(d_upper) || !kd::aligned4(d_rows) ||
+      (reinterpret_cast<uintptr_t>(d_offsets) & 7u))
+    return KD_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // a null row buffer (capacity 0) still walks: nothing is written
+  KD_QLAUNCH( kd::launch_region(d_tuples, n, k, fl, d_perm, d_n_nodes, d_lower, d_upper,
+                                          nq, nullptr, d_offsets, d_rows, rows_capacity,
+                                          reinterpret_cast<unsigned long long*>(d_visits), st));
+  return KD_OK;
+}
+
+int kd_nearest(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, const int32_t* d_perm,
+               const int64_t* d_n_nodes, const void* d_points, int64_t nq, int32_t m,
+               int32_t* d_rows, uint64_t* d_visits, void* stream) {
+  int fl = 0;
+  int rc = check_query(d_tuples, n, k, dtype, d_perm, d_n_nodes, nq, d_visits, &fl);
+  if (rc != KD_OK) return rc;
+  if (m < 1 || m > KD_MAX_NEIGHBORS) return KD_EINVAL;
+  if (nq == 0) return KD_OK;
+  if (!d_points || !d_rows) return KD_EINVAL;
+  if (!kd::aligned4(d_points) || !kd::aligned4(d_rows)) return KD_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  KD_QLAUNCH( kd::launch_nearest(d_tuples, n, k, fl, d_perm, d_n_nodes, d_points, nq, m,
+                                           d_rows, reinterpret_cast<unsigned long long*>(d_visits),
+                                           st));
+  return KD_OK;
+}
+
 int kd_probe_start(int32_t kernel_class, int32_t capacity) {
-  if (kernel_class < KD_K_ONESWEEP || kernel_class > KD_K_TIES || capacity < 1 ||
+  if (kernel_class < KD_K_ONESWEEP || kernel_class > KD_K_QUERY || capacity < 1 ||
       capacity > (1 << 20))
     return KD_EINVAL;
   kd::Probe& p = kd::g_probe;

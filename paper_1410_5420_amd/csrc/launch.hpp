@@ -218,6 +218,23 @@ hipError_t launch_certify(const CertArgs& ca, int64_t n, const int32_t* n_dev, i
                           hipStream_t st);
 hipError_t launch_copy_i32(const int32_t* src, int count, int32_t* dst, hipStream_t st);
 
+// ---- queries over a built tree (queries.hip) ---------------------------------------
+
+constexpr int kMaxNeighbors = 64;
+// Box queries over the *nn nodes (device count) of the in-order layout perm:
+// counts[q] (offsets == null), or the rows of query q written from
+// rows[offsets[q]] in increasing tree position (no write at or past cap).
+// visits: null, or a counter that receives the number of nodes visited.
+hipError_t launch_region(const void* tuples, int64_t n, int k, int is_float, const int32_t* perm,
+                         const int64_t* nn, const void* lower, const void* upper, int64_t nq,
+                         int32_t* counts, const int64_t* offsets, int32_t* rows, int64_t cap,
+                         unsigned long long* visits, hipStream_t st);
+// The m (1 .. kMaxNeighbors) nodes smallest in (squared distance, row) of
+// every query point, ascending, -1 past the node count: rows[q * m + i].
+hipError_t launch_nearest(const void* tuples, int64_t n, int k, int is_float, const int32_t* perm,
+                          const int64_t* nn, const void* points, int64_t nq, int32_t m, int32_t* rows,
+                          unsigned long long* visits, hipStream_t st);
+
 // Child positions from the implicit shape of a single tree (uoff[1] rows).
 hipError_t launch_children(const int32_t* uoff, int64_t n, int32_t* lo, int32_t* hi,
                            hipStream_t st);

@@ -45,6 +45,7 @@ def test_workspace_bytes(L):
 
 
 FAKE = 0x7F0000000000  # never dereferenced: every call below fails validation first
+FAKE8 = 1 << 20  # an 8-byte aligned stand-in address (never dereferenced)
 
 
 def call_build(L, n=100, k=3, dtype=0, tuples=FAKE, perm=FAKE, lo=None, hi=None, nu=FAKE, ws=FAKE,
@@ -127,3 +128,39 @@ def test_strerror(L):
 def test_probe_rejects_bad_class(L):
     assert L.lib.kd_probe_start(0, 10) == -1
     assert L.lib.kd_probe_start(2, 0) == -1
+
+
+def test_queries_reject_bad_arguments(L):
+    """Tree searches: every bad size, dtype, alignment or null pointer is
+    caught on the host (nothing reaches the device, so the fake pointers are
+    never dereferenced)."""
+    vp = ctypes.c_void_p
+    F, F8 = vp(FAKE), vp(FAKE8)
+    # region counts: bad k, dtype, n, nq; null and misaligned pointers
+    assert L.lib.kd_region_count(F, 100, 0, 0, F, F8, F, F, 10, F, None, None) == -1
+    assert L.lib.kd_region_count(F, 100, 9, 0, F, F8, F, F, 10, F, None, None) == -4
+    assert L.lib.kd_region_count(F, 100, 3, 2, F, F8, F, F, 10, F, None, None) == -1
+    assert L.lib.kd_region_count(F, -1, 3, 0, F, F8, F, F, 10, F, None, None) == -1
+    assert L.lib.kd_region_count(F, 100, 3, 0, F, F8, F, F, -1, F, None, None) == -1
+    assert L.lib.kd_region_count(F, 100, 3, 0, F, F8, F, F, (1 << 28) + 1, F, None, None) == -4
+    assert L.lib.kd_region_count(F, 100, 3, 0, None, F8, F, F, 10, F, None, None) == -1
+    assert L.lib.kd_region_count(F, 100, 3, 0, F, None, F, F, 10, F, None, None) == -1
+    assert L.lib.kd_region_count(F, 100, 3, 0, F, F8, None, F, 10, F, None, None) == -1
+    assert L.lib.kd_region_count(F, 100, 3, 0, F, F8, F, F, 10, None, None, None) == -1
+    assert L.lib.kd_region_count(vp(FAKE + 2), 100, 3, 0, F, F8, F, F, 10, F, None, None) == -1
+    assert L.lib.kd_region_count(F, 100, 3, 0, F, vp(FAKE8 + 4), F, F, 10, F, None, None) == -1
+    assert L.lib.kd_region_count(F, 100, 3, 0, F, F8, F, F, 10, F, vp(FAKE8 + 4), None) == -1
+    # no queries: nothing to do
+    assert L.lib.kd_region_count(F, 100, 3, 0, F, F8, None, None, 0, None, None, None) == 0
+    # region rows: negative capacity, null offsets, rows null with a capacity
+    assert L.lib.kd_region_rows(F, 100, 3, 0, F, F8, F, F, 10, F8, F, -1, None, None) == -1
+    assert L.lib.kd_region_rows(F, 100, 3, 0, F, F8, F, F, 10, None, F, 10, None, None) == -1
+    assert L.lib.kd_region_rows(F, 100, 3, 0, F, F8, F, F, 10, F8, None, 10, None, None) == -1
+    assert L.lib.kd_region_rows(F, 100, 3, 0, F, F8, F, F, 10, vp(FAKE8 + 4), F, 10, None, None) == -1
+    # nearest: m out of range, null points or rows
+    assert L.lib.kd_nearest(F, 100, 3, 0, F, F8, F, 10, 0, F, None, None) == -1
+    assert L.lib.kd_nearest(F, 100, 3, 0, F, F8, F, 10, 65, F, None, None) == -1
+    assert L.lib.kd_nearest(F, 100, 3, 0, F, F8, None, 10, 4, F, None, None) == -1
+    assert L.lib.kd_nearest(F, 100, 3, 0, F, F8, F, 10, 4, None, None, None) == -1
+    assert L.lib.kd_nearest(F, 100, 3, 1, F, F8, F, 0, 4, None, None, None) == 0
+    assert L.lib.kd_probe_start(11, 10) == -1
