@@ -326,11 +326,11 @@ def main():
 
 def queries_c2(torch, kd, _lib, kdgen, t, t_host, perm, n_nodes, nu, args):
     """Batched searches over the C2 tree just built: 2^20 nearest-neighbour
-    queries (m = 8) and 2^20 box counts, each kernel timed over its launches
-    with the library's probe (HIP events on the launch stream).  Bytes: every
-    visited node reads its row id (4 B) and its coordinates (4k B); the
-    visits are counted by the kernels.  The CPU oracle runs a sample of the
-    same queries."""
+    queries (m = 8) and 2^20 box counts over the node coordinates gathered
+    once into tree-position order, each kernel timed over its launches with
+    the library's probe (HIP events on the launch stream).  Bytes: every
+    visited node reads its coordinates (4k B); the visits are counted by the
+    kernels.  The CPU oracle runs a sample of the same queries."""
     n, k = t.shape
     nq = 1 << 20
     pts, lo, hi = kdgen.c2_queries(t_host, nq)
@@ -339,8 +339,12 @@ def queries_c2(torch, kd, _lib, kdgen, t, t_host, perm, n_nodes, nu, args):
     res = {"workload": "C2 tree (k=3, 2^24 int32 rows); 2^20 points within 1000 of a random row "
                        "(m = 8 nearest) and 2^20 boxes of half-width 2^26 around random rows"}
     visits = torch.zeros(1, dtype=torch.int64, device=t.device)
-    runs = {"nearest_m8": lambda v: kd.nearest(t, perm, n_nodes, dp, 8, visits=v),
-            "box_count": lambda v: kd.region_count(t, perm, n_nodes, dlo, dhi, visits=v)}
+    _lib.probe_start("query", 1)
+    nodes = kd.gather_nodes(t, perm, n_nodes)
+    torch.cuda.synchronize()
+    res["gather_nodes_ms"] = round(float(_lib.probe_stop(1)[0]), 4)
+    runs = {"nearest_m8": lambda v: kd.nearest(t, perm, n_nodes, dp, 8, visits=v, nodes=nodes),
+            "box_count": lambda v: kd.region_count(t, perm, n_nodes, dlo, dhi, visits=v, nodes=nodes)}
     outs = {}
     for name, fn in runs.items():
         fn(None)
@@ -353,7 +357,7 @@ def queries_c2(torch, kd, _lib, kdgen, t, t_host, perm, n_nodes, nu, args):
             fn(None)
         torch.cuda.synchronize()
         ms = float(np.mean(_lib.probe_stop(reps)))
-        gbs = per_query * nq * (4 + 4 * k) / (ms * 1e-3) / 1e9
+        gbs = per_query * nq * (4 * k) / (ms * 1e-3) / 1e9
         res[name] = {"ms_per_batch": round(ms, 4), "queries_per_s": round(nq / (ms * 1e-3), 1),
                      "visits_per_query": round(per_query, 2), "node_bytes_gbs": round(gbs, 1),
                      "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}

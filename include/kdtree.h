@@ -225,10 +225,13 @@ int kdtree_presort_learned(const void* d_tuples, int64_t n, int32_t k, int32_t d
  * Coordinates compare as values of dtype (float32: IEEE comparisons, so
  * -0.0 == +0.0 and a NaN coordinate is never inside a box; distances that
  * involve NaN order unpredictably).
- *   d_tuples    n*k of dtype, row-major: the rows the tree was built from
- *   d_perm      int32 in-order layout from kdtree_build (positions
- *               0 .. n_nodes - 1 are read; every entry must be a row < n,
- *               an entry that is not is skipped with its subtree)
+ *
+ * The searches read the nodes' coordinates in tree-position order, written
+ * once per tree by kd_gather_nodes: a visit is one read at the node's own
+ * position, and every subtree is contiguous.
+ *   d_nodes     n*k of dtype, row-major: node pos at row pos (pos < n_nodes)
+ *   d_perm      int32 in-order layout from kdtree_build: the row reported for
+ *               node pos is d_perm[pos]
  *   d_n_nodes   int64[1] device: the tree's node count (kdtree_build's
  *               d_n_unique), clamped to 0 .. n
  *   d_visits    uint64[1] device, or NULL: the number of nodes the queries
@@ -238,17 +241,21 @@ int kdtree_presort_learned(const void* d_tuples, int64_t n, int32_t k, int32_t d
 #define KD_MAX_QUERIES ((int64_t)1 << 28)
 #define KD_MAX_NEIGHBORS 64
 
+/* Node coordinates in tree-position order: d_nodes[pos][d] =
+ * d_tuples[d_perm[pos]][d] for pos < n_nodes (n*k of dtype; a perm entry
+ * that is not a row below n gives zeros). */
+int kd_gather_nodes(const void* d_tuples, int64_t n, int32_t k, int32_t dtype,
+                    const int32_t* d_perm, const int64_t* d_n_nodes, void* d_nodes, void* stream);
 /* Box queries, counts: d_counts[q] = number of nodes x with
  * d_lower[q][d] <= x[d] <= d_upper[q][d] for every d (int32[nq]). */
-int kd_region_count(const void* d_tuples, int64_t n, int32_t k, int32_t dtype,
-                    const int32_t* d_perm, const int64_t* d_n_nodes, const void* d_lower,
-                    const void* d_upper, int64_t nq, int32_t* d_counts, uint64_t* d_visits,
-                    void* stream);
+int kd_region_count(const void* d_nodes, int64_t n, int32_t k, int32_t dtype,
+                    const int64_t* d_n_nodes, const void* d_lower, const void* d_upper, int64_t nq,
+                    int32_t* d_counts, uint64_t* d_visits, void* stream);
 /* Box queries, rows: the rows of query q's nodes are written to
  * d_rows[d_offsets[q]], d_rows[d_offsets[q] + 1], ... in increasing tree
  * position (int64 d_offsets[nq], e.g. the exclusive scan of kd_region_count's
  * counts); no write goes at or past rows_capacity. */
-int kd_region_rows(const void* d_tuples, int64_t n, int32_t k, int32_t dtype,
+int kd_region_rows(const void* d_nodes, int64_t n, int32_t k, int32_t dtype,
                    const int32_t* d_perm, const int64_t* d_n_nodes, const void* d_lower,
                    const void* d_upper, int64_t nq, const int64_t* d_offsets, int32_t* d_rows,
                    int64_t rows_capacity, uint64_t* d_visits, void* stream);
@@ -259,7 +266,7 @@ int kd_region_rows(const void* d_tuples, int64_t n, int32_t k, int32_t dtype,
  * of the m nodes smallest in (distance, row), in that order, and -1 past the
  * node count; ties in distance go to the smaller row, so the result does not
  * depend on the walk. */
-int kd_nearest(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, const int32_t* d_perm,
+int kd_nearest(const void* d_nodes, int64_t n, int32_t k, int32_t dtype, const int32_t* d_perm,
                const int64_t* d_n_nodes, const void* d_points, int64_t nq, int32_t m,
                int32_t* d_rows, uint64_t* d_visits, void* stream);
 

@@ -18,8 +18,8 @@ from . import _lib
 from ._lib import KD_F32, KD_I32, KdError  # noqa: F401
 
 __all__ = ["Builder", "BatchedBuilder", "LearnedBuilder", "build", "build_batched", "build_learned",
-           "train_cdf", "cdf_loss_grad", "cdf_eval", "region_count", "region_rows", "nearest",
-           "KdError"]
+           "train_cdf", "cdf_loss_grad", "cdf_eval", "gather_nodes", "region_count", "region_rows",
+           "nearest", "KdError"]
 
 
 def _dtype_code(t: torch.Tensor) -> int:
@@ -182,40 +182,56 @@ def _query_args(tuples: torch.Tensor, perm: torch.Tensor, n_nodes, queries: torc
     return n, k, _dtype_code(tuples), n_nodes.reshape(1).to(torch.int64).contiguous()
 
 
+def gather_nodes(tuples: torch.Tensor, perm: torch.Tensor, n_nodes, stream=None) -> torch.Tensor:
+    """The tree's node coordinates in tree-position order (kd_gather_nodes):
+    row pos of the result is ``tuples[perm[pos]]``.  The searches read these;
+    gather once per tree and pass them as ``nodes=``."""
+    n, k, code, nn = _query_args(tuples, perm, n_nodes, tuples[:0])
+    nodes = torch.empty_like(tuples)
+    _lib.check(_lib.lib.kd_gather_nodes(_ptr(tuples.contiguous()), n, k, code, _ptr(perm), _ptr(nn),
+                                        _ptr(nodes), _stream(stream)), "kd_gather_nodes")
+    return nodes
+
+
 def region_count(tuples: torch.Tensor, perm: torch.Tensor, n_nodes, lower: torch.Tensor,
-                 upper: torch.Tensor, visits: torch.Tensor | None = None, stream=None):
+                 upper: torch.Tensor, visits: torch.Tensor | None = None, nodes=None, stream=None):
     """Number of tree nodes inside every box (kd_region_count).
 
     ``perm``: the in-order layout of ``tuples``' tree; ``n_nodes``: its node
     count (int or device int64 tensor); ``lower``/``upper``: (nq, k) box
-    corners, inclusive.  ``visits``: optional uint64 device counter.
+    corners, inclusive.  ``visits``: optional uint64 device counter;
+    ``nodes``: ``gather_nodes``' result, gathered here when not given.
     """
     n, k, code, nn = _query_args(tuples, perm, n_nodes, lower)
+    if nodes is None:
+        nodes = gather_nodes(tuples, perm, nn, stream)
     lower, upper = lower.contiguous(), upper.contiguous()
     if upper.shape != lower.shape or upper.dtype != lower.dtype:
         raise ValueError("lower and upper must match")
     nq = lower.shape[0]
     counts = torch.empty(nq, dtype=torch.int32, device=tuples.device)
-    _lib.check(_lib.lib.kd_region_count(_ptr(tuples.contiguous()), n, k, code, _ptr(perm), _ptr(nn),
-                                        _ptr(lower), _ptr(upper), nq, _ptr(counts), _ptr(visits),
-                                        _stream(stream)), "kd_region_count")
+    _lib.check(_lib.lib.kd_region_count(_ptr(nodes), n, k, code, _ptr(nn), _ptr(lower), _ptr(upper),
+                                        nq, _ptr(counts), _ptr(visits), _stream(stream)),
+               "kd_region_count")
     return counts
 
 
 def region_rows(tuples: torch.Tensor, perm: torch.Tensor, n_nodes, lower: torch.Tensor,
-                upper: torch.Tensor, stream=None):
+                upper: torch.Tensor, nodes=None, stream=None):
     """Rows of the tree nodes inside every box, as ``(rows, offsets)``: the
     rows of box q are ``rows[offsets[q]:offsets[q + 1]]`` in increasing tree
     position.  Counts first (kd_region_count), then rows (kd_region_rows);
     this synchronises once to size the output."""
-    counts = region_count(tuples, perm, n_nodes, lower, upper, stream=stream)
     n, k, code, nn = _query_args(tuples, perm, n_nodes, lower)
+    if nodes is None:
+        nodes = gather_nodes(tuples, perm, nn, stream)
+    counts = region_count(tuples, perm, nn, lower, upper, nodes=nodes, stream=stream)
     nq = lower.shape[0]
     offsets = torch.zeros(nq + 1, dtype=torch.int64, device=tuples.device)
     torch.cumsum(counts.to(torch.int64), 0, out=offsets[1:])
     total = int(offsets[-1].item())
     rows = torch.empty(max(total, 1), dtype=torch.int32, device=tuples.device)
-    _lib.check(_lib.lib.kd_region_rows(_ptr(tuples.contiguous()), n, k, code, _ptr(perm), _ptr(nn),
+    _lib.check(_lib.lib.kd_region_rows(_ptr(nodes), n, k, code, _ptr(perm), _ptr(nn),
                                        _ptr(lower.contiguous()), _ptr(upper.contiguous()), nq,
                                        _ptr(offsets), _ptr(rows), total, None, _stream(stream)),
                "kd_region_rows")
@@ -223,17 +239,18 @@ def region_rows(tuples: torch.Tensor, perm: torch.Tensor, n_nodes, lower: torch.
 
 
 def nearest(tuples: torch.Tensor, perm: torch.Tensor, n_nodes, points: torch.Tensor, m: int,
-            visits: torch.Tensor | None = None, stream=None):
+            visits: torch.Tensor | None = None, nodes=None, stream=None):
     """The m nearest tree nodes of every query point (kd_nearest): an (nq, m)
     int32 tensor of rows in increasing (squared distance, row), -1 past the
     node count."""
     n, k, code, nn = _query_args(tuples, perm, n_nodes, points)
+    if nodes is None:
+        nodes = gather_nodes(tuples, perm, nn, stream)
     points = points.contiguous()
     nq = points.shape[0]
     rows = torch.empty((nq, m), dtype=torch.int32, device=tuples.device)
-    _lib.check(_lib.lib.kd_nearest(_ptr(tuples.contiguous()), n, k, code, _ptr(perm), _ptr(nn),
-                                   _ptr(points), nq, int(m), _ptr(rows), _ptr(visits),
-                                   _stream(stream)), "kd_nearest")
+    _lib.check(_lib.lib.kd_nearest(_ptr(nodes), n, k, code, _ptr(perm), _ptr(nn), _ptr(points), nq,
+                                   int(m), _ptr(rows), _ptr(visits), _stream(stream)), "kd_nearest")
     return rows
 
 

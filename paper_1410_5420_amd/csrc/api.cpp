@@ -950,13 +950,15 @@ int kdtree_build_learned(const void* d_tuples, int64_t n, int32_t k, int32_t dty
   } while (0)
 
 namespace {
-// Shared checks of the tree searches; on success *is_float is set.
-int check_query(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, const int32_t* d_perm,
-                const int64_t* d_n_nodes, int64_t nq, uint64_t* d_visits, int* is_float) {
+// Shared checks of the tree searches; on success *is_float is set.  perm may
+// be null only where the caller says so.
+int check_query(const void* d_nodes, int64_t n, int32_t k, int32_t dtype, const int32_t* d_perm,
+                bool need_perm, const int64_t* d_n_nodes, int64_t nq, uint64_t* d_visits,
+                int* is_float) {
   if (n < 0 || k < 1 || nq < 0 || (dtype != KD_I32 && dtype != KD_F32)) return KD_EINVAL;
   if (n > KD_MAX_N || k > KD_MAX_K || nq > KD_MAX_QUERIES) return KD_EUNSUPPORTED;
-  if (!d_tuples || !d_perm || !d_n_nodes) return KD_EINVAL;
-  if (!kd::aligned4(d_tuples) || !kd::aligned4(d_perm) ||
+  if (!d_nodes || !d_n_nodes || (need_perm && !d_perm)) return KD_EINVAL;
+  if (!kd::aligned4(d_nodes) || !kd::aligned4(d_perm) ||
       (reinterpret_cast<uintptr_t>(d_n_nodes) & 7u) || (reinterpret_cast<uintptr_t>(d_visits) & 7u))
     return KD_EINVAL;
   *is_float = dtype == KD_F32;
@@ -964,29 +966,40 @@ int check_query(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, const
 }
 }  // namespace
 
-int kd_region_count(const void* d_tuples, int64_t n, int32_t k, int32_t dtype,
-                    const int32_t* d_perm, const int64_t* d_n_nodes, const void* d_lower,
-                    const void* d_upper, int64_t nq, int32_t* d_counts, uint64_t* d_visits,
-                    void* stream) {
+int kd_gather_nodes(const void* d_tuples, int64_t n, int32_t k, int32_t dtype,
+                    const int32_t* d_perm, const int64_t* d_n_nodes, void* d_nodes, void* stream) {
   int fl = 0;
-  int rc = check_query(d_tuples, n, k, dtype, d_perm, d_n_nodes, nq, d_visits, &fl);
+  int rc = check_query(d_tuples, n, k, dtype, d_perm, true, d_n_nodes, 0, nullptr, &fl);
+  if (rc != KD_OK) return rc;
+  if (n == 0) return KD_OK;
+  if (!d_nodes || !kd::aligned4(d_nodes)) return KD_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  KD_QLAUNCH(kd::launch_gather_nodes(d_tuples, n, k, fl, d_perm, d_n_nodes, d_nodes, st));
+  return KD_OK;
+}
+
+int kd_region_count(const void* d_nodes, int64_t n, int32_t k, int32_t dtype,
+                    const int64_t* d_n_nodes, const void* d_lower, const void* d_upper, int64_t nq,
+                    int32_t* d_counts, uint64_t* d_visits, void* stream) {
+  int fl = 0;
+  int rc = check_query(d_nodes, n, k, dtype, nullptr, false, d_n_nodes, nq, d_visits, &fl);
   if (rc != KD_OK) return rc;
   if (nq == 0) return KD_OK;
   if (!d_lower || !d_upper || !d_counts) return KD_EINVAL;
   if (!kd::aligned4(d_lower) || !kd::aligned4(d_upper) || !kd::aligned4(d_counts)) return KD_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  KD_QLAUNCH( kd::launch_region(d_tuples, n, k, fl, d_perm, d_n_nodes, d_lower, d_upper,
-                                          nq, d_counts, nullptr, nullptr, 0,
-                                          reinterpret_cast<unsigned long long*>(d_visits), st));
+  KD_QLAUNCH(kd::launch_region(d_nodes, n, k, fl, nullptr, d_n_nodes, d_lower, d_upper, nq,
+                               d_counts, nullptr, nullptr, 0,
+                               reinterpret_cast<unsigned long long*>(d_visits), st));
   return KD_OK;
 }
 
-int kd_region_rows(const void* d_tuples, int64_t n, int32_t k, int32_t dtype,
+int kd_region_rows(const void* d_nodes, int64_t n, int32_t k, int32_t dtype,
                    const int32_t* d_perm, const int64_t* d_n_nodes, const void* d_lower,
                    const void* d_upper, int64_t nq, const int64_t* d_offsets, int32_t* d_rows,
                    int64_t rows_capacity, uint64_t* d_visits, void* stream) {
   int fl = 0;
-  int rc = check_query(d_tuples, n, k, dtype, d_perm, d_n_nodes, nq, d_visits, &fl);
+  int rc = check_query(d_nodes, n, k, dtype, d_perm, true, d_n_nodes, nq, d_visits, &fl);
   if (rc != KD_OK) return rc;
   if (rows_capacity < 0) return KD_EINVAL;
   if (nq == 0) return KD_OK;
@@ -996,26 +1009,25 @@ int kd_region_rows(const void* d_tuples, int64_t n, int32_t k, int32_t dtype,
     return KD_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   // a null row buffer (capacity 0) still walks: nothing is written
-  KD_QLAUNCH( kd::launch_region(d_tuples, n, k, fl, d_perm, d_n_nodes, d_lower, d_upper,
-                                          nq, nullptr, d_offsets, d_rows, rows_capacity,
-                                          reinterpret_cast<unsigned long long*>(d_visits), st));
+  KD_QLAUNCH(kd::launch_region(d_nodes, n, k, fl, d_perm, d_n_nodes, d_lower, d_upper, nq,
+                               nullptr, d_offsets, d_rows, rows_capacity,
+                               reinterpret_cast<unsigned long long*>(d_visits), st));
   return KD_OK;
 }
 
-int kd_nearest(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, const int32_t* d_perm,
+int kd_nearest(const void* d_nodes, int64_t n, int32_t k, int32_t dtype, const int32_t* d_perm,
                const int64_t* d_n_nodes, const void* d_points, int64_t nq, int32_t m,
                int32_t* d_rows, uint64_t* d_visits, void* stream) {
   int fl = 0;
-  int rc = check_query(d_tuples, n, k, dtype, d_perm, d_n_nodes, nq, d_visits, &fl);
+  int rc = check_query(d_nodes, n, k, dtype, d_perm, true, d_n_nodes, nq, d_visits, &fl);
   if (rc != KD_OK) return rc;
   if (m < 1 || m > KD_MAX_NEIGHBORS) return KD_EINVAL;
   if (nq == 0) return KD_OK;
   if (!d_points || !d_rows) return KD_EINVAL;
   if (!kd::aligned4(d_points) || !kd::aligned4(d_rows)) return KD_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  KD_QLAUNCH( kd::launch_nearest(d_tuples, n, k, fl, d_perm, d_n_nodes, d_points, nq, m,
-                                           d_rows, reinterpret_cast<unsigned long long*>(d_visits),
-                                           st));
+  KD_QLAUNCH(kd::launch_nearest(d_nodes, n, k, fl, d_perm, d_n_nodes, d_points, nq, m, d_rows,
+                                reinterpret_cast<unsigned long long*>(d_visits), st));
   return KD_OK;
 }
 

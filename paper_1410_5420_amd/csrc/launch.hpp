@@ -221,17 +221,21 @@ hipError_t launch_copy_i32(const int32_t* src, int count, int32_t* dst, hipStrea
 // ---- queries over a built tree (queries.hip) ---------------------------------------
 
 constexpr int kMaxNeighbors = 64;
-// Box queries over the *nn nodes (device count) of the in-order layout perm:
-// counts[q] (offsets == null), or the rows of query q written from
-// rows[offsets[q]] in increasing tree position (no write at or past cap).
-// visits: null, or a counter that receives the number of nodes visited.
-hipError_t launch_region(const void* tuples, int64_t n, int k, int is_float, const int32_t* perm,
+// nodes[pos][d] = tuples[perm[pos]][d] for the *nn (device count) nodes.
+hipError_t launch_gather_nodes(const void* tuples, int64_t n, int k, int is_float,
+                               const int32_t* perm, const int64_t* nn, void* nodes, hipStream_t st);
+// Box queries over the *nn nodes whose coordinates `nodes` holds in tree
+// position order: counts[q] (offsets == null), or the rows (perm entries) of
+// query q written from rows[offsets[q]] in increasing tree position (no write
+// at or past cap).  visits: null, or a counter that receives the number of
+// nodes visited.
+hipError_t launch_region(const void* nodes, int64_t n, int k, int is_float, const int32_t* perm,
                          const int64_t* nn, const void* lower, const void* upper, int64_t nq,
                          int32_t* counts, const int64_t* offsets, int32_t* rows, int64_t cap,
                          unsigned long long* visits, hipStream_t st);
 // The m (1 .. kMaxNeighbors) nodes smallest in (squared distance, row) of
 // every query point, ascending, -1 past the node count: rows[q * m + i].
-hipError_t launch_nearest(const void* tuples, int64_t n, int k, int is_float, const int32_t* perm,
+hipError_t launch_nearest(const void* nodes, int64_t n, int k, int is_float, const int32_t* perm,
                           const int64_t* nn, const void* points, int64_t nq, int32_t m, int32_t* rows,
                           unsigned long long* visits, hipStream_t st);
 

@@ -136,28 +136,40 @@ def test_queries_reject_bad_arguments(L):
     never dereferenced)."""
     vp = ctypes.c_void_p
     F, F8 = vp(FAKE), vp(FAKE8)
+    # gathering the node coordinates: bad k, dtype, n; null perm, count, output
+    assert L.lib.kd_gather_nodes(F, 100, 0, 0, F, F8, F, None) == -1
+    assert L.lib.kd_gather_nodes(F, 100, 9, 0, F, F8, F, None) == -4
+    assert L.lib.kd_gather_nodes(F, 100, 3, 2, F, F8, F, None) == -1
+    assert L.lib.kd_gather_nodes(F, -1, 3, 0, F, F8, F, None) == -1
+    assert L.lib.kd_gather_nodes(F, 100, 3, 0, None, F8, F, None) == -1
+    assert L.lib.kd_gather_nodes(F, 100, 3, 0, F, None, F, None) == -1
+    assert L.lib.kd_gather_nodes(F, 100, 3, 0, F, F8, None, None) == -1
+    assert L.lib.kd_gather_nodes(F, 100, 3, 0, F, vp(FAKE8 + 4), F, None) == -1
+    assert L.lib.kd_gather_nodes(F, 0, 3, 0, F, F8, None, None) == 0  # no rows: nothing to do
     # region counts: bad k, dtype, n, nq; null and misaligned pointers
-    assert L.lib.kd_region_count(F, 100, 0, 0, F, F8, F, F, 10, F, None, None) == -1
-    assert L.lib.kd_region_count(F, 100, 9, 0, F, F8, F, F, 10, F, None, None) == -4
-    assert L.lib.kd_region_count(F, 100, 3, 2, F, F8, F, F, 10, F, None, None) == -1
-    assert L.lib.kd_region_count(F, -1, 3, 0, F, F8, F, F, 10, F, None, None) == -1
-    assert L.lib.kd_region_count(F, 100, 3, 0, F, F8, F, F, -1, F, None, None) == -1
-    assert L.lib.kd_region_count(F, 100, 3, 0, F, F8, F, F, (1 << 28) + 1, F, None, None) == -4
-    assert L.lib.kd_region_count(F, 100, 3, 0, None, F8, F, F, 10, F, None, None) == -1
-    assert L.lib.kd_region_count(F, 100, 3, 0, F, None, F, F, 10, F, None, None) == -1
-    assert L.lib.kd_region_count(F, 100, 3, 0, F, F8, None, F, 10, F, None, None) == -1
-    assert L.lib.kd_region_count(F, 100, 3, 0, F, F8, F, F, 10, None, None, None) == -1
-    assert L.lib.kd_region_count(vp(FAKE + 2), 100, 3, 0, F, F8, F, F, 10, F, None, None) == -1
-    assert L.lib.kd_region_count(F, 100, 3, 0, F, vp(FAKE8 + 4), F, F, 10, F, None, None) == -1
-    assert L.lib.kd_region_count(F, 100, 3, 0, F, F8, F, F, 10, F, vp(FAKE8 + 4), None) == -1
+    assert L.lib.kd_region_count(F, 100, 0, 0, F8, F, F, 10, F, None, None) == -1
+    assert L.lib.kd_region_count(F, 100, 9, 0, F8, F, F, 10, F, None, None) == -4
+    assert L.lib.kd_region_count(F, 100, 3, 2, F8, F, F, 10, F, None, None) == -1
+    assert L.lib.kd_region_count(F, -1, 3, 0, F8, F, F, 10, F, None, None) == -1
+    assert L.lib.kd_region_count(F, 100, 3, 0, F8, F, F, -1, F, None, None) == -1
+    assert L.lib.kd_region_count(F, 100, 3, 0, F8, F, F, (1 << 28) + 1, F, None, None) == -4
+    assert L.lib.kd_region_count(None, 100, 3, 0, F8, F, F, 10, F, None, None) == -1
+    assert L.lib.kd_region_count(F, 100, 3, 0, None, F, F, 10, F, None, None) == -1
+    assert L.lib.kd_region_count(F, 100, 3, 0, F8, None, F, 10, F, None, None) == -1
+    assert L.lib.kd_region_count(F, 100, 3, 0, F8, F, F, 10, None, None, None) == -1
+    assert L.lib.kd_region_count(vp(FAKE + 2), 100, 3, 0, F8, F, F, 10, F, None, None) == -1
+    assert L.lib.kd_region_count(F, 100, 3, 0, vp(FAKE8 + 4), F, F, 10, F, None, None) == -1
+    assert L.lib.kd_region_count(F, 100, 3, 0, F8, F, F, 10, F, vp(FAKE8 + 4), None) == -1
     # no queries: nothing to do
-    assert L.lib.kd_region_count(F, 100, 3, 0, F, F8, None, None, 0, None, None, None) == 0
-    # region rows: negative capacity, null offsets, rows null with a capacity
+    assert L.lib.kd_region_count(F, 100, 3, 0, F8, None, None, 0, None, None, None) == 0
+    # region rows: null perm, negative capacity, null offsets, rows null with a capacity
+    assert L.lib.kd_region_rows(F, 100, 3, 0, None, F8, F, F, 10, F8, F, 10, None, None) == -1
     assert L.lib.kd_region_rows(F, 100, 3, 0, F, F8, F, F, 10, F8, F, -1, None, None) == -1
     assert L.lib.kd_region_rows(F, 100, 3, 0, F, F8, F, F, 10, None, F, 10, None, None) == -1
     assert L.lib.kd_region_rows(F, 100, 3, 0, F, F8, F, F, 10, F8, None, 10, None, None) == -1
     assert L.lib.kd_region_rows(F, 100, 3, 0, F, F8, F, F, 10, vp(FAKE8 + 4), F, 10, None, None) == -1
-    # nearest: m out of range, null points or rows
+    # nearest: null perm, m out of range, null points or rows
+    assert L.lib.kd_nearest(F, 100, 3, 0, None, F8, F, 10, 4, F, None, None) == -1
     assert L.lib.kd_nearest(F, 100, 3, 0, F, F8, F, 10, 0, F, None, None) == -1
     assert L.lib.kd_nearest(F, 100, 3, 0, F, F8, F, 10, 65, F, None, None) == -1
     assert L.lib.kd_nearest(F, 100, 3, 0, F, F8, None, 10, 4, F, None, None) == -1

@@ -92,8 +92,11 @@ def check_region(kd, t, dt, perm, nu, lo, hi, with_oracle=True):
     pos = np.empty(t.shape[0], dtype=np.int64)
     pos[p] = np.arange(nu)
     dlo, dhi = torch.from_numpy(lo).cuda(), torch.from_numpy(hi).cuda()
-    counts = kd.region_count(dt, perm, nu, dlo, dhi).cpu().numpy()
-    rows, offs = kd.region_rows(dt, perm, nu, dlo, dhi)
+    nodes = kd.gather_nodes(dt, perm, nu)
+    assert np.array_equal(nodes[:nu].cpu().numpy(), t[p])
+    counts = kd.region_count(dt, perm, nu, dlo, dhi, nodes=nodes).cpu().numpy()
+    assert np.array_equal(kd.region_count(dt, perm, nu, dlo, dhi).cpu().numpy(), counts)
+    rows, offs = kd.region_rows(dt, perm, nu, dlo, dhi, nodes=nodes)
     rows, offs = rows.cpu().numpy(), offs.cpu().numpy()
     assert np.array_equal(np.diff(offs), counts)
     nodes = t[p]
