@@ -363,6 +363,22 @@ def queries_c2(torch, kd, _lib, kdgen, t, t_host, perm, n_nodes, nu, args):
                      "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
         log(f"queries {name}: {ms:.3f} ms per 2^20, {per_query:.1f} visits per query")
     res["box_mean_count"] = round(float(outs["box_count"].float().mean().item()), 2)
+    # every node as a query (m = 8, itself excluded), then the reverse lists
+    visits.zero_()
+    _lib.probe_start("query", 1)
+    near = kd.all_nearest(t, perm, n_nodes, 8, visits=visits, nodes=nodes)
+    torch.cuda.synchronize()
+    all_ms = float(_lib.probe_stop(1)[0])
+    all_visits = int(visits.item()) / nu
+    _lib.probe_start("query", 1)
+    offs, _lists = kd.reverse_nearest(perm, n_nodes, near)
+    torch.cuda.synchronize()
+    rev_ms = float(_lib.probe_stop(1)[0])
+    res["all_nearest_m8"] = {"ms": round(all_ms, 3), "nodes_per_s": round(nu / (all_ms * 1e-3), 1),
+                             "visits_per_query": round(all_visits, 2)}
+    res["reverse_lists"] = {"ms": round(rev_ms, 3), "entries": int(offs[-1].item())}
+    log(f"queries all nearest: {all_ms:.2f} ms over {nu} nodes; reverse lists {rev_ms:.2f} ms")
+    del near, offs, _lists
     # spot check against the oracle on a few queries
     from oracle import queries as oq
 

@@ -270,6 +270,28 @@ int kd_nearest(const void* d_nodes, int64_t n, int32_t k, int32_t dtype, const i
                const int64_t* d_n_nodes, const void* d_points, int64_t nq, int32_t m,
                int32_t* d_rows, uint64_t* d_visits, void* stream);
 
+/* All-points nearest neighbours (Appendix, "Nearest Neighbors": every point
+ * of the tree taken as a query point): for node position pos < n_nodes,
+ * d_rows[pos * m + i] (int32[n * m]) receives the rows of the m other nodes
+ * smallest in (distance, row), in that order, and -1 past n_nodes - 1; a node
+ * is not its own neighbour.  Rows of positions >= n_nodes are left
+ * untouched.  n <= KD_MAX_QUERIES. */
+int kd_all_nearest(const void* d_nodes, int64_t n, int32_t k, int32_t dtype, const int32_t* d_perm,
+                   const int64_t* d_n_nodes, int32_t m, int32_t* d_rows, uint64_t* d_visits,
+                   void* stream);
+/* Reverse nearest neighbours (the same Appendix section: the points to which
+ * a point is a nearest neighbour) from kd_all_nearest's output: the list of
+ * row r is d_lists[d_offsets[r]] .. d_lists[d_offsets[r + 1] - 1], the rows
+ * of the nodes that have r among their m nearest, in ascending order.
+ *   d_offsets   int64[n + 1] over row ids 0 .. n-1 (a row that is no node
+ *               has an empty list)
+ *   d_lists     int32[n * m] (at most n_nodes * m entries are written)
+ *   d_workspace >= kd_reverse_workspace_bytes(n), 8-byte aligned        */
+int kd_reverse_workspace_bytes(int64_t n, size_t* h_bytes);
+int kd_reverse_nearest(const int32_t* d_perm, const int64_t* d_n_nodes, int64_t n, int32_t m,
+                       const int32_t* d_rows, int64_t* d_offsets, int32_t* d_lists,
+                       void* d_workspace, size_t workspace_bytes, void* stream);
+
 /* ---- diagnostics ------------------------------------------------------------
  * Kernel probe for measurement tools.  kd_probe_start() makes the library
  * record a HIP event pair around every launch of one kernel class (on the

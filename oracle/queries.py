@@ -65,9 +65,10 @@ def region_search(tuples: np.ndarray, perm: np.ndarray, lower, upper):
     return sorted(found)
 
 
-def nearest_neighbors(tuples: np.ndarray, perm: np.ndarray, query, m: int):
+def nearest_neighbors(tuples: np.ndarray, perm: np.ndarray, query, m: int, exclude=None):
     """The m nearest tree nodes to ``query`` as ``[(sq_distance, row), ...]``
-    in increasing distance, found with a bounded max-priority queue."""
+    in increasing distance, found with a bounded max-priority queue.  The node
+    of row ``exclude`` (if given) is not a candidate."""
     pts = _coords(tuples)
     k = tuples.shape[1]
     q = tuple(query)
@@ -83,7 +84,9 @@ def nearest_neighbors(tuples: np.ndarray, perm: np.ndarray, query, m: int):
         row = int(perm[mid])
         x = pts[row]
         dist = sqd(x)
-        if len(heap) < m:
+        if row == exclude:
+            pass
+        elif len(heap) < m:
             heapq.heappush(heap, (-dist, -row))
         elif dist < -heap[0][0]:
             heapq.heapreplace(heap, (-dist, -row))
@@ -96,3 +99,22 @@ def nearest_neighbors(tuples: np.ndarray, perm: np.ndarray, query, m: int):
 
     visit(0, len(perm) - 1, 0)
     return sorted((-d, -r) for d, r in heap)
+
+
+def all_nearest(tuples: np.ndarray, perm: np.ndarray, m: int):
+    """Every node's m nearest other nodes (Appendix, "Nearest Neighbors":
+    each point of the tree taken as a query point), as one list of
+    ``[(sq_distance, row), ...]`` per tree position."""
+    return [nearest_neighbors(tuples, perm, tuples[int(r)].tolist(), m, exclude=int(r))
+            for r in perm]
+
+
+def reverse_lists(perm: np.ndarray, near_rows):
+    """Reverse nearest neighbours: for every row, the rows of the nodes that
+    have it among their nearest (``near_rows[pos]``: the neighbour rows of
+    the node at tree position pos), ascending."""
+    out = {}
+    for pos, rows in enumerate(near_rows):
+        for r in rows:
+            out.setdefault(int(r), []).append(int(perm[pos]))
+    return {r: sorted(v) for r, v in out.items()}

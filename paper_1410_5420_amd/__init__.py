@@ -19,7 +19,7 @@ from ._lib import KD_F32, KD_I32, KdError  # noqa: F401
 
 __all__ = ["Builder", "BatchedBuilder", "LearnedBuilder", "build", "build_batched", "build_learned",
            "train_cdf", "cdf_loss_grad", "cdf_eval", "gather_nodes", "region_count", "region_rows",
-           "nearest", "KdError"]
+           "nearest", "all_nearest", "reverse_nearest", "KdError"]
 
 
 def _dtype_code(t: torch.Tensor) -> int:
@@ -252,6 +252,39 @@ def nearest(tuples: torch.Tensor, perm: torch.Tensor, n_nodes, points: torch.Ten
     _lib.check(_lib.lib.kd_nearest(_ptr(nodes), n, k, code, _ptr(perm), _ptr(nn), _ptr(points), nq,
                                    int(m), _ptr(rows), _ptr(visits), _stream(stream)), "kd_nearest")
     return rows
+
+
+def all_nearest(tuples: torch.Tensor, perm: torch.Tensor, n_nodes, m: int,
+                visits: torch.Tensor | None = None, nodes=None, stream=None):
+    """Every tree node's m nearest other nodes (kd_all_nearest): an (n, m)
+    int32 tensor whose row pos (a tree position) lists rows in increasing
+    (squared distance, row); -1 past the node count, rows past it unset."""
+    n, k, code, nn = _query_args(tuples, perm, n_nodes, tuples[:0])
+    if nodes is None:
+        nodes = gather_nodes(tuples, perm, nn, stream)
+    rows = torch.full((n, m), -1, dtype=torch.int32, device=tuples.device)
+    _lib.check(_lib.lib.kd_all_nearest(_ptr(nodes), n, k, code, _ptr(perm), _ptr(nn), int(m),
+                                       _ptr(rows), _ptr(visits), _stream(stream)), "kd_all_nearest")
+    return rows
+
+
+def reverse_nearest(perm: torch.Tensor, n_nodes, near_rows: torch.Tensor, stream=None):
+    """Reverse nearest-neighbour lists from ``all_nearest``'s output
+    (kd_reverse_nearest): ``(offsets, lists)`` with the list of row r in
+    ``lists[offsets[r]:offsets[r + 1]]``, ascending."""
+    n, m = near_rows.shape
+    if not torch.is_tensor(n_nodes):
+        n_nodes = torch.tensor([int(n_nodes)], dtype=torch.int64, device=near_rows.device)
+    nn = n_nodes.reshape(1).to(torch.int64).contiguous()
+    ws = torch.empty(_lib._size("kd_reverse_workspace_bytes", n), dtype=torch.uint8,
+                     device=near_rows.device)
+    offsets = torch.empty(n + 1, dtype=torch.int64, device=near_rows.device)
+    lists = torch.empty(max(n * m, 1), dtype=torch.int32, device=near_rows.device)
+    _lib.check(_lib.lib.kd_reverse_nearest(_ptr(perm), _ptr(nn), n, int(m),
+                                           _ptr(near_rows.contiguous()), _ptr(offsets), _ptr(lists),
+                                           _ptr(ws), ws.numel(), _stream(stream)),
+               "kd_reverse_nearest")
+    return offsets, lists
 
 
 # ---- learned presort ------------------------------------------------------------

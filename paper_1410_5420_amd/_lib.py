@@ -74,6 +74,12 @@ def _load():
     lib.kd_region_rows.restype = ctypes.c_int
     lib.kd_nearest.argtypes = [vp, i64, i32, i32, vp, vp, vp, i64, i32, vp, vp, vp]
     lib.kd_nearest.restype = ctypes.c_int
+    lib.kd_all_nearest.argtypes = [vp, i64, i32, i32, vp, vp, i32, vp, vp, vp]
+    lib.kd_all_nearest.restype = ctypes.c_int
+    lib.kd_reverse_workspace_bytes.argtypes = [i64, ctypes.POINTER(sz)]
+    lib.kd_reverse_workspace_bytes.restype = ctypes.c_int
+    lib.kd_reverse_nearest.argtypes = [vp, vp, i64, i32, vp, vp, vp, vp, sz, vp]
+    lib.kd_reverse_nearest.restype = ctypes.c_int
     lib.kd_probe_start.argtypes = [i32, i32]
     lib.kd_probe_start.restype = ctypes.c_int
     lib.kd_probe_stop.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int32)]
@@ -89,7 +95,8 @@ EXPORTED = ["kd_strerror", "kdtree_workspace_bytes", "kdtree_build", "kdtree_pre
             "kd_cdf_model_bytes", "kd_cdf_train_workspace_bytes", "kd_cdf_train",
             "kd_cdf_loss_grad", "kd_cdf_eval", "kdtree_workspace_bytes_learned",
             "kdtree_build_learned", "kdtree_presort_learned", "kd_gather_nodes", "kd_region_count",
-            "kd_region_rows", "kd_nearest", "kd_probe_start", "kd_probe_stop"]
+            "kd_region_rows", "kd_nearest", "kd_all_nearest", "kd_reverse_workspace_bytes",
+            "kd_reverse_nearest", "kd_probe_start", "kd_probe_stop"]
 
 KERNEL_CLASSES = {"onesweep": 1, "level": 2, "leaf": 3, "dedup": 4, "hist": 5, "canon": 6,
                   "records": 7, "bucket": 8, "ties": 9, "query": 10}

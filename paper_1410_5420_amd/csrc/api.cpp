@@ -1031,6 +1031,47 @@ int kd_nearest(const void* d_nodes, int64_t n, int32_t k, int32_t dtype, const i
   return KD_OK;
 }
 
+int kd_all_nearest(const void* d_nodes, int64_t n, int32_t k, int32_t dtype, const int32_t* d_perm,
+                   const int64_t* d_n_nodes, int32_t m, int32_t* d_rows, uint64_t* d_visits,
+                   void* stream) {
+  int fl = 0;
+  int rc = check_query(d_nodes, n, k, dtype, d_perm, true, d_n_nodes, 0, d_visits, &fl);
+  if (rc != KD_OK) return rc;
+  if (m < 1 || m > KD_MAX_NEIGHBORS) return KD_EINVAL;
+  if (n > KD_MAX_QUERIES) return KD_EUNSUPPORTED;
+  if (n == 0) return KD_OK;
+  if (!d_rows || !kd::aligned4(d_rows)) return KD_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  KD_QLAUNCH(kd::launch_nearest(d_nodes, n, k, fl, d_perm, d_n_nodes, nullptr, n, m, d_rows,
+                                reinterpret_cast<unsigned long long*>(d_visits), st));
+  return KD_OK;
+}
+
+int kd_reverse_workspace_bytes(int64_t n, size_t* h_bytes) {
+  if (!h_bytes || n < 0) return KD_EINVAL;
+  if (n > KD_MAX_N) return KD_EUNSUPPORTED;
+  *h_bytes = kd::reverse_workspace_bytes(n);
+  return KD_OK;
+}
+
+int kd_reverse_nearest(const int32_t* d_perm, const int64_t* d_n_nodes, int64_t n, int32_t m,
+                       const int32_t* d_rows, int64_t* d_offsets, int32_t* d_lists,
+                       void* d_workspace, size_t workspace_bytes, void* stream) {
+  if (n < 0 || m < 1 || m > KD_MAX_NEIGHBORS) return KD_EINVAL;
+  if (n > KD_MAX_N) return KD_EUNSUPPORTED;
+  if (n == 0) return KD_OK;
+  if (!d_perm || !d_n_nodes || !d_rows || !d_offsets || !d_lists || !d_workspace) return KD_EINVAL;
+  if (!kd::aligned4(d_perm) || !kd::aligned4(d_rows) || !kd::aligned4(d_lists) ||
+      (reinterpret_cast<uintptr_t>(d_n_nodes) & 7u) || (reinterpret_cast<uintptr_t>(d_offsets) & 7u) ||
+      (reinterpret_cast<uintptr_t>(d_workspace) & 7u))
+    return KD_EINVAL;
+  if (workspace_bytes < kd::reverse_workspace_bytes(n)) return KD_ENOMEM;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  KD_QLAUNCH(kd::launch_reverse_nearest(d_perm, d_n_nodes, n, m, d_rows, d_offsets, d_lists,
+                                        d_workspace, st));
+  return KD_OK;
+}
+
 int kd_probe_start(int32_t kernel_class, int32_t capacity) {
   if (kernel_class < KD_K_ONESWEEP || kernel_class > KD_K_QUERY || capacity < 1 ||
       capacity > (1 << 20))

@@ -235,9 +235,20 @@ hipError_t launch_region(const void* nodes, int64_t n, int k, int is_float, cons
                          unsigned long long* visits, hipStream_t st);
 // The m (1 .. kMaxNeighbors) nodes smallest in (squared distance, row) of
 // every query point, ascending, -1 past the node count: rows[q * m + i].
+// points == null: the queries are the nodes themselves (nq = n; query q is
+// node position q, rows of positions past the count are left alone), and a
+// node is not its own neighbour.
 hipError_t launch_nearest(const void* nodes, int64_t n, int k, int is_float, const int32_t* perm,
                           const int64_t* nn, const void* points, int64_t nq, int32_t m, int32_t* rows,
                           unsigned long long* visits, hipStream_t st);
+
+// Reverse lists from launch_nearest's all-nodes output (rows, n * m): the
+// list of row r is lists[offsets[r] .. offsets[r + 1] - 1], ascending
+// (offsets: n + 1 words).  ws: reverse_workspace_bytes(n) bytes.
+size_t reverse_workspace_bytes(int64_t n);
+hipError_t launch_reverse_nearest(const int32_t* perm, const int64_t* nn, int64_t n, int m,
+                                  const int32_t* rows, int64_t* offsets, int32_t* lists, void* ws,
+                                  hipStream_t st);
 
 // Child positions from the implicit shape of a single tree (uoff[1] rows).
 hipError_t launch_children(const int32_t* uoff, int64_t n, int32_t* lo, int32_t* hi,

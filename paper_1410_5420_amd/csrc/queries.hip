@@ -226,7 +226,9 @@ __device__ __forceinline__ bool bound_above(float b, unsigned __int128 dist) {
 }
 __device__ __forceinline__ bool bound_above(float b, double dist) { return (double)b > dist; }
 
-template <typename T, int K, int kM>
+// kSelf: the queries are the tree's own nodes (query q is the node at
+// position q < the node count), and a node is not its own neighbour.
+template <typename T, int K, int kM, bool kSelf>
 __global__ __launch_bounds__(kQThreads) void k_nearest(
     const T* __restrict__ nodes, int64_t n, const int32_t* __restrict__ perm,
     const int64_t* __restrict__ n_nodes, const T* __restrict__ points, int64_t nq,
@@ -235,7 +237,7 @@ __global__ __launch_bounds__(kQThreads) void k_nearest(
   const int64_t q = (int64_t)blockIdx.x * kQThreads + threadIdx.x;
   const int nn = node_count(n_nodes, n);
   uint32_t seen = 0;
-  if (q < nq) {
+  if (q < nq && (!kSelf || q < nn)) {
     T qp[K];
 #pragma unroll
     for (int d = 0; d < K; ++d) qp[d] = points[q * K + d];
@@ -259,8 +261,9 @@ __global__ __launch_bounds__(kQThreads) void k_nearest(
         load_point<T, K>(nodes, mid, x);
         const D dist = sq_dist<T, K>(x, qp);
         // the row (the tie-break) is read only for a possible candidate
-        const int32_t row = dist <= bd[kM - 1] ? perm[mid] : INT32_MAX;
-        if (dist < bd[kM - 1] || (dist == bd[kM - 1] && row < br[kM - 1])) {
+        const bool cand = dist <= bd[kM - 1] && (!kSelf || mid != q);
+        const int32_t row = cand ? perm[mid] : INT32_MAX;
+        if (cand && (dist < bd[kM - 1] || (dist == bd[kM - 1] && row < br[kM - 1]))) {
           // insert, keeping the list sorted (static indices only)
 #pragma unroll
           for (int i = kM - 1; i >= 0; --i) {
@@ -399,12 +402,20 @@ hipError_t launch_region(const void* nodes, int64_t n, int k, int is_float, cons
 hipError_t launch_nearest(const void* nodes, int64_t n, int k, int is_float, const int32_t* perm,
                           const int64_t* nn, const void* points, int64_t nq, int32_t m, int32_t* rows,
                           unsigned long long* visits, hipStream_t st) {
+  const bool self = points == nullptr;  // every node of the tree as a query (nq = n)
   if (nq <= 0) return hipSuccess;
   if (m < 1 || m > kMaxNeighbors) return hipErrorInvalidValue;
 #define KD_NN_M(T, KK, MM)                                                                    \
-  hipLaunchKernelGGL((k_nearest<T, KK, MM>), dim3(query_blocks(nq)), dim3(kQThreads), 0, st,  \
-                     static_cast<const T*>(nodes), n, perm, nn, static_cast<const T*>(points), \
-                     nq, m, rows, visits)
+  do {                                                                                        \
+    if (self)                                                                                 \
+      hipLaunchKernelGGL((k_nearest<T, KK, MM, true>), dim3(query_blocks(nq)), dim3(kQThreads), \
+                         0, st, static_cast<const T*>(nodes), n, perm, nn,                    \
+                         static_cast<const T*>(nodes), nq, m, rows, visits);                  \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_nearest<T, KK, MM, false>), dim3(query_blocks(nq)), dim3(kQThreads), \
+                         0, st, static_cast<const T*>(nodes), n, perm, nn,                    \
+                         static_cast<const T*>(points), nq, m, rows, visits);                 \
+  } while (0)
 #define KD_NN_T(T, KK)                         \
   do {                                         \
     if (m <= 1)                                \
@@ -435,5 +446,148 @@ hipError_t launch_nearest(const void* nodes, int64_t n, int k, int is_float, con
 }
 
 #undef KD_FOR_K
+
+
+// ---- reverse nearest neighbours ---------------------------------------------------
+// From every node's m nearest (rows[pos * m + i], -1 past the count), the
+// reverse list of every row r: the rows of the nodes that have r among their
+// m nearest, as compressed lists (offsets over row ids 0 .. n-1), each in
+// ascending row order.  Counts, a scan of the counts, a fill that claims list
+// slots with atomics, then a sort of every list (they are short: m on
+// average), so the output does not depend on the order of the atomics.
+constexpr int kRevChunk = 4096;  // rows per scan block (256 threads x 16)
+
+__global__ __launch_bounds__(256) void k_rev_count(const int32_t* __restrict__ rows, int64_t n,
+                                                  const int64_t* __restrict__ n_nodes, int m,
+                                                  uint32_t* __restrict__ cnt) {
+  const int64_t total = (int64_t)node_count(n_nodes, n) * m;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t r = rows[i];
+    if ((uint64_t)r < (uint64_t)n) atomicAdd(&cnt[r], 1u);
+  }
+}
+
+// per-chunk sums of the counts
+__global__ __launch_bounds__(256) void k_rev_sums(const uint32_t* __restrict__ cnt, int64_t n,
+                                                 uint64_t* __restrict__ sums) {
+  __shared__ uint64_t s_tmp[256 / kWave + 1];
+  const int64_t base = (int64_t)blockIdx.x * kRevChunk;
+  uint64_t v = 0;
+  for (int i = threadIdx.x; i < kRevChunk; i += 256)
+    if (base + i < n) v += cnt[base + i];
+  uint64_t all;
+  block_exclusive_sum<256>(v, s_tmp, &all);
+  if (threadIdx.x == 0) sums[blockIdx.x] = all;
+}
+
+// one block: exclusive scan of the chunk sums, in place
+__global__ __launch_bounds__(1024) void k_rev_scan_sums(uint64_t* __restrict__ sums, int64_t nb) {
+  __shared__ uint64_t s_tmp[1024 / kWave + 1];
+  __shared__ uint64_t s_carry;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (int64_t b0 = 0; b0 < nb; b0 += 1024) {
+    const int64_t b = b0 + threadIdx.x;
+    const uint64_t v = b < nb ? sums[b] : 0;
+    uint64_t all;
+    const uint64_t ex = block_exclusive_sum<1024>(v, s_tmp, &all);
+    const uint64_t carry = s_carry;
+    if (b < nb) sums[b] = carry + ex;
+    __syncthreads();
+    if (threadIdx.x == 0) s_carry = carry + all;
+    __syncthreads();
+  }
+}
+
+// offsets[r] = chunk start + the counts before r in its chunk; offsets[n] =
+// the total.  Each thread owns 16 consecutive rows of the chunk.
+__global__ __launch_bounds__(256) void k_rev_offsets(const uint32_t* __restrict__ cnt, int64_t n,
+                                                    const uint64_t* __restrict__ sums,
+                                                    int64_t* __restrict__ offsets) {
+  __shared__ uint64_t s_tmp[256 / kWave + 1];
+  constexpr int kPer = kRevChunk / 256;
+  const int64_t r0 = (int64_t)blockIdx.x * kRevChunk + (int64_t)threadIdx.x * kPer;
+  uint32_t c[kPer];
+  uint64_t v = 0;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    c[j] = r0 + j < n ? cnt[r0 + j] : 0u;
+    v += c[j];
+  }
+  uint64_t all;
+  uint64_t run = sums[blockIdx.x] + block_exclusive_sum<256>(v, s_tmp, &all);
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    if (r0 + j < n) offsets[r0 + j] = (int64_t)run;
+    run += c[j];
+  }
+  if (r0 < n && r0 + kPer >= n) offsets[n] = (int64_t)run;  // the thread holding the last row
+}
+
+__global__ __launch_bounds__(256) void k_rev_fill(const int32_t* __restrict__ rows, int64_t n,
+                                                 const int32_t* __restrict__ perm,
+                                                 const int64_t* __restrict__ n_nodes, int m,
+                                                 const int64_t* __restrict__ offsets,
+                                                 uint32_t* __restrict__ cursor,
+                                                 int32_t* __restrict__ lists) {
+  const int64_t total = (int64_t)node_count(n_nodes, n) * m;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t r = rows[i];
+    if ((uint64_t)r >= (uint64_t)n) continue;
+    const uint32_t slot = atomicAdd(&cursor[r], 1u);
+    const int64_t at = offsets[r] + slot;
+    if (at < offsets[r + 1]) lists[at] = perm[i / m];  // the querying node's row
+  }
+}
+
+// every list in ascending order (insertion sort by one thread)
+__global__ __launch_bounds__(256) void k_rev_sort(int64_t n, const int64_t* __restrict__ offsets,
+                                                 int32_t* __restrict__ lists) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = offsets[r], b = offsets[r + 1];
+    for (int64_t i = a + 1; i < b; ++i) {
+      const int32_t v = lists[i];
+      int64_t j = i - 1;
+      while (j >= a && lists[j] > v) {
+        lists[j + 1] = lists[j];
+        --j;
+      }
+      lists[j + 1] = v;
+    }
+  }
+}
+
+size_t reverse_workspace_bytes(int64_t n) {
+  const int64_t nb = (n + kRevChunk - 1) / kRevChunk;
+  return (size_t)(4 * n + 255) / 256 * 256 + (size_t)8 * (nb > 0 ? nb : 1);
+}
+
+hipError_t launch_reverse_nearest(const int32_t* perm, const int64_t* nn, int64_t n, int m,
+                                  const int32_t* rows, int64_t* offsets, int32_t* lists, void* ws,
+                                  hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  uint32_t* cnt = static_cast<uint32_t*>(ws);
+  uint64_t* sums = reinterpret_cast<uint64_t*>(static_cast<char*>(ws) + (4 * n + 255) / 256 * 256);
+  const int64_t nb = (n + kRevChunk - 1) / kRevChunk;
+  int64_t g = (n * m + 255) / 256;
+  if (g > 16384) g = 16384;
+  int64_t gs = (n + 255) / 256;
+  if (gs > 16384) gs = 16384;
+  hipError_t e = launch_fill_u32(cnt, 0u, n, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rev_count, dim3((unsigned)g), dim3(256), 0, st, rows, n, nn, m, cnt);
+  hipLaunchKernelGGL(k_rev_sums, dim3((unsigned)nb), dim3(256), 0, st, cnt, n, sums);
+  hipLaunchKernelGGL(k_rev_scan_sums, dim3(1), dim3(1024), 0, st, sums, nb);
+  hipLaunchKernelGGL(k_rev_offsets, dim3((unsigned)nb), dim3(256), 0, st, cnt, n, sums, offsets);
+  e = launch_fill_u32(cnt, 0u, n, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rev_fill, dim3((unsigned)g), dim3(256), 0, st, rows, n, perm, nn, m, offsets,
+                     cnt, lists);
+  hipLaunchKernelGGL(k_rev_sort, dim3((unsigned)gs), dim3(256), 0, st, n, offsets, lists);
+  return hipGetLastError();
+}
 
 }  // namespace kd

@@ -176,3 +176,22 @@ def test_queries_reject_bad_arguments(L):
     assert L.lib.kd_nearest(F, 100, 3, 0, F, F8, F, 10, 4, None, None, None) == -1
     assert L.lib.kd_nearest(F, 100, 3, 1, F, F8, F, 0, 4, None, None, None) == 0
     assert L.lib.kd_probe_start(11, 10) == -1
+
+
+def test_all_nearest_and_reverse_reject_bad_arguments(L):
+    vp = ctypes.c_void_p
+    F, F8 = vp(FAKE), vp(FAKE8)
+    out = ctypes.c_size_t(0)
+    assert L.lib.kd_all_nearest(F, 100, 3, 0, F, F8, 0, F, None, None) == -1
+    assert L.lib.kd_all_nearest(F, 100, 3, 0, F, F8, 65, F, None, None) == -1
+    assert L.lib.kd_all_nearest(F, 100, 3, 0, None, F8, 4, F, None, None) == -1
+    assert L.lib.kd_all_nearest(F, 100, 3, 0, F, F8, 4, None, None, None) == -1
+    assert L.lib.kd_all_nearest(F, 0, 3, 0, F, F8, 4, None, None, None) == 0
+    assert L.lib.kd_reverse_workspace_bytes(-1, ctypes.byref(out)) == -1
+    assert L.lib.kd_reverse_workspace_bytes(1 << 20, ctypes.byref(out)) == 0 and out.value >= 4 << 20
+    need = out.value
+    assert L.lib.kd_reverse_nearest(F, F8, 1 << 20, 0, F, F8, F, F8, need, None) == -1
+    assert L.lib.kd_reverse_nearest(None, F8, 1 << 20, 4, F, F8, F, F8, need, None) == -1
+    assert L.lib.kd_reverse_nearest(F, F8, 1 << 20, 4, F, vp(FAKE8 + 4), F, F8, need, None) == -1
+    assert L.lib.kd_reverse_nearest(F, F8, 1 << 20, 4, F, F8, F, F8, need - 8, None) == -2
+    assert L.lib.kd_reverse_nearest(F, F8, 0, 4, None, None, None, None, 0, None) == 0

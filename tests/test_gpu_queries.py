@@ -233,3 +233,37 @@ def brute_nearest_fast(t, nodes, q, m):
     approx = ((x - q.astype(np.float64)) ** 2).sum(axis=1)
     cand = nodes[np.argsort(approx, kind="stable")[:max(64, 8 * m)]]
     return brute_nearest(t, cand, q, m)
+
+
+@pytest.mark.parametrize("k,dtype,n", [(3, "i32", 700), (2, "f32", 600), (5, "i32", 500),
+                                       (3, "i32", 1)])
+def test_all_nearest_and_reverse(kd, k, dtype, n):
+    g = kdgen.rng(970 + k + n)
+    if dtype == "i32":
+        t = kdgen.uniform_int(n, k, -2**31, 2**31, 0.05, 971 + k)
+    else:
+        t = g.normal(size=(n, k)).astype(np.float32)
+    print(f"[gpu case] all nearest k={k} dtype={dtype} n={n}", flush=True)
+    dt, perm, nu = gpu_tree(kd, t)
+    p = perm.cpu().numpy()
+    m = 6
+    near = kd.all_nearest(dt, perm, nu, m)
+    got = near.cpu().numpy()
+    assert got.shape == (n, m)
+    for pos in range(nu):
+        others = np.array([x for x in p if x != p[pos]], dtype=np.int64)
+        want_rows, _ = brute_nearest(t, others, t[p[pos]], m)
+        assert got[pos, :len(want_rows)].tolist() == want_rows, f"pos {pos}"
+        assert np.all(got[pos, len(want_rows):] == -1)
+    if nu >= 2:
+        # distances against the oracle on a few nodes
+        oq_near = [oq.nearest_neighbors(t, p, t[p[pos]].tolist(), m, exclude=int(p[pos])) for pos in range(5)]
+        for pos in range(5):
+            d = exact_sq_dist(t, got[pos][got[pos] >= 0], t[p[pos]])
+            assert [x for x, _ in oq_near[pos]] == d
+    offsets, lists = kd.reverse_nearest(perm, nu, near)
+    offsets, lists = offsets.cpu().numpy(), lists.cpu().numpy()
+    want = oq.reverse_lists(p, [[int(r) for r in got[pos] if r >= 0] for pos in range(nu)])
+    assert offsets[0] == 0 and offsets[-1] == sum(len(v) for v in want.values())
+    for r in range(n):
+        assert lists[offsets[r]:offsets[r + 1]].tolist() == want.get(r, []), f"row {r}"

@@ -233,3 +233,40 @@ def test_region_and_nn_queries(dtype):
         assert queries.region_search(t, perm, lower, upper) == bf.region_scan(t, perm.astype(np.int64), lower, upper)
         got = [d for d, _ in queries.nearest_neighbors(t, perm, q, 7)]
         assert got == bf.knn_scan_distances(t, perm.astype(np.int64), q, 7)
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.float32])
+def test_all_nearest_and_reverse_lists(dtype):
+    # every node as a query, itself excluded; reverse lists are the transpose
+    # (inputs without distance ties, so the neighbour sets are unique)
+    g = kdgen.rng(34)
+    if dtype == np.int32:
+        t = g.integers(-10**6, 10**6, size=(300, 3)).astype(np.int32)
+    else:
+        t = g.normal(size=(300, 3)).astype(np.float32)
+    r = oracle.build_tree(t)
+    perm = r["perm"]
+    m = 4
+    near = queries.all_nearest(t, perm, m)
+    assert len(near) == len(perm)
+    scan_rows = []
+    for pos, row in enumerate(perm):
+        others = np.array([int(x) for x in perm if int(x) != int(row)], dtype=np.int64)
+        want = bf.knn_scan_distances(t, others, t[int(row)].tolist(), m)
+        assert [d for d, _ in near[pos]] == want
+        assert int(row) not in [rr for _, rr in near[pos]]
+        # brute-force neighbour rows (ties absent): the m smallest distances
+        if dtype == np.int32:
+            d = [sum((int(a) - int(b)) ** 2 for a, b in zip(t[o], t[int(row)])) for o in others]
+        else:
+            d = [float(np.sum((t[o].astype(np.float64) - t[int(row)].astype(np.float64)) ** 2)) for o in others]
+        order = np.argsort(np.array(d), kind="stable")[:m]
+        scan_rows.append([int(others[i]) for i in order])
+        assert sorted(rr for _, rr in near[pos]) == sorted(scan_rows[-1])
+    rev = queries.reverse_lists(perm, [[rr for _, rr in nb] for nb in near])
+    want = {}
+    for pos, rows in enumerate(scan_rows):
+        for rr in rows:
+            want.setdefault(rr, []).append(int(perm[pos]))
+    assert rev == {k: sorted(v) for k, v in want.items()}
+    assert sum(len(v) for v in rev.values()) == m * len(perm)
