@@ -173,6 +173,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the learned and batched forms")
     ap.add_argument("--no-tune", action="store_true", help="use the default knobs instead of autotuning")
     ap.add_argument("--no-queries", action="store_true", help="skip the tree searches on the C2 tree")
+    ap.add_argument("--no-select", action="store_true",
+                    help="skip the comparison builder's k sweep on the C3 inputs")
     ap.add_argument("--n", type=int, default=1 << 24, help=argparse.SUPPRESS)
     ap.add_argument("--calibrate", action="store_true",
                     help="first run one plain 256 MiB device copy (a reference for profiler byte counters)")
@@ -307,6 +309,9 @@ def main():
     if not args.no_queries:
         out["queries"] = queries_c2(torch, kd, _lib, kdgen, t, t_host, perm, b.n_unique, nu, args)
 
+    if not args.no_select:
+        out["select_c3"] = select_c3(torch, kd, kdgen, args)
+
     if not args.no_forms:
         plain_perm = perm.clone()
         out["forms"] = {"learned_c2": learned_form(torch, kd, t, plain_perm, nu, args, "c2 (same input)",
@@ -411,6 +416,36 @@ def queries_c2(torch, kd, _lib, kdgen, t, t_host, perm, n_nodes, nu, args):
                                "sample": f"the first {s_nn} points and {s_box} boxes of the same "
                                          f"batches ({nn_s + box_s:.1f} s, one Python thread)"}
         log(f"queries cpu oracle: {s_nn / nn_s:.0f} nn/s, {s_box / box_s:.0f} boxes/s")
+    return res
+
+
+def select_c3(torch, kd, kdgen, args):
+    """The paper's comparison (its Fig. 7 varies k): the presort builder
+    against the per-level sorting builder on the C3 inputs (n = 2^22, 256
+    Gaussian clusters, 10% copies) for k in {2, 3, 4, 6, 8}; both produce the
+    same tree, checked here."""
+    res = {"workload": "C3: k in {2,3,4,6,8}, n=2^22 int32 from 256 Gaussian clusters "
+                       "(sigma 2^12), 10% exact copies", "per_k": {}}
+    reps = max(3, args.steps // 4)
+    for k in (2, 3, 4, 6, 8):
+        x = kdgen.c3_clustered(k)
+        t = torch.from_numpy(x).cuda()
+        n = t.shape[0]
+        b = kd.Builder(n, k, torch.int32)
+        sb = kd.SelectBuilder(n, k, torch.int32)
+        p1 = torch.full((n,), -1, dtype=torch.int32, device=t.device)
+        p2 = torch.full((n,), -1, dtype=torch.int32, device=t.device)
+        plain_ms = time_steps(torch, lambda: b.build(t, p1), reps, 1)
+        sel_ms = time_steps(torch, lambda: sb.build(t, p2), reps, 1)
+        nu = int(b.n_unique.item())
+        same = int(sb.n_unique.item()) == nu and torch.equal(p1[:nu], p2[:nu])
+        res["per_k"][str(k)] = {"presort_builder_ms": round(plain_ms, 3),
+                                "select_builder_ms": round(sel_ms, 3),
+                                "ratio": round(sel_ms / plain_ms, 2), "same_tree": bool(same)}
+        log(f"c3 k={k}: presort builder {plain_ms:.2f} ms, per-level sorting builder {sel_ms:.2f} ms, "
+            f"same={same}")
+        del b, sb, p1, p2, t
+        torch.cuda.empty_cache()
     return res
 
 

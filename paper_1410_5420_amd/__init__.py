@@ -19,7 +19,7 @@ from ._lib import KD_F32, KD_I32, KdError  # noqa: F401
 
 __all__ = ["Builder", "BatchedBuilder", "LearnedBuilder", "build", "build_batched", "build_learned",
            "train_cdf", "cdf_loss_grad", "cdf_eval", "gather_nodes", "region_count", "region_rows",
-           "nearest", "all_nearest", "reverse_nearest", "KdError"]
+           "nearest", "all_nearest", "reverse_nearest", "build_select", "SelectBuilder", "KdError"]
 
 
 def _dtype_code(t: torch.Tensor) -> int:
@@ -285,6 +285,41 @@ def reverse_nearest(perm: torch.Tensor, n_nodes, near_rows: torch.Tensor, stream
                                            _ptr(ws), ws.numel(), _stream(stream)),
                "kd_reverse_nearest")
     return offsets, lists
+
+
+def build_select(tuples: torch.Tensor, stream=None):
+    """The same tree by the comparison method (kdtree_build_select): a stable
+    radix sort of the rows within every subarray at each level instead of k
+    presorts and partitions.  Returns ``(perm, n_unique)`` like ``build``."""
+    n, k = tuples.shape
+    code = _dtype_code(tuples)
+    nbytes = _lib.workspace_bytes(max(n, 1), k, code)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=tuples.device)
+    nu = torch.zeros(1, dtype=torch.int64, device=tuples.device)
+    perm = torch.full((max(n, 1),), -1, dtype=torch.int32, device=tuples.device)
+    _lib.check(_lib.lib.kdtree_build_select(_ptr(tuples.contiguous()), n, k, code, _ptr(perm),
+                                            _ptr(nu), _ptr(ws), nbytes, None, _stream(stream)),
+               "kdtree_build_select")
+    u = int(nu.item())
+    return perm[:u], u
+
+
+class SelectBuilder:
+    """Reusable workspace for ``build_select`` (no allocation per build)."""
+
+    def __init__(self, n: int, k: int, dtype=torch.int32, device="cuda"):
+        self.n, self.k = int(n), int(k)
+        self.code = _dtype_code(torch.empty(0, dtype=dtype))
+        nbytes = _lib.workspace_bytes(self.n, self.k, self.code)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.n_unique = torch.zeros(1, dtype=torch.int64, device=device)
+
+    def build(self, tuples: torch.Tensor, perm: torch.Tensor, stream=None):
+        n, k = tuples.shape
+        _lib.check(_lib.lib.kdtree_build_select(_ptr(tuples), n, k, self.code, _ptr(perm),
+                                                _ptr(self.n_unique), _ptr(self.workspace),
+                                                self.workspace.numel(), None, _stream(stream)),
+                   "kdtree_build_select")
 
 
 # ---- learned presort ------------------------------------------------------------

@@ -45,6 +45,8 @@ def _load():
     lib.kdtree_presort.restype = ctypes.c_int
     lib.kdtree_partition.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp, vp, sz, opt, vp]
     lib.kdtree_partition.restype = ctypes.c_int
+    lib.kdtree_build_select.argtypes = [vp, i64, i32, i32, vp, vp, vp, sz, opt, vp]
+    lib.kdtree_build_select.restype = ctypes.c_int
     lib.kdtree_workspace_bytes_batched.argtypes = [i64, i32, i32, i32, ctypes.POINTER(sz)]
     lib.kdtree_workspace_bytes_batched.restype = ctypes.c_int
     lib.kdtree_build_batched.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp, sz, opt, vp]
@@ -91,7 +93,8 @@ lib = _load()
 
 # Every symbol include/kdtree.h declares (the tests check the library exports them).
 EXPORTED = ["kd_strerror", "kdtree_workspace_bytes", "kdtree_build", "kdtree_presort",
-            "kdtree_partition", "kdtree_workspace_bytes_batched", "kdtree_build_batched",
+            "kdtree_partition", "kdtree_build_select", "kdtree_workspace_bytes_batched",
+            "kdtree_build_batched",
             "kd_cdf_model_bytes", "kd_cdf_train_workspace_bytes", "kd_cdf_train",
             "kd_cdf_loss_grad", "kd_cdf_eval", "kdtree_workspace_bytes_learned",
             "kdtree_build_learned", "kdtree_presort_learned", "kd_gather_nodes", "kd_region_count",

@@ -343,7 +343,7 @@ bool learned_sort_on(const Job& J, int d) {
   return J.learned_sorts == 0 || ((J.learned_sorts >> d) & 1) != 0;
 }
 
-int presort_impl(const Job& J, hipStream_t st) {
+int presort_impl(const Job& J, hipStream_t st, bool first_only = false) {
   const int64_t n = J.n;
   const int k = J.k;
   const int B = J.B;
@@ -428,7 +428,7 @@ int presort_impl(const Job& J, hipStream_t st) {
   }
   KD_TRY(launch_forest_finish(uoff, B, J.cutover, J.n_unique, at<int32_t>(ws, L.lmax),
                               at<int32_t>(ws, L.wgbase), at<int32_t>(ws, L.queue), st));
-  if (n == 0) return KD_OK;
+  if (n == 0 || first_only) return KD_OK;  // first_only: array 0 and the duplicate removal
   const int32_t* total = uoff + B;
   // Chain: the array for super key d is the stable sort by word d (then tree)
   // of the array for super key d+1.  Each sort carries the ranks already
@@ -609,6 +609,65 @@ int check_job(Job& J, size_t ws_bytes, const kd_options* opts) {
   return KD_OK;
 }
 
+// The comparison builder (Sec. 3: an O(n log n) method that finds each
+// subarray's median at every level): array 0 and duplicate removal as in the
+// presort (so the nodes are the same distinct rows), then one stable radix
+// sort per level of the single array of rows within every subarray, by the
+// level's super key (least significant word first) and then by the range
+// start of every position.  After the sort of depth d every subarray of
+// depth d holds its rows in super-key order, so its median is at its middle
+// position and its halves are already partitioned; depth 0 needs no sort.
+// Uses the build's workspace: key words in the level-0 record space, rows and
+// range starts in the first moved-record space.
+int select_impl(const Job& J, hipStream_t st) {
+  const int64_t n = J.n;
+  const int k = J.k;
+  int rc = presort_impl(J, st, true);
+  if (rc != KD_OK) return rc;
+  if (n == 0) return KD_OK;
+  void* ws = J.ws;
+  const Layout L = plan(n, k, J.B);
+  const size_t un = (size_t)n;
+  uint32_t* S = at<uint32_t>(ws, L.S);
+  int32_t* uoff = at<int32_t>(ws, L.uoff);
+  const int32_t* nu = uoff + 1;
+  const ForestArgs fa = forest_args(J, L);
+  if (k == 1) {
+    KD_TRY(launch_copy_k1(S, fa, n, J.perm, st));
+    return KD_OK;
+  }
+  uint32_t* words = at<uint32_t>(ws, L.rec0);   // k planes (k (k-1) n words available)
+  uint32_t* rows = at<uint32_t>(ws, L.rec1);    // rows, then range starts
+  uint32_t* range = rows + un;
+  const TupleSrc ts{static_cast<const uint32_t*>(J.tuples), k, J.dtype == KD_F32 ? 1 : 0};
+  KD_TRY(launch_gather_words(ts.t, k, ts.is_float, S, nu, n, words, st));
+  int range_passes = 1;
+  while (range_passes < 4 && ((uint64_t)(n - 1) >> (8 * range_passes)) != 0) ++range_passes;
+  uint32_t* vb = at<uint32_t>(ws, L.vbuf);
+  uint32_t* rcnt = at<uint32_t>(ws, L.rcnt);
+  uint32_t* rgrp = at<uint32_t>(ws, L.rgrp);
+  const uint32_t* cur_rows = S;
+  for (int d = 1; (n >> d) >= 2 && d < kMaxLevels; ++d) {
+    const int p = d % k;
+    KD_TRY(launch_range_starts(nu, n, d, range, st));
+    // quantities: 0 = row, 1 + j = word j, k + 1 = range start
+    std::vector<Quant> q(k + 2);
+    q[0] = Quant{kPlaneArray, cur_rows, 0, rows};
+    for (int j = 0; j < k; ++j)
+      q[1 + j] = Quant{kPlaneArray, words + (size_t)j * un, 0, words + (size_t)j * un};
+    q[k + 1] = Quant{kPlaneArray, range, 0, nullptr};
+    std::vector<Pass> passes;
+    for (int c = k - 1; c >= 0; --c)  // super key p: words p, p+1, ..., least significant last
+      for (int ps = 0; ps < kPassesPerWord; ++ps) passes.push_back({1 + (p + c) % k, ps * kRadixBits});
+    for (int ps = 0; ps < range_passes; ++ps) passes.push_back({k + 1, ps * kRadixBits});
+    rc = run_sort(q, passes, ts, n, nu, vb, k + 2, rcnt, rgrp, st);
+    if (rc != KD_OK) return rc;
+    cur_rows = rows;
+  }
+  KD_TRY(launch_copy_k1(cur_rows, fa, n, J.perm, st));
+  return KD_OK;
+}
+
 int check_outputs(const Job& J) {
   if ((J.n > 0 && !J.perm) || !aligned4(J.perm)) return KD_EINVAL;
   if ((J.lo == nullptr) != (J.hi == nullptr)) return KD_EINVAL;
@@ -767,6 +826,29 @@ int kdtree_build(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, int3
   rc = kd::presort_impl(J, st);
   if (rc != KD_OK) return rc;
   return kd::partition_impl(J, st);
+}
+
+int kdtree_build_select(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, int32_t* d_perm,
+                        int64_t* d_n_unique, void* d_workspace, size_t workspace_bytes,
+                        const kd_options* opts, void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  {
+    kd::Job V;
+    int64_t h2[2];
+    int rc = kd::single_job(V, d_tuples, n, k, dtype, d_n_unique, d_workspace, workspace_bytes,
+                            opts, h2, st, false);
+    if (rc != KD_OK) return rc;
+    V.perm = d_perm;
+    rc = kd::check_outputs(V);
+    if (rc != KD_OK) return rc;
+  }
+  kd::Job J;
+  int64_t h_off[2];
+  int rc = kd::single_job(J, d_tuples, n, k, dtype, d_n_unique, d_workspace, workspace_bytes, opts,
+                          h_off, st, true);
+  if (rc != KD_OK) return rc;
+  J.perm = d_perm;
+  return kd::select_impl(J, st);
 }
 
 int kdtree_build_batched(const void* d_tuples, const int64_t* d_offsets, const int64_t* h_offsets,

@@ -160,6 +160,14 @@ hipError_t launch_leaf(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1,
                        int64_t cutover, const ForestArgs& fa, int32_t* perm, int64_t items_bound,
                        int blocks, hipStream_t st);
 
+// Per-level sorting builder: the k canonical words of rows[pos] for pos <
+// *nu (plane j at words + j * n), and every position's range start at
+// `depth` (its subarray's first position, or itself for an earlier node).
+hipError_t launch_gather_words(const uint32_t* tuples, int k, int is_float, const uint32_t* rows,
+                               const int32_t* nu, int64_t n, uint32_t* words, hipStream_t st);
+hipError_t launch_range_starts(const int32_t* nu, int64_t n, int depth, uint32_t* range,
+                               hipStream_t st);
+
 // k == 1: the in-order layout is the sorted unique order.
 hipError_t launch_copy_k1(const uint32_t* S0, const ForestArgs& fa, int64_t n, int32_t* perm,
                           hipStream_t st);

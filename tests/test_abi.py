@@ -195,3 +195,16 @@ def test_all_nearest_and_reverse_reject_bad_arguments(L):
     assert L.lib.kd_reverse_nearest(F, F8, 1 << 20, 4, F, vp(FAKE8 + 4), F, F8, need, None) == -1
     assert L.lib.kd_reverse_nearest(F, F8, 1 << 20, 4, F, F8, F, F8, need - 8, None) == -2
     assert L.lib.kd_reverse_nearest(F, F8, 0, 4, None, None, None, None, 0, None) == 0
+
+
+def test_select_build_rejects_bad_arguments(L):
+    vp = ctypes.c_void_p
+    out = ctypes.c_size_t(0)
+    assert L.lib.kdtree_workspace_bytes(100, 3, 0, ctypes.byref(out)) == 0
+    ws = out.value
+    nu = FAKE
+    assert L.lib.kdtree_build_select(vp(FAKE), 100, 0, 0, vp(FAKE), vp(nu), vp(FAKE), ws, None, None) == -1
+    assert L.lib.kdtree_build_select(vp(FAKE), 100, 9, 0, vp(FAKE), vp(nu), vp(FAKE), ws, None, None) == -4
+    assert L.lib.kdtree_build_select(vp(FAKE), 100, 3, 2, vp(FAKE), vp(nu), vp(FAKE), ws, None, None) == -1
+    assert L.lib.kdtree_build_select(vp(FAKE), 100, 3, 0, None, vp(nu), vp(FAKE), ws, None, None) == -1
+    assert L.lib.kdtree_build_select(vp(FAKE), 100, 3, 0, vp(FAKE), vp(nu), vp(FAKE), ws - 8, None, None) == -2
