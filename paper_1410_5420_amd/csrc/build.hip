@@ -198,12 +198,12 @@ __global__ __launch_bounds__(kSegThreads) void k_level_seg(const RecBufs B, cons
   __shared__ SegInfo s_si;
   __shared__ uint32_t s_c[kMaxK];
   const int tid = threadIdx.x;
-  const int nu = F.uoff[F.B];
-  if (depth >= *F.lmax) return;
   const int t = blockIdx.x;
   const int t0 = t * kLevelTile;
-  if (t >= tiles || t0 >= nu) return;
-  const int t1 = min(t0 + kLevelTile, nu);
+  if (t >= tiles) return;
+  // The rank planes are loaded first, bounded by the rows (every plane holds
+  // n entries); the device counts decide afterwards what is used.
+  const int tl = (int)min((int64_t)t0 + kLevelTile, n);
   const int p = depth % k;
   constexpr int arrays = R;
   uint32_t rp[R > 0 ? R : 1][kSegItems];
@@ -216,9 +216,12 @@ __global__ __launch_bounds__(kSegThreads) void k_level_seg(const RecBufs B, cons
 #pragma unroll
     for (int it = 0; it < kSegItems; ++it) {
       const int i = t0 + it * kSegThreads + tid;
-      rp[a][it] = i < t1 ? plane[i] : 0u;
+      rp[a][it] = i < tl ? plane[i] : 0u;
     }
   }
+  const int nu = F.uoff[F.B];
+  if (depth >= *F.lmax || t0 >= nu) return;
+  const int t1 = min(t0 + kLevelTile, nu);
   if (tid < kWave) find_subarrays(B, F, n, k, depth, cutover, t0, t1, true, perm, &s_si);
   if (tid < kMaxK) s_c[tid] = 0;
   __syncthreads();
