@@ -348,8 +348,15 @@ def queries_c2(torch, kd, _lib, kdgen, t, t_host, perm, n_nodes, nu, args):
     nodes = kd.gather_nodes(t, perm, n_nodes)
     torch.cuda.synchronize()
     res["gather_nodes_ms"] = round(float(_lib.probe_stop(1)[0]), 4)
+    _lib.probe_start("query", 1)
+    bounds = kd.subtree_bounds(nodes, n_nodes)
+    torch.cuda.synchronize()
+    res["subtree_bounds_ms"] = round(float(np.sum(_lib.probe_stop(1))), 4)
     runs = {"nearest_m8": lambda v: kd.nearest(t, perm, n_nodes, dp, 8, visits=v, nodes=nodes),
-            "box_count": lambda v: kd.region_count(t, perm, n_nodes, dlo, dhi, visits=v, nodes=nodes)}
+            "box_count": lambda v: kd.region_count(t, perm, n_nodes, dlo, dhi, visits=v, nodes=nodes,
+                                                   bounds=bounds),
+            "box_count_no_bounds": lambda v: kd.region_count(t, perm, n_nodes, dlo, dhi, visits=v,
+                                                             nodes=nodes)}
     outs = {}
     for name, fn in runs.items():
         fn(None)
@@ -368,6 +375,7 @@ def queries_c2(torch, kd, _lib, kdgen, t, t_host, perm, n_nodes, nu, args):
                      "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
         log(f"queries {name}: {ms:.3f} ms per 2^20, {per_query:.1f} visits per query")
     res["box_mean_count"] = round(float(outs["box_count"].float().mean().item()), 2)
+    res["box_bounds_same_counts"] = bool(torch.equal(outs["box_count"], outs["box_count_no_bounds"]))
     # every node as a query (m = 8, itself excluded), then the reverse lists
     visits.zero_()
     _lib.probe_start("query", 1)

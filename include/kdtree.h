@@ -259,16 +259,24 @@ int kdtree_presort_learned(const void* d_tuples, int64_t n, int32_t k, int32_t d
  * that is not a row below n gives zeros). */
 int kd_gather_nodes(const void* d_tuples, int64_t n, int32_t k, int32_t dtype,
                     const int32_t* d_perm, const int64_t* d_n_nodes, void* d_nodes, void* stream);
+/* Bounding box of every subtree, at its node's position: d_bounds[pos][d] is
+ * the smallest and d_bounds[pos][k + d] the largest coordinate d of the
+ * subtree rooted at pos (n*2k of dtype; float subtrees that hold a NaN get
+ * NaN bounds).  Optional input of the box queries: a subtree inside a box is
+ * then taken whole and one outside it skipped, without visiting its nodes. */
+int kd_subtree_bounds(const void* d_nodes, int64_t n, int32_t k, int32_t dtype,
+                      const int64_t* d_n_nodes, void* d_bounds, void* stream);
 /* Box queries, counts: d_counts[q] = number of nodes x with
- * d_lower[q][d] <= x[d] <= d_upper[q][d] for every d (int32[nq]). */
-int kd_region_count(const void* d_nodes, int64_t n, int32_t k, int32_t dtype,
+ * d_lower[q][d] <= x[d] <= d_upper[q][d] for every d (int32[nq]).  d_bounds:
+ * kd_subtree_bounds' output, or NULL; the result is the same. */
+int kd_region_count(const void* d_nodes, const void* d_bounds, int64_t n, int32_t k, int32_t dtype,
                     const int64_t* d_n_nodes, const void* d_lower, const void* d_upper, int64_t nq,
                     int32_t* d_counts, uint64_t* d_visits, void* stream);
 /* Box queries, rows: the rows of query q's nodes are written to
  * d_rows[d_offsets[q]], d_rows[d_offsets[q] + 1], ... in increasing tree
  * position (int64 d_offsets[nq], e.g. the exclusive scan of kd_region_count's
- * counts); no write goes at or past rows_capacity. */
-int kd_region_rows(const void* d_nodes, int64_t n, int32_t k, int32_t dtype,
+ * counts); no write goes at or past rows_capacity.  d_bounds as above. */
+int kd_region_rows(const void* d_nodes, const void* d_bounds, int64_t n, int32_t k, int32_t dtype,
                    const int32_t* d_perm, const int64_t* d_n_nodes, const void* d_lower,
                    const void* d_upper, int64_t nq, const int64_t* d_offsets, int32_t* d_rows,
                    int64_t rows_capacity, uint64_t* d_visits, void* stream);

@@ -56,9 +56,11 @@ def region_search(tuples: np.ndarray, perm: np.ndarray, lower, upper):
         if all(lower[d] <= x[d] <= upper[d] for d in range(k)):
             found.append(row)
         p = depth % k
-        if lower[p] <= x[p]:
+        # a side is skipped only when the split value proves the box misses it
+        # (a NaN split value proves nothing)
+        if not lower[p] > x[p]:
             visit(s, m - 1, depth + 1)
-        if upper[p] >= x[p]:
+        if not upper[p] < x[p]:
             visit(m + 1, e, depth + 1)
 
     visit(0, len(perm) - 1, 0)

@@ -18,7 +18,8 @@ from . import _lib
 from ._lib import KD_F32, KD_I32, KdError  # noqa: F401
 
 __all__ = ["Builder", "BatchedBuilder", "LearnedBuilder", "build", "build_batched", "build_learned",
-           "train_cdf", "cdf_loss_grad", "cdf_eval", "gather_nodes", "region_count", "region_rows",
+           "train_cdf", "cdf_loss_grad", "cdf_eval", "gather_nodes", "subtree_bounds", "region_count",
+           "region_rows",
            "nearest", "all_nearest", "reverse_nearest", "build_select", "SelectBuilder", "KdError"]
 
 
@@ -193,14 +194,30 @@ def gather_nodes(tuples: torch.Tensor, perm: torch.Tensor, n_nodes, stream=None)
     return nodes
 
 
+def subtree_bounds(nodes: torch.Tensor, n_nodes, stream=None) -> torch.Tensor:
+    """Bounding box of every subtree at its node's position
+    (kd_subtree_bounds): an (n, 2k) tensor, the k smallest then the k
+    largest coordinates.  Optional ``bounds=`` of the box queries."""
+    n, k = nodes.shape
+    if not torch.is_tensor(n_nodes):
+        n_nodes = torch.tensor([int(n_nodes)], dtype=torch.int64, device=nodes.device)
+    nn = n_nodes.reshape(1).to(torch.int64).contiguous()
+    bounds = torch.empty((n, 2 * k), dtype=nodes.dtype, device=nodes.device)
+    _lib.check(_lib.lib.kd_subtree_bounds(_ptr(nodes), n, k, _dtype_code(nodes), _ptr(nn),
+                                          _ptr(bounds), _stream(stream)), "kd_subtree_bounds")
+    return bounds
+
+
 def region_count(tuples: torch.Tensor, perm: torch.Tensor, n_nodes, lower: torch.Tensor,
-                 upper: torch.Tensor, visits: torch.Tensor | None = None, nodes=None, stream=None):
+                 upper: torch.Tensor, visits: torch.Tensor | None = None, nodes=None, bounds=None,
+                 stream=None):
     """Number of tree nodes inside every box (kd_region_count).
 
     ``perm``: the in-order layout of ``tuples``' tree; ``n_nodes``: its node
     count (int or device int64 tensor); ``lower``/``upper``: (nq, k) box
     corners, inclusive.  ``visits``: optional uint64 device counter;
-    ``nodes``: ``gather_nodes``' result, gathered here when not given.
+    ``nodes``: ``gather_nodes``' result, gathered here when not given;
+    ``bounds``: ``subtree_bounds``' result, or None (same counts, more visits).
     """
     n, k, code, nn = _query_args(tuples, perm, n_nodes, lower)
     if nodes is None:
@@ -210,14 +227,14 @@ def region_count(tuples: torch.Tensor, perm: torch.Tensor, n_nodes, lower: torch
         raise ValueError("lower and upper must match")
     nq = lower.shape[0]
     counts = torch.empty(nq, dtype=torch.int32, device=tuples.device)
-    _lib.check(_lib.lib.kd_region_count(_ptr(nodes), n, k, code, _ptr(nn), _ptr(lower), _ptr(upper),
-                                        nq, _ptr(counts), _ptr(visits), _stream(stream)),
-               "kd_region_count")
+    _lib.check(_lib.lib.kd_region_count(_ptr(nodes), _ptr(bounds), n, k, code, _ptr(nn), _ptr(lower),
+                                        _ptr(upper), nq, _ptr(counts), _ptr(visits),
+                                        _stream(stream)), "kd_region_count")
     return counts
 
 
 def region_rows(tuples: torch.Tensor, perm: torch.Tensor, n_nodes, lower: torch.Tensor,
-                upper: torch.Tensor, nodes=None, stream=None):
+                upper: torch.Tensor, nodes=None, bounds=None, stream=None):
     """Rows of the tree nodes inside every box, as ``(rows, offsets)``: the
     rows of box q are ``rows[offsets[q]:offsets[q + 1]]`` in increasing tree
     position.  Counts first (kd_region_count), then rows (kd_region_rows);
@@ -225,13 +242,13 @@ def region_rows(tuples: torch.Tensor, perm: torch.Tensor, n_nodes, lower: torch.
     n, k, code, nn = _query_args(tuples, perm, n_nodes, lower)
     if nodes is None:
         nodes = gather_nodes(tuples, perm, nn, stream)
-    counts = region_count(tuples, perm, nn, lower, upper, nodes=nodes, stream=stream)
+    counts = region_count(tuples, perm, nn, lower, upper, nodes=nodes, bounds=bounds, stream=stream)
     nq = lower.shape[0]
     offsets = torch.zeros(nq + 1, dtype=torch.int64, device=tuples.device)
     torch.cumsum(counts.to(torch.int64), 0, out=offsets[1:])
     total = int(offsets[-1].item())
     rows = torch.empty(max(total, 1), dtype=torch.int32, device=tuples.device)
-    _lib.check(_lib.lib.kd_region_rows(_ptr(nodes), n, k, code, _ptr(perm), _ptr(nn),
+    _lib.check(_lib.lib.kd_region_rows(_ptr(nodes), _ptr(bounds), n, k, code, _ptr(perm), _ptr(nn),
                                        _ptr(lower.contiguous()), _ptr(upper.contiguous()), nq,
                                        _ptr(offsets), _ptr(rows), total, None, _stream(stream)),
                "kd_region_rows")

@@ -70,9 +70,11 @@ def _load():
     lib.kdtree_presort_learned.restype = ctypes.c_int
     lib.kd_gather_nodes.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp]
     lib.kd_gather_nodes.restype = ctypes.c_int
-    lib.kd_region_count.argtypes = [vp, i64, i32, i32, vp, vp, vp, i64, vp, vp, vp]
+    lib.kd_subtree_bounds.argtypes = [vp, i64, i32, i32, vp, vp, vp]
+    lib.kd_subtree_bounds.restype = ctypes.c_int
+    lib.kd_region_count.argtypes = [vp, vp, i64, i32, i32, vp, vp, vp, i64, vp, vp, vp]
     lib.kd_region_count.restype = ctypes.c_int
-    lib.kd_region_rows.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp, i64, vp, vp, i64, vp, vp]
+    lib.kd_region_rows.argtypes = [vp, vp, i64, i32, i32, vp, vp, vp, vp, i64, vp, vp, i64, vp, vp]
     lib.kd_region_rows.restype = ctypes.c_int
     lib.kd_nearest.argtypes = [vp, i64, i32, i32, vp, vp, vp, i64, i32, vp, vp, vp]
     lib.kd_nearest.restype = ctypes.c_int
@@ -97,7 +99,8 @@ EXPORTED = ["kd_strerror", "kdtree_workspace_bytes", "kdtree_build", "kdtree_pre
             "kdtree_build_batched",
             "kd_cdf_model_bytes", "kd_cdf_train_workspace_bytes", "kd_cdf_train",
             "kd_cdf_loss_grad", "kd_cdf_eval", "kdtree_workspace_bytes_learned",
-            "kdtree_build_learned", "kdtree_presort_learned", "kd_gather_nodes", "kd_region_count",
+            "kdtree_build_learned", "kdtree_presort_learned", "kd_gather_nodes", "kd_subtree_bounds",
+            "kd_region_count",
             "kd_region_rows", "kd_nearest", "kd_all_nearest", "kd_reverse_workspace_bytes",
             "kd_reverse_nearest", "kd_probe_start", "kd_probe_stop"]
 

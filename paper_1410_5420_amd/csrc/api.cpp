@@ -1060,30 +1060,43 @@ int kd_gather_nodes(const void* d_tuples, int64_t n, int32_t k, int32_t dtype,
   return KD_OK;
 }
 
-int kd_region_count(const void* d_nodes, int64_t n, int32_t k, int32_t dtype,
+int kd_subtree_bounds(const void* d_nodes, int64_t n, int32_t k, int32_t dtype,
+                      const int64_t* d_n_nodes, void* d_bounds, void* stream) {
+  int fl = 0;
+  int rc = check_query(d_nodes, n, k, dtype, nullptr, false, d_n_nodes, 0, nullptr, &fl);
+  if (rc != KD_OK) return rc;
+  if (n == 0) return KD_OK;
+  if (!d_bounds || !kd::aligned4(d_bounds)) return KD_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  KD_QLAUNCH(kd::launch_subtree_bounds(d_nodes, n, k, fl, d_n_nodes, d_bounds, st));
+  return KD_OK;
+}
+
+int kd_region_count(const void* d_nodes, const void* d_bounds, int64_t n, int32_t k, int32_t dtype,
                     const int64_t* d_n_nodes, const void* d_lower, const void* d_upper, int64_t nq,
                     int32_t* d_counts, uint64_t* d_visits, void* stream) {
   int fl = 0;
   int rc = check_query(d_nodes, n, k, dtype, nullptr, false, d_n_nodes, nq, d_visits, &fl);
   if (rc != KD_OK) return rc;
+  if (!kd::aligned4(d_bounds)) return KD_EINVAL;
   if (nq == 0) return KD_OK;
   if (!d_lower || !d_upper || !d_counts) return KD_EINVAL;
   if (!kd::aligned4(d_lower) || !kd::aligned4(d_upper) || !kd::aligned4(d_counts)) return KD_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  KD_QLAUNCH(kd::launch_region(d_nodes, n, k, fl, nullptr, d_n_nodes, d_lower, d_upper, nq,
+  KD_QLAUNCH(kd::launch_region(d_nodes, d_bounds, n, k, fl, nullptr, d_n_nodes, d_lower, d_upper, nq,
                                d_counts, nullptr, nullptr, 0,
                                reinterpret_cast<unsigned long long*>(d_visits), st));
   return KD_OK;
 }
 
-int kd_region_rows(const void* d_nodes, int64_t n, int32_t k, int32_t dtype,
+int kd_region_rows(const void* d_nodes, const void* d_bounds, int64_t n, int32_t k, int32_t dtype,
                    const int32_t* d_perm, const int64_t* d_n_nodes, const void* d_lower,
                    const void* d_upper, int64_t nq, const int64_t* d_offsets, int32_t* d_rows,
                    int64_t rows_capacity, uint64_t* d_visits, void* stream) {
   int fl = 0;
   int rc = check_query(d_nodes, n, k, dtype, d_perm, true, d_n_nodes, nq, d_visits, &fl);
   if (rc != KD_OK) return rc;
-  if (rows_capacity < 0) return KD_EINVAL;
+  if (rows_capacity < 0 || !kd::aligned4(d_bounds)) return KD_EINVAL;
   if (nq == 0) return KD_OK;
   if (!d_lower || !d_upper || !d_offsets || (!d_rows && rows_capacity > 0)) return KD_EINVAL;
   if (!kd::aligned4(d_lower) || !kd::aligned4(d_upper) || !kd::aligned4(d_rows) ||
@@ -1091,7 +1104,7 @@ int kd_region_rows(const void* d_nodes, int64_t n, int32_t k, int32_t dtype,
     return KD_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   // a null row buffer (capacity 0) still walks: nothing is written
-  KD_QLAUNCH(kd::launch_region(d_nodes, n, k, fl, d_perm, d_n_nodes, d_lower, d_upper, nq,
+  KD_QLAUNCH(kd::launch_region(d_nodes, d_bounds, n, k, fl, d_perm, d_n_nodes, d_lower, d_upper, nq,
                                nullptr, d_offsets, d_rows, rows_capacity,
                                reinterpret_cast<unsigned long long*>(d_visits), st));
   return KD_OK;

@@ -232,15 +232,19 @@ constexpr int kMaxNeighbors = 64;
 // nodes[pos][d] = tuples[perm[pos]][d] for the *nn (device count) nodes.
 hipError_t launch_gather_nodes(const void* tuples, int64_t n, int k, int is_float,
                                const int32_t* perm, const int64_t* nn, void* nodes, hipStream_t st);
+// Subtree bounding boxes (n * 2k values: smallest k, then largest k) at every
+// node position, from the node coordinates.
+hipError_t launch_subtree_bounds(const void* nodes, int64_t n, int k, int is_float,
+                                 const int64_t* nn, void* bounds, hipStream_t st);
 // Box queries over the *nn nodes whose coordinates `nodes` holds in tree
-// position order: counts[q] (offsets == null), or the rows (perm entries) of
-// query q written from rows[offsets[q]] in increasing tree position (no write
-// at or past cap).  visits: null, or a counter that receives the number of
-// nodes visited.
-hipError_t launch_region(const void* nodes, int64_t n, int k, int is_float, const int32_t* perm,
-                         const int64_t* nn, const void* lower, const void* upper, int64_t nq,
-                         int32_t* counts, const int64_t* offsets, int32_t* rows, int64_t cap,
-                         unsigned long long* visits, hipStream_t st);
+// position order (bounds: their subtree boxes, or null): counts[q] (offsets ==
+// null), or the rows (perm entries) of query q written from rows[offsets[q]]
+// in increasing tree position (no write at or past cap).  visits: null, or a
+// counter that receives the number of nodes visited.
+hipError_t launch_region(const void* nodes, const void* bounds, int64_t n, int k, int is_float,
+                         const int32_t* perm, const int64_t* nn, const void* lower,
+                         const void* upper, int64_t nq, int32_t* counts, const int64_t* offsets,
+                         int32_t* rows, int64_t cap, unsigned long long* visits, hipStream_t st);
 // The m (1 .. kMaxNeighbors) nodes smallest in (squared distance, row) of
 // every query point, ascending, -1 past the node count: rows[q * m + i].
 // points == null: the queries are the nodes themselves (nq = n; query q is

@@ -99,6 +99,69 @@ __device__ __forceinline__ int node_count(const int64_t* n_nodes, int64_t n) {
   return (int)(v < 0 ? 0 : (v > n ? n : v));
 }
 
+// Bounding box of every subtree, stored at the subtree's node position:
+// bounds[pos][d] = smallest, bounds[pos][K + d] = largest coordinate d in the
+// subtree (a float subtree holding a NaN gets NaN bounds, which no test
+// passes, so the search walks it).  One launch per depth, deepest first: the
+// g-th subarray of `depth` (its path from the root spelled by the bits of g)
+// joins its node's point with its children's boxes.
+template <typename T>
+__device__ __forceinline__ T bound_lo(T a, T b) {
+  if constexpr (sizeof(T) == 4 && (T)0.5 != (T)0) {
+    if (a != a || b != b) return a != a ? a : b;
+  }
+  return b < a ? b : a;
+}
+template <typename T>
+__device__ __forceinline__ T bound_hi(T a, T b) {
+  if constexpr (sizeof(T) == 4 && (T)0.5 != (T)0) {
+    if (a != a || b != b) return a != a ? a : b;
+  }
+  return a < b ? b : a;
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_subtree_bounds(const T* __restrict__ nodes, int64_t n,
+                                                       const int64_t* __restrict__ n_nodes,
+                                                       int depth, T* __restrict__ bounds) {
+  const int nn = node_count(n_nodes, n);
+  const int64_t count = (int64_t)1 << depth;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < count;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    int s = 0, e = nn - 1;
+    for (int l = depth - 1; l >= 0 && s <= e; --l) {
+      const int m = s + ((e - s) >> 1);
+      if ((g >> l) & 1)
+        s = m + 1;
+      else
+        e = m - 1;
+    }
+    if (s > e) continue;
+    const int m = s + ((e - s) >> 1);
+    T lo[K], hi[K];
+#pragma unroll
+    for (int d = 0; d < K; ++d) lo[d] = hi[d] = nodes[(int64_t)m * K + d];
+    const int cl[2] = {s + ((m - 1 - s) >> 1), (m + 1) + ((e - m - 1) >> 1)};
+    const bool has[2] = {m - 1 >= s, e >= m + 1};
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (!has[c]) continue;
+      const T* cb = bounds + (int64_t)cl[c] * 2 * K;
+#pragma unroll
+      for (int d = 0; d < K; ++d) {
+        lo[d] = bound_lo(lo[d], cb[d]);
+        hi[d] = bound_hi(hi[d], cb[K + d]);
+      }
+    }
+    T* ob = bounds + (int64_t)m * 2 * K;
+#pragma unroll
+    for (int d = 0; d < K; ++d) {
+      ob[d] = lo[d];
+      ob[K + d] = hi[d];
+    }
+  }
+}
+
 // ---- region search ---------------------------------------------------------------
 // In-order walk (lower subtree, node, upper subtree), so the rows of a query
 // come out in increasing tree position.  No stack: the path from the root is
@@ -118,8 +181,8 @@ __device__ __forceinline__ bool in_box(const T* x, const T* lo, const T* hi) {
 
 template <typename T, int K, bool kRows>
 __global__ __launch_bounds__(kQThreads) void k_region(
-    const T* __restrict__ nodes, int64_t n, const int32_t* __restrict__ perm,
-    const int64_t* __restrict__ n_nodes, const T* __restrict__ lower,
+    const T* __restrict__ nodes, const T* __restrict__ bounds, int64_t n,
+    const int32_t* __restrict__ perm, const int64_t* __restrict__ n_nodes, const T* __restrict__ lower,
     const T* __restrict__ upper, int64_t nq, int32_t* __restrict__ counts,
     const int64_t* __restrict__ offsets, int32_t* __restrict__ rows, int64_t cap,
     unsigned long long* __restrict__ visits) {
@@ -134,11 +197,11 @@ __global__ __launch_bounds__(kQThreads) void k_region(
       hi[d] = upper[q * K + d];
     }
     int32_t found = 0;
-    int64_t out = kRows ? offsets[q] : 0;
+    int64_t out_pos = kRows ? offsets[q] : 0;
     auto take = [&](int m) {
       if (kRows) {
-        if (out < cap) rows[out] = perm[m];
-        ++out;
+        if (out_pos < cap) rows[out_pos] = perm[m];
+        ++out_pos;
       }
       ++found;
     };
@@ -149,9 +212,32 @@ __global__ __launch_bounds__(kQThreads) void k_region(
       while (s <= e) {
         const int m = s + ((e - s) >> 1);
         ++seen;
+        if (bounds) {
+          // a subtree outside the box is skipped, one inside it is taken whole
+          const T* bb = bounds + (int64_t)m * 2 * K;
+          bool out = false, inside = true;
+#pragma unroll
+          for (int d = 0; d < K; ++d) {
+            const T bl = bb[d], bh = bb[K + d];
+            out = out || hi[d] < bl || bh < lo[d];
+            inside = inside && lo[d] <= bl && bh <= hi[d];
+          }
+          if (out) break;
+          if (inside) {
+            found += e - s + 1;
+            if (kRows)
+              for (int i = s; i <= e; ++i) {
+                if (out_pos < cap) rows[out_pos] = perm[i];
+                ++out_pos;
+              }
+            break;
+          }
+        }
         const int p = depth % K;
         const T xp = nodes[(int64_t)m * K + p];
-        if (lo[p] <= xp) {
+        // a side is skipped only when the split value proves the box misses
+        // it (a NaN split value proves nothing)
+        if (!(lo[p] > xp)) {
           pend |= 1u << depth;
           dirs &= ~(1u << depth);
           e = m - 1;
@@ -162,7 +248,7 @@ __global__ __launch_bounds__(kQThreads) void k_region(
         T x[K];
         load_point<T, K>(nodes, m, x);
         if (in_box<T, K>(x, lo, hi)) take(m);
-        if (!(hi[p] >= xp)) break;
+        if (hi[p] < xp) break;
         dirs |= 1u << depth;
         pend &= ~(1u << depth);
         s = m + 1;
@@ -189,7 +275,7 @@ __global__ __launch_bounds__(kQThreads) void k_region(
       const int p = a % K;
       dirs |= 1u << a;
       depth = a + 1;
-      if (hi[p] >= x[p]) {
+      if (!(hi[p] < x[p])) {
         s = m + 1;  // e stays: the upper subtree of [s, e]
       } else {
         s = 1;  // nothing above
@@ -369,21 +455,48 @@ hipError_t launch_gather_nodes(const void* tuples, int64_t n, int k, int is_floa
   return hipGetLastError();
 }
 
-hipError_t launch_region(const void* nodes, int64_t n, int k, int is_float, const int32_t* perm,
-                         const int64_t* nn, const void* lower, const void* upper, int64_t nq,
-                         int32_t* counts, const int64_t* offsets, int32_t* rows, int64_t cap,
-                         unsigned long long* visits, hipStream_t st) {
+hipError_t launch_subtree_bounds(const void* nodes, int64_t n, int k, int is_float,
+                                 const int64_t* nn, void* bounds, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int top = 0;  // deepest depth with a node: floor(log2 n)
+  while (((int64_t)2 << top) <= n) ++top;
+  for (int depth = top; depth >= 0; --depth) {
+    int64_t blocks = (((int64_t)1 << depth) + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+#define KD_SB_T(T, KK)                                                                          \
+  hipLaunchKernelGGL((k_subtree_bounds<T, KK>), dim3((unsigned)blocks), dim3(256), 0, st,       \
+                     static_cast<const T*>(nodes), n, nn, depth, static_cast<T*>(bounds))
+#define KD_SB_I(KK) KD_SB_T(int32_t, KK)
+#define KD_SB_F(KK) KD_SB_T(float, KK)
+    if (is_float) {
+      KD_FOR_K(KD_SB_F)
+    } else {
+      KD_FOR_K(KD_SB_I)
+    }
+#undef KD_SB_F
+#undef KD_SB_I
+#undef KD_SB_T
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_region(const void* nodes, const void* bounds, int64_t n, int k, int is_float,
+                         const int32_t* perm, const int64_t* nn, const void* lower,
+                         const void* upper, int64_t nq, int32_t* counts, const int64_t* offsets,
+                         int32_t* rows, int64_t cap, unsigned long long* visits, hipStream_t st) {
   if (nq <= 0) return hipSuccess;
   const bool want_rows = offsets != nullptr;
 #define KD_RG_T(T, KK)                                                                          \
   do {                                                                                          \
     if (want_rows)                                                                              \
       hipLaunchKernelGGL((k_region<T, KK, true>), dim3(query_blocks(nq)), dim3(kQThreads), 0, st, \
-                         static_cast<const T*>(nodes), n, perm, nn, static_cast<const T*>(lower), \
+                         static_cast<const T*>(nodes), static_cast<const T*>(bounds), n, perm, nn, \
+                         static_cast<const T*>(lower),                                          \
                          static_cast<const T*>(upper), nq, counts, offsets, rows, cap, visits);  \
     else                                                                                        \
       hipLaunchKernelGGL((k_region<T, KK, false>), dim3(query_blocks(nq)), dim3(kQThreads), 0, st, \
-                         static_cast<const T*>(nodes), n, perm, nn, static_cast<const T*>(lower), \
+                         static_cast<const T*>(nodes), static_cast<const T*>(bounds), n, perm, nn, \
+                         static_cast<const T*>(lower),                                          \
                          static_cast<const T*>(upper), nq, counts, offsets, rows, cap, visits);  \
   } while (0)
 #define KD_RG_I(KK) KD_RG_T(int32_t, KK)

@@ -147,27 +147,27 @@ def test_queries_reject_bad_arguments(L):
     assert L.lib.kd_gather_nodes(F, 100, 3, 0, F, vp(FAKE8 + 4), F, None) == -1
     assert L.lib.kd_gather_nodes(F, 0, 3, 0, F, F8, None, None) == 0  # no rows: nothing to do
     # region counts: bad k, dtype, n, nq; null and misaligned pointers
-    assert L.lib.kd_region_count(F, 100, 0, 0, F8, F, F, 10, F, None, None) == -1
-    assert L.lib.kd_region_count(F, 100, 9, 0, F8, F, F, 10, F, None, None) == -4
-    assert L.lib.kd_region_count(F, 100, 3, 2, F8, F, F, 10, F, None, None) == -1
-    assert L.lib.kd_region_count(F, -1, 3, 0, F8, F, F, 10, F, None, None) == -1
-    assert L.lib.kd_region_count(F, 100, 3, 0, F8, F, F, -1, F, None, None) == -1
-    assert L.lib.kd_region_count(F, 100, 3, 0, F8, F, F, (1 << 28) + 1, F, None, None) == -4
-    assert L.lib.kd_region_count(None, 100, 3, 0, F8, F, F, 10, F, None, None) == -1
-    assert L.lib.kd_region_count(F, 100, 3, 0, None, F, F, 10, F, None, None) == -1
-    assert L.lib.kd_region_count(F, 100, 3, 0, F8, None, F, 10, F, None, None) == -1
-    assert L.lib.kd_region_count(F, 100, 3, 0, F8, F, F, 10, None, None, None) == -1
-    assert L.lib.kd_region_count(vp(FAKE + 2), 100, 3, 0, F8, F, F, 10, F, None, None) == -1
-    assert L.lib.kd_region_count(F, 100, 3, 0, vp(FAKE8 + 4), F, F, 10, F, None, None) == -1
-    assert L.lib.kd_region_count(F, 100, 3, 0, F8, F, F, 10, F, vp(FAKE8 + 4), None) == -1
+    assert L.lib.kd_region_count(F, None, 100, 0, 0, F8, F, F, 10, F, None, None) == -1
+    assert L.lib.kd_region_count(F, None, 100, 9, 0, F8, F, F, 10, F, None, None) == -4
+    assert L.lib.kd_region_count(F, None, 100, 3, 2, F8, F, F, 10, F, None, None) == -1
+    assert L.lib.kd_region_count(F, None, -1, 3, 0, F8, F, F, 10, F, None, None) == -1
+    assert L.lib.kd_region_count(F, None, 100, 3, 0, F8, F, F, -1, F, None, None) == -1
+    assert L.lib.kd_region_count(F, None, 100, 3, 0, F8, F, F, (1 << 28) + 1, F, None, None) == -4
+    assert L.lib.kd_region_count(None, None, 100, 3, 0, F8, F, F, 10, F, None, None) == -1
+    assert L.lib.kd_region_count(F, None, 100, 3, 0, None, F, F, 10, F, None, None) == -1
+    assert L.lib.kd_region_count(F, None, 100, 3, 0, F8, None, F, 10, F, None, None) == -1
+    assert L.lib.kd_region_count(F, None, 100, 3, 0, F8, F, F, 10, None, None, None) == -1
+    assert L.lib.kd_region_count(vp(FAKE + 2), None, 100, 3, 0, F8, F, F, 10, F, None, None) == -1
+    assert L.lib.kd_region_count(F, None, 100, 3, 0, vp(FAKE8 + 4), F, F, 10, F, None, None) == -1
+    assert L.lib.kd_region_count(F, None, 100, 3, 0, F8, F, F, 10, F, vp(FAKE8 + 4), None) == -1
     # no queries: nothing to do
-    assert L.lib.kd_region_count(F, 100, 3, 0, F8, None, None, 0, None, None, None) == 0
+    assert L.lib.kd_region_count(F, None, 100, 3, 0, F8, None, None, 0, None, None, None) == 0
     # region rows: null perm, negative capacity, null offsets, rows null with a capacity
-    assert L.lib.kd_region_rows(F, 100, 3, 0, None, F8, F, F, 10, F8, F, 10, None, None) == -1
-    assert L.lib.kd_region_rows(F, 100, 3, 0, F, F8, F, F, 10, F8, F, -1, None, None) == -1
-    assert L.lib.kd_region_rows(F, 100, 3, 0, F, F8, F, F, 10, None, F, 10, None, None) == -1
-    assert L.lib.kd_region_rows(F, 100, 3, 0, F, F8, F, F, 10, F8, None, 10, None, None) == -1
-    assert L.lib.kd_region_rows(F, 100, 3, 0, F, F8, F, F, 10, vp(FAKE8 + 4), F, 10, None, None) == -1
+    assert L.lib.kd_region_rows(F, None, 100, 3, 0, None, F8, F, F, 10, F8, F, 10, None, None) == -1
+    assert L.lib.kd_region_rows(F, None, 100, 3, 0, F, F8, F, F, 10, F8, F, -1, None, None) == -1
+    assert L.lib.kd_region_rows(F, None, 100, 3, 0, F, F8, F, F, 10, None, F, 10, None, None) == -1
+    assert L.lib.kd_region_rows(F, None, 100, 3, 0, F, F8, F, F, 10, F8, None, 10, None, None) == -1
+    assert L.lib.kd_region_rows(F, None, 100, 3, 0, F, F8, F, F, 10, vp(FAKE8 + 4), F, 10, None, None) == -1
     # nearest: null perm, m out of range, null points or rows
     assert L.lib.kd_nearest(F, 100, 3, 0, None, F8, F, 10, 4, F, None, None) == -1
     assert L.lib.kd_nearest(F, 100, 3, 0, F, F8, F, 10, 0, F, None, None) == -1
@@ -175,6 +175,11 @@ def test_queries_reject_bad_arguments(L):
     assert L.lib.kd_nearest(F, 100, 3, 0, F, F8, None, 10, 4, F, None, None) == -1
     assert L.lib.kd_nearest(F, 100, 3, 0, F, F8, F, 10, 4, None, None, None) == -1
     assert L.lib.kd_nearest(F, 100, 3, 1, F, F8, F, 0, 4, None, None, None) == 0
+    # subtree bounds: null output, misaligned bounds given to a search
+    assert L.lib.kd_subtree_bounds(F, 100, 3, 0, F8, None, None) == -1
+    assert L.lib.kd_subtree_bounds(F, 100, 9, 0, F8, F, None) == -4
+    assert L.lib.kd_subtree_bounds(F, 0, 3, 0, F8, None, None) == 0
+    assert L.lib.kd_region_count(F, vp(FAKE + 2), 100, 3, 0, F8, F, F, 10, F, None, None) == -1
     assert L.lib.kd_probe_start(11, 10) == -1
 
 

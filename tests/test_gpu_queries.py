@@ -96,7 +96,13 @@ def check_region(kd, t, dt, perm, nu, lo, hi, with_oracle=True):
     assert np.array_equal(nodes[:nu].cpu().numpy(), t[p])
     counts = kd.region_count(dt, perm, nu, dlo, dhi, nodes=nodes).cpu().numpy()
     assert np.array_equal(kd.region_count(dt, perm, nu, dlo, dhi).cpu().numpy(), counts)
+    bounds = kd.subtree_bounds(nodes, nu)
+    check_bounds(t[p], bounds[:nu].cpu().numpy())
+    assert np.array_equal(kd.region_count(dt, perm, nu, dlo, dhi, nodes=nodes, bounds=bounds).cpu().numpy(),
+                          counts)
+    rows_b, offs_b = kd.region_rows(dt, perm, nu, dlo, dhi, nodes=nodes, bounds=bounds)
     rows, offs = kd.region_rows(dt, perm, nu, dlo, dhi, nodes=nodes)
+    assert torch.equal(rows_b, rows) and torch.equal(offs_b, offs)
     rows, offs = rows.cpu().numpy(), offs.cpu().numpy()
     assert np.array_equal(np.diff(offs), counts)
     nodes = t[p]
@@ -107,6 +113,24 @@ def check_region(kd, t, dt, perm, nu, lo, hi, with_oracle=True):
         assert sorted(got.tolist()) == sorted(p[inside].tolist()), f"box {q}"
         if with_oracle:
             assert sorted(got.tolist()) == oq.region_search(t, p, lo[q].tolist(), hi[q].tolist())
+
+
+def check_bounds(nodes: np.ndarray, bounds: np.ndarray):
+    """Every subtree's box is the min / max over its contiguous range."""
+    nu, k = nodes.shape
+
+    def walk(s, e):
+        if e < s:
+            return
+        m = s + (e - s) // 2
+        sub = nodes[s:e + 1]
+        assert np.array_equal(bounds[m, :k], sub.min(axis=0)), (s, e)
+        assert np.array_equal(bounds[m, k:], sub.max(axis=0)), (s, e)
+        walk(s, m - 1)
+        walk(m + 1, e)
+
+    if nu <= 4096:
+        walk(0, nu - 1)
 
 
 def check_nearest(kd, t, dt, perm, nu, pts, m, with_oracle=True):
@@ -195,6 +219,12 @@ def test_visit_counter(kd):
                     torch.from_numpy(everything[1]).cuda(), visits=v)
     assert int(v.item()) == nu  # a box around everything visits every node once
     v.zero_()
+    nodes = kd.gather_nodes(dt, perm, nu)
+    c = kd.region_count(dt, perm, nu, torch.from_numpy(everything[0]).cuda(),
+                        torch.from_numpy(everything[1]).cuda(), visits=v, nodes=nodes,
+                        bounds=kd.subtree_bounds(nodes, nu))
+    assert int(v.item()) == 1 and int(c.item()) == nu  # with bounds: the root's box is inside
+    v.zero_()
     kd.nearest(dt, perm, nu, torch.from_numpy(t[:3]).cuda(), 1, visits=v)
     assert 3 <= int(v.item()) < 3 * nu
 
@@ -218,6 +248,10 @@ def test_queries_large_brute_force(kd, dtype):
                              torch.from_numpy(hi).cuda()).cpu().numpy()
     pts = query_points(g, t, nq)
     got = kd.nearest(dt, perm, nu, torch.from_numpy(pts).cuda(), 8).cpu().numpy()
+    dn = kd.gather_nodes(dt, perm, nu)
+    counts_b = kd.region_count(dt, perm, nu, torch.from_numpy(lo).cuda(), torch.from_numpy(hi).cuda(),
+                               nodes=dn, bounds=kd.subtree_bounds(dn, nu)).cpu().numpy()
+    assert np.array_equal(counts_b, counts)
     for q in g.choice(nq, size=24, replace=False):
         inside = np.all((nodes >= lo[q]) & (nodes <= hi[q]), axis=1)
         assert counts[q] == int(inside.sum()), f"box {q}"
@@ -267,3 +301,27 @@ def test_all_nearest_and_reverse(kd, k, dtype, n):
     assert offsets[0] == 0 and offsets[-1] == sum(len(v) for v in want.values())
     for r in range(n):
         assert lists[offsets[r]:offsets[r + 1]].tolist() == want.get(r, []), f"row {r}"
+
+
+def test_region_with_nan_coordinates(kd):
+    # a NaN coordinate is never inside a box; subtree boxes holding a NaN are
+    # walked, so the counts with and without bounds agree with a scan
+    g = kdgen.rng(990)
+    t = g.normal(size=(4000, 3)).astype(np.float32)
+    t[g.integers(0, 4000, size=400), g.integers(0, 3, size=400)] = np.nan
+    t[g.integers(0, 4000, size=200), g.integers(0, 3, size=200)] = -np.nan
+    print("[gpu case] region with NaN coordinates", flush=True)
+    dt, perm, nu = gpu_tree(kd, t)
+    p = perm.cpu().numpy()
+    nodes_h = t[p]
+    lo, hi = boxes(g, t[~np.isnan(t).any(axis=1)], 100)
+    dn = kd.gather_nodes(dt, perm, nu)
+    bounds = kd.subtree_bounds(dn, nu)
+    dlo, dhi = torch.from_numpy(lo).cuda(), torch.from_numpy(hi).cuda()
+    c0 = kd.region_count(dt, perm, nu, dlo, dhi, nodes=dn).cpu().numpy()
+    c1 = kd.region_count(dt, perm, nu, dlo, dhi, nodes=dn, bounds=bounds).cpu().numpy()
+    assert np.array_equal(c0, c1)
+    for q in range(lo.shape[0]):
+        with np.errstate(invalid="ignore"):
+            inside = np.all((nodes_h >= lo[q]) & (nodes_h <= hi[q]), axis=1)
+        assert c1[q] == int(inside.sum()), f"box {q}"

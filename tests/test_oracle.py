@@ -270,3 +270,25 @@ def test_all_nearest_and_reverse_lists(dtype):
             want.setdefault(rr, []).append(int(perm[pos]))
     assert rev == {k: sorted(v) for k, v in want.items()}
     assert sum(len(v) for v in rev.values()) == m * len(perm)
+
+
+def test_region_search_with_nan_coordinates():
+    # a NaN coordinate is never inside a box, and a NaN split value does not
+    # prune the subtrees below it: the search equals a linear scan
+    g = kdgen.rng(35)
+    t = g.normal(size=(500, 3)).astype(np.float32)
+    # positive and negative NaNs, dense enough that some split values are NaN
+    t[g.integers(0, 500, size=60), g.integers(0, 3, size=60)] = np.nan
+    t[g.integers(0, 500, size=30), g.integers(0, 3, size=30)] = -np.nan
+    r = oracle.build_tree(t)
+    perm = r["perm"]
+    nodes = t[perm]
+    for _ in range(30):
+        a, b = g.normal(size=3) * 1.5, g.normal(size=3) * 1.5
+        lower, upper = np.minimum(a, b).astype(np.float32), np.maximum(a, b).astype(np.float32)
+        with np.errstate(invalid="ignore"):
+            inside = np.all((nodes >= lower) & (nodes <= upper), axis=1)
+        want = sorted(int(v) for v in perm[inside])
+        assert queries.region_search(t, perm, lower.tolist(), upper.tolist()) == want
+    everything = queries.region_search(t, perm, [-1e9] * 3, [1e9] * 3)
+    assert len(everything) == int((~np.isnan(nodes).any(axis=1)).sum())
