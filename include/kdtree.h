@@ -236,8 +236,9 @@ int kdtree_presort_learned(const void* d_tuples, int64_t n, int32_t k, int32_t d
  * values occur when a later portion of the super key decides), so the
  * results are exactly those of a linear scan over the tree's nodes.
  * Coordinates compare as values of dtype (float32: IEEE comparisons, so
- * -0.0 == +0.0 and a NaN coordinate is never inside a box; distances that
- * involve NaN order unpredictably).
+ * -0.0 == +0.0 and a NaN coordinate is never inside a box, while a NaN split
+ * value prunes neither side; a node whose distance is NaN is never a
+ * neighbour).
  *
  * The searches read the nodes' coordinates in tree-position order, written
  * once per tree by kd_gather_nodes: a visit is one read at the node's own
