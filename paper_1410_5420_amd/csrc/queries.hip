@@ -655,20 +655,47 @@ __global__ __launch_bounds__(256) void k_rev_fill(const int32_t* __restrict__ ro
   }
 }
 
-// every list in ascending order (insertion sort by one thread)
+// every list in ascending order, by one thread: insertion sort for the usual
+// short lists, heapsort (L log L at worst) once a list is longer than 32 (a
+// row that is among the nearest of very many nodes has a long list)
+__device__ __forceinline__ void rev_sift(int32_t* __restrict__ v, int64_t i, int64_t len) {
+  for (;;) {
+    const int64_t l = 2 * i + 1;
+    if (l >= len) return;
+    int64_t c = l;
+    if (l + 1 < len && v[l + 1] > v[l]) c = l + 1;
+    if (!(v[c] > v[i])) return;
+    const int32_t t = v[i];
+    v[i] = v[c];
+    v[c] = t;
+    i = c;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_rev_sort(int64_t n, const int64_t* __restrict__ offsets,
                                                  int32_t* __restrict__ lists) {
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
        r += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t a = offsets[r], b = offsets[r + 1];
-    for (int64_t i = a + 1; i < b; ++i) {
-      const int32_t v = lists[i];
-      int64_t j = i - 1;
-      while (j >= a && lists[j] > v) {
-        lists[j + 1] = lists[j];
-        --j;
+    const int64_t a = offsets[r], len = offsets[r + 1] - a;
+    int32_t* v = lists + a;
+    if (len <= 32) {
+      for (int64_t i = 1; i < len; ++i) {
+        const int32_t x = v[i];
+        int64_t j = i - 1;
+        while (j >= 0 && v[j] > x) {
+          v[j + 1] = v[j];
+          --j;
+        }
+        v[j + 1] = x;
       }
-      lists[j + 1] = v;
+      continue;
+    }
+    for (int64_t i = len / 2 - 1; i >= 0; --i) rev_sift(v, i, len);
+    for (int64_t end = len - 1; end > 0; --end) {
+      const int32_t t = v[0];
+      v[0] = v[end];
+      v[end] = t;
+      rev_sift(v, 0, end);
     }
   }
 }

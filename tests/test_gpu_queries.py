@@ -325,3 +325,24 @@ def test_region_with_nan_coordinates(kd):
         with np.errstate(invalid="ignore"):
             inside = np.all((nodes_h >= lo[q]) & (nodes_h <= hi[q]), axis=1)
         assert c1[q] == int(inside.sum()), f"box {q}"
+
+
+def test_reverse_lists_with_a_hub_row(kd):
+    # a neighbour table in which every node names the same row: that row's
+    # reverse list holds every node (sorted at L log L, not L^2)
+    n, m = 1 << 18, 4
+    print(f"[gpu case] reverse lists with a hub row n={n}", flush=True)
+    g = kdgen.rng(995)
+    perm = torch.from_numpy(g.permutation(n).astype(np.int32)).cuda()
+    near = torch.from_numpy(g.integers(0, n, size=(n, m)).astype(np.int32)).cuda()
+    hub = 12345
+    near[:, 0] = hub
+    offsets, lists = kd.reverse_nearest(perm, n, near)
+    o, l = offsets.cpu().numpy(), lists.cpu().numpy()
+    got = l[o[hub]:o[hub + 1]]
+    nr, pm = near.cpu().numpy(), perm.cpu().numpy()
+    want = np.sort(np.repeat(pm, (nr == hub).sum(axis=1)))
+    assert np.array_equal(got, want)
+    for r in g.choice(n, size=50, replace=False):
+        want_r = np.sort(np.repeat(pm, (nr == r).sum(axis=1)))
+        assert np.array_equal(l[o[r]:o[r + 1]], want_r), f"row {r}"
