@@ -80,14 +80,26 @@ def onesweep_bytes(n: int, nu: int, k: int):
 def level_bytes(nu: int, k: int, cutover: int):
     """(total algorithmic bytes, launches) of the global partition levels:
     every array but the split one is read once and written once; a moving
-    record holds k-1 ranks (row ids stay in the level-0 records)."""
+    record holds k-1 ranks (row ids stay in the level-0 records).  The last
+    level feeds the on-chip finish, which reads only the order-0 rank of
+    arrays 1 .. k-1: array 0 stays put, and the others read the plane that
+    decides the side plus the order-0 plane and write the order-0 plane."""
     R = k - 1
     levels = 0
     while (nu >> levels) > cutover:
         levels += 1
     total = 0
     for L in range(levels):
-        total += nu * R * R * 4 * 2
+        if L < levels - 1:
+            total += nu * R * R * 4 * 2
+            continue
+        p = L % k
+        for a in range(R):
+            j = (p + 1 + a) % k
+            if j == 0:
+                continue
+            cp, c0 = (p - j - 1 + 2 * k) % k, k - 1 - j
+            total += nu * 4 * (len({cp, c0}) + 1)
     return total, levels
 
 
@@ -97,7 +109,8 @@ def byte_model(kernel: str, n: int, nu: int, k: int, cutover: int):
     if kernel == "level":
         total, launches = level_bytes(nu, k, cutover)
         return total / max(launches, 1), (f"{launches} levels: per level (k-1) arrays x (k-1) ranks "
-                                          f"x 4 B, read + write, x n_unique")
+                                          f"x 4 B, read + write, x n_unique; the last level only "
+                                          f"the planes the on-chip finish reads")
     if kernel == "onesweep":
         total, launches = onesweep_bytes(n, nu, k)
         return total / launches, f"radix key + payload words of the build's {launches} passes, averaged"

@@ -582,7 +582,8 @@ int partition_impl(const Job& J, hipStream_t st) {
       for (int d = 0; d < levels; ++d)
         KD_LAUNCH(KD_K_LEVEL, launch_level(r0, S, r1, r2, n, k, d, cutover, fa, J.perm,
                                            at<void>(ws, L.seginfo), at<uint32_t>(ws, L.lcnt),
-                                           at<uint64_t>(ws, L.lcarry), lstat, ltick, st));
+                                           at<uint64_t>(ws, L.lcarry), lstat, ltick,
+                                           J.B == 1 && d == levels - 1, st));
       // the finish takes its items from a counter; partition may run again
       // after one presort, so the counter is cleared here
       KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(fa.queue), 0u, 1, st));

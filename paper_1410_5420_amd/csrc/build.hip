@@ -432,13 +432,14 @@ __device__ uint64_t level_lookback(const LookBack& lb, uint64_t agg, bool head, 
 // kFused: the carry comes from the look-back instead of `carry`.
 // The tile's subarrays (gsi, global) are copied to si (LDS) while the planes
 // are in flight.
+// wmask: the planes to write (bit c: plane c); the others are not read again.
 template <int W, bool kFused>
 __device__ __forceinline__ void level_move_tile(const uint32_t* __restrict__ src,
                                                uint32_t* __restrict__ dst, int64_t n, int cp,
                                                int t0, int t1, const SegInfo* __restrict__ gsi,
                                                SegInfo& si, uint64_t carry, uint32_t* s_chunk,
                                                uint32_t* s_pre, const LookBack& lb,
-                                               uint64_t* s_carry) {
+                                               uint64_t* s_carry, uint32_t wmask) {
   const int tid = threadIdx.x;
   const int w = tid / kWave;
   const int lane = tid % kWave;
@@ -447,10 +448,11 @@ __device__ __forceinline__ void level_move_tile(const uint32_t* __restrict__ src
 #pragma unroll
   for (int c = 0; c < W; ++c) {
     const uint32_t* sp = src + (int64_t)c * n;
+    const bool need = ((wmask >> c) & 1u) || c == cp;  // written, or decides the side
 #pragma unroll
     for (int it = 0; it < kLvItems; ++it) {
       const int i = t0 + it * kLvThreads + tid;
-      v[c][it] = i < t1 ? sp[i] : 0u;
+      v[c][it] = need && i < t1 ? sp[i] : 0u;
     }
   }
   if (tid < kMaxSeg) {
@@ -548,6 +550,7 @@ __device__ __forceinline__ void level_move_tile(const uint32_t* __restrict__ src
   }
 #pragma unroll
   for (int c = 0; c < W; ++c) {
+    if (!((wmask >> c) & 1u)) continue;
     uint32_t* dp = dst + (int64_t)c * n;
 #pragma unroll
     for (int it = 0; it < kLvItems; ++it)
@@ -560,18 +563,30 @@ __global__ __launch_bounds__(kLvThreads) void k_level_move(const RecBufs B, cons
                                                           int64_t n, int k, int depth,
                                                           const SegInfo* __restrict__ seginfo,
                                                           const uint64_t* __restrict__ carry,
-                                                          int tiles_per_array) {
+                                                          int tiles_per_array, int skip_a) {
   __shared__ uint32_t s_chunk[kLvChunks];
   __shared__ uint32_t s_pre[kLevelTile];
   __shared__ SegInfo s_si;
   const int nu = F.uoff[F.B];
-  if (depth >= *F.lmax) return;
+  const int lmax = *F.lmax;
+  if (depth >= lmax) return;
   const int p = depth % k;
+  // XCD-aware: each XCD takes a contiguous range of (array, tile) numbers.
+  // skip_a >= 0: the grid leaves out moving array skip_a (array 0 at the
+  // last level, which stays put), so no XCD is handed only idle tiles.
   const int bt = xcd_tile(blockIdx.x, gridDim.x);
-  const int a = bt / tiles_per_array;
+  int a = bt / tiles_per_array;
   const int t = bt % tiles_per_array;
+  if (skip_a >= 0 && a >= skip_a) ++a;
   if (a >= k - 1) return;
   const int j = (p + 1 + a) % k;
+  // The deepest global level (the last one for every tree still at global
+  // levels) is followed by the on-chip finish, which reads only the order-0
+  // plane of arrays 1 .. k-1 and nothing of array 0: array 0 stays put and
+  // the others write that one plane.
+  const bool last = depth == lmax - 1;
+  if (last && j == 0) return;
+  const uint32_t wmask = last ? 1u << (k - 1 - j) : ~0u;
   const int t0 = t * kLevelTile;
   if (t0 >= nu) return;
   const int t1 = min(t0 + kLevelTile, nu);
@@ -582,7 +597,7 @@ __global__ __launch_bounds__(kLvThreads) void k_level_move(const RecBufs B, cons
   const int cp = (p - j - 1 + 2 * k) % k;
   const LookBack lb{};
   level_move_tile<R, false>(src, dst, n, cp, t0, t1, seginfo + t, s_si, cy, s_chunk, s_pre, lb,
-                            nullptr);
+                            nullptr, wmask);
 }
 
 // Count, chain and move in one launch (look-back).  Tile numbers come from
@@ -617,14 +632,14 @@ __global__ __launch_bounds__(kLvThreads) void k_level_fused(const RecBufs B, con
   const int cp = (p - j - 1 + 2 * k) % k;
   const LookBack lb{status, k - 1, a, t, (uint32_t)depth + 1};
   level_move_tile<R, true>(src, dst, n, cp, t0, t1, seginfo + t, s_si, 0, s_chunk, s_pre, lb,
-                           &s_carry);
+                           &s_carry, ~0u);
 }
 
 hipError_t launch_level(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1, uint32_t* b2,
                         int64_t n, int k,
                         int depth, int64_t cutover, const ForestArgs& fa, int32_t* perm,
                         void* seginfo, uint32_t* cnt, uint64_t* carry, uint64_t* status,
-                        int32_t* tickets, hipStream_t st) {
+                        int32_t* tickets, bool last, hipStream_t st) {
   if (n <= 0 || k < 2) return hipSuccess;
   const int tiles = (int)((n + kLevelTile - 1) / kLevelTile);
   const unsigned grid = (unsigned)(tiles * (k - 1));
@@ -666,10 +681,16 @@ hipError_t launch_level(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_level_scan, dim3(k - 1), dim3(1024), 0, st, F, depth, tval, carry, tiles);
+  // the last level before the on-chip finish: array 0 stays put (when it is
+  // one of the moving arrays), so its tiles are left out of the grid
+  const int p = depth % k;
+  const int skip_a = last && p != 0 ? k - 1 - p : -1;
+  const unsigned mgrid = skip_a >= 0 ? (unsigned)(tiles * (k - 2)) : grid;
+  if (mgrid == 0) return hipGetLastError();  // k == 2: the only moving array is array 0
 #define KD_LV(RR)                                                                               \
-  hipLaunchKernelGGL(k_level_move<RR>, dim3(xcd_grid(grid)), dim3(kLvThreads), 0, st, B, F, n, \
+  hipLaunchKernelGGL(k_level_move<RR>, dim3(xcd_grid(mgrid)), dim3(kLvThreads), 0, st, B, F, n, \
                      k, depth,                                                                   \
-                     si, carry, tiles)
+                     si, carry, tiles, skip_a)
   switch (k - 1) {
     case 1: KD_LV(1); break;
     case 2: KD_LV(2); break;
