@@ -194,7 +194,8 @@ __global__ __launch_bounds__(kSegThreads) void k_level_seg(const RecBufs B, cons
                                                           int k, int depth, int64_t cutover,
                                                           int32_t* __restrict__ perm,
                                                           SegInfo* __restrict__ seginfo,
-                                                          uint64_t* __restrict__ tval, int tiles) {
+                                                          uint64_t* __restrict__ tval, int tiles,
+                                                          int skip_j0) {
   __shared__ SegInfo s_si;
   __shared__ uint32_t s_c[kMaxK];
   const int tid = threadIdx.x;
@@ -213,10 +214,12 @@ __global__ __launch_bounds__(kSegThreads) void k_level_seg(const RecBufs B, cons
     const int cp = (p - j - 1 + 2 * k) % k;  // the plane holding the rank in order p
     const uint32_t* plane = buf_after(B, moves_before(depth, j, k)) + record_offset(j, k, n) +
                             (int64_t)cp * n;
+    // skip_j0: array 0 stays put at this level, so its counts are not needed
+    const bool need = !(skip_j0 && j == 0);
 #pragma unroll
     for (int it = 0; it < kSegItems; ++it) {
       const int i = t0 + it * kSegThreads + tid;
-      rp[a][it] = i < tl ? plane[i] : 0u;
+      rp[a][it] = need && i < tl ? plane[i] : 0u;
     }
   }
   const int nu = F.uoff[F.B];
@@ -647,9 +650,10 @@ hipError_t launch_level(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1
   Forest F{fa.B, fa.off, fa.uoff, fa.lmax, fa.wgbase, fa.queue};
   SegInfo* si = static_cast<SegInfo*>(seginfo);
   uint64_t* tval = status ? nullptr : reinterpret_cast<uint64_t*>(cnt);
+  const int skip_j0 = last && status == nullptr && depth % k != 0 ? 1 : 0;
 #define KD_SEG(RR)                                                                                  \
   hipLaunchKernelGGL(k_level_seg<RR>, dim3(tiles), dim3(kSegThreads), 0, st, B, F, n, k, depth, cutover, \
-                     perm, si, tval, tiles)
+                     perm, si, tval, tiles, skip_j0)
   switch (status ? 0 : k - 1) {
     case 0: KD_SEG(0); break;
     case 1: KD_SEG(1); break;
