@@ -77,29 +77,46 @@ def onesweep_bytes(n: int, nu: int, k: int):
     return 4 * words, launches
 
 
+def level_write_masks(k: int, levels: int):
+    """The planes each level's move writes (per array), walking back from the
+    on-chip finish exactly as the library does: later levels and the finish
+    read, of a split array p, plane 0 and (p != 0) its order-0 plane; of a
+    moving array, the side-deciding plane and every plane it writes; the
+    finish reads the order-0 plane of arrays 1 .. k-1."""
+    need = [0] * k
+    for j in range(1, k):
+        need[j] = 1 << (k - 1 - j)
+    masks = [None] * levels
+    for d in range(levels - 1, -1, -1):
+        p = d % k
+        masks[d] = {j: need[j] for j in range(k) if j != p}
+        for j in range(k):
+            if j == p:
+                need[j] |= 1
+                if p != 0:
+                    need[j] |= 1 << ((k - p - 1) % k)
+            elif need[j]:
+                need[j] |= 1 << ((p - j - 1 + 2 * k) % k)
+    return masks
+
+
 def level_bytes(nu: int, k: int, cutover: int):
     """(total algorithmic bytes, launches) of the global partition levels:
-    every array but the split one is read once and written once; a moving
-    record holds k-1 ranks (row ids stay in the level-0 records).  The last
-    level feeds the on-chip finish, which reads only the order-0 rank of
-    arrays 1 .. k-1: array 0 stays put, and the others read the plane that
-    decides the side plus the order-0 plane and write the order-0 plane."""
-    R = k - 1
+    every moving array reads the plane that decides the side and the planes
+    it moves, and writes the planes later levels or the on-chip finish read
+    (all k-1 rank planes except near the end; row ids stay in the level-0
+    records)."""
     levels = 0
     while (nu >> levels) > cutover:
         levels += 1
     total = 0
-    for L in range(levels):
-        if L < levels - 1:
-            total += nu * R * R * 4 * 2
-            continue
-        p = L % k
-        for a in range(R):
-            j = (p + 1 + a) % k
-            if j == 0:
+    for d, m in enumerate(level_write_masks(k, levels)):
+        p = d % k
+        for j, w in m.items():
+            if not w:
                 continue
-            cp, c0 = (p - j - 1 + 2 * k) % k, k - 1 - j
-            total += nu * 4 * (len({cp, c0}) + 1)
+            cp = (p - j - 1 + 2 * k) % k
+            total += nu * 4 * (bin(w | (1 << cp)).count("1") + bin(w).count("1"))
     return total, levels
 
 
@@ -109,8 +126,8 @@ def byte_model(kernel: str, n: int, nu: int, k: int, cutover: int):
     if kernel == "level":
         total, launches = level_bytes(nu, k, cutover)
         return total / max(launches, 1), (f"{launches} levels: per level (k-1) arrays x (k-1) ranks "
-                                          f"x 4 B, read + write, x n_unique; the last level only "
-                                          f"the planes the on-chip finish reads")
+                                          f"x 4 B, read + write, x n_unique; near the end only the "
+                                          f"planes later levels and the on-chip finish read")
     if kernel == "onesweep":
         total, launches = onesweep_bytes(n, nu, k)
         return total / launches, f"radix key + payload words of the build's {launches} passes, averaged"

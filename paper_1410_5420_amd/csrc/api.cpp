@@ -579,11 +579,15 @@ int partition_impl(const Job& J, hipStream_t st) {
                                2 * level_tiles(n) * (k - 1), st));
         KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(ltick), 0u, kMaxLevels, st));
       }
+      // one tree: every level moves only the planes later levels and the
+      // on-chip finish read (a batch's trees end at different depths)
+      std::vector<uint64_t> wm(levels > 0 ? levels : 1, ~0ull);
+      if (J.B == 1 && !lookback && levels > 0) level_write_masks(k, levels, wm.data());
       for (int d = 0; d < levels; ++d)
         KD_LAUNCH(KD_K_LEVEL, launch_level(r0, S, r1, r2, n, k, d, cutover, fa, J.perm,
                                            at<void>(ws, L.seginfo), at<uint32_t>(ws, L.lcnt),
-                                           at<uint64_t>(ws, L.lcarry), lstat, ltick,
-                                           J.B == 1 && d == levels - 1, st));
+                                           at<uint64_t>(ws, L.lcarry), lstat, ltick, wm[d],
+                                           st));
       // the finish takes its items from a counter; partition may run again
       // after one presort, so the counter is cleared here
       KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(fa.queue), 0u, 1, st));

@@ -195,7 +195,7 @@ __global__ __launch_bounds__(kSegThreads) void k_level_seg(const RecBufs B, cons
                                                           int32_t* __restrict__ perm,
                                                           SegInfo* __restrict__ seginfo,
                                                           uint64_t* __restrict__ tval, int tiles,
-                                                          int skip_j0) {
+                                                          uint64_t wmasks) {
   __shared__ SegInfo s_si;
   __shared__ uint32_t s_c[kMaxK];
   const int tid = threadIdx.x;
@@ -214,8 +214,8 @@ __global__ __launch_bounds__(kSegThreads) void k_level_seg(const RecBufs B, cons
     const int cp = (p - j - 1 + 2 * k) % k;  // the plane holding the rank in order p
     const uint32_t* plane = buf_after(B, moves_before(depth, j, k)) + record_offset(j, k, n) +
                             (int64_t)cp * n;
-    // skip_j0: array 0 stays put at this level, so its counts are not needed
-    const bool need = !(skip_j0 && j == 0);
+    // an array that writes no plane at this level stays put: no counts
+    const bool need = ((wmasks >> (8 * j)) & 0xFFu) != 0;
 #pragma unroll
     for (int it = 0; it < kSegItems; ++it) {
       const int i = t0 + it * kSegThreads + tid;
@@ -566,7 +566,8 @@ __global__ __launch_bounds__(kLvThreads) void k_level_move(const RecBufs B, cons
                                                           int64_t n, int k, int depth,
                                                           const SegInfo* __restrict__ seginfo,
                                                           const uint64_t* __restrict__ carry,
-                                                          int tiles_per_array, int skip_a) {
+                                                          int tiles_per_array, int skip_a,
+                                                          uint64_t wmasks) {
   __shared__ uint32_t s_chunk[kLvChunks];
   __shared__ uint32_t s_pre[kLevelTile];
   __shared__ SegInfo s_si;
@@ -587,9 +588,12 @@ __global__ __launch_bounds__(kLvThreads) void k_level_move(const RecBufs B, cons
   // levels) is followed by the on-chip finish, which reads only the order-0
   // plane of arrays 1 .. k-1 and nothing of array 0: array 0 stays put and
   // the others write that one plane.
-  const bool last = depth == lmax - 1;
-  if (last && j == 0) return;
-  const uint32_t wmask = last ? 1u << (k - 1 - j) : ~0u;
+  // wmasks (8 bits per array: the planes later levels and the finish read),
+  // or all ones when the caller does not know the levels ahead (a batch):
+  // then only the deepest level is trimmed, to what the finish reads
+  uint32_t wmask = (uint32_t)(wmasks >> (8 * j)) & 0xFFu;
+  if (wmasks == ~0ull) wmask = depth == lmax - 1 ? (j == 0 ? 0u : 1u << (k - 1 - j)) : ~0u;
+  if (wmask == 0) return;
   const int t0 = t * kLevelTile;
   if (t0 >= nu) return;
   const int t1 = min(t0 + kLevelTile, nu);
@@ -642,7 +646,7 @@ hipError_t launch_level(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1
                         int64_t n, int k,
                         int depth, int64_t cutover, const ForestArgs& fa, int32_t* perm,
                         void* seginfo, uint32_t* cnt, uint64_t* carry, uint64_t* status,
-                        int32_t* tickets, bool last, hipStream_t st) {
+                        int32_t* tickets, uint64_t wmasks, hipStream_t st) {
   if (n <= 0 || k < 2) return hipSuccess;
   const int tiles = (int)((n + kLevelTile - 1) / kLevelTile);
   const unsigned grid = (unsigned)(tiles * (k - 1));
@@ -650,10 +654,10 @@ hipError_t launch_level(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1
   Forest F{fa.B, fa.off, fa.uoff, fa.lmax, fa.wgbase, fa.queue};
   SegInfo* si = static_cast<SegInfo*>(seginfo);
   uint64_t* tval = status ? nullptr : reinterpret_cast<uint64_t*>(cnt);
-  const int skip_j0 = last && status == nullptr && depth % k != 0 ? 1 : 0;
+  const uint64_t seg_masks = status == nullptr ? wmasks : ~0ull;
 #define KD_SEG(RR)                                                                                  \
   hipLaunchKernelGGL(k_level_seg<RR>, dim3(tiles), dim3(kSegThreads), 0, st, B, F, n, k, depth, cutover, \
-                     perm, si, tval, tiles, skip_j0)
+                     perm, si, tval, tiles, seg_masks)
   switch (status ? 0 : k - 1) {
     case 0: KD_SEG(0); break;
     case 1: KD_SEG(1); break;
@@ -685,16 +689,16 @@ hipError_t launch_level(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_level_scan, dim3(k - 1), dim3(1024), 0, st, F, depth, tval, carry, tiles);
-  // the last level before the on-chip finish: array 0 stays put (when it is
-  // one of the moving arrays), so its tiles are left out of the grid
+  // array 0 staying put at this level (it writes no plane): its tiles are
+  // left out of the grid
   const int p = depth % k;
-  const int skip_a = last && p != 0 ? k - 1 - p : -1;
+  const int skip_a = wmasks != ~0ull && p != 0 && (wmasks & 0xFFu) == 0 ? k - 1 - p : -1;
   const unsigned mgrid = skip_a >= 0 ? (unsigned)(tiles * (k - 2)) : grid;
   if (mgrid == 0) return hipGetLastError();  // k == 2: the only moving array is array 0
 #define KD_LV(RR)                                                                               \
   hipLaunchKernelGGL(k_level_move<RR>, dim3(xcd_grid(mgrid)), dim3(kLvThreads), 0, st, B, F, n, \
                      k, depth,                                                                   \
-                     si, carry, tiles, skip_a)
+                     si, carry, tiles, skip_a, wmasks)
   switch (k - 1) {
     case 1: KD_LV(1); break;
     case 2: KD_LV(2); break;
@@ -710,6 +714,33 @@ hipError_t launch_level(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1
 }
 
 size_t level_seginfo_bytes() { return sizeof(SegInfo); }
+
+// Walking back from the on-chip finish (which reads the order-0 plane of
+// arrays 1 .. k-1 and nothing of array 0): a level's move writes exactly the
+// planes that later levels or the finish read.  A level reads, of its split
+// array p, plane 0 (the median's rank in order p+1) and, when p != 0, the
+// order-0 plane (the median's row id); of every array it moves, the plane
+// deciding the side and every plane it writes.  An array with nothing to
+// write stays put and is not read.
+void level_write_masks(int k, int levels, uint64_t* masks) {
+  uint32_t need[kMaxK] = {};
+  for (int j = 1; j < k; ++j) need[j] = 1u << (k - 1 - j);
+  for (int d = levels - 1; d >= 0; --d) {
+    const int p = d % k;
+    uint64_t m = 0;
+    for (int j = 0; j < k; ++j)
+      if (j != p) m |= (uint64_t)need[j] << (8 * j);
+    masks[d] = m;
+    for (int j = 0; j < k; ++j) {
+      if (j == p) {
+        need[j] |= 1u;
+        if (p != 0) need[j] |= 1u << ((k - p - 1) % k);
+      } else if (need[j] != 0) {
+        need[j] |= 1u << ((p - j - 1 + 2 * k) % k);
+      }
+    }
+  }
+}
 
 // ---- on-chip finish (leaf phase) -----------------------------------------------------
 // One workgroup takes one subarray of at most C elements at the cutover depth

@@ -137,16 +137,20 @@ hipError_t launch_complete_records(uint32_t* rec, int64_t n, int k, const int32_
 // (k-1) * level_tiles(n) 64-bit words of tile counts, carry (k-1) *
 // level_tiles(n) 64-bit words); otherwise the counts are chained by
 // look-back inside the move launch (status (k-1) * level_tiles(n) 64-bit
-// words and tickets kMaxLevels words, both zeroed before depth 0).  At the
-// deepest global level the move writes only what the on-chip finish reads;
-// last (set by a caller that knows this is that level) also leaves array 0's
-// tiles out of the launch.
+// words and tickets kMaxLevels words, both zeroed before depth 0).
+// wmasks: for every array j, bits 8j .. 8j+7 = the record planes its move
+// writes (the planes later levels and the on-chip finish read; an array with
+// none stays put and is left out of the launch); ~0 when unknown, and then
+// only the deepest level is trimmed, to what the finish reads.
 constexpr int kMaxLevels = 64;
 hipError_t launch_level(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1, uint32_t* b2,
                         int64_t n, int k,
                         int depth, int64_t cutover, const ForestArgs& fa, int32_t* perm,
                         void* seginfo, uint32_t* cnt, uint64_t* carry, uint64_t* status,
-                        int32_t* tickets, bool last, hipStream_t st);
+                        int32_t* tickets, uint64_t wmasks, hipStream_t st);
+// The write masks of every global level of one tree with `levels` global
+// levels (element d for depth d).
+void level_write_masks(int k, int levels, uint64_t* masks);
 size_t level_seginfo_bytes();
 inline int64_t level_tiles(int64_t n) { return (n + kLevelTile - 1) / kLevelTile; }
 
