@@ -304,7 +304,10 @@ int kd_all_nearest(const void* d_nodes, int64_t n, int32_t k, int32_t dtype, con
 /* Reverse nearest neighbours (the same Appendix section: the points to which
  * a point is a nearest neighbour) from kd_all_nearest's output: the list of
  * row r is d_lists[d_offsets[r]] .. d_lists[d_offsets[r + 1] - 1], the rows
- * of the nodes that have r among their m nearest, in ascending order.
+ * of the nodes that have r among their m nearest, in ascending order.  Any
+ * table of that shape is accepted (entries that are not a row below n are
+ * ignored); a row may appear in at most 2^32 - 1 entries in all, which
+ * kd_all_nearest's output (a row at most once per node) always meets.
  *   d_offsets   int64[n + 1] over row ids 0 .. n-1 (a row that is no node
  *               has an empty list)
  *   d_lists     int32[n * m] (at most n_nodes * m entries are written)
