@@ -345,7 +345,8 @@ def main():
     if not args.no_forms:
         plain_perm = perm.clone()
         out["forms"] = {"learned_c2": learned_form(torch, kd, t, plain_perm, nu, args, "c2 (same input)",
-                                                   knobs)}
+                                                   knobs),
+                        "deferred_c2": deferred_form(torch, kd, t, plain_perm, nu, args, knobs)}
         del b, t, perm, plain_perm
         torch.cuda.empty_cache()
         out["forms"]["learned_c5"] = learned_c5(torch, kd, kdgen, args)
@@ -460,8 +461,9 @@ def queries_c2(torch, kd, _lib, kdgen, t, t_host, perm, n_nodes, nu, args):
 def select_c3(torch, kd, kdgen, args):
     """The paper's comparison (its Fig. 7 varies k): the presort builder
     against the per-level sorting builder on the C3 inputs (n = 2^22, 256
-    Gaussian clusters, 10% copies) for k in {2, 3, 4, 6, 8}; both produce the
-    same tree, checked here."""
+    Gaussian clusters, 10% copies) for k in {2, 3, 4, 6, 8}, and the presort
+    builder with deferred partitioning (level form 3); all produce the same
+    tree, checked here."""
     res = {"workload": "C3: k in {2,3,4,6,8}, n=2^22 int32 from 256 Gaussian clusters "
                        "(sigma 2^12), 10% exact copies", "per_k": {}}
     reps = max(3, args.steps // 4)
@@ -470,21 +472,40 @@ def select_c3(torch, kd, kdgen, args):
         t = torch.from_numpy(x).cuda()
         n = t.shape[0]
         b = kd.Builder(n, k, torch.int32)
+        db = kd.Builder(n, k, torch.int32, level=3)
         sb = kd.SelectBuilder(n, k, torch.int32)
         p1 = torch.full((n,), -1, dtype=torch.int32, device=t.device)
         p2 = torch.full((n,), -1, dtype=torch.int32, device=t.device)
+        p3 = torch.full((n,), -1, dtype=torch.int32, device=t.device)
         plain_ms = time_steps(torch, lambda: b.build(t, p1), reps, 1)
+        def_ms = time_steps(torch, lambda: db.build(t, p3), reps, 1)
         sel_ms = time_steps(torch, lambda: sb.build(t, p2), reps, 1)
         nu = int(b.n_unique.item())
         same = int(sb.n_unique.item()) == nu and torch.equal(p1[:nu], p2[:nu])
+        dsame = int(db.n_unique.item()) == nu and torch.equal(p1[:nu], p3[:nu])
         res["per_k"][str(k)] = {"presort_builder_ms": round(plain_ms, 3),
+                                "deferred_partitioning_ms": round(def_ms, 3),
                                 "select_builder_ms": round(sel_ms, 3),
-                                "ratio": round(sel_ms / plain_ms, 2), "same_tree": bool(same)}
-        log(f"c3 k={k}: presort builder {plain_ms:.2f} ms, per-level sorting builder {sel_ms:.2f} ms, "
-            f"same={same}")
-        del b, sb, p1, p2, t
+                                "ratio": round(sel_ms / plain_ms, 2),
+                                "same_tree": bool(same and dsame)}
+        log(f"c3 k={k}: presort builder {plain_ms:.2f} ms, deferred partitioning {def_ms:.2f} ms, "
+            f"per-level sorting builder {sel_ms:.2f} ms, same={same} {dsame}")
+        del b, db, sb, p1, p2, p3, t
         torch.cuda.empty_cache()
     return res
+
+
+def deferred_form(torch, kd, t, plain_perm, nu, args, knobs):
+    """Deferred partitioning (level form 3) on the same input: build time and
+    equality with the plain perm."""
+    n, k = t.shape
+    kn = {key: v for key, v in knobs.items() if key != "level"}
+    db = kd.Builder(n, k, t.dtype, level=3, **kn)
+    perm = torch.full((n,), -1, dtype=torch.int32, device=t.device)
+    ms = time_steps(torch, lambda: db.build(t, perm), max(5, args.steps // 2), 2)
+    same = int(db.n_unique.item()) == nu and torch.equal(perm[:nu], plain_perm[:nu])
+    log(f"deferred partitioning c2: {ms:.3f} ms, same={same}")
+    return {"workload": "c2 (same input)", "build_ms": round(ms, 3), "same_tree": bool(same)}
 
 
 def learned_form(torch, kd, t, plain_perm, nu, args, label, knobs=None):

@@ -38,7 +38,7 @@ int tree_digit_passes(int B) {
 struct Layout {
   size_t vbuf, carry, S, rec0, rec1, rec2;
   size_t rcnt, rgrp, dcnt, seginfo, lcnt, lcarry, lstat, ltick;
-  size_t uoff, wgbase, lmax, queue, offs, ties;
+  size_t uoff, wgbase, lmax, queue, offs, ties, nodes;
   size_t starts, flags, lkey, carry2;  // learned presort only
   size_t end;
 };
@@ -84,6 +84,7 @@ Layout plan(int64_t n, int k, int B, bool learned = false) {
   L.queue = take(4);
   L.offs = take(16);
   L.ties = take(4 * ((size_t)kMaxTieRuns + 2));  // run list, count, flag
+  L.nodes = take(4 * ((size_t)1 << (kMaxK - 1)));  // node ranks of deferred partitioning
   if (learned) {
     L.starts = take(4 * (((size_t)1 << kMaxBucketBits) + 1));
     L.flags = take(4 * kMaxK);
@@ -111,7 +112,7 @@ int check_opts(const kd_options* opts, int64_t* cutover, int* leaf_blocks, int* 
   if (opts) {
     for (int i = 0; i < 3; ++i)
       if (opts->reserved[i] != 0) return KD_EINVAL;
-    if (opts->level < 0 || opts->level > 2) return KD_EINVAL;
+    if (opts->level < 0 || opts->level > 3) return KD_EINVAL;
     *level = opts->level;
     if (opts->learned_sorts < 0 || opts->learned_sorts > 0xFF) return KD_EINVAL;
     *learned_sorts = opts->learned_sorts;
@@ -581,18 +582,57 @@ int partition_impl(const Job& J, hipStream_t st) {
       }
       // one tree: every level moves only the planes later levels and the
       // on-chip finish read (a batch's trees end at different depths)
+      const int defer = J.level == 3 && J.B == 1 && k >= 3 ? 1 : 0;
       std::vector<uint64_t> wm(levels > 0 ? levels : 1, ~0ull);
-      if (J.B == 1 && !lookback && levels > 0) level_write_masks(k, levels, wm.data());
-      for (int d = 0; d < levels; ++d)
+      if (J.B == 1 && !lookback && levels > 0) level_write_masks(k, levels, wm.data(), defer);
+      // Deferred partitioning: array j >= 2 reaches its layout at depth
+      // min(j, deepest global level) in one stable radix pass by bucket
+      // (keys in the radix slots, which the partition does not use), right
+      // before the level that splits it, or before the finish when no such
+      // level runs; the node ranks of depth d are taken while array d has its
+      // depth-d layout.
+      uint32_t* nodes = at<uint32_t>(ws, L.nodes);
+      uint32_t* dkey = at<uint32_t>(ws, L.vbuf);
+      const int32_t* nu_dev = fa.uoff + 1;
+      auto split = [&](int j) -> int {
+        KD_LAUNCH(KD_K_LEVEL, launch_defer_bucket(r0, S, r1, r2, n, k, j, fa, nodes, dkey, st));
+        Payload pay{};
+        pay.count = k - 1;
+        for (int c = 0; c < k - 1; ++c) {
+          const int64_t o = record_offset(j, k, n) + (int64_t)c * n;
+          pay.p[c].in = r0 + o;
+          pay.p[c].out = r1 + o;  // one write: the first moved-record buffer
+          pay.p[c].kind = kPlaneArray;
+          pay.p[c].word = 0;
+        }
+        const TupleSrc none{nullptr, k, 0};
+        KD_LAUNCH(KD_K_LEVEL, launch_radix_pass(dkey, none, 0, nullptr, pay, n, nu_dev, 0,
+                                                at<uint32_t>(ws, L.rcnt), at<uint32_t>(ws, L.rgrp),
+                                                st, RadixExtra{}));
+        return KD_OK;
+      };
+      for (int d = 0; d < levels; ++d) {
+        if (defer && d >= 2 && d < k) {
+          const int rc = split(d);
+          if (rc != KD_OK) return rc;
+        }
+        if (defer && d <= k - 2)
+          KD_LAUNCH(KD_K_LEVEL, launch_node_ranks(r0, S, r1, r2, n, k, d, fa, nodes, st));
         KD_LAUNCH(KD_K_LEVEL, launch_level(r0, S, r1, r2, n, k, d, cutover, fa, J.perm,
                                            at<void>(ws, L.seginfo), at<uint32_t>(ws, L.lcnt),
                                            at<uint64_t>(ws, L.lcarry), lstat, ltick, wm[d],
-                                           st));
+                                           defer, st));
+      }
+      if (defer)
+        for (int j = levels > 2 ? levels : 2; j < k; ++j) {
+          const int rc = split(j);
+          if (rc != KD_OK) return rc;
+        }
       // the finish takes its items from a counter; partition may run again
       // after one presort, so the counter is cleared here
       KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(fa.queue), 0u, 1, st));
       KD_LAUNCH(KD_K_LEAF, launch_leaf(r0, S, r1, r2, n, k, cutover, fa, J.perm, items, J.leaf_blocks,
-                                       st));
+                                       defer, st));
     }
     if (J.lo && J.hi) KD_TRY(launch_children(fa.uoff, n, J.lo, J.hi, st));
   }

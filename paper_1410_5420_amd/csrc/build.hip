@@ -29,6 +29,11 @@ __device__ __host__ __forceinline__ int moves_before(int depth, int j, int k) {
 // Record buffers: level-0 records stay untouched in rec0 (they double as the
 // rank-translation tables); moved arrays alternate between b1 and b2.  rows:
 // the row id of every order-0 rank (the deduplicated order-0 id array).
+// Deferred partitioning (Appendix, "Deferred Merge Sort and Partitioning",
+// in the form that suits radix sorts; one tree only): every array j >= 2
+// keeps its presorted order until depth j and then reaches its depth-j
+// layout in one stable split (one write into b1), which stands for its
+// first j moves.
 struct RecBufs {
   const uint32_t* rec0;
   const uint32_t* rows;
@@ -37,6 +42,20 @@ struct RecBufs {
 };
 __device__ __forceinline__ const uint32_t* buf_after(const RecBufs& B, int moves) {
   return moves == 0 ? B.rec0 : ((moves & 1) ? B.b1 : B.b2);
+}
+// Writes into array j's records before `depth`.  Deferred, an array j >= 2
+// is only read from depth j on, or by the on-chip finish of a tree whose
+// global levels end above depth j; its split output counts as one write.
+__device__ __host__ __forceinline__ int array_moves(int defer, int depth, int j, int k) {
+  if (!defer || j < 2) return moves_before(depth, j, k);
+  return depth >= j ? moves_before(depth, j, k) - (j - 1) : 1;
+}
+// Array j's records as they are at `depth` (kDefer: deferred partitioning;
+// a template argument, so that the plain build carries no test of it).
+template <bool kDefer>
+__device__ __forceinline__ const uint32_t* rec_array(const RecBufs& B, int depth, int j, int k,
+                                                     int64_t n) {
+  return buf_after(B, array_moves(kDefer ? 1 : 0, depth, j, k)) + record_offset(j, k, n);
 }
 
 // ---- forests ------------------------------------------------------------------
@@ -135,6 +154,7 @@ __device__ __forceinline__ T wave_sum(T v) {
 
 // Wave 0 of a block: subarrays meeting [t0, t1) at `depth`, their medians'
 // ranks in order p, and (write_perm) the row id of every median in the tile.
+template <bool kDefer>
 __device__ void find_subarrays(const RecBufs& B, const Forest& F, int64_t n, int k, int depth,
                                int64_t cutover, int t0, int t1, bool write_perm, int32_t* perm,
                                SegInfo* out) {
@@ -163,7 +183,7 @@ __device__ void find_subarrays(const RecBufs& B, const Forest& F, int64_t n, int
       // in order p+1 (plane 0), and the level-0 records of array p+1 translate
       // that (their plane k-2 is order p).
       const int m = s + ((e - s) >> 1);
-      const uint32_t* split = buf_after(B, moves_before(depth, p, k)) + record_offset(p, k, n);
+      const uint32_t* split = rec_array<kDefer>(B, depth, p, k, n);
       const uint32_t r1 = split[m];
       const int p1 = (p + 1) % k;
       const uint32_t rp = B.rec0[record_offset(p1, k, n) + (int64_t)(k - 2) * n + r1];
@@ -189,7 +209,8 @@ __device__ void find_subarrays(const RecBufs& B, const Forest& F, int64_t n, int
 // loaded before the subarrays are known, so the loads overlap that search.
 constexpr int kSegThreads = 256;
 constexpr int kSegItems = kLevelTile / kSegThreads;
-template <int R>  // moving arrays counted (k - 1, or 0 when only the subarrays are wanted)
+// R: moving arrays counted (k - 1, or 0 when only the subarrays are wanted)
+template <int R, bool kDefer>
 __global__ __launch_bounds__(kSegThreads) void k_level_seg(const RecBufs B, const Forest F, int64_t n,
                                                           int k, int depth, int64_t cutover,
                                                           int32_t* __restrict__ perm,
@@ -212,8 +233,7 @@ __global__ __launch_bounds__(kSegThreads) void k_level_seg(const RecBufs B, cons
   for (int a = 0; a < R; ++a) {
     const int j = (p + 1 + a) % k;
     const int cp = (p - j - 1 + 2 * k) % k;  // the plane holding the rank in order p
-    const uint32_t* plane = buf_after(B, moves_before(depth, j, k)) + record_offset(j, k, n) +
-                            (int64_t)cp * n;
+    const uint32_t* plane = rec_array<kDefer>(B, depth, j, k, n) + (int64_t)cp * n;
     // an array that writes no plane at this level stays put: no counts
     const bool need = ((wmasks >> (8 * j)) & 0xFFu) != 0;
 #pragma unroll
@@ -225,7 +245,8 @@ __global__ __launch_bounds__(kSegThreads) void k_level_seg(const RecBufs B, cons
   const int nu = F.uoff[F.B];
   if (depth >= *F.lmax || t0 >= nu) return;
   const int t1 = min(t0 + kLevelTile, nu);
-  if (tid < kWave) find_subarrays(B, F, n, k, depth, cutover, t0, t1, true, perm, &s_si);
+  if (tid < kWave)
+    find_subarrays<kDefer>(B, F, n, k, depth, cutover, t0, t1, true, perm, &s_si);
   if (tid < kMaxK) s_c[tid] = 0;
   __syncthreads();
   if (tid < kMaxSeg) {
@@ -561,12 +582,12 @@ __device__ __forceinline__ void level_move_tile(const uint32_t* __restrict__ src
   }
 }
 
-template <int R>
+template <int R, bool kDefer>
 __global__ __launch_bounds__(kLvThreads) void k_level_move(const RecBufs B, const Forest F,
                                                           int64_t n, int k, int depth,
                                                           const SegInfo* __restrict__ seginfo,
                                                           const uint64_t* __restrict__ carry,
-                                                          int tiles_per_array, int skip_a,
+                                                          int tiles_per_array, uint32_t arows,
                                                           uint64_t wmasks) {
   __shared__ uint32_t s_chunk[kLvChunks];
   __shared__ uint32_t s_pre[kLevelTile];
@@ -576,12 +597,14 @@ __global__ __launch_bounds__(kLvThreads) void k_level_move(const RecBufs B, cons
   if (depth >= lmax) return;
   const int p = depth % k;
   // XCD-aware: each XCD takes a contiguous range of (array, tile) numbers.
-  // skip_a >= 0: the grid leaves out moving array skip_a (array 0 at the
-  // last level, which stays put), so no XCD is handed only idle tiles.
+  // The grid covers only the moving arrays that write anything (the others
+  // stay put), so no XCD is handed only idle tiles: grid row r moves array
+  // (p + 1 + a) mod k with a = bits 4r .. 4r+3 of `arows` (15: no array).
   const int bt = xcd_tile(blockIdx.x, gridDim.x);
-  int a = bt / tiles_per_array;
+  const int r = bt / tiles_per_array;
   const int t = bt % tiles_per_array;
-  if (skip_a >= 0 && a >= skip_a) ++a;
+  if (r >= 8) return;
+  const int a = (int)((arows >> (4 * r)) & 0xFu);
   if (a >= k - 1) return;
   const int j = (p + 1 + a) % k;
   // The deepest global level (the last one for every tree still at global
@@ -598,7 +621,7 @@ __global__ __launch_bounds__(kLvThreads) void k_level_move(const RecBufs B, cons
   if (t0 >= nu) return;
   const int t1 = min(t0 + kLevelTile, nu);
   const uint64_t cy = carry[(int64_t)a * tiles_per_array + t];
-  const int mj = moves_before(depth, j, k);
+  const int mj = array_moves(kDefer ? 1 : 0, depth, j, k);
   const uint32_t* src = buf_after(B, mj) + record_offset(j, k, n);
   uint32_t* dst = const_cast<uint32_t*>(buf_after(B, mj + 1)) + record_offset(j, k, n);
   const int cp = (p - j - 1 + 2 * k) % k;
@@ -646,18 +669,25 @@ hipError_t launch_level(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1
                         int64_t n, int k,
                         int depth, int64_t cutover, const ForestArgs& fa, int32_t* perm,
                         void* seginfo, uint32_t* cnt, uint64_t* carry, uint64_t* status,
-                        int32_t* tickets, uint64_t wmasks, hipStream_t st) {
+                        int32_t* tickets, uint64_t wmasks, int defer, hipStream_t st) {
   if (n <= 0 || k < 2) return hipSuccess;
   const int tiles = (int)((n + kLevelTile - 1) / kLevelTile);
   const unsigned grid = (unsigned)(tiles * (k - 1));
   RecBufs B{rec0, rows, b1, b2};
   Forest F{fa.B, fa.off, fa.uoff, fa.lmax, fa.wgbase, fa.queue};
   SegInfo* si = static_cast<SegInfo*>(seginfo);
+  if (defer && status) return hipErrorInvalidValue;  // deferred: three-launch levels only
   uint64_t* tval = status ? nullptr : reinterpret_cast<uint64_t*>(cnt);
   const uint64_t seg_masks = status == nullptr ? wmasks : ~0ull;
-#define KD_SEG(RR)                                                                                  \
-  hipLaunchKernelGGL(k_level_seg<RR>, dim3(tiles), dim3(kSegThreads), 0, st, B, F, n, k, depth, cutover, \
-                     perm, si, tval, tiles, seg_masks)
+#define KD_SEG(RR)                                                                                \
+  do {                                                                                            \
+    if (defer)                                                                                    \
+      hipLaunchKernelGGL((k_level_seg<RR, true>), dim3(tiles), dim3(kSegThreads), 0, st, B, F, n, k, \
+                         depth, cutover, perm, si, tval, tiles, seg_masks);                       \
+    else                                                                                          \
+      hipLaunchKernelGGL((k_level_seg<RR, false>), dim3(tiles), dim3(kSegThreads), 0, st, B, F, n, \
+                         k, depth, cutover, perm, si, tval, tiles, seg_masks);                    \
+  } while (0)
   switch (status ? 0 : k - 1) {
     case 0: KD_SEG(0); break;
     case 1: KD_SEG(1); break;
@@ -689,16 +719,27 @@ hipError_t launch_level(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_level_scan, dim3(k - 1), dim3(1024), 0, st, F, depth, tval, carry, tiles);
-  // array 0 staying put at this level (it writes no plane): its tiles are
-  // left out of the grid
+  // arrays staying put at this level (they write no plane) are left out of
+  // the grid
   const int p = depth % k;
-  const int skip_a = wmasks != ~0ull && p != 0 && (wmasks & 0xFFu) == 0 ? k - 1 - p : -1;
-  const unsigned mgrid = skip_a >= 0 ? (unsigned)(tiles * (k - 2)) : grid;
-  if (mgrid == 0) return hipGetLastError();  // k == 2: the only moving array is array 0
+  uint32_t arows = ~0u;
+  int nact = 0;
+  for (int a = 0; a < k - 1; ++a)
+    if (wmasks == ~0ull || ((wmasks >> (8 * ((p + 1 + a) % k))) & 0xFFu) != 0) {
+      arows = (arows & ~(0xFu << (4 * nact))) | ((uint32_t)a << (4 * nact));
+      ++nact;
+    }
+  const unsigned mgrid = (unsigned)(tiles * nact);
+  if (mgrid == 0) return hipGetLastError();
 #define KD_LV(RR)                                                                               \
-  hipLaunchKernelGGL(k_level_move<RR>, dim3(xcd_grid(mgrid)), dim3(kLvThreads), 0, st, B, F, n, \
-                     k, depth,                                                                   \
-                     si, carry, tiles, skip_a, wmasks)
+  do {                                                                                          \
+    if (defer)                                                                                  \
+      hipLaunchKernelGGL((k_level_move<RR, true>), dim3(xcd_grid(mgrid)), dim3(kLvThreads), 0, st, \
+                         B, F, n, k, depth, si, carry, tiles, arows, wmasks);                   \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_level_move<RR, false>), dim3(xcd_grid(mgrid)), dim3(kLvThreads), 0, \
+                         st, B, F, n, k, depth, si, carry, tiles, arows, wmasks);               \
+  } while (0)
   switch (k - 1) {
     case 1: KD_LV(1); break;
     case 2: KD_LV(2); break;
@@ -721,15 +762,16 @@ size_t level_seginfo_bytes() { return sizeof(SegInfo); }
 // array p, plane 0 (the median's rank in order p+1) and, when p != 0, the
 // order-0 plane (the median's row id); of every array it moves, the plane
 // deciding the side and every plane it writes.  An array with nothing to
-// write stays put and is not read.
-void level_write_masks(int k, int levels, uint64_t* masks) {
+// write stays put and is not read.  Deferred, arrays j >= 2 write nothing
+// above depth j (their split writes every plane).
+void level_write_masks(int k, int levels, uint64_t* masks, int defer) {
   uint32_t need[kMaxK] = {};
   for (int j = 1; j < k; ++j) need[j] = 1u << (k - 1 - j);
   for (int d = levels - 1; d >= 0; --d) {
     const int p = d % k;
     uint64_t m = 0;
     for (int j = 0; j < k; ++j)
-      if (j != p) m |= (uint64_t)need[j] << (8 * j);
+      if (j != p && !(defer && j >= 2 && d < j)) m |= (uint64_t)need[j] << (8 * j);
     masks[d] = m;
     for (int j = 0; j < k; ++j) {
       if (j == p) {
@@ -740,6 +782,92 @@ void level_write_masks(int k, int levels, uint64_t* masks) {
       }
     }
   }
+}
+
+// ---- deferred partitioning: the split of array j ----------------------------------
+// One tree only.  node_rank[(1 << d) - 1 + q] is the rank in order d of the
+// node of subarray q at depth d (subarrays numbered left to right), taken
+// once array d has its depth-d layout: the median sits at the middle of the
+// subarray in array d, and the level-0 records of array d+1 translate its
+// rank in order d+1 (plane 0) to order d, as at a global level.
+__global__ __launch_bounds__(64) void k_node_ranks(const RecBufs B, const Forest F, int64_t n,
+                                                   int k, int depth,
+                                                   uint32_t* __restrict__ node_rank) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (1 << depth) || depth >= *F.lmax) return;
+  const int base = F.uoff[0];
+  int s = 0, e = F.uoff[1] - base - 1;
+  for (int l = 0; l < depth; ++l) {
+    const int m = s + ((e - s) >> 1);
+    if ((q >> (depth - 1 - l)) & 1)
+      s = m + 1;
+    else
+      e = m - 1;
+  }
+  if (e < s) return;  // not reached: global-level subarrays hold at least C rows
+  const int p = depth % k;
+  const int m = base + s + ((e - s) >> 1);
+  const uint32_t r1 = rec_array<true>(B, depth, p, k, n)[m];
+  if (r1 >= (uint32_t)n) return;  // not reached: a rank
+  node_rank[(1 << depth) - 1 + q] = B.rec0[record_offset((p + 1) % k, k, n) + (int64_t)(k - 2) * n + r1];
+}
+
+// Bucket of every element of array j (level-0 records, presorted order j)
+// among the subarrays and nodes of depth D = min(j, deepest global level),
+// numbered in order (subarray q is 2q; the node of subarray q at depth d < D
+// sits between the halves below it, at q * 2^(D-d+1) + 2^(D-d) - 1).  The
+// element walks down from the root comparing its rank in order d with the
+// node's.  A stable sort by bucket then gives array j's layout at depth D.
+__global__ __launch_bounds__(256) void k_defer_bucket(const RecBufs B, const Forest F, int64_t n,
+                                                      int k, int j,
+                                                      const uint32_t* __restrict__ node_rank,
+                                                      uint32_t* __restrict__ key) {
+  __shared__ uint32_t s_nr[1 << (kMaxK - 1)];
+  const int lmax = *F.lmax;
+  const int D = j < lmax ? j : lmax;
+  for (int i = threadIdx.x; i < (1 << D) - 1; i += blockDim.x) s_nr[i] = node_rank[i];
+  __syncthreads();
+  const int base = F.uoff[0];
+  const int nu = F.uoff[1] - base;
+  const uint32_t* rec = B.rec0 + record_offset(j, k, n);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nu; i += gridDim.x * blockDim.x) {
+    uint32_t q = 0, b = 0xFFFFFFFFu;
+    for (int d = 0; d < D; ++d) {
+      const int c = (d - j - 1 + 2 * k) % k;  // the plane holding the rank in order d
+      const uint32_t r = rec[(int64_t)c * n + base + i];
+      const uint32_t nr = s_nr[(1 << d) - 1 + q];
+      if (r == nr) {
+        b = q * (2u << (D - d)) + (1u << (D - d)) - 1u;
+        break;
+      }
+      q = 2 * q + (r > nr ? 1u : 0u);
+    }
+    key[base + i] = b != 0xFFFFFFFFu ? b : 2 * q;
+  }
+}
+
+hipError_t launch_node_ranks(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1,
+                             uint32_t* b2, int64_t n, int k, int depth, const ForestArgs& fa,
+                             uint32_t* node_rank, hipStream_t st) {
+  if (n <= 0 || k < 2 || fa.B != 1 || depth < 0 || depth > kMaxK - 2) return hipErrorInvalidValue;
+  RecBufs B{rec0, rows, b1, b2};
+  Forest F{fa.B, fa.off, fa.uoff, fa.lmax, fa.wgbase, fa.queue};
+  const int nodes = 1 << depth;
+  hipLaunchKernelGGL(k_node_ranks, dim3((nodes + 63) / 64), dim3(64), 0, st, B, F, n, k, depth,
+                     node_rank);
+  return hipGetLastError();
+}
+
+hipError_t launch_defer_bucket(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1,
+                               uint32_t* b2, int64_t n, int k, int j, const ForestArgs& fa,
+                               const uint32_t* node_rank, uint32_t* key, hipStream_t st) {
+  if (n <= 0 || k < 3 || fa.B != 1 || j < 2 || j >= k) return hipErrorInvalidValue;
+  RecBufs B{rec0, rows, b1, b2};
+  Forest F{fa.B, fa.off, fa.uoff, fa.lmax, fa.wgbase, fa.queue};
+  const int64_t want = (n + 255) / 256;
+  const unsigned grid = (unsigned)(want < 4096 ? want : 4096);
+  hipLaunchKernelGGL(k_defer_bucket, dim3(grid), dim3(256), 0, st, B, F, n, k, j, node_rank, key);
+  return hipGetLastError();
 }
 
 // ---- on-chip finish (leaf phase) -----------------------------------------------------
@@ -839,7 +967,7 @@ __device__ bool lds_radix_sort(uint32_t* ka, uint16_t* va, uint32_t* kb, uint16_
   return flipped;
 }
 
-template <int kItems, int R>
+template <int kItems, int R, bool kDefer>
 __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Forest F, int64_t n,
                                                     int /* k: R + 1 */, int32_t* __restrict__ perm) {
   constexpr int k = R + 1;  // known at compile time: index arithmetic mod k folds
@@ -892,7 +1020,7 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
   // local id, and the sorted list lets the other arrays find theirs by binary
   // search.  The row ids are read at the end at the order-0 ranks.
   {
-    const uint32_t* a1 = buf_after(B, moves_before(lc, 1, k)) + record_offset(1, k, n);
+    const uint32_t* a1 = rec_array<kDefer>(B, lc, 1, k, n);
     uint32_t* sk = reinterpret_cast<uint32_t*>(s_lid);        // sort scratch (aliases s_lid)
     uint16_t* sv = reinterpret_cast<uint16_t*>(sk + C);
     uint16_t* sv2 = sv + C;
@@ -929,7 +1057,7 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
       }
     }
     for (int j = 2; j < k; ++j) {
-      const uint32_t* aj = buf_after(B, moves_before(lc, j, k)) + record_offset(j, k, n);
+      const uint32_t* aj = rec_array<kDefer>(B, lc, j, k, n);
       const int c0 = k - 1 - j;  // plane of order 0 in array j
 #pragma unroll
       for (int it = 0; it < kItems; ++it) {
@@ -1085,7 +1213,7 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
 hipError_t launch_leaf(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1, uint32_t* b2,
                        int64_t n, int k,
                        int64_t cutover, const ForestArgs& fa, int32_t* perm, int64_t items_bound,
-                       int blocks, hipStream_t st) {
+                       int blocks, int defer, hipStream_t st) {
   if (n <= 0 || k < 2) return hipSuccess;
   const size_t lds = leaf_lds_bytes(cutover, k);
   RecBufs B{rec0, rows, b1, b2};
@@ -1093,13 +1221,27 @@ hipError_t launch_leaf(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1,
   const void* fn = nullptr;
 #define KD_LF_R(IT)                                                  \
   switch (k - 1) {                                                   \
-    case 1: fn = reinterpret_cast<const void*>(k_leaf<IT, 1>); break; \
-    case 2: fn = reinterpret_cast<const void*>(k_leaf<IT, 2>); break; \
-    case 3: fn = reinterpret_cast<const void*>(k_leaf<IT, 3>); break; \
-    case 4: fn = reinterpret_cast<const void*>(k_leaf<IT, 4>); break; \
-    case 5: fn = reinterpret_cast<const void*>(k_leaf<IT, 5>); break; \
-    case 6: fn = reinterpret_cast<const void*>(k_leaf<IT, 6>); break; \
-    case 7: fn = reinterpret_cast<const void*>(k_leaf<IT, 7>); break; \
+    case 1: fn = defer ? reinterpret_cast<const void*>(k_leaf<IT, 1, true>)   \
+                 : reinterpret_cast<const void*>(k_leaf<IT, 1, false>); \
+      break;                                                         \
+    case 2: fn = defer ? reinterpret_cast<const void*>(k_leaf<IT, 2, true>)   \
+                 : reinterpret_cast<const void*>(k_leaf<IT, 2, false>); \
+      break;                                                         \
+    case 3: fn = defer ? reinterpret_cast<const void*>(k_leaf<IT, 3, true>)   \
+                 : reinterpret_cast<const void*>(k_leaf<IT, 3, false>); \
+      break;                                                         \
+    case 4: fn = defer ? reinterpret_cast<const void*>(k_leaf<IT, 4, true>)   \
+                 : reinterpret_cast<const void*>(k_leaf<IT, 4, false>); \
+      break;                                                         \
+    case 5: fn = defer ? reinterpret_cast<const void*>(k_leaf<IT, 5, true>)   \
+                 : reinterpret_cast<const void*>(k_leaf<IT, 5, false>); \
+      break;                                                         \
+    case 6: fn = defer ? reinterpret_cast<const void*>(k_leaf<IT, 6, true>)   \
+                 : reinterpret_cast<const void*>(k_leaf<IT, 6, false>); \
+      break;                                                         \
+    case 7: fn = defer ? reinterpret_cast<const void*>(k_leaf<IT, 7, true>)   \
+                 : reinterpret_cast<const void*>(k_leaf<IT, 7, false>); \
+      break;                                                         \
     default: return hipErrorInvalidValue;                            \
   }
   switch (cutover) {

@@ -147,10 +147,22 @@ hipError_t launch_level(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1
                         int64_t n, int k,
                         int depth, int64_t cutover, const ForestArgs& fa, int32_t* perm,
                         void* seginfo, uint32_t* cnt, uint64_t* carry, uint64_t* status,
-                        int32_t* tickets, uint64_t wmasks, hipStream_t st);
+                        int32_t* tickets, uint64_t wmasks, int defer, hipStream_t st);
 // The write masks of every global level of one tree with `levels` global
-// levels (element d for depth d).
-void level_write_masks(int k, int levels, uint64_t* masks);
+// levels (element d for depth d); defer: deferred partitioning.
+void level_write_masks(int k, int levels, uint64_t* masks, int defer);
+// Deferred partitioning of one tree (defer = 1 in launch_level and
+// launch_leaf): node_rank (2^(k-1) - 1 words) receives the ranks of the nodes
+// of depth `depth` (<= k-2) once array `depth` has its depth layout; key[i]
+// receives the in-order bucket of element i of array j (2 <= j < k) at depth
+// min(j, deepest global level), the key of the stable split that gives array
+// j that layout.
+hipError_t launch_node_ranks(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1,
+                             uint32_t* b2, int64_t n, int k, int depth, const ForestArgs& fa,
+                             uint32_t* node_rank, hipStream_t st);
+hipError_t launch_defer_bucket(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1,
+                               uint32_t* b2, int64_t n, int k, int j, const ForestArgs& fa,
+                               const uint32_t* node_rank, uint32_t* key, hipStream_t st);
 size_t level_seginfo_bytes();
 inline int64_t level_tiles(int64_t n) { return (n + kLevelTile - 1) / kLevelTile; }
 
@@ -165,7 +177,7 @@ inline size_t leaf_lds_bytes(int64_t cutover, int k) {
 hipError_t launch_leaf(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1, uint32_t* b2,
                        int64_t n, int k,
                        int64_t cutover, const ForestArgs& fa, int32_t* perm, int64_t items_bound,
-                       int blocks, hipStream_t st);
+                       int blocks, int defer, hipStream_t st);
 
 // Per-level sorting builder: the k canonical words of rows[pos] for pos <
 // *nu (plane j at words + j * n), and every position's range start at

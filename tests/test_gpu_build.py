@@ -88,6 +88,47 @@ def test_level_launch_forms(kd, level, k, n):
     assert_same(kd, t, cutover=1024, level=level)
 
 
+@pytest.mark.parametrize("k", [2, 3, 4, 5, 8])
+@pytest.mark.parametrize("n", [1, 7, 1000, 1025, 4097, 70001, 600000])
+def test_deferred_partitioning(kd, k, n):
+    """Level form 3 (deferred partitioning: array j >= 2 reaches its depth-j
+    layout in one split): the oracle's tree, also where the tree has fewer
+    global levels than k - 1 and where no global level runs."""
+    t = kdgen.uniform_int(n, k, -(1 << 20), 1 << 20, 0.05, 500 + n + k)
+    assert_same(kd, t, cutover=1024, level=3)
+
+
+@pytest.mark.parametrize("k", [3, 6])
+@pytest.mark.parametrize("cutover", [1024, 4096])
+def test_deferred_partitioning_duplicates(kd, k, cutover):
+    """Deferred, with duplicate removal leaving far fewer distinct rows than
+    rows (the device's global levels end above the host's bound) and with
+    runs of equal first coordinates."""
+    r = 6 if k == 3 else 3  # at most 1728 (k = 3) or 46656 (k = 6) distinct rows
+    t = kdgen.uniform_int(200000, k, -r, r, 0.0, 77 + k + cutover)
+    assert_same(kd, t, cutover=cutover, level=3)
+    t = kdgen.uniform_int(150000, k, -(1 << 30), 1 << 30, 0.0, 78 + k)
+    t[:, 0] = t[:, 0] % 7
+    assert_same(kd, t, cutover=cutover, level=3)
+
+
+@pytest.mark.parametrize("k", [3, 8])
+def test_deferred_partitioning_full_size(kd, k):
+    """Deferred partitioning on the dimension sweep's full size (n=2^22, 256
+    Gaussian clusters, 10% copies), every output compared."""
+    assert_same(kd, kdgen.c3_clustered(k), threads=os.cpu_count() or 8, level=3)
+
+
+def test_deferred_partitioning_c2_bit_exact(kd):
+    """Deferred partitioning on the headline workload (k=3, n=2^24), every
+    output compared."""
+    t = kdgen.c2_full_range()
+    want = oracle.build_tree(t, threads=os.cpu_count() or 8, children=False)
+    perm, nu = run_gpu(kd, t, children=False, level=3)
+    assert nu == want["n_unique"]
+    assert np.array_equal(perm, want["perm"])
+
+
 @pytest.mark.parametrize("records", [1, 2])
 @pytest.mark.parametrize("k", [2, 3, 5])
 def test_record_completion_paths(kd, records, k):
@@ -247,7 +288,7 @@ def test_batched_mixed_sizes(kd, k):
     assert_batched_same(kd, t, offsets)
 
 
-@pytest.mark.parametrize("level", [1, 2])
+@pytest.mark.parametrize("level", [1, 2, 3])
 def test_batched_level_forms(kd, level):
     """Forests whose trees reach different depths: global levels in both
     launch forms."""
