@@ -74,7 +74,13 @@ typedef struct kd_options {
                           others through the radix passes; 0 = all */
   int32_t level;       /* global partition levels: 0 = default (1), 1 = count,
                           chain and move launches, 2 = one move launch per
-                          level whose tiles chain their counts by look-back */
+                          level whose tiles chain their counts by look-back,
+                          3 = form 1 with deferred partitioning (Appendix,
+                          "Deferred Merge Sort and Partitioning"): array j
+                          >= 2 keeps its presorted order until depth j and
+                          then reaches its depth-j layout in one stable
+                          radix split by subtree instead of j moves (single
+                          builds; a batch runs form 1) */
   int32_t reserved[3]; /* must be zero */
 } kd_options;
 
