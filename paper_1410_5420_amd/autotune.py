@@ -2,8 +2,9 @@
 
 The knobs -- the cutover C below which a subarray is finished on-chip, the
 number of workgroups of the persistent on-chip finish, how the level-0 rank
-records are completed, and (learned form) which sorts use the learned
-buckets -- change speed only.  tune() times every candidate configuration on the caller's input, and
+records are completed, (learned form) which sorts use the learned
+buckets, and (plain form, k >= 5) whether the partition is deferred --
+change speed only.  tune() times every candidate configuration on the caller's input, and
 checks that each one returns exactly the output of the default
 configuration (a difference would be a bug, and raises); the fastest is
 cached per (form, k, dtype, log2 n) in a JSON file, from which
@@ -22,12 +23,18 @@ CANDIDATES = [{"cutover": c, "leaf_blocks": b, "records": r} for c in (1024, 204
 # all of them, or only the first (the multi-word sort, where the buckets save
 # the most passes)
 LEARNED_SORTS = (0, 1)
+# deferred partitioning (level form 3) saves (k-1)(k-2)/2 array moves for the
+# price of one radix split per array j >= 2; measured, it loses at k <= 4 and
+# gains at k = 6 and 8, so only k >= 5 try it
+DEFERRED_MIN_K = 5
 
 
-def candidates_for(form: str) -> list:
-    if form != "learned":
-        return list(CANDIDATES)
-    return [dict(c, learned_sorts=m) for c in CANDIDATES for m in LEARNED_SORTS]
+def candidates_for(form: str, k: int | None = None) -> list:
+    if form == "learned":
+        return [dict(c, learned_sorts=m) for c in CANDIDATES for m in LEARNED_SORTS]
+    if form == "plain" and k is not None and k >= DEFERRED_MIN_K:
+        return list(CANDIDATES) + [dict(c, level=3) for c in CANDIDATES]
+    return list(CANDIDATES)
 
 
 def cache_path() -> str:
@@ -82,7 +89,7 @@ def tune(tuples, form: str = "plain", offsets=None, models=None, candidates=None
 
     n, k = tuples.shape
     dev = tuples.device
-    candidates = candidates or candidates_for(form)
+    candidates = candidates or candidates_for(form, k)
     dtype = str(tuples.dtype).replace("torch.", "")
 
     def make(cfg):

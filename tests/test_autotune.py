@@ -45,3 +45,12 @@ def test_candidates_are_valid_options(at):
         assert c["cutover"] in (1024, 2048, 4096)
         assert 256 <= c["leaf_blocks"] <= 16384
         assert c["records"] in (0, 1, 2)
+
+
+def test_deferred_form_only_for_large_k(at):
+    """Deferred partitioning is a candidate of the plain form from k = 5 on."""
+    assert all("level" not in c for c in at.candidates_for("plain", 3))
+    big = at.candidates_for("plain", 8)
+    assert sum(c.get("level") == 3 for c in big) == len(at.CANDIDATES)
+    assert all("level" not in c for c in at.candidates_for("batched", 8))
+    assert all("level" not in c for c in at.candidates_for("learned", 8))
