@@ -400,3 +400,11 @@ def test_autotune_keeps_output_and_caches(kd, tmp_path, monkeypatch):
     rb = autotune.tune(torch.from_numpy(x).cuda(), "batched", offsets=offsets, candidates=cands, reps=2)
     assert rb["config"] in cands
     assert autotune.best_options("batched", int(offsets[-1]), 3, "float32") == rb["config"]
+    # k >= 5: the deferred partitioning is among the candidates, and its
+    # output is checked against the default configuration's like any other
+    t6 = torch.from_numpy(kdgen.uniform_int(200000, 6, 0, 1 << 20, 0.02, 6)).cuda()
+    dc = [c for c in autotune.candidates_for("plain", 6) if c["records"] == 1 and c["cutover"] == 1024
+          and c["leaf_blocks"] == 2048]
+    assert any(c.get("level") == 3 for c in dc)
+    r6 = autotune.tune(t6, "plain", candidates=dc, reps=2)
+    assert len(r6["results"]) == len(dc)
