@@ -221,10 +221,13 @@ def test_workspace_reuse_shrinking_input(kd):
         assert np.array_equal(perm[: want["n_unique"]].cpu().numpy(), want["perm"])
 
 
-def test_presort_then_partition_equals_build(kd):
+@pytest.mark.parametrize("level", [None, 3])
+def test_presort_then_partition_equals_build(kd, level):
+    """The two halves as separate calls (level 3: deferred partitioning)."""
+    print(f"[gpu case] presort + partition level={level}", flush=True)
     t = kdgen.uniform_int(123457, 3, 0, 1 << 18, 0.05, 77)
     want = oracle.build_tree(t, threads=8, children=False)
-    b = kd.Builder(t.shape[0], 3, torch.int32)
+    b = kd.Builder(t.shape[0], 3, torch.int32, level=level)
     dt = torch.from_numpy(t).cuda()
     perm = torch.full((t.shape[0],), -1, dtype=torch.int32, device="cuda")
     b.presort(dt)

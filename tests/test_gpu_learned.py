@@ -149,6 +149,22 @@ def test_learned_small(kd, k, n):
     assert_learned_same(kd, t)
 
 
+@pytest.mark.parametrize("k", [3, 6])
+def test_learned_deferred_partitioning(kd, k):
+    """The learned presort followed by deferred partitioning (level form 3)."""
+    case(f"learned deferred k={k}")
+    t = kdgen.uniform_int(300001, k, -(1 << 24), 1 << 24, 0.05, 950 + k)
+    dt = torch.from_numpy(t).cuda()
+    models = kd.train_cdf(dt)
+    b = kd.LearnedBuilder(t.shape[0], k, torch.int32, level=3)
+    perm = torch.full((t.shape[0],), -1, dtype=torch.int32, device="cuda")
+    b.build(dt, perm, models=models)
+    torch.cuda.synchronize()
+    want = oracle_tree(t)
+    assert int(b.n_unique.item()) == want["n_unique"]
+    assert np.array_equal(perm[: want["n_unique"]].cpu().numpy(), want["perm"])
+
+
 @pytest.mark.parametrize("k", [1, 3, 8])
 @pytest.mark.parametrize("n", [1000, 70001])
 def test_learned_heavy_duplicates(kd, k, n):
