@@ -411,3 +411,62 @@ def test_autotune_keeps_output_and_caches(kd, tmp_path, monkeypatch):
     assert any(c.get("level") == 3 for c in dc)
     r6 = autotune.tune(t6, "plain", candidates=dc, reps=2)
     assert len(r6["results"]) == len(dc)
+
+
+def test_maximum_size_properties(kd):
+    """n = 2^30 - 1 rows (the largest the library accepts), k = 2, full-range
+    int32 with 0.1% planted copies, drawn on the GPU from a seeded generator.
+    The oracle cannot build a tree of this size within a test, so the tree is
+    checked by properties that hold at any size:
+    - n_unique equals the number of distinct rows;
+    - the nodes are exactly the first row of every distinct tuple;
+    - every node of the top six depths has only smaller super keys (in its
+      split dimension) before it in its subtree's range, and only larger ones
+      after it."""
+    n, k = (1 << 30) - 1, 2
+    print(f"[gpu case] maximum size n={n} k={k}", flush=True)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(14105420)
+    t = torch.randint(-(1 << 31), 1 << 31, (n, k), dtype=torch.int64, device="cuda",
+                      generator=g).to(torch.int32)
+    d = n // 1000
+    src = torch.randint(0, n, (d,), device="cuda", generator=g)
+    dst = torch.randint(0, n, (d,), device="cuda", generator=g)
+    t[dst] = t[src]
+    del src, dst
+    perm = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    b = kd.Builder(n, k, torch.int32)
+    b.build(t, perm)
+    torch.cuda.synchronize()
+    nu = int(b.n_unique.item())
+    del b
+    torch.cuda.empty_cache()
+
+    def super_key(p):  # (word p, word p+1) in signed order as one int64
+        hi = t[:, p].to(torch.int64)
+        lo = t[:, (p + 1) % k].to(torch.int64) + (1 << 31)
+        return (hi << 32) + lo
+
+    key0 = super_key(0)
+    skeys, order = torch.sort(key0, stable=True)
+    head = torch.ones(n, dtype=torch.bool, device="cuda")
+    head[1:] = skeys[1:] != skeys[:-1]
+    first_rows = order[head]
+    del skeys, order, head
+    assert nu == first_rows.numel()
+    nodes = perm[:nu].to(torch.int64)
+    assert torch.equal(torch.sort(nodes).values, torch.sort(first_rows).values)
+    del first_rows
+    for p in range(k):
+        kp = (key0 if p == 0 else super_key(p))[nodes]
+        subs = [(0, nu - 1)]
+        for depth in range(6):
+            nxt = []
+            for s, e in subs:
+                m = s + (e - s) // 2
+                if depth % k == p:
+                    assert bool((kp[s:m] < kp[m]).all()), f"depth {depth} node {m}: lower side"
+                    assert bool((kp[m + 1:e + 1] > kp[m]).all()), f"depth {depth} node {m}: upper side"
+                nxt += [(s, m - 1), (m + 1, e)]
+            subs = nxt
+        del kp
