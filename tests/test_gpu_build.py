@@ -470,3 +470,39 @@ def test_maximum_size_properties(kd):
                 nxt += [(s, m - 1), (m + 1, e)]
             subs = nxt
         del kp
+
+
+def test_batched_maximum_tree_count(kd):
+    """The largest forest the library accepts: 2^20 trees of 0 .. 16 rows
+    (empty trees included) with three trees large enough for global levels,
+    int32 from a small range so that trees hold duplicates.  Every tree's
+    distinct count is checked; 3000 sampled trees and the large ones are
+    compared with the oracle element by element."""
+    g = kdgen.rng(2024)
+    B, k = 1 << 20, 3
+    sizes = g.integers(0, 17, size=B)
+    sizes[[0, 1000, 500000]] = [5000, 70000, 20000]
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    t = g.integers(-4, 4, size=(int(offsets[-1]), k)).astype(np.int32)
+    big = np.repeat(sizes > 1000, sizes)
+    t[big] = g.integers(-3000, 3000, size=(int(big.sum()), k)).astype(np.int32)
+    print(f"[gpu case] batched maximum tree count B={B} rows={offsets[-1]}", flush=True)
+    perm, nu = kd.build_batched(torch.from_numpy(t).cuda(), offsets)
+    torch.cuda.synchronize()
+    perm = perm.cpu().numpy()
+    nu = nu.cpu().numpy()
+    # distinct rows per tree, for every tree
+    tree = np.repeat(np.arange(B, dtype=np.int64), sizes)
+    key = tree << 39  # tree id, then the three coordinates in 13 bits each
+    for c in range(k):
+        key |= (t[:, c].astype(np.int64) + 4096) << (13 * (k - 1 - c))
+    want_nu = np.bincount(np.unique(key) >> 39, minlength=B)
+    assert np.array_equal(nu, want_nu)
+    sample = np.concatenate([[0, 1000, 500000], g.choice(B, 3000, replace=False)])
+    for b in sample:
+        s, e = int(offsets[b]), int(offsets[b + 1])
+        if e == s:
+            assert nu[b] == 0
+            continue
+        want = oracle.build_tree(t[s:e], children=False)
+        assert np.array_equal(perm[s:s + nu[b]], want["perm"]), f"tree {b}"
