@@ -346,3 +346,36 @@ def test_reverse_lists_with_a_hub_row(kd):
     for r in g.choice(n, size=50, replace=False):
         want_r = np.sort(np.repeat(pm, (nr == r).sum(axis=1)))
         assert np.array_equal(l[o[r]:o[r + 1]], want_r), f"row {r}"
+
+
+def test_queries_maximum_count(kd):
+    """The largest query batch accepted (KD_MAX_QUERIES = 2^28), nearest
+    neighbour and box counts over a 2^16-row tree, queries drawn on the GPU
+    from a seeded generator; a sample of them is checked by a scan."""
+    g = kdgen.rng(970)
+    n, k, nq = 1 << 16, 3, 1 << 28
+    t = kdgen.uniform_int(n, k, -(1 << 20), 1 << 20, 0.01, 971)
+    print(f"[gpu case] queries maximum count nq={nq} n={n}", flush=True)
+    dt, perm, nu = gpu_tree(kd, t)
+    p = perm.cpu().numpy()
+    nodes = t[p]
+    tg = torch.Generator(device="cuda")
+    tg.manual_seed(972)
+    pts = torch.randint(-(1 << 20), 1 << 20, (nq, k), dtype=torch.int32, device="cuda", generator=tg)
+    got = kd.nearest(dt, perm, nu, pts, 1)
+    half = torch.randint(0, 1 << 15, (nq, k), dtype=torch.int32, device="cuda", generator=tg)
+    lo, hi = pts - half, pts + half
+    del half
+    counts = kd.region_count(dt, perm, nu, lo, hi)
+    torch.cuda.synchronize()
+    sample = g.choice(nq, size=40, replace=False)
+    got_s = got[torch.from_numpy(sample).cuda()].cpu().numpy()
+    pts_s = pts[torch.from_numpy(sample).cuda()].cpu().numpy()
+    lo_s = lo[torch.from_numpy(sample).cuda()].cpu().numpy()
+    hi_s = hi[torch.from_numpy(sample).cuda()].cpu().numpy()
+    counts_s = counts[torch.from_numpy(sample).cuda()].cpu().numpy()
+    for i in range(len(sample)):
+        want_rows, _ = brute_nearest_fast(t, p, pts_s[i], 1)
+        assert got_s[i].tolist() == want_rows, f"query {sample[i]}"
+        inside = np.all((nodes >= lo_s[i]) & (nodes <= hi_s[i]), axis=1)
+        assert counts_s[i] == int(inside.sum()), f"box {sample[i]}"
