@@ -120,6 +120,50 @@ def level_bytes(nu: int, k: int, cutover: int):
     return total, levels
 
 
+# The byte model fixed before measuring (the scope's measurement section):
+# per tuple, a word-sort of the chain presort moves 8 + 16 (P - 1) + 12 bytes
+# over its P = 4 digit passes (17 B per pass on average), a global level moves
+# 5 + 9 (k - 1) bytes (a side-flag design: the split array's index read and
+# flag write, each other array's index read, flag gather and index write), and
+# the whole build at k = 3, n = 2^24 (r = 8, C = 4096) moves 672 B per tuple.
+SURVEY_PASS_BYTES = 17
+SURVEY_WHOLE_BUILD_BYTES_PER_TUPLE = 672
+
+
+def survey_level_bytes(k: int) -> int:
+    return 5 + 9 * (k - 1)
+
+
+def survey_whole_build_bytes(n: int, k: int, nu: int) -> int:
+    """B_model of the whole build, P = 4, C = 4096: chain presort (2k - 1)
+    word-sorts of 68 B, duplicate removal 8 + 4k, ceil(log2(n_u / 4096))
+    levels of 5 + 9 (k - 1), the on-chip finish and emission 8k + 12 (672 B
+    per tuple at k = 3, n = 2^24)."""
+    levels = 0
+    while (nu >> levels) > 4096:
+        levels += 1
+    per = (2 * k - 1) * 68 + (8 + 4 * k) + levels * survey_level_bytes(k) + (8 * k + 12)
+    return per * n
+
+
+def survey_bytes_per_launch(kernel: str, n: int, nu: int, k: int, cutover: int):
+    """(algorithmic bytes per launch, description) under the fixed model:
+    a level moves n_u tuples, a radix pass 17 B per row it sorts (word 0
+    passes over n rows, the chain's over n_u; gated passes count as launches
+    of no bytes, as in the design model)."""
+    if kernel == "level":
+        return survey_level_bytes(k) * nu, f"{survey_level_bytes(k)} B x n_unique per level (5 + 9(k-1))"
+    if kernel == "onesweep":
+        _, launches = onesweep_bytes(n, nu, k)
+        P = 4
+        rows = P * n + (k - 1) * P * nu if k > 1 else P * n
+        return SURVEY_PASS_BYTES * rows / launches, (f"17 B per sorted row per pass over the "
+                                                     f"{launches} passes, averaged")
+    if kernel == "leaf":
+        return (8 * k + 12) * nu, f"{8 * k + 12} B x n_unique (8k + 12)"
+    raise ValueError(kernel)
+
+
 def byte_model(kernel: str, n: int, nu: int, k: int, cutover: int):
     """Algorithmic bytes of one launch of a kernel class (averaged over the
     build's launches of that class), and how they arise."""
@@ -164,20 +208,52 @@ def recorded_traffic(kernel: str, workload: str):
 
 # ---- CPU baseline -------------------------------------------------------------------
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(t: np.ndarray):
+    """The oracle as it stands, median of 3 runs in each of two modes: one
+    thread on a bounded sample (the first quarter of the rows), and q =
+    2^floor(log2 nproc) threads (the paper's parent/child scheme allows only
+    powers of two) on the whole input, nproc capped at the 16 CPUs a GPU's
+    share of the host provides."""
     import oracle
 
-    cores = min(16, os.cpu_count() or 1)
+    nproc = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cores = min(16, nproc)
     q = 1
     while q * 2 <= cores:
         q *= 2
-    t0 = time.perf_counter()
-    r = oracle.build_tree(t, threads=q, children=False)
-    dt = time.perf_counter() - t0
-    return {"value": round(t.shape[0] / dt, 1), "unit": "tuples/s", "cores": q, "kind": "oracle",
-            "sample": f"one whole build of the same {t.shape[0]}-row input "
-                      f"({dt:.1f} s; presort {r['times'][0]:.1f} s, partition {r['times'][1]:.1f} s), "
-                      f"paper's parent/child threads, q={q}"}
+
+    def median_rate(x, threads):
+        runs = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            r = oracle.build_tree(x, threads=threads, children=False)
+            runs.append((time.perf_counter() - t0, r["times"]))
+        runs.sort(key=lambda v: v[0])
+        dt, times = runs[1]
+        return x.shape[0] / dt, dt, times
+
+    sample = t[: t.shape[0] // 4]
+    r1, d1, t1 = median_rate(sample, 1)
+    rq, dq, tq = median_rate(t, q)
+    return {"value": round(rq, 1), "unit": "tuples/s", "cores": q, "kind": "oracle",
+            "cpu_model": cpu_model(), "nproc": nproc,
+            "one_thread": {"value": round(r1, 1), "unit": "tuples/s", "cores": 1,
+                           "rows": int(sample.shape[0]), "median_s": round(d1, 3),
+                           "presort_s": round(t1[0], 3), "partition_s": round(t1[1], 3)},
+            "sample": f"median of 3 whole builds of the same {t.shape[0]}-row input at q={q} threads "
+                      f"({dq:.2f} s; presort {tq[0]:.2f} s, partition {tq[1]:.2f} s; paper's parent/"
+                      f"child threads); one_thread: median of 3 builds of its first "
+                      f"{sample.shape[0]} rows on one thread ({d1:.2f} s)"}
 
 
 # ---- timing helpers ----------------------------------------------------------------
@@ -253,21 +329,21 @@ def main():
     nu = int(b.n_unique.item())
     log(f"warmup done, n_unique={nu}")
 
-    # timed region: K whole builds; the library's probe times the level launches
-    cap = 64 * args.steps
-    _lib.probe_start("level", cap)
+    # timed region: K whole builds, nothing else enqueued between them
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         b.build(t, perm)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    durations = {"level": _lib.probe_stop(cap)}
     ms_per_step = elapsed * 1e3 / args.steps
     log(f"{args.steps} steps, {ms_per_step:.3f} ms/step")
+    b.status()  # raises if a kernel reported inconsistent counts
 
-    # the other kernel classes, each over its own (untimed) builds
-    for cls in ("onesweep", "leaf", "records", "dedup"):
+    # every kernel class over its own (untimed) builds: the library records
+    # HIP events around that class's launches on the build's stream
+    durations = {}
+    for cls in ("level", "onesweep", "leaf", "records", "dedup"):
         reps = max(3, args.steps // 4)
         c2 = 64 * reps
         _lib.probe_start(cls, c2)
@@ -276,11 +352,9 @@ def main():
         torch.cuda.synchronize()
         durations[cls] = _lib.probe_stop(c2)
         durations[cls + "_reps"] = reps
-    steps_of = {"level": args.steps}
     class_ms = {}
     for cls in ("level", "onesweep", "leaf", "records", "dedup"):
-        reps = steps_of.get(cls, durations.get(cls + "_reps", 1))
-        class_ms[cls] = round(float(np.sum(durations[cls])) / reps, 4)
+        class_ms[cls] = round(float(np.sum(durations[cls])) / durations[cls + "_reps"], 4)
 
     # phase split, measured separately with events on the same stream
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
@@ -296,16 +370,34 @@ def main():
         part_ms.append(ev[1].elapsed_time(ev[2]))
 
     def roofline_of(cls):
-        bytes_per_launch, unit_desc = byte_model(cls, n, nu, k, cutover)
+        # achieved: the fixed model's algorithmic bytes per launch over the
+        # class's average launch time; the design's own byte model beside it
+        bytes_per_launch, unit_desc = survey_bytes_per_launch(cls, n, nu, k, cutover)
+        design_bytes, design_desc = byte_model(cls, n, nu, k, cutover)
         real = [d for d in durations[cls] if d > 0.002]  # no-op launches (levels past the cutover) excluded
         avg_ms = float(np.mean(real)) if real else float("nan")
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+        design_achieved = design_bytes / (avg_ms * 1e-3) / 1e9
         traffic = recorded_traffic(cls, "c2")
         return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": cls,
                 "avg_launch_ms": round(avg_ms, 4), "launches": len(real),
-                "bytes_per_launch": int(bytes_per_launch), "byte_model": unit_desc}
+                "bytes_per_launch": int(bytes_per_launch), "byte_model": unit_desc,
+                "design_model": {"bytes_per_launch": int(design_bytes), "byte_model": design_desc,
+                                 "achieved": round(design_achieved, 1),
+                                 "frac": round(design_achieved / HBM_PEAK_GBS, 4)}}
 
+    B_model = survey_whole_build_bytes(n, k, nu)
+    wb_gbs = B_model / (ms_per_step * 1e-3) / 1e9
+    whole_build = {"bytes_per_tuple": round(B_model / n, 1), "B_model": int(B_model),
+                   "ms_per_step": round(ms_per_step, 4), "achieved": round(wb_gbs, 1),
+                   "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(wb_gbs / HBM_PEAK_GBS, 4),
+                   "bar": 0.40,
+                   "byte_model": "fixed before measuring: chain presort (2k-1) x 68 B, dedup 8 + 4k, "
+                                 "ceil(log2(n_u/4096)) levels x (5 + 9(k-1)), finish 8k + 12 "
+                                 "(672 B per tuple at k = 3, n = 2^24)"}
+    log(f"whole build: {B_model / 1e9:.2f} GB model bytes in {ms_per_step:.3f} ms = "
+        f"{wb_gbs / HBM_PEAK_GBS:.3f} of HBM peak")
     dominant = max(("level", "onesweep"), key=lambda c: class_ms[c])
     roofline = roofline_of(dominant)
     secondary = roofline_of("onesweep" if dominant == "level" else "level")
@@ -334,6 +426,7 @@ def main():
                    "kernel_class_ms_per_step": class_ms},
         "roofline": roofline,
         "roofline_secondary": secondary,
+        "whole_build": whole_build,
     }
 
     if not args.no_queries:
@@ -540,6 +633,7 @@ def learned_form(torch, kd, t, plain_perm, nu, args, label, knobs=None):
     same = int(lb.n_unique.item()) == nu and torch.equal(perm[:nu], plain_perm[:nu])
     res = {"workload": label, "n": n, "knobs": knobs, "train_ms": round(train_ms, 3),
            "ms_per_build": round(ms, 4),
+           "ms_per_build_with_training": round(ms + train_ms, 4),
            "tuples_per_s": round(n / (ms * 1e-3), 1), "presort_ms": round(float(np.median(pre)), 4),
            "fell_back": lb.fell_back.cpu().numpy().tolist(), "bit_exact_vs_plain": bool(same)}
     log(f"learned {label}: {ms:.3f} ms/build, presort {res['presort_ms']} ms, fell_back {res['fell_back']}")
@@ -579,7 +673,59 @@ def learned_c5(torch, kd, kdgen, args):
     res["plain_ms_per_build"] = round(plain_ms, 4)
     res["plain_presort_ms"] = round(float(np.median(pre)), 4)
     res["speedup_vs_plain"] = round(plain_ms / res["ms_per_build"], 3)
-    log(f"c5 plain {plain_ms:.3f} ms, learned {res['ms_per_build']} ms")
+    res["speedup_vs_plain_with_training"] = round(plain_ms / res["ms_per_build_with_training"], 3)
+    log(f"c5 plain {plain_ms:.3f} ms, learned {res['ms_per_build']} ms "
+        f"({res['ms_per_build_with_training']} ms with training)")
+    res["reuse"] = learned_reuse(torch, kd, kdgen, t, knobs, res["knobs"], args)
+    return res
+
+
+def learned_reuse(torch, kd, kdgen, t_a, plain_knobs, learned_knobs, args):
+    """The learned form as it is meant to be used: a model trained once, on
+    draw A of the mixture, then reused for a build of draw B (same
+    distribution, other rows), against the plain build of draw B.  Both
+    builds are timed alternately, reps each, and the spread is reported."""
+    log("reuse: model trained on draw A, builds of draw B")
+    models = kd.train_cdf(t_a)
+    torch.cuda.synchronize()
+    xb = kdgen.c5_mixture(draw=1)
+    tb = torch.from_numpy(xb).cuda()
+    del xb
+    n, k = tb.shape
+    b = kd.Builder(n, k, torch.float32, **plain_knobs)
+    lb = kd.LearnedBuilder(n, k, torch.float32, **learned_knobs)
+    pp = torch.full((n,), -1, dtype=torch.int32, device=tb.device)
+    pl = torch.full((n,), -1, dtype=torch.int32, device=tb.device)
+    for _ in range(2):
+        b.build(tb, pp)
+        lb.build(tb, pl, models=models)
+    torch.cuda.synchronize()
+    plain, learned = [], []
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for _ in range(max(5, args.steps // 2)):
+        for builder, out, times, kw in ((b, pp, plain, {}), (lb, pl, learned, {"models": models})):
+            ev[0].record()
+            builder.build(tb, out, **kw)
+            ev[1].record()
+            torch.cuda.synchronize()
+            times.append(ev[0].elapsed_time(ev[1]))
+    nu = int(b.n_unique.item())
+    same = int(lb.n_unique.item()) == nu and torch.equal(pp[:nu], pl[:nu])
+    b.status()
+    lb.status()
+    fb = lb.fell_back.cpu().numpy().tolist()
+    res = {"workload": "model trained on draw A of the C5 mixture, builds of draw B (same mixture, "
+                       "other rows)",
+           "plain_ms_median": round(float(np.median(plain)), 4),
+           "learned_ms_median": round(float(np.median(learned)), 4),
+           "plain_ms_min_max": [round(min(plain), 4), round(max(plain), 4)],
+           "learned_ms_min_max": [round(min(learned), 4), round(max(learned), 4)],
+           "speedup_vs_plain": round(float(np.median(plain)) / float(np.median(learned)), 3),
+           "fell_back": fb, "bit_exact_vs_plain": bool(same), "reps": len(plain)}
+    log(f"reuse: plain {res['plain_ms_median']} ms, learned {res['learned_ms_median']} ms, "
+        f"fell_back {fb}, same={same}")
+    del b, lb, pp, pl, tb
+    torch.cuda.empty_cache()
     return res
 
 

@@ -56,7 +56,8 @@ enum kd_status {
   KD_EINVAL = -1,        /* bad argument (null, misaligned, out of range) */
   KD_ENOMEM = -2,        /* workspace smaller than kdtree_workspace_bytes() */
   KD_EHIP = -3,          /* a HIP runtime call failed */
-  KD_EUNSUPPORTED = -4   /* k or n beyond the limits above */
+  KD_EUNSUPPORTED = -4,  /* k or n beyond the limits above */
+  KD_EINTERNAL = -5      /* kd_status(): a kernel found inconsistent counts */
 };
 
 /* Tuning knobs; pass NULL for the defaults.  They change speed only, never the
@@ -86,6 +87,18 @@ typedef struct kd_options {
 
 /* Human-readable name of a status code (static string). */
 const char* kd_strerror(int code);
+
+/* Consistency check of the last build enqueued with this workspace (any
+ * entry point that takes a build workspace).  The build's kernels clear a
+ * device status word at the start of the workspace when the presort starts,
+ * and a kernel that finds counts contradicting each other -- which a correct
+ * build never does -- drops the write it cannot place and sets a bit there,
+ * instead of writing out of bounds.  kd_status() waits for `stream`, copies
+ * that word to *h_bits (0 when clean) and returns KD_EINTERNAL when a bit is
+ * set, KD_OK otherwise.  Bits: 1 radix pass, 2 level tile subarrays, 4 level
+ * move, 8 on-chip finish, 16 multi-level split, 32 record placement, 64 node
+ * rank.  Synchronises the stream, so it is not for capture into a graph. */
+int kd_status(const void* d_workspace, size_t workspace_bytes, uint32_t* h_bits, void* stream);
 
 /* Bytes of device workspace a build of n rows in k dimensions needs.  Host
  * only; writes *h_bytes.  Returns KD_EINVAL / KD_EUNSUPPORTED on bad sizes. */
@@ -190,10 +203,15 @@ int kd_cdf_model_bytes(int32_t k, size_t* h_bytes);
 int kd_cdf_train_workspace_bytes(int32_t k, int32_t n_samples, size_t* h_bytes);
 /* Train one model per dimension on d_tuples (n >= 1 rows).  Asynchronous on
  * `stream`; writes d_models (kd_cdf_model_bytes(k) bytes, 4-byte aligned).
- * 1 <= n_samples <= KD_CDF_MAX_SAMPLES, 0 <= steps <= KD_CDF_MAX_STEPS,
- * lr > 0. */
-int kd_cdf_train(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, int32_t n_samples,
-                 int32_t steps, float lr, void* d_models, void* d_workspace,
+ * kind selects the model family: KD_CDF_PWL (0), the piecewise-linear model
+ * above, is the one built; any other value (KD_CDF_MLP = 1, a small
+ * multi-layer perceptron, is not built) returns KD_EUNSUPPORTED before
+ * anything is enqueued.  1 <= n_samples <= KD_CDF_MAX_SAMPLES,
+ * 0 <= steps <= KD_CDF_MAX_STEPS, lr > 0. */
+#define KD_CDF_PWL 0
+#define KD_CDF_MLP 1
+int kd_cdf_train(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, int32_t kind,
+                 int32_t n_samples, int32_t steps, float lr, void* d_models, void* d_workspace,
                  size_t workspace_bytes, void* stream);
 /* The training objective for given logits, for checking: d_values holds m
  * coordinates of `dtype` sorted ascending in the order above; lo_bits /

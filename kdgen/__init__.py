@@ -92,10 +92,12 @@ def point_cloud(n: int, g: np.random.Generator) -> np.ndarray:
 
 
 def gaussian_mixture_f32(n: int, k: int, components: int, seed: int, log_sigma: float = 1.5,
-                         mean_range: float = 100.0) -> np.ndarray:
+                         mean_range: float = 100.0, sample_seed: int | None = None) -> np.ndarray:
     """float32 rows from ``components`` equal-weight anisotropic Gaussians:
     means uniform in [-mean_range, mean_range]^k, per-axis scales
-    exp(N(0, log_sigma)), a random rotation per component."""
+    exp(N(0, log_sigma)), a random rotation per component.  The components
+    come from ``seed``; the rows from the same generator, or from
+    ``sample_seed`` when given (another draw of the same distribution)."""
     g = rng(seed)
     means = g.uniform(-mean_range, mean_range, size=(components, k))
     scales = np.exp(g.normal(0.0, log_sigma, size=(components, k)))
@@ -104,6 +106,8 @@ def gaussian_mixture_f32(n: int, k: int, components: int, seed: int, log_sigma: 
         q, r = np.linalg.qr(g.normal(size=(k, k)))
         rots.append(q * np.sign(np.diag(r)))
     rots = np.stack(rots)
+    if sample_seed is not None:
+        g = rng(sample_seed)
     which = g.integers(0, components, size=n)
     out = np.empty((n, k), dtype=np.float32)
     chunk = 1 << 22
@@ -152,10 +156,13 @@ def c4_batched(trees: int = 4096, lo: int = 64, hi: int = 65536, seed: int = SEE
     return np.ascontiguousarray(np.concatenate(parts, axis=0)), offsets
 
 
-def c5_mixture(n: int = 1 << 26) -> np.ndarray:
+def c5_mixture(n: int = 1 << 26, draw: int = 0) -> np.ndarray:
     """k=3, n=2^26, float32 mixture of 64 anisotropic Gaussians with lognormal
-    scales (mu 0, sigma 1.5)."""
-    return gaussian_mixture_f32(n, 3, 64, SEED_BASE + 5)
+    scales (mu 0, sigma 1.5).  draw > 0: another sample of the same mixture
+    (same components, rows from seed SEED_BASE + 5 + 1000 * draw)."""
+    if draw == 0:
+        return gaussian_mixture_f32(n, 3, 64, SEED_BASE + 5)
+    return gaussian_mixture_f32(n, 3, 64, SEED_BASE + 5, sample_seed=SEED_BASE + 5 + 1000 * draw)
 
 
 def c2_queries(t: np.ndarray, nq: int = 1 << 20, seed: int = SEED_BASE + 6):

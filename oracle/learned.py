@@ -153,7 +153,10 @@ def loss_grad(theta: np.ndarray, p: np.ndarray):
 
 
 def train_adam(p: np.ndarray, steps: int, lr: float, b1=0.9, b2=0.999, eps=1e-8) -> np.ndarray:
-    """Adam from theta = 0 on the objective above (fp64)."""
+    """Adam (Kingma and Ba, 2015: exponential moving averages of the gradient
+    and of its square, each divided by its bias correction 1 - beta^t, and a
+    step of lr * m_hat / (sqrt(v_hat) + eps)) from theta = 0 on the
+    objective above (fp64)."""
     th = np.zeros(K)
     m = np.zeros(K)
     s = np.zeros(K)
@@ -165,16 +168,25 @@ def train_adam(p: np.ndarray, steps: int, lr: float, b1=0.9, b2=0.999, eps=1e-8)
     return th
 
 
-def levels(theta: np.ndarray, S: int = 0) -> np.ndarray:
-    """c_0 .. c_K (fp64): running sums of the segment masses, c_K = 1.  With
-    a sample size S, every mass first gets a floor of 1/(4S) and the masses
-    are renormalised (the exported model; segments the sample missed still
-    cover some range)."""
+def running_levels(theta: np.ndarray, S: int = 0) -> np.ndarray:
+    """c_0 .. c_K (fp64) exactly as summed: c_i = q'_0 + ... + q'_{i-1}.
+    With a sample size S, every mass first gets a floor of 1/(4S) and the
+    masses are renormalised (the exported model; segments the sample missed
+    still cover some range).  c_K is 1 up to rounding when the masses are
+    normalised correctly."""
     q = softmax(theta)
     if S > 0:
         fl = 0.25 / S
         q = (q + fl) / (1.0 + len(q) * fl)
-    c = np.concatenate([[0.0], np.cumsum(q)])
+    return np.concatenate([[0.0], np.cumsum(q)])
+
+
+def levels(theta: np.ndarray, S: int = 0) -> np.ndarray:
+    """The exported levels: :func:`running_levels` with c_K set to exactly 1
+    (the model's definition), after checking that the sum reached 1."""
+    c = running_levels(theta, S)
+    if abs(c[-1] - 1.0) > 1e-9:
+        raise ValueError(f"segment masses sum to {c[-1]!r}, not 1")
     c[-1] = 1.0
     return np.minimum(c, 1.0)
 

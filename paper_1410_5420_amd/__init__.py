@@ -57,6 +57,12 @@ class Builder:
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.n_unique = torch.zeros(1, dtype=torch.int64, device=self.device)
 
+    def status(self, stream=None) -> int:
+        """Waits for the stream and checks the last build's device status
+        word (kd_status): raises KdError if a kernel found inconsistent
+        counts, else returns 0."""
+        return _lib.status(_ptr(self.workspace), self.workspace.numel(), _stream(stream))
+
     def _opts(self):
         return _lib.options(self.cutover, getattr(self, "leaf_blocks", None),
                             getattr(self, "records", None), getattr(self, "learned_sorts", None),
@@ -134,6 +140,10 @@ class BatchedBuilder:
             _stream(stream))
         _lib.check(rc, "kdtree_build_batched")
 
+    def status(self, stream=None) -> int:
+        """As :meth:`Builder.status`."""
+        return _lib.status(_ptr(self.workspace), self.workspace.numel(), _stream(stream))
+
 
 def build_batched(tuples: torch.Tensor, offsets, cutover: int | None = None, stream=None,
                   level: int | None = None):
@@ -146,6 +156,7 @@ def build_batched(tuples: torch.Tensor, offsets, cutover: int | None = None, str
     b = BatchedBuilder(offsets, tuples.shape[1], tuples.dtype, tuples.device, cutover, level=level)
     perm = torch.full((max(b.total, 1),), -1, dtype=torch.int32, device=tuples.device)
     b.build(tuples.contiguous(), perm, stream)
+    b.status(stream)
     return perm[: b.total], b.n_unique
 
 
@@ -164,6 +175,7 @@ def build(tuples: torch.Tensor, children: bool = False, cutover: int | None = No
         lo = torch.full_like(perm, -2)
         hi = torch.full_like(perm, -2)
     b.build(tuples.contiguous(), perm, lo, hi, stream)
+    b.status(stream)
     nu = int(b.n_unique.item())
     if children:
         return perm[:nu], nu, lo[:nu], hi[:nu]
@@ -317,6 +329,7 @@ def build_select(tuples: torch.Tensor, stream=None):
     _lib.check(_lib.lib.kdtree_build_select(_ptr(tuples.contiguous()), n, k, code, _ptr(perm),
                                             _ptr(nu), _ptr(ws), nbytes, None, _stream(stream)),
                "kdtree_build_select")
+    _lib.status(_ptr(ws), nbytes, _stream(stream))
     u = int(nu.item())
     return perm[:u], u
 
@@ -338,13 +351,19 @@ class SelectBuilder:
                                                 self.workspace.numel(), None, _stream(stream)),
                    "kdtree_build_select")
 
+    def status(self, stream=None) -> int:
+        """As :meth:`Builder.status`."""
+        return _lib.status(_ptr(self.workspace), self.workspace.numel(), _stream(stream))
+
 
 # ---- learned presort ------------------------------------------------------------
 
 def train_cdf(tuples: torch.Tensor, n_samples: int = 1 << 18, steps: int = 300, lr: float = 0.1,
-              stream=None) -> torch.Tensor:
+              stream=None, kind: int = _lib.KD_CDF_PWL) -> torch.Tensor:
     """Train one CDF model per dimension on the GPU (kd_cdf_train).
 
+    ``kind`` is the model family: only the piecewise-linear model (0) is
+    built; any other kind raises KdError (KD_EUNSUPPORTED).
     Returns the model buffer (uint8 device tensor of k * 33024 bytes)."""
     if tuples.dim() != 2 or not tuples.is_cuda or not tuples.is_contiguous():
         raise ValueError("tuples must be a contiguous (n, k) device tensor")
@@ -353,8 +372,8 @@ def train_cdf(tuples: torch.Tensor, n_samples: int = 1 << 18, steps: int = 300, 
     models = torch.zeros(_lib.cdf_model_bytes(k), dtype=torch.uint8, device=tuples.device)
     ws = torch.empty(_lib.cdf_train_workspace_bytes(k, n_samples), dtype=torch.uint8,
                      device=tuples.device)
-    rc = _lib.lib.kd_cdf_train(_ptr(tuples), n, k, code, n_samples, steps, float(lr), _ptr(models),
-                               _ptr(ws), ws.numel(), _stream(stream))
+    rc = _lib.lib.kd_cdf_train(_ptr(tuples), n, k, code, int(kind), n_samples, steps, float(lr),
+                               _ptr(models), _ptr(ws), ws.numel(), _stream(stream))
     _lib.check(rc, "kd_cdf_train")
     return models
 
@@ -459,6 +478,7 @@ def build_learned(tuples: torch.Tensor, models: torch.Tensor, children: bool = F
         lo = torch.full_like(perm, -2)
         hi = torch.full_like(perm, -2)
     b.build(tuples.contiguous(), perm, lo, hi, stream, models=models)
+    b.status(stream)
     nu = int(b.n_unique.item())
     fb = b.fell_back.cpu()
     if children:

@@ -13,8 +13,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libkdtree.so")
 
 KD_OK = 0
+KD_EUNSUPPORTED = -4
+KD_EINTERNAL = -5
 KD_I32 = 0
 KD_F32 = 1
+KD_CDF_PWL = 0
+KD_CDF_MLP = 1
 
 
 class KdError(RuntimeError):
@@ -37,6 +41,8 @@ def _load():
     opt = ctypes.POINTER(kd_options)
     lib.kd_strerror.argtypes = [ctypes.c_int]
     lib.kd_strerror.restype = ctypes.c_char_p
+    lib.kd_status.argtypes = [vp, sz, ctypes.POINTER(ctypes.c_uint32), vp]
+    lib.kd_status.restype = ctypes.c_int
     lib.kdtree_workspace_bytes.argtypes = [i64, i32, i32, ctypes.POINTER(sz)]
     lib.kdtree_workspace_bytes.restype = ctypes.c_int
     lib.kdtree_build.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp, vp, sz, opt, vp]
@@ -56,7 +62,7 @@ def _load():
     lib.kd_cdf_model_bytes.restype = ctypes.c_int
     lib.kd_cdf_train_workspace_bytes.argtypes = [i32, i32, ctypes.POINTER(sz)]
     lib.kd_cdf_train_workspace_bytes.restype = ctypes.c_int
-    lib.kd_cdf_train.argtypes = [vp, i64, i32, i32, i32, i32, fp, vp, vp, sz, vp]
+    lib.kd_cdf_train.argtypes = [vp, i64, i32, i32, i32, i32, i32, fp, vp, vp, sz, vp]
     lib.kd_cdf_train.restype = ctypes.c_int
     lib.kd_cdf_loss_grad.argtypes = [vp, i32, i32, u32, u32, vp, vp, vp, vp, vp]
     lib.kd_cdf_loss_grad.restype = ctypes.c_int
@@ -94,7 +100,7 @@ def _load():
 lib = _load()
 
 # Every symbol include/kdtree.h declares (the tests check the library exports them).
-EXPORTED = ["kd_strerror", "kdtree_workspace_bytes", "kdtree_build", "kdtree_presort",
+EXPORTED = ["kd_strerror", "kd_status", "kdtree_workspace_bytes", "kdtree_build", "kdtree_presort",
             "kdtree_partition", "kdtree_build_select", "kdtree_workspace_bytes_batched",
             "kdtree_build_batched",
             "kd_cdf_model_bytes", "kd_cdf_train_workspace_bytes", "kd_cdf_train",
@@ -122,6 +128,16 @@ def probe_stop(capacity: int):
     cnt = ctypes.c_int32(0)
     check(lib.kd_probe_stop(buf, ctypes.byref(cnt)), "kd_probe_stop")
     return [float(buf[i]) for i in range(cnt.value)]
+
+
+def status(workspace_ptr, workspace_bytes: int, stream_ptr) -> int:
+    """The status bits of the last build enqueued with a workspace
+    (kd_status: waits for the stream); raises KdError when one is set."""
+    bits = ctypes.c_uint32(0)
+    rc = lib.kd_status(workspace_ptr, workspace_bytes, ctypes.byref(bits), stream_ptr)
+    if rc != KD_OK:
+        raise KdError(f"kd_status: {lib.kd_strerror(rc).decode()} ({rc}), bits {bits.value:#x}")
+    return int(bits.value)
 
 
 def check(rc: int, what: str) -> None:

@@ -22,6 +22,7 @@ namespace kd {
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kStatusWords = 4;  // the status word and spare words at the workspace start
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -36,7 +37,7 @@ int tree_digit_passes(int B) {
 // The learned presort appends its own regions, so the regions shared with the
 // plain build sit at the same offsets in both layouts.
 struct Layout {
-  size_t vbuf, carry, S, rec0, rec1, rec2;
+  size_t status, vbuf, carry, S, rec0, rec1, rec2;
   size_t rcnt, rgrp, dcnt, seginfo, lcnt, lcarry, lstat, ltick;
   size_t uoff, wgbase, lmax, queue, offs, ties, nodes;
   size_t starts, flags, lkey, carry2;  // learned presort only
@@ -62,6 +63,7 @@ Layout plan(int64_t n, int k, int B, bool learned = false) {
     o = align_up(o + bytes);
     return at;
   };
+  L.status = take(4 * kStatusWords);    // device status word, always at offset 0
   L.vbuf = take(4 * un * (k + 2) * 2);  // radix passes: two sets of k+2 quantity slots
   L.carry = take(4 * un * (k + 1));     // key words (and tree ids) handed between sorts
   L.S = take(4 * un);                   // row ids in order 0 (the deduplicated order-0 array)
@@ -181,11 +183,16 @@ struct Pass {
   int shift;  // digit
 };
 
+// The status word of the build being enqueued (set by every entry point that
+// enqueues a build before its first launch; null outside builds).
+thread_local uint32_t* t_status = nullptr;
+
 int run_sort(std::vector<Quant>& q, const std::vector<Pass>& passes, const TupleSrc& ts, int64_t n,
              const int32_t* n_dev, uint32_t* vb, int slots, uint32_t* rcnt, uint32_t* rgrp,
              hipStream_t st, const int32_t* gate = nullptr) {
   RadixExtra ex;
   ex.gate = gate;
+  ex.status = t_status;
   const size_t un = (size_t)n;
   auto slot = [&](int set, int i) { return vb + ((size_t)set * slots + i) * un; };
   const int np = (int)passes.size();
@@ -254,6 +261,7 @@ int learned_sort(std::vector<Quant> q, const LearnedSort& ls, const TupleSrc& ts
   auto slot = [&](int set, int i) { return vb + ((size_t)set * slots + i) * un; };
   KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(ls.flag), 0u, 1, st));
   RadixExtra ex;
+  ex.status = t_status;
   ex.model = ls.model;
   ex.nb_bits = ls.nb_bits;
   // bucket passes: stable, keyed by the bucket's 8-bit digits, moving everything
@@ -331,6 +339,7 @@ ForestArgs forest_args(const Job& J, const Layout& L) {
   fa.lmax = at<int32_t>(J.ws, L.lmax);
   fa.wgbase = at<int32_t>(J.ws, L.wgbase);
   fa.queue = at<int32_t>(J.ws, L.queue);
+  fa.status = at<uint32_t>(J.ws, L.status);
   return fa;
 }
 
@@ -363,6 +372,8 @@ int presort_impl(const Job& J, hipStream_t st, bool first_only = false) {
   const int tp = tree_digit_passes(B);
   const TupleSrc ts{static_cast<const uint32_t*>(J.tuples), k, J.dtype == KD_F32 ? 1 : 0};
 
+  t_status = at<uint32_t>(ws, L.status);
+  KD_TRY(launch_fill_u32(t_status, 0u, kStatusWords, st));
   if (learned) KD_TRY(launch_fill_u32(at<uint32_t>(ws, L.flags), 0u, k, st));
   KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(uoff), 0x7FFFFFFFu, B, st));
   KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(uoff + B), 0u, 1, st));
@@ -530,8 +541,10 @@ int presort_impl(const Job& J, hipStream_t st, bool first_only = false) {
           pl.word = 0;
           pl.out = slot(set ^ 1, v + 1);
         }
+        RadixExtra rx;
+        rx.status = t_status;
         KD_LAUNCH(KD_K_RECORDS, launch_radix_pass(kin, ts, 0, slot(set ^ 1, 0), pay, n, total,
-                                                  place_shift(p), rcnt, rgrp, st));
+                                                  place_shift(p), rcnt, rgrp, st, rx));
         set ^= 1;
         kin = slot(set, 0);
       }
@@ -541,7 +554,7 @@ int presort_impl(const Job& J, hipStream_t st, bool first_only = false) {
         pa.val[v] = slot(set, v + 1);
         pa.dst[v] = vals[v].second;
       }
-      KD_LAUNCH(KD_K_RECORDS, launch_place(slot(set, 0), pa, n, total, st));
+      KD_LAUNCH(KD_K_RECORDS, launch_place(slot(set, 0), pa, n, total, t_status, st));
     }
   }
   return KD_OK;
@@ -606,9 +619,11 @@ int partition_impl(const Job& J, hipStream_t st) {
           pay.p[c].word = 0;
         }
         const TupleSrc none{nullptr, k, 0};
+        RadixExtra rx;
+        rx.status = fa.status;
         KD_LAUNCH(KD_K_LEVEL, launch_radix_pass(dkey, none, 0, nullptr, pay, n, nu_dev, 0,
                                                 at<uint32_t>(ws, L.rcnt), at<uint32_t>(ws, L.rgrp),
-                                                st, RadixExtra{}));
+                                                st, rx));
         return KD_OK;
       };
       for (int d = 0; d < levels; ++d) {
@@ -792,9 +807,21 @@ const char* kd_strerror(int code) {
     case KD_EINVAL: return "invalid argument";
     case KD_ENOMEM: return "workspace too small";
     case KD_EHIP: return "HIP runtime error";
-    case KD_EUNSUPPORTED: return "unsupported size (n or k beyond the limits)";
+    case KD_EUNSUPPORTED: return "unsupported size (n or k beyond the limits) or model kind";
+    case KD_EINTERNAL: return "internal inconsistency found by a kernel (see kd_status)";
     default: return "unknown status";
   }
+}
+
+int kd_status(const void* d_workspace, size_t workspace_bytes, uint32_t* h_bits, void* stream) {
+  if (!d_workspace || !h_bits || !kd::aligned4(d_workspace)) return KD_EINVAL;
+  if (workspace_bytes < 4 * (size_t)kd::kStatusWords) return KD_ENOMEM;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  uint32_t bits = 0;
+  if (hipMemcpyAsync(&bits, d_workspace, 4, hipMemcpyDeviceToHost, st) != hipSuccess) return KD_EHIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return KD_EHIP;
+  *h_bits = bits;
+  return bits ? KD_EINTERNAL : KD_OK;
 }
 
 int kdtree_workspace_bytes(int64_t n, int32_t k, int32_t dtype, size_t* h_bytes) {
@@ -948,11 +975,12 @@ int kd_cdf_train_workspace_bytes(int32_t k, int32_t n_samples, size_t* h_bytes) 
   return KD_OK;
 }
 
-int kd_cdf_train(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, int32_t n_samples,
-                 int32_t steps, float lr, void* d_models, void* d_workspace, size_t workspace_bytes,
-                 void* stream) {
+int kd_cdf_train(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, int32_t kind,
+                 int32_t n_samples, int32_t steps, float lr, void* d_models, void* d_workspace,
+                 size_t workspace_bytes, void* stream) {
   if (n < 1 || k < 1 || n_samples < 1 || steps < 0 || (dtype != KD_I32 && dtype != KD_F32))
     return KD_EINVAL;
+  if (kind != KD_CDF_PWL) return KD_EUNSUPPORTED;
   if (!(lr > 0.f) || !std::isfinite(lr)) return KD_EINVAL;
   if (n > KD_MAX_N || k > KD_MAX_K || n_samples > KD_CDF_MAX_SAMPLES || steps > KD_CDF_MAX_STEPS)
     return KD_EUNSUPPORTED;

@@ -71,6 +71,7 @@ struct Forest {
   const int32_t* lmax;    // deepest global level any tree needs
   const int32_t* wgbase;  // on-chip finish items of tree b: wgbase[b] .. wgbase[b+1]-1
   int32_t* queue;         // work counter of the on-chip finish (zero before it runs)
+  uint32_t* status;       // the build's status word
 };
 
 // Largest b < B with v[b] <= x (v non-decreasing, v[0] <= x).
@@ -198,7 +199,11 @@ __device__ void find_subarrays(const RecBufs& B, const Forest& F, int64_t n, int
       }
     }
   }
-  if (lane == 0) out->nseg = min((int)popc64(km), kMaxSeg);
+  if (lane == 0) {
+    const int ns = (int)popc64(km);
+    if (ns > kMaxSeg) atomicOr(F.status, kStatusLevelSeg);  // subarrays below C elements
+    out->nseg = min(ns, kMaxSeg);
+  }
 }
 
 // Subarrays meeting every tile, their medians' ranks, and the row ids of the
@@ -463,7 +468,8 @@ __device__ __forceinline__ void level_move_tile(const uint32_t* __restrict__ src
                                                int t0, int t1, const SegInfo* __restrict__ gsi,
                                                SegInfo& si, uint64_t carry, uint32_t* s_chunk,
                                                uint32_t* s_pre, const LookBack& lb,
-                                               uint64_t* s_carry, uint32_t wmask) {
+                                               uint64_t* s_carry, uint32_t wmask,
+                                               uint32_t* status) {
   const int tid = threadIdx.x;
   const int w = tid / kWave;
   const int lane = tid % kWave;
@@ -570,7 +576,10 @@ __device__ __forceinline__ void level_move_tile(const uint32_t* __restrict__ src
     }
     const int m = s + ((e - s) >> 1);
     const int d = (flag[it] == 1u) ? s + low : m + 1 + (i - s - low - nd);
-    if (d >= s && d <= e && d != m) dest[it] = d;  // otherwise the counts were inconsistent
+    if (d >= s && d <= e && d != m)
+      dest[it] = d;
+    else  // only if the counts were inconsistent
+      atomicOr(status, kStatusLevelMove);
   }
 #pragma unroll
   for (int c = 0; c < W; ++c) {
@@ -627,7 +636,7 @@ __global__ __launch_bounds__(kLvThreads) void k_level_move(const RecBufs B, cons
   const int cp = (p - j - 1 + 2 * k) % k;
   const LookBack lb{};
   level_move_tile<R, false>(src, dst, n, cp, t0, t1, seginfo + t, s_si, cy, s_chunk, s_pre, lb,
-                            nullptr, wmask);
+                            nullptr, wmask, F.status);
 }
 
 // Count, chain and move in one launch (look-back).  Tile numbers come from
@@ -662,7 +671,7 @@ __global__ __launch_bounds__(kLvThreads) void k_level_fused(const RecBufs B, con
   const int cp = (p - j - 1 + 2 * k) % k;
   const LookBack lb{status, k - 1, a, t, (uint32_t)depth + 1};
   level_move_tile<R, true>(src, dst, n, cp, t0, t1, seginfo + t, s_si, 0, s_chunk, s_pre, lb,
-                           &s_carry, ~0u);
+                           &s_carry, ~0u, F.status);
 }
 
 hipError_t launch_level(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1, uint32_t* b2,
@@ -674,7 +683,7 @@ hipError_t launch_level(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1
   const int tiles = (int)((n + kLevelTile - 1) / kLevelTile);
   const unsigned grid = (unsigned)(tiles * (k - 1));
   RecBufs B{rec0, rows, b1, b2};
-  Forest F{fa.B, fa.off, fa.uoff, fa.lmax, fa.wgbase, fa.queue};
+  Forest F{fa.B, fa.off, fa.uoff, fa.lmax, fa.wgbase, fa.queue, fa.status};
   SegInfo* si = static_cast<SegInfo*>(seginfo);
   if (defer && status) return hipErrorInvalidValue;  // deferred: three-launch levels only
   uint64_t* tval = status ? nullptr : reinterpret_cast<uint64_t*>(cnt);
@@ -804,11 +813,17 @@ __global__ __launch_bounds__(64) void k_node_ranks(const RecBufs B, const Forest
     else
       e = m - 1;
   }
-  if (e < s) return;  // not reached: global-level subarrays hold at least C rows
+  if (e < s) {  // not reached: global-level subarrays hold at least C rows
+    atomicOr(F.status, kStatusNode);
+    return;
+  }
   const int p = depth % k;
   const int m = base + s + ((e - s) >> 1);
   const uint32_t r1 = rec_array<true>(B, depth, p, k, n)[m];
-  if (r1 >= (uint32_t)n) return;  // not reached: a rank
+  if (r1 >= (uint32_t)n) {  // not reached: a rank
+    atomicOr(F.status, kStatusNode);
+    return;
+  }
   node_rank[(1 << depth) - 1 + q] = B.rec0[record_offset((p + 1) % k, k, n) + (int64_t)(k - 2) * n + r1];
 }
 
@@ -851,7 +866,7 @@ hipError_t launch_node_ranks(const uint32_t* rec0, const uint32_t* rows, uint32_
                              uint32_t* node_rank, hipStream_t st) {
   if (n <= 0 || k < 2 || fa.B != 1 || depth < 0 || depth > kMaxK - 2) return hipErrorInvalidValue;
   RecBufs B{rec0, rows, b1, b2};
-  Forest F{fa.B, fa.off, fa.uoff, fa.lmax, fa.wgbase, fa.queue};
+  Forest F{fa.B, fa.off, fa.uoff, fa.lmax, fa.wgbase, fa.queue, fa.status};
   const int nodes = 1 << depth;
   hipLaunchKernelGGL(k_node_ranks, dim3((nodes + 63) / 64), dim3(64), 0, st, B, F, n, k, depth,
                      node_rank);
@@ -863,7 +878,7 @@ hipError_t launch_defer_bucket(const uint32_t* rec0, const uint32_t* rows, uint3
                                const uint32_t* node_rank, uint32_t* key, hipStream_t st) {
   if (n <= 0 || k < 3 || fa.B != 1 || j < 2 || j >= k) return hipErrorInvalidValue;
   RecBufs B{rec0, rows, b1, b2};
-  Forest F{fa.B, fa.off, fa.uoff, fa.lmax, fa.wgbase, fa.queue};
+  Forest F{fa.B, fa.off, fa.uoff, fa.lmax, fa.wgbase, fa.queue, fa.status};
   const int64_t want = (n + 255) / 256;
   const unsigned grid = (unsigned)(want < 4096 ? want : 4096);
   hipLaunchKernelGGL(k_defer_bucket, dim3(grid), dim3(256), 0, st, B, F, n, k, j, node_rank, key);
@@ -1187,6 +1202,8 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
         const int cb = (curmask >> j) & 1;
         if (dest >= ss && dest <= ee)
           s_lid[((cb ^ 1) * k + j) * C + dest] = s_lid[(cb * k + j) * C + it * kLfThreads + tid];
+        else  // only if the counts were inconsistent
+          atomicOr(F.status, kStatusLeaf);
       }
     }
     curmask ^= ((1u << k) - 1) & ~(1u << p);  // every array but the split one moved
@@ -1217,7 +1234,7 @@ hipError_t launch_leaf(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1,
   if (n <= 0 || k < 2) return hipSuccess;
   const size_t lds = leaf_lds_bytes(cutover, k);
   RecBufs B{rec0, rows, b1, b2};
-  Forest F{fa.B, fa.off, fa.uoff, fa.lmax, fa.wgbase, fa.queue};
+  Forest F{fa.B, fa.off, fa.uoff, fa.lmax, fa.wgbase, fa.queue, fa.status};
   const void* fn = nullptr;
 #define KD_LF_R(IT)                                                  \
   switch (k - 1) {                                                   \
@@ -1279,7 +1296,7 @@ hipError_t launch_copy_k1(const uint32_t* S0, const ForestArgs& fa, int64_t n, i
   if (n <= 0) return hipSuccess;
   int64_t blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  Forest F{fa.B, fa.off, fa.uoff, fa.lmax, fa.wgbase, fa.queue};
+  Forest F{fa.B, fa.off, fa.uoff, fa.lmax, fa.wgbase, fa.queue, fa.status};
   hipLaunchKernelGGL(k_copy_k1, dim3((unsigned)blocks), dim3(256), 0, st, S0, F, perm);
   return hipGetLastError();
 }

@@ -24,6 +24,21 @@ struct ForestArgs {
   const int32_t* lmax;
   const int32_t* wgbase;
   int32_t* queue;
+  uint32_t* status;  // the build's status word (see kStatus* below)
+};
+
+// Bits of a build's device status word (the first word of its workspace,
+// cleared when the presort starts).  A kernel that finds counts contradicting
+// each other (which a correct build never does) drops the write it cannot
+// place and sets its bit; the host then reports KD_EINTERNAL.
+enum : uint32_t {
+  kStatusRadix = 1u,       // a radix pass computed a destination outside the array
+  kStatusLevelSeg = 2u,    // more subarrays meet a level tile than it can hold
+  kStatusLevelMove = 4u,   // a level move computed a destination outside its subarray
+  kStatusLeaf = 8u,        // the on-chip finish computed a destination outside its subarray
+  kStatusSplit = 16u,      // a multi-level split computed a destination outside its subarray
+  kStatusPlace = 32u,      // a record placement key was not a permutation
+  kStatusNode = 64u,       // a node rank lookup found no subarray or no rank
 };
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t st);
@@ -62,6 +77,7 @@ struct RadixExtra {
   const CdfModel* model = nullptr;
   int nb_bits = 0;
   const int32_t* gate = nullptr;
+  uint32_t* status = nullptr;  // status word (kStatusRadix), or null
 };
 
 // One stable LSD radix pass on 8-bit digit `shift`: per-tile digit counts, a
@@ -121,7 +137,7 @@ struct PlaceArgs {
   uint32_t* dst[kMaxK];
 };
 hipError_t launch_place(const uint32_t* key, const PlaceArgs& pa, int64_t n, const int32_t* total,
-                        hipStream_t st);
+                        uint32_t* status, hipStream_t st);
 int place_passes(int64_t n);
 int place_shift(int pass);
 

@@ -352,7 +352,10 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
       const uint32_t kk = s_keys[i];
       const uint32_t d = (kk >> shift) & 0xFF;
       const int g = (int)s_gbase[d] + (i - (int)s_tile_excl[d]);
-      if (g >= 0 && g < n) dest[j] = g;  // out of range only if the counts were inconsistent
+      if (g >= 0 && g < n)
+        dest[j] = g;
+      else if (ex.status)  // only if the counts were inconsistent
+        atomicOr(ex.status, kStatusRadix);
       if (kWriteKeys && dest[j] >= 0) keys_out[g] = kk;
     }
   }
@@ -1060,7 +1063,7 @@ constexpr int kPlaceBits = 12;
 constexpr int kPlaceTile = 1 << kPlaceBits;
 
 __global__ __launch_bounds__(512) void k_place(const uint32_t* __restrict__ key, const PlaceArgs pa,
-                                              const int32_t* total) {
+                                              const int32_t* total, uint32_t* status) {
   extern __shared__ uint32_t s_val[];  // [nv][kPlaceTile]
   const int nu = *total;
   const int base = blockIdx.x * kPlaceTile;
@@ -1068,7 +1071,10 @@ __global__ __launch_bounds__(512) void k_place(const uint32_t* __restrict__ key,
   const int cnt = min(nu - base, kPlaceTile);
   for (int p = (int)threadIdx.x; p < cnt; p += 512) {
     const uint32_t slot = key[base + p] - (uint32_t)base;
-    if (slot >= (uint32_t)cnt) continue;  // not a permutation (cannot happen)
+    if (slot >= (uint32_t)cnt) {  // not a permutation: the counts were inconsistent
+      atomicOr(status, kStatusPlace);
+      continue;
+    }
 #pragma unroll
     for (int v = 0; v < kMaxK; ++v)
       if (v < pa.nv) s_val[v * kPlaceTile + slot] = pa.val[v][base + p];
@@ -1091,14 +1097,14 @@ int place_passes(int64_t n) {
 int place_shift(int pass) { return kPlaceBits + pass * kRadixBits; }
 
 hipError_t launch_place(const uint32_t* key, const PlaceArgs& pa, int64_t n, const int32_t* total,
-                        hipStream_t st) {
+                        uint32_t* status, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const size_t lds = (size_t)pa.nv * kPlaceTile * 4;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_place),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int blocks = (int)((n + kPlaceTile - 1) / kPlaceTile);
-  hipLaunchKernelGGL(k_place, dim3(blocks), dim3(512), lds, st, key, pa, total);
+  hipLaunchKernelGGL(k_place, dim3(blocks), dim3(512), lds, st, key, pa, total, status);
   return hipGetLastError();
 }
 

@@ -99,11 +99,17 @@ def test_learned_and_training_reject_bad_arguments(L):
     assert L.lib.kd_cdf_train_workspace_bytes(3, (1 << 20) + 1, ctypes.byref(out)) == -4
     ws = 1 << 30
     # n < 1, bad steps, non-positive learning rate, null model: rejected before any launch
-    assert L.lib.kd_cdf_train(vp(FAKE), 0, 3, 0, 1024, 10, 0.1, vp(FAKE), vp(FAKE), ws, None) == -1
-    assert L.lib.kd_cdf_train(vp(FAKE), 100, 3, 0, 1024, -1, 0.1, vp(FAKE), vp(FAKE), ws, None) == -1
-    assert L.lib.kd_cdf_train(vp(FAKE), 100, 3, 0, 1024, 10, 0.0, vp(FAKE), vp(FAKE), ws, None) == -1
-    assert L.lib.kd_cdf_train(vp(FAKE), 100, 3, 0, 1024, 10, 0.1, None, vp(FAKE), ws, None) == -1
-    assert L.lib.kd_cdf_train(vp(FAKE), 100, 3, 0, 1024, 10, 0.1, vp(FAKE), vp(FAKE), 8, None) == -2
+    assert L.lib.kd_cdf_train(vp(FAKE), 0, 3, 0, 0, 1024, 10, 0.1, vp(FAKE), vp(FAKE), ws, None) == -1
+    assert L.lib.kd_cdf_train(vp(FAKE), 100, 3, 0, 0, 1024, -1, 0.1, vp(FAKE), vp(FAKE), ws, None) == -1
+    assert L.lib.kd_cdf_train(vp(FAKE), 100, 3, 0, 0, 1024, 10, 0.0, vp(FAKE), vp(FAKE), ws, None) == -1
+    assert L.lib.kd_cdf_train(vp(FAKE), 100, 3, 0, 0, 1024, 10, 0.1, None, vp(FAKE), ws, None) == -1
+    assert L.lib.kd_cdf_train(vp(FAKE), 100, 3, 0, 0, 1024, 10, 0.1, vp(FAKE), vp(FAKE), 8, None) == -2
+    # model kinds: only the piecewise-linear model (0) is built; the MLP (1)
+    # and unknown kinds are refused before any launch
+    assert L.lib.kd_cdf_train(vp(FAKE), 100, 3, 0, L.KD_CDF_MLP, 1024, 10, 0.1, vp(FAKE), vp(FAKE), ws,
+                              None) == L.KD_EUNSUPPORTED
+    assert L.lib.kd_cdf_train(vp(FAKE), 100, 3, 0, 7, 1024, 10, 0.1, vp(FAKE), vp(FAKE), ws,
+                              None) == L.KD_EUNSUPPORTED
     assert L.lib.kd_cdf_eval(vp(FAKE), vp(FAKE), 10, 17, vp(FAKE), vp(FAKE), None) == -1
     assert L.lib.kd_cdf_loss_grad(vp(FAKE), 0, 0, 0, 1, vp(FAKE), vp(FAKE), vp(FAKE), vp(FAKE), None) == -1
     assert L.lib.kdtree_workspace_bytes_learned(-1, 3, 0, ctypes.byref(out)) == -1
@@ -120,9 +126,19 @@ def test_learned_and_training_reject_bad_arguments(L):
 
 
 def test_strerror(L):
-    for code in (0, -1, -2, -3, -4):
-        assert L.lib.kd_strerror(code)
+    for code in (0, -1, -2, -3, -4, -5):
+        assert L.lib.kd_strerror(code) and L.lib.kd_strerror(code) != b"unknown status"
     assert L.lib.kd_strerror(-99) == b"unknown status"
+
+
+def test_status_rejects_bad_arguments(L):
+    """kd_status validates before it touches the stream or the device."""
+    vp = ctypes.c_void_p
+    bits = ctypes.c_uint32(0)
+    assert L.lib.kd_status(None, 1024, ctypes.byref(bits), None) == -1
+    assert L.lib.kd_status(vp(FAKE + 2), 1024, ctypes.byref(bits), None) == -1
+    assert L.lib.kd_status(vp(FAKE), 1024, None, None) == -1
+    assert L.lib.kd_status(vp(FAKE), 8, ctypes.byref(bits), None) == -2
 
 
 def test_probe_rejects_bad_class(L):

@@ -313,20 +313,38 @@ def test_batched_single_tree_equals_plain(kd):
     assert_batched_same(kd, t, np.array([0, 50000], dtype=np.int64))
 
 
-def test_batched_c4_workload_sampled(kd):
-    """The batched workload (4096 point-cloud trees, log-uniform 64..65536 rows,
-    float32) in the benchmark's configuration; every 64th tree is compared."""
-    t, offsets = kdgen.c4_batched()
-    print(f"[gpu case] c4 batched rows={offsets[-1]}", flush=True)
-    perm, nu = kd.build_batched(torch.from_numpy(t).cuda(), offsets)
-    torch.cuda.synchronize()
-    perm = perm.cpu().numpy()
-    nu = nu.cpu().numpy()
-    for b in range(0, len(offsets) - 1, 64):
+def _oracle_forest(t, offsets, threads=16):
+    """The single-tree oracle of every tree of a batch (trees in parallel:
+    the oracle's C calls release the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(b):
         s, e = int(offsets[b]), int(offsets[b + 1])
-        want = oracle.build_tree(t[s:e], children=False)
-        assert nu[b] == want["n_unique"]
-        assert np.array_equal(perm[s:s + nu[b]], want["perm"])
+        return oracle.build_tree(t[s:e], children=False)
+
+    with ThreadPoolExecutor(threads) as ex:
+        return list(ex.map(one, range(len(offsets) - 1)))
+
+
+@pytest.mark.parametrize("knobs", [{}, {"cutover": 1024, "leaf_blocks": 4096, "records": 2}])
+def test_batched_c4_workload_every_tree(kd, knobs):
+    """The batched workload (4096 point-cloud trees, log-uniform 64..65536 rows,
+    float32) in the default and in the benchmark's tuned configuration; every
+    tree is compared with its own oracle build."""
+    t, offsets = kdgen.c4_batched()
+    print(f"[gpu case] c4 batched rows={offsets[-1]} knobs={knobs}", flush=True)
+    bb = kd.BatchedBuilder(offsets, 3, torch.float32, **knobs)
+    perm_t = torch.full((int(offsets[-1]),), -1, dtype=torch.int32, device="cuda")
+    bb.build(torch.from_numpy(t).cuda(), perm_t)
+    assert bb.status() == 0
+    perm = perm_t.cpu().numpy()
+    nu = bb.n_unique.cpu().numpy()
+    wants = _oracle_forest(t, offsets)
+    for b, want in enumerate(wants):
+        s = int(offsets[b])
+        assert nu[b] == want["n_unique"], b
+        assert np.array_equal(perm[s:s + nu[b]], want["perm"]), b
+        assert np.all(perm[s + nu[b]:int(offsets[b + 1])] == -1), b
 
 
 def _capture(fn):

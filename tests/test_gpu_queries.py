@@ -231,7 +231,8 @@ def test_visit_counter(kd):
 
 @pytest.mark.parametrize("dtype", ["i32", "f32"])
 def test_queries_large_brute_force(kd, dtype):
-    # 2^20 rows, 2^16 queries, checked on a sample of them against a scan
+    # 2^20 rows, 2^16 queries; 1000 boxes and 256 nearest-neighbour queries
+    # of them are checked against a scan
     g = kdgen.rng(960)
     n = 1 << 20
     if dtype == "i32":
@@ -252,10 +253,17 @@ def test_queries_large_brute_force(kd, dtype):
     counts_b = kd.region_count(dt, perm, nu, torch.from_numpy(lo).cuda(), torch.from_numpy(hi).cuda(),
                                nodes=dn, bounds=kd.subtree_bounds(dn, nu)).cpu().numpy()
     assert np.array_equal(counts_b, counts)
-    for q in g.choice(nq, size=24, replace=False):
-        inside = np.all((nodes >= lo[q]) & (nodes <= hi[q]), axis=1)
+    # scan of each box over the nodes in the slab of its first coordinate
+    # (nodes sorted by that coordinate once; every node of the slab checked)
+    order = np.argsort(nodes[:, 0], kind="stable")
+    by_x = nodes[order]
+    for q in g.choice(nq, size=1000, replace=False):
+        a = np.searchsorted(by_x[:, 0], lo[q, 0], side="left")
+        b = np.searchsorted(by_x[:, 0], hi[q, 0], side="right")
+        slab = by_x[a:b]
+        inside = np.all((slab >= lo[q]) & (slab <= hi[q]), axis=1)
         assert counts[q] == int(inside.sum()), f"box {q}"
-    for q in g.choice(nq, size=6, replace=False):
+    for q in g.choice(nq, size=256, replace=False):
         want_rows, _ = brute_nearest_fast(t, p, pts[q], 8)
         assert got[q].tolist() == want_rows, f"query {q}"
 
@@ -265,7 +273,8 @@ def brute_nearest_fast(t, nodes, q, m):
     the exact order on a generous candidate set."""
     x = t[nodes].astype(np.float64)
     approx = ((x - q.astype(np.float64)) ** 2).sum(axis=1)
-    cand = nodes[np.argsort(approx, kind="stable")[:max(64, 8 * m)]]
+    c = max(64, 8 * m)
+    cand = nodes[np.argpartition(approx, c)[:c]] if len(nodes) > c else nodes
     return brute_nearest(t, cand, q, m)
 
 

@@ -126,3 +126,116 @@ def test_mass_floor_keeps_levels_increasing():
     c = L.levels(th, 1 << 16)
     assert c[0] == 0.0 and c[-1] == 1.0
     assert np.all(np.diff(c) > 0.2 / (1 << 16))
+
+
+# ---- training and export pinned to outside facts ------------------------------------
+
+def _p_with_edge_cases(seed):
+    """Segment masses with zeros and one entry of exactly 1/K (gradient 0 at
+    theta = 0), the rest Dirichlet."""
+    g = rng(seed)
+    p = g.dirichlet(np.full(L.K, 0.5))
+    p[:100] = 0.0
+    p[100] = 1.0 / L.K
+    rest = np.ones(L.K, dtype=bool)
+    rest[:101] = False
+    p[rest] *= (1.0 - p[100]) / p[rest].sum()
+    return p
+
+
+def _adam_pins_hold(train):
+    """True when `train` (signature of L.train_adam) satisfies both pins:
+    the first step's closed form and agreement with torch.optim.Adam."""
+    import torch
+
+    lr = 0.05
+    for seed in (11, 12):
+        p = _p_with_edge_cases(seed)
+        # Step 1 from theta = 0: the moment estimates after bias correction
+        # are g and g^2 exactly, so the step is -lr * g / (|g| + eps) with the
+        # gradient at theta = 0 (about 1/K - p; the gradient itself is pinned
+        # by finite differences above).
+        g = L.loss_grad(np.zeros(L.K), p)[1]
+        assert np.max(np.abs(g - (1.0 / L.K - p))) < 1e-15
+        want1 = -lr * g / (np.abs(g) + 1e-8)
+        if not np.allclose(train(p, 1, lr), want1, rtol=1e-12, atol=1e-15):
+            return False
+        # Many steps: torch's Adam (the same published rule, a library
+        # implementation) fed the oracle's own gradient of the objective.
+        th = torch.zeros(L.K, dtype=torch.float64, requires_grad=True)
+        opt = torch.optim.Adam([th], lr=lr, betas=(0.9, 0.999), eps=1e-8)
+        for _ in range(40):
+            _, gr = L.loss_grad(th.detach().numpy(), p)
+            th.grad = torch.from_numpy(gr.copy())
+            opt.step()
+        if not np.allclose(train(p, 40, lr), th.detach().numpy(), rtol=1e-9, atol=1e-12):
+            return False
+    return True
+
+
+def test_adam_matches_first_step_and_torch_optim():
+    assert _adam_pins_hold(L.train_adam)
+
+
+def _adam_variant(bias_correct=True, eps_inside=False, b2=0.999):
+    """A copy of the oracle's Adam with one planted mistake (CPU only), to
+    show the pins above catch it."""
+    def train(p, steps, lr, b1=0.9, eps=1e-8):
+        th = np.zeros(L.K)
+        m = np.zeros(L.K)
+        s = np.zeros(L.K)
+        for t in range(1, steps + 1):
+            _, g = L.loss_grad(th, p)
+            m = b1 * m + (1 - b1) * g
+            s = b2 * s + (1 - b2) * g * g
+            mh = m / (1 - b1 ** t) if bias_correct else m
+            sh = s / (1 - b2 ** t) if bias_correct else s
+            den = np.sqrt(sh + eps) if eps_inside else np.sqrt(sh) + eps
+            th = th - lr * mh / den
+        return th
+    return train
+
+
+@pytest.mark.parametrize("mistake", [dict(bias_correct=False), dict(eps_inside=True), dict(b2=0.99)])
+def test_adam_pins_catch_planted_mistakes(mistake):
+    assert _adam_pins_hold(_adam_variant())  # the variant without a mistake passes
+    assert not _adam_pins_hold(_adam_variant(**mistake))
+
+
+@pytest.mark.parametrize("S", [0, 1 << 16])
+def test_levels_of_uniform_logits_are_equal_steps(S):
+    """Equal logits give equal masses 1/K; the floor adds the same amount to
+    each and the renormalisation divides it back out, so c_i = i/K."""
+    c = L.running_levels(np.zeros(L.K), S)
+    assert np.max(np.abs(c - np.arange(L.K + 1) / L.K)) < 1e-12
+
+
+@pytest.mark.parametrize("S", [0, 1 << 10, 1 << 16])
+def test_levels_of_two_valued_logits_by_hand(S):
+    """theta = log 2 on the first half of the segments, 0 on the second:
+    softmax gives 4/(3K) and 2/(3K); with the floor f = 1/(4S) (0 without
+    a sample size) every mass becomes (q + f) / (1 + K f).  Hence
+    c_{K/4} = (1/3 + K f/4) / (1 + K f), c_{K/2} = (2/3 + K f/2) / (1 + K f)
+    and c_K = 1, checked before anything is set to 1."""
+    th = np.zeros(L.K)
+    th[: L.K // 2] = np.log(2.0)
+    c = L.running_levels(th, S)
+    f = 0.25 / S if S else 0.0
+    K = L.K
+    assert abs(c[K // 4] - (1 / 3 + K * f / 4) / (1 + K * f)) < 1e-12
+    assert abs(c[K // 2] - (2 / 3 + K * f / 2) / (1 + K * f)) < 1e-12
+    assert abs(c[K] - 1.0) < 1e-12
+    assert abs(c[3 * K // 4] - (2 / 3 + 3 * K * f / 4 + 1 / 6) / (1 + K * f)) < 1e-12
+    assert np.array_equal(L.levels(th, S)[:-1], np.minimum(c[:-1], 1.0))
+
+
+def test_levels_refuse_masses_that_do_not_sum_to_one():
+    """A wrong normaliser (planted in a copy of the export on the CPU) is
+    seen at c_K instead of being hidden by setting c_K to 1."""
+    th = np.zeros(L.K)
+    q = L.softmax(th)
+    fl = 0.25 / 1024
+    wrong = (q + fl) / (1.0 + (L.K - 1) * fl)  # normaliser off by one segment's floor
+    c = np.concatenate([[0.0], np.cumsum(wrong)])
+    assert abs(c[-1] - 1.0) > 1e-6
+    assert abs(L.running_levels(th, 1024)[-1] - 1.0) < 1e-12
