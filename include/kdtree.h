@@ -81,9 +81,22 @@ typedef struct kd_options {
                           >= 2 keeps its presorted order until depth j and
                           then reaches its depth-j layout in one stable
                           radix split by subtree instead of j moves (single
-                          builds; a batch runs form 1) */
+                          builds; a batch runs form 1), 4 = deferred
+                          partitioning at every level: at level L only the
+                          array sorted by dimension L mod k moves, in one
+                          stable split by subtree about the medians of the
+                          k-1 levels since it last split (single builds; a
+                          batch runs form 1) */
   int32_t reserved[3]; /* must be zero */
 } kd_options;
+
+/* Write masks of level form 4 for a tree with `levels` global levels
+ * (host only, diagnostic; no device work): h_level_mask[L] (levels words) =
+ * the record planes (bit c = plane c) the split at level L writes into the
+ * array sorted by dimension L mod k; h_final_mask[j] (k words) = the planes
+ * the last split of array j before the on-chip finish writes (0: none).
+ * 2 <= k <= KD_MAX_K, 0 <= levels <= 30. */
+int kd_level_plan(int32_t k, int32_t levels, uint32_t* h_level_mask, uint32_t* h_final_mask);
 
 /* Human-readable name of a status code (static string). */
 const char* kd_strerror(int code);

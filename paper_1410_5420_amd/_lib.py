@@ -43,6 +43,9 @@ def _load():
     lib.kd_strerror.restype = ctypes.c_char_p
     lib.kd_status.argtypes = [vp, sz, ctypes.POINTER(ctypes.c_uint32), vp]
     lib.kd_status.restype = ctypes.c_int
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    lib.kd_level_plan.argtypes = [i32, i32, u32p, u32p]
+    lib.kd_level_plan.restype = ctypes.c_int
     lib.kdtree_workspace_bytes.argtypes = [i64, i32, i32, ctypes.POINTER(sz)]
     lib.kdtree_workspace_bytes.restype = ctypes.c_int
     lib.kdtree_build.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp, vp, sz, opt, vp]
@@ -100,7 +103,7 @@ def _load():
 lib = _load()
 
 # Every symbol include/kdtree.h declares (the tests check the library exports them).
-EXPORTED = ["kd_strerror", "kd_status", "kdtree_workspace_bytes", "kdtree_build", "kdtree_presort",
+EXPORTED = ["kd_strerror", "kd_status", "kd_level_plan", "kdtree_workspace_bytes", "kdtree_build", "kdtree_presort",
             "kdtree_partition", "kdtree_build_select", "kdtree_workspace_bytes_batched",
             "kdtree_build_batched",
             "kd_cdf_model_bytes", "kd_cdf_train_workspace_bytes", "kd_cdf_train",
@@ -138,6 +141,14 @@ def status(workspace_ptr, workspace_bytes: int, stream_ptr) -> int:
     if rc != KD_OK:
         raise KdError(f"kd_status: {lib.kd_strerror(rc).decode()} ({rc}), bits {bits.value:#x}")
     return int(bits.value)
+
+
+def level_plan(k: int, levels: int):
+    """(level masks, final masks) of level form 4 (kd_level_plan, host only)."""
+    lm = (ctypes.c_uint32 * max(levels, 1))()
+    fm = (ctypes.c_uint32 * k)()
+    check(lib.kd_level_plan(k, levels, lm, fm), "kd_level_plan")
+    return [int(lm[i]) for i in range(levels)], [int(fm[j]) for j in range(k)]
 
 
 def check(rc: int, what: str) -> None:

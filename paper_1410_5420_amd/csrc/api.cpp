@@ -40,6 +40,7 @@ struct Layout {
   size_t status, vbuf, carry, S, rec0, rec1, rec2;
   size_t rcnt, rgrp, dcnt, seginfo, lcnt, lcarry, lstat, ltick;
   size_t uoff, wgbase, lmax, queue, offs, ties, nodes;
+  size_t med, sinfo, stval, stflag, scarry;  // level form 4
   size_t starts, flags, lkey, carry2;  // learned presort only
   size_t end;
 };
@@ -87,6 +88,13 @@ Layout plan(int64_t n, int k, int B, bool learned = false) {
   L.offs = take(16);
   L.ties = take(4 * ((size_t)kMaxTieRuns + 2));  // run list, count, flag
   L.nodes = take(4 * ((size_t)1 << (kMaxK - 1)));  // node ranks of deferred partitioning
+  // level form 4: median table (every depth above the smallest cutover),
+  // per-tile pieces, bucket counts, flags and carries
+  L.med = take(4 * ((size_t)2 << cutover_depth(nn, 1024)));
+  L.sinfo = take(lt * split_info_bytes());
+  L.stval = take(4 * (lt << (k > 1 ? k - 1 : 0)));
+  L.stflag = take(4 * lt);
+  L.scarry = take(4 * (lt << (k > 1 ? k - 1 : 0)));
   if (learned) {
     L.starts = take(4 * (((size_t)1 << kMaxBucketBits) + 1));
     L.flags = take(4 * kMaxK);
@@ -114,7 +122,7 @@ int check_opts(const kd_options* opts, int64_t* cutover, int* leaf_blocks, int* 
   if (opts) {
     for (int i = 0; i < 3; ++i)
       if (opts->reserved[i] != 0) return KD_EINVAL;
-    if (opts->level < 0 || opts->level > 3) return KD_EINVAL;
+    if (opts->level < 0 || opts->level > 4) return KD_EINVAL;
     *level = opts->level;
     if (opts->learned_sorts < 0 || opts->learned_sorts > 0xFF) return KD_EINVAL;
     *learned_sorts = opts->learned_sorts;
@@ -596,6 +604,44 @@ int partition_impl(const Job& J, hipStream_t st) {
       // one tree: every level moves only the planes later levels and the
       // on-chip finish read (a batch's trees end at different depths)
       const int defer = J.level == 3 && J.B == 1 && k >= 3 ? 1 : 0;
+      if (J.level == 4 && J.B == 1) {
+        // level form 4: at level L only array L mod k moves (one multi-level
+        // split), then the nodes of depth L are recorded; the arrays the
+        // on-chip finish reads get their last split after the last level
+        std::vector<uint32_t> lm(levels > 0 ? levels : 1, 0u), fm(kMaxK, 0u);
+        rolling_masks(k, levels, lm.data(), fm.data());
+        SplitJob sj{};
+        sj.n = n;
+        sj.k = k;
+        sj.uoff = fa.uoff;
+        sj.lmax = fa.lmax;
+        sj.status = fa.status;
+        uint32_t* med = at<uint32_t>(ws, L.med);
+        sj.med = med;
+        SplitInfo* info = at<SplitInfo>(ws, L.sinfo);
+        uint32_t* tval = at<uint32_t>(ws, L.stval);
+        uint32_t* tflag = at<uint32_t>(ws, L.stflag);
+        uint32_t* scarry = at<uint32_t>(ws, L.scarry);
+        for (int d = 0; d < levels; ++d) {
+          sj.level = d;
+          sj.final_j = -1;
+          sj.wmask = lm[d];
+          if (d >= 1)
+            KD_LAUNCH(KD_K_LEVEL, launch_split(r0, S, r1, r2, sj, info, tval, tflag, scarry, st));
+          KD_LAUNCH(KD_K_LEVEL, launch_split_medians(r0, S, r1, r2, sj, med, J.perm, st));
+        }
+        for (int j = 1; j < k && levels > 0; ++j) {
+          sj.level = -1;
+          sj.final_j = j;
+          sj.wmask = fm[j];
+          KD_LAUNCH(KD_K_LEVEL, launch_split(r0, S, r1, r2, sj, info, tval, tflag, scarry, st));
+        }
+        KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(fa.queue), 0u, 1, st));
+        KD_LAUNCH(KD_K_LEAF, launch_leaf(r0, S, r1, r2, n, k, cutover, fa, J.perm, items,
+                                         J.leaf_blocks, 2, st));
+        if (J.lo && J.hi) KD_TRY(launch_children(fa.uoff, n, J.lo, J.hi, st));
+        return KD_OK;
+      }
       std::vector<uint64_t> wm(levels > 0 ? levels : 1, ~0ull);
       if (J.B == 1 && !lookback && levels > 0) level_write_masks(k, levels, wm.data(), defer);
       // Deferred partitioning: array j >= 2 reaches its layout at depth
@@ -811,6 +857,16 @@ const char* kd_strerror(int code) {
     case KD_EINTERNAL: return "internal inconsistency found by a kernel (see kd_status)";
     default: return "unknown status";
   }
+}
+
+int kd_level_plan(int32_t k, int32_t levels, uint32_t* h_level_mask, uint32_t* h_final_mask) {
+  if (k < 2 || levels < 0 || !h_final_mask || (levels > 0 && !h_level_mask)) return KD_EINVAL;
+  if (k > KD_MAX_K || levels > 30) return KD_EUNSUPPORTED;
+  std::vector<uint32_t> lm(levels > 0 ? levels : 1, 0u), fm(kd::kMaxK, 0u);
+  kd::rolling_masks(k, levels, lm.data(), fm.data());
+  for (int l = 0; l < levels; ++l) h_level_mask[l] = lm[l];
+  for (int j = 0; j < k; ++j) h_final_mask[j] = fm[j];
+  return KD_OK;
 }
 
 int kd_status(const void* d_workspace, size_t workspace_bytes, uint32_t* h_bits, void* stream) {

@@ -58,6 +58,20 @@ __device__ __forceinline__ const uint32_t* rec_array(const RecBufs& B, int depth
   return buf_after(B, array_moves(kDefer ? 1 : 0, depth, j, k)) + record_offset(j, k, n);
 }
 
+// The on-chip finish's view of array j at the cutover depth: form 0 (levels
+// of form 1/2), 1 (deferred partitioning) or 2 (one split per level, whose
+// last split of each array the finish reads brought it to that depth).
+template <int kForm>
+__device__ __forceinline__ const uint32_t* leaf_array(const RecBufs& B, int depth, int j, int k,
+                                                      int64_t n) {
+  int moves;
+  if constexpr (kForm == 2)
+    moves = roll_moves(depth, j, k) + (depth >= 1 && roll_depth(depth, j, k) < depth ? 1 : 0);
+  else
+    moves = array_moves(kForm, depth, j, k);
+  return buf_after(B, moves) + record_offset(j, k, n);
+}
+
 // ---- forests ------------------------------------------------------------------
 // Several independent trees are built at once as a forest.  In the sorted
 // orders the distinct rows of tree b occupy positions uoff[b] .. uoff[b+1]-1
@@ -982,7 +996,7 @@ __device__ bool lds_radix_sort(uint32_t* ka, uint16_t* va, uint32_t* kb, uint16_
   return flipped;
 }
 
-template <int kItems, int R, bool kDefer>
+template <int kItems, int R, int kForm>
 __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Forest F, int64_t n,
                                                     int /* k: R + 1 */, int32_t* __restrict__ perm) {
   constexpr int k = R + 1;  // known at compile time: index arithmetic mod k folds
@@ -1035,7 +1049,7 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
   // local id, and the sorted list lets the other arrays find theirs by binary
   // search.  The row ids are read at the end at the order-0 ranks.
   {
-    const uint32_t* a1 = rec_array<kDefer>(B, lc, 1, k, n);
+    const uint32_t* a1 = leaf_array<kForm>(B, lc, 1, k, n);
     uint32_t* sk = reinterpret_cast<uint32_t*>(s_lid);        // sort scratch (aliases s_lid)
     uint16_t* sv = reinterpret_cast<uint16_t*>(sk + C);
     uint16_t* sv2 = sv + C;
@@ -1072,7 +1086,7 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
       }
     }
     for (int j = 2; j < k; ++j) {
-      const uint32_t* aj = rec_array<kDefer>(B, lc, j, k, n);
+      const uint32_t* aj = leaf_array<kForm>(B, lc, j, k, n);
       const int c0 = k - 1 - j;  // plane of order 0 in array j
 #pragma unroll
       for (int it = 0; it < kItems; ++it) {
@@ -1230,36 +1244,27 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
 hipError_t launch_leaf(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1, uint32_t* b2,
                        int64_t n, int k,
                        int64_t cutover, const ForestArgs& fa, int32_t* perm, int64_t items_bound,
-                       int blocks, int defer, hipStream_t st) {
+                       int blocks, int form, hipStream_t st) {
   if (n <= 0 || k < 2) return hipSuccess;
+  if (form < 0 || form > 2) return hipErrorInvalidValue;
   const size_t lds = leaf_lds_bytes(cutover, k);
   RecBufs B{rec0, rows, b1, b2};
   Forest F{fa.B, fa.off, fa.uoff, fa.lmax, fa.wgbase, fa.queue, fa.status};
   const void* fn = nullptr;
-#define KD_LF_R(IT)                                                  \
-  switch (k - 1) {                                                   \
-    case 1: fn = defer ? reinterpret_cast<const void*>(k_leaf<IT, 1, true>)   \
-                 : reinterpret_cast<const void*>(k_leaf<IT, 1, false>); \
-      break;                                                         \
-    case 2: fn = defer ? reinterpret_cast<const void*>(k_leaf<IT, 2, true>)   \
-                 : reinterpret_cast<const void*>(k_leaf<IT, 2, false>); \
-      break;                                                         \
-    case 3: fn = defer ? reinterpret_cast<const void*>(k_leaf<IT, 3, true>)   \
-                 : reinterpret_cast<const void*>(k_leaf<IT, 3, false>); \
-      break;                                                         \
-    case 4: fn = defer ? reinterpret_cast<const void*>(k_leaf<IT, 4, true>)   \
-                 : reinterpret_cast<const void*>(k_leaf<IT, 4, false>); \
-      break;                                                         \
-    case 5: fn = defer ? reinterpret_cast<const void*>(k_leaf<IT, 5, true>)   \
-                 : reinterpret_cast<const void*>(k_leaf<IT, 5, false>); \
-      break;                                                         \
-    case 6: fn = defer ? reinterpret_cast<const void*>(k_leaf<IT, 6, true>)   \
-                 : reinterpret_cast<const void*>(k_leaf<IT, 6, false>); \
-      break;                                                         \
-    case 7: fn = defer ? reinterpret_cast<const void*>(k_leaf<IT, 7, true>)   \
-                 : reinterpret_cast<const void*>(k_leaf<IT, 7, false>); \
-      break;                                                         \
-    default: return hipErrorInvalidValue;                            \
+#define KD_LF_F(IT, RR)                                                          \
+  fn = form == 2   ? reinterpret_cast<const void*>(k_leaf<IT, RR, 2>)           \
+       : form == 1 ? reinterpret_cast<const void*>(k_leaf<IT, RR, 1>)           \
+                   : reinterpret_cast<const void*>(k_leaf<IT, RR, 0>)
+#define KD_LF_R(IT)                                  \
+  switch (k - 1) {                                   \
+    case 1: KD_LF_F(IT, 1); break;                   \
+    case 2: KD_LF_F(IT, 2); break;                   \
+    case 3: KD_LF_F(IT, 3); break;                   \
+    case 4: KD_LF_F(IT, 4); break;                   \
+    case 5: KD_LF_F(IT, 5); break;                   \
+    case 6: KD_LF_F(IT, 6); break;                   \
+    case 7: KD_LF_F(IT, 7); break;                   \
+    default: return hipErrorInvalidValue;            \
   }
   switch (cutover) {
     case 1024: KD_LF_R(4); break;
@@ -1268,6 +1273,7 @@ hipError_t launch_leaf(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1,
     default: return hipErrorInvalidValue;
   }
 #undef KD_LF_R
+#undef KD_LF_F
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   // persistent grid: enough workgroups to fill the chip, never more than items

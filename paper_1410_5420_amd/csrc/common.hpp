@@ -156,6 +156,29 @@ __device__ __host__ __forceinline__ int cutover_depth(int64_t nu, int64_t cutove
   return d;
 }
 
+// ---- rolling schedule of the index arrays ----------------------------------
+// One tree, level form 4 (Appendix, "Deferred Merge Sort and Partitioning",
+// carried through every level): an array is partitioned only right before
+// the level that splits it.  At level L the array p = L mod k is brought from
+// the layout it had after it last split (depth roll_depth(L, p)) to depth L in
+// one stable multi-way split, by the medians of the levels in between; no
+// other array moves.  After the last global level D the arrays the on-chip
+// finish reads get one last split to depth D.
+
+// Depth of array j's layout before level L's split (L <= D): one below the
+// last level < L that split with it, 0 before the first.
+__host__ __device__ __forceinline__ int roll_depth(int L, int j, int k) {
+  return L > j ? j + k * ((L - 1 - j) / k) + 1 : 0;
+}
+// Splits of array j at the levels 1 .. L-1 (level 0 splits presorted array 0
+// in place).
+__host__ __device__ __forceinline__ int roll_moves(int L, int j, int k) {
+  if (j == 0) return L >= 1 ? (L - 1) / k : 0;
+  return L > j ? (L - 1 - j) / k + 1 : 0;
+}
+// Record plane of array j that holds the rank in order o (o != j).
+__host__ __device__ __forceinline__ int plane_of(int j, int o, int k) { return (o - j - 1 + 2 * k) % k; }
+
 // ---- learned CDF model ------------------------------------------------------
 // A monotone piecewise-linear estimate F of the cumulative distribution of one
 // coordinate, used by the learned presort to send a key straight to its

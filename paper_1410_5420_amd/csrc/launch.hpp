@@ -180,6 +180,43 @@ hipError_t launch_defer_bucket(const uint32_t* rec0, const uint32_t* rows, uint3
                                uint32_t* b2, int64_t n, int k, int j, const ForestArgs& fa,
                                const uint32_t* node_rank, uint32_t* key, hipStream_t st);
 size_t level_seginfo_bytes();
+
+// ---- level form 4: one multi-level split per level (split.hip) -----------------
+// A split launch brings one array to a deeper layout (see roll_depth in
+// common.hpp): the regular split of level `level` (final_j < 0), or the last
+// split of array final_j to the deepest global level before the on-chip
+// finish.  What it does is decided on the device from *lmax.
+struct SplitJob {
+  int64_t n;
+  int k;
+  int level;
+  int final_j;
+  const int32_t* uoff;   // uoff[1] = n_unique (one tree)
+  const int32_t* lmax;   // deepest global level
+  uint32_t* status;
+  const uint32_t* med;   // median table: med[(1 << l) - 1 + c] (depth l, subarray c)
+  uint32_t wmask;        // record planes the split writes
+};
+struct SplitInfo {
+  int32_t s[8];
+  int32_t e[8];
+  int32_t c[8];
+  int32_t np;
+};
+size_t split_info_bytes();
+// Count, chain and move launches of one split.  info: level_tiles(n)
+// SplitInfo; tval, carry: level_tiles(n) << (k - 1) words; tflag:
+// level_tiles(n) words.
+hipError_t launch_split(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1, uint32_t* b2,
+                        const SplitJob& J, SplitInfo* info, uint32_t* tval, uint32_t* tflag,
+                        uint32_t* carry, hipStream_t st);
+// The nodes of depth J.level: their ranks into med, their rows into perm.
+hipError_t launch_split_medians(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1,
+                                uint32_t* b2, const SplitJob& J, uint32_t* med, int32_t* perm,
+                                hipStream_t st);
+// Planes written by the split of every level (level_mask[L]) and by the final
+// split of every array (final_mask[j]) of a tree with `levels` global levels.
+void rolling_masks(int k, int levels, uint32_t* level_mask, uint32_t* final_mask);
 inline int64_t level_tiles(int64_t n) { return (n + kLevelTile - 1) / kLevelTile; }
 
 // LDS bytes the on-chip finish needs for a cutover C in k dimensions.
@@ -190,10 +227,12 @@ inline size_t leaf_lds_bytes(int64_t cutover, int k) {
 // On-chip finish of every subarray at the cutover depth (row ids come from
 // array 0's records): a persistent grid of `blocks` workgroups (at most one
 // per item).
+// form: 0 = levels of form 1/2, 1 = deferred partitioning (form 3), 2 = one
+// split per level (form 4); it decides which buffer holds each array.
 hipError_t launch_leaf(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1, uint32_t* b2,
                        int64_t n, int k,
                        int64_t cutover, const ForestArgs& fa, int32_t* perm, int64_t items_bound,
-                       int blocks, int defer, hipStream_t st);
+                       int blocks, int form, hipStream_t st);
 
 // Per-level sorting builder: the k canonical words of rows[pos] for pos <
 // *nu (plane j at words + j * n), and every position's range start at

@@ -82,7 +82,7 @@ def test_build_rejects_bad_arguments(L):
     o.records = 3  # 0, 1 or 2
     assert call_build(L, opts=ctypes.byref(o)) == -1
     o.records = 0
-    o.level = 4  # 0 .. 3
+    o.level = 5  # 0 .. 4
     assert call_build(L, opts=ctypes.byref(o)) == -1
     o.level = 0
     o.reserved[2] = 1  # reserved words must be zero

@@ -291,10 +291,10 @@ def test_batched_mixed_sizes(kd, k):
     assert_batched_same(kd, t, offsets)
 
 
-@pytest.mark.parametrize("level", [1, 2, 3])
+@pytest.mark.parametrize("level", [1, 2, 3, 4])
 def test_batched_level_forms(kd, level):
     """Forests whose trees reach different depths: global levels in both
-    launch forms."""
+    launch forms (a batch asked for form 3 or 4 runs form 1)."""
     g = kdgen.rng(90 + level)
     sizes = [70000, 3, 1024, 1025, 250000, 0, 9000, 4097, 130000, 17]
     offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
