@@ -73,7 +73,8 @@ typedef struct kd_options {
   int32_t learned_sorts; /* learned builds only: bit d set = the sort for
                           super key d goes through the learned buckets, the
                           others through the radix passes; 0 = all */
-  int32_t level;       /* global partition levels: 0 = default (1), 1 = count,
+  int32_t level;       /* global partition levels: 0 = default (4 for a
+                          single build of k >= 3, else 1), 1 = count,
                           chain and move launches, 2 = one move launch per
                           level whose tiles chain their counts by look-back,
                           3 = form 1 with deferred partitioning (Appendix,

@@ -3,7 +3,8 @@
 The knobs -- the cutover C below which a subarray is finished on-chip, the
 number of workgroups of the persistent on-chip finish, how the level-0 rank
 records are completed, (learned form) which sorts use the learned
-buckets, and (plain form, k >= 5) whether the partition is deferred --
+buckets, and (plain form) the level form: k-1 arrays moved per level, one
+multi-level split per level, or (k >= 5) deferred partitioning --
 change speed only.  tune() times every candidate configuration on the caller's input, and
 checks that each one returns exactly the output of the default
 configuration (a difference would be a bug, and raises); the fastest is
@@ -23,17 +24,20 @@ CANDIDATES = [{"cutover": c, "leaf_blocks": b, "records": r} for c in (1024, 204
 # all of them, or only the first (the multi-word sort, where the buckets save
 # the most passes)
 LEARNED_SORTS = (0, 1)
-# deferred partitioning (level form 3) saves (k-1)(k-2)/2 array moves for the
-# price of one radix split per array j >= 2; measured, it loses at k <= 4 and
-# gains at k = 6 and 8, so only k >= 5 try it
+# level forms of a single tree: 1 (every level moves k-1 arrays) and 4 (one
+# multi-level split per level); deferred partitioning (form 3) saves
+# (k-1)(k-2)/2 array moves for the price of one radix split per array j >= 2,
+# measured to lose at k <= 4, so only k >= 5 try it
+LEVEL_FORMS = (1, 4)
 DEFERRED_MIN_K = 5
 
 
 def candidates_for(form: str, k: int | None = None) -> list:
     if form == "learned":
         return [dict(c, learned_sorts=m) for c in CANDIDATES for m in LEARNED_SORTS]
-    if form == "plain" and k is not None and k >= DEFERRED_MIN_K:
-        return list(CANDIDATES) + [dict(c, level=3) for c in CANDIDATES]
+    if form == "plain":
+        levels = LEVEL_FORMS + ((3,) if k is not None and k >= DEFERRED_MIN_K else ())
+        return [dict(c, level=lv) for lv in levels for c in CANDIDATES]
     return list(CANDIDATES)
 
 

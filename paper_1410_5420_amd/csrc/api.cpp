@@ -40,7 +40,7 @@ struct Layout {
   size_t status, vbuf, carry, S, rec0, rec1, rec2;
   size_t rcnt, rgrp, dcnt, seginfo, lcnt, lcarry, lstat, ltick;
   size_t uoff, wgbase, lmax, queue, offs, ties, nodes;
-  size_t med, sinfo, stval, stflag, scarry;  // level form 4
+  size_t med, sinfo, stval, stflag, scarry, skeys;  // level form 4
   size_t starts, flags, lkey, carry2;  // learned presort only
   size_t end;
 };
@@ -95,6 +95,7 @@ Layout plan(int64_t n, int k, int B, bool learned = false) {
   L.stval = take(4 * (lt << (k > 1 ? k - 1 : 0)));
   L.stflag = take(4 * lt);
   L.scarry = take(4 * (lt << (k > 1 ? k - 1 : 0)));
+  L.skeys = take(2 * lt * kLevelTile);  // 2 bytes per position of every tile
   if (learned) {
     L.starts = take(4 * (((size_t)1 << kMaxBucketBits) + 1));
     L.flags = take(4 * kMaxK);
@@ -592,8 +593,11 @@ int partition_impl(const Job& J, hipStream_t st) {
         levels = lc > levels ? lc : levels;
         items += nb > 0 ? ((int64_t)1 << lc) : 0;
       }
+      // the default level form: one split per level (form 4) for a single
+      // tree of k >= 3 (measured faster from k = 3 on), else form 1
+      const int level = J.level != 0 ? J.level : (J.B == 1 && k >= 3 ? 4 : 1);
       // look-back levels: status words and tile counters start from zero
-      const bool lookback = J.level == 2;
+      const bool lookback = level == 2;
       uint64_t* lstat = lookback ? at<uint64_t>(ws, L.lstat) : nullptr;
       int32_t* ltick = at<int32_t>(ws, L.ltick);
       if (lookback && levels > 0) {
@@ -603,8 +607,8 @@ int partition_impl(const Job& J, hipStream_t st) {
       }
       // one tree: every level moves only the planes later levels and the
       // on-chip finish read (a batch's trees end at different depths)
-      const int defer = J.level == 3 && J.B == 1 && k >= 3 ? 1 : 0;
-      if (J.level == 4 && J.B == 1) {
+      const int defer = level == 3 && J.B == 1 && k >= 3 ? 1 : 0;
+      if (level == 4 && J.B == 1) {
         // level form 4: at level L only array L mod k moves (one multi-level
         // split), then the nodes of depth L are recorded; the arrays the
         // on-chip finish reads get their last split after the last level
@@ -622,19 +626,20 @@ int partition_impl(const Job& J, hipStream_t st) {
         uint32_t* tval = at<uint32_t>(ws, L.stval);
         uint32_t* tflag = at<uint32_t>(ws, L.stflag);
         uint32_t* scarry = at<uint32_t>(ws, L.scarry);
+        void* skeys = at<void>(ws, L.skeys);
         for (int d = 0; d < levels; ++d) {
           sj.level = d;
           sj.final_j = -1;
           sj.wmask = lm[d];
           if (d >= 1)
-            KD_LAUNCH(KD_K_LEVEL, launch_split(r0, S, r1, r2, sj, info, tval, tflag, scarry, st));
+            KD_LAUNCH(KD_K_LEVEL, launch_split(r0, S, r1, r2, sj, info, tval, tflag, scarry, skeys, st));
           KD_LAUNCH(KD_K_LEVEL, launch_split_medians(r0, S, r1, r2, sj, med, J.perm, st));
         }
         for (int j = 1; j < k && levels > 0; ++j) {
           sj.level = -1;
           sj.final_j = j;
           sj.wmask = fm[j];
-          KD_LAUNCH(KD_K_LEVEL, launch_split(r0, S, r1, r2, sj, info, tval, tflag, scarry, st));
+          KD_LAUNCH(KD_K_LEVEL, launch_split(r0, S, r1, r2, sj, info, tval, tflag, scarry, skeys, st));
         }
         KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(fa.queue), 0u, 1, st));
         KD_LAUNCH(KD_K_LEAF, launch_leaf(r0, S, r1, r2, n, k, cutover, fa, J.perm, items,

@@ -206,10 +206,10 @@ struct SplitInfo {
 size_t split_info_bytes();
 // Count, chain and move launches of one split.  info: level_tiles(n)
 // SplitInfo; tval, carry: level_tiles(n) << (k - 1) words; tflag:
-// level_tiles(n) words.
+// level_tiles(n) words; keys: 2 * kLevelTile * level_tiles(n) bytes.
 hipError_t launch_split(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1, uint32_t* b2,
                         const SplitJob& J, SplitInfo* info, uint32_t* tval, uint32_t* tflag,
-                        uint32_t* carry, hipStream_t st);
+                        uint32_t* carry, void* keys, hipStream_t st);
 // The nodes of depth J.level: their ranks into med, their rows into perm.
 hipError_t launch_split_medians(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1,
                                 uint32_t* b2, const SplitJob& J, uint32_t* med, int32_t* perm,

@@ -13,9 +13,11 @@
 // the array's order.  The tree is the same: a stable split of a sorted
 // subarray by subtree yields every subtree in sorted order.
 //
-// A split is three launches (count, chain, move) as a level of the other
-// forms; a fourth small launch per level records the medians' ranks (the
-// walks of later splits read them) and writes the nodes into perm.
+// A split is three launches as a level of the other forms: the count walks
+// every element once (its key goes to a byte array the move reads instead of
+// walking again), the chain scans the counts along every piece, the move
+// ranks and writes.  A fourth small launch per level records the medians'
+// ranks (the walks of later splits read them) and writes the nodes to perm.
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -27,7 +29,6 @@ constexpr int kSpThreads = 512;
 constexpr int kSpItems = kLevelTile / kSpThreads;  // 8 positions per thread
 constexpr int kSpWaves = kSpThreads / kWave;
 constexpr int kSpMaxPieces = 8;   // subarrays of the source depth meeting a tile
-constexpr int kSpSamples = kLevelTile / 512 + 1;
 constexpr int kSpKeys = 256;      // (piece, bucket) pairs of a tile
 constexpr int kSpMaxBuckets = 1 << (kMaxK - 1);
 constexpr uint32_t kDrop = 0xFFFFFFFFu;
@@ -103,83 +104,73 @@ __device__ __forceinline__ void subarray_index(int pos, int nu, int depth, int* 
   *c_out = c;
 }
 
-// Wave 0: the subarrays of depth `depth` meeting positions [t0, t1).  Every
-// such subarray holds at least 1024 positions, so one of the positions t0,
-// t0 + 512, ..., t1 - 1 (or the one after it, if that one is a node) lies in
-// it.  Returns the count in every lane of wave 0 (more than kSpMaxPieces is
-// an inconsistency: only the first kSpMaxPieces are kept).
-__device__ int find_pieces(int nu, int depth, int t0, int t1, SplitInfo* out, uint32_t* status) {
-  const int lane = lane_id();
-  int s = INT32_MAX, e = -1, c = -1;
-  if (lane < kSpSamples) {
-    int pos = t0 + lane * 512;
-    if (pos > t1 - 1) pos = t1 - 1;
-    subarray_index(pos, nu, depth, &s, &e, &c);
-    if (e < s && pos + 1 < t1) subarray_index(pos + 1, nu, depth, &s, &e, &c);
-    if (e < s) {
-      s = INT32_MAX;
-      e = -1;
-    }
-  }
-  const int prev_s = __shfl_up(s, 1, kWave);
-  const bool keep = lane < kSpSamples && s != INT32_MAX && (lane == 0 || prev_s != s);
-  const uint64_t km = __ballot(keep);
-  if (keep) {
-    const int idx = (int)popc64(km & lanes_below_mask());
-    if (idx < kSpMaxPieces) {
-      out->s[idx] = s;
-      out->e[idx] = e;
-      out->c[idx] = c;
-    }
-  }
-  const int np = (int)popc64(km);
-  if (lane == 0) {
-    if (np > kSpMaxPieces) atomicOr(status, kStatusSplit);
-    out->np = min(np, kSpMaxPieces);
-  }
-  return min(np, kSpMaxPieces);
+// The subarrays of depth `depth` meeting positions [t0, t1) are the
+// consecutive ones c_lo .. c_hi: those holding the first and the last
+// position of the range that is not a node of a shallower depth (such a node
+// has subarray positions on both sides, and subarrays here hold at least 1024
+// positions).  Every thread computes the same two indices.
+__device__ __forceinline__ void tile_pieces(int nu, int depth, int t0, int t1, int* c_lo, int* c_hi) {
+  int s, e, c;
+  subarray_index(t0, nu, depth, &s, &e, &c);
+  if (c < 0) subarray_index(t0 + 1, nu, depth, &s, &e, &c);
+  *c_lo = c;
+  subarray_index(t1 - 1, nu, depth, &s, &e, &c);
+  if (c < 0) subarray_index(t1 - 2, nu, depth, &s, &e, &c);
+  *c_hi = c;
 }
 
-// Ranks (in the orders of the levels walked) of the nodes below every piece,
-// in heap order: s_med[piece * kSpMaxBuckets + h], h = 1 for the piece's own
-// node, 2h / 2h+1 for the nodes of its lower / upper half.  The table
-// med[(1 << l) - 1 + c] holds the rank in order l mod k of subarray c's node
-// at depth l.
-__device__ __forceinline__ void stage_medians(const SplitInfo& si, int from, int s_levels,
-                                              const uint32_t* __restrict__ med, uint32_t* s_med) {
-  const int B = 1 << s_levels;
-  for (int t = threadIdx.x; t < si.np * B; t += blockDim.x) {
-    const int pc = t / B, h = t % B;
-    if (h == 0) continue;
-    const int lr = 31 - __clz(h);  // level below the piece
-    const int c = (si.c[pc] << lr) + (h - (1 << lr));
-    s_med[pc * kSpMaxBuckets + h] = med[((1 << (from + lr)) - 1) + c];
+// Range of subarray c at `depth` (one tree of nu positions).
+__device__ __forceinline__ void subarray_range(int nu, int depth, int c, int* s_out, int* e_out) {
+  int s = 0, e = nu - 1;
+  for (int l = depth - 1; l >= 0; --l) {
+    const int m = s + ((e - s) >> 1);
+    if ((c >> l) & 1)
+      s = m + 1;
+    else
+      e = m - 1;
   }
+  *s_out = s;
+  *e_out = e;
 }
 
-// Bucket of an element (its subtree k-1 levels down, 0 .. 2^s - 1), or kDrop
-// when it is one of the nodes passed on the way.  v: its record planes.
+// Record plane compared at each level of the walk from depth `from`, three
+// bits per level (the same for every element of a split).
+template <int K>
+__device__ __forceinline__ uint32_t walk_planes(int q, int from, int s_levels) {
+  uint32_t packed = 0;
+  for (int l = 0; l < s_levels; ++l) packed |= (uint32_t)plane_of(q, (from + l) % K, K) << (3 * l);
+  return packed;
+}
+
+// Bucket of an element (its subtree sl levels down, 0 .. 2^sl - 1), or kDrop
+// when it is one of the nodes passed on the way.  v: its record planes;
+// planes: walk_planes().  Branch-free, so the walks of a thread's elements
+// interleave: after a node is met the remaining steps run on harmlessly.
 template <int W>
-__device__ __forceinline__ uint32_t walk(const uint32_t (&v)[W], const uint32_t* s_med_piece, int q,
-                                         int from, int s_levels, int k) {
+__device__ __forceinline__ uint32_t walk(const uint32_t (&v)[W], const uint32_t* s_med_piece,
+                                         uint32_t planes, int sl) {
   uint32_t h = 1;
-  for (int l = 0; l < s_levels; ++l) {
-    const int pl = plane_of(q, (from + l) % k, k);
-    uint32_t r = 0;
+  bool node = false;
 #pragma unroll
-    for (int c = 0; c < W; ++c)
-      if (c == pl) r = v[c];
-    const uint32_t nr = s_med_piece[h];
-    if (r == nr) return kDrop;
-    h = 2 * h + (r > nr ? 1u : 0u);
+  for (int l = 0; l < W; ++l) {
+    if (l < sl) {
+      const int pl = (int)((planes >> (3 * l)) & 7u);
+      uint32_t r = 0;
+#pragma unroll
+      for (int c = 0; c < W; ++c)
+        if (c == pl) r = v[c];
+      const uint32_t nr = s_med_piece[h];
+      node = node || r == nr;
+      h = 2 * h + (r > nr ? 1u : 0u);
+    }
   }
-  return h - (1u << s_levels);
+  return node ? kDrop : h - (1u << sl);
 }
 
 // Range of the subtree reached from [s, e] by the bucket's bits (most
-// significant first, s_levels of them).
-__device__ __forceinline__ void descend(int& s, int& e, uint32_t b, int s_levels) {
-  for (int l = s_levels - 1; l >= 0; --l) {
+// significant first, sl of them).
+__device__ __forceinline__ void descend(int& s, int& e, uint32_t b, int sl) {
+  for (int l = sl - 1; l >= 0; --l) {
     const int m = s + ((e - s) >> 1);
     if ((b >> l) & 1u)
       s = m + 1;
@@ -188,7 +179,67 @@ __device__ __forceinline__ void descend(int& s, int& e, uint32_t b, int s_levels
   }
 }
 
-// Counts of every bucket among the tile's last piece (tval[b][t]) and the
+// The same walk for a tile inside one piece, at most three levels deep: the
+// seven node ranks below the piece are the same for every element (m[h],
+// heap order), so they sit in registers and each step picks one of them.
+template <int W>
+__device__ __forceinline__ uint32_t walk3(const uint32_t (&v)[W], const uint32_t (&m)[8],
+                                          uint32_t planes, int sl) {
+  uint32_t h = 1;
+  bool node = false;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    if (l < sl) {
+      const int pl = (int)((planes >> (3 * l)) & 7u);
+      uint32_t r = 0;
+#pragma unroll
+      for (int c = 0; c < W; ++c)
+        if (c == pl) r = v[c];
+      uint32_t nr;
+      if (l == 0)
+        nr = m[1];
+      else if (l == 1)
+        nr = h == 2 ? m[2] : m[3];
+      else
+        nr = h == 4 ? m[4] : (h == 5 ? m[5] : (h == 6 ? m[6] : m[7]));
+      node = node || r == nr;
+      h = 2 * h + (r > nr ? 1u : 0u);
+    }
+  }
+  return node ? kDrop : h - (1u << sl);
+}
+
+// Key of an element for the move: piece << sl | bucket, below 256 (pieces
+// are few where buckets are many); 8 bits, or 16 at k = 8 where all 256
+// values occur.  The largest value marks an element that does not move.
+// A thread's keys are packed into 32-bit words, stored where only the same
+// thread of the move reads them: word j of thread (tile t, wave w, lane) at
+// ((t * kSpWaves + w) * KeyWords + j) * 64 + lane, so every store and load is
+// a whole 256-byte run.
+template <int W>
+struct SplitKeys {
+  static constexpr int kBits = W >= 7 ? 16 : 8;
+  static constexpr uint32_t kNone = (1u << kBits) - 1u;
+  static constexpr int kPerWord = 32 / kBits;
+  static constexpr int kWords = kSpItems / kPerWord;
+};
+
+// Piece of position i among the tile's pieces (bounds in registers), or -1.
+__device__ __forceinline__ int piece_of(int i, const int (&ps)[kSpMaxPieces],
+                                        const int (&pe)[kSpMaxPieces], int np) {
+  int pc = -1;
+#pragma unroll
+  for (int q = 0; q < kSpMaxPieces; ++q)
+    if (q < np && i >= ps[q]) pc = q;
+  int e = -1;
+#pragma unroll
+  for (int q = 0; q < kSpMaxPieces; ++q)
+    if (q == pc) e = pe[q];
+  return (pc >= 0 && i <= e) ? pc : -1;
+}
+
+// Walks every element of the tile once: its key for the move (keys[i]), the
+// counts of every bucket among the tile's last piece (tval[b][t]) and the
 // tile's flags (bit 0: that piece starts inside the tile; bit 1: the first
 // piece started before it), with the pieces kept for the move (info[t]).
 template <int W>
@@ -196,7 +247,9 @@ __global__ __launch_bounds__(kSpThreads) void k_split_count(const Bufs Bf, const
                                                            SplitInfo* __restrict__ info,
                                                            uint32_t* __restrict__ tval,
                                                            uint32_t* __restrict__ tflag,
-                                                           int tiles_stride) {
+                                                           int tiles_stride,
+                                                           uint32_t* __restrict__ keys) {
+  using K = SplitKeys<W>;
   __shared__ SplitInfo s_si;
   __shared__ uint32_t s_med[kSpMaxPieces * kSpMaxBuckets];
   __shared__ uint32_t s_hist[kSpMaxBuckets];
@@ -210,8 +263,9 @@ __global__ __launch_bounds__(kSpThreads) void k_split_count(const Bufs Bf, const
   const int t1 = min(t0 + kLevelTile, nu);
   const int sl = P.to - P.from;
   const int B = 1 << sl;
-  const int k = J.k;
+  constexpr int k = W + 1;
   const uint32_t dmask = deciding_planes(P.q, P.from, P.to, k);
+  const uint32_t planes = walk_planes<k>(P.q, P.from, sl);
   const uint32_t* src = buf_of(Bf, P.moves) + record_offset(P.q, k, J.n);
   // planes first: their loads overlap the piece search
   uint32_t v[W][kSpItems];
@@ -224,46 +278,86 @@ __global__ __launch_bounds__(kSpThreads) void k_split_count(const Bufs Bf, const
       v[c][it] = need && i < t1 ? src[(int64_t)c * J.n + i] : 0u;
     }
   }
-  if (tid < kWave) find_pieces(nu, P.from, t0, t1, &s_si, J.status);
+  // the pieces and the medians below them, without waiting for the planes
+  int c_lo, c_hi;
+  tile_pieces(nu, P.from, t0, t1, &c_lo, &c_hi);
+  int np = c_hi - c_lo + 1;
+  if (np > kSpMaxPieces || np < 1) {  // not reached: pieces hold at least 1024 positions
+    if (tid == 0) atomicOr(J.status, kStatusSplit);
+    np = max(1, min(np, kSpMaxPieces));
+  }
+  if (tid < kSpMaxPieces) {
+    int ss = 1, ee = 0;
+    if (tid < np) subarray_range(nu, P.from, c_lo + tid, &ss, &ee);
+    s_si.s[tid] = ss;
+    s_si.e[tid] = ee;
+    info[t].s[tid] = ss;
+    info[t].e[tid] = ee;
+    info[t].c[tid] = c_lo + tid;
+    if (tid == 0) info[t].np = np;
+  }
+  for (int q = tid; q < np * B; q += kSpThreads) {
+    const int pc = q >> sl, h = q & (B - 1);
+    if (h == 0) continue;
+    const int lr = 31 - __clz(h);  // level below the piece
+    const int c = ((c_lo + pc) << lr) + (h - (1 << lr));
+    s_med[pc * kSpMaxBuckets + h] = J.med[((1 << (P.from + lr)) - 1) + c];
+  }
   if (tid < kSpMaxBuckets) s_hist[tid] = 0;
   __syncthreads();
-  stage_medians(s_si, P.from, sl, J.med, s_med);
-  if (tid < kSpMaxPieces) {
-    info[t].s[tid] = s_si.s[tid];
-    info[t].e[tid] = s_si.e[tid];
-    info[t].c[tid] = s_si.c[tid];
-    if (tid == 0) info[t].np = s_si.np;
+  int ps[kSpMaxPieces], pe[kSpMaxPieces];
+#pragma unroll
+  for (int q = 0; q < kSpMaxPieces; ++q) {
+    ps[q] = s_si.s[q];
+    pe[q] = s_si.e[q];
   }
-  __syncthreads();
-  const int np = s_si.np;
-  const int ls = np > 0 ? max(s_si.s[np - 1], t0) : t1;
-  const int le = np > 0 ? min(s_si.e[np - 1] + 1, t1) : t1;
   const uint64_t below = lanes_below_mask();
+  // one piece in the tile (the usual case): no piece search, and for up to
+  // three levels the node ranks in registers
+  const bool single = np == 1 && sl <= 3;
+  uint32_t kw[K::kWords];
+#pragma unroll
+  for (int j = 0; j < K::kWords; ++j) kw[j] = 0u;
+  uint32_t m1[8];
+#pragma unroll
+  for (int h = 0; h < 8; ++h) m1[h] = single && h >= 1 && h < B ? s_med[h] : 0u;
 #pragma unroll
   for (int it = 0; it < kSpItems; ++it) {
     const int i = t0 + w * (kWave * kSpItems) + it * kWave + lane;
+    int pc;
     uint32_t b = kDrop;
-    if (i >= ls && i < le) {
-      uint32_t x[W];
+    uint32_t x[W];
 #pragma unroll
-      for (int c = 0; c < W; ++c) x[c] = v[c][it];
-      b = walk<W>(x, s_med + (np - 1) * kSpMaxBuckets, P.q, P.from, sl, k);
+    for (int c = 0; c < W; ++c) x[c] = v[c][it];
+    if (single) {  // a node of a shallower depth may still open or close the tile
+      pc = (i < t1 && i >= ps[0] && i <= pe[0]) ? 0 : -1;
+      if (pc == 0) b = walk3<W>(x, m1, planes, sl);
+    } else {
+      pc = i < t1 ? piece_of(i, ps, pe, np) : -1;
+      if (pc >= 0) b = walk<W>(x, s_med + pc * kSpMaxBuckets, planes, sl);
     }
-    // lanes with the same bucket: one LDS add per distinct bucket
-    const bool valid = b != kDrop;
-    uint64_t m = __ballot(valid);
+    const uint32_t kk = b == kDrop ? K::kNone : (((uint32_t)pc << sl) | b);
+    kw[it / K::kPerWord] |= kk << (K::kBits * (it % K::kPerWord));
+    // the last piece's buckets: one LDS add per distinct bucket of a wave
+    const bool last = b != kDrop && pc == np - 1;
+    uint64_t m = __ballot(last);
     for (int bit = 0; bit < sl; ++bit) {
       const bool on = (b >> bit) & 1u;
       const uint64_t bb = __ballot(on);
       m &= on ? bb : ~bb;
     }
-    if (valid && popc64(m & below) == 0) atomicAdd(&s_hist[b], popc64(m));
+    if (last && popc64(m & below) == 0) atomicAdd(&s_hist[b], popc64(m));
+  }
+  {
+    uint32_t* kp = keys + ((int64_t)t * kSpWaves + w) * K::kWords * kWave + lane;
+#pragma unroll
+    for (int j = 0; j < K::kWords; ++j) kp[j * kWave] = kw[j];
   }
   __syncthreads();
   if (tid < B) tval[(int64_t)tid * tiles_stride + t] = s_hist[tid];
   if (tid == 0) {
-    const bool head = np == 0 || s_si.s[np - 1] >= t0;
-    const bool cont = np > 0 && s_si.s[0] < t0;
+    const bool head = ps[np - 1] >= t0;
+    const bool cont = ps[0] < t0;
     tflag[t] = (head ? 1u : 0u) | (cont ? 2u : 0u);
   }
 }
@@ -343,18 +437,20 @@ __global__ __launch_bounds__(1024) void k_split_scan(const SplitJob J,
   }
 }
 
-// Moves one tile: every element's (piece, bucket) key, its stable rank among
-// the tile's elements of that key (wave ballots, as in a radix pass), and the
-// start of its subtree plus the carried count give its new position; the
-// planes in wmask are written there.
+// Moves one tile: every element's key (from the count), its stable rank
+// among the tile's elements of that key (wave ballots, as in a radix pass),
+// and the start of its subtree plus the carried count give its new position;
+// the planes in wmask are written there.
 template <int W>
 __global__ __launch_bounds__(kSpThreads) void k_split_move(const Bufs Bf, const SplitJob J,
                                                           const SplitInfo* __restrict__ info,
                                                           const uint32_t* __restrict__ tflag,
                                                           const uint32_t* __restrict__ carry,
-                                                          int tiles_stride) {
+                                                          int tiles_stride,
+                                                          const uint32_t* __restrict__ keys) {
+  using K = SplitKeys<W>;
+  constexpr uint32_t kNoKey = K::kNone;
   __shared__ SplitInfo s_si;
-  __shared__ uint32_t s_med[kSpMaxPieces * kSpMaxBuckets];
   __shared__ uint32_t s_wcnt[kSpWaves][kSpKeys];
   __shared__ int32_t s_base[kSpKeys];
   __shared__ int32_t s_end[kSpKeys];
@@ -369,27 +465,39 @@ __global__ __launch_bounds__(kSpThreads) void k_split_move(const Bufs Bf, const 
   const int t1 = min(t0 + kLevelTile, nu);
   const int sl = P.to - P.from;
   const int B = 1 << sl;
-  const int k = J.k;
-  const uint32_t dmask = deciding_planes(P.q, P.from, P.to, k);
+  constexpr int k = W + 1;
   const uint32_t wmask = J.wmask;
   const uint32_t* src = buf_of(Bf, P.moves) + record_offset(P.q, k, J.n);
   uint32_t* dst = const_cast<uint32_t*>(buf_of(Bf, P.moves + 1)) + record_offset(P.q, k, J.n);
+  uint32_t key[kSpItems];
+  {
+    const uint32_t* kp = keys + ((int64_t)t * kSpWaves + w) * K::kWords * kWave + lane;
+    uint32_t kw[K::kWords];
+#pragma unroll
+    for (int j = 0; j < K::kWords; ++j) kw[j] = kp[j * kWave];
+#pragma unroll
+    for (int it = 0; it < kSpItems; ++it)
+      key[it] = (kw[it / K::kPerWord] >> (K::kBits * (it % K::kPerWord))) & K::kNone;
+  }
   uint32_t v[W][kSpItems];
 #pragma unroll
   for (int c = 0; c < W; ++c) {
-    const bool need = ((dmask | wmask) >> c) & 1u;
+    const bool need = (wmask >> c) & 1u;
 #pragma unroll
     for (int it = 0; it < kSpItems; ++it) {
       const int i = t0 + w * (kWave * kSpItems) + it * kWave + lane;
       v[c][it] = need && i < t1 ? src[(int64_t)c * J.n + i] : 0u;
     }
   }
+  // the carry of the first piece's buckets, loaded with the planes
+  const uint32_t f = tflag[t];
+  const uint32_t cy0 = tid < B ? carry[(int64_t)tid * tiles_stride + t] : 0u;
   if (tid < kSpMaxPieces) {
     s_si.s[tid] = info[t].s[tid];
     s_si.e[tid] = info[t].e[tid];
-    s_si.c[tid] = info[t].c[tid];
     if (tid == 0) s_si.np = info[t].np;
   }
+  if (tid < B) s_end[tid] = (f & 2u) ? (int32_t)cy0 : 0;  // staged in s_end for a moment
   for (int q = tid; q < kSpWaves * kSpKeys; q += kSpThreads) (&s_wcnt[0][0])[q] = 0;
   __syncthreads();
   const int np = s_si.np;
@@ -397,46 +505,29 @@ __global__ __launch_bounds__(kSpThreads) void k_split_move(const Bufs Bf, const 
     if (tid == 0) atomicOr(J.status, kStatusSplit);
     return;
   }
-  stage_medians(s_si, P.from, sl, J.med, s_med);
-  const uint32_t f = tflag[t];
+  int base_q = 0, end_q = 0;
   if (tid < np * B) {
-    const int pc = tid / B;
-    const uint32_t b = (uint32_t)(tid % B);
+    const int pc = tid >> sl;
+    const uint32_t b = (uint32_t)(tid & (B - 1));
     int s = s_si.s[pc], e = s_si.e[pc];
     descend(s, e, b, sl);
-    const int cy = (pc == 0 && (f & 2u)) ? (int)carry[(int64_t)b * tiles_stride + t] : 0;
-    s_base[tid] = s + cy;
-    s_end[tid] = e;
+    base_q = s + (pc == 0 ? s_end[b] : 0);
+    end_q = e;
   }
   __syncthreads();
-  // key of every element: piece * B + bucket, or kDrop (a node passed on the
-  // way, or a position that is a node of a shallower depth)
-  uint32_t key[kSpItems], rank[kSpItems];
+  if (tid < np * B) {
+    s_base[tid] = base_q;
+    s_end[tid] = end_q;
+  }
+  const int kbits = np * B > 1 ? 32 - __clz((uint32_t)(np * B) - 1u) : 1;  // bits of the largest key
+  uint32_t rank[kSpItems];
   const uint64_t below = lanes_below_mask();
 #pragma unroll
   for (int it = 0; it < kSpItems; ++it) {
-    const int i = t0 + w * (kWave * kSpItems) + it * kWave + lane;
-    uint32_t kk = kDrop;
-    if (i < t1) {
-      int pc = -1;
-      for (int q = 0; q < np; ++q)
-        if (i >= s_si.s[q] && i <= s_si.e[q]) {
-          pc = q;
-          break;
-        }
-      if (pc >= 0) {
-        uint32_t x[W];
-#pragma unroll
-        for (int c = 0; c < W; ++c) x[c] = v[c][it];
-        const uint32_t b = walk<W>(x, s_med + pc * kSpMaxBuckets, P.q, P.from, sl, k);
-        if (b != kDrop) kk = (uint32_t)pc * (uint32_t)B + b;
-      }
-    }
-    key[it] = kk;
-    const bool valid = kk != kDrop;
+    const uint32_t kk = key[it];
+    const bool valid = kk != kNoKey;
     uint64_t m = __ballot(valid);
-#pragma unroll
-    for (int bit = 0; bit < 8; ++bit) {
+    for (int bit = 0; bit < kbits; ++bit) {
       const bool on = (kk >> bit) & 1u;
       const uint64_t bb = __ballot(on);
       m &= on ? bb : ~bb;
@@ -445,7 +536,7 @@ __global__ __launch_bounds__(kSpThreads) void k_split_move(const Bufs Bf, const 
     if (valid) pre = s_wcnt[w][kk & 0xFF];
     __builtin_amdgcn_wave_barrier();
     const uint32_t before = popc64(m & below);
-    if (valid && before == 0) s_wcnt[w][kk] = pre + popc64(m);
+    if (valid && before == 0) s_wcnt[w][kk & 0xFF] = pre + popc64(m);
     __builtin_amdgcn_wave_barrier();
     rank[it] = pre + before;
   }
@@ -466,7 +557,11 @@ __global__ __launch_bounds__(kSpThreads) void k_split_move(const Bufs Bf, const 
   for (int it = 0; it < kSpItems; ++it) {
     dest[it] = -1;
     const uint32_t kk = key[it];
-    if (kk == kDrop) continue;
+    if (kk == kNoKey) continue;
+    if (kk >= (uint32_t)(np * B)) {  // not reached: a key of this tile
+      atomicOr(J.status, kStatusSplit);
+      continue;
+    }
     const int d = s_base[kk] + (int)(s_wcnt[w][kk] + rank[it]);
     if (d <= s_end[kk])
       dest[it] = d;
@@ -534,18 +629,18 @@ size_t split_info_bytes() { return sizeof(SplitInfo); }
 
 hipError_t launch_split(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1, uint32_t* b2,
                         const SplitJob& J, SplitInfo* info, uint32_t* tval, uint32_t* tflag,
-                        uint32_t* carry, hipStream_t st) {
+                        uint32_t* carry, void* keys, hipStream_t st) {
   if (J.n <= 0 || J.k < 2 || J.k > kMaxK) return hipSuccess;
   const int tiles = (int)level_tiles(J.n);
   const Bufs Bf{rec0, rows, b1, b2};
 #define KD_SP(WW)                                                                              \
   do {                                                                                         \
     hipLaunchKernelGGL(k_split_count<WW>, dim3(tiles), dim3(kSpThreads), 0, st, Bf, J, info,  \
-                       tval, tflag, tiles);                                                    \
+                       tval, tflag, tiles, static_cast<uint32_t*>(keys));                      \
     hipLaunchKernelGGL(k_split_scan, dim3(1 << (J.k - 1)), dim3(1024), 0, st, J, tval, tflag, \
                        carry, tiles);                                                          \
     hipLaunchKernelGGL(k_split_move<WW>, dim3(xcd_grid(tiles)), dim3(kSpThreads), 0, st, Bf, J, \
-                       info, tflag, carry, tiles);                                             \
+                       info, tflag, carry, tiles, static_cast<const uint32_t*>(keys));         \
   } while (0)
   switch (J.k - 1) {
     case 1: KD_SP(1); break;

@@ -47,10 +47,13 @@ def test_candidates_are_valid_options(at):
         assert c["records"] in (0, 1, 2)
 
 
-def test_deferred_form_only_for_large_k(at):
-    """Deferred partitioning is a candidate of the plain form from k = 5 on."""
-    assert all("level" not in c for c in at.candidates_for("plain", 3))
+def test_level_forms_of_the_plain_form(at):
+    """The plain form tries level forms 1 and 4 at every k and deferred
+    partitioning (form 3) from k = 5 on; the other forms have no level knob."""
+    small = at.candidates_for("plain", 3)
+    assert sorted({c["level"] for c in small}) == [1, 4]
+    assert len(small) == 2 * len(at.CANDIDATES)
     big = at.candidates_for("plain", 8)
-    assert sum(c.get("level") == 3 for c in big) == len(at.CANDIDATES)
+    assert sum(c["level"] == 3 for c in big) == len(at.CANDIDATES)
     assert all("level" not in c for c in at.candidates_for("batched", 8))
     assert all("level" not in c for c in at.candidates_for("learned", 8))
