@@ -103,7 +103,8 @@ def _load():
 lib = _load()
 
 # Every symbol include/kdtree.h declares (the tests check the library exports them).
-EXPORTED = ["kd_strerror", "kd_status", "kd_level_plan", "kdtree_workspace_bytes", "kdtree_build", "kdtree_presort",
+EXPORTED = ["kd_strerror", "kd_status", "kd_level_plan", "kdtree_workspace_bytes", "kdtree_build",
+            "kdtree_presort",
             "kdtree_partition", "kdtree_build_select", "kdtree_workspace_bytes_batched",
             "kdtree_build_batched",
             "kd_cdf_model_bytes", "kd_cdf_train_workspace_bytes", "kd_cdf_train",

@@ -850,6 +850,25 @@ TrainLayout train_plan(int k, int S) {
 }  // namespace
 }  // namespace kd
 
+namespace kd {
+namespace {
+// Shared checks of the tree searches; on success *is_float is set.  perm may
+// be null only where the caller says so.
+int check_query(const void* d_nodes, int64_t n, int32_t k, int32_t dtype, const int32_t* d_perm,
+                bool need_perm, const int64_t* d_n_nodes, int64_t nq, uint64_t* d_visits,
+                int* is_float) {
+  if (n < 0 || k < 1 || nq < 0 || (dtype != KD_I32 && dtype != KD_F32)) return KD_EINVAL;
+  if (n > KD_MAX_N || k > KD_MAX_K || nq > KD_MAX_QUERIES) return KD_EUNSUPPORTED;
+  if (!d_nodes || !d_n_nodes || (need_perm && !d_perm)) return KD_EINVAL;
+  if (!kd::aligned4(d_nodes) || !kd::aligned4(d_perm) ||
+      (reinterpret_cast<uintptr_t>(d_n_nodes) & 7u) || (reinterpret_cast<uintptr_t>(d_visits) & 7u))
+    return KD_EINVAL;
+  *is_float = dtype == KD_F32;
+  return KD_OK;
+}
+}  // namespace
+}  // namespace kd
+
 extern "C" {
 
 const char* kd_strerror(int code) {
@@ -1165,27 +1184,11 @@ int kdtree_build_learned(const void* d_tuples, int64_t n, int32_t k, int32_t dty
     if (e__ != hipSuccess) return KD_EHIP;            \
   } while (0)
 
-namespace {
-// Shared checks of the tree searches; on success *is_float is set.  perm may
-// be null only where the caller says so.
-int check_query(const void* d_nodes, int64_t n, int32_t k, int32_t dtype, const int32_t* d_perm,
-                bool need_perm, const int64_t* d_n_nodes, int64_t nq, uint64_t* d_visits,
-                int* is_float) {
-  if (n < 0 || k < 1 || nq < 0 || (dtype != KD_I32 && dtype != KD_F32)) return KD_EINVAL;
-  if (n > KD_MAX_N || k > KD_MAX_K || nq > KD_MAX_QUERIES) return KD_EUNSUPPORTED;
-  if (!d_nodes || !d_n_nodes || (need_perm && !d_perm)) return KD_EINVAL;
-  if (!kd::aligned4(d_nodes) || !kd::aligned4(d_perm) ||
-      (reinterpret_cast<uintptr_t>(d_n_nodes) & 7u) || (reinterpret_cast<uintptr_t>(d_visits) & 7u))
-    return KD_EINVAL;
-  *is_float = dtype == KD_F32;
-  return KD_OK;
-}
-}  // namespace
 
 int kd_gather_nodes(const void* d_tuples, int64_t n, int32_t k, int32_t dtype,
                     const int32_t* d_perm, const int64_t* d_n_nodes, void* d_nodes, void* stream) {
   int fl = 0;
-  int rc = check_query(d_tuples, n, k, dtype, d_perm, true, d_n_nodes, 0, nullptr, &fl);
+  int rc = kd::check_query(d_tuples, n, k, dtype, d_perm, true, d_n_nodes, 0, nullptr, &fl);
   if (rc != KD_OK) return rc;
   if (n == 0) return KD_OK;
   if (!d_nodes || !kd::aligned4(d_nodes)) return KD_EINVAL;
@@ -1197,7 +1200,7 @@ int kd_gather_nodes(const void* d_tuples, int64_t n, int32_t k, int32_t dtype,
 int kd_subtree_bounds(const void* d_nodes, int64_t n, int32_t k, int32_t dtype,
                       const int64_t* d_n_nodes, void* d_bounds, void* stream) {
   int fl = 0;
-  int rc = check_query(d_nodes, n, k, dtype, nullptr, false, d_n_nodes, 0, nullptr, &fl);
+  int rc = kd::check_query(d_nodes, n, k, dtype, nullptr, false, d_n_nodes, 0, nullptr, &fl);
   if (rc != KD_OK) return rc;
   if (n == 0) return KD_OK;
   if (!d_bounds || !kd::aligned4(d_bounds)) return KD_EINVAL;
@@ -1210,7 +1213,7 @@ int kd_region_count(const void* d_nodes, const void* d_bounds, int64_t n, int32_
                     const int64_t* d_n_nodes, const void* d_lower, const void* d_upper, int64_t nq,
                     int32_t* d_counts, uint64_t* d_visits, void* stream) {
   int fl = 0;
-  int rc = check_query(d_nodes, n, k, dtype, nullptr, false, d_n_nodes, nq, d_visits, &fl);
+  int rc = kd::check_query(d_nodes, n, k, dtype, nullptr, false, d_n_nodes, nq, d_visits, &fl);
   if (rc != KD_OK) return rc;
   if (!kd::aligned4(d_bounds)) return KD_EINVAL;
   if (nq == 0) return KD_OK;
@@ -1228,7 +1231,7 @@ int kd_region_rows(const void* d_nodes, const void* d_bounds, int64_t n, int32_t
                    const void* d_upper, int64_t nq, const int64_t* d_offsets, int32_t* d_rows,
                    int64_t rows_capacity, uint64_t* d_visits, void* stream) {
   int fl = 0;
-  int rc = check_query(d_nodes, n, k, dtype, d_perm, true, d_n_nodes, nq, d_visits, &fl);
+  int rc = kd::check_query(d_nodes, n, k, dtype, d_perm, true, d_n_nodes, nq, d_visits, &fl);
   if (rc != KD_OK) return rc;
   if (rows_capacity < 0 || !kd::aligned4(d_bounds)) return KD_EINVAL;
   if (nq == 0) return KD_OK;
@@ -1248,7 +1251,7 @@ int kd_nearest(const void* d_nodes, int64_t n, int32_t k, int32_t dtype, const i
                const int64_t* d_n_nodes, const void* d_points, int64_t nq, int32_t m,
                int32_t* d_rows, uint64_t* d_visits, void* stream) {
   int fl = 0;
-  int rc = check_query(d_nodes, n, k, dtype, d_perm, true, d_n_nodes, nq, d_visits, &fl);
+  int rc = kd::check_query(d_nodes, n, k, dtype, d_perm, true, d_n_nodes, nq, d_visits, &fl);
   if (rc != KD_OK) return rc;
   if (m < 1 || m > KD_MAX_NEIGHBORS) return KD_EINVAL;
   if (nq == 0) return KD_OK;
@@ -1264,7 +1267,7 @@ int kd_all_nearest(const void* d_nodes, int64_t n, int32_t k, int32_t dtype, con
                    const int64_t* d_n_nodes, int32_t m, int32_t* d_rows, uint64_t* d_visits,
                    void* stream) {
   int fl = 0;
-  int rc = check_query(d_nodes, n, k, dtype, d_perm, true, d_n_nodes, 0, d_visits, &fl);
+  int rc = kd::check_query(d_nodes, n, k, dtype, d_perm, true, d_n_nodes, 0, d_visits, &fl);
   if (rc != KD_OK) return rc;
   if (m < 1 || m > KD_MAX_NEIGHBORS) return KD_EINVAL;
   if (n > KD_MAX_QUERIES) return KD_EUNSUPPORTED;

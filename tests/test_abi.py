@@ -32,6 +32,22 @@ def test_header_declarations_are_exported(L):
     assert sorted(L.EXPORTED) == names
 
 
+def test_only_declared_functions_have_c_linkage(L):
+    """The library's unmangled exports are exactly the header's functions:
+    internal helpers are not exported with C linkage."""
+    import shutil
+    import subprocess
+
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("no nm")
+    out = subprocess.run([nm, "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = sorted({ln.split()[-1] for ln in out.splitlines()
+                       if ln.split()[1:2] == ["T"] and not ln.split()[-1].startswith(("_Z", "_"))})
+    assert exported == declared_functions()
+
+
 def test_workspace_bytes(L):
     small = L.workspace_bytes(4096, 3, L.KD_I32)
     big = L.workspace_bytes(1 << 24, 3, L.KD_I32)
