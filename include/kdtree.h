@@ -130,6 +130,23 @@ int kdtree_build(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, int3
                  int32_t* d_lo, int32_t* d_hi, int64_t* d_n_unique, void* d_workspace,
                  size_t workspace_bytes, const kd_options* opts, void* stream);
 
+/* kdtree_build for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same build, arguments and result, with no workspace argument.  The
+ * workspace is a device array inside the library of
+ * KD_NOALLOC_WORKSPACE_BYTES bytes, one per GPU, held until the process ends;
+ * inputs whose kdtree_workspace_bytes() exceeds it are refused with
+ * KD_ENOMEM before anything is enqueued.  The call allocates nothing and
+ * never calls hipMalloc or hipFree.  Every call on a GPU uses that GPU's
+ * array, so calls that may overlap on one GPU (two streams, two threads)
+ * race and must be serialised by the caller; each build rewrites what it
+ * reads, so nothing needs clearing between calls.  With k = 3 the largest
+ * accepted n is about 450,000 rows. */
+#define KD_NOALLOC_WORKSPACE_BYTES ((size_t)64 << 20)
+int kdtree_build_noalloc(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, int32_t* d_perm,
+                         int32_t* d_lo, int32_t* d_hi, int64_t* d_n_unique,
+                         const kd_options* opts, void* stream);
+
 /* The two halves of kdtree_build, for phase timing.  kdtree_presort() runs the
  * presort and duplicate removal (Sec. 2.1, first half) into the workspace and
  * writes d_n_unique; kdtree_partition() must follow on the same stream with

@@ -17,6 +17,7 @@ KD_EUNSUPPORTED = -4
 KD_EINTERNAL = -5
 KD_I32 = 0
 KD_F32 = 1
+KD_NOALLOC_WORKSPACE_BYTES = 64 << 20
 KD_CDF_PWL = 0
 KD_CDF_MLP = 1
 
@@ -50,6 +51,8 @@ def _load():
     lib.kdtree_workspace_bytes.restype = ctypes.c_int
     lib.kdtree_build.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp, vp, sz, opt, vp]
     lib.kdtree_build.restype = ctypes.c_int
+    lib.kdtree_build_noalloc.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp, opt, vp]
+    lib.kdtree_build_noalloc.restype = ctypes.c_int
     lib.kdtree_presort.argtypes = [vp, i64, i32, i32, vp, vp, sz, opt, vp]
     lib.kdtree_presort.restype = ctypes.c_int
     lib.kdtree_partition.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp, vp, sz, opt, vp]
@@ -104,7 +107,7 @@ lib = _load()
 
 # Every symbol include/kdtree.h declares (the tests check the library exports them).
 EXPORTED = ["kd_strerror", "kd_status", "kd_level_plan", "kdtree_workspace_bytes", "kdtree_build",
-            "kdtree_presort",
+            "kdtree_build_noalloc", "kdtree_presort",
             "kdtree_partition", "kdtree_build_select", "kdtree_workspace_bytes_batched",
             "kdtree_build_batched",
             "kd_cdf_model_bytes", "kd_cdf_train_workspace_bytes", "kd_cdf_train",

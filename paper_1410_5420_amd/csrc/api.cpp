@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -869,6 +870,35 @@ int check_query(const void* d_nodes, int64_t n, int32_t k, int32_t dtype, const 
 }  // namespace
 }  // namespace kd
 
+// ---- builds without allocation: the library's own workspace --------------------
+// kdtree_build_noalloc() builds with a workspace that is a file-scope device
+// array of KD_NOALLOC_WORKSPACE_BYTES bytes instead of one the caller passes.
+// Each device holds its own copy at its own address, taken once per device
+// (with that device current) and kept; host code uses that address, never the
+// array's name, which on the host is only a stand-in.
+__device__ __align__(256) unsigned char scratch[KD_NOALLOC_WORKSPACE_BYTES];
+
+namespace kd {
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch[kMaxDevices] = {};
+
+// The current device's copy of `scratch` (null on failure).
+void* scratch_on_current_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    g_scratch[dev] = p;
+  }
+  return g_scratch[dev];
+}
+}  // namespace
+}  // namespace kd
+
 extern "C" {
 
 const char* kd_strerror(int code) {
@@ -978,6 +1008,33 @@ int kdtree_build(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, int3
   rc = kd::presort_impl(J, st);
   if (rc != KD_OK) return rc;
   return kd::partition_impl(J, st);
+}
+
+int kdtree_build_noalloc(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, int32_t* d_perm,
+                         int32_t* d_lo, int32_t* d_hi, int64_t* d_n_unique,
+                         const kd_options* opts, void* stream) {
+  // the same validation as kdtree_build, with the workspace's size checked
+  // against the array before anything touches the device
+  if (n < 0 || k < 1 || (dtype != KD_I32 && dtype != KD_F32)) return KD_EINVAL;
+  if (n > KD_MAX_N || k > KD_MAX_K) return KD_EUNSUPPORTED;
+  if (kd::plan(n, k, 1).end > (size_t)KD_NOALLOC_WORKSPACE_BYTES) return KD_ENOMEM;
+  {
+    kd::Job V;
+    int64_t h2[2];
+    // any aligned non-null stand-in: single_job only checks it
+    int rc = kd::single_job(V, d_tuples, n, k, dtype, d_n_unique, reinterpret_cast<void*>(256),
+                            KD_NOALLOC_WORKSPACE_BYTES, opts, h2, nullptr, false);
+    if (rc != KD_OK) return rc;
+    V.perm = d_perm;
+    V.lo = d_lo;
+    V.hi = d_hi;
+    rc = kd::check_outputs(V);
+    if (rc != KD_OK) return rc;
+  }
+  void* ws = kd::scratch_on_current_device();
+  if (!ws) return KD_EHIP;
+  return kdtree_build(d_tuples, n, k, dtype, d_perm, d_lo, d_hi, d_n_unique, ws,
+                      KD_NOALLOC_WORKSPACE_BYTES, opts, stream);
 }
 
 int kdtree_build_select(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, int32_t* d_perm,
