@@ -164,9 +164,50 @@ def survey_bytes_per_launch(kernel: str, n: int, nu: int, k: int, cutover: int):
     raise ValueError(kernel)
 
 
-def byte_model(kernel: str, n: int, nu: int, k: int, cutover: int):
+def roll_depth(L: int, j: int, k: int) -> int:
+    return j + k * ((L - 1 - j) // k) + 1 if L > j else 0
+
+
+def split_bytes(nu: int, k: int, cutover: int):
+    """(total algorithmic bytes, levels) of level form 4: at level L >= 1 the
+    array L mod k splits from its last layout to depth L; its count reads
+    the planes the walk compares and writes a key per element (1 byte, 2 at
+    k = 8), its move reads the key and the planes it writes and writes them
+    (write masks from the library's own plan); after the last level the
+    arrays the on-chip finish reads split to its depth."""
+    from paper_1410_5420_amd import _lib
+
+    levels = 0
+    while (nu >> levels) > cutover:
+        levels += 1
+    lm, fm = _lib.level_plan(k, levels) if k > 1 else ([], [])
+    kb = 2 if k >= 8 else 1
+
+    def one(q, frm, to, mask):
+        deciding = {((l % k) - q - 1 + 2 * k) % k for l in range(frm, to)}
+        w = bin(mask).count("1")
+        return nu * (4 * len(deciding) + kb + kb + 8 * w)
+
+    total = 0
+    for L in range(1, levels):
+        q = L % k
+        total += one(q, roll_depth(L, q, k), L, lm[L])
+    for j in range(1, k):
+        a = roll_depth(levels, j, k)
+        if levels >= 1 and a < levels:
+            total += one(j, a, levels, fm[j])
+    return total, levels
+
+
+def byte_model(kernel: str, n: int, nu: int, k: int, cutover: int, level_form: int = 1):
     """Algorithmic bytes of one launch of a kernel class (averaged over the
-    build's launches of that class), and how they arise."""
+    build's launches of that class; a global level counts as one launch),
+    and how they arise."""
+    if kernel == "level" and level_form == 4:
+        total, levels = split_bytes(nu, k, cutover)
+        return total / max(levels, 1), (f"{levels} levels, one multi-level split per level: count "
+                                        f"reads the compared rank planes and writes a key, move reads "
+                                        f"the key and moves the written planes (library's write masks)")
     if kernel == "level":
         total, launches = level_bytes(nu, k, cutover)
         return total / max(launches, 1), (f"{launches} levels: per level (k-1) arrays x (k-1) ranks "
@@ -313,6 +354,7 @@ def main():
         tuned = autotune.tune(t, "plain", reps=3, record=False)
         knobs = dict(tuned["config"])
     cutover = knobs["cutover"] or 1024
+    level_form = knobs.get("level") or 4  # the library's default for one tree of k >= 3
     b = kd.Builder(n, k, torch.int32, dev, **knobs)
     perm = torch.full((n,), -1, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
@@ -369,13 +411,23 @@ def main():
         pre_ms.append(ev[0].elapsed_time(ev[1]))
         part_ms.append(ev[1].elapsed_time(ev[2]))
 
+    levels = 0
+    while (nu >> levels) > cutover:
+        levels += 1
+
     def roofline_of(cls):
         # achieved: the fixed model's algorithmic bytes per launch over the
-        # class's average launch time; the design's own byte model beside it
+        # class's average launch time; the design's own byte model beside it.
+        # A global level is one launch of the level class: its time is the
+        # class's time per build over the levels (the library records its
+        # launch groups separately, two or three per level).
         bytes_per_launch, unit_desc = survey_bytes_per_launch(cls, n, nu, k, cutover)
-        design_bytes, design_desc = byte_model(cls, n, nu, k, cutover)
+        design_bytes, design_desc = byte_model(cls, n, nu, k, cutover, level_form)
         real = [d for d in durations[cls] if d > 0.002]  # no-op launches (levels past the cutover) excluded
         avg_ms = float(np.mean(real)) if real else float("nan")
+        if cls == "level":
+            avg_ms = class_ms["level"] / max(levels, 1)
+            real = [0] * levels
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
         design_achieved = design_bytes / (avg_ms * 1e-3) / 1e9
         traffic = recorded_traffic(cls, "c2")
@@ -420,6 +472,7 @@ def main():
                    "k": k, "n": n, "n_unique": nu, "tuple_dtype": "int32", "cutover": cutover,
                    "leaf_blocks": knobs["leaf_blocks"] or 2048,
                    "records": knobs["records"] or 0,
+                   "level_form": level_form,
                    "autotuned": tuned is not None,
                    "presort_ms": round(float(np.median(pre_ms)), 4),
                    "partition_ms": round(float(np.median(part_ms)), 4),
