@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libkdtree.so")
-SOURCES = ["presort.hip", "build.hip", "split.hip", "learned.hip", "queries.hip", "api.cpp"]
+SOURCES = ["presort.hip", "build.hip", "split.hip", "select.hip", "learned.hip", "queries.hip", "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -721,16 +721,14 @@ int check_job(Job& J, size_t ws_bytes, const kd_options* opts) {
   return KD_OK;
 }
 
-// The comparison builder (Sec. 3: an O(n log n) method that finds each
-// subarray's median at every level): array 0 and duplicate removal as in the
-// presort (so the nodes are the same distinct rows), then one stable radix
-// sort per level of the single array of rows within every subarray, by the
-// level's super key (least significant word first) and then by the range
-// start of every position.  After the sort of depth d every subarray of
-// depth d holds its rows in super-key order, so its median is at its middle
-// position and its halves are already partitioned; depth 0 needs no sort.
-// Uses the build's workspace: key words in the level-0 record space, rows and
-// range starts in the first moved-record space.
+// The comparison builder (Sec. 3: an O(n log n) method that selects each
+// subarray's median afresh at every level and partitions about it): array 0
+// and duplicate removal as in the presort (so the nodes are the same distinct
+// rows), then the rows with their k key words go through the global levels of
+// select.hip (a radix-select of every subarray's median by the level's super
+// key and a partition about it) and the on-chip finish below 2048 rows.
+// Uses the build's workspace: the row planes in the radix slots, the
+// histograms and per-subarray state in the record space.
 int select_impl(const Job& J, hipStream_t st) {
   const int64_t n = J.n;
   const int k = J.k;
@@ -742,41 +740,30 @@ int select_impl(const Job& J, hipStream_t st) {
   const size_t un = (size_t)n;
   uint32_t* S = at<uint32_t>(ws, L.S);
   int32_t* uoff = at<int32_t>(ws, L.uoff);
-  const int32_t* nu = uoff + 1;
   const ForestArgs fa = forest_args(J, L);
   if (k == 1) {
     KD_TRY(launch_copy_k1(S, fa, n, J.perm, st));
     return KD_OK;
   }
-  uint32_t* words = at<uint32_t>(ws, L.rec0);   // k planes (k (k-1) n words available)
-  uint32_t* rows = at<uint32_t>(ws, L.rec1);    // rows, then range starts
-  uint32_t* range = rows + un;
+  uint32_t* P = at<uint32_t>(ws, L.vbuf);
+  uint32_t* Q = P + (size_t)(k + 1) * un;
+  uint32_t* hist = at<uint32_t>(ws, L.rec0);
+  SelState* state = at<SelState>(ws, L.rec1);
+  const int levels = select_levels_host(n);
+  KD_TRY(launch_fill_u32(hist, 0u, (int64_t)256 << levels, st));
   const TupleSrc ts{static_cast<const uint32_t*>(J.tuples), k, J.dtype == KD_F32 ? 1 : 0};
-  KD_TRY(launch_gather_words(ts.t, k, ts.is_float, S, nu, n, words, st));
-  int range_passes = 1;
-  while (range_passes < 4 && ((uint64_t)(n - 1) >> (8 * range_passes)) != 0) ++range_passes;
-  uint32_t* vb = at<uint32_t>(ws, L.vbuf);
-  uint32_t* rcnt = at<uint32_t>(ws, L.rcnt);
-  uint32_t* rgrp = at<uint32_t>(ws, L.rgrp);
-  const uint32_t* cur_rows = S;
-  for (int d = 1; (n >> d) >= 2 && d < kMaxLevels; ++d) {
-    const int p = d % k;
-    KD_TRY(launch_range_starts(nu, n, d, range, st));
-    // quantities: 0 = row, 1 + j = word j, k + 1 = range start
-    std::vector<Quant> q(k + 2);
-    q[0] = Quant{kPlaneArray, cur_rows, 0, rows};
-    for (int j = 0; j < k; ++j)
-      q[1 + j] = Quant{kPlaneArray, words + (size_t)j * un, 0, words + (size_t)j * un};
-    q[k + 1] = Quant{kPlaneArray, range, 0, nullptr};
-    std::vector<Pass> passes;
-    for (int c = k - 1; c >= 0; --c)  // super key p: words p, p+1, ..., least significant last
-      for (int ps = 0; ps < kPassesPerWord; ++ps) passes.push_back({1 + (p + c) % k, ps * kRadixBits});
-    for (int ps = 0; ps < range_passes; ++ps) passes.push_back({k + 1, ps * kRadixBits});
-    rc = run_sort(q, passes, ts, n, nu, vb, k + 2, rcnt, rgrp, st);
-    if (rc != KD_OK) return rc;
-    cur_rows = rows;
+  KD_TRY(launch_sel_init(ts.t, k, ts.is_float, S, uoff + 1, n, P, st));
+  SelJob sj{n, k, 0, uoff + 1, fa.status};
+  for (int d = 0; d < levels; ++d) {  // levels past the device's own count do nothing
+    sj.depth = d;
+    uint32_t* in = (d & 1) ? Q : P;
+    uint32_t* out = (d & 1) ? P : Q;
+    KD_LAUNCH(KD_K_LEVEL, launch_sel_level(sj, in, out, hist, state, at<uint64_t>(ws, L.lstat),
+                                           at<uint32_t>(ws, L.stflag), at<uint64_t>(ws, L.lcarry),
+                                           J.perm, st));
   }
-  KD_TRY(launch_copy_k1(cur_rows, fa, n, J.perm, st));
+  KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(fa.queue), 0u, 1, st));
+  KD_LAUNCH(KD_K_LEAF, launch_sel_leaf(sj, P, Q, J.perm, fa.queue, (int64_t)1 << levels, st));
   return KD_OK;
 }
 

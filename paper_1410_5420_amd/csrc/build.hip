@@ -1307,57 +1307,6 @@ hipError_t launch_copy_k1(const uint32_t* S0, const ForestArgs& fa, int64_t n, i
   return hipGetLastError();
 }
 
-// ---- per-level sorting builder (the comparison method) ---------------------------
-// The paper's O(n log n) builder (Sec. 3) finds every subarray's median afresh
-// at each level instead of keeping presorted arrays.  Here each level is one
-// stable radix sort of the single array of rows by the level's super key
-// within every subarray; these two kernels supply its inputs.
-
-// words[j][pos] = canonical word j of row rows[pos] (pos < *nu).
-__global__ __launch_bounds__(256) void k_gather_words(const uint32_t* __restrict__ tuples, int k,
-                                                     int is_float, const uint32_t* __restrict__ rows,
-                                                     const int32_t* __restrict__ nu, int64_t n,
-                                                     uint32_t* __restrict__ words) {
-  const int64_t total = *nu;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = rows[i];
-    for (int j = 0; j < k; ++j) words[(int64_t)j * n + i] = canon_word(tuples[r * k + j], is_float);
-  }
-}
-
-// range[pos] = the first position of pos's subarray at `depth`, or pos itself
-// when pos is the node of a shallower level.  Sorting by it (most
-// significant) keeps every subarray and every earlier node in place.
-__global__ __launch_bounds__(256) void k_range_starts(const int32_t* __restrict__ nu_dev, int depth,
-                                                     uint32_t* __restrict__ range) {
-  const int nu = *nu_dev;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nu; i += gridDim.x * blockDim.x) {
-    int s, e;
-    subarray_at(i, nu, depth, &s, &e);
-    range[i] = e < s ? (uint32_t)i : (uint32_t)s;
-  }
-}
-
-hipError_t launch_gather_words(const uint32_t* tuples, int k, int is_float, const uint32_t* rows,
-                               const int32_t* nu, int64_t n, uint32_t* words, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_gather_words, dim3((unsigned)blocks), dim3(256), 0, st, tuples, k, is_float,
-                     rows, nu, n, words);
-  return hipGetLastError();
-}
-
-hipError_t launch_range_starts(const int32_t* nu, int64_t n, int depth, uint32_t* range,
-                               hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_range_starts, dim3((unsigned)blocks), dim3(256), 0, st, nu, depth, range);
-  return hipGetLastError();
-}
-
 // Child positions of a single tree's in-order layout.
 __global__ __launch_bounds__(256) void k_children(const int32_t* __restrict__ uoff,
                                                  int32_t* __restrict__ lo, int32_t* __restrict__ hi) {

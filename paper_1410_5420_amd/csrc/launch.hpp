@@ -234,13 +234,33 @@ hipError_t launch_leaf(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1,
                        int64_t cutover, const ForestArgs& fa, int32_t* perm, int64_t items_bound,
                        int blocks, int form, hipStream_t st);
 
-// Per-level sorting builder: the k canonical words of rows[pos] for pos <
-// *nu (plane j at words + j * n), and every position's range start at
-// `depth` (its subarray's first position, or itself for an earlier node).
-hipError_t launch_gather_words(const uint32_t* tuples, int k, int is_float, const uint32_t* rows,
-                               const int32_t* nu, int64_t n, uint32_t* words, hipStream_t st);
-hipError_t launch_range_starts(const int32_t* nu, int64_t n, int depth, uint32_t* range,
-                               hipStream_t st);
+// ---- the comparison builder (select.hip) -------------------------------------
+// Planes P: row id, then the k canonical words (plane c at P + c * n).
+struct SelJob {
+  int64_t n;
+  int k;
+  int depth;
+  const int32_t* nu;  // distinct rows (device)
+  uint32_t* status;
+};
+struct SelState {
+  uint32_t lo, cnt, digit, rank;  // rows below / in the picked bucket, its digit, median rank
+};
+// Global levels: subarrays of more than 2048 rows (a function of n).
+int select_levels_host(int64_t n);
+hipError_t launch_sel_init(const uint32_t* tuples, int k, int is_float, const uint32_t* S,
+                           const int32_t* nu, int64_t n, uint32_t* P, hipStream_t st);
+// One global level from planes P into Q (P then serves as scratch).  hist:
+// (1 << depth) * 256 words, zero on entry and left zero; state: 1 << depth
+// entries; tval, carry: level_tiles(n) 64-bit words; tflag: level_tiles(n).
+hipError_t launch_sel_level(const SelJob& J, uint32_t* P, uint32_t* Q, uint32_t* hist,
+                            SelState* state, uint64_t* tval, uint32_t* tflag, uint64_t* carry,
+                            int32_t* perm, hipStream_t st);
+// Every subarray below the global levels, finished on-chip (persistent;
+// queue zero on entry).  Level d reads P0 (d even) or P1 and writes the
+// other; the finish reads the one the device's last level wrote.
+hipError_t launch_sel_leaf(const SelJob& J, uint32_t* P0, uint32_t* P1, int32_t* perm,
+                           int32_t* queue, int64_t items_bound, hipStream_t st);
 
 // k == 1: the in-order layout is the sorted unique order.
 hipError_t launch_copy_k1(const uint32_t* S0, const ForestArgs& fa, int64_t n, int32_t* perm,

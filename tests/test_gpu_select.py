@@ -1,7 +1,8 @@
-"""GPU parity of the comparison builder (kdtree_build_select: one stable
-radix sort of the rows within every subarray per level, no rank records and
-no partition kernels).  Its in-order layout must equal, bit for bit, the
-presort builder's and the oracle's."""
+"""GPU parity of the comparison builder (kdtree_build_select: every level
+selects each subarray's median afresh by a radix-select and partitions the
+subarray about it; no presort beyond the first array, no rank records).  Its
+in-order layout must equal, bit for bit, the presort builder's and the
+oracle's."""
 import numpy as np
 import pytest
 
@@ -62,3 +63,39 @@ def test_select_float_and_ties(kd):
 def test_select_large_clustered(kd, k):
     t = kdgen.clustered_int(1 << 20, k, 256, float(1 << 12), 1 << 30, 0.10, 1300 + k)
     check(kd, t, False)
+
+
+@pytest.mark.parametrize("k", [2, 3, 5, 8])
+@pytest.mark.parametrize("n", [2049, 4097, 70001, 600000])
+def test_select_global_levels(kd, k, n):
+    """Sizes with global levels (subarrays above 2048 rows) and ragged tails."""
+    t = kdgen.uniform_int(n, k, -(1 << 30), 1 << 30, 0.05, 1400 + n + k)
+    check(kd, t, True)
+
+
+@pytest.mark.parametrize("k", [3, 6])
+def test_select_heavy_ties(kd, k):
+    """Few distinct first coordinates: the median's candidates are many (digit
+    rounds over word p and later words in the candidate zone), and long tie
+    runs in the on-chip sorts take the full multi-word sort."""
+    t = kdgen.uniform_int(300000, k, -(1 << 30), 1 << 30, 0.0, 1500 + k)
+    t[:, 0] = t[:, 0] % 7
+    check(kd, t, True)
+    t = kdgen.uniform_int(200000, k, -3, 3, 0.0, 1510 + k)
+    check(kd, t, True)
+
+
+def test_select_float_mixture(kd):
+    t = kdgen.gaussian_mixture_f32(500000, 3, 16, 1600)
+    t[:100] = np.array([[np.inf, -0.0, 0.0]] * 100, dtype=np.float32)
+    check(kd, t, True)
+
+
+def test_select_c2_full_size(kd):
+    """The headline input (k=3, n=2^24) through the comparison builder."""
+    check(kd, kdgen.c2_full_range(), False)
+
+
+@pytest.mark.parametrize("k", [2, 8])
+def test_select_c3_full_size(kd, k):
+    check(kd, kdgen.c3_clustered(k), False)
