@@ -473,6 +473,8 @@ def main():
                    "leaf_blocks": knobs["leaf_blocks"] or 2048,
                    "records": knobs["records"] or 0,
                    "level_form": level_form,
+                   "digit_bits": knobs.get("digit_bits") or 8,
+                   "sort_tile": knobs.get("sort_tile") or 4096,
                    "autotuned": tuned is not None,
                    "presort_ms": round(float(np.median(pre_ms)), 4),
                    "partition_ms": round(float(np.median(part_ms)), 4),

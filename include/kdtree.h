@@ -88,7 +88,12 @@ typedef struct kd_options {
                           stable split by subtree about the medians of the
                           k-1 levels since it last split (single builds; a
                           batch runs form 1) */
-  int32_t reserved[3]; /* must be zero */
+  int32_t digit_bits;  /* radix digit width of the presort's key-word passes:
+                          0 = default (8), 8 (four passes per 32-bit word)
+                          or 11 (three) */
+  int32_t sort_tile;   /* keys per radix tile: 0 = default (4096), 4096 or
+                          8192 */
+  int32_t reserved[1]; /* must be zero */
 } kd_options;
 
 /* Write masks of level form 4 for a tree with `levels` global levels

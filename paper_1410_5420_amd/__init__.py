@@ -45,7 +45,8 @@ class Builder:
     dimensions, so repeated builds allocate nothing."""
 
     def __init__(self, n: int, k: int, dtype=torch.int32, device="cuda", cutover: int | None = None,
-                 leaf_blocks: int | None = None, records: int | None = None, level: int | None = None):
+                 leaf_blocks: int | None = None, records: int | None = None, level: int | None = None,
+                 digit_bits: int | None = None, sort_tile: int | None = None):
         self.n, self.k = int(n), int(k)
         self.code = _dtype_code(torch.empty(0, dtype=dtype))
         self.device = torch.device(device)
@@ -53,6 +54,8 @@ class Builder:
         self.leaf_blocks = leaf_blocks
         self.records = records
         self.level = level
+        self.digit_bits = digit_bits
+        self.sort_tile = sort_tile
         nbytes = _lib.workspace_bytes(self.n, self.k, self.code)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.n_unique = torch.zeros(1, dtype=torch.int64, device=self.device)
@@ -66,7 +69,8 @@ class Builder:
     def _opts(self):
         return _lib.options(self.cutover, getattr(self, "leaf_blocks", None),
                             getattr(self, "records", None), getattr(self, "learned_sorts", None),
-                            getattr(self, "level", None))
+                            getattr(self, "level", None), getattr(self, "digit_bits", None),
+                            getattr(self, "sort_tile", None))
 
     def _check_input(self, tuples: torch.Tensor):
         if tuples.dim() != 2 or tuples.shape[1] != self.k or tuples.shape[0] > self.n:
@@ -108,12 +112,15 @@ class BatchedBuilder:
     ``tuples`` into trees; the workspace is sized for exactly that split."""
 
     def __init__(self, offsets, k: int, dtype=torch.int32, device="cuda", cutover: int | None = None,
-                 leaf_blocks: int | None = None, records: int | None = None, level: int | None = None):
+                 leaf_blocks: int | None = None, records: int | None = None, level: int | None = None,
+                 digit_bits: int | None = None, sort_tile: int | None = None):
         import numpy as np
 
         self.leaf_blocks = leaf_blocks
         self.records = records
         self.level = level
+        self.digit_bits = digit_bits
+        self.sort_tile = sort_tile
         off = np.asarray(offsets.cpu() if isinstance(offsets, torch.Tensor) else offsets, dtype=np.int64)
         self.h_offsets = np.ascontiguousarray(off)
         self.trees = int(off.shape[0] - 1)
@@ -136,7 +143,8 @@ class BatchedBuilder:
             _ptr(tuples), _ptr(self.d_offsets), self.h_offsets.ctypes.data_as(ctypes.c_void_p),
             self.trees, self.k, self.code, _ptr(perm), _ptr(self.n_unique), _ptr(self.workspace),
             self.workspace.numel(), _lib.options(self.cutover, self.leaf_blocks, self.records,
-                                                 level=self.level),
+                                                 level=self.level, digit_bits=self.digit_bits,
+                                                 sort_tile=self.sort_tile),
             _stream(stream))
         _lib.check(rc, "kdtree_build_batched")
 
@@ -146,14 +154,15 @@ class BatchedBuilder:
 
 
 def build_batched(tuples: torch.Tensor, offsets, cutover: int | None = None, stream=None,
-                  level: int | None = None):
+                  level: int | None = None, **knobs):
     """Build one tree per row range ``offsets[b] .. offsets[b+1]-1``.
 
     Returns ``(perm, n_unique)``: perm (int32, length offsets[-1]) holds tree
     b's in-order layout at positions offsets[b] .. offsets[b]+n_unique[b]-1,
     as row indices local to the tree.
     """
-    b = BatchedBuilder(offsets, tuples.shape[1], tuples.dtype, tuples.device, cutover, level=level)
+    b = BatchedBuilder(offsets, tuples.shape[1], tuples.dtype, tuples.device, cutover, level=level,
+                       **knobs)
     perm = torch.full((max(b.total, 1),), -1, dtype=torch.int32, device=tuples.device)
     b.build(tuples.contiguous(), perm, stream)
     b.status(stream)
@@ -161,14 +170,16 @@ def build_batched(tuples: torch.Tensor, offsets, cutover: int | None = None, str
 
 
 def build(tuples: torch.Tensor, children: bool = False, cutover: int | None = None, stream=None,
-          records: int | None = None, level: int | None = None):
+          records: int | None = None, level: int | None = None, digit_bits: int | None = None,
+          sort_tile: int | None = None):
     """Build the tree of ``tuples`` ((n, k) int32/float32 device tensor).
 
     Returns ``(perm, n_unique)`` or ``(perm, n_unique, lo, hi)`` with device
     tensors trimmed to ``n_unique`` (this synchronises to read the count).
     """
     n, k = tuples.shape
-    b = Builder(max(n, 1), k, tuples.dtype, tuples.device, cutover, records=records, level=level)
+    b = Builder(max(n, 1), k, tuples.dtype, tuples.device, cutover, records=records, level=level,
+                digit_bits=digit_bits, sort_tile=sort_tile)
     perm = torch.full((max(n, 1),), -1, dtype=torch.int32, device=tuples.device)
     lo = hi = None
     if children:
@@ -316,7 +327,8 @@ def reverse_nearest(perm: torch.Tensor, n_nodes, near_rows: torch.Tensor, stream
     return offsets, lists
 
 
-def build_select(tuples: torch.Tensor, stream=None):
+def build_select(tuples: torch.Tensor, stream=None, digit_bits: int | None = None,
+                 sort_tile: int | None = None):
     """The same tree by the comparison method (kdtree_build_select): a stable
     radix sort of the rows within every subarray at each level instead of k
     presorts and partitions.  Returns ``(perm, n_unique)`` like ``build``."""
@@ -327,7 +339,10 @@ def build_select(tuples: torch.Tensor, stream=None):
     nu = torch.zeros(1, dtype=torch.int64, device=tuples.device)
     perm = torch.full((max(n, 1),), -1, dtype=torch.int32, device=tuples.device)
     _lib.check(_lib.lib.kdtree_build_select(_ptr(tuples.contiguous()), n, k, code, _ptr(perm),
-                                            _ptr(nu), _ptr(ws), nbytes, None, _stream(stream)),
+                                            _ptr(nu), _ptr(ws), nbytes,
+                                            _lib.options(None, digit_bits=digit_bits,
+                                                         sort_tile=sort_tile),
+                                            _stream(stream)),
                "kdtree_build_select")
     _lib.status(_ptr(ws), nbytes, _stream(stream))
     u = int(nu.item())
@@ -429,8 +444,11 @@ class LearnedBuilder(Builder):
 
     def __init__(self, n: int, k: int, dtype=torch.int32, device="cuda", cutover: int | None = None,
                  leaf_blocks: int | None = None, records: int | None = None,
-                 learned_sorts: int | None = None, level: int | None = None):
+                 learned_sorts: int | None = None, level: int | None = None,
+                 digit_bits: int | None = None, sort_tile: int | None = None):
         self.n, self.k = int(n), int(k)
+        self.digit_bits = digit_bits
+        self.sort_tile = sort_tile
         self.code = _dtype_code(torch.empty(0, dtype=dtype))
         self.device = torch.device(device)
         self.cutover = cutover
@@ -467,11 +485,11 @@ class LearnedBuilder(Builder):
 
 
 def build_learned(tuples: torch.Tensor, models: torch.Tensor, children: bool = False,
-                  cutover: int | None = None, stream=None):
+                  cutover: int | None = None, stream=None, **knobs):
     """Like :func:`build`, through the learned presort.  Returns ``(perm,
     n_unique, fell_back)`` or ``(perm, n_unique, fell_back, lo, hi)``."""
     n, k = tuples.shape
-    b = LearnedBuilder(max(n, 1), k, tuples.dtype, tuples.device, cutover)
+    b = LearnedBuilder(max(n, 1), k, tuples.dtype, tuples.device, cutover, **knobs)
     perm = torch.full((max(n, 1),), -1, dtype=torch.int32, device=tuples.device)
     lo = hi = None
     if children:

@@ -29,7 +29,8 @@ class KdError(RuntimeError):
 class kd_options(ctypes.Structure):
     _fields_ = [("cutover", ctypes.c_int32), ("leaf_blocks", ctypes.c_int32),
                 ("records", ctypes.c_int32), ("learned_sorts", ctypes.c_int32),
-                ("level", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("level", ctypes.c_int32), ("digit_bits", ctypes.c_int32),
+                ("sort_tile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 def _load():
@@ -174,9 +175,10 @@ def workspace_bytes_batched(total: int, trees: int, k: int, dtype: int) -> int:
 
 
 def options(cutover: int | None, leaf_blocks: int | None = None, records: int | None = None,
-            learned_sorts: int | None = None, level: int | None = None):
-    if cutover is None and leaf_blocks is None and records is None and learned_sorts is None \
-            and level is None:
+            learned_sorts: int | None = None, level: int | None = None,
+            digit_bits: int | None = None, sort_tile: int | None = None):
+    vals = (cutover, leaf_blocks, records, learned_sorts, level, digit_bits, sort_tile)
+    if all(v is None for v in vals):
         return None
     o = kd_options()
     o.cutover = int(cutover or 0)
@@ -184,6 +186,8 @@ def options(cutover: int | None, leaf_blocks: int | None = None, records: int | 
     o.records = int(records or 0)
     o.learned_sorts = int(learned_sorts or 0)
     o.level = int(level or 0)
+    o.digit_bits = int(digit_bits or 0)
+    o.sort_tile = int(sort_tile or 0)
     return ctypes.byref(o)
 
 

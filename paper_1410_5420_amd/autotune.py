@@ -2,10 +2,10 @@
 
 The knobs -- the cutover C below which a subarray is finished on-chip, the
 number of workgroups of the persistent on-chip finish, how the level-0 rank
-records are completed, (learned form) which sorts use the learned
-buckets, and (plain form) the level form: k-1 arrays moved per level, one
-multi-level split per level, or (k >= 5) deferred partitioning --
-change speed only.  tune() times every candidate configuration on the caller's input, and
+records are completed, the radix digit width and tile size of the presort,
+(learned form) which sorts use the learned buckets, and (plain form) the
+level form: k-1 arrays moved per level, one multi-level split per level, or
+(k >= 5) deferred partitioning -- change speed only.  tune() times every candidate configuration on the caller's input, and
 checks that each one returns exactly the output of the default
 configuration (a difference would be a bug, and raises); the fastest is
 cached per (form, k, dtype, log2 n) in a JSON file, from which
@@ -24,15 +24,32 @@ CANDIDATES = [{"cutover": c, "leaf_blocks": b, "records": r} for c in (1024, 204
 # all of them, or only the first (the multi-word sort, where the buckets save
 # the most passes)
 LEARNED_SORTS = (0, 1)
-# level forms of a single tree: 1 (every level moves k-1 arrays) and 4 (one
-# multi-level split per level); deferred partitioning (form 3) saves
+# level forms of a single tree: 4 (one multi-level split per level; the
+# default from k = 3 on) and 1 (every level moves k-1 arrays); deferred partitioning (form 3) saves
 # (k-1)(k-2)/2 array moves for the price of one radix split per array j >= 2,
 # measured to lose at k <= 4, so only k >= 5 try it
-LEVEL_FORMS = (1, 4)
+LEVEL_FORMS = (4, 1)
 DEFERRED_MIN_K = 5
+# radix geometry: digit width (8 or 11 bits: four or three passes per key
+# word) and keys per tile
+DIGIT_BITS = (8, 11)
+SORT_TILES = (4096, 8192)
+
+
+def knob_values(form: str, k: int | None = None) -> dict:
+    """The values every knob of a form may take (the first is its default)."""
+    v = {"cutover": (1024, 2048, 4096), "leaf_blocks": (2048, 1024, 4096), "records": (0, 1, 2),
+         "digit_bits": DIGIT_BITS, "sort_tile": SORT_TILES}
+    if form == "plain":
+        v["level"] = LEVEL_FORMS + ((3,) if k is not None and k >= DEFERRED_MIN_K else ())
+    if form == "learned":
+        v["learned_sorts"] = LEARNED_SORTS
+    return v
 
 
 def candidates_for(form: str, k: int | None = None) -> list:
+    """Every combination of cutover, finish grid and record completion, with
+    the form's own knob (learned sorts; level form of the plain form)."""
     if form == "learned":
         return [dict(c, learned_sorts=m) for c in CANDIDATES for m in LEARNED_SORTS]
     if form == "plain":
@@ -82,18 +99,30 @@ def select(results: list) -> dict:
     return min(results, key=lambda r: r["ms"])
 
 
+def coordinate_order(form: str, k: int | None = None) -> list:
+    """The knobs in the order coordinate descent sweeps them."""
+    order = ["level", "cutover", "leaf_blocks", "records", "digit_bits", "sort_tile",
+             "learned_sorts"]
+    vals = knob_values(form, k)
+    return [(name, vals[name]) for name in order if name in vals]
+
+
 def tune(tuples, form: str = "plain", offsets=None, models=None, candidates=None, reps: int = 5,
-         warmup: int = 1, path: str | None = None, record: bool = True) -> dict:
-    """Time the candidate configurations on ``tuples`` (a device tensor) and
-    cache the fastest.  form: "plain", "learned" (needs ``models``) or
-    "batched" (needs ``offsets``).  Returns {"config", "ms", "results"}."""
+         warmup: int = 1, path: str | None = None, record: bool = True,
+         strategy: str = "coordinate") -> dict:
+    """Time configurations on ``tuples`` (a device tensor) and cache the
+    fastest.  form: "plain", "learned" (needs ``models``) or "batched" (needs
+    ``offsets``).  With ``candidates`` (a list of configurations) every one
+    is timed; otherwise strategy "coordinate" sweeps one knob at a time from
+    the defaults, keeping the best value found so far (knob_values), and
+    "exhaustive" times candidates_for(form).  Every configuration's output
+    must equal the default's.  Returns {"config", "ms", "results"}."""
     import torch
 
     from . import BatchedBuilder, Builder, LearnedBuilder
 
     n, k = tuples.shape
     dev = tuples.device
-    candidates = candidates or candidates_for(form, k)
     dtype = str(tuples.dtype).replace("torch.", "")
 
     def make(cfg):
@@ -117,7 +146,8 @@ def tune(tuples, form: str = "plain", offsets=None, models=None, candidates=None
 
     results = []
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    for cfg in candidates:
+
+    def time_cfg(cfg):
         b, run = make(dict(cfg))
         perm = torch.full_like(ref, -1)
         for _ in range(warmup):
@@ -133,9 +163,27 @@ def tune(tuples, form: str = "plain", offsets=None, models=None, candidates=None
             torch.cuda.synchronize()
             times.append(ev0.elapsed_time(ev1))
         times.sort()
-        results.append({"config": dict(cfg), "ms": times[len(times) // 2]})
+        res = {"config": dict(cfg), "ms": times[len(times) // 2]}
+        results.append(res)
         del b
-    best = select(results)
+        return res
+
+    if candidates is not None or strategy == "exhaustive":
+        for cfg in candidates or candidates_for(form, k):
+            time_cfg(cfg)
+        best = select(results)
+    elif strategy == "coordinate":
+        cur = {name: vals[0] for name, vals in coordinate_order(form, k)}
+        best = time_cfg(cur)
+        for name, vals in coordinate_order(form, k):
+            for v in vals:
+                if v == best["config"][name]:
+                    continue
+                r = time_cfg(dict(best["config"], **{name: v}))
+                if r["ms"] < best["ms"]:
+                    best = r
+    else:
+        raise ValueError(strategy)
     if record:
         entries = load(path)
         entries[cache_key(form, n, k, dtype)] = {"config": best["config"], "ms": best["ms"]}

@@ -115,15 +115,20 @@ T* at(void* base, size_t off) {
 bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
 
 int check_opts(const kd_options* opts, int64_t* cutover, int* leaf_blocks, int* records,
-               int* learned_sorts, int* level) {
+               int* learned_sorts, int* level, int* digit_bits, int* sort_items) {
   *cutover = 1024;
   *leaf_blocks = 2048;
   *records = 0;
   *learned_sorts = 0;
   *level = 0;
+  *digit_bits = 8;
+  *sort_items = 8;
   if (opts) {
-    for (int i = 0; i < 3; ++i)
-      if (opts->reserved[i] != 0) return KD_EINVAL;
+    if (opts->reserved[0] != 0) return KD_EINVAL;
+    if (opts->digit_bits != 0 && opts->digit_bits != 8 && opts->digit_bits != 11) return KD_EINVAL;
+    if (opts->digit_bits != 0) *digit_bits = opts->digit_bits;
+    if (opts->sort_tile != 0 && opts->sort_tile != 4096 && opts->sort_tile != 8192) return KD_EINVAL;
+    if (opts->sort_tile != 0) *sort_items = opts->sort_tile / 512;
     if (opts->level < 0 || opts->level > 4) return KD_EINVAL;
     *level = opts->level;
     if (opts->learned_sorts < 0 || opts->learned_sorts > 0xFF) return KD_EINVAL;
@@ -189,8 +194,9 @@ struct Quant {
 };
 
 struct Pass {
-  int key;    // quantity index
-  int shift;  // digit
+  int key;       // quantity index
+  int shift;     // digit
+  int bits = 8;  // digit width
 };
 
 // The status word of the build being enqueued (set by every entry point that
@@ -199,10 +205,11 @@ thread_local uint32_t* t_status = nullptr;
 
 int run_sort(std::vector<Quant>& q, const std::vector<Pass>& passes, const TupleSrc& ts, int64_t n,
              const int32_t* n_dev, uint32_t* vb, int slots, uint32_t* rcnt, uint32_t* rgrp,
-             hipStream_t st, const int32_t* gate = nullptr) {
+             hipStream_t st, const int32_t* gate = nullptr, int items = 8) {
   RadixExtra ex;
   ex.gate = gate;
   ex.status = t_status;
+  ex.items = items;
   const size_t un = (size_t)n;
   auto slot = [&](int set, int i) { return vb + ((size_t)set * slots + i) * un; };
   const int np = (int)passes.size();
@@ -231,6 +238,7 @@ int run_sort(std::vector<Quant>& q, const std::vector<Pass>& passes, const Tuple
       moved.push_back(i);
     }
     pay.count = c;
+    ex.bits = passes[p].bits;
     KD_LAUNCH(KD_K_ONESWEEP, launch_radix_pass(kin, ts, q[kq].word, kout, pay, n, n_dev,
                                                passes[p].shift, rcnt, rgrp, st, ex));
     for (int i = 0; i < (int)q.size(); ++i) {
@@ -337,6 +345,8 @@ struct Job {
   int records = 0;  // 0: by size, 1: direct scatter, 2: radix pass + placement
   int learned_sorts = 0;  // learned presort: bit d = sort d uses the buckets; 0 = all
   int level = 0;          // 0/1: seg + chain + move launches per level, 2: look-back launch
+  int digit_bits = 8;     // digit width of the presort's key-word passes (8 or 11)
+  int sort_items = 8;     // keys per thread of every radix pass (tiles of 512 * this)
   const CdfModel* models = nullptr;  // learned presort: one model per dimension
   int32_t* fell_back = nullptr;      // learned presort: per-sort fallback flags (device)
 };
@@ -394,7 +404,12 @@ int presort_impl(const Job& J, hipStream_t st, bool first_only = false) {
     uint32_t* tree_in = carry + (size_t)(k - 1) * un;
     if (B > 1) KD_TRY(launch_tree_ids(J.d_off, B, tree_in, st));
     std::vector<Quant> q(k + 2);
-    const int fs = (k * kPassesPerWord + tp) & 1;  // buffer set holding the sorted result
+    // word 0 at the chosen digit width in both sorts of array 0, the other
+    // words of the complete sort at 8 bits: the two sorts then differ by
+    // 4 (k - 1) passes, so they end in the same buffer set
+    const int r = J.digit_bits;
+    const int P0 = passes_per_word(r);
+    const int fs = (P0 + 4 * (k - 1) + tp) & 1;  // buffer set holding the sorted result
     auto final_slot = [&](int i) { return vb + ((size_t)fs * slots + i) * un; };
     q[0] = Quant{kPlaneIndex, nullptr, 0, final_slot(0)};
     for (int d = 1; d < k; ++d) q[d] = Quant{kPlaneTupleWord, nullptr, d, final_slot(d)};
@@ -402,19 +417,21 @@ int presort_impl(const Job& J, hipStream_t st, bool first_only = false) {
     q[k + 1] = B > 1 ? Quant{kPlaneArray, tree_in, 0, final_slot(k + 1)}
                      : Quant{-1, nullptr, 0, nullptr};
     std::vector<Pass> passes;
-    for (int w = k - 1; w >= 0; --w)
-      for (int ps = 0; ps < kPassesPerWord; ++ps) passes.push_back({w == 0 ? k : w, ps * kRadixBits});
-    for (int ps = 0; ps < tp; ++ps) passes.push_back({k + 1, ps * kRadixBits});
+    for (int w = k - 1; w >= 1; --w)
+      for (int ps = 0; ps < kPassesPerWord; ++ps) passes.push_back({w, ps * kRadixBits, 8});
+    for (int ps = 0; ps < P0; ++ps) passes.push_back({k, ps * r, r});
+    for (int ps = 0; ps < tp; ++ps) passes.push_back({k + 1, ps * kRadixBits, 8});
     const int32_t* gate = nullptr;
     if (k > 1 && !(learned && learned_sort_on(J, 0))) {
       // word 0 first (then tree), then the runs of equal word 0 by the other
       // words and row; the complete sort above runs only if a run is too
       // long for the tie step
       std::vector<Pass> first;
-      for (int ps = 0; ps < kPassesPerWord; ++ps) first.push_back({k, ps * kRadixBits});
-      for (int ps = 0; ps < tp; ++ps) first.push_back({k + 1, ps * kRadixBits});
+      for (int ps = 0; ps < P0; ++ps) first.push_back({k, ps * r, r});
+      for (int ps = 0; ps < tp; ++ps) first.push_back({k + 1, ps * kRadixBits, 8});
       std::vector<Quant> qf = q;
-      int rc = run_sort(qf, first, ts, n, nullptr, vb, slots, rcnt, rgrp, st);
+      int rc = run_sort(qf, first, ts, n, nullptr, vb, slots, rcnt, rgrp, st, nullptr,
+                        J.sort_items);
       if (rc != KD_OK) return rc;
       int32_t* tl = at<int32_t>(ws, L.ties);
       int32_t* tcount = tl + kMaxTieRuns;
@@ -440,7 +457,7 @@ int presort_impl(const Job& J, hipStream_t st, bool first_only = false) {
       if (rc != KD_OK) return rc;
       gate = ls.flag;
     }
-    int rc = run_sort(q, passes, ts, n, nullptr, vb, slots, rcnt, rgrp, st, gate);
+    int rc = run_sort(q, passes, ts, n, nullptr, vb, slots, rcnt, rgrp, st, gate, J.sort_items);
     if (rc != KD_OK) return rc;
     // Sec. 2.1 duplicate removal on the fully sorted order; hands the words
     // w1..w_{k-1} (and tree ids) of the kept rows to the chain
@@ -484,8 +501,9 @@ int presort_impl(const Job& J, hipStream_t st, bool first_only = false) {
       q.push_back(Quant{kPlaneArray, tree_c, 0, tree_c});
     }
     std::vector<Pass> passes;
-    for (int ps = 0; ps < kPassesPerWord; ++ps) passes.push_back({keyq, ps * kRadixBits});
-    for (int ps = 0; ps < tp; ++ps) passes.push_back({treeq, ps * kRadixBits});
+    const int r = J.digit_bits;
+    for (int ps = 0; ps < passes_per_word(r); ++ps) passes.push_back({keyq, ps * r, r});
+    for (int ps = 0; ps < tp; ++ps) passes.push_back({treeq, ps * kRadixBits, 8});
     const int32_t* gate = nullptr;
     if (learned && learned_sort_on(J, d)) {
       // bucket on word d and finish by it; ties keep the order of array d+1,
@@ -505,7 +523,7 @@ int presort_impl(const Job& J, hipStream_t st, bool first_only = false) {
       if (rc != KD_OK) return rc;
       gate = ls.flag;
     }
-    int rc = run_sort(q, passes, ts, n, total, vb, slots, rcnt, rgrp, st, gate);
+    int rc = run_sort(q, passes, ts, n, total, vb, slots, rcnt, rgrp, st, gate, J.sort_items);
     if (rc != KD_OK) return rc;
     if (learned) std::swap(cin, cout);
   }
@@ -715,7 +733,8 @@ int check_job(Job& J, size_t ws_bytes, const kd_options* opts) {
   if (!aligned4(J.tuples) || !aligned4(J.ws)) return KD_EINVAL;
   if ((reinterpret_cast<uintptr_t>(J.n_unique) & 7u) != 0) return KD_EINVAL;
   if (ws_bytes < plan(J.n, J.k, J.B, J.models != nullptr).end) return KD_ENOMEM;
-  int rc = check_opts(opts, &J.cutover, &J.leaf_blocks, &J.records, &J.learned_sorts, &J.level);
+  int rc = check_opts(opts, &J.cutover, &J.leaf_blocks, &J.records, &J.learned_sorts, &J.level,
+                      &J.digit_bits, &J.sort_items);
   if (rc != KD_OK) return rc;
   while (J.cutover > 1024 && leaf_lds_bytes(J.cutover, J.k) + 8192 > 160 * 1024) J.cutover /= 2;
   return KD_OK;

@@ -8,10 +8,13 @@
 namespace kd {
 
 constexpr int kMaxK = 8;
-constexpr int kRadixBits = 8;
+constexpr int kRadixBits = 8;      // the default digit width
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kPassesPerWord = 32 / kRadixBits;
-constexpr int kSortTile = 4096;   // elements per onesweep tile
+constexpr int kSortTile = 4096;   // elements per radix tile (the smaller of the two tile sizes)
+constexpr int kMaxBins = 1 << 11; // bins of the widest digit (11 bits)
+// Digit passes of a 32-bit word at digit width `bits` (8: 4 passes, 11: 3).
+inline int passes_per_word(int bits) { return (32 + bits - 1) / bits; }
 constexpr int kLevelTile = 4096;  // elements per level-partition tile
 
 // Device view of a forest of independent trees (a single build is one tree):
@@ -78,9 +81,12 @@ struct RadixExtra {
   int nb_bits = 0;
   const int32_t* gate = nullptr;
   uint32_t* status = nullptr;  // status word (kStatusRadix), or null
+  int bits = 8;                // digit width: 8 or 11 (model passes always 8)
+  int items = 8;               // keys per thread: 8 (tiles of 4096) or 16 (8192)
 };
 
-// One stable LSD radix pass on 8-bit digit `shift`: per-tile digit counts, a
+// One stable LSD radix pass on the digit of width ex.bits at bit `shift`
+// (tiles of 512 * ex.items keys): per-tile digit counts, a
 // two-level scan and the scatter (four launches, no waiting between
 // workgroups).  The key of element i is keys_in[i], or (keys_in == nullptr)
 // the canonical word `key_word` of tuple row i.  keys_out may be null.  Every
@@ -91,8 +97,9 @@ hipError_t launch_radix_pass(const uint32_t* keys_in, const TupleSrc& ts, int ke
                              const int32_t* n_dev, int shift, uint32_t* cnt, uint32_t* group_tot,
                              hipStream_t st, const RadixExtra& ex = RadixExtra());
 inline int64_t radix_tiles(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
-inline int64_t radix_count_words(int64_t n) { return radix_tiles(n) * kRadix; }
-inline int64_t radix_group_words(int64_t n) { return (radix_tiles(n) + 63) / 64 * kRadix; }
+// sized for every geometry: the smaller tile and the wider digit
+inline int64_t radix_count_words(int64_t n) { return radix_tiles(n) * kMaxBins; }
+inline int64_t radix_group_words(int64_t n) { return (radix_tiles(n) + 63) / 64 * kMaxBins; }
 
 // Duplicate removal over the fully sorted order.  w0: sorted first key word;
 // planes: n-strided planes [id, w1, ..., w_{k-1}] in the same order.  Writes

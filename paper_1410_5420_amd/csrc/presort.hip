@@ -14,6 +14,8 @@
 // the key words of later passes, the ranks known so far) travels with the key
 // as a payload plane and is staged through LDS, so all global traffic is in
 // coalesced runs.
+#include <type_traits>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -60,10 +62,27 @@ hipError_t launch_store_i64(int64_t* dst, const int64_t* src, hipStream_t st) {
 //               order and writes them out in runs.
 
 constexpr int kOsThreads = 512;
-constexpr int kOsItems = kSortTile / kOsThreads;  // 8
 constexpr int kOsWaves = kOsThreads / kWave;
 constexpr int kScanGroup = 64;                      // tiles per first-level scan block
 constexpr int kGatedGrid = 256;                     // workgroups of a gated pass (a multiple of 8)
+
+// Geometry of a pass: digit width (8 or 11 bits: 4 or 3 passes per 32-bit
+// word) and keys per thread (a tile of 512 * kItems keys).  Per-wave digit
+// counters are 16-bit for 11-bit digits (a wave counts at most 64 * kItems
+// keys), so that 2048 bins fit in LDS beside the tile.
+template <int kB, int kI>
+struct Geom {
+  static constexpr int bits = kB;
+  static constexpr int bins = 1 << kB;
+  static constexpr uint32_t mask = (uint32_t)bins - 1u;
+  static constexpr int items = kI;
+  static constexpr int tile = kOsThreads * kI;
+  using WCnt = typename std::conditional<(kB > 8), uint16_t, uint32_t>::type;
+  // the threads that own digits for the tile scan own dpt consecutive ones
+  static constexpr int dpt = bins > kOsThreads ? bins / kOsThreads : 1;
+  static constexpr int owners = bins / dpt;
+  static_assert(bins <= kMaxBins && tile >= kSortTile, "geometry within the workspace's sizing");
+};
 
 // Positions fit in 31 bits (n <= 2^30 - 1); only tuple rows are addressed in
 // 64-bit, since row * k can exceed that.
@@ -108,13 +127,13 @@ __device__ __forceinline__ bool gated_off(const RadixExtra& ex) {
 
 // Workgroup b counts tiles b, b + grid, ... (one tile each in an ordinary
 // pass), loading the next tile's keys while it counts the current one.
-template <bool kFromTuples, bool kModel>
+template <class G, bool kFromTuples, bool kModel>
 __global__ __launch_bounds__(kOsThreads) void k_radix_count(const uint32_t* __restrict__ keys_in,
                                                            const TupleSrc ts, int key_word,
                                                            int64_t n_host, const int32_t* n_dev,
                                                            int shift, uint32_t* __restrict__ cnt,
                                                            const RadixExtra ex) {
-  __shared__ uint32_t s_h[kRadix];
+  __shared__ uint32_t s_h[G::bins];
   __shared__ float s_c[kModel ? kCdfSegments + 1 : 1];
   if (gated_off(ex)) return;
   const int tid = threadIdx.x;
@@ -122,12 +141,12 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_count(const uint32_t* __re
   if constexpr (kModel) mv = load_model(ex, s_c);
   const int n = (int)(n_dev ? *n_dev : n_host);
   // every tile of the launch bound gets its row (zeros beyond the device count)
-  const int tiles = (int)((n_host + kSortTile - 1) / kSortTile);
-  uint32_t key[kOsItems];
+  const int tiles = (int)((n_host + G::tile - 1) / G::tile);
+  uint32_t key[G::items];
   auto load = [&](int tile) {
-    const int base = tile * kSortTile;
+    const int base = tile * G::tile;
 #pragma unroll
-    for (int j = 0; j < kOsItems; ++j) {
+    for (int j = 0; j < G::items; ++j) {
       const int i = base + j * kOsThreads + tid;
       key[j] = 0u;
       if (i < n)
@@ -137,97 +156,131 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_count(const uint32_t* __re
   int tile = blockIdx.x;
   if (tile < tiles) load(tile);
   for (; tile < tiles; tile += gridDim.x) {
-    if (tid < kRadix) s_h[tid] = 0;
+    for (int d = tid; d < G::bins; d += kOsThreads) s_h[d] = 0;
     __syncthreads();
-    const int base = tile * kSortTile;
+    const int base = tile * G::tile;
 #pragma unroll
-    for (int j = 0; j < kOsItems; ++j) {
+    for (int j = 0; j < G::items; ++j) {
       const int i = base + j * kOsThreads + tid;
       if (i < n) {
         const uint32_t kk = kModel ? model_bucket(mv, key[j]) : key[j];
-        atomicAdd(&s_h[(kk >> shift) & 0xFF], 1u);
+        atomicAdd(&s_h[(kk >> shift) & G::mask], 1u);
       }
     }
     if (tile + (int)gridDim.x < tiles) load(tile + gridDim.x);
     __syncthreads();
-    if (tid < kRadix) cnt[(int64_t)tile * kRadix + tid] = s_h[tid];
+    for (int d = tid; d < G::bins; d += kOsThreads) cnt[(int64_t)tile * G::bins + d] = s_h[d];
     __syncthreads();
   }
 }
 
-// First level: exclusive prefix over the tiles of one group, per digit.
-__global__ __launch_bounds__(kRadix) void k_radix_scan_tiles(uint32_t* __restrict__ cnt,
-                                                            uint32_t* __restrict__ group_tot,
-                                                            int tiles, const RadixExtra ex) {
+// First level: exclusive prefix over the tiles of one group, per digit (256
+// digits per block; blockIdx.y picks them).
+template <int kBins>
+__global__ __launch_bounds__(256) void k_radix_scan_tiles(uint32_t* __restrict__ cnt,
+                                                         uint32_t* __restrict__ group_tot,
+                                                         int tiles, const RadixExtra ex) {
   if (gated_off(ex)) return;
-  const int d = threadIdx.x;
+  const int d = blockIdx.y * 256 + threadIdx.x;
   const int t0 = blockIdx.x * kScanGroup;
   const int t1 = min(t0 + kScanGroup, tiles);
   uint32_t run = 0;
   for (int t = t0; t < t1; t += 8) {
     uint32_t c[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) c[q] = (t + q < t1) ? cnt[(int64_t)(t + q) * kRadix + d] : 0u;
+    for (int q = 0; q < 8; ++q) c[q] = (t + q < t1) ? cnt[(int64_t)(t + q) * kBins + d] : 0u;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      if (t + q < t1) cnt[(int64_t)(t + q) * kRadix + d] = run;
+      if (t + q < t1) cnt[(int64_t)(t + q) * kBins + d] = run;
       run += c[q];
     }
   }
-  group_tot[(int64_t)blockIdx.x * kRadix + d] = run;
+  group_tot[(int64_t)blockIdx.x * kBins + d] = run;
 }
 
 // Second level: one block turns group totals into group starts that already
-// include every digit's global start.  Four threads per digit each take a
-// quarter of the groups, with their loads batched.
-constexpr int kSgSub = 4;
+// include every digit's global start.  256 digits: four threads per digit
+// each take a quarter of the groups; 2048 digits: each thread takes two
+// consecutive digits over all groups.  Loads are batched.
 constexpr int kSgBatch = 16;
-__global__ __launch_bounds__(kRadix * kSgSub) void k_radix_scan_groups(
-    uint32_t* __restrict__ group_tot, int groups, const RadixExtra ex) {
-  __shared__ uint32_t s_part[kSgSub][kRadix];
-  __shared__ uint32_t s_tmp[kRadix * kSgSub / kWave + 1];
+template <int kBins>
+__global__ __launch_bounds__(1024) void k_radix_scan_groups(uint32_t* __restrict__ group_tot,
+                                                           int groups, const RadixExtra ex) {
+  constexpr int kSub = kBins <= 1024 ? 1024 / kBins : 1;  // threads per digit
+  constexpr int kDpt = kBins <= 1024 ? 1 : kBins / 1024;  // digits per thread
+  __shared__ uint32_t s_part[kSub][kBins <= 1024 ? kBins : 1];
+  __shared__ uint32_t s_tmp[1024 / kWave + 1];
   if (gated_off(ex)) return;
-  const int d = threadIdx.x % kRadix;
-  const int sub = threadIdx.x / kRadix;
-  const int per = (groups + kSgSub - 1) / kSgSub;
-  const int g0 = sub * per, g1 = min(groups, g0 + per);
-  uint32_t sum = 0;
-  for (int g = g0; g < g1; g += kSgBatch) {
-    uint32_t c[kSgBatch];
+  if constexpr (kDpt == 1) {
+    const int d = threadIdx.x % kBins;
+    const int sub = threadIdx.x / kBins;
+    const int per = (groups + kSub - 1) / kSub;
+    const int g0 = sub * per, g1 = min(groups, g0 + per);
+    uint32_t sum = 0;
+    for (int g = g0; g < g1; g += kSgBatch) {
+      uint32_t c[kSgBatch];
 #pragma unroll
-    for (int q = 0; q < kSgBatch; ++q)
-      c[q] = g + q < g1 ? group_tot[(int64_t)(g + q) * kRadix + d] : 0u;
+      for (int q = 0; q < kSgBatch; ++q)
+        c[q] = g + q < g1 ? group_tot[(int64_t)(g + q) * kBins + d] : 0u;
 #pragma unroll
-    for (int q = 0; q < kSgBatch; ++q) sum += c[q];
-  }
-  s_part[sub][d] = sum;
-  __syncthreads();
-  uint32_t digit_total = 0;
-  if (sub == 0)
-    for (int q = 0; q < kSgSub; ++q) digit_total += s_part[q][d];
-  uint32_t all;
-  const uint32_t digit_start = block_exclusive_sum<kRadix * kSgSub>(digit_total, s_tmp, &all);
-  __syncthreads();
-  if (sub == 0) {
-    uint32_t run = digit_start;
-    for (int q = 0; q < kSgSub; ++q) {
-      const uint32_t c = s_part[q][d];
-      s_part[q][d] = run;
-      run += c;
+      for (int q = 0; q < kSgBatch; ++q) sum += c[q];
     }
-  }
-  __syncthreads();
-  uint32_t run = s_part[sub][d];
-  for (int g = g0; g < g1; g += kSgBatch) {
-    uint32_t c[kSgBatch];
-#pragma unroll
-    for (int q = 0; q < kSgBatch; ++q)
-      c[q] = g + q < g1 ? group_tot[(int64_t)(g + q) * kRadix + d] : 0u;
-#pragma unroll
-    for (int q = 0; q < kSgBatch; ++q) {
-      if (g + q < g1) group_tot[(int64_t)(g + q) * kRadix + d] = run;
-      run += c[q];
+    s_part[sub][d] = sum;
+    __syncthreads();
+    uint32_t digit_total = 0;
+    if (sub == 0)
+      for (int q = 0; q < kSub; ++q) digit_total += s_part[q][d];
+    uint32_t all;
+    const uint32_t digit_start = block_exclusive_sum<1024>(digit_total, s_tmp, &all);
+    __syncthreads();
+    if (sub == 0) {
+      uint32_t run = digit_start;
+      for (int q = 0; q < kSub; ++q) {
+        const uint32_t c = s_part[q][d];
+        s_part[q][d] = run;
+        run += c;
+      }
     }
+    __syncthreads();
+    uint32_t run = s_part[sub][d];
+    for (int g = g0; g < g1; g += kSgBatch) {
+      uint32_t c[kSgBatch];
+#pragma unroll
+      for (int q = 0; q < kSgBatch; ++q)
+        c[q] = g + q < g1 ? group_tot[(int64_t)(g + q) * kBins + d] : 0u;
+#pragma unroll
+      for (int q = 0; q < kSgBatch; ++q) {
+        if (g + q < g1) group_tot[(int64_t)(g + q) * kBins + d] = run;
+        run += c[q];
+      }
+    }
+  } else {
+    const int d0 = threadIdx.x * kDpt;
+    uint32_t tot[kDpt];
+#pragma unroll
+    for (int q = 0; q < kDpt; ++q) tot[q] = 0;
+    for (int g = 0; g < groups; ++g)
+#pragma unroll
+      for (int q = 0; q < kDpt; ++q) tot[q] += group_tot[(int64_t)g * kBins + d0 + q];
+    uint32_t mine = 0;
+#pragma unroll
+    for (int q = 0; q < kDpt; ++q) mine += tot[q];
+    uint32_t all;
+    uint32_t run0 = block_exclusive_sum<1024>(mine, s_tmp, &all);
+    uint32_t run[kDpt];
+#pragma unroll
+    for (int q = 0; q < kDpt; ++q) {
+      run[q] = run0;
+      run0 += tot[q];
+    }
+    for (int g = 0; g < groups; ++g)
+#pragma unroll
+      for (int q = 0; q < kDpt; ++q) {
+        uint32_t* p = group_tot + (int64_t)g * kBins + d0 + q;
+        const uint32_t c = *p;
+        *p = run[q];
+        run[q] += c;
+      }
   }
 }
 
@@ -235,20 +288,23 @@ __global__ __launch_bounds__(kRadix * kSgSub) void k_radix_scan_groups(
 // XCD, and workgroup b (on XCD b mod 8) walks its XCD's range with a stride of
 // grid / 8 (one tile each in an ordinary pass), loading the next tile's keys
 // while it writes the current tile's planes.
-template <bool kFromTuples, bool kWriteKeys, bool kModel, bool kLoop>
+template <class G, bool kFromTuples, bool kWriteKeys, bool kModel, bool kLoop>
 __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const TupleSrc ts, int key_word,
     uint32_t* __restrict__ keys_out, const Payload pay, int64_t n_host, const int32_t* n_dev,
     int shift, const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ group_start,
     int tiles_pad, const RadixExtra ex) {
+  constexpr int kItems = G::items;
+  constexpr int kTile = G::tile;
+  using WCnt = typename G::WCnt;
   // keys and staging; before the keys are placed, the model table lives here
-  __shared__ uint32_t s_buf[2 * kSortTile];
-  static_assert(2 * kSortTile >= kCdfSegments + 1, "model table fits the tile buffers");
+  __shared__ uint32_t s_buf[2 * kTile];
+  static_assert(2 * kTile >= kCdfSegments + 1, "model table fits the tile buffers");
   uint32_t* s_keys = s_buf;
-  uint32_t* s_stage = s_buf + kSortTile;
-  __shared__ uint32_t s_wcnt[kOsWaves][kRadix];
-  __shared__ uint32_t s_tile_excl[kRadix];
-  __shared__ uint32_t s_gbase[kRadix];
+  uint32_t* s_stage = s_buf + kTile;
+  __shared__ WCnt s_wcnt[kOsWaves][G::bins];
+  __shared__ uint32_t s_tile_excl[G::bins];
+  __shared__ uint32_t s_gbase[G::bins];
   __shared__ uint32_t s_tmp[kOsWaves + 1];
   if (gated_off(ex)) return;
 
@@ -259,11 +315,11 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
   ModelView mv{};
   const int range = tiles_pad / kXcds;
   const int xcd = blockIdx.x % kXcds, step = gridDim.x / kXcds;
-  uint32_t key[kOsItems], rank[kOsItems];
+  uint32_t key[kItems], rank[kItems];
   auto load_keys = [&](int tile) {
-    const int wb = tile * kSortTile + w * (kWave * kOsItems) + lane;
+    const int wb = tile * kTile + w * (kWave * kItems) + lane;
 #pragma unroll
-    for (int j = 0; j < kOsItems; ++j) {
+    for (int j = 0; j < kItems; ++j) {
       const int i = wb + j * kWave;
       key[j] = 0;
       if (i < n)
@@ -272,34 +328,34 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
     }
   };
   int lt = blockIdx.x / kXcds;
-  if (lt < range && (xcd * range + lt) * kSortTile < n) load_keys(xcd * range + lt);
+  if (lt < range && (xcd * range + lt) * kTile < n) load_keys(xcd * range + lt);
   for (; lt < range; lt += step) {
   const int tile = xcd * range + lt;
-  const int base = tile * kSortTile;
+  const int base = tile * kTile;
   if (base >= n) break;  // the XCD's later tiles lie further on
-  for (int q = tid; q < kOsWaves * kRadix; q += kOsThreads) (&s_wcnt[0][0])[q] = 0;
+  for (int q = tid; q < kOsWaves * G::bins; q += kOsThreads) (&s_wcnt[0][0])[q] = 0;
   if constexpr (kModel) mv = load_model(ex, reinterpret_cast<float*>(s_buf));
-  // global start of this tile's run of digit tid
-  if (tid < kRadix)
-    s_gbase[tid] = cnt[(int64_t)tile * kRadix + tid] +
-                   group_start[(int64_t)(tile / kScanGroup) * kRadix + tid];
-  const int wbase = base + w * (kWave * kOsItems) + lane;
+  // global start of this tile's run of every digit
+  for (int d = tid; d < G::bins; d += kOsThreads)
+    s_gbase[d] = cnt[(int64_t)tile * G::bins + d] +
+                 group_start[(int64_t)(tile / kScanGroup) * G::bins + d];
+  const int wbase = base + w * (kWave * kItems) + lane;
   __syncthreads();
   // learned digits: rank by bucket (the raw key travels as a payload plane)
   if (kModel) {
 #pragma unroll
-    for (int j = 0; j < kOsItems; ++j) key[j] = model_bucket(mv, key[j]);
+    for (int j = 0; j < kItems; ++j) key[j] = model_bucket(mv, key[j]);
   }
 
   const uint64_t below = lanes_below_mask();
 #pragma unroll
-  for (int j = 0; j < kOsItems; ++j) {
+  for (int j = 0; j < kItems; ++j) {
     const int i = wbase + j * kWave;
     const bool valid = i < n;
-    const uint32_t d = (key[j] >> shift) & 0xFF;
+    const uint32_t d = (key[j] >> shift) & G::mask;
     uint64_t m = __ballot(valid);
 #pragma unroll
-    for (int b = 0; b < kRadixBits; ++b) {
+    for (int b = 0; b < G::bits; ++b) {
       const bool bit = (d >> b) & 1;
       const uint64_t bb = __ballot(bit);
       m &= bit ? bb : ~bb;
@@ -308,33 +364,48 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
     if (valid) pre = s_wcnt[w][d];
     __builtin_amdgcn_wave_barrier();
     const uint32_t before = popc64(m & below);
-    if (valid && before == 0) s_wcnt[w][d] = pre + popc64(m);
+    if (valid && before == 0) s_wcnt[w][d] = (WCnt)(pre + popc64(m));
     __builtin_amdgcn_wave_barrier();
     rank[j] = pre + before;
   }
   __syncthreads();
 
-  // threads below 256 own one digit each: wave bases and the tile count
+  // the first G::owners threads own G::dpt consecutive digits each: wave
+  // bases (exclusive over the waves, in place) and the tile's counts
+  uint32_t own[G::dpt];
   uint32_t tile_cnt = 0;
-  if (tid < kRadix) {
+  if (tid < G::owners) {
 #pragma unroll
-    for (int q = 0; q < kOsWaves; ++q) {
-      const uint32_t c = s_wcnt[q][tid];
-      s_wcnt[q][tid] = tile_cnt;
-      tile_cnt += c;
+    for (int q = 0; q < G::dpt; ++q) {
+      const int d = tid * G::dpt + q;
+      uint32_t c_d = 0;
+#pragma unroll
+      for (int v = 0; v < kOsWaves; ++v) {
+        const uint32_t c = s_wcnt[v][d];
+        s_wcnt[v][d] = (WCnt)c_d;
+        c_d += c;
+      }
+      own[q] = c_d;
+      tile_cnt += c_d;
     }
   }
   uint32_t total;
-  const uint32_t texcl = block_exclusive_sum<kOsThreads>(tile_cnt, s_tmp, &total);
-  if (tid < kRadix) s_tile_excl[tid] = texcl;
+  uint32_t texcl = block_exclusive_sum<kOsThreads>(tile_cnt, s_tmp, &total);
+  if (tid < G::owners) {
+#pragma unroll
+    for (int q = 0; q < G::dpt; ++q) {
+      s_tile_excl[tid * G::dpt + q] = texcl;
+      texcl += own[q];
+    }
+  }
   __syncthreads();
 
   // local (tile-sorted) slot of every item
 #pragma unroll
-  for (int j = 0; j < kOsItems; ++j) {
+  for (int j = 0; j < kItems; ++j) {
     const int i = wbase + j * kWave;
     if (i < n) {
-      const uint32_t d = (key[j] >> shift) & 0xFF;
+      const uint32_t d = (key[j] >> shift) & G::mask;
       rank[j] = s_tile_excl[d] + s_wcnt[w][d] + rank[j];
       s_keys[rank[j]] = key[j];
     }
@@ -342,15 +413,15 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
   __syncthreads();
 
   // global destination of every tile-sorted slot this thread writes out
-  const int tile_n = min(n - base, kSortTile);
-  int dest[kOsItems];
+  const int tile_n = min(n - base, kTile);
+  int dest[kItems];
 #pragma unroll
-  for (int j = 0; j < kOsItems; ++j) {
+  for (int j = 0; j < kItems; ++j) {
     const int i = tid + j * kOsThreads;
     dest[j] = -1;
     if (i < tile_n) {
       const uint32_t kk = s_keys[i];
-      const uint32_t d = (kk >> shift) & 0xFF;
+      const uint32_t d = (kk >> shift) & G::mask;
       const int g = (int)s_gbase[d] + (i - (int)s_tile_excl[d]);
       if (g >= 0 && g < n)
         dest[j] = g;
@@ -361,28 +432,28 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
   }
   // the next tile's keys load while this tile's planes are written
   if constexpr (kLoop)
-    if (lt + step < range && (xcd * range + lt + step) * kSortTile < n) load_keys(xcd * range + lt + step);
+    if (lt + step < range && (xcd * range + lt + step) * kTile < n) load_keys(xcd * range + lt + step);
 
   // payload planes: the next plane's values are loaded before the current
   // one is written out
-  uint32_t nxt[kOsItems];
+  uint32_t nxt[kItems];
   if (pay.count > 0) {
 #pragma unroll
-    for (int j = 0; j < kOsItems; ++j) {
+    for (int j = 0; j < kItems; ++j) {
       const int i = wbase + j * kWave;
       nxt[j] = i < n ? plane_value(pay.p[0], ts, i) : 0u;
     }
   }
   for (int q = 0; q < pay.count; ++q) {
 #pragma unroll
-    for (int j = 0; j < kOsItems; ++j) {
+    for (int j = 0; j < kItems; ++j) {
       const int i = wbase + j * kWave;
       if (i < n) s_stage[rank[j]] = nxt[j];
     }
     if (q + 1 < pay.count) {
       const Plane pn = pay.p[q + 1];
 #pragma unroll
-      for (int j = 0; j < kOsItems; ++j) {
+      for (int j = 0; j < kItems; ++j) {
         const int i = wbase + j * kWave;
         nxt[j] = i < n ? plane_value(pn, ts, i) : 0u;
       }
@@ -390,7 +461,7 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
     __syncthreads();
     uint32_t* out = pay.p[q].out;
 #pragma unroll
-    for (int j = 0; j < kOsItems; ++j) {
+    for (int j = 0; j < kItems; ++j) {
       if (dest[j] >= 0) out[dest[j]] = s_stage[tid + j * kOsThreads];
     }
     __syncthreads();
@@ -400,12 +471,12 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
   }
 }
 
-hipError_t launch_radix_pass(const uint32_t* keys_in, const TupleSrc& ts, int key_word,
-                             uint32_t* keys_out, const Payload& pay_in, int64_t n,
-                             const int32_t* n_dev, int shift, uint32_t* cnt, uint32_t* group_tot,
-                             hipStream_t st, const RadixExtra& ex) {
-  if (n <= 0) return hipSuccess;
-  const int tiles = (int)((n + kSortTile - 1) / kSortTile);
+template <class G>
+hipError_t radix_pass_g(const uint32_t* keys_in, const TupleSrc& ts, int key_word,
+                        uint32_t* keys_out, const Payload& pay_in, int64_t n,
+                        const int32_t* n_dev, int shift, uint32_t* cnt, uint32_t* group_tot,
+                        hipStream_t st, const RadixExtra& ex) {
+  const int tiles = (int)((n + G::tile - 1) / G::tile);
   const int groups = (tiles + kScanGroup - 1) / kScanGroup;
   const bool ft = keys_in == nullptr;
   const bool md = ex.model != nullptr;
@@ -426,8 +497,8 @@ hipError_t launch_radix_pass(const uint32_t* keys_in, const TupleSrc& ts, int ke
   const int cgrid = gated && tiles > kGatedGrid ? kGatedGrid : tiles;
   const int tiles_pad = xcd_grid(tiles);
   const int sgrid = gated && tiles_pad > kGatedGrid ? kGatedGrid : tiles_pad;
-#define KD_RC(FT, MD)                                                                   \
-  hipLaunchKernelGGL((k_radix_count<FT, MD>), dim3(cgrid), dim3(kOsThreads), 0, st, keys_in, \
+#define KD_RC(FT, MD)                                                                           \
+  hipLaunchKernelGGL((k_radix_count<G, FT, MD>), dim3(cgrid), dim3(kOsThreads), 0, st, keys_in, \
                      ts, key_word, n, n_dev, shift, cnt, ex)
   if (ft) {
     if (md) KD_RC(true, true); else KD_RC(true, false);
@@ -435,20 +506,19 @@ hipError_t launch_radix_pass(const uint32_t* keys_in, const TupleSrc& ts, int ke
     if (md) KD_RC(false, true); else KD_RC(false, false);
   }
 #undef KD_RC
-  hipLaunchKernelGGL(k_radix_scan_tiles, dim3(groups), dim3(kRadix), 0, st, cnt, group_tot, tiles,
-                     ex);
-  hipLaunchKernelGGL(k_radix_scan_groups, dim3(1), dim3(kRadix * kSgSub), 0, st, group_tot, groups,
-                     ex);
-#define KD_RS(FT, WK, MD)                                                                       \
-  do {                                                                                          \
-    if (gated)                                                                                  \
-      hipLaunchKernelGGL((k_radix_scatter<FT, WK, MD, true>), dim3(sgrid), dim3(kOsThreads), 0, st, \
-                         keys_in, ts, key_word, keys_out, pay, n, n_dev, shift, cnt, group_tot,      \
-                         tiles_pad, ex);                                                        \
-    else                                                                                        \
-      hipLaunchKernelGGL((k_radix_scatter<FT, WK, MD, false>), dim3(sgrid), dim3(kOsThreads), 0,    \
-                         st, keys_in, ts, key_word, keys_out, pay, n, n_dev, shift, cnt, group_tot,  \
-                         tiles_pad, ex);                                                        \
+  hipLaunchKernelGGL(k_radix_scan_tiles<G::bins>, dim3(groups, G::bins / 256), dim3(256), 0, st, cnt,
+                     group_tot, tiles, ex);
+  hipLaunchKernelGGL(k_radix_scan_groups<G::bins>, dim3(1), dim3(1024), 0, st, group_tot, groups, ex);
+#define KD_RS(FT, WK, MD)                                                                        \
+  do {                                                                                           \
+    if (gated)                                                                                   \
+      hipLaunchKernelGGL((k_radix_scatter<G, FT, WK, MD, true>), dim3(sgrid), dim3(kOsThreads), 0, \
+                         st, keys_in, ts, key_word, keys_out, pay, n, n_dev, shift, cnt,         \
+                         group_tot, tiles_pad, ex);                                              \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_radix_scatter<G, FT, WK, MD, false>), dim3(sgrid), dim3(kOsThreads), \
+                         0, st, keys_in, ts, key_word, keys_out, pay, n, n_dev, shift, cnt,      \
+                         group_tot, tiles_pad, ex);                                              \
   } while (0)
   const bool wk = keys_out != nullptr;
   if (md) {
@@ -460,6 +530,29 @@ hipError_t launch_radix_pass(const uint32_t* keys_in, const TupleSrc& ts, int ke
   }
 #undef KD_RS
   return hipGetLastError();
+}
+
+hipError_t launch_radix_pass(const uint32_t* keys_in, const TupleSrc& ts, int key_word,
+                             uint32_t* keys_out, const Payload& pay_in, int64_t n,
+                             const int32_t* n_dev, int shift, uint32_t* cnt, uint32_t* group_tot,
+                             hipStream_t st, const RadixExtra& ex) {
+  if (n <= 0) return hipSuccess;
+  // learned (model) passes run with the default geometry
+  const int bits = ex.model ? 8 : ex.bits;
+  const int items = ex.model ? 8 : ex.items;
+  if (bits == 8 && items == 8)
+    return radix_pass_g<Geom<8, 8>>(keys_in, ts, key_word, keys_out, pay_in, n, n_dev, shift, cnt,
+                                    group_tot, st, ex);
+  if (bits == 8 && items == 16)
+    return radix_pass_g<Geom<8, 16>>(keys_in, ts, key_word, keys_out, pay_in, n, n_dev, shift, cnt,
+                                     group_tot, st, ex);
+  if (bits == 11 && items == 8)
+    return radix_pass_g<Geom<11, 8>>(keys_in, ts, key_word, keys_out, pay_in, n, n_dev, shift, cnt,
+                                     group_tot, st, ex);
+  if (bits == 11 && items == 16)
+    return radix_pass_g<Geom<11, 16>>(keys_in, ts, key_word, keys_out, pay_in, n, n_dev, shift, cnt,
+                                      group_tot, st, ex);
+  return hipErrorInvalidValue;
 }
 
 // ---- word-0-first order of array 0 ------------------------------------------

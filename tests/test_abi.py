@@ -101,7 +101,13 @@ def test_build_rejects_bad_arguments(L):
     o.level = 5  # 0 .. 4
     assert call_build(L, opts=ctypes.byref(o)) == -1
     o.level = 0
-    o.reserved[2] = 1  # reserved words must be zero
+    o.digit_bits = 10  # 8 or 11
+    assert call_build(L, opts=ctypes.byref(o)) == -1
+    o.digit_bits = 0
+    o.sort_tile = 2048  # 4096 or 8192
+    assert call_build(L, opts=ctypes.byref(o)) == -1
+    o.sort_tile = 0
+    o.reserved[0] = 1  # reserved words must be zero
     assert call_build(L, opts=ctypes.byref(o)) == -1
 
 

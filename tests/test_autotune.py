@@ -57,3 +57,17 @@ def test_level_forms_of_the_plain_form(at):
     assert sum(c["level"] == 3 for c in big) == len(at.CANDIDATES)
     assert all("level" not in c for c in at.candidates_for("batched", 8))
     assert all("level" not in c for c in at.candidates_for("learned", 8))
+
+
+def test_coordinate_order_covers_every_knob(at):
+    """Coordinate descent sweeps the level form (plain), the cutover, the
+    finish grid, the record completion, the radix digit width and tile size,
+    and (learned) the learned sorts; each knob's first value is its default."""
+    plain = dict(at.coordinate_order("plain", 3))
+    assert plain["digit_bits"] == (8, 11) and plain["sort_tile"] == (4096, 8192)
+    assert plain["level"] == (4, 1) and plain["cutover"][0] == 1024
+    assert "level" not in dict(at.coordinate_order("batched", 3))
+    assert "learned_sorts" in dict(at.coordinate_order("learned", 3))
+    assert 3 in dict(at.coordinate_order("plain", 6))["level"]
+    for name, vals in at.coordinate_order("learned", 8):
+        assert len(set(vals)) == len(vals) >= 2, name

@@ -267,11 +267,11 @@ def test_c5_full_size_plain(kd):
 
 # ---- batched form ---------------------------------------------------------------
 
-def assert_batched_same(kd, t, offsets, cutover=None, level=None):
+def assert_batched_same(kd, t, offsets, cutover=None, level=None, **knobs):
     print(f"[gpu case] batched trees={len(offsets) - 1} rows={offsets[-1]} k={t.shape[1]} "
-          f"dtype={t.dtype} cutover={cutover} level={level}", flush=True)
+          f"dtype={t.dtype} cutover={cutover} level={level} {knobs}", flush=True)
     perm, nu = kd.build_batched(torch.from_numpy(np.ascontiguousarray(t)).cuda(), offsets,
-                                cutover=cutover, level=level)
+                                cutover=cutover, level=level, **knobs)
     torch.cuda.synchronize()
     perm = perm.cpu().numpy()
     nu = nu.cpu().numpy()
