@@ -319,6 +319,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip the learned and batched forms")
     ap.add_argument("--no-tune", action="store_true", help="use the default knobs instead of autotuning")
+    ap.add_argument("--knobs", type=str, default=None,
+                    help="JSON object of build knobs for the plain build (no autotuning), e.g. the "
+                         "config a tuned run reported, so a profiled run repeats it")
     ap.add_argument("--no-queries", action="store_true", help="skip the tree searches on the C2 tree")
     ap.add_argument("--no-select", action="store_true",
                     help="skip the comparison builder's k sweep on the C3 inputs")
@@ -345,6 +348,9 @@ def main():
     tuned = None
     if args.cutover:
         knobs = {"cutover": args.cutover, "leaf_blocks": None, "records": None}
+    elif args.knobs:
+        knobs = {"cutover": None, "leaf_blocks": None, "records": None}
+        knobs.update(json.loads(args.knobs))
     elif args.no_tune:
         knobs = {"cutover": None, "leaf_blocks": None, "records": None}
     else:

@@ -936,7 +936,6 @@ __device__ bool lds_radix_sort(uint32_t* ka, uint16_t* va, uint32_t* kb, uint16_
   const int tid = threadIdx.x;
   const int w = tid / kWave;
   const int lane = tid % kWave;
-  const uint64_t below = lanes_below_mask();
   bool flipped = false;
   for (int ps = 0; ps < passes; ++ps) {
     const int shift = ps * kRadixBits;
@@ -952,17 +951,11 @@ __device__ bool lds_radix_sort(uint32_t* ka, uint16_t* va, uint32_t* kb, uint16_
       key[j] = valid ? ka[e] : 0u;
       val[j] = valid ? va[e] : (uint16_t)0;
       const uint32_t d = (key[j] >> shift) & 0xFF;
-      uint64_t m = __ballot(valid);
-#pragma unroll
-      for (int b = 0; b < kRadixBits; ++b) {
-        const bool bit = (d >> b) & 1;
-        const uint64_t bb = __ballot(bit);
-        m &= bit ? bb : ~bb;
-      }
+      const uint64_t m = same_digit_lanes<kRadixBits>(d, kRadixBits, __ballot(valid));
       uint32_t pre = 0;
       if (valid) pre = s_cnt[w][d];
       __builtin_amdgcn_wave_barrier();
-      const uint32_t before = popc64(m & below);
+      const uint32_t before = lanes_below(m);
       if (valid && before == 0) s_cnt[w][d] = pre + popc64(m);
       __builtin_amdgcn_wave_barrier();
       rank[j] = pre + before;

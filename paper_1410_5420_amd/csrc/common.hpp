@@ -21,6 +21,33 @@ __device__ __forceinline__ uint64_t lanes_below_mask() {
 
 __device__ __forceinline__ uint32_t popc64(uint64_t m) { return (uint32_t)__popcll(m); }
 
+// Set lanes of m below this lane (two mbcnt steps, no mask of lanes below).
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Lanes of `among` whose digit (the low `bits` bits of d) equals this lane's.
+// A compare per bit gives the lanes having that bit set; where that set
+// disagrees with this lane's own bit (taken as 0 or all ones), a lane holds
+// another digit, so the disagreements ORed over the bits mark every lane to
+// drop: two 32-bit logic ops per bit and half besides the compare.  All 64
+// lanes must be active.  kMax bounds `bits` (a compile-time count unrolls
+// fully; a smaller run-time count skips the later bits).
+template <int kMax>
+__device__ __forceinline__ uint64_t same_digit_lanes(uint32_t d, int bits, uint64_t among) {
+  uint32_t lo = 0u, hi = 0u;
+#pragma unroll
+  for (int b = 0; b < kMax; ++b) {
+    if (b < bits) {
+      const uint32_t s = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
+      const uint64_t bb = __builtin_amdgcn_uicmp(s, 0u, 33);  // lanes where s != 0
+      lo |= (uint32_t)bb ^ s;
+      hi |= (uint32_t)(bb >> 32) ^ s;
+    }
+  }
+  return among & ~(((uint64_t)hi << 32) | lo);
+}
+
 // Inclusive prefix sum across the 64 lanes of a wave through DPP lane moves:
 // shifts by 1, 2, 4 and 8 within each row of 16 lanes, then the last lane of
 // row r added to row r+1 and the last lane of row 1 to rows 2 and 3.  All 64

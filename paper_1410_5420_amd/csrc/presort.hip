@@ -353,17 +353,11 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
     const int i = wbase + j * kWave;
     const bool valid = i < n;
     const uint32_t d = (key[j] >> shift) & G::mask;
-    uint64_t m = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < G::bits; ++b) {
-      const bool bit = (d >> b) & 1;
-      const uint64_t bb = __ballot(bit);
-      m &= bit ? bb : ~bb;
-    }
+    const uint64_t m = same_digit_lanes<G::bits>(d, G::bits, __ballot(valid));
     uint32_t pre = 0;
     if (valid) pre = s_wcnt[w][d];
     __builtin_amdgcn_wave_barrier();
-    const uint32_t before = popc64(m & below);
+    const uint32_t before = lanes_below(m);
     if (valid && before == 0) s_wcnt[w][d] = (WCnt)(pre + popc64(m));
     __builtin_amdgcn_wave_barrier();
     rank[j] = pre + before;

@@ -461,7 +461,6 @@ struct ChunkLds {
 // One stable LSD pass of 8-bit digit `shift` over (ka, va) -> (kb, vb).
 __device__ void chunk_pass(ChunkLds& L, int N, int shift) {
   const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
-  const uint64_t below = lanes_below_mask();
   for (int q = tid; q < kSelWaves * 256; q += kSelThreads) (&L.cnt[0][0])[q] = 0;
   __syncthreads();
   uint32_t key[kSelItems], rank[kSelItems];
@@ -473,17 +472,11 @@ __device__ void chunk_pass(ChunkLds& L, int N, int shift) {
     key[j] = valid ? L.ka[e] : 0u;
     val[j] = valid ? L.va[e] : (uint16_t)0;
     const uint32_t d = (key[j] >> shift) & 0xFF;
-    uint64_t m = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1;
-      const uint64_t bb = __ballot(bit);
-      m &= bit ? bb : ~bb;
-    }
+    const uint64_t m = same_digit_lanes<8>(d, 8, __ballot(valid));
     uint32_t pre = 0;
     if (valid) pre = L.cnt[w][d];
     __builtin_amdgcn_wave_barrier();
-    const uint32_t before = popc64(m & below);
+    const uint32_t before = lanes_below(m);
     if (valid && before == 0) L.cnt[w][d] = pre + popc64(m);
     __builtin_amdgcn_wave_barrier();
     rank[j] = pre + before;

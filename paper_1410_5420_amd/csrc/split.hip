@@ -311,7 +311,6 @@ __global__ __launch_bounds__(kSpThreads) void k_split_count(const Bufs Bf, const
     ps[q] = s_si.s[q];
     pe[q] = s_si.e[q];
   }
-  const uint64_t below = lanes_below_mask();
   // one piece in the tile (the usual case): no piece search, and for up to
   // three levels the node ranks in registers
   const bool single = np == 1 && sl <= 3;
@@ -340,13 +339,8 @@ __global__ __launch_bounds__(kSpThreads) void k_split_count(const Bufs Bf, const
     kw[it / K::kPerWord] |= kk << (K::kBits * (it % K::kPerWord));
     // the last piece's buckets: one LDS add per distinct bucket of a wave
     const bool last = b != kDrop && pc == np - 1;
-    uint64_t m = __ballot(last);
-    for (int bit = 0; bit < sl; ++bit) {
-      const bool on = (b >> bit) & 1u;
-      const uint64_t bb = __ballot(on);
-      m &= on ? bb : ~bb;
-    }
-    if (last && popc64(m & below) == 0) atomicAdd(&s_hist[b], popc64(m));
+    const uint64_t m = same_digit_lanes<W>(b, sl, __ballot(last));
+    if (last && lanes_below(m) == 0) atomicAdd(&s_hist[b], popc64(m));
   }
   {
     uint32_t* kp = keys + ((int64_t)t * kSpWaves + w) * K::kWords * kWave + lane;
@@ -521,21 +515,15 @@ __global__ __launch_bounds__(kSpThreads) void k_split_move(const Bufs Bf, const 
   }
   const int kbits = np * B > 1 ? 32 - __clz((uint32_t)(np * B) - 1u) : 1;  // bits of the largest key
   uint32_t rank[kSpItems];
-  const uint64_t below = lanes_below_mask();
 #pragma unroll
   for (int it = 0; it < kSpItems; ++it) {
     const uint32_t kk = key[it];
     const bool valid = kk != kNoKey;
-    uint64_t m = __ballot(valid);
-    for (int bit = 0; bit < kbits; ++bit) {
-      const bool on = (kk >> bit) & 1u;
-      const uint64_t bb = __ballot(on);
-      m &= on ? bb : ~bb;
-    }
+    const uint64_t m = same_digit_lanes<8>(kk, kbits, __ballot(valid));
     uint32_t pre = 0;
     if (valid) pre = s_wcnt[w][kk & 0xFF];
     __builtin_amdgcn_wave_barrier();
-    const uint32_t before = popc64(m & below);
+    const uint32_t before = lanes_below(m);
     if (valid && before == 0) s_wcnt[w][kk & 0xFF] = pre + popc64(m);
     __builtin_amdgcn_wave_barrier();
     rank[it] = pre + before;
