@@ -71,13 +71,6 @@ __device__ __forceinline__ Plan split_plan(const SplitJob& J) {
   return P;
 }
 
-// Planes holding the ranks the walk from depth `from` to `to` compares.
-__device__ __forceinline__ uint32_t deciding_planes(int q, int from, int to, int k) {
-  uint32_t m = 0;
-  for (int l = from; l < to; ++l) m |= 1u << plane_of(q, l % k, k);
-  return m;
-}
-
 // Subarray of depth `depth` holding position pos of a tree of nu positions:
 // its range and index (left to right), or e < s when pos is the node of a
 // shallower subarray.
@@ -143,22 +136,18 @@ __device__ __forceinline__ uint32_t walk_planes(int q, int from, int s_levels) {
 }
 
 // Bucket of an element (its subtree sl levels down, 0 .. 2^sl - 1), or kDrop
-// when it is one of the nodes passed on the way.  v: its record planes;
-// planes: walk_planes().  Branch-free, so the walks of a thread's elements
-// interleave: after a node is met the remaining steps run on harmlessly.
+// when it is one of the nodes passed on the way.  xv[l]: its rank in the order
+// compared at level l of the walk.  Branch-free, so the walks of a thread's
+// elements interleave: after a node is met the remaining steps run on
+// harmlessly.
 template <int W>
-__device__ __forceinline__ uint32_t walk(const uint32_t (&v)[W], const uint32_t* s_med_piece,
-                                         uint32_t planes, int sl) {
+__device__ __forceinline__ uint32_t walk(const uint32_t (&xv)[W], const uint32_t* s_med_piece, int sl) {
   uint32_t h = 1;
   bool node = false;
 #pragma unroll
   for (int l = 0; l < W; ++l) {
     if (l < sl) {
-      const int pl = (int)((planes >> (3 * l)) & 7u);
-      uint32_t r = 0;
-#pragma unroll
-      for (int c = 0; c < W; ++c)
-        if (c == pl) r = v[c];
+      const uint32_t r = xv[l];
       const uint32_t nr = s_med_piece[h];
       node = node || r == nr;
       h = 2 * h + (r > nr ? 1u : 0u);
@@ -179,34 +168,64 @@ __device__ __forceinline__ void descend(int& s, int& e, uint32_t b, int sl) {
   }
 }
 
-// The same walk for a tile inside one piece, at most three levels deep: the
+// The same walk for a tile inside one piece, kSl <= 3 levels deep: the
 // seven node ranks below the piece are the same for every element (m[h],
 // heap order), so they sit in registers and each step picks one of them.
-template <int W>
-__device__ __forceinline__ uint32_t walk3(const uint32_t (&v)[W], const uint32_t (&m)[8],
-                                          uint32_t planes, int sl) {
+template <int W, int kSl>
+__device__ __forceinline__ uint32_t walk3(const uint32_t (&xv)[W], const uint32_t (&m)[8]) {
   uint32_t h = 1;
   bool node = false;
 #pragma unroll
-  for (int l = 0; l < 3; ++l) {
-    if (l < sl) {
-      const int pl = (int)((planes >> (3 * l)) & 7u);
-      uint32_t r = 0;
-#pragma unroll
-      for (int c = 0; c < W; ++c)
-        if (c == pl) r = v[c];
-      uint32_t nr;
-      if (l == 0)
-        nr = m[1];
-      else if (l == 1)
-        nr = h == 2 ? m[2] : m[3];
-      else
-        nr = h == 4 ? m[4] : (h == 5 ? m[5] : (h == 6 ? m[6] : m[7]));
-      node = node || r == nr;
-      h = 2 * h + (r > nr ? 1u : 0u);
-    }
+  for (int l = 0; l < kSl; ++l) {
+    const uint32_t r = xv[l];
+    uint32_t nr;
+    if (l == 0)
+      nr = m[1];
+    else if (l == 1)
+      nr = h == 2 ? m[2] : m[3];
+    else
+      nr = h == 4 ? m[4] : (h == 5 ? m[5] : (h == 6 ? m[6] : m[7]));
+    node = node || r == nr;
+    h = 2 * h + (r > nr ? 1u : 0u);
   }
-  return node ? kDrop : h - (1u << sl);
+  return node ? kDrop : h - (1u << kSl);
+}
+
+// The elements of a tile inside one piece, walked kSl levels: keys packed
+// into kw, bucket counts by wave ballots summed in scalar registers and added
+// to s_hist once per wave.
+template <int W, int kSl, int kBits, int kPerWord, int kWords>
+__device__ __forceinline__ void count_single(const uint32_t (&x)[W][kSpItems], const uint32_t* s_med,
+                                             int t0, int t1, int ps0, int pe0, int w, int lane,
+                                             uint32_t (&kw)[kWords], uint32_t* s_hist) {
+  constexpr int kB = 1 << kSl;
+  constexpr uint32_t kNone = (1u << kBits) - 1u;
+  uint32_t m1[8];
+#pragma unroll
+  for (int h = 0; h < 8; ++h) m1[h] = h >= 1 && h < kB ? s_med[h] : 0u;
+  // a tile wholly inside the piece needs no per-element test; otherwise a
+  // node of a shallower depth may open or close the tile
+  const bool whole = ps0 <= t0 && pe0 >= t1 - 1;
+  uint32_t hc[kB];
+#pragma unroll
+  for (int bb = 0; bb < kB; ++bb) hc[bb] = 0u;
+#pragma unroll
+  for (int it = 0; it < kSpItems; ++it) {
+    const int i = t0 + w * (kWave * kSpItems) + it * kWave + lane;
+    uint32_t xv[W];
+#pragma unroll
+    for (int l = 0; l < W; ++l) xv[l] = x[l][it];
+    const bool in = i < t1 && (whole || (i >= ps0 && i <= pe0));
+    const uint32_t b = in ? walk3<W, kSl>(xv, m1) : kDrop;
+    kw[it / kPerWord] |= (b == kDrop ? kNone : b) << (kBits * (it % kPerWord));
+#pragma unroll
+    for (int bb = 0; bb < kB; ++bb) hc[bb] += popc64(__ballot(b == (uint32_t)bb));
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int bb = 0; bb < kB; ++bb)
+      if (hc[bb] != 0u) atomicAdd(&s_hist[bb], hc[bb]);
+  }
 }
 
 // Key of an element for the move: piece << sl | bucket, below 256 (pieces
@@ -242,6 +261,10 @@ __device__ __forceinline__ int piece_of(int i, const int (&ps)[kSpMaxPieces],
 // counts of every bucket among the tile's last piece (tval[b][t]) and the
 // tile's flags (bit 0: that piece starts inside the tile; bit 1: the first
 // piece started before it), with the pieces kept for the move (info[t]).
+// The usual tile lies inside one piece and walks at most three levels: its
+// node ranks sit in registers and its bucket counts are wave ballots summed in
+// scalar registers; other tiles search each element's piece and count with a
+// digit match.
 template <int W>
 __global__ __launch_bounds__(kSpThreads) void k_split_count(const Bufs Bf, const SplitJob J,
                                                            SplitInfo* __restrict__ info,
@@ -264,18 +287,18 @@ __global__ __launch_bounds__(kSpThreads) void k_split_count(const Bufs Bf, const
   const int sl = P.to - P.from;
   const int B = 1 << sl;
   constexpr int k = W + 1;
-  const uint32_t dmask = deciding_planes(P.q, P.from, P.to, k);
   const uint32_t planes = walk_planes<k>(P.q, P.from, sl);
   const uint32_t* src = buf_of(Bf, P.moves) + record_offset(P.q, k, J.n);
-  // planes first: their loads overlap the piece search
-  uint32_t v[W][kSpItems];
+  // the compared planes, in walk order, first: their loads overlap the piece search
+  uint32_t x[W][kSpItems];
 #pragma unroll
-  for (int c = 0; c < W; ++c) {
-    const bool need = (dmask >> c) & 1u;
+  for (int l = 0; l < W; ++l) {
+    const bool need = l < sl;
+    const int pl = (int)((planes >> (3 * l)) & 7u);
 #pragma unroll
     for (int it = 0; it < kSpItems; ++it) {
       const int i = t0 + w * (kWave * kSpItems) + it * kWave + lane;
-      v[c][it] = need && i < t1 ? src[(int64_t)c * J.n + i] : 0u;
+      x[l][it] = need && i < t1 ? src[(int64_t)pl * J.n + i] : 0u;
     }
   }
   // the pieces and the medians below them, without waiting for the planes
@@ -311,36 +334,34 @@ __global__ __launch_bounds__(kSpThreads) void k_split_count(const Bufs Bf, const
     ps[q] = s_si.s[q];
     pe[q] = s_si.e[q];
   }
-  // one piece in the tile (the usual case): no piece search, and for up to
-  // three levels the node ranks in registers
-  const bool single = np == 1 && sl <= 3;
   uint32_t kw[K::kWords];
 #pragma unroll
   for (int j = 0; j < K::kWords; ++j) kw[j] = 0u;
-  uint32_t m1[8];
-#pragma unroll
-  for (int h = 0; h < 8; ++h) m1[h] = single && h >= 1 && h < B ? s_med[h] : 0u;
-#pragma unroll
-  for (int it = 0; it < kSpItems; ++it) {
-    const int i = t0 + w * (kWave * kSpItems) + it * kWave + lane;
-    int pc;
-    uint32_t b = kDrop;
-    uint32_t x[W];
-#pragma unroll
-    for (int c = 0; c < W; ++c) x[c] = v[c][it];
-    if (single) {  // a node of a shallower depth may still open or close the tile
-      pc = (i < t1 && i >= ps[0] && i <= pe[0]) ? 0 : -1;
-      if (pc == 0) b = walk3<W>(x, m1, planes, sl);
-    } else {
-      pc = i < t1 ? piece_of(i, ps, pe, np) : -1;
-      if (pc >= 0) b = walk<W>(x, s_med + pc * kSpMaxBuckets, planes, sl);
+  if (np == 1 && sl <= 3) {
+    if (sl == 1)
+      count_single<W, 1, K::kBits, K::kPerWord, K::kWords>(x, s_med, t0, t1, ps[0], pe[0], w, lane, kw, s_hist);
+    else if constexpr (W >= 2) {
+      if (sl == 2)
+        count_single<W, 2, K::kBits, K::kPerWord, K::kWords>(x, s_med, t0, t1, ps[0], pe[0], w, lane, kw, s_hist);
+      else if constexpr (W >= 3)
+        count_single<W, 3, K::kBits, K::kPerWord, K::kWords>(x, s_med, t0, t1, ps[0], pe[0], w, lane, kw, s_hist);
     }
-    const uint32_t kk = b == kDrop ? K::kNone : (((uint32_t)pc << sl) | b);
-    kw[it / K::kPerWord] |= kk << (K::kBits * (it % K::kPerWord));
-    // the last piece's buckets: one LDS add per distinct bucket of a wave
-    const bool last = b != kDrop && pc == np - 1;
-    const uint64_t m = same_digit_lanes<W>(b, sl, __ballot(last));
-    if (last && lanes_below(m) == 0) atomicAdd(&s_hist[b], popc64(m));
+  } else {
+#pragma unroll
+    for (int it = 0; it < kSpItems; ++it) {
+      const int i = t0 + w * (kWave * kSpItems) + it * kWave + lane;
+      uint32_t xv[W];
+#pragma unroll
+      for (int l = 0; l < W; ++l) xv[l] = x[l][it];
+      const int pc = i < t1 ? piece_of(i, ps, pe, np) : -1;
+      const uint32_t b = pc >= 0 ? walk<W>(xv, s_med + pc * kSpMaxBuckets, sl) : kDrop;
+      const uint32_t kk = b == kDrop ? K::kNone : (((uint32_t)pc << sl) | b);
+      kw[it / K::kPerWord] |= kk << (K::kBits * (it % K::kPerWord));
+      // the last piece's buckets: one LDS add per distinct bucket of a wave
+      const bool last = b != kDrop && pc == np - 1;
+      const uint64_t m = same_digit_lanes<W>(b, sl, __ballot(last));
+      if (last && lanes_below(m) == 0) atomicAdd(&s_hist[b], popc64(m));
+    }
   }
   {
     uint32_t* kp = keys + ((int64_t)t * kSpWaves + w) * K::kWords * kWave + lane;
