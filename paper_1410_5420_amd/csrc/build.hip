@@ -989,6 +989,87 @@ __device__ bool lds_radix_sort(uint32_t* ka, uint16_t* va, uint32_t* kb, uint16_
   return flipped;
 }
 
+// Local ids of the subarray of N elements at s0 (cutover depth lc): an
+// element's local id is its position in array 0 (sorted by order 0).
+// Array 1 stores the order-0 rank of each of its elements (plane k-2);
+// sorting those ranks gives array 0's order, hence every array-1 element's
+// local id, and the sorted list lets the other arrays find theirs by binary
+// search.  On return s_r0[id] is the order-0 rank of id and s_lid[j * C + i]
+// the id at position i of array j (the row ids are read at the end at the
+// order-0 ranks).  No barrier after the last writes.
+template <int kItems, int R, int kForm>
+__device__ void leaf_local_ids(const RecBufs& B, const Forest& F, int64_t n, int lc, int N, int s0,
+                               uint32_t* s_r0, uint16_t* s_lid, uint32_t (*s_cnt)[kRadix],
+                               uint32_t* s_dbase, uint32_t* s_tmp) {
+  constexpr int k = R + 1;
+  constexpr int C = kItems * kLfThreads;
+  const int tid = threadIdx.x;
+  const uint32_t* a1 = leaf_array<kForm>(B, lc, 1, k, n);
+  uint32_t* sk = reinterpret_cast<uint32_t*>(s_lid);        // sort scratch (aliases s_lid)
+  uint16_t* sv = reinterpret_cast<uint16_t*>(sk + C);
+  uint16_t* sv2 = sv + C;
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    const int i = it * kLfThreads + tid;
+    if (i < N) {
+      s_r0[i] = a1[(int64_t)(k - 2) * n + s0 + i];
+      sv2[i] = (uint16_t)i;
+    }
+  }
+  __syncthreads();
+  int passes = 1;
+  const uint32_t total = (uint32_t)F.uoff[F.B];
+  while (passes < 4 && ((uint64_t)(total - 1) >> (8 * passes)) != 0) ++passes;
+  const bool in_b = lds_radix_sort<kItems>(s_r0, sv2, sk, sv, N, passes, s_cnt, s_dbase, s_tmp);
+  // sorted ranks must end in s_r0; the array-1 positions they came from in regs
+  uint16_t from[kItems];
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    const int i = it * kLfThreads + tid;
+    if (i < N) {
+      from[it] = in_b ? sv[i] : sv2[i];
+      if (in_b) s_r0[i] = sk[i];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    const int i = it * kLfThreads + tid;
+    if (i < N) {
+      s_lid[i] = (uint16_t)i;                 // array 0
+      s_lid[1 * C + from[it]] = (uint16_t)i;  // array 1
+    }
+  }
+  // the other arrays: lower bound of each order-0 rank among the sorted ones,
+  // by halving steps taken for all of a thread's items at once
+  int top = 1;
+  while (2 * top <= N) top *= 2;
+  for (int j = 2; j < k; ++j) {
+    const uint32_t* aj = leaf_array<kForm>(B, lc, j, k, n);
+    const int c0 = k - 1 - j;  // plane of order 0 in array j
+    uint32_t x[kItems];
+    int pos[kItems];
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+      const int i = it * kLfThreads + tid;
+      x[it] = i < N ? aj[(int64_t)c0 * n + s0 + i] : 0u;
+      pos[it] = 0;
+    }
+    for (int step = top; step > 0; step >>= 1) {
+#pragma unroll
+      for (int it = 0; it < kItems; ++it) {
+        const int cand = pos[it] + step;  // ranks at 0 .. cand-1 all below x?
+        if (cand <= N && s_r0[cand - 1] < x[it]) pos[it] = cand;
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+      const int i = it * kLfThreads + tid;
+      if (i < N) s_lid[j * C + i] = (uint16_t)(pos[it] < N ? pos[it] : N - 1);
+    }
+  }
+}
+
 template <int kItems, int R, int kForm>
 __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Forest F, int64_t n,
                                                     int /* k: R + 1 */, int32_t* __restrict__ perm) {
@@ -1036,69 +1117,7 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
   if (N <= 0) continue;
   s0 += tbase;
 
-  // Local id of an element = its position in array 0 (sorted by order 0).
-  // Array 1 stores the order-0 rank of each of its elements (plane k-2);
-  // sorting those ranks gives array 0's order, hence every array-1 element's
-  // local id, and the sorted list lets the other arrays find theirs by binary
-  // search.  The row ids are read at the end at the order-0 ranks.
-  {
-    const uint32_t* a1 = leaf_array<kForm>(B, lc, 1, k, n);
-    uint32_t* sk = reinterpret_cast<uint32_t*>(s_lid);        // sort scratch (aliases s_lid)
-    uint16_t* sv = reinterpret_cast<uint16_t*>(sk + C);
-    uint16_t* sv2 = sv + C;
-#pragma unroll
-    for (int it = 0; it < kItems; ++it) {
-      const int i = it * kLfThreads + tid;
-      if (i < N) {
-        s_r0[i] = a1[(int64_t)(k - 2) * n + s0 + i];
-        sv2[i] = (uint16_t)i;
-      }
-    }
-    __syncthreads();
-    int passes = 1;
-    const uint32_t total = (uint32_t)F.uoff[F.B];
-    while (passes < 4 && ((uint64_t)(total - 1) >> (8 * passes)) != 0) ++passes;
-    const bool in_b = lds_radix_sort<kItems>(s_r0, sv2, sk, sv, N, passes, s_cnt, s_dbase, s_tmp);
-    // sorted ranks must end in s_r0; the array-1 positions they came from in regs
-    uint16_t from[kItems];
-#pragma unroll
-    for (int it = 0; it < kItems; ++it) {
-      const int i = it * kLfThreads + tid;
-      if (i < N) {
-        from[it] = in_b ? sv[i] : sv2[i];
-        if (in_b) s_r0[i] = sk[i];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < kItems; ++it) {
-      const int i = it * kLfThreads + tid;
-      if (i < N) {
-        s_lid[i] = (uint16_t)i;                 // array 0
-        s_lid[1 * C + from[it]] = (uint16_t)i;  // array 1
-      }
-    }
-    for (int j = 2; j < k; ++j) {
-      const uint32_t* aj = leaf_array<kForm>(B, lc, j, k, n);
-      const int c0 = k - 1 - j;  // plane of order 0 in array j
-#pragma unroll
-      for (int it = 0; it < kItems; ++it) {
-        const int i = it * kLfThreads + tid;
-        if (i < N) {
-          const uint32_t x = aj[(int64_t)c0 * n + s0 + i];
-          int lo = 0, hi = N;  // lower bound of x among the sorted order-0 ranks
-          while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (s_r0[mid] < x)
-              lo = mid + 1;
-            else
-              hi = mid;
-          }
-          s_lid[j * C + i] = (uint16_t)(lo < N ? lo : N - 1);
-        }
-      }
-    }
-  }
+  leaf_local_ids<kItems, R, kForm>(B, F, n, lc, N, s0, s_r0, s_lid, s_cnt, s_dbase, s_tmp);
 
   // Position i = it * kLfThreads + tid is owned by one thread for the whole
   // phase, so its subarray (s | e << 16, or a hole) lives in registers.
