@@ -452,6 +452,38 @@ __global__ __launch_bounds__(1024) void k_split_scan(const SplitJob J,
   }
 }
 
+// Stable rank of every element of a wave among the wave's elements of its
+// key, for keys below kNk: one ballot per key value and item, the wave's
+// running count per key in scalar registers, written to wcnt[0 .. kNk) once.
+// Elements whose key is kNk or more (not moving) get no rank.
+template <int kNk>
+__device__ __forceinline__ void rank_few_keys(const uint32_t (&key)[kSpItems], int lane,
+                                              uint32_t (&rank)[kSpItems], uint32_t* wcnt) {
+  uint32_t run[kNk];
+#pragma unroll
+  for (int q = 0; q < kNk; ++q) run[q] = 0u;
+#pragma unroll
+  for (int it = 0; it < kSpItems; ++it) {
+    const uint32_t kk = key[it];
+    uint64_t mine = 0;
+    uint32_t base = 0;
+#pragma unroll
+    for (int q = 0; q < kNk; ++q) {
+      const uint64_t mq = __ballot(kk == (uint32_t)q);
+      if (kk == (uint32_t)q) {
+        mine = mq;
+        base = run[q];
+      }
+      run[q] += popc64(mq);
+    }
+    rank[it] = base + lanes_below(mine);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < kNk; ++q) wcnt[q] = run[q];
+  }
+}
+
 // Moves one tile: every element's key (from the count), its stable rank
 // among the tile's elements of that key (wave ballots, as in a radix pass),
 // and the start of its subtree plus the carried count give its new position;
@@ -534,20 +566,26 @@ __global__ __launch_bounds__(kSpThreads) void k_split_move(const Bufs Bf, const 
     s_base[tid] = base_q;
     s_end[tid] = end_q;
   }
-  const int kbits = np * B > 1 ? 32 - __clz((uint32_t)(np * B) - 1u) : 1;  // bits of the largest key
   uint32_t rank[kSpItems];
+  if (np * B <= 4) {
+    rank_few_keys<4>(key, lane, rank, s_wcnt[w]);
+  } else if (np * B <= 8) {
+    rank_few_keys<8>(key, lane, rank, s_wcnt[w]);
+  } else {
+    const int kbits = 32 - __clz((uint32_t)(np * B) - 1u);  // bits of the largest key
 #pragma unroll
-  for (int it = 0; it < kSpItems; ++it) {
-    const uint32_t kk = key[it];
-    const bool valid = kk != kNoKey;
-    const uint64_t m = same_digit_lanes<8>(kk, kbits, __ballot(valid));
-    uint32_t pre = 0;
-    if (valid) pre = s_wcnt[w][kk & 0xFF];
-    __builtin_amdgcn_wave_barrier();
-    const uint32_t before = lanes_below(m);
-    if (valid && before == 0) s_wcnt[w][kk & 0xFF] = pre + popc64(m);
-    __builtin_amdgcn_wave_barrier();
-    rank[it] = pre + before;
+    for (int it = 0; it < kSpItems; ++it) {
+      const uint32_t kk = key[it];
+      const bool valid = kk != kNoKey;
+      const uint64_t m = same_digit_lanes<8>(kk, kbits, __ballot(valid));
+      uint32_t pre = 0;
+      if (valid) pre = s_wcnt[w][kk & 0xFF];
+      __builtin_amdgcn_wave_barrier();
+      const uint32_t before = lanes_below(m);
+      if (valid && before == 0) s_wcnt[w][kk & 0xFF] = pre + popc64(m);
+      __builtin_amdgcn_wave_barrier();
+      rank[it] = pre + before;
+    }
   }
   __syncthreads();
   // waves before this one, per key
