@@ -215,3 +215,30 @@ def test_level_plan_rejects_bad_arguments(L):
     assert L.lib.kd_level_plan(3, -1, lm, fm) == -1
     assert L.lib.kd_level_plan(3, 31, lm, fm) == -4
     assert L.lib.kd_level_plan(3, 3, lm, None) == -1
+
+
+@pytest.mark.parametrize("k,n", [(3, 2000), (5, 1500)])
+def test_replay_catches_a_dropped_plane(L, k, n):
+    """The replay is a check of the plan, not a copy of it: a level whose write
+    mask loses one plane that a later split or the finish reads must fail."""
+    t = kdgen.uniform_int(n, k, -1000, 1000, 0.0, 777 + k)
+    want = oracle.build_tree(t, children=False)
+    C = 4
+    host_levels = cutover_depth(want["n_unique"], C)
+    lm, fm = L.level_plan(k, host_levels)
+    caught = 0
+    for lv in range(1, host_levels):
+        for c in range(k - 1):
+            if not (lm[lv] >> c) & 1:
+                continue
+            bad = list(lm)
+            bad[lv] &= ~(1 << c)
+            try:
+                perm, _ = replay(t, C, host_levels, bad, fm)
+            except AssertionError:
+                caught += 1
+                continue
+            # a plane nobody reads again may be dropped harmlessly, but then
+            # the tree must still be right
+            assert np.array_equal(perm, want["perm"])
+    assert caught > 0
