@@ -951,9 +951,12 @@ __global__ __launch_bounds__(1024) void k_scan_counts(uint32_t* __restrict__ cnt
   if (tid == 0) *total = (int32_t)s_carry;
 }
 
+// K = k at compile time: every plane of a thread's positions is loaded once,
+// together, and the same registers decide the kept rows and are written out.
+template <int K>
 __global__ __launch_bounds__(kDdThreads) void k_dedup_write(
     const uint32_t* __restrict__ w0, const uint32_t* __restrict__ planes,
-    const uint32_t* __restrict__ tree, int n, int k, const uint32_t* __restrict__ cnt,
+    const uint32_t* __restrict__ tree, int n, const uint32_t* __restrict__ cnt,
     uint32_t* __restrict__ out_ids, uint32_t* __restrict__ out_words, int64_t out_stride,
     uint32_t* __restrict__ out_tree, int32_t* __restrict__ uoff) {
   __shared__ uint32_t s_chunk[kDdItems * kDdWaves];
@@ -962,11 +965,32 @@ __global__ __launch_bounds__(kDdThreads) void k_dedup_write(
   const int lane = tid % kWave;
   const int base = blockIdx.x * kSortTile;
   if (base >= n) return;
+  uint32_t id[kDdItems], key[kDdItems], prev[kDdItems];
+  uint32_t wd[K > 1 ? K - 1 : 1][kDdItems];
+#pragma unroll
+  for (int j = 0; j < kDdItems; ++j) {
+    const int i = base + j * kDdThreads + tid;
+    const bool in = i < n;
+    id[j] = in ? planes[i] : 0u;
+    key[j] = in ? w0[i] : 0u;
+    prev[j] = in && i > 0 ? w0[i - 1] : ~key[j];
+#pragma unroll
+    for (int d = 1; d < K; ++d) wd[d - 1][j] = in ? planes[(int64_t)d * n + i] : 0u;
+  }
   uint32_t keep[kDdItems], within[kDdItems];
 #pragma unroll
   for (int j = 0; j < kDdItems; ++j) {
     const int i = base + j * kDdThreads + tid;
-    keep[j] = (i < n && keep_row(w0, planes, tree, n, k, i)) ? 1u : 0u;
+    bool k1 = false;
+    if (i < n) {
+      k1 = i == 0 || key[j] != prev[j];
+      if (!k1 && tree) k1 = tree[i] != tree[i - 1];
+      if (!k1) {  // equal first words (rare): compare the others with the row before
+#pragma unroll
+        for (int d = 1; d < K; ++d) k1 = k1 || wd[d - 1][j] != planes[(int64_t)d * n + i - 1];
+      }
+    }
+    keep[j] = k1 ? 1u : 0u;
     const uint32_t inc = wave_inclusive_sum(keep[j]);
     within[j] = inc - keep[j];
     if (lane == kWave - 1) s_chunk[j * kDdWaves + wv] = inc;
@@ -984,8 +1008,9 @@ __global__ __launch_bounds__(kDdThreads) void k_dedup_write(
     const int i = base + j * kDdThreads + tid;
     const int o = (int)(gb + s_chunk[j * kDdWaves + wv] + within[j]);
     if (!keep[j] || o >= n) continue;
-    out_ids[o] = planes[i];
-    for (int d = 1; d < k; ++d) out_words[(d - 1) * out_stride + o] = planes[(int64_t)d * n + i];
+    out_ids[o] = id[j];
+#pragma unroll
+    for (int d = 1; d < K; ++d) out_words[(d - 1) * out_stride + o] = wd[d - 1][j];
     if (tree) {
       const uint32_t b = tree[i];
       out_tree[o] = b;
@@ -1005,8 +1030,21 @@ hipError_t launch_dedup(const uint32_t* w0, const uint32_t* planes, const uint32
   hipLaunchKernelGGL(k_dedup_count, dim3(tiles), dim3(kDdThreads), 0, st, w0, planes, tree, (int)n,
                      k, cnt);
   hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, cnt, tiles, uoff + num_trees);
-  hipLaunchKernelGGL(k_dedup_write, dim3(tiles), dim3(kDdThreads), 0, st, w0, planes, tree, (int)n,
-                     k, cnt, out_ids, out_words, out_stride, out_tree, uoff);
+#define KD_DW(KK)                                                                                \
+  hipLaunchKernelGGL(k_dedup_write<KK>, dim3(tiles), dim3(kDdThreads), 0, st, w0, planes, tree,    \
+                     (int)n, cnt, out_ids, out_words, out_stride, out_tree, uoff)
+  switch (k) {
+    case 1: KD_DW(1); break;
+    case 2: KD_DW(2); break;
+    case 3: KD_DW(3); break;
+    case 4: KD_DW(4); break;
+    case 5: KD_DW(5); break;
+    case 6: KD_DW(6); break;
+    case 7: KD_DW(7); break;
+    case 8: KD_DW(8); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef KD_DW
   return hipGetLastError();
 }
 
@@ -1151,27 +1189,48 @@ constexpr int kPlaceTile = 1 << kPlaceBits;
 
 __global__ __launch_bounds__(512) void k_place(const uint32_t* __restrict__ key, const PlaceArgs pa,
                                               const int32_t* total, uint32_t* status) {
+  constexpr int kItems = kPlaceTile / 512;
   extern __shared__ uint32_t s_val[];  // [nv][kPlaceTile]
   const int nu = *total;
   const int base = blockIdx.x * kPlaceTile;
   if (base >= nu) return;
   const int cnt = min(nu - base, kPlaceTile);
-  for (int p = (int)threadIdx.x; p < cnt; p += 512) {
-    const uint32_t slot = key[base + p] - (uint32_t)base;
-    if (slot >= (uint32_t)cnt) {  // not a permutation: the counts were inconsistent
+  // every position's slot, then each plane's values, loaded for all of a
+  // thread's positions at once
+  uint32_t slot[kItems];
+#pragma unroll
+  for (int q = 0; q < kItems; ++q) {
+    const int p = (int)threadIdx.x + q * 512;
+    slot[q] = p < cnt ? key[base + p] - (uint32_t)base : 0xFFFFFFFFu;
+  }
+#pragma unroll
+  for (int q = 0; q < kItems; ++q) {
+    const int p = (int)threadIdx.x + q * 512;
+    if (p < cnt && slot[q] >= (uint32_t)cnt) {  // not a permutation: the counts were inconsistent
       atomicOr(status, kStatusPlace);
-      continue;
+      slot[q] = 0xFFFFFFFFu;
+    }
+  }
+  for (int v = 0; v < pa.nv; ++v) {
+    const uint32_t* src = pa.val[v] + base;
+    uint32_t val[kItems];
+#pragma unroll
+    for (int q = 0; q < kItems; ++q) {
+      const int p = (int)threadIdx.x + q * 512;
+      val[q] = p < cnt ? src[p] : 0u;
     }
 #pragma unroll
-    for (int v = 0; v < kMaxK; ++v)
-      if (v < pa.nv) s_val[v * kPlaceTile + slot] = pa.val[v][base + p];
+    for (int q = 0; q < kItems; ++q)
+      if (slot[q] < (uint32_t)cnt) s_val[v * kPlaceTile + slot[q]] = val[q];
   }
   __syncthreads();
-#pragma unroll
-  for (int v = 0; v < kMaxK; ++v) {
-    if (v >= pa.nv) continue;
+  for (int v = 0; v < pa.nv; ++v) {
     uint32_t* d = pa.dst[v] + base;
-    for (int p = (int)threadIdx.x; p < cnt; p += 512) d[p] = s_val[v * kPlaceTile + p];
+#pragma unroll
+    for (int q = 0; q < kItems; ++q) {
+      const int p = (int)threadIdx.x + q * 512;
+      if (p < cnt) d[p] = s_val[v * kPlaceTile + p];
+    }
   }
 }
 
