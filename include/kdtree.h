@@ -104,6 +104,16 @@ typedef struct kd_options {
  * 2 <= k <= KD_MAX_K, 0 <= levels <= 30. */
 int kd_level_plan(int32_t k, int32_t levels, uint32_t* h_level_mask, uint32_t* h_final_mask);
 
+/* The plan of level forms 1 and 3 (host only, diagnostic; no device work):
+ * h_masks[L] (levels words) = the record planes each array's move writes at
+ * global level L, 8 bits per array (bits 8j .. 8j+7 for array j, bit c of
+ * them = plane c); h_moves[d * k + j] ((levels + 1) * k words) = the number
+ * of moves array j has taken before depth d, which decides the buffer that
+ * holds its layout there.  defer = 1 for the deferred partitioning (form 3),
+ * 0 for form 1.  2 <= k <= KD_MAX_K, 0 <= levels <= 30; KD_EINVAL on null
+ * pointers or a bad defer. */
+int kd_level_masks(int32_t k, int32_t levels, int32_t defer, uint64_t* h_masks, int32_t* h_moves);
+
 /* Human-readable name of a status code (static string). */
 const char* kd_strerror(int code);
 

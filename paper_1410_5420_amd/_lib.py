@@ -48,6 +48,9 @@ def _load():
     u32p = ctypes.POINTER(ctypes.c_uint32)
     lib.kd_level_plan.argtypes = [i32, i32, u32p, u32p]
     lib.kd_level_plan.restype = ctypes.c_int
+    lib.kd_level_masks.argtypes = [i32, i32, i32, ctypes.POINTER(ctypes.c_uint64),
+                                   ctypes.POINTER(ctypes.c_int32)]
+    lib.kd_level_masks.restype = ctypes.c_int
     lib.kdtree_workspace_bytes.argtypes = [i64, i32, i32, ctypes.POINTER(sz)]
     lib.kdtree_workspace_bytes.restype = ctypes.c_int
     lib.kdtree_build.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp, vp, sz, opt, vp]
@@ -107,7 +110,7 @@ def _load():
 lib = _load()
 
 # Every symbol include/kdtree.h declares (the tests check the library exports them).
-EXPORTED = ["kd_strerror", "kd_status", "kd_level_plan", "kdtree_workspace_bytes", "kdtree_build",
+EXPORTED = ["kd_strerror", "kd_status", "kd_level_plan", "kd_level_masks", "kdtree_workspace_bytes", "kdtree_build",
             "kdtree_build_noalloc", "kdtree_presort",
             "kdtree_partition", "kdtree_build_select", "kdtree_workspace_bytes_batched",
             "kdtree_build_batched",
@@ -154,6 +157,16 @@ def level_plan(k: int, levels: int):
     fm = (ctypes.c_uint32 * k)()
     check(lib.kd_level_plan(k, levels, lm, fm), "kd_level_plan")
     return [int(lm[i]) for i in range(levels)], [int(fm[j]) for j in range(k)]
+
+
+def level_masks(k: int, levels: int, defer: int):
+    """(write masks per level, moves per (depth, array)) of level forms 1 and
+    3 (kd_level_masks, host only)."""
+    wm = (ctypes.c_uint64 * max(levels, 1))()
+    mv = (ctypes.c_int32 * ((levels + 1) * k))()
+    check(lib.kd_level_masks(k, levels, defer, wm, mv), "kd_level_masks")
+    return ([int(wm[i]) for i in range(levels)],
+            [[int(mv[d * k + j]) for j in range(k)] for d in range(levels + 1)])
 
 
 def check(rc: int, what: str) -> None:

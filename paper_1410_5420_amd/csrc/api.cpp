@@ -929,6 +929,16 @@ int kd_level_plan(int32_t k, int32_t levels, uint32_t* h_level_mask, uint32_t* h
   return KD_OK;
 }
 
+int kd_level_masks(int32_t k, int32_t levels, int32_t defer, uint64_t* h_masks, int32_t* h_moves) {
+  if (k < 2 || levels < 0 || !h_moves || (levels > 0 && !h_masks) || (defer != 0 && defer != 1))
+    return KD_EINVAL;
+  if (k > KD_MAX_K || levels > 30) return KD_EUNSUPPORTED;
+  if (levels > 0) kd::level_write_masks(k, levels, h_masks, defer);
+  for (int d = 0; d <= levels; ++d)
+    for (int j = 0; j < k; ++j) h_moves[d * k + j] = kd::level_array_moves(defer, d, j, k);
+  return KD_OK;
+}
+
 int kd_status(const void* d_workspace, size_t workspace_bytes, uint32_t* h_bits, void* stream) {
   if (!d_workspace || !h_bits || !kd::aligned4(d_workspace)) return KD_EINVAL;
   if (workspace_bytes < 4 * (size_t)kd::kStatusWords) return KD_ENOMEM;

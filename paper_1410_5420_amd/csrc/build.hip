@@ -787,6 +787,8 @@ size_t level_seginfo_bytes() { return sizeof(SegInfo); }
 // deciding the side and every plane it writes.  An array with nothing to
 // write stays put and is not read.  Deferred, arrays j >= 2 write nothing
 // above depth j (their split writes every plane).
+int level_array_moves(int defer, int depth, int j, int k) { return array_moves(defer, depth, j, k); }
+
 void level_write_masks(int k, int levels, uint64_t* masks, int defer) {
   uint32_t need[kMaxK] = {};
   for (int j = 1; j < k; ++j) need[j] = 1u << (k - 1 - j);

@@ -174,6 +174,8 @@ hipError_t launch_level(const uint32_t* rec0, const uint32_t* rows, uint32_t* b1
 // The write masks of every global level of one tree with `levels` global
 // levels (element d for depth d); defer: deferred partitioning.
 void level_write_masks(int k, int levels, uint64_t* masks, int defer);
+// Moves array j has taken before `depth` (levels of form 1, or 3 with defer).
+int level_array_moves(int defer, int depth, int j, int k);
 // Deferred partitioning of one tree (defer = 1 in launch_level and
 // launch_leaf): node_rank (2^(k-1) - 1 words) receives the ranks of the nodes
 // of depth `depth` (<= k-2) once array `depth` has its depth layout; key[i]

@@ -1,4 +1,4 @@
-"""Layout rules of deferred partitioning (level form 3), on the CPU.
+"""Layout rules of level forms 1 and 3 (deferred partitioning), on the CPU.
 
 Two models of what the library computes, checked against definitions:
 - the bucket numbering of the split (Appendix, "Deferred Merge Sort and
@@ -9,8 +9,12 @@ Two models of what the library computes, checked against definitions:
   a depth (the plain count less j - 1 once array j is split, one write before
   that) must make every read of a level, of a split and of the on-chip finish
   find the layout of its depth with the planes it needs.
+Both rules are also read from the compiled library (kd_level_masks) and
+replayed from there, so the model and the library cannot drift apart.
 """
 import random
+
+import pytest
 
 
 def moves_before(depth, j, k):
@@ -50,8 +54,18 @@ def write_masks(k, levels, defer):
     return masks
 
 
-def replay(k, levels, deepest, defer):
-    """Every read finds the layout of its depth with the planes it needs."""
+def replay(k, levels, deepest, defer, plan=None):
+    """Every read finds the layout of its depth with the planes it needs.
+    plan: (masks, moves[depth][j]) to replay instead of this file's rules
+    (the compiled library's, from kd_level_masks)."""
+    if plan is not None:
+        lib_masks, lib_moves = plan
+
+        def array_moves(defer_, d, j, k_):  # noqa: F811
+            return lib_moves[d][j]
+    else:
+        lib_masks = None
+        array_moves = globals()["array_moves"]
     state = {(0, j): (0, 0xFF) for j in range(k)}  # (buffer, array) -> (depth, planes)
     have_nodes = set()
 
@@ -64,7 +78,7 @@ def replay(k, levels, deepest, defer):
         assert all(x in have_nodes for x in range(depth))
         state[(1, j)] = (depth, 0xFF)
 
-    masks = write_masks(k, levels, defer) if levels else []
+    masks = lib_masks if lib_masks is not None else (write_masks(k, levels, defer) if levels else [])
     for d in range(levels):
         if defer and 2 <= d < k:
             split(d)
@@ -97,6 +111,35 @@ def test_buffer_accounting():
                 replay(k, levels, deepest, 0)
                 if k >= 3:
                     replay(k, levels, deepest, 1)
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1410_5420_amd import _lib
+
+    return _lib
+
+
+def test_rules_equal_the_compiled_plan(L):
+    """The rules above are the library's own (kd_level_masks: the host's
+    write masks and the move count that picks each array's buffer)."""
+    for k in range(2, 9):
+        for levels in range(0, 21):
+            for defer in ((0, 1) if k >= 3 else (0,)):
+                masks, moves = L.level_masks(k, levels, defer)
+                assert masks == (write_masks(k, levels, defer) if levels else []), (k, levels, defer)
+                for d in range(levels + 1):
+                    for j in range(k):
+                        assert moves[d][j] == array_moves(defer, d, j, k), (k, levels, defer, d, j)
+
+
+def test_buffer_accounting_of_the_compiled_plan(L):
+    for k in range(2, 9):
+        for levels in range(0, 18):
+            for defer in ((0, 1) if k >= 3 else (0,)):
+                plan = L.level_masks(k, levels, defer)
+                for deepest in range(0, levels + 1):
+                    replay(k, levels, deepest, defer, plan)
 
 
 def test_buffer_accounting_catches_a_wrong_count():
@@ -159,3 +202,16 @@ def test_bucket_split_equals_level_partition():
                     assert max(bucket(ranks, node_rank, x, D) for x in range(nu)) <= 254
                     for s, e, _ in subs:
                         assert got[s:e + 1] == arrays[j][s:e + 1], (seed, k, j, D)
+
+
+def test_level_masks_rejects_bad_arguments(L):
+    import ctypes
+
+    wm = (ctypes.c_uint64 * 32)()
+    mv = (ctypes.c_int32 * 512)()
+    assert L.lib.kd_level_masks(1, 3, 0, wm, mv) == -1
+    assert L.lib.kd_level_masks(3, 3, 2, wm, mv) == -1
+    assert L.lib.kd_level_masks(3, 3, 0, wm, None) == -1
+    assert L.lib.kd_level_masks(3, 3, 0, None, mv) == -1
+    assert L.lib.kd_level_masks(9, 3, 0, wm, mv) == -4
+    assert L.lib.kd_level_masks(3, 31, 0, wm, mv) == -4
