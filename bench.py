@@ -614,10 +614,10 @@ def queries_c2(torch, kd, _lib, kdgen, t, t_host, perm, n_nodes, nu, args):
 
 def select_c3(torch, kd, kdgen, args):
     """The paper's comparison (its Fig. 7 varies k): the presort builder
-    against the per-level sorting builder on the C3 inputs (n = 2^22, 256
-    Gaussian clusters, 10% copies) for k in {2, 3, 4, 6, 8}, and the presort
-    builder with deferred partitioning (level form 3); all produce the same
-    tree, checked here."""
+    against the comparison builder (per-level median selection) on the C3
+    inputs (n = 2^22, 256 Gaussian clusters, 10% copies) for k in
+    {2, 3, 4, 6, 8}, and the presort builder with deferred partitioning
+    (level form 3); all produce the same tree, checked here."""
     res = {"workload": "C3: k in {2,3,4,6,8}, n=2^22 int32 from 256 Gaussian clusters "
                        "(sigma 2^12), 10% exact copies", "per_k": {}}
     reps = max(3, args.steps // 4)
@@ -643,7 +643,7 @@ def select_c3(torch, kd, kdgen, args):
                                 "ratio": round(sel_ms / plain_ms, 2),
                                 "same_tree": bool(same and dsame)}
         log(f"c3 k={k}: presort builder {plain_ms:.2f} ms, deferred partitioning {def_ms:.2f} ms, "
-            f"per-level sorting builder {sel_ms:.2f} ms, same={same} {dsame}")
+            f"per-level selection builder {sel_ms:.2f} ms, same={same} {dsame}")
         del b, db, sb, p1, p2, p3, t
         torch.cuda.empty_cache()
     return res

@@ -173,12 +173,15 @@ int kdtree_partition(const void* d_tuples, int64_t n, int32_t k, int32_t dtype, 
                      int32_t* d_lo, int32_t* d_hi, int64_t* d_n_unique, void* d_workspace,
                      size_t workspace_bytes, const kd_options* opts, void* stream);
 
-/* The same tree by the comparison method (Sec. 3: an O(n log n) builder that
- * finds every subarray's median afresh at each level instead of presorting
- * k times): array 0 is sorted by its super key and its duplicates removed as
- * in kdtree_build; then each level is one stable radix sort of the single
- * array of rows, within every subarray, by that level's super key, after
- * which every subarray's median sits at its middle position.  Arguments and
+/* The same tree by the comparison method (Sec. 3.1, "The O(n log n)
+ * Algorithm": every subarray's median is found afresh at each level and the
+ * subarray partitioned about it, instead of presorting k times): array 0 is
+ * sorted by its super key and its duplicates removed as in kdtree_build;
+ * then, at each level, an MSD radix-select by that level's super key finds
+ * every subarray's median (digit histograms, a stable three-way partition
+ * by the median's digit, the candidates finished by one workgroup each) and
+ * leaves the subarray partitioned with the median at its middle position;
+ * subarrays of at most 2048 rows are finished in LDS.  Arguments and
  * workspace as kdtree_build (no child positions).  The result equals
  * kdtree_build's; it is a cross-check built on none of the rank records or
  * partition kernels, and the timing baseline of the paper's comparison. */

@@ -329,9 +329,10 @@ def reverse_nearest(perm: torch.Tensor, n_nodes, near_rows: torch.Tensor, stream
 
 def build_select(tuples: torch.Tensor, stream=None, digit_bits: int | None = None,
                  sort_tile: int | None = None):
-    """The same tree by the comparison method (kdtree_build_select): a stable
-    radix sort of the rows within every subarray at each level instead of k
-    presorts and partitions.  Returns ``(perm, n_unique)`` like ``build``."""
+    """The same tree by the comparison method (kdtree_build_select): every
+    subarray's median selected afresh at each level (an MSD radix-select and
+    a three-way partition) instead of k presorts and partitions.  Returns
+    ``(perm, n_unique)`` like ``build``."""
     n, k = tuples.shape
     code = _dtype_code(tuples)
     nbytes = _lib.workspace_bytes(max(n, 1), k, code)
