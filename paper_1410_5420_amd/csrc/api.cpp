@@ -393,10 +393,18 @@ int presort_impl(const Job& J, hipStream_t st, bool first_only = false) {
   const TupleSrc ts{static_cast<const uint32_t*>(J.tuples), k, J.dtype == KD_F32 ? 1 : 0};
 
   t_status = at<uint32_t>(ws, L.status);
-  KD_TRY(launch_fill_u32(t_status, 0u, kStatusWords, st));
-  if (learned) KD_TRY(launch_fill_u32(at<uint32_t>(ws, L.flags), 0u, k, st));
-  KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(uoff), 0x7FFFFFFFu, B, st));
-  KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(uoff + B), 0u, 1, st));
+  {
+    // the status word, the learned sorts' fallback flags, the tree starts
+    // (empty until duplicate removal writes them) and the distinct count,
+    // and the tie step's run count and fallback flag
+    FillList init;
+    init.add(t_status, 0u, kStatusWords);
+    if (learned) init.add(at<uint32_t>(ws, L.flags), 0u, k);
+    init.add(reinterpret_cast<uint32_t*>(uoff), 0x7FFFFFFFu, B);
+    init.add(reinterpret_cast<uint32_t*>(uoff + B), 0u, 1);
+    init.add(at<uint32_t>(ws, L.ties) + kMaxTieRuns, 0u, 2);
+    KD_TRY(launch_fills(init, st));
+  }
   if (n > 0) {
     // Array 0: LSD over the words of x:y:z:..., least significant word first,
     // then (several trees) the tree id, which groups the rows by tree.
@@ -434,8 +442,7 @@ int presort_impl(const Job& J, hipStream_t st, bool first_only = false) {
                         J.sort_items);
       if (rc != KD_OK) return rc;
       int32_t* tl = at<int32_t>(ws, L.ties);
-      int32_t* tcount = tl + kMaxTieRuns;
-      KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(tcount), 0u, 2, st));  // count, flag
+      int32_t* tcount = tl + kMaxTieRuns;  // count, flag (cleared above)
       TieArgs ta{final_slot(k), B > 1 ? final_slot(k + 1) : nullptr, final_slot(0), k};
       KD_LAUNCH(KD_K_TIES, launch_ties(ta, n, tl, tcount, tcount + 1, st));
       gate = tcount + 1;
@@ -815,10 +822,12 @@ int single_job(Job& J, const void* tuples, int64_t n, int32_t k, int32_t dtype, 
   int64_t* d_off = at<int64_t>(ws, plan(n, k, 1).offs);
   J.d_off = d_off;
   if (upload) {
-    const uint32_t words[4] = {0u, 0u, (uint32_t)(n & 0xFFFFFFFF), (uint32_t)(n >> 32)};
-    KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(d_off), words[0], 2, st));
-    KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(d_off) + 2, words[2], 1, st));
-    KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(d_off) + 3, words[3], 1, st));
+    // {0, n} as 64-bit words
+    FillList f;
+    f.add(reinterpret_cast<uint32_t*>(d_off), 0u, 2);
+    f.add(reinterpret_cast<uint32_t*>(d_off) + 2, (uint32_t)(n & 0xFFFFFFFF), 1);
+    f.add(reinterpret_cast<uint32_t*>(d_off) + 3, (uint32_t)(n >> 32), 1);
+    KD_TRY(launch_fills(f, st));
   }
   return KD_OK;
 }

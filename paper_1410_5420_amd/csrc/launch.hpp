@@ -46,6 +46,25 @@ enum : uint32_t {
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t st);
 hipError_t launch_store_i64(int64_t* dst, const int64_t* src, hipStream_t st);
+// Several short runs of equal words written by one launch: the small
+// initialisations a build makes before its kernels (one launch instead of
+// one per run).
+constexpr int kMaxFills = 8;
+struct FillList {
+  uint32_t* p[kMaxFills];
+  uint32_t value[kMaxFills];
+  int32_t count[kMaxFills];
+  int n = 0;
+  void add(uint32_t* ptr, uint32_t v, int32_t c) {
+    p[n] = ptr;
+    value[n] = v;
+    count[n] = c;
+    ++n;
+  }
+};
+// Fails (hipErrorInvalidValue) if a run is null with a positive count or the
+// list holds more than kMaxFills runs.
+hipError_t launch_fills(const FillList& f, hipStream_t st);
 
 // Row-major tuples as a source of canonical (order-preserving unsigned) keys.
 struct TupleSrc {

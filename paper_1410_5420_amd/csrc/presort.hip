@@ -41,6 +41,28 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream
   return hipGetLastError();
 }
 
+// Run r of the list is written by the workgroups with blockIdx.y == r.
+__global__ __launch_bounds__(256) void k_fills(const FillList f) {
+  const int r = blockIdx.y;
+  uint32_t* p = f.p[r];
+  const uint32_t v = f.value[r];
+  const int c = f.count[r];
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < c; i += gridDim.x * 256) p[i] = v;
+}
+
+hipError_t launch_fills(const FillList& f, hipStream_t st) {
+  if (f.n < 0 || f.n > kMaxFills) return hipErrorInvalidValue;
+  int32_t most = 0;
+  for (int r = 0; r < f.n; ++r) {
+    if (f.count[r] > 0 && f.p[r] == nullptr) return hipErrorInvalidValue;
+    most = f.count[r] > most ? f.count[r] : most;
+  }
+  if (f.n == 0 || most <= 0) return hipSuccess;
+  const int gx = (int)((most + 255) / 256 < 64 ? (most + 255) / 256 : 64);
+  hipLaunchKernelGGL(k_fills, dim3(gx, f.n), dim3(256), 0, st, f);
+  return hipGetLastError();
+}
+
 hipError_t launch_store_i64(int64_t* dst, const int64_t* src, hipStream_t st) {
   hipLaunchKernelGGL(k_store_i64, dim3(1), dim3(64), 0, st, dst, src);
   return hipGetLastError();
@@ -1072,32 +1094,35 @@ __global__ __launch_bounds__(1024) void k_forest_finish(int32_t* __restrict__ uo
                                                        int64_t cutover, int64_t* n_unique,
                                                        int32_t* lmax, int32_t* wgbase,
                                                        int32_t* queue) {
-  __shared__ int32_t s_rmin[1024];
+  __shared__ int32_t s_wmin[1024 / kWave];
   __shared__ uint32_t s_tmp[1024 / kWave + 1];
   __shared__ int32_t s_lmax[1024 / kWave];
   __shared__ uint32_t s_carry;
   const int tid = threadIdx.x;
+  const int lane = (int)lane_id(), w = tid / kWave;
   // Empty trees (still marked INT32_MAX) start where the next tree starts:
   // every start becomes the minimum over itself and all later trees (starts of
   // non-empty trees increase with the tree index).  Thread t owns a range of
-  // `per` trees: local suffix minima, then one thread chains the ranges.
+  // `per` trees: local minima, a suffix minimum over the ranges (lanes, then
+  // waves), then local suffix minima.
   const int per = (B + 1023) / 1024;
   const int r0 = tid * per, r1 = min(B, r0 + per);
   int32_t m = INT32_MAX;
   for (int b = r1 - 1; b >= r0; --b) m = min(m, uoff[b]);
-  s_rmin[tid] = m;
-  __syncthreads();
-  if (tid == 0) {
-    int32_t run = uoff[B];
-    for (int q = 1023; q >= 0; --q) {
-      const int32_t here = min(s_rmin[q], run);
-      s_rmin[q] = run;  // minimum over all trees after range q
-      run = here;
-    }
+  int32_t incl = m;  // minimum over the ranges of this lane and the lanes above it
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int32_t o = __shfl_down(incl, d, kWave);
+    if (lane + d < kWave) incl = min(incl, o);
   }
+  if (lane == 0) s_wmin[w] = incl;
   __syncthreads();
+  int32_t after = uoff[B];  // minimum over every range after this thread's
+  for (int q = w + 1; q < 1024 / kWave; ++q) after = min(after, s_wmin[q]);
+  const int32_t above = __shfl_down(incl, 1, kWave);
+  if (lane + 1 < kWave) after = min(after, above);
   {
-    int32_t run = s_rmin[tid];
+    int32_t run = after;
     for (int b = r1 - 1; b >= r0; --b) {
       run = min(run, uoff[b]);
       uoff[b] = run;

@@ -308,6 +308,22 @@ def test_batched_point_clouds(kd, cutover):
     assert_batched_same(kd, t, offsets, cutover=cutover)
 
 
+def test_batched_many_trees_with_empties(kd):
+    """3001 trees, many of them empty: at the first and last place, in runs,
+    and around the boundaries of the ranges and waves over which the tree
+    starts of empty trees are filled in (3 trees per thread's range here,
+    192 per wave)."""
+    g = kdgen.rng(4242)
+    B = 3001
+    sizes = g.integers(1, 40, size=B)
+    empty = [0, 1, 2, 3, 5, 6, 190, 191, 192, 383, 384, 959, 960, 961, 2879, 2880, 2999, 3000]
+    empty += list(range(600, 700))
+    sizes[np.array(empty)] = 0
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    t = g.integers(-50, 50, size=(int(offsets[-1]), 3)).astype(np.int32)
+    assert_batched_same(kd, t, offsets)
+
+
 def test_batched_single_tree_equals_plain(kd):
     t = kdgen.uniform_int(50000, 3, 0, 1000, 0.05, 8)
     assert_batched_same(kd, t, np.array([0, 50000], dtype=np.int64))
