@@ -38,7 +38,7 @@ int tree_digit_passes(int B) {
 // The learned presort appends its own regions, so the regions shared with the
 // plain build sit at the same offsets in both layouts.
 struct Layout {
-  size_t status, vbuf, carry, S, rec0, rec1, rec2;
+  size_t status, rsync, vbuf, carry, S, rec0, rec1, rec2;
   size_t rcnt, rgrp, dcnt, seginfo, lcnt, lcarry, lstat, ltick;
   size_t uoff, wgbase, lmax, queue, offs, ties, nodes;
   size_t med, sinfo, stval, stflag, scarry, skeys;  // level form 4
@@ -66,6 +66,7 @@ Layout plan(int64_t n, int k, int B, bool learned = false) {
     return at;
   };
   L.status = take(4 * kStatusWords);    // device status word, always at offset 0
+  L.rsync = take(4 * (size_t)radix_sync_words(nn));  // counters of the gated radix passes
   L.vbuf = take(4 * un * (k + 2) * 2);  // radix passes: two sets of k+2 quantity slots
   L.carry = take(4 * un * (k + 1));     // key words (and tree ids) handed between sorts
   L.S = take(4 * un);                   // row ids in order 0 (the deduplicated order-0 array)
@@ -202,6 +203,8 @@ struct Pass {
 // The status word of the build being enqueued (set by every entry point that
 // enqueues a build before its first launch; null outside builds).
 thread_local uint32_t* t_status = nullptr;
+// Its counters of the gated radix passes (cleared with the status word).
+thread_local uint32_t* t_sync = nullptr;
 
 int run_sort(std::vector<Quant>& q, const std::vector<Pass>& passes, const TupleSrc& ts, int64_t n,
              const int32_t* n_dev, uint32_t* vb, int slots, uint32_t* rcnt, uint32_t* rgrp,
@@ -209,6 +212,7 @@ int run_sort(std::vector<Quant>& q, const std::vector<Pass>& passes, const Tuple
   RadixExtra ex;
   ex.gate = gate;
   ex.status = t_status;
+  ex.sync = t_sync;
   ex.items = items;
   const size_t un = (size_t)n;
   auto slot = [&](int set, int i) { return vb + ((size_t)set * slots + i) * un; };
@@ -280,6 +284,7 @@ int learned_sort(std::vector<Quant> q, const LearnedSort& ls, const TupleSrc& ts
   KD_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(ls.flag), 0u, 1, st));
   RadixExtra ex;
   ex.status = t_status;
+  ex.sync = t_sync;
   ex.model = ls.model;
   ex.nb_bits = ls.nb_bits;
   // bucket passes: stable, keyed by the bucket's 8-bit digits, moving everything
@@ -393,16 +398,19 @@ int presort_impl(const Job& J, hipStream_t st, bool first_only = false) {
   const TupleSrc ts{static_cast<const uint32_t*>(J.tuples), k, J.dtype == KD_F32 ? 1 : 0};
 
   t_status = at<uint32_t>(ws, L.status);
+  t_sync = at<uint32_t>(ws, L.rsync);
   {
     // the status word, the learned sorts' fallback flags, the tree starts
     // (empty until duplicate removal writes them) and the distinct count,
-    // and the tie step's run count and fallback flag
+    // the tie step's run count and fallback flag, and the counters of the
+    // gated radix passes
     FillList init;
     init.add(t_status, 0u, kStatusWords);
     if (learned) init.add(at<uint32_t>(ws, L.flags), 0u, k);
     init.add(reinterpret_cast<uint32_t*>(uoff), 0x7FFFFFFFu, B);
     init.add(reinterpret_cast<uint32_t*>(uoff + B), 0u, 1);
     init.add(at<uint32_t>(ws, L.ties) + kMaxTieRuns, 0u, 2);
+    init.add(t_sync, 0u, (int32_t)radix_sync_words(n > 0 ? n : 1));
     KD_TRY(launch_fills(init, st));
   }
   if (n > 0) {

@@ -48,6 +48,27 @@ __device__ __forceinline__ uint64_t same_digit_lanes(uint32_t d, int bits, uint6
   return among & ~(((uint64_t)hi << 32) | lo);
 }
 
+// ---- hand-off between workgroups of one launch ---------------------------------
+// Each XCD has its own L2, and a device-scope fence on gfx950 writes back and
+// invalidates the whole L2, which costs about a microsecond per fence and
+// serialises per XCD.  Values that one workgroup hands to another within a
+// launch therefore travel by device-scope atomic loads and stores, which the
+// L2s keep coherent, and the waits below only order them around the
+// counter that signals the hand-off; no cache is flushed.
+__device__ __forceinline__ void store_dev(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t load_dev(uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// This thread's memory operations have completed (vmcnt 0) before any later
+// one: after the stores of a hand-off, before the signal.
+__device__ __forceinline__ void wait_memory_ops() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt 0; expcnt and lgkmcnt not waited on
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // Inclusive prefix sum across the 64 lanes of a wave through DPP lane moves:
 // shifts by 1, 2, 4 and 8 within each row of 16 lanes, then the last lane of
 // row r added to row r+1 and the last lane of row 1 to rows 2 and 3.  All 64

@@ -102,14 +102,20 @@ struct RadixExtra {
   uint32_t* status = nullptr;  // status word (kStatusRadix), or null
   int bits = 8;                // digit width: 8 or 11 (model passes always 8)
   int items = 8;               // keys per thread: 8 (tiles of 4096) or 16 (8192)
+  uint32_t* sync = nullptr;    // gated passes: radix_sync_words(n) counters, zero at first
 };
 
 // One stable LSD radix pass on the digit of width ex.bits at bit `shift`
 // (tiles of 512 * ex.items keys): per-tile digit counts, a
 // two-level scan and the scatter (four launches, no waiting between
-// workgroups).  The key of element i is keys_in[i], or (keys_in == nullptr)
-// the canonical word `key_word` of tuple row i.  keys_out may be null.  Every
-// payload plane travels with its key.  Elements: i < (n_dev ? *n_dev : n).
+// workgroups).  A gated pass, which usually does nothing, is two launches
+// instead: the count's last workgroups do the scans, signalled through the
+// ex.sync counters (required then: radix_sync_words(n) words, zero before a
+// workspace's first gated pass; every pass leaves them zero again, and
+// passes sharing them run one after another on one stream).  The key of
+// element i is keys_in[i], or (keys_in == nullptr) the canonical word
+// `key_word` of tuple row i.  keys_out may be null.  Every payload plane
+// travels with its key.  Elements: i < (n_dev ? *n_dev : n).
 // cnt: radix_count_words(n) words; group_tot: radix_group_words(n) words.
 hipError_t launch_radix_pass(const uint32_t* keys_in, const TupleSrc& ts, int key_word,
                              uint32_t* keys_out, const Payload& pay, int64_t n,
@@ -119,6 +125,7 @@ inline int64_t radix_tiles(int64_t n) { return (n + kSortTile - 1) / kSortTile; 
 // sized for every geometry: the smaller tile and the wider digit
 inline int64_t radix_count_words(int64_t n) { return radix_tiles(n) * kMaxBins; }
 inline int64_t radix_group_words(int64_t n) { return (radix_tiles(n) + 63) / 64 * kMaxBins; }
+inline int64_t radix_sync_words(int64_t n) { return 1 + (radix_tiles(n) + 63) / 64; }
 
 // Duplicate removal over the fully sorted order.  w0: sorted first key word;
 // planes: n-strided planes [id, w1, ..., w_{k-1}] in the same order.  Writes

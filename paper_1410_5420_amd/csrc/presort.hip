@@ -79,6 +79,8 @@ hipError_t launch_store_i64(int64_t* dst, const int64_t* src, hipStream_t st) {
 //   2. scan:    blocks of 64 tiles turn those into exclusive prefixes per digit
 //               (plus per-block totals), one block then scans the block
 //               totals and adds each digit's global start;
+//               in a gated pass (one that usually does nothing) the count's
+//               last workgroups do this instead, to save two launches;
 //   3. scatter: tile t ranks its elements stably (wave ballots), adds the
 //               offsets, stages keys and payload planes through LDS in output
 //               order and writes them out in runs.
@@ -145,55 +147,6 @@ __device__ __forceinline__ uint32_t model_bucket(const ModelView& m, uint32_t ke
 
 __device__ __forceinline__ bool gated_off(const RadixExtra& ex) {
   return ex.gate != nullptr && *ex.gate == 0;
-}
-
-// Workgroup b counts tiles b, b + grid, ... (one tile each in an ordinary
-// pass), loading the next tile's keys while it counts the current one.
-template <class G, bool kFromTuples, bool kModel>
-__global__ __launch_bounds__(kOsThreads) void k_radix_count(const uint32_t* __restrict__ keys_in,
-                                                           const TupleSrc ts, int key_word,
-                                                           int64_t n_host, const int32_t* n_dev,
-                                                           int shift, uint32_t* __restrict__ cnt,
-                                                           const RadixExtra ex) {
-  __shared__ uint32_t s_h[G::bins];
-  __shared__ float s_c[kModel ? kCdfSegments + 1 : 1];
-  if (gated_off(ex)) return;
-  const int tid = threadIdx.x;
-  ModelView mv{};
-  if constexpr (kModel) mv = load_model(ex, s_c);
-  const int n = (int)(n_dev ? *n_dev : n_host);
-  // every tile of the launch bound gets its row (zeros beyond the device count)
-  const int tiles = (int)((n_host + G::tile - 1) / G::tile);
-  uint32_t key[G::items];
-  auto load = [&](int tile) {
-    const int base = tile * G::tile;
-#pragma unroll
-    for (int j = 0; j < G::items; ++j) {
-      const int i = base + j * kOsThreads + tid;
-      key[j] = 0u;
-      if (i < n)
-        key[j] = kFromTuples ? canon_word(ts.t[(int64_t)i * ts.k + key_word], ts.is_float) : keys_in[i];
-    }
-  };
-  int tile = blockIdx.x;
-  if (tile < tiles) load(tile);
-  for (; tile < tiles; tile += gridDim.x) {
-    for (int d = tid; d < G::bins; d += kOsThreads) s_h[d] = 0;
-    __syncthreads();
-    const int base = tile * G::tile;
-#pragma unroll
-    for (int j = 0; j < G::items; ++j) {
-      const int i = base + j * kOsThreads + tid;
-      if (i < n) {
-        const uint32_t kk = kModel ? model_bucket(mv, key[j]) : key[j];
-        atomicAdd(&s_h[(kk >> shift) & G::mask], 1u);
-      }
-    }
-    if (tile + (int)gridDim.x < tiles) load(tile + gridDim.x);
-    __syncthreads();
-    for (int d = tid; d < G::bins; d += kOsThreads) cnt[(int64_t)tile * G::bins + d] = s_h[d];
-    __syncthreads();
-  }
 }
 
 // First level: exclusive prefix over the tiles of one group, per digit (256
@@ -303,6 +256,199 @@ __global__ __launch_bounds__(1024) void k_radix_scan_groups(uint32_t* __restrict
         *p = run[q];
         run[q] += c;
       }
+  }
+}
+
+// How a count workgroup shares the scans: kSub threads split a digit's tiles
+// (or groups), or each thread takes kDpt digits.  256 digits: 2 and 1; 2048
+// digits: 1 and 4.
+template <class G>
+struct ScanShape {
+  static constexpr int sub = G::bins >= kOsThreads ? 1 : kOsThreads / G::bins;
+  static constexpr int dpt = G::bins >= kOsThreads ? G::bins / kOsThreads : 1;
+  static constexpr int per = kScanGroup / sub;  // tiles of a group per thread
+};
+
+// Exclusive prefix over the tg tiles of group g, per digit, in place; the
+// group's totals go to group_tot[g].  Called by the whole workgroup.
+template <class G>
+__device__ void scan_group(uint32_t* __restrict__ cnt, uint32_t* __restrict__ group_tot, int g,
+                           int tg, uint32_t* s_part) {
+  using S = ScanShape<G>;
+  const int tid = threadIdx.x;
+  const int sub = S::sub > 1 ? tid / G::bins : 0;
+  const int lo = sub * S::per;
+  const int64_t t0 = (int64_t)g * kScanGroup + lo;
+  for (int q = 0; q < S::dpt; ++q) {
+    const int d = S::sub > 1 ? tid % G::bins : q * kOsThreads + tid;
+    uint32_t c[S::per];
+#pragma unroll
+    for (int u = 0; u < S::per; ++u) c[u] = lo + u < tg ? load_dev(cnt + (t0 + u) * G::bins + d) : 0u;
+    uint32_t run = 0;
+    if constexpr (S::sub > 1) {
+      uint32_t sum = 0;
+#pragma unroll
+      for (int u = 0; u < S::per; ++u) sum += c[u];
+      s_part[sub * G::bins + d] = sum;
+      __syncthreads();
+      for (int v = 0; v < sub; ++v) run += s_part[v * G::bins + d];
+    }
+#pragma unroll
+    for (int u = 0; u < S::per; ++u) {
+      if (lo + u < tg) cnt[(t0 + u) * G::bins + d] = run;
+      run += c[u];
+    }
+    if (sub == S::sub - 1) store_dev(group_tot + (int64_t)g * G::bins + d, run);
+  }
+}
+
+// Group totals to group starts that include every digit's global start, in
+// place.  Called by the whole workgroup; s_start holds G::bins words.
+template <class G>
+__device__ void scan_groups(uint32_t* __restrict__ group_tot, int groups, uint32_t* s_part,
+                            uint32_t* s_start, uint32_t* s_tmp) {
+  using S = ScanShape<G>;
+  const int tid = threadIdx.x;
+  const int sub = S::sub > 1 ? tid / G::bins : 0;
+  const int per = (groups + S::sub - 1) / S::sub;
+  const int g0 = min(groups, sub * per), g1 = min(groups, g0 + per);
+  auto digit = [&](int q) { return S::sub > 1 ? tid % G::bins : q * kOsThreads + tid; };
+  uint32_t run[S::dpt];
+  uint32_t base = 0;  // digits of the earlier q rounds
+#pragma unroll
+  for (int q = 0; q < S::dpt; ++q) {
+    const int d = digit(q);
+    uint32_t part = 0;
+    for (int g = g0; g < g1; g += kSgBatch) {
+      uint32_t c[kSgBatch];
+#pragma unroll
+      for (int u = 0; u < kSgBatch; ++u)
+        c[u] = g + u < g1 ? load_dev(group_tot + (int64_t)(g + u) * G::bins + d) : 0u;
+#pragma unroll
+      for (int u = 0; u < kSgBatch; ++u) part += c[u];
+    }
+    // the digit's total, held by the thread of its first sub-range (those
+    // threads come first and hold the digits in order), and the part of the
+    // sub-ranges before this thread's
+    uint32_t tot = part, before = 0;
+    if constexpr (S::sub > 1) {
+      s_part[sub * G::bins + d] = part;
+      __syncthreads();
+      tot = 0;
+      if (sub == 0)
+        for (int v = 0; v < S::sub; ++v) tot += s_part[v * G::bins + d];
+      for (int v = 0; v < sub; ++v) before += s_part[v * G::bins + d];
+    }
+    uint32_t all;
+    const uint32_t ds = base + block_exclusive_sum<kOsThreads>(tot, s_tmp, &all);
+    base += all;
+    if constexpr (S::sub > 1) {
+      if (sub == 0) s_start[d] = ds;
+      __syncthreads();
+      run[q] = s_start[d] + before;
+    } else {
+      run[q] = ds;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < S::dpt; ++q) {
+    const int d = digit(q);
+    for (int g = g0; g < g1; g += kSgBatch) {
+      uint32_t c[kSgBatch];
+#pragma unroll
+      for (int u = 0; u < kSgBatch; ++u)
+        c[u] = g + u < g1 ? load_dev(group_tot + (int64_t)(g + u) * G::bins + d) : 0u;
+#pragma unroll
+      for (int u = 0; u < kSgBatch; ++u) {
+        if (g + u < g1) group_tot[(int64_t)(g + u) * G::bins + d] = run[q];
+        run[q] += c[u];
+      }
+    }
+  }
+}
+
+// Workgroup b counts tiles b, b + grid, ... (one tile each in an ordinary
+// pass), loading the next tile's keys while it counts the current one.
+// kFused (gated passes): after a tile's counts are written, the last tile of
+// its group to complete scans the group, and the last group to complete
+// scans the groups, as the two scan launches would.  sync[0] counts
+// completed groups and sync[1 + g] completed tiles of group g; atomicInc
+// wraps each back to zero on its last arrival, so a pass leaves the counters
+// as it found them.
+template <class G, bool kFromTuples, bool kModel, bool kFused>
+__global__ __launch_bounds__(kOsThreads) void k_radix_count(const uint32_t* __restrict__ keys_in,
+                                                           const TupleSrc ts, int key_word,
+                                                           int64_t n_host, const int32_t* n_dev,
+                                                           int shift, uint32_t* __restrict__ cnt,
+                                                           uint32_t* __restrict__ group_tot,
+                                                           uint32_t* __restrict__ sync,
+                                                           const RadixExtra ex) {
+  __shared__ uint32_t s_h[G::bins];
+  __shared__ uint32_t s_part[kFused && ScanShape<G>::sub > 1 ? kOsThreads : 1];
+  __shared__ uint32_t s_tmp[kFused ? kOsWaves + 1 : 1];
+  __shared__ float s_c[kModel ? kCdfSegments + 1 : 1];
+  __shared__ int s_last;
+  if (gated_off(ex)) return;
+  const int tid = threadIdx.x;
+  ModelView mv{};
+  if constexpr (kModel) mv = load_model(ex, s_c);
+  const int n = (int)(n_dev ? *n_dev : n_host);
+  // every tile of the launch bound gets its row (zeros beyond the device count)
+  const int tiles = (int)((n_host + G::tile - 1) / G::tile);
+  const int groups = (tiles + kScanGroup - 1) / kScanGroup;
+  uint32_t key[G::items];
+  auto load = [&](int tile) {
+    const int base = tile * G::tile;
+#pragma unroll
+    for (int j = 0; j < G::items; ++j) {
+      const int i = base + j * kOsThreads + tid;
+      key[j] = 0u;
+      if (i < n)
+        key[j] = kFromTuples ? canon_word(ts.t[(int64_t)i * ts.k + key_word], ts.is_float) : keys_in[i];
+    }
+  };
+  int tile = blockIdx.x;
+  if (tile < tiles) load(tile);
+  for (; tile < tiles; tile += gridDim.x) {
+    for (int d = tid; d < G::bins; d += kOsThreads) s_h[d] = 0;
+    __syncthreads();
+    const int base = tile * G::tile;
+#pragma unroll
+    for (int j = 0; j < G::items; ++j) {
+      const int i = base + j * kOsThreads + tid;
+      if (i < n) {
+        const uint32_t kk = kModel ? model_bucket(mv, key[j]) : key[j];
+        atomicAdd(&s_h[(kk >> shift) & G::mask], 1u);
+      }
+    }
+    if (tile + (int)gridDim.x < tiles) load(tile + gridDim.x);
+    __syncthreads();
+    if constexpr (!kFused) {
+      for (int d = tid; d < G::bins; d += kOsThreads) cnt[(int64_t)tile * G::bins + d] = s_h[d];
+    } else {
+      for (int d = tid; d < G::bins; d += kOsThreads) store_dev(cnt + (int64_t)tile * G::bins + d, s_h[d]);
+      // every thread's counts have reached the device before the group's
+      // counter moves
+      wait_memory_ops();
+      __syncthreads();
+      const int g = tile / kScanGroup;
+      const unsigned tg = (unsigned)min(kScanGroup, tiles - g * kScanGroup);
+      if (tid == 0) s_last = atomicInc(&sync[1 + g], tg - 1u) == tg - 1u;
+      __syncthreads();
+      if (s_last) {
+        wait_memory_ops();  // the counter was read before the other tiles' counts
+        scan_group<G>(cnt, group_tot, g, (int)tg, s_part);
+        wait_memory_ops();
+        __syncthreads();
+        if (tid == 0) s_last = atomicInc(&sync[0], (unsigned)groups - 1u) == (unsigned)groups - 1u;
+        __syncthreads();
+        if (s_last) {
+          wait_memory_ops();  // the counter was read before the other groups' totals
+          scan_groups<G>(group_tot, groups, s_part, s_h, s_tmp);
+        }
+      }
+    }
+    __syncthreads();  // s_h and s_last are reused by the next tile
   }
 }
 
@@ -513,18 +659,27 @@ hipError_t radix_pass_g(const uint32_t* keys_in, const TupleSrc& ts, int key_wor
   const int cgrid = gated && tiles > kGatedGrid ? kGatedGrid : tiles;
   const int tiles_pad = xcd_grid(tiles);
   const int sgrid = gated && tiles_pad > kGatedGrid ? kGatedGrid : tiles_pad;
-#define KD_RC(FT, MD)                                                                           \
-  hipLaunchKernelGGL((k_radix_count<G, FT, MD>), dim3(cgrid), dim3(kOsThreads), 0, st, keys_in, \
-                     ts, key_word, n, n_dev, shift, cnt, ex)
+  if (gated && ex.sync == nullptr) return hipErrorInvalidValue;
+#define KD_RC(FT, MD)                                                                          \
+  do {                                                                                         \
+    if (gated)                                                                                 \
+      hipLaunchKernelGGL((k_radix_count<G, FT, MD, true>), dim3(cgrid), dim3(kOsThreads), 0, st, \
+                         keys_in, ts, key_word, n, n_dev, shift, cnt, group_tot, ex.sync, ex); \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_radix_count<G, FT, MD, false>), dim3(cgrid), dim3(kOsThreads), 0,  \
+                         st, keys_in, ts, key_word, n, n_dev, shift, cnt, group_tot, nullptr, ex); \
+  } while (0)
   if (ft) {
     if (md) KD_RC(true, true); else KD_RC(true, false);
   } else {
     if (md) KD_RC(false, true); else KD_RC(false, false);
   }
 #undef KD_RC
-  hipLaunchKernelGGL(k_radix_scan_tiles<G::bins>, dim3(groups, G::bins / 256), dim3(256), 0, st, cnt,
-                     group_tot, tiles, ex);
-  hipLaunchKernelGGL(k_radix_scan_groups<G::bins>, dim3(1), dim3(1024), 0, st, group_tot, groups, ex);
+  if (!gated) {
+    hipLaunchKernelGGL(k_radix_scan_tiles<G::bins>, dim3(groups, G::bins / 256), dim3(256), 0, st,
+                       cnt, group_tot, tiles, ex);
+    hipLaunchKernelGGL(k_radix_scan_groups<G::bins>, dim3(1), dim3(1024), 0, st, group_tot, groups, ex);
+  }
 #define KD_RS(FT, WK, MD)                                                                        \
   do {                                                                                           \
     if (gated)                                                                                   \

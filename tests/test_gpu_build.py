@@ -170,6 +170,17 @@ def test_first_coordinate_run_too_long(kd):
     assert_same(kd, word0_runs([3, 5000, 70, 2, 9000, 1], 3, 61, 1 << 20))
 
 
+def test_run_too_long_at_size(kd):
+    """The complete sort that a too-long run turns on, over 2.4 M rows: more
+    tiles than the gated passes' workgroups (each walks several) and several
+    groups of 64 tiles, whose scans the counts' last workgroups do."""
+    g = kdgen.rng(62)
+    lengths = np.concatenate([g.choice([1, 1, 1, 2, 3], size=1_500_000), [6000]])
+    t = word0_runs(lengths, 3, 63, 1 << 20)
+    assert t.shape[0] > 256 * 8192
+    assert_same(kd, t)
+
+
 def test_all_duplicates(kd):
     t = np.tile(np.array([[5, -7, 9]], dtype=np.int32), (10000, 1))
     assert_same(kd, t)
