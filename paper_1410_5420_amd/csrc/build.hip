@@ -1145,28 +1145,20 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
       const int i = it * kLfThreads + tid;
-      if (seg[it] == kHole) continue;
+      const bool was = seg[it] != kHole;
       int ss = (int)(seg[it] & 0xFFFF), ee = (int)(seg[it] >> 16);
+      bool live = was;
       if (rel > 0) {
         const int pm = ss + ((ee - ss) >> 1);
-        if (i == pm) {
-          seg[it] = kHole;
-          continue;
-        }
-        if (i < pm)
-          ee = pm - 1;
-        else
-          ss = pm + 1;
-        seg[it] = (uint32_t)ss | ((uint32_t)ee << 16);
+        live = was && i != pm;
+        ee = i < pm ? pm - 1 : ee;
+        ss = i > pm ? pm + 1 : ss;
       }
+      seg[it] = live ? ((uint32_t)ss | ((uint32_t)ee << 16)) : kHole;
       const uint16_t id = ap[i];
-      if (last) {
-        s_out[i] = id;
-        continue;
-      }
       const int m = ss + ((ee - ss) >> 1);
-      s_side[id] = i < m ? 1 : (i > m ? 2 : 0);  // lower, upper, node
-      if (i == m) s_out[i] = id;
+      if (live && (last || i == m)) s_out[i] = id;
+      if (live && !last) s_side[id] = i < m ? 1 : (i > m ? 2 : 0);  // lower, upper, node
     }
     __syncthreads();
     if (last) break;
@@ -1190,8 +1182,8 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
 #pragma unroll
       for (int a2 = 0; a2 < R; ++a2) {
         const int j = (p + 1 + a2) % k;
-        uint32_t side = 0;
-        if (live) side = s_side[s_lid[((((curmask >> j) & 1) * k) + j) * C + i]];
+        const uint32_t sd = s_side[s_lid[((((curmask >> j) & 1) * k) + j) * C + i] & (C - 1)];
+        const uint32_t side = live ? sd : 0u;
         const uint32_t f = (side & 1u) | ((side & 2u) << 15);
         const uint32_t inc = wave_scan_dpp(f);
         const uint32_t exc = inc - f;
@@ -1215,23 +1207,24 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
     // phase 4: move every element of the k-1 arrays to its new position
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
-      if (seg[it] == kHole) continue;
       const int ss = (int)(seg[it] & 0xFFFF), ee = (int)(seg[it] >> 16);
       const int m = ss + ((ee - ss) >> 1);
 #pragma unroll
       for (int a2 = 0; a2 < R; ++a2) {
         const uint32_t x = pref[a2][it];
-        const uint32_t side = (x >> 29) & 3u;
-        if (side == 0u) continue;  // the node itself is not copied
+        const uint32_t side = (x >> 29) & 3u;  // 0: a hole, or the node (not copied)
         const int j = (p + 1 + a2) % k;
-        uint32_t pre = x & 0x1FFFFFFFu;
-        if (!(x >> 31)) pre += s_chunk[a2][it * kLfWaves + w];
+        const uint32_t carry = s_chunk[a2][it * kLfWaves + w];
+        const uint32_t pre = (x & 0x1FFFFFFFu) + ((x >> 31) ? 0u : carry);
         const int dest = side == 1u ? ss + (int)(pre & 0xFFFF) : m + 1 + (int)(pre >> 16);
         const int cb = (curmask >> j) & 1;
-        if (dest >= ss && dest <= ee)
-          s_lid[((cb ^ 1) * k + j) * C + dest] = s_lid[(cb * k + j) * C + it * kLfThreads + tid];
-        else  // only if the counts were inconsistent
-          atomicOr(F.status, kStatusLeaf);
+        const uint16_t v = s_lid[(cb * k + j) * C + it * kLfThreads + tid];
+        if (side != 0u) {
+          if (dest >= ss && dest <= ee)
+            s_lid[((cb ^ 1) * k + j) * C + dest] = v;
+          else  // only if the counts were inconsistent
+            atomicOr(F.status, kStatusLeaf);
+        }
       }
     }
     curmask ^= ((1u << k) - 1) & ~(1u << p);  // every array but the split one moved

@@ -759,7 +759,7 @@ __device__ __forceinline__ bool tie_less(const TieArgs& ta, int64_t n, int x, in
 
 constexpr int kTileThreads = 256;
 constexpr int kTileItems = (kTieSpan + kTileThreads - 1) / kTileThreads;  // positions per thread
-constexpr int kTileGrid = 1024;  // resident workgroups walking the tiles
+constexpr int kTileGrid = 1280;  // resident workgroups walking the tiles (5 per CU)
 
 // Exclusive max over the threads of a kTileThreads workgroup (-1 for thread
 // 0); s_tmp holds kTileThreads/64 words.  Contains barriers.
