@@ -1142,6 +1142,11 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
     // phase 1: step down one level (the parent's node becomes a hole), then
     // record the side of each id (from its place in the split array) and
     // each subarray's node
+    // (every LDS read of a phase is issued before its first write: the reads
+    // then overlap instead of each waiting behind the writes before it)
+    uint16_t idv[kItems];
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) idv[it] = ap[it * kLfThreads + tid];
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
       const int i = it * kLfThreads + tid;
@@ -1155,7 +1160,7 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
         ss = i > pm ? pm + 1 : ss;
       }
       seg[it] = live ? ((uint32_t)ss | ((uint32_t)ee << 16)) : kHole;
-      const uint16_t id = ap[i];
+      const uint16_t id = idv[it];
       const int m = ss + ((ee - ss) >> 1);
       if (live && (last || i == m)) s_out[i] = id;
       if (live && !last) s_side[id] = i < m ? 1 : (i > m ? 2 : 0);  // lower, upper, node
@@ -1171,9 +1176,34 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
     // per element and array: count of the same side before it (bits 0-28),
     // side << 29 (1 lower, 2 upper, 0 node), head in this chunk << 31
     uint32_t pref[R][kItems];
+    uint32_t sdv[R][kItems];
+    {
+      uint16_t idr[R][kItems];
+#pragma unroll
+      for (int it = 0; it < kItems; ++it)
+#pragma unroll
+        for (int a2 = 0; a2 < R; ++a2) {
+          const int j = (p + 1 + a2) % k;
+          idr[a2][it] = s_lid[((((curmask >> j) & 1) * k) + j) * C + it * kLfThreads + tid];
+        }
+#pragma unroll
+      for (int it = 0; it < kItems; ++it)
+#pragma unroll
+        for (int a2 = 0; a2 < R; ++a2) sdv[a2][it] = s_side[idr[a2][it] & (C - 1)];
+    }
+    // the scans of all items and arrays together, so that their lane moves
+    // interleave
+    uint32_t incv[R][kItems];
+#pragma unroll
+    for (int it = 0; it < kItems; ++it)
+#pragma unroll
+      for (int a2 = 0; a2 < R; ++a2) {
+        if (seg[it] == kHole) sdv[a2][it] = 0u;
+        const uint32_t side = sdv[a2][it];
+        incv[a2][it] = wave_scan_dpp((side & 1u) | ((side & 2u) << 15));
+      }
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
-      const int i = it * kLfThreads + tid;
       const bool live = seg[it] != kHole;
       const int ss = (int)(seg[it] & 0xFFFF);
       const int cbase = it * kLfThreads + w * kWave;
@@ -1181,11 +1211,9 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
       const int hlane = hin ? ss - cbase : 0;
 #pragma unroll
       for (int a2 = 0; a2 < R; ++a2) {
-        const int j = (p + 1 + a2) % k;
-        const uint32_t sd = s_side[s_lid[((((curmask >> j) & 1) * k) + j) * C + i] & (C - 1)];
-        const uint32_t side = live ? sd : 0u;
+        const uint32_t side = sdv[a2][it];
         const uint32_t f = (side & 1u) | ((side & 2u) << 15);
-        const uint32_t inc = wave_scan_dpp(f);
+        const uint32_t inc = incv[a2][it];
         const uint32_t exc = inc - f;
         const uint32_t hexc = __shfl(exc, hlane, kWave);
         pref[a2][it] = (hin ? exc - hexc : exc) | (side << 29) | (hin ? 1u << 31 : 0u);
@@ -1205,6 +1233,16 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
     }
     __syncthreads();
     // phase 4: move every element of the k-1 arrays to its new position
+    uint16_t vv[R][kItems];
+    uint32_t cyv[R][kItems];
+#pragma unroll
+    for (int it = 0; it < kItems; ++it)
+#pragma unroll
+      for (int a2 = 0; a2 < R; ++a2) {
+        const int j = (p + 1 + a2) % k;
+        vv[a2][it] = s_lid[(((curmask >> j) & 1) * k + j) * C + it * kLfThreads + tid];
+        cyv[a2][it] = s_chunk[a2][it * kLfWaves + w];
+      }
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
       const int ss = (int)(seg[it] & 0xFFFF), ee = (int)(seg[it] >> 16);
@@ -1214,11 +1252,10 @@ __global__ __launch_bounds__(kLfThreads) void k_leaf(const RecBufs B, const Fore
         const uint32_t x = pref[a2][it];
         const uint32_t side = (x >> 29) & 3u;  // 0: a hole, or the node (not copied)
         const int j = (p + 1 + a2) % k;
-        const uint32_t carry = s_chunk[a2][it * kLfWaves + w];
-        const uint32_t pre = (x & 0x1FFFFFFFu) + ((x >> 31) ? 0u : carry);
+        const uint32_t pre = (x & 0x1FFFFFFFu) + ((x >> 31) ? 0u : cyv[a2][it]);
         const int dest = side == 1u ? ss + (int)(pre & 0xFFFF) : m + 1 + (int)(pre >> 16);
         const int cb = (curmask >> j) & 1;
-        const uint16_t v = s_lid[(cb * k + j) * C + it * kLfThreads + tid];
+        const uint16_t v = vv[a2][it];
         if (side != 0u) {
           if (dest >= ss && dest <= ee)
             s_lid[((cb ^ 1) * k + j) * C + dest] = v;
