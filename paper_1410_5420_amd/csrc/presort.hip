@@ -574,22 +574,29 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
   }
   __syncthreads();
 
-  // global destination of every tile-sorted slot this thread writes out
+  // global destination of every tile-sorted slot this thread writes out.  A
+  // full tile (every tile but the last) writes every slot, so its stores and
+  // loads need no guard: the compiler can then count them and wait for the
+  // next plane's loads alone, not for the stores issued after them.
   const int tile_n = min(n - base, kTile);
+  const bool full = tile_n == kTile;
   int dest[kItems];
+  bool bad = false;
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
     const int i = tid + j * kOsThreads;
-    dest[j] = -1;
-    if (i < tile_n) {
-      const uint32_t kk = s_keys[i];
-      const uint32_t d = (kk >> shift) & G::mask;
-      const int g = (int)s_gbase[d] + (i - (int)s_tile_excl[d]);
-      if (g >= 0 && g < n)
-        dest[j] = g;
-      else if (ex.status)  // only if the counts were inconsistent
-        atomicOr(ex.status, kStatusRadix);
-      if (kWriteKeys && dest[j] >= 0) keys_out[g] = kk;
+    const uint32_t kk = s_keys[i];  // (a stale key beyond tile_n: its slot is not written)
+    const uint32_t d = (kk >> shift) & G::mask;
+    const int g = (int)s_gbase[d] + (i - (int)s_tile_excl[d]);
+    // out of range only if the counts were inconsistent: flagged, and kept
+    // inside the array
+    bad = bad || (i < tile_n && (g < 0 || g >= n));
+    dest[j] = i < tile_n ? min(max(g, 0), n - 1) : -1;
+    if (kWriteKeys) {
+      if (full)
+        keys_out[dest[j]] = kk;
+      else if (dest[j] >= 0)
+        keys_out[dest[j]] = kk;
     }
   }
   // the next tile's keys load while this tile's planes are written
@@ -598,36 +605,49 @@ __global__ __launch_bounds__(kOsThreads) void k_radix_scatter(
 
   // payload planes: the next plane's values are loaded before the current
   // one is written out
-  uint32_t nxt[kItems];
-  if (pay.count > 0) {
+  auto planes = [&](auto full_tag) {
+    constexpr bool kFull = decltype(full_tag)::value;
+    uint32_t nxt[kItems];
+    auto load_plane = [&](const Plane& pl) {
+      if (pl.kind == kPlaneArray) {
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-      const int i = wbase + j * kWave;
-      nxt[j] = i < n ? plane_value(pay.p[0], ts, i) : 0u;
-    }
-  }
-  for (int q = 0; q < pay.count; ++q) {
+        for (int j = 0; j < kItems; ++j) {
+          const int i = wbase + j * kWave;
+          nxt[j] = (kFull || i < n) ? pl.in[i] : 0u;
+        }
+      } else {
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-      const int i = wbase + j * kWave;
-      if (i < n) s_stage[rank[j]] = nxt[j];
-    }
-    if (q + 1 < pay.count) {
-      const Plane pn = pay.p[q + 1];
+        for (int j = 0; j < kItems; ++j) {
+          const int i = wbase + j * kWave;
+          nxt[j] = (kFull || i < n) ? plane_value(pl, ts, i) : 0u;
+        }
+      }
+    };
+    if (pay.count > 0) load_plane(pay.p[0]);
+    for (int q = 0; q < pay.count; ++q) {
 #pragma unroll
       for (int j = 0; j < kItems; ++j) {
         const int i = wbase + j * kWave;
-        nxt[j] = i < n ? plane_value(pn, ts, i) : 0u;
+        if (kFull || i < n) s_stage[rank[j]] = nxt[j];
       }
-    }
-    __syncthreads();
-    uint32_t* out = pay.p[q].out;
+      if (q + 1 < pay.count) load_plane(pay.p[q + 1]);
+      __syncthreads();
+      uint32_t* out = pay.p[q].out;
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-      if (dest[j] >= 0) out[dest[j]] = s_stage[tid + j * kOsThreads];
+      for (int j = 0; j < kItems; ++j) {
+        if (kFull)
+          out[dest[j]] = s_stage[tid + j * kOsThreads];
+        else if (dest[j] >= 0)
+          out[dest[j]] = s_stage[tid + j * kOsThreads];
+      }
+      __syncthreads();
     }
-    __syncthreads();
-  }
+  };
+  if (full)
+    planes(std::true_type{});
+  else
+    planes(std::false_type{});
+  if (bad && ex.status) atomicOr(ex.status, kStatusRadix);
   if constexpr (!kLoop) break;  // one tile per workgroup
   __syncthreads();  // LDS is reused by the next tile
   }
