@@ -1109,11 +1109,21 @@ __global__ __launch_bounds__(kDdThreads) void k_dedup_count(const uint32_t* __re
   __shared__ uint32_t s_part[kDdWaves];
   const int tid = threadIdx.x;
   const int base = blockIdx.x * kSortTile;
+  // every position's first word and its predecessor's, loaded together
+  // (clamped into the array); the other words only where they are equal
+  uint32_t cur[kDdItems], prv[kDdItems];
+#pragma unroll
+  for (int j = 0; j < kDdItems; ++j) {
+    const int i = min(base + j * kDdThreads + tid, n - 1);
+    cur[j] = w0[i];
+    prv[j] = w0[max(i - 1, 0)];
+  }
   uint32_t c = 0;
 #pragma unroll
   for (int j = 0; j < kDdItems; ++j) {
     const int i = base + j * kDdThreads + tid;
-    if (i < n && keep_row(w0, planes, tree, n, k, i)) ++c;
+    if (i >= n) continue;
+    if (i == 0 || cur[j] != prv[j] || keep_row(w0, planes, tree, n, k, i)) ++c;
   }
   c = wave_inclusive_sum(c);
   if (lane_id() == kWave - 1) s_part[tid / kWave] = c;
