@@ -73,14 +73,14 @@ hipError_t launch_store_i64(int64_t* dst, const int64_t* src, hipStream_t st) {
 // into unsigned order; it is applied as the tuples are read.
 
 // ---- radix passes: per-tile counts, a two-level scan, then the scatter ----------
-// Every pass is three launches with no waiting between workgroups:
-//   1. count:   tile t (kSortTile elements, fixed by blockIdx) counts its 256
-//               digits into cnt[t][d];
+// Every pass is three steps, with no workgroup waiting on another:
+//   1. count:   tile t (512 * items elements) counts its digits (256, or 2048
+//               for 11-bit digits) into cnt[t][d];
 //   2. scan:    blocks of 64 tiles turn those into exclusive prefixes per digit
 //               (plus per-block totals), one block then scans the block
-//               totals and adds each digit's global start;
+//               totals and adds each digit's global start (two launches);
 //               in a gated pass (one that usually does nothing) the count's
-//               last workgroups do this instead, to save two launches;
+//               last workgroups do this instead, to save the two launches;
 //   3. scatter: tile t ranks its elements stably (wave ballots), adds the
 //               offsets, stages keys and payload planes through LDS in output
 //               order and writes them out in runs.
