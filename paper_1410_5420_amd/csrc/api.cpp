@@ -419,6 +419,13 @@ int presort_impl(const Job& J, hipStream_t st, bool first_only = false) {
     // Quantities: 0 = row id, d = word d (1 <= d < k), k = word 0, k+1 = tree.
     uint32_t* tree_in = carry + (size_t)(k - 1) * un;
     if (B > 1) KD_TRY(launch_tree_ids(J.d_off, B, tree_in, st));
+    // The rows' words as planes of canonical words: carry's planes 0 .. k-2
+    // take words 1 .. k-1 and its plane k word 0 (plane k-1 holds the tree
+    // ids); duplicate removal overwrites them only after both sorts of
+    // array 0.
+    PlaneOut rp{};
+    for (int d = 0; d < k; ++d) rp.p[d] = carry + (size_t)(d == 0 ? k : d - 1) * un;
+    KD_LAUNCH(KD_K_CANON, launch_rows_to_planes(ts, n, rp, st));
     std::vector<Quant> q(k + 2);
     // word 0 at the chosen digit width in both sorts of array 0, the other
     // words of the complete sort at 8 bits: the two sorts then differ by
@@ -428,8 +435,8 @@ int presort_impl(const Job& J, hipStream_t st, bool first_only = false) {
     const int fs = (P0 + 4 * (k - 1) + tp) & 1;  // buffer set holding the sorted result
     auto final_slot = [&](int i) { return vb + ((size_t)fs * slots + i) * un; };
     q[0] = Quant{kPlaneIndex, nullptr, 0, final_slot(0)};
-    for (int d = 1; d < k; ++d) q[d] = Quant{kPlaneTupleWord, nullptr, d, final_slot(d)};
-    q[k] = Quant{kPlaneTupleWord, nullptr, 0, final_slot(k)};
+    for (int d = 1; d < k; ++d) q[d] = Quant{kPlaneArray, rp.p[d], 0, final_slot(d)};
+    q[k] = Quant{kPlaneArray, rp.p[0], 0, final_slot(k)};
     q[k + 1] = B > 1 ? Quant{kPlaneArray, tree_in, 0, final_slot(k + 1)}
                      : Quant{-1, nullptr, 0, nullptr};
     std::vector<Pass> passes;

@@ -73,6 +73,13 @@ struct TupleSrc {
   int is_float;
 };
 
+// Tuple rows (row-major, k words each) to k planes of canonical words (plane
+// d at out.p[d]), so that every radix pass reads coalesced planes.
+struct PlaneOut {
+  uint32_t* p[kMaxK];
+};
+hipError_t launch_rows_to_planes(const TupleSrc& ts, int64_t n, const PlaneOut& out, hipStream_t st);
+
 // One payload plane of a radix pass.  Element i's value is in[i] (kind
 // kPlaneArray), i itself (kPlaneIndex) or the canonical key word `word` of
 // tuple row i (kPlaneTupleWord); it is written to out[dest].

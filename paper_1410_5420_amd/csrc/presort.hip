@@ -72,6 +72,28 @@ hipError_t launch_store_i64(int64_t* dst, const int64_t* src, hipStream_t st) {
 // canon_word (common.hpp) turns int32 signed order and float32 IEEE totalOrder
 // into unsigned order; it is applied as the tuples are read.
 
+// ---- tuple rows to planes -------------------------------------------------------
+// A pass that reads one word of every row straight from the rows fetches the
+// rows' cache lines once per word it reads; the words are therefore
+// canonicalised into planes once, before the first sort.
+__global__ __launch_bounds__(256) void k_rows_to_planes(const TupleSrc ts, int64_t n,
+                                                       const PlaneOut out) {
+  for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const uint32_t* r = ts.t + i * ts.k;
+    for (int d = 0; d < ts.k; ++d) out.p[d][i] = canon_word(r[d], ts.is_float);
+  }
+}
+
+hipError_t launch_rows_to_planes(const TupleSrc& ts, int64_t n, const PlaneOut& out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  for (int d = 0; d < ts.k; ++d)
+    if (out.p[d] == nullptr) return hipErrorInvalidValue;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_rows_to_planes, dim3((unsigned)blocks), dim3(256), 0, st, ts, n, out);
+  return hipGetLastError();
+}
+
 // ---- radix passes: per-tile counts, a two-level scan, then the scatter ----------
 // Every pass is three steps, with no workgroup waiting on another:
 //   1. count:   tile t (512 * items elements) counts its digits (256, or 2048
