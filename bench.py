@@ -51,7 +51,7 @@ def onesweep_bytes(n: int, nu: int, k: int):
     build (each pass counts as one launch of the class).  Array 0 is sorted
     over all n rows by its first word alone (k > 1): every pass moves that
     key word and k payload words (the row id, made by the first pass, and the
-    other key words), the first one reading the tuple rows themselves.  The
+    other key words), read from the planes the rows were canonicalised into.  The
     complete word-by-word sort of array 0 is also enqueued, gated on the tie
     step's flag: its k * 4 passes move nothing unless a run of equal first
     words is too long, and count as launches of no bytes.  Each of the k-1
