@@ -274,6 +274,7 @@ struct LearnedSort {
   int tieq;
   int32_t* starts;
   int32_t* flag;
+  int items = 8;  // keys per thread of the bucket passes
 };
 
 int learned_sort(std::vector<Quant> q, const LearnedSort& ls, const TupleSrc& ts, int64_t n,
@@ -287,6 +288,7 @@ int learned_sort(std::vector<Quant> q, const LearnedSort& ls, const TupleSrc& ts
   ex.sync = t_sync;
   ex.model = ls.model;
   ex.nb_bits = ls.nb_bits;
+  ex.items = ls.items;
   // bucket passes: stable, keyed by the bucket's 8-bit digits, moving everything
   const int bpasses = ls.nb_bits > kRadixBits ? 2 : 1;
   int set = 0;
@@ -474,6 +476,7 @@ int presort_impl(const Job& J, hipStream_t st, bool first_only = false) {
       ls.tieq = 0;
       ls.starts = at<int32_t>(ws, L.starts);
       ls.flag = at<int32_t>(ws, L.flags);
+      ls.items = J.sort_items;
       std::vector<Quant> ql(q.begin(), q.begin() + k + 1);
       int rc = learned_sort(ql, ls, ts, n, nullptr, vb, slots, rcnt, rgrp, st);
       if (rc != KD_OK) return rc;
@@ -539,6 +542,7 @@ int presort_impl(const Job& J, hipStream_t st, bool first_only = false) {
       ls.tieq = 0;
       ls.starts = at<int32_t>(ws, L.starts);
       ls.flag = at<int32_t>(ws, L.flags) + d;
+      ls.items = J.sort_items;
       std::vector<Quant> ql = q;
       ql[keyq].dst = at<uint32_t>(ws, L.lkey);
       int rc = learned_sort(ql, ls, ts, n, total, vb, slots, rcnt, rgrp, st);

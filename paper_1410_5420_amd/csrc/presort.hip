@@ -750,9 +750,10 @@ hipError_t launch_radix_pass(const uint32_t* keys_in, const TupleSrc& ts, int ke
                              const int32_t* n_dev, int shift, uint32_t* cnt, uint32_t* group_tot,
                              hipStream_t st, const RadixExtra& ex) {
   if (n <= 0) return hipSuccess;
-  // learned (model) passes run with the default geometry
+  // learned (model) passes rank by the bucket's 8-bit digits; every pass
+  // takes the build's tile size
   const int bits = ex.model ? 8 : ex.bits;
-  const int items = ex.model ? 8 : ex.items;
+  const int items = ex.items;
   if (bits == 8 && items == 8)
     return radix_pass_g<Geom<8, 8>>(keys_in, ts, key_word, keys_out, pay_in, n, n_dev, shift, cnt,
                                     group_tot, st, ex);

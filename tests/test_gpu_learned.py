@@ -149,6 +149,25 @@ def test_learned_small(kd, k, n):
     assert_learned_same(kd, t)
 
 
+@pytest.mark.parametrize("k", [2, 3, 6])
+@pytest.mark.parametrize("n", [8191, 300001])
+def test_learned_large_tiles(kd, k, n):
+    """Every sort through the learned buckets, whose bucket passes then run
+    on tiles of 8192 keys, as the bucket passes of the tuned C2 and C5 builds
+    do."""
+    case(f"learned sort_tile=8192 n={n} k={k}")
+    t = kdgen.uniform_int(n, k, -(1 << 24), 1 << 24, 0.05, 960 + n + k)
+    dt = torch.from_numpy(t).cuda()
+    models = kd.train_cdf(dt)
+    perm, nu, fb, lo, hi = kd.build_learned(dt, models, children=True, sort_tile=8192)
+    torch.cuda.synchronize()
+    want = oracle_tree(t)
+    assert nu == want["n_unique"]
+    assert np.array_equal(perm.cpu().numpy(), want["perm"])
+    assert np.array_equal(lo.cpu().numpy(), want["lo"]) and np.array_equal(hi.cpu().numpy(), want["hi"])
+    assert fb.numpy().tolist() == [0] * k, fb
+
+
 @pytest.mark.parametrize("k", [3, 6])
 def test_learned_deferred_partitioning(kd, k):
     """The learned presort followed by deferred partitioning (level form 3)."""
