@@ -395,15 +395,29 @@ __global__ void k_bucket_bounds(const uint32_t* __restrict__ keys, int64_t n_hos
     for (int b = gid; b <= NB; b += stride) starts[b] = 0;
     return;
   }
-  for (int i = gid; i < nu; i += stride) {
-    const int b = (int)cdf_bucket(cdf_eval(s_c, lo, scale, kmin, kmax, is_float, keys[i]), nb_bits);
-    const int pb = i == 0 ? -1
-                          : (int)cdf_bucket(cdf_eval(s_c, lo, scale, kmin, kmax, is_float, keys[i - 1]),
-                                            nb_bits);
-    if (b < pb) atomicOr(flag, 4);
-    for (int bb = pb + 1; bb <= b; ++bb) starts[bb] = i;
-    if (i == nu - 1)
-      for (int bb = b + 1; bb <= NB; ++bb) starts[bb] = nu;
+  // kBbBatch positions per thread and round, their keys and their
+  // predecessors' loaded together (one round trip per round, not per key)
+  constexpr int kBbBatch = 8;
+  for (int i0 = gid; i0 < nu; i0 += kBbBatch * stride) {
+    uint32_t kc[kBbBatch], kp[kBbBatch];
+#pragma unroll
+    for (int j = 0; j < kBbBatch; ++j) {
+      const int i = min(i0 + j * stride, nu - 1);
+      kc[j] = keys[i];
+      kp[j] = keys[max(i - 1, 0)];
+    }
+#pragma unroll
+    for (int j = 0; j < kBbBatch; ++j) {
+      const int i = i0 + j * stride;
+      if (i >= nu) break;
+      const int b = (int)cdf_bucket(cdf_eval(s_c, lo, scale, kmin, kmax, is_float, kc[j]), nb_bits);
+      const int pb =
+          i == 0 ? -1 : (int)cdf_bucket(cdf_eval(s_c, lo, scale, kmin, kmax, is_float, kp[j]), nb_bits);
+      if (b < pb) atomicOr(flag, 4);
+      for (int bb = pb + 1; bb <= b; ++bb) starts[bb] = i;
+      if (i == nu - 1)
+        for (int bb = b + 1; bb <= NB; ++bb) starts[bb] = nu;
+    }
   }
 }
 
