@@ -46,6 +46,18 @@ def test_geometry_long_runs_take_the_complete_sort(kd, bits, tile):
 
 
 @pytest.mark.parametrize("bits,tile", GEOMS)
+def test_geometry_complete_sort_at_size(kd, bits, tile):
+    """The gated complete sort over 1.2 M rows: more tiles than its
+    workgroups (each walks several) and several groups of 64 tiles, whose
+    scans the counts' last workgroups do, at every digit width (2048 digits
+    per tile at 11 bits)."""
+    t = kdgen.uniform_int(1_200_000, 3, -(1 << 20), 1 << 20, 0.02, 1850)
+    t[:, 0] = 7
+    print(f"[gpu case] complete sort n=1.2M bits={bits} tile={tile}", flush=True)
+    assert_same(kd, t, digit_bits=bits, sort_tile=tile)
+
+
+@pytest.mark.parametrize("bits,tile", GEOMS)
 def test_geometry_floats_and_forest(kd, bits, tile):
     t = kdgen.gaussian_mixture_f32(200000, 3, 16, 1900)
     t[:30] = np.array([[np.inf, -0.0, np.nan]] * 30, dtype=np.float32)
